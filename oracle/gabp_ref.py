@@ -1,0 +1,424 @@
+"""FP64 reference (oracle) for the GaBP SVM solver -- TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, obviously correct NumPy code.  Only the test-suite, the smoke
+check and the CPU-baseline leg of the benchmark may import it; the product
+path never does.  It shares no code with the HIP library.
+
+Paper: Bickson, Yom-Tov, Dolev, "A Gaussian Belief Propagation Solver for
+Large Scale Support Vector Machines" (arXiv 0810.1648).
+
+What is computed, with the passage each step follows:
+
+* The SVM dual (section "Classification Using Support Vector Machines",
+  eqs. dual/cons1/cons2): maximise sum(h) - 1/2 h'Dh with
+  D_ij = y_i y_j K(x_i, x_j).
+* The constraints are dropped (section "Proposed Solution of SVM Solver
+  Based on GaBP"): the method solves the linear system A h = 1 whose
+  solution is the mean of p(h) ~ exp(-1/2 h'Ah + h'1).
+* Bias by augmentation with the constant lambda = 1/N (same section); in
+  feature space this adds lambda^2 to every kernel entry (reading C2 in the
+  design notes).
+* The diagonal of D is weighted to make it diagonally dominant (subsection
+  "GaBP Algorithm Convergence"; the 2-norm soft margin adds 1/C).
+* GaBP: Algorithm 1 (per-message exclusion sums) and Algorithm 2
+  (broadcast aggregates, each outgoing message = aggregate minus the
+  recipient's own term), in synchronous rounds (section "Experimental
+  Results": synchronous communication rounds).
+
+Parity unpinned: none -- every function below is pinned by a test in
+tests/test_oracle_pins.py against closed forms, LAPACK, brute force or an
+invariant.
+"""
+from __future__ import annotations
+
+import itertools
+from dataclasses import dataclass
+
+import numpy as np
+
+# --------------------------------------------------------------------------
+# System construction
+# --------------------------------------------------------------------------
+
+DIAG_NONE = "none"
+DIAG_SOFTMARGIN = "softmargin"
+DIAG_DOMINANT_ROW = "dominant_row"
+DIAG_DOMINANT_UNIFORM = "dominant_uniform"
+
+
+def rbf_augmented_kernel(X, gamma: float, lam: float, chunk: int = 64) -> np.ndarray:
+    """K'_ij = exp(-gamma ||x_i - x_j||^2) + lam^2, in FP64.
+
+    The RBF kernel is the one used in every experiment (section
+    "Experimental Results"); the lam^2 term is the bias augmentation of
+    section "Proposed Solution of SVM Solver Based on GaBP" read in feature
+    space.  Distances are direct differences (no Gram expansion).
+    """
+    X = np.asarray(X, dtype=np.float64)
+    n = X.shape[0]
+    K = np.empty((n, n))
+    for i0 in range(0, n, chunk):
+        d2 = ((X[i0:i0 + chunk, None, :] - X[None, :, :]) ** 2).sum(axis=-1)
+        K[i0:i0 + chunk] = np.exp(-gamma * d2)
+    return K + lam * lam
+
+
+def signed_matrix(K: np.ndarray, y) -> np.ndarray:
+    """D_ij = y_i y_j K_ij (eq. dual)."""
+    y = np.asarray(y, dtype=np.float64)
+    return y[:, None] * y[None, :] * K
+
+
+def weight_diagonal(D: np.ndarray, C: float, mode: str = DIAG_DOMINANT_ROW,
+                    delta: float = 0.1) -> np.ndarray:
+    """Return A = D with its diagonal weighted (subsection "GaBP Algorithm
+    Convergence").
+
+    none:             A_ii = D_ii
+    softmargin:       A_ii = D_ii + 1/C   (2-norm soft margin)
+    dominant_row:     A_ii = max(D_ii + 1/C, (1 + delta) r_i),
+                      r_i = sum_{j != i} |D_ij|
+    dominant_uniform: one shift w = max_i (max(D_ii + 1/C, (1+delta) r_i) - D_ii)
+                      added to every diagonal entry.
+    """
+    A = np.array(D, dtype=np.float64, copy=True)
+    d = np.diag(D).copy()
+    r = np.abs(D).sum(axis=1) - np.abs(d)
+    if mode == DIAG_NONE:
+        new = d
+    elif mode == DIAG_SOFTMARGIN:
+        new = d + 1.0 / C
+    elif mode == DIAG_DOMINANT_ROW:
+        new = np.maximum(d + 1.0 / C, (1.0 + delta) * r)
+    elif mode == DIAG_DOMINANT_UNIFORM:
+        w = np.max(np.maximum(d + 1.0 / C, (1.0 + delta) * r) - d)
+        new = d + w
+    else:
+        raise ValueError(mode)
+    A[np.diag_indices_from(A)] = new
+    return A
+
+
+def svm_system(X, y, gamma: float, C: float, lam: float,
+               mode: str = DIAG_DOMINANT_ROW, delta: float = 0.1):
+    """A = weighted(Y K' Y) and b = 1: the linear system GaBP solves."""
+    K = rbf_augmented_kernel(X, gamma, lam)
+    A = weight_diagonal(signed_matrix(K, y), C, mode, delta)
+    return A, np.ones(A.shape[0])
+
+
+# --------------------------------------------------------------------------
+# Algorithm 1: GaBP with per-message exclusion sums (tiny N only)
+# --------------------------------------------------------------------------
+
+def gabp_algorithm1(A, b, sweeps: int):
+    """Algorithm 1, synchronous schedule.  Returns the list of marginal
+    means after each sweep 1..sweeps (step 4 "Infer").
+
+    Messages are kept in the paper's mean/precision form: P[k, i] and
+    M[k, i] are the precision and mean of the message k -> i.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    n = len(b)
+    nbr = [[k for k in range(n) if k != i and A[k, i] != 0.0] for i in range(n)]
+    Pii = np.diag(A).copy()                 # scalar fixes, step 1
+    mu_ii = b / Pii
+    P = np.zeros((n, n))
+    M = np.zeros((n, n))
+    out = []
+    for _ in range(sweeps):
+        Pn = np.zeros((n, n))
+        Mn = np.zeros((n, n))
+        for i in range(n):
+            for j in nbr[i]:
+                excl = [k for k in nbr[i] if k != j]
+                prec = Pii[i] + sum(P[k, i] for k in excl)
+                info = Pii[i] * mu_ii[i] + sum(P[k, i] * M[k, i] for k in excl)
+                Pn[i, j] = -A[i, j] ** 2 / prec
+                Mn[i, j] = info / A[i, j]
+        P, M = Pn, Mn
+        mu = np.array([(Pii[i] * mu_ii[i] + sum(P[k, i] * M[k, i] for k in nbr[i]))
+                       / (Pii[i] + sum(P[k, i] for k in nbr[i])) for i in range(n)])
+        out.append(mu)
+    return out
+
+
+# --------------------------------------------------------------------------
+# Algorithm 2 in the paper's mean form (small N)
+# --------------------------------------------------------------------------
+
+def gabp_algorithm2_mean_form(A, b, sweeps: int):
+    """Algorithm 2 exactly as printed: broadcast P~_i, mu~_i, then every
+    internal scalar from the aggregate minus the recipient's own term,
+    P_ij = -A_ij^2 / (P~_i - P_ji), mu_ij = (P~_i mu~_i - P_ji mu_ji) / A_ij.
+    Requires A_ij != 0 wherever messages flow (dense positive kernels).
+    Returns the marginal means after each sweep.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    n = len(b)
+    off = ~np.eye(n, dtype=bool) & (A != 0.0)
+    Pii = np.diag(A).copy()
+    mu_ii = b / Pii
+    P = np.zeros((n, n))                    # P[k, i]: k -> i
+    M = np.zeros((n, n))
+    out = []
+    for _ in range(sweeps):
+        Pt = Pii + P.sum(axis=0)
+        mut = (Pii * mu_ii + (P * M).sum(axis=0)) / Pt
+        Pn = np.zeros((n, n))
+        Mn = np.zeros((n, n))
+        for i in range(n):
+            for j in range(n):
+                if off[i, j]:
+                    Pn[i, j] = -A[i, j] ** 2 / (Pt[i] - P[j, i])
+                    Mn[i, j] = (Pt[i] * mut[i] - P[j, i] * M[j, i]) / A[i, j]
+        P, M = Pn, Mn
+        Pt = Pii + P.sum(axis=0)
+        out.append((Pii * mu_ii + (P * M).sum(axis=0)) / Pt)
+    return out
+
+
+# --------------------------------------------------------------------------
+# Algorithm 2 in information form: the oracle used for parity
+# --------------------------------------------------------------------------
+
+CONVERGED = "converged"
+NOT_CONVERGED = "not_converged"
+DIVERGED = "diverged"
+STAGNATED = "stagnated"
+
+
+@dataclass
+class GabpResult:
+    alpha: np.ndarray          # marginal means after the last sweep
+    ptilde: np.ndarray         # aggregate precisions P~ after the last sweep
+    sweeps: int                # completed sweeps
+    status: str
+    deltas: list               # ||alpha^t - alpha^(t-1)||_inf, t = 1..sweeps
+    trajectory: list | None    # alpha^0, alpha^1, ... if requested
+
+
+def gabp_solve(A, b, max_sweeps: int = 1000, tol_abs: float = 0.0,
+               tol_rel: float = 1e-12, keep_trajectory: bool = False) -> GabpResult:
+    """Synchronous Algorithm 2 with messages stored in information form.
+
+    State: P[i, j] = precision of the message i -> j and
+    E[i, j] = P_ij mu_ij (its information).  Aggregates (step 2
+    "broadcast"): P~_j = A_jj + sum_i P_ij, S_j = b_j + sum_i E_ij, so that
+    mu~_j = S_j / P~_j.  Internal scalars from the aggregate minus the
+    recipient's own term: with Q_ij = P~_i - P_ji,
+        P_ij <- -A_ij^2 / Q_ij,     E_ij <- -A_ij (S_i - E_ji) / Q_ij,
+    which is Algorithm 2's mu_ij multiplied by P_ij.  Sweep 0 is the
+    aggregate of all-zero messages; alpha^t = S^t / P~^t (step 4 "Infer").
+
+    Stops when ||alpha^t - alpha^(t-1)||_inf <= tol_abs + tol_rel
+    ||alpha^t||_inf (step 3 "Check", tested on alpha), after max_sweeps
+    (not converged), or when some Q_ij <= 0, P~ <= 0 or a value is not
+    finite (diverged: no valid Gaussian message exists).
+    """
+    A = np.asarray(A, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    n = len(b)
+    off = ~np.eye(n, dtype=bool)
+    Aoff = np.where(off, A, 0.0)
+    A2 = Aoff * Aoff
+    P = np.zeros((n, n))
+    E = np.zeros((n, n))
+    Pt = np.diag(A).copy()
+    S = b.copy()
+    alpha = S / Pt
+    traj = [alpha.copy()] if keep_trajectory else None
+    deltas = []
+    status = NOT_CONVERGED
+    t = 0
+    for t in range(1, max_sweeps + 1):
+        Q = Pt[:, None] - P.T                       # Q[i, j] = P~_i - P_ji
+        Qok = np.where(off, Q, 1.0)
+        if not (np.all(np.isfinite(Qok)) and np.all(Qok > 0.0)):
+            status = DIVERGED
+            t -= 1
+            break
+        Pn = np.where(off, -A2 / Qok, 0.0)
+        En = np.where(off, -Aoff * (S[:, None] - E.T) / Qok, 0.0)
+        P, E = Pn, En
+        Pt = np.diag(A) + P.sum(axis=0)
+        S = b + E.sum(axis=0)
+        if not (np.all(np.isfinite(Pt)) and np.all(Pt > 0.0) and np.all(np.isfinite(S))):
+            status = DIVERGED
+            break
+        new = S / Pt
+        d = float(np.max(np.abs(new - alpha)))
+        alpha = new
+        deltas.append(d)
+        if keep_trajectory:
+            traj.append(alpha.copy())
+        if d <= tol_abs + tol_rel * float(np.max(np.abs(alpha))):
+            status = CONVERGED
+            break
+    return GabpResult(alpha, Pt, t, status, deltas, traj)
+
+
+def svm_alpha_labels_folded(Kp, y, C, mode=DIAG_DOMINANT_ROW, delta=0.1, **kw):
+    """Solve (K' + W) g = y and return alpha = y * g.
+
+    Because A = Y (K' + W) Y and Y^2 = I, GaBP on (K' + W, b = y) produces
+    the iterates of GaBP on (A, b = 1) up to exact sign flips; this routine
+    exists so a test can check that identity bitwise.
+    """
+    W = weight_diagonal(Kp, C, mode, delta)
+    y = np.asarray(y, dtype=np.float64)
+    r = gabp_solve(W, y, **kw)
+    r.alpha = y * r.alpha
+    if r.trajectory is not None:
+        r.trajectory = [y * a for a in r.trajectory]
+    return r
+
+
+# --------------------------------------------------------------------------
+# Stateless (truncated) messages: no per-edge state, only aggregate history
+# --------------------------------------------------------------------------
+
+def gabp_solve_stateless(A, b, depth: int, sweeps: int):
+    """Synchronous GaBP where each sweep's messages are rebuilt from the
+    history of aggregates instead of stored messages.
+
+    The message i -> j at sweep t depends on the stored state only through
+    the reverse message j -> i at sweep t-1, which in turn depends on
+    i -> j at t-2, and so on down to the all-zero messages of sweep 0.
+    Unrolling `depth` levels and replacing the message at level t-depth by
+    zero reproduces the stored recursion exactly while t <= depth.
+    Returns the list alpha^1 .. alpha^sweeps.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    n = len(b)
+    off = ~np.eye(n, dtype=bool)
+    Aoff = np.where(off, A, 0.0)
+    hist_P = [np.diag(A).copy()]            # P~^0, P~^1, ...
+    hist_S = [b.copy()]
+    out = []
+    for t in range(1, sweeps + 1):
+        lo = max(1, t - depth + 1)           # first sweep rebuilt from zero state
+        # level s: messages of sweep s, computed from sweep s-1 aggregates and
+        # the reverse messages of sweep s-1 (zero at the start of the chain)
+        P = np.zeros((n, n))
+        E = np.zeros((n, n))
+        for s in range(lo, t + 1):
+            Pt, S = hist_P[s - 1], hist_S[s - 1]
+            Q = np.where(off, Pt[:, None] - P.T, 1.0)
+            Pn = np.where(off, -Aoff * Aoff / Q, 0.0)
+            En = np.where(off, -Aoff * (S[:, None] - E.T) / Q, 0.0)
+            P, E = Pn, En
+        hist_P.append(np.diag(A) + P.sum(axis=0))
+        hist_S.append(b + E.sum(axis=0))
+        out.append(hist_S[-1] / hist_P[-1])
+    return out
+
+
+# --------------------------------------------------------------------------
+# Closed forms, library solves and bounds used as pins
+# --------------------------------------------------------------------------
+
+def first_sweep(A, b):
+    """Aggregates after one sweep from zero messages:
+    P~^1_j = A_jj - sum_{i != j} A_ij^2 / A_ii,
+    S^1_j = b_j - sum_{i != j} A_ij b_i / A_ii."""
+    A = np.asarray(A, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    d = np.diag(A)
+    Aoff = A - np.diag(d)
+    Pt = d - (Aoff ** 2 / d[:, None]).sum(axis=0)
+    S = b - (Aoff * (b / d)[:, None]).sum(axis=0)
+    return Pt, S
+
+
+def cholesky_solve(A, b):
+    """alpha* = A^-1 b through LAPACK's Cholesky factorisation."""
+    L = np.linalg.cholesky(np.asarray(A, dtype=np.float64))
+    z = np.linalg.solve(L, np.asarray(b, dtype=np.float64))
+    return np.linalg.solve(L.T, z)
+
+
+def cg_solve(matvec, b, tol: float = 1e-13, max_iter: int = 10000):
+    """Plain conjugate gradients for an SPD operator."""
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b)
+    r = b.copy()
+    p = r.copy()
+    rr = r @ r
+    bn = np.sqrt(b @ b)
+    for _ in range(max_iter):
+        Ap = matvec(p)
+        a = rr / (p @ Ap)
+        x += a * p
+        r -= a * Ap
+        rn = r @ r
+        if np.sqrt(rn) <= tol * bn:
+            break
+        p = r + (rn / rr) * p
+        rr = rn
+    return x
+
+
+def varah_bound(A, alpha, b):
+    """||alpha - A^-1 b||_inf <= ||b - A alpha||_inf / min_i (|A_ii| - r_i)
+    for a strictly diagonally dominant A (Varah's bound)."""
+    A = np.asarray(A, dtype=np.float64)
+    d = np.abs(np.diag(A))
+    r = np.abs(A).sum(axis=1) - d
+    gap = np.min(d - r)
+    if gap <= 0:
+        return np.inf
+    return float(np.max(np.abs(np.asarray(b) - A @ alpha)) / gap)
+
+
+def box_qp_bruteforce(A, C: float):
+    """max 1'h - 1/2 h'Ah s.t. 0 <= h <= C, by enumerating the 3^N
+    active sets (lower bound, upper bound, free) and keeping the KKT point
+    (eqs. dual and cons1, without cons2, which the bias augmentation
+    removes).  For SPD A the KKT point is the unique optimum."""
+    A = np.asarray(A, dtype=np.float64)
+    n = A.shape[0]
+    one = np.ones(n)
+    best = None
+    for state in itertools.product((0, 1, 2), repeat=n):
+        state = np.array(state)
+        lo, hi, fr = state == 0, state == 1, state == 2
+        h = np.zeros(n)
+        h[hi] = C
+        if fr.any():
+            rhs = one[fr] - A[np.ix_(fr, ~fr)] @ h[~fr]
+            h[fr] = np.linalg.solve(A[np.ix_(fr, fr)], rhs)
+            if np.any(h[fr] < -1e-12) or np.any(h[fr] > C + 1e-12):
+                continue
+        g = one - A @ h
+        if np.any(g[lo] > 1e-10) or np.any(g[hi] < -1e-10):
+            continue
+        val = one @ h - 0.5 * h @ A @ h
+        if best is None or val > best[1]:
+            best = (h, val)
+    return best[0]
+
+
+def decision_function(Xtr, y, alpha, Xq, gamma: float, lam: float):
+    """f(x) = sum_i alpha_i y_i (K(x_i, x) + lam^2) (section "Classification
+    Using Support Vector Machines": the sign of f classifies x, with the bias
+    carried by the augmentation)."""
+    Xtr = np.asarray(Xtr, dtype=np.float64)
+    Xq = np.asarray(Xq, dtype=np.float64)
+    w = np.asarray(alpha, dtype=np.float64) * np.asarray(y, dtype=np.float64)
+    f = np.empty(Xq.shape[0])
+    for q in range(Xq.shape[0]):
+        d2 = ((Xtr - Xq[q]) ** 2).sum(axis=1)
+        f[q] = w @ (np.exp(-gamma * d2) + lam * lam)
+    return f
+
+
+def krr_dual_closed_form(K, y, lam_ridge: float):
+    """Kernel ridge regression dual optimum alpha = 2 lam (K + lam I)^-1 y
+    (section "Kernel Ridge Regression problem")."""
+    K = np.asarray(K, dtype=np.float64)
+    n = K.shape[0]
+    return 2.0 * lam_ridge * np.linalg.solve(K + lam_ridge * np.eye(n), np.asarray(y, dtype=np.float64))
