@@ -1,0 +1,258 @@
+/*
+ * gabp_svm.h -- C ABI of the MI355X (gfx950) GaBP SVM solver.
+ *
+ * Method: Bickson, Yom-Tov, Dolev, "A Gaussian Belief Propagation Solver for
+ * Large Scale Support Vector Machines" (arXiv 0810.1648).
+ *
+ * Problem statement (section "Classification Using Support Vector
+ * Machines"): a training set {(x_i, y_i)}, i = 1..N, x_i in R^m,
+ * y_i in {-1, +1}, a kernel K and a cost C go in; the Lagrange multipliers
+ * h = alpha and the decision function sign(sum_i alpha_i y_i K(x_i, x) + b)
+ * come out.  Following section "Proposed Solution of SVM Solver Based on
+ * GaBP", the solver drops the box and equality constraints and returns the
+ * mean of p(h) ~ exp(-1/2 h'Ah + h'1), i.e. alpha = A^-1 1 with
+ * A = Y K' Y + W: K' = K + lambda^2 (bias augmentation), W the diagonal
+ * weighting of subsection "GaBP Algorithm Convergence".  alpha is computed
+ * by synchronous sweeps of Algorithm 2 (section "Algorithm Optimization"):
+ * every node broadcasts its aggregate precision and mean, and every
+ * message is that aggregate minus the recipient's own term.
+ *
+ * Conventions for every call:
+ *   - No exception crosses the ABI; every call returns a gabp_status.
+ *   - The caller owns every buffer it passes.  Host inputs are copied before
+ *     the call returns; device inputs (mem = GABP_MEM_DEVICE) are read on the
+ *     given HIP stream and must stay valid until the call returns.
+ *   - A handle owns all device memory it allocates and frees it in
+ *     gabp_svm_destroy or when the next solve needs a different plan.
+ *   - One thread at a time per handle; distinct handles are independent.
+ *   - There is no CPU fallback: without a usable gfx950 device every
+ *     compute call fails with GABP_E_DEVICE.
+ */
+#ifndef GABP_SVM_H
+#define GABP_SVM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GABP_ABI_VERSION 1
+
+/* Opaque solver handle; owns every device buffer it allocates. */
+typedef struct gabp_svm gabp_svm;
+
+typedef enum gabp_status {
+    GABP_OK = 0,
+    GABP_E_INVALID = 1,        /* bad argument; nothing was computed */
+    GABP_E_NOMEM = 2,          /* plan does not fit the device-memory budget */
+    GABP_E_NOT_CONVERGED = 3,  /* max_sweeps reached; alpha = last iterate */
+    GABP_E_DIVERGED = 4,       /* a cavity precision P~_i - P_ji <= 0, or a
+                                  non-finite value: alpha is undefined */
+    GABP_E_DEVICE = 5,         /* HIP runtime error or no usable device */
+    GABP_E_STATE = 6,          /* call not valid in the handle's state */
+    GABP_E_BUFSIZE = 7         /* destination buffer too small */
+} gabp_status;
+
+/* Kernel K(x, z).  RBF: exp(-gamma ||x - z||^2), the kernel of every
+ * experiment in section "Experimental Results".  PRECOMPUTED: the caller
+ * passes the N x N matrix K' itself (gabp_svm_solve_kernel). */
+typedef enum gabp_kernel { GABP_KERNEL_RBF = 0, GABP_KERNEL_PRECOMPUTED = 2 } gabp_kernel;
+
+/* Diagonal weighting (subsection "GaBP Algorithm Convergence"), with
+ * r_i = sum_{j != i} |K'_ij|:
+ *   NONE:             A_ii = K'_ii
+ *   SOFTMARGIN:       A_ii = K'_ii + 1/C            (2-norm soft margin)
+ *   DOMINANT_ROW:     A_ii = max(K'_ii + 1/C, (1 + delta) r_i)   [default]
+ *   DOMINANT_UNIFORM: A_ii = K'_ii + max_k (max(K'_kk + 1/C, (1+delta) r_k) - K'_kk) */
+typedef enum gabp_diag {
+    GABP_DIAG_NONE = 0,
+    GABP_DIAG_SOFTMARGIN = 1,
+    GABP_DIAG_DOMINANT_ROW = 2,
+    GABP_DIAG_DOMINANT_UNIFORM = 3
+} gabp_diag;
+
+/* Box constraint 0 <= alpha <= C (eq. cons1).  The paper drops it; NONE
+ * reports alpha as solved, CLIP_OUTPUT reports clip(alpha, 0, C) (the sweep
+ * itself is never projected). */
+typedef enum gabp_box { GABP_BOX_NONE = 0, GABP_BOX_CLIP_OUTPUT = 1 } gabp_box;
+
+/* Arithmetic of the sweep.
+ *   FP64:  FP64 kernel entries, messages, aggregates.
+ *   FP32:  FP32 kernel entries (FP32 MFMA Gram), messages and aggregates.
+ *   MIXED: BF16 MFMA Gram with FP32 accumulation, FP32 stored messages,
+ *          FP64 aggregates and FP64 cavity denominators P~_i - P_ji. */
+typedef enum gabp_prec { GABP_PREC_FP64 = 0, GABP_PREC_FP32 = 1, GABP_PREC_MIXED = 2 } gabp_prec;
+
+/* Kernel-matrix storage: MATERIALISE keeps K' (upper triangle) in device
+ * memory; RECOMPUTE rebuilds each tile of K' from the features in every
+ * sweep.  AUTO materialises when it fits the budget. */
+typedef enum gabp_kstore {
+    GABP_KSTORE_AUTO = 0, GABP_KSTORE_MATERIALISE = 1, GABP_KSTORE_RECOMPUTE = 2
+} gabp_kstore;
+
+/* Edge (message) state: STORED keeps both directions of every pair's
+ * messages in device memory; STATELESS rebuilds them each sweep from a
+ * short history of aggregates (exact while the sweep count <= depth, a
+ * truncation with bound (max|A_ij| / min Q)^depth after). */
+typedef enum gabp_edge { GABP_EDGE_AUTO = 0, GABP_EDGE_STORED = 1, GABP_EDGE_STATELESS = 2 } gabp_edge;
+
+/* Gram of the MIXED path: one BF16 product, or the three-term split
+ * hi*hi + hi*lo + lo*hi of x = hi + lo for ~2^-16 relative accuracy. */
+typedef enum gabp_gram { GABP_GRAM_AUTO = 0, GABP_GRAM_BF16 = 1, GABP_GRAM_BF16X3 = 2 } gabp_gram;
+
+/* Where the caller's buffers live. */
+typedef enum gabp_mem { GABP_MEM_HOST = 0, GABP_MEM_DEVICE = 1 } gabp_mem;
+
+/* Stop reason of the last solve (GABP_Q_REASON). */
+typedef enum gabp_reason {
+    GABP_REASON_NONE = 0, GABP_REASON_CONVERGED = 1, GABP_REASON_MAX_SWEEPS = 2,
+    GABP_REASON_DIVERGED = 3, GABP_REASON_STAGNATED = 4
+} gabp_reason;
+
+typedef struct gabp_svm_params {
+    uint32_t struct_size;      /* sizeof(gabp_svm_params), for ABI checks */
+    int32_t kernel;            /* gabp_kernel */
+    double gamma;              /* RBF width, > 0 */
+    double C;                  /* > 0: 1/C enters the diagonal weighting */
+    double lambda_aug;         /* bias augmentation lambda; < 0 means 1/N.
+                                  lambda^2 is added to every RBF entry */
+    int32_t diag_mode;         /* gabp_diag, default DOMINANT_ROW */
+    double diag_delta;         /* dominance margin, default 0.1 */
+    int32_t box_mode;          /* gabp_box, default NONE */
+    double sv_tau;             /* support vector iff alpha_i > sv_tau (0) */
+    double tol_abs, tol_rel;   /* stop when ||alpha^t - alpha^(t-1)||_inf <=
+                                  tol_abs + tol_rel ||alpha^t||_inf */
+    int32_t max_sweeps;        /* >= 1 */
+    int32_t check_every;       /* host polls the device status every k sweeps */
+    int32_t stagnation_window; /* stop when the change has not decreased for
+                                  this many sweeps and is <= stagnation_rel
+                                  ||alpha||_inf (precision floor); 0 = off */
+    double stagnation_rel;
+    int32_t precision;         /* gabp_prec, default MIXED */
+    int32_t kstore;            /* gabp_kstore */
+    int32_t edge_state;        /* gabp_edge */
+    int32_t gram;              /* gabp_gram (MIXED only) */
+    int32_t stateless_depth;   /* STATELESS unroll depth; 0 = from the bound */
+    int32_t device;            /* HIP device ordinal */
+    uint64_t hbm_budget_bytes; /* 0 = 90% of the device's free memory */
+    int32_t time_sweeps;       /* 1: bracket every sweep kernel with HIP
+                                  events (GABP_Q_TIMINGS.sweep_kernel_ms) */
+    int32_t reserved;
+} gabp_svm_params;
+
+/* Per-phase device times of the last solve, in milliseconds (HIP events on
+ * the solve's stream). */
+typedef struct gabp_timings {
+    double stage_ms;           /* feature staging (and H2D copies) */
+    double kbuild_ms;          /* K' build (materialised) or none */
+    double diag_ms;            /* row sums + diagonal weighting + init */
+    double sweep_loop_ms;      /* all sweeps + finalize + status polls */
+    double sweep_kernel_ms;    /* sum over sweep-kernel launches (time_sweeps) */
+    int64_t sweep_launches;    /* sweep-kernel launches that did work */
+    double d2h_ms;             /* alpha download (host output) */
+    double total_ms;           /* whole solve call, host wall clock */
+} gabp_timings;
+
+/* The memory plan chosen for the last solve. */
+typedef struct gabp_plan {
+    int32_t precision, kstore, edge_state, gram;
+    int32_t tile;              /* tile edge T (pairs are processed in T x T tiles) */
+    int32_t stateless_depth;
+    int64_t n_blocks;          /* ceil(N / T) */
+    int64_t n_tiles;           /* n_blocks (n_blocks + 1) / 2 */
+    uint64_t device_bytes;     /* device memory held by the handle */
+    uint64_t alg_bytes_per_sweep; /* algorithmic HBM bytes of one sweep:
+                                     N(N-1)/2 pairs x bytes per pair */
+    double alg_bytes_per_pair;
+} gabp_plan;
+
+/* Query selectors for gabp_svm_query: dst type and size in brackets. */
+enum {
+    GABP_Q_N = 0,          /* [int64_t] N of the last solve */
+    GABP_Q_ALPHA = 1,      /* [double N] alpha (box handling applied) */
+    GABP_Q_PTILDE = 2,     /* [double N] aggregate precisions P~ (Alg. 2, "Infer") */
+    GABP_Q_ADIAG = 3,      /* [double N] weighted diagonal A_ii */
+    GABP_Q_BIAS = 4,       /* [double] b = lambda^2 sum_i alpha_i y_i */
+    GABP_Q_SV_MASK = 5,    /* [uint8_t N] 1 iff alpha_i > sv_tau */
+    GABP_Q_SV_COUNT = 6,   /* [int64_t] */
+    GABP_Q_SWEEPS = 7,     /* [int32_t] completed sweeps */
+    GABP_Q_DELTA = 8,      /* [double] last ||alpha^t - alpha^(t-1)||_inf */
+    GABP_Q_STATUS = 9,     /* [int32_t] gabp_status of the last solve */
+    GABP_Q_TIMINGS = 10,   /* [gabp_timings] */
+    GABP_Q_TRACE = 11,     /* [double sweeps] change per sweep, t = 1..sweeps */
+    GABP_Q_PLAN = 12,      /* [gabp_plan] */
+    GABP_Q_REASON = 13     /* [int32_t] gabp_reason */
+};
+
+/* Fills *p with the defaults: RBF, gamma 1, C 1, lambda 1/N, DOMINANT_ROW
+ * with delta 0.1, no box, tol_abs 0, tol_rel 1e-7, max_sweeps 1000,
+ * check_every 8, stagnation window 10 at 1e-5, MIXED, AUTO storage,
+ * device 0. */
+void gabp_svm_params_default(gabp_svm_params *p);
+
+/* Creates a solver handle on params->device.  Validates the parameters
+ * (GABP_E_INVALID), binds the device (GABP_E_DEVICE).  *out receives the
+ * handle (NULL on error). */
+gabp_status gabp_svm_create(const gabp_svm_params *params, gabp_svm **out);
+
+/* Solves the SVM of section "Proposed Solution of SVM Solver Based on GaBP"
+ * for the training set X (N x m float32, row-major) with labels y (N
+ * float32, each exactly +1 or -1).  mem tells whether X and y are host or
+ * device pointers; stream is a hipStream_t (NULL = the default stream) on
+ * which all device work runs.  Blocks until the sweeps stop.
+ * Returns GABP_OK (converged or stagnated at the precision floor),
+ * GABP_E_NOT_CONVERGED (alpha = last iterate, queryable),
+ * GABP_E_DIVERGED, GABP_E_INVALID (N < 1, m < 1, non-finite X, y not +-1,
+ * checked before any device work), GABP_E_NOMEM, GABP_E_DEVICE. */
+gabp_status gabp_svm_solve(gabp_svm *h, const float *X, const float *y,
+                           int64_t N, int64_t m, int32_t mem, void *stream);
+
+/* Same solve for a caller-supplied symmetric kernel matrix K' (N x N
+ * float64, row-major; only the upper triangle and the diagonal are read),
+ * used as is: lambda_aug is not added.  The diagonal weighting and labels
+ * apply as in gabp_svm_solve, so with y = +1 and GABP_DIAG_NONE this solves
+ * K' alpha = 1 for any symmetric K'.  Requires kernel = PRECOMPUTED and a
+ * materialised plan.  Used to test the sweep on chosen matrices. */
+gabp_status gabp_svm_solve_kernel(gabp_svm *h, const double *K, const float *y,
+                                  int64_t N, int32_t mem, void *stream);
+
+/* Copies the quantity `what` (GABP_Q_*) of the last solve into dst, which
+ * holds `bytes` bytes of host memory.  GABP_E_BUFSIZE if too small,
+ * GABP_E_STATE if no solve has run, GABP_E_INVALID for an unknown selector. */
+gabp_status gabp_svm_query(const gabp_svm *h, int32_t what, void *dst, size_t bytes);
+
+/* Entries K'_{ij} of the materialised kernel matrix of the last solve, for
+ * the `n` index pairs (rows[k], cols[k]) (host int64 arrays, i != j), as
+ * float64 into out (host).  GABP_E_STATE unless K' is materialised. */
+gabp_status gabp_svm_kernel_entries(const gabp_svm *h, const int64_t *rows,
+                                    const int64_t *cols, int64_t n, double *out);
+
+/* Decision function of section "Classification Using Support Vector
+ * Machines" with the bias carried by the augmentation:
+ * f(x) = sum_i alpha_i y_i (K(x_i, x) + lambda^2) for the nq query points
+ * Xq (nq x m float32, row-major; m of the last solve); f_out receives nq
+ * float64 values; the class is sign(f) with sign(0) = +1.  mem applies to
+ * Xq and f_out alike.  RBF solves only (GABP_E_STATE otherwise). */
+gabp_status gabp_svm_predict(gabp_svm *h, const float *Xq, int64_t nq,
+                             double *f_out, int32_t mem, void *stream);
+
+/* Frees the handle and everything it holds.  NULL is ignored. */
+void gabp_svm_destroy(gabp_svm *h);
+
+/* Static description of a status code. */
+const char *gabp_status_string(int32_t status);
+
+/* Message of the last failed call on h (empty if none); valid until the
+ * next call on h. */
+const char *gabp_svm_last_error(const gabp_svm *h);
+
+/* GABP_ABI_VERSION of the library. */
+int32_t gabp_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GABP_SVM_H */

@@ -1,0 +1,112 @@
+// Internal declarations shared by the host runtime and the HIP kernels of
+// the GaBP SVM solver.  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gabp {
+
+// Pairs {i, j}, i < j, are processed in TILE x TILE tiles of the upper
+// triangle; every per-pair device array is a sequence of full tiles stored
+// row-major (tile-local row r, column c at r * TILE + c).
+constexpr int TILE = 256;
+constexpr int TT = TILE * TILE;
+constexpr int WG = 256;               // threads per workgroup (4 wave64)
+
+enum Prec : int { PREC_FP64 = 0, PREC_FP32 = 1, PREC_MIXED = 2 };
+enum GramKind : int { GRAM_F32 = 0, GRAM_BF16 = 1, GRAM_BF16X3 = 2, GRAM_F64 = 3 };
+enum Reason : int { R_NONE = 0, R_CONVERGED = 1, R_MAX_SWEEPS = 2, R_DIVERGED = 3, R_STAGNATED = 4 };
+
+// Device-resident solve status, advanced by k_status once per sweep.  Every
+// sweep kernel returns at once when `done` is set, so the state a solve
+// stops in does not depend on how often the host polls.
+struct DevStatus {
+    int32_t t;           // completed sweeps
+    int32_t done;
+    int32_t reason;
+    int32_t since_best;  // sweeps since the smallest change so far
+    int32_t bad;         // set when a cavity precision <= 0 or a value is not finite
+    int32_t pad;
+    double delta;        // ||alpha^t - alpha^(t-1)||_inf
+    double amax;         // ||alpha^t||_inf
+    double best_delta;
+};
+
+struct StopRule {
+    double tol_abs, tol_rel, stag_rel;
+    int32_t max_sweeps, stag_window;
+};
+
+// Features staged for the Gram: row-major NPAD x m_pad, zero padded.
+struct Features {
+    const float* f32;        // GRAM_F32: centred FP32
+    const uint16_t* hi;      // GRAM_BF16/BF16X3: centred, rounded to BF16
+    const uint16_t* lo;      // GRAM_BF16X3: BF16 of the rounding remainder
+    const double* f64;       // GRAM_F64: uncentred FP64
+    const float* nrm;        // squared norms of the staged rows (FP32)
+    int32_t m_pad;
+    int32_t kind;            // GramKind
+};
+
+struct KernelParams {
+    int64_t N;
+    int32_t NB;
+    float neg_gamma_log2e;   // -gamma * log2(e): K = exp2(neg_gamma_log2e * d2)
+    double gamma;
+    double lam2;             // lambda^2 added to every RBF entry
+};
+
+inline int64_t n_tiles(int NB) { return (int64_t)NB * (NB + 1) / 2; }
+// Storage index of tile (I, J), I <= J: row-major over the upper triangle.
+__host__ __device__ inline int64_t tile_index(int I, int J, int NB) {
+    return (int64_t)I * NB - (int64_t)I * (I - 1) / 2 + (J - I);
+}
+
+// ---- launchers (gabp_kernels.hip); all asynchronous on `s` ----
+hipError_t launch_fill_tiles(uint32_t* tiles, int NB, hipStream_t s);
+hipError_t launch_validate(const float* X, const float* y, int64_t N, int64_t m,
+                           int32_t* flag, hipStream_t s);
+hipError_t launch_colmean(const float* X, int64_t N, int64_t m, double* mean, hipStream_t s);
+hipError_t launch_stage(const float* X, const double* mean, int64_t N, int64_t m,
+                        int64_t NPAD, int m_pad, int kind, float* f32, uint16_t* hi,
+                        uint16_t* lo, double* f64, float* nrm, hipStream_t s);
+hipError_t launch_gram(const Features& F, const KernelParams& kp, const uint32_t* tiles,
+                       int64_t ntiles, void* Kp, int prec, hipStream_t s);
+hipError_t launch_gather_dense(const double* K, const KernelParams& kp,
+                               const uint32_t* tiles, int64_t ntiles, void* Kp, int prec,
+                               double* kdiag, hipStream_t s);
+hipError_t launch_fill_value(double* dst, int64_t n, double v, hipStream_t s);
+hipError_t launch_rowsum(const void* Kp, int prec, const uint32_t* tiles, int64_t ntiles,
+                         int NB, double* partR, hipStream_t s);
+hipError_t launch_diag(int64_t N, int NB, const double* partR, const double* kdiag, int mode,
+                       double C, double delta, double* Adiag, double* scratch_blk,
+                       double* scratch_one, hipStream_t s);
+hipError_t launch_init(int prec, int64_t N, int64_t NPAD, const double* Adiag, const float* y,
+                       void* Pt, void* S, double* alpha, DevStatus* st, hipStream_t s);
+
+struct SweepBufs {
+    const uint32_t* tiles;
+    int64_t ntiles;
+    int NB;
+    const void* Kp;
+    void *Pf, *Pb, *Ef, *Eb;      // pair planes: P_ij, P_ji, E_ij, E_ji (i < j)
+    const void *Pt, *S;           // aggregates of the previous sweep
+    void *partP, *partE;          // [NB][NB+1][TILE] partial sums
+    DevStatus* st;
+};
+hipError_t launch_sweep_stored(int prec, bool first, const SweepBufs& b, hipStream_t s);
+hipError_t launch_finalize(int prec, int64_t N, int NB, const void* partP, const void* partE,
+                           const double* Adiag, const float* y, void* Pt, void* S,
+                           double* alpha, double* blk_delta, double* blk_amax,
+                           DevStatus* st, hipStream_t s);
+hipError_t launch_status(int nblk, const double* blk_delta, const double* blk_amax,
+                         DevStatus* st, double* trace, StopRule rule, hipStream_t s);
+hipError_t launch_kernel_entries(const void* Kp, int prec, int NB, const int64_t* rows,
+                                 const int64_t* cols, int64_t n, double* out, hipStream_t s);
+hipError_t launch_predict(const float* Xtr, const float* y, const double* alpha, int64_t N,
+                          int64_t m, const float* Xq, int64_t nq, double gamma, double lam2,
+                          bool fp64, double* f, hipStream_t s);
+hipError_t launch_convert_agg(int prec, const void* src, double* dst, int64_t n, hipStream_t s);
+
+}  // namespace gabp

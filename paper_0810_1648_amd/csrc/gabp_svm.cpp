@@ -1,0 +1,616 @@
+// Host runtime and C ABI of the GaBP SVM solver (see include/gabp_svm.h).
+//
+// A solve is: validate -> stage features -> build K' (materialised tiles) ->
+// row sums + diagonal weighting -> sweep 0 aggregates -> synchronous sweeps
+// (sweep kernel, finalize, device-side stop rule) until the device status
+// says done -> download alpha.  The host polls an 8-word status every
+// `check_every` sweeps; sweeps launched after the stop are no-ops on the
+// device, so the result does not depend on the polling period.
+#include "../../include/gabp_svm.h"
+#include "gabp_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace gabp;
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t n) {
+        if (n == 0) n = 256;
+        if (p && n <= bytes) return hipSuccess;
+        release();
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            p = nullptr;
+            bytes = 0;
+            (void)hipGetLastError();
+            return e;
+        }
+        bytes = n;
+        return hipSuccess;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct gabp_svm {
+    gabp_svm_params p{};
+    std::string err;
+    bool have_result = false;
+    bool rbf = true;
+    // geometry of the last solve
+    int64_t N = 0, m = 0, NPAD = 0, ntiles = 0;
+    int NB = 0, m_pad = 0, prec = PREC_MIXED, gram = GRAM_BF16;
+    double lam = 0.0;
+    int32_t status = GABP_E_STATE, reason = R_NONE, sweeps = 0;
+    double delta = 0.0;
+    std::vector<double> alpha, ptilde, adiag, trace;
+    std::vector<float> yh;
+    gabp_timings tm{};
+    gabp_plan plan{};
+    // device memory owned by the handle
+    DevBuf tiles, Kp, Pf, Pb, Ef, Eb, partP, partE, Xin, yd, mean, xs32, xhi, xlo, x64, nrm, kdiag,
+        Adiag, Pt, S, alpha_d, blk1, blk2, one, status_d, trace_d, flag, tmp, Kin, q_rows, q_cols,
+        q_out;
+
+    DevBuf* all[33] = {&tiles, &Kp, &Pf, &Pb, &Ef, &Eb, &partP, &partE, &Xin, &yd, &mean,
+                       &xs32, &xhi, &xlo, &x64, &nrm, &kdiag, &Adiag, &Pt, &S, &alpha_d,
+                       &blk1, &blk2, &one, &status_d, &trace_d, &flag, &tmp, &Kin, &q_rows,
+                       &q_cols, &q_out, nullptr};
+    size_t held() const {
+        size_t b = 0;
+        for (int k = 0; all[k]; ++k) b += all[k]->bytes;
+        return b;
+    }
+    void release_all() {
+        for (int k = 0; all[k]; ++k) all[k]->release();
+    }
+};
+
+namespace {
+
+gabp_status fail(gabp_svm* h, gabp_status st, const std::string& msg) {
+    if (h) h->err = msg;
+    return st;
+}
+
+#define HIPCHK(h, expr)                                                                   \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail((h), GABP_E_DEVICE,                                               \
+                        std::string(#expr ": ") + hipGetErrorString(e_));                 \
+    } while (0)
+
+gabp_status check_params(const gabp_svm_params* p, std::string& why) {
+    if (!p) { why = "params is NULL"; return GABP_E_INVALID; }
+    if (p->struct_size != sizeof(gabp_svm_params)) { why = "params.struct_size mismatch"; return GABP_E_INVALID; }
+    if (p->kernel != GABP_KERNEL_RBF && p->kernel != GABP_KERNEL_PRECOMPUTED) { why = "unknown kernel"; return GABP_E_INVALID; }
+    if (p->kernel == GABP_KERNEL_RBF && !(p->gamma > 0.0 && std::isfinite(p->gamma))) { why = "gamma must be > 0"; return GABP_E_INVALID; }
+    if (!(p->C > 0.0) || !std::isfinite(p->C)) { why = "C must be > 0"; return GABP_E_INVALID; }
+    if (p->diag_mode < 0 || p->diag_mode > 3) { why = "unknown diag_mode"; return GABP_E_INVALID; }
+    if (!(p->diag_delta >= 0.0)) { why = "diag_delta must be >= 0"; return GABP_E_INVALID; }
+    if (p->box_mode < 0 || p->box_mode > 1) { why = "unknown box_mode"; return GABP_E_INVALID; }
+    if (!(p->tol_abs >= 0.0) || !(p->tol_rel >= 0.0)) { why = "tolerances must be >= 0"; return GABP_E_INVALID; }
+    if (p->max_sweeps < 1) { why = "max_sweeps must be >= 1"; return GABP_E_INVALID; }
+    if (p->check_every < 1) { why = "check_every must be >= 1"; return GABP_E_INVALID; }
+    if (p->stagnation_window < 0) { why = "stagnation_window must be >= 0"; return GABP_E_INVALID; }
+    if (p->precision < 0 || p->precision > 2) { why = "unknown precision"; return GABP_E_INVALID; }
+    if (p->kstore < 0 || p->kstore > 2) { why = "unknown kstore"; return GABP_E_INVALID; }
+    if (p->edge_state < 0 || p->edge_state > 2) { why = "unknown edge_state"; return GABP_E_INVALID; }
+    if (p->gram < 0 || p->gram > 2) { why = "unknown gram"; return GABP_E_INVALID; }
+    if (p->stateless_depth < 0 || p->stateless_depth > 16) { why = "stateless_depth must be in [0, 16]"; return GABP_E_INVALID; }
+    return GABP_OK;
+}
+
+struct EventPool {
+    std::vector<hipEvent_t> ev;
+    ~EventPool() { for (auto e : ev) (void)hipEventDestroy(e); }
+    hipError_t make(size_t n) {
+        while (ev.size() < n) {
+            hipEvent_t e;
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+            ev.push_back(e);
+        }
+        return hipSuccess;
+    }
+};
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) { (void)hipGetLastError(); return 0.0f; }
+    return ms;
+}
+
+// One solve, for RBF features (X != nullptr) or a dense kernel (K != nullptr).
+gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float* y, int64_t N,
+                       int64_t m, int32_t mem, hipStream_t s) {
+    const double t_start = now_ms();
+    const gabp_svm_params& p = h->p;
+    h->have_result = false;
+    h->err.clear();
+    if (!y || N < 1 || (X && m < 1) || (!X && !K)) return fail(h, GABP_E_INVALID, "need N >= 1, m >= 1 and non-NULL inputs");
+    if (mem != GABP_MEM_HOST && mem != GABP_MEM_DEVICE) return fail(h, GABP_E_INVALID, "unknown mem kind");
+    if (N > (int64_t)TILE * 65535) return fail(h, GABP_E_INVALID, "N too large for 16-bit tile coordinates");
+    const bool rbf = (X != nullptr);
+    if (rbf && p.kernel != GABP_KERNEL_RBF) return fail(h, GABP_E_INVALID, "gabp_svm_solve needs kernel = RBF");
+    if (!rbf && p.kernel != GABP_KERNEL_PRECOMPUTED) return fail(h, GABP_E_INVALID, "gabp_svm_solve_kernel needs kernel = PRECOMPUTED");
+
+    // host-side validation, before any device work
+    if (mem == GABP_MEM_HOST) {
+        if (rbf) {
+            for (int64_t k = 0; k < N * m; ++k)
+                if (!std::isfinite(X[k])) return fail(h, GABP_E_INVALID, "X has a non-finite entry");
+        } else {
+            for (int64_t k = 0; k < N * N; ++k)
+                if (!std::isfinite(K[k])) return fail(h, GABP_E_INVALID, "K has a non-finite entry");
+        }
+        for (int64_t k = 0; k < N; ++k)
+            if (!(y[k] == 1.0f || y[k] == -1.0f)) return fail(h, GABP_E_INVALID, "labels must be +1 or -1");
+    }
+
+    // ---- plan
+    const int prec = p.precision;
+    int gram = GRAM_F32;
+    if (prec == PREC_FP64) gram = GRAM_F64;
+    else if (prec == PREC_MIXED) gram = (p.gram == GABP_GRAM_BF16X3) ? GRAM_BF16X3 : GRAM_BF16;
+    if (p.kstore == GABP_KSTORE_RECOMPUTE) return fail(h, GABP_E_INVALID, "kstore RECOMPUTE is not available in this build");
+    if (p.edge_state == GABP_EDGE_STATELESS) return fail(h, GABP_E_INVALID, "edge_state STATELESS is not available in this build");
+    const int NB = (int)((N + TILE - 1) / TILE);
+    const int64_t NPAD = (int64_t)NB * TILE;
+    const int64_t nt = n_tiles(NB);
+    const int m_pad = rbf ? (int)((m + 15) / 16 * 16) : 16;
+    const size_t st_bytes = (prec == PREC_FP64) ? 8 : 4;
+    const size_t plane = (size_t)nt * TT * st_bytes;
+    const size_t part = (size_t)NB * (NB + 1) * TILE * sizeof(double);
+    size_t feat = 0;
+    if (rbf) {
+        switch (gram) {
+            case GRAM_F32: feat = (size_t)NPAD * m_pad * 4; break;
+            case GRAM_BF16: feat = (size_t)NPAD * m_pad * 2; break;
+            case GRAM_BF16X3: feat = (size_t)NPAD * m_pad * 4; break;
+            default: feat = (size_t)NPAD * m_pad * 8; break;
+        }
+        feat += (size_t)N * m * 4 + (size_t)NPAD * 4 + (size_t)m * 8;
+    } else if (mem == GABP_MEM_HOST) {
+        feat = (size_t)N * N * 8;
+    }
+    const size_t vecs = (size_t)NPAD * 8 * 8 + (size_t)nt * 4 + (size_t)p.max_sweeps * 8 + 4096;
+    const size_t need = 5 * plane + 2 * part + feat + vecs;
+    size_t free_b = 0, total_b = 0;
+    HIPCHK(h, hipSetDevice(p.device));
+    HIPCHK(h, hipMemGetInfo(&free_b, &total_b));
+    const size_t avail = free_b + h->held();
+    const size_t budget = p.hbm_budget_bytes ? (size_t)p.hbm_budget_bytes : (size_t)(0.92 * (double)avail);
+    if (need > budget) {
+        char msg[256];
+        snprintf(msg, sizeof msg, "plan needs %.3f GB, budget %.3f GB", need / 1e9, budget / 1e9);
+        return fail(h, GABP_E_NOMEM, msg);
+    }
+    if (need > avail) h->release_all();
+
+    auto alloc = [&](DevBuf& b, size_t n) -> hipError_t { return b.ensure(n); };
+    hipError_t ae = hipSuccess;
+    auto A = [&](DevBuf& b, size_t n) { if (ae == hipSuccess) ae = alloc(b, n); };
+    A(h->tiles, (size_t)nt * 4);
+    A(h->Kp, plane);
+    A(h->Pf, plane); A(h->Pb, plane); A(h->Ef, plane); A(h->Eb, plane);
+    A(h->partP, part); A(h->partE, part);
+    A(h->yd, (size_t)N * 4);
+    A(h->kdiag, (size_t)N * 8); A(h->Adiag, (size_t)N * 8);
+    A(h->Pt, (size_t)NPAD * 8); A(h->S, (size_t)NPAD * 8);
+    A(h->alpha_d, (size_t)N * 8); A(h->tmp, (size_t)NPAD * 8);
+    A(h->blk1, (size_t)(NPAD / WG + 1) * 8); A(h->blk2, (size_t)(NPAD / WG + 1) * 8);
+    A(h->one, 64); A(h->status_d, sizeof(DevStatus)); A(h->flag, 64);
+    A(h->trace_d, (size_t)p.max_sweeps * 8);
+    if (rbf) {
+        A(h->Xin, (size_t)N * m * 4); A(h->mean, (size_t)m * 8); A(h->nrm, (size_t)NPAD * 4);
+        if (gram == GRAM_F32) A(h->xs32, (size_t)NPAD * m_pad * 4);
+        if (gram == GRAM_BF16 || gram == GRAM_BF16X3) A(h->xhi, (size_t)NPAD * m_pad * 2);
+        if (gram == GRAM_BF16X3) A(h->xlo, (size_t)NPAD * m_pad * 2);
+        if (gram == GRAM_F64) A(h->x64, (size_t)NPAD * m_pad * 8);
+    } else if (mem == GABP_MEM_HOST) {
+        A(h->Kin, (size_t)N * N * 8);
+    }
+    if (ae != hipSuccess) {
+        h->release_all();
+        return fail(h, GABP_E_NOMEM, std::string("device allocation failed: ") + hipGetErrorString(ae));
+    }
+
+    EventPool evp;
+    const int ce = p.check_every;
+    HIPCHK(h, evp.make(6 + 2 * (size_t)ce));
+    hipEvent_t* ev = evp.ev.data();
+    hipEvent_t* sev = ev + 6;
+
+    // ---- inputs and staging
+    HIPCHK(h, hipEventRecord(ev[0], s));
+    const float* Xd = nullptr;
+    const double* Kd = nullptr;
+    if (mem == GABP_MEM_HOST) {
+        HIPCHK(h, hipMemcpyAsync(h->yd.p, y, (size_t)N * 4, hipMemcpyHostToDevice, s));
+        if (rbf) HIPCHK(h, hipMemcpyAsync(h->Xin.p, X, (size_t)N * m * 4, hipMemcpyHostToDevice, s));
+        else HIPCHK(h, hipMemcpyAsync(h->Kin.p, K, (size_t)N * N * 8, hipMemcpyHostToDevice, s));
+        Xd = h->Xin.as<float>();
+        Kd = h->Kin.as<double>();
+    } else {
+        HIPCHK(h, hipMemcpyAsync(h->yd.p, y, (size_t)N * 4, hipMemcpyDeviceToDevice, s));
+        if (rbf) HIPCHK(h, hipMemcpyAsync(h->Xin.p, X, (size_t)N * m * 4, hipMemcpyDeviceToDevice, s));
+        Xd = h->Xin.as<float>();
+        Kd = K;
+        // device-side validation of device inputs
+        HIPCHK(h, hipMemsetAsync(h->flag.p, 0, 4, s));
+        HIPCHK(h, launch_validate(rbf ? Xd : nullptr, h->yd.as<float>(), N, rbf ? m : 0, h->flag.as<int32_t>(), s));
+        int32_t fl = 0;
+        HIPCHK(h, hipMemcpyAsync(&fl, h->flag.p, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+        if (fl & 1) return fail(h, GABP_E_INVALID, "X has a non-finite entry");
+        if (fl & 2) return fail(h, GABP_E_INVALID, "labels must be +1 or -1");
+    }
+    const double lam = (p.lambda_aug < 0.0) ? 1.0 / (double)N : p.lambda_aug;
+    KernelParams kp{};
+    kp.N = N;
+    kp.NB = NB;
+    kp.gamma = p.gamma;
+    kp.neg_gamma_log2e = (float)(-p.gamma * 1.4426950408889634);
+    kp.lam2 = rbf ? lam * lam : 0.0;
+    Features F{};
+    F.m_pad = m_pad;
+    F.kind = gram;
+    if (rbf) {
+        if (gram != GRAM_F64) HIPCHK(h, launch_colmean(Xd, N, m, h->mean.as<double>(), s));
+        HIPCHK(h, launch_stage(Xd, h->mean.as<double>(), N, m, NPAD, m_pad, gram, h->xs32.as<float>(),
+                               h->xhi.as<uint16_t>(), h->xlo.as<uint16_t>(), h->x64.as<double>(),
+                               h->nrm.as<float>(), s));
+        F.f32 = h->xs32.as<float>();
+        F.hi = h->xhi.as<uint16_t>();
+        F.lo = h->xlo.as<uint16_t>();
+        F.f64 = h->x64.as<double>();
+        F.nrm = h->nrm.as<float>();
+    }
+    HIPCHK(h, hipEventRecord(ev[1], s));
+
+    // ---- K' tiles
+    HIPCHK(h, launch_fill_tiles(h->tiles.as<uint32_t>(), NB, s));
+    if (rbf) {
+        HIPCHK(h, launch_gram(F, kp, h->tiles.as<uint32_t>(), nt, h->Kp.p, prec, s));
+        HIPCHK(h, launch_fill_value(h->kdiag.as<double>(), N, 1.0 + lam * lam, s));
+    } else {
+        HIPCHK(h, launch_gather_dense(Kd, kp, h->tiles.as<uint32_t>(), nt, h->Kp.p, prec,
+                                      h->kdiag.as<double>(), s));
+    }
+    HIPCHK(h, hipEventRecord(ev[2], s));
+
+    // ---- diagonal weighting and sweep 0
+    HIPCHK(h, launch_rowsum(h->Kp.p, prec, h->tiles.as<uint32_t>(), nt, NB, h->partP.as<double>(), s));
+    HIPCHK(h, launch_diag(N, NB, h->partP.as<double>(), h->kdiag.as<double>(), p.diag_mode, p.C,
+                          p.diag_delta, h->Adiag.as<double>(), h->blk1.as<double>(),
+                          h->one.as<double>(), s));
+    DevStatus* st = h->status_d.as<DevStatus>();
+    HIPCHK(h, launch_init(prec, N, NPAD, h->Adiag.as<double>(), h->yd.as<float>(), h->Pt.p, h->S.p,
+                          h->alpha_d.as<double>(), st, s));
+    HIPCHK(h, hipEventRecord(ev[3], s));
+
+    // ---- sweeps
+    SweepBufs sb{};
+    sb.tiles = h->tiles.as<uint32_t>();
+    sb.ntiles = nt;
+    sb.NB = NB;
+    sb.Kp = h->Kp.p;
+    sb.Pf = h->Pf.p; sb.Pb = h->Pb.p; sb.Ef = h->Ef.p; sb.Eb = h->Eb.p;
+    sb.Pt = h->Pt.p; sb.S = h->S.p;
+    sb.partP = h->partP.p; sb.partE = h->partE.p;
+    sb.st = st;
+    StopRule rule{p.tol_abs, p.tol_rel, p.stagnation_rel, p.max_sweeps, p.stagnation_window};
+    const int nblk = (int)((N + WG - 1) / WG);
+    DevStatus hs{};
+    double sweep_kernel_ms = 0.0;
+    int64_t launches = 0;
+    int polled = 0;
+    for (int t = 0; t < p.max_sweeps; ++t) {
+        const int slot = t % ce;
+        if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot], s));
+        HIPCHK(h, launch_sweep_stored(prec, t == 0, sb, s));
+        if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot + 1], s));
+        HIPCHK(h, launch_finalize(prec, N, NB, h->partP.p, h->partE.p, h->Adiag.as<double>(),
+                                  h->yd.as<float>(), h->Pt.p, h->S.p, h->alpha_d.as<double>(),
+                                  h->blk1.as<double>(), h->blk2.as<double>(), st, s));
+        HIPCHK(h, launch_status(nblk, h->blk1.as<double>(), h->blk2.as<double>(), st,
+                                h->trace_d.as<double>(), rule, s));
+        if ((t + 1) % ce == 0 || t + 1 == p.max_sweeps) {
+            HIPCHK(h, hipMemcpyAsync(&hs, st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+            HIPCHK(h, hipStreamSynchronize(s));
+            if (p.time_sweeps) {
+                for (int u = polled; u <= t; ++u) {
+                    if (u >= hs.t) break;
+                    sweep_kernel_ms += elapsed(sev[2 * (u % ce)], sev[2 * (u % ce) + 1]);
+                    ++launches;
+                }
+            }
+            polled = t + 1;
+            if (hs.done) break;
+        }
+    }
+    HIPCHK(h, hipEventRecord(ev[4], s));
+
+    // ---- outputs
+    h->alpha.assign((size_t)N, 0.0);
+    h->ptilde.assign((size_t)N, 0.0);
+    h->adiag.assign((size_t)N, 0.0);
+    h->yh.assign((size_t)N, 0.0f);
+    HIPCHK(h, launch_convert_agg(prec, h->Pt.p, h->tmp.as<double>(), N, s));
+    HIPCHK(h, hipMemcpyAsync(h->alpha.data(), h->alpha_d.p, (size_t)N * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipMemcpyAsync(h->ptilde.data(), h->tmp.p, (size_t)N * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipMemcpyAsync(h->adiag.data(), h->Adiag.p, (size_t)N * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipMemcpyAsync(h->yh.data(), h->yd.p, (size_t)N * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipMemcpyAsync(&hs, st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipEventRecord(ev[5], s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    h->trace.assign((size_t)std::max(hs.t, 0), 0.0);
+    if (hs.t > 0)
+        HIPCHK(h, hipMemcpy(h->trace.data(), h->trace_d.p, (size_t)hs.t * 8, hipMemcpyDeviceToHost));
+
+    h->N = N; h->m = rbf ? m : 0; h->NB = NB; h->NPAD = NPAD; h->ntiles = nt; h->m_pad = m_pad;
+    h->prec = prec; h->gram = gram; h->lam = lam; h->rbf = rbf;
+    h->sweeps = hs.t;
+    h->delta = hs.delta;
+    h->reason = hs.reason;
+    switch (hs.reason) {
+        case R_CONVERGED: case R_STAGNATED: h->status = GABP_OK; break;
+        case R_DIVERGED: h->status = GABP_E_DIVERGED; break;
+        default: h->status = GABP_E_NOT_CONVERGED; break;
+    }
+    h->tm = gabp_timings{};
+    h->tm.stage_ms = elapsed(ev[0], ev[1]);
+    h->tm.kbuild_ms = elapsed(ev[1], ev[2]);
+    h->tm.diag_ms = elapsed(ev[2], ev[3]);
+    h->tm.sweep_loop_ms = elapsed(ev[3], ev[4]);
+    h->tm.sweep_kernel_ms = sweep_kernel_ms;
+    h->tm.sweep_launches = launches;
+    h->tm.d2h_ms = elapsed(ev[4], ev[5]);
+    h->tm.total_ms = now_ms() - t_start;
+    h->plan = gabp_plan{};
+    h->plan.precision = prec;
+    h->plan.kstore = GABP_KSTORE_MATERIALISE;
+    h->plan.edge_state = GABP_EDGE_STORED;
+    h->plan.gram = (gram == GRAM_BF16X3) ? GABP_GRAM_BF16X3 : (gram == GRAM_BF16 ? GABP_GRAM_BF16 : GABP_GRAM_AUTO);
+    h->plan.tile = TILE;
+    h->plan.stateless_depth = 0;
+    h->plan.n_blocks = NB;
+    h->plan.n_tiles = nt;
+    h->plan.device_bytes = h->held();
+    h->plan.alg_bytes_per_pair = 9.0 * (double)st_bytes;
+    h->plan.alg_bytes_per_sweep = (uint64_t)((double)N * (double)(N - 1) / 2.0 * h->plan.alg_bytes_per_pair);
+    h->have_result = true;
+    if (h->status != GABP_OK) {
+        h->err = (h->status == GABP_E_DIVERGED) ? "GaBP diverged: a cavity precision became <= 0 or non-finite"
+                                                : "max_sweeps reached before the stop rule held";
+    }
+    return (gabp_status)h->status;
+}
+
+std::vector<double> boxed_alpha(const gabp_svm* h) {
+    std::vector<double> a = h->alpha;
+    if (h->p.box_mode == GABP_BOX_CLIP_OUTPUT)
+        for (auto& v : a) v = std::min(std::max(v, 0.0), h->p.C);
+    return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t gabp_abi_version(void) { return GABP_ABI_VERSION; }
+
+const char* gabp_status_string(int32_t s) {
+    switch (s) {
+        case GABP_OK: return "ok";
+        case GABP_E_INVALID: return "invalid argument";
+        case GABP_E_NOMEM: return "plan does not fit the device-memory budget";
+        case GABP_E_NOT_CONVERGED: return "not converged within max_sweeps";
+        case GABP_E_DIVERGED: return "diverged";
+        case GABP_E_DEVICE: return "device error";
+        case GABP_E_STATE: return "invalid state";
+        case GABP_E_BUFSIZE: return "buffer too small";
+        default: return "unknown status";
+    }
+}
+
+void gabp_svm_params_default(gabp_svm_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->struct_size = sizeof(gabp_svm_params);
+    p->kernel = GABP_KERNEL_RBF;
+    p->gamma = 1.0;
+    p->C = 1.0;
+    p->lambda_aug = -1.0;
+    p->diag_mode = GABP_DIAG_DOMINANT_ROW;
+    p->diag_delta = 0.1;
+    p->box_mode = GABP_BOX_NONE;
+    p->sv_tau = 0.0;
+    p->tol_abs = 0.0;
+    p->tol_rel = 1e-7;
+    p->max_sweeps = 1000;
+    p->check_every = 8;
+    p->stagnation_window = 10;
+    p->stagnation_rel = 1e-5;
+    p->precision = GABP_PREC_MIXED;
+    p->kstore = GABP_KSTORE_AUTO;
+    p->edge_state = GABP_EDGE_AUTO;
+    p->gram = GABP_GRAM_AUTO;
+    p->stateless_depth = 0;
+    p->device = 0;
+    p->hbm_budget_bytes = 0;
+    p->time_sweeps = 0;
+}
+
+gabp_status gabp_svm_create(const gabp_svm_params* params, gabp_svm** out) {
+    if (!out) return GABP_E_INVALID;
+    *out = nullptr;
+    std::string why;
+    gabp_status st = check_params(params, why);
+    if (st != GABP_OK) return st;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) { (void)hipGetLastError(); return GABP_E_DEVICE; }
+    if (params->device < 0 || params->device >= ndev) return GABP_E_INVALID;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, params->device) != hipSuccess) return GABP_E_DEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return GABP_E_DEVICE;
+    gabp_svm* h = new (std::nothrow) gabp_svm();
+    if (!h) return GABP_E_NOMEM;
+    h->p = *params;
+    *out = h;
+    return GABP_OK;
+}
+
+gabp_status gabp_svm_solve(gabp_svm* h, const float* X, const float* y, int64_t N, int64_t m,
+                           int32_t mem, void* stream) {
+    if (!h) return GABP_E_INVALID;
+    if (!X) return fail(h, GABP_E_INVALID, "X is NULL");
+    return solve_impl(h, X, nullptr, y, N, m, mem, (hipStream_t)stream);
+}
+
+gabp_status gabp_svm_solve_kernel(gabp_svm* h, const double* K, const float* y, int64_t N,
+                                  int32_t mem, void* stream) {
+    if (!h) return GABP_E_INVALID;
+    if (!K) return fail(h, GABP_E_INVALID, "K is NULL");
+    return solve_impl(h, nullptr, K, y, N, 0, mem, (hipStream_t)stream);
+}
+
+gabp_status gabp_svm_query(const gabp_svm* h, int32_t what, void* dst, size_t bytes) {
+    if (!h || !dst) return GABP_E_INVALID;
+    if (!h->have_result && what != GABP_Q_STATUS) return GABP_E_STATE;
+    const size_t N = (size_t)h->N;
+    auto put = [&](const void* src, size_t n) -> gabp_status {
+        if (bytes < n) return GABP_E_BUFSIZE;
+        std::memcpy(dst, src, n);
+        return GABP_OK;
+    };
+    switch (what) {
+        case GABP_Q_N: { int64_t v = h->N; return put(&v, sizeof v); }
+        case GABP_Q_ALPHA: { auto a = boxed_alpha(h); return put(a.data(), N * 8); }
+        case GABP_Q_PTILDE: return put(h->ptilde.data(), N * 8);
+        case GABP_Q_ADIAG: return put(h->adiag.data(), N * 8);
+        case GABP_Q_BIAS: {
+            auto a = boxed_alpha(h);
+            double b = 0.0;
+            for (size_t i = 0; i < N; ++i) b += a[i] * (double)h->yh[i];
+            b *= h->rbf ? h->lam * h->lam : 0.0;
+            return put(&b, sizeof b);
+        }
+        case GABP_Q_SV_MASK: {
+            if (bytes < N) return GABP_E_BUFSIZE;
+            auto a = boxed_alpha(h);
+            uint8_t* o = static_cast<uint8_t*>(dst);
+            for (size_t i = 0; i < N; ++i) o[i] = a[i] > h->p.sv_tau ? 1 : 0;
+            return GABP_OK;
+        }
+        case GABP_Q_SV_COUNT: {
+            auto a = boxed_alpha(h);
+            int64_t c = 0;
+            for (size_t i = 0; i < N; ++i) c += a[i] > h->p.sv_tau ? 1 : 0;
+            return put(&c, sizeof c);
+        }
+        case GABP_Q_SWEEPS: return put(&h->sweeps, sizeof h->sweeps);
+        case GABP_Q_DELTA: return put(&h->delta, sizeof h->delta);
+        case GABP_Q_STATUS: return put(&h->status, sizeof h->status);
+        case GABP_Q_TIMINGS: return put(&h->tm, sizeof h->tm);
+        case GABP_Q_TRACE: return put(h->trace.data(), h->trace.size() * 8);
+        case GABP_Q_PLAN: return put(&h->plan, sizeof h->plan);
+        case GABP_Q_REASON: return put(&h->reason, sizeof h->reason);
+        default: return GABP_E_INVALID;
+    }
+}
+
+gabp_status gabp_svm_kernel_entries(const gabp_svm* hc, const int64_t* rows, const int64_t* cols,
+                                    int64_t n, double* out) {
+    gabp_svm* h = const_cast<gabp_svm*>(hc);
+    if (!h || !rows || !cols || !out || n < 0) return GABP_E_INVALID;
+    if (!h->have_result) return GABP_E_STATE;
+    if (n == 0) return GABP_OK;
+    for (int64_t k = 0; k < n; ++k)
+        if (rows[k] < 0 || cols[k] < 0 || rows[k] >= h->N || cols[k] >= h->N || rows[k] == cols[k])
+            return fail(h, GABP_E_INVALID, "index pair out of range or on the diagonal");
+    HIPCHK(h, hipSetDevice(h->p.device));
+    if (h->q_rows.ensure((size_t)n * 8) != hipSuccess || h->q_cols.ensure((size_t)n * 8) != hipSuccess ||
+        h->q_out.ensure((size_t)n * 8) != hipSuccess)
+        return fail(h, GABP_E_NOMEM, "device allocation failed");
+    HIPCHK(h, hipMemcpy(h->q_rows.p, rows, (size_t)n * 8, hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(h->q_cols.p, cols, (size_t)n * 8, hipMemcpyHostToDevice));
+    HIPCHK(h, launch_kernel_entries(h->Kp.p, h->prec, h->NB, h->q_rows.as<int64_t>(),
+                                    h->q_cols.as<int64_t>(), n, h->q_out.as<double>(), nullptr));
+    HIPCHK(h, hipMemcpy(out, h->q_out.p, (size_t)n * 8, hipMemcpyDeviceToHost));
+    return GABP_OK;
+}
+
+gabp_status gabp_svm_predict(gabp_svm* h, const float* Xq, int64_t nq, double* f_out, int32_t mem,
+                             void* stream) {
+    if (!h || !Xq || !f_out || nq < 0) return GABP_E_INVALID;
+    if (!h->have_result || !h->rbf) return fail(h, GABP_E_STATE, "predict needs a finished RBF solve");
+    if (nq == 0) return GABP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(h, hipSetDevice(h->p.device));
+    const size_t m = (size_t)h->m;
+    DevBuf xq, fo, al;
+    if (mem == GABP_MEM_HOST) {
+        for (int64_t k = 0; k < nq * (int64_t)m; ++k)
+            if (!std::isfinite(Xq[k])) return fail(h, GABP_E_INVALID, "Xq has a non-finite entry");
+    }
+    if (xq.ensure((size_t)nq * m * 4) != hipSuccess || fo.ensure((size_t)nq * 8) != hipSuccess ||
+        al.ensure((size_t)h->N * 8) != hipSuccess) {
+        xq.release(); fo.release(); al.release();
+        return fail(h, GABP_E_NOMEM, "device allocation failed");
+    }
+    auto a = boxed_alpha(h);
+    gabp_status rc = GABP_OK;
+    do {
+        if (hipMemcpyAsync(al.p, a.data(), (size_t)h->N * 8, hipMemcpyHostToDevice, s) != hipSuccess) { rc = GABP_E_DEVICE; break; }
+        const float* xqd = Xq;
+        if (mem == GABP_MEM_HOST) {
+            if (hipMemcpyAsync(xq.p, Xq, (size_t)nq * m * 4, hipMemcpyHostToDevice, s) != hipSuccess) { rc = GABP_E_DEVICE; break; }
+            xqd = xq.as<float>();
+        }
+        double* fd = (mem == GABP_MEM_HOST) ? fo.as<double>() : f_out;
+        if (launch_predict(h->Xin.as<float>(), h->yd.as<float>(), al.as<double>(), h->N, (int64_t)m, xqd,
+                           nq, h->p.gamma, h->lam * h->lam, h->prec == PREC_FP64, fd, s) != hipSuccess) { rc = GABP_E_DEVICE; break; }
+        if (mem == GABP_MEM_HOST &&
+            hipMemcpyAsync(f_out, fo.p, (size_t)nq * 8, hipMemcpyDeviceToHost, s) != hipSuccess) { rc = GABP_E_DEVICE; break; }
+        if (hipStreamSynchronize(s) != hipSuccess) { rc = GABP_E_DEVICE; break; }
+    } while (0);
+    xq.release(); fo.release(); al.release();
+    if (rc != GABP_OK) return fail(h, rc, "predict failed on the device");
+    return GABP_OK;
+}
+
+void gabp_svm_destroy(gabp_svm* h) {
+    if (!h) return;
+    (void)hipSetDevice(h->p.device);
+    h->release_all();
+    delete h;
+}
+
+const char* gabp_svm_last_error(const gabp_svm* h) { return h ? h->err.c_str() : ""; }
+
+}  // extern "C"

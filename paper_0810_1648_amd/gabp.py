@@ -1,0 +1,302 @@
+"""Python binding of the GaBP SVM C ABI (include/gabp_svm.h).
+
+Argument marshalling only: every step of the solve runs in the HIP kernels
+of libgabp_svm.so.  Inputs may be NumPy arrays (host memory) or torch CUDA
+tensors (device memory, read on the current torch stream).  There is no
+fallback: if the library is not built, or no gfx950 device is usable, the
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgabp_svm.so")
+
+# enums (mirrors of the header)
+OK, E_INVALID, E_NOMEM, E_NOT_CONVERGED, E_DIVERGED, E_DEVICE, E_STATE, E_BUFSIZE = range(8)
+KERNEL_RBF, KERNEL_PRECOMPUTED = 0, 2
+DIAG = {"none": 0, "softmargin": 1, "dominant_row": 2, "dominant_uniform": 3}
+BOX = {"none": 0, "clip_output": 1}
+PREC = {"fp64": 0, "fp32": 1, "mixed": 2}
+KSTORE = {"auto": 0, "materialise": 1, "recompute": 2}
+EDGE = {"auto": 0, "stored": 1, "stateless": 2}
+GRAM = {"auto": 0, "bf16": 1, "bf16x3": 2}
+MEM_HOST, MEM_DEVICE = 0, 1
+REASON = {0: "none", 1: "converged", 2: "max_sweeps", 3: "diverged", 4: "stagnated"}
+Q_N, Q_ALPHA, Q_PTILDE, Q_ADIAG, Q_BIAS, Q_SV_MASK, Q_SV_COUNT, Q_SWEEPS, Q_DELTA, Q_STATUS, \
+    Q_TIMINGS, Q_TRACE, Q_PLAN, Q_REASON = range(14)
+
+
+class Params(ct.Structure):
+    _fields_ = [
+        ("struct_size", ct.c_uint32), ("kernel", ct.c_int32), ("gamma", ct.c_double),
+        ("C", ct.c_double), ("lambda_aug", ct.c_double), ("diag_mode", ct.c_int32),
+        ("diag_delta", ct.c_double), ("box_mode", ct.c_int32), ("sv_tau", ct.c_double),
+        ("tol_abs", ct.c_double), ("tol_rel", ct.c_double), ("max_sweeps", ct.c_int32),
+        ("check_every", ct.c_int32), ("stagnation_window", ct.c_int32),
+        ("stagnation_rel", ct.c_double), ("precision", ct.c_int32), ("kstore", ct.c_int32),
+        ("edge_state", ct.c_int32), ("gram", ct.c_int32), ("stateless_depth", ct.c_int32),
+        ("device", ct.c_int32), ("hbm_budget_bytes", ct.c_uint64), ("time_sweeps", ct.c_int32),
+        ("reserved", ct.c_int32),
+    ]
+
+
+class Timings(ct.Structure):
+    _fields_ = [("stage_ms", ct.c_double), ("kbuild_ms", ct.c_double), ("diag_ms", ct.c_double),
+                ("sweep_loop_ms", ct.c_double), ("sweep_kernel_ms", ct.c_double),
+                ("sweep_launches", ct.c_int64), ("d2h_ms", ct.c_double), ("total_ms", ct.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Plan(ct.Structure):
+    _fields_ = [("precision", ct.c_int32), ("kstore", ct.c_int32), ("edge_state", ct.c_int32),
+                ("gram", ct.c_int32), ("tile", ct.c_int32), ("stateless_depth", ct.c_int32),
+                ("n_blocks", ct.c_int64), ("n_tiles", ct.c_int64), ("device_bytes", ct.c_uint64),
+                ("alg_bytes_per_sweep", ct.c_uint64), ("alg_bytes_per_pair", ct.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class GabpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Loads libgabp_svm.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build()")
+        L = ct.CDLL(LIB_PATH)
+        vp, i32, i64, sz = ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_size_t
+        L.gabp_svm_params_default.argtypes = [ct.POINTER(Params)]
+        L.gabp_svm_params_default.restype = None
+        L.gabp_svm_create.argtypes = [ct.POINTER(Params), ct.POINTER(vp)]
+        L.gabp_svm_create.restype = i32
+        L.gabp_svm_solve.argtypes = [vp, vp, vp, i64, i64, i32, vp]
+        L.gabp_svm_solve.restype = i32
+        L.gabp_svm_solve_kernel.argtypes = [vp, vp, vp, i64, i32, vp]
+        L.gabp_svm_solve_kernel.restype = i32
+        L.gabp_svm_query.argtypes = [vp, i32, vp, sz]
+        L.gabp_svm_query.restype = i32
+        L.gabp_svm_kernel_entries.argtypes = [vp, vp, vp, i64, vp]
+        L.gabp_svm_kernel_entries.restype = i32
+        L.gabp_svm_predict.argtypes = [vp, vp, i64, vp, i32, vp]
+        L.gabp_svm_predict.restype = i32
+        L.gabp_svm_destroy.argtypes = [vp]
+        L.gabp_svm_destroy.restype = None
+        L.gabp_status_string.argtypes = [i32]
+        L.gabp_status_string.restype = ct.c_char_p
+        L.gabp_svm_last_error.argtypes = [vp]
+        L.gabp_svm_last_error.restype = ct.c_char_p
+        L.gabp_abi_version.argtypes = []
+        L.gabp_abi_version.restype = i32
+        _lib = L
+    return _lib
+
+
+def default_params() -> Params:
+    p = Params()
+    lib().gabp_svm_params_default(ct.byref(p))
+    return p
+
+
+def make_params(**kw) -> Params:
+    """Defaults of the library, overridden by keyword arguments; enum fields
+    accept the lower-case names of the header (e.g. precision="fp32")."""
+    p = default_params()
+    maps = {"diag_mode": DIAG, "box_mode": BOX, "precision": PREC, "kstore": KSTORE,
+            "edge_state": EDGE, "gram": GRAM}
+    for k, v in kw.items():
+        if k in maps and isinstance(v, str):
+            v = maps[k][v]
+        if k == "kernel" and isinstance(v, str):
+            v = KERNEL_RBF if v == "rbf" else KERNEL_PRECOMPUTED
+        if not hasattr(p, k):
+            raise TypeError(f"unknown parameter {k!r}")
+        setattr(p, k, v)
+    return p
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x, dtype):
+    """(pointer, mem kind, keep-alive) for a NumPy array or torch tensor."""
+    if _is_torch(x):
+        import torch
+        want = {np.float32: torch.float32, np.float64: torch.float64}[dtype]
+        if x.dtype != want or not x.is_contiguous():
+            raise TypeError(f"tensor must be contiguous {want}")
+        return ct.c_void_p(x.data_ptr()), (MEM_DEVICE if x.is_cuda else MEM_HOST), x
+    a = np.ascontiguousarray(x, dtype=dtype)
+    return a.ctypes.data_as(ct.c_void_p), MEM_HOST, a
+
+
+def _stream_of(x, stream):
+    if stream is not None:
+        return ct.c_void_p(int(stream))
+    if _is_torch(x) and x.is_cuda:
+        import torch
+        return ct.c_void_p(torch.cuda.current_stream(x.device).cuda_stream)
+    return ct.c_void_p(0)
+
+
+class GabpSVM:
+    """One solver handle (gabp_svm_create / solve / query / predict / destroy)."""
+
+    def __init__(self, params: Params | None = None, **kw):
+        self.params = params if params is not None else make_params(**kw)
+        h = ct.c_void_p()
+        st = lib().gabp_svm_create(ct.byref(self.params), ct.byref(h))
+        if st != OK:
+            raise GabpError(st, "gabp_svm_create failed: " + lib().gabp_status_string(st).decode())
+        self._h = h
+        self.last_status = None
+
+    # -- lifecycle
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gabp_svm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _err(self, st, what):
+        msg = lib().gabp_svm_last_error(self._h).decode()
+        return GabpError(st, f"{what}: {lib().gabp_status_string(st).decode()}: {msg}")
+
+    # -- solves
+    def solve(self, X, y, stream=None, raise_on=(E_INVALID, E_NOMEM, E_DEVICE, E_STATE)):
+        """Runs gabp_svm_solve; returns the status code (OK, NOT_CONVERGED,
+        DIVERGED) and raises on argument/device errors."""
+        n, m = int(X.shape[0]), int(X.shape[1])
+        px, mx, kx = _ptr(X, np.float32)
+        py, my, ky = _ptr(y, np.float32)
+        if mx != my:
+            raise TypeError("X and y must live in the same memory")
+        st = lib().gabp_svm_solve(self._h, px, py, n, m, mx, _stream_of(X, stream))
+        del kx, ky
+        self.last_status = st
+        if st in raise_on:
+            raise self._err(st, "gabp_svm_solve")
+        return st
+
+    def solve_kernel(self, K, y, stream=None, raise_on=(E_INVALID, E_NOMEM, E_DEVICE, E_STATE)):
+        n = int(K.shape[0])
+        pk, mk, kk = _ptr(K, np.float64)
+        py, my, ky = _ptr(y, np.float32)
+        if mk != my:
+            raise TypeError("K and y must live in the same memory")
+        st = lib().gabp_svm_solve_kernel(self._h, pk, py, n, mk, _stream_of(K, stream))
+        del kk, ky
+        self.last_status = st
+        if st in raise_on:
+            raise self._err(st, "gabp_svm_solve_kernel")
+        return st
+
+    # -- queries
+    def _q(self, what, arr):
+        st = lib().gabp_svm_query(self._h, what, arr.ctypes.data_as(ct.c_void_p), arr.nbytes)
+        if st != OK:
+            raise self._err(st, "gabp_svm_query")
+        return arr
+
+    def _qs(self, what, obj):
+        st = lib().gabp_svm_query(self._h, what, ct.byref(obj), ct.sizeof(obj))
+        if st != OK:
+            raise self._err(st, "gabp_svm_query")
+        return obj
+
+    @property
+    def n(self):
+        return int(self._q(Q_N, np.zeros(1, np.int64))[0])
+
+    def alpha(self):
+        return self._q(Q_ALPHA, np.zeros(self.n))
+
+    def ptilde(self):
+        return self._q(Q_PTILDE, np.zeros(self.n))
+
+    def adiag(self):
+        return self._q(Q_ADIAG, np.zeros(self.n))
+
+    def bias(self):
+        return float(self._q(Q_BIAS, np.zeros(1))[0])
+
+    def sv_mask(self):
+        return self._q(Q_SV_MASK, np.zeros(self.n, np.uint8)).astype(bool)
+
+    def sv_count(self):
+        return int(self._q(Q_SV_COUNT, np.zeros(1, np.int64))[0])
+
+    def sweeps(self):
+        return int(self._q(Q_SWEEPS, np.zeros(1, np.int32))[0])
+
+    def delta(self):
+        return float(self._q(Q_DELTA, np.zeros(1))[0])
+
+    def status(self):
+        return int(self._q(Q_STATUS, np.zeros(1, np.int32))[0])
+
+    def reason(self):
+        return REASON[int(self._q(Q_REASON, np.zeros(1, np.int32))[0])]
+
+    def trace(self):
+        return self._q(Q_TRACE, np.zeros(self.sweeps()))
+
+    def timings(self):
+        return self._qs(Q_TIMINGS, Timings()).as_dict()
+
+    def plan(self):
+        return self._qs(Q_PLAN, Plan()).as_dict()
+
+    def kernel_entries(self, rows, cols):
+        r = np.ascontiguousarray(rows, dtype=np.int64)
+        c = np.ascontiguousarray(cols, dtype=np.int64)
+        out = np.zeros(len(r))
+        st = lib().gabp_svm_kernel_entries(self._h, r.ctypes.data_as(ct.c_void_p),
+                                           c.ctypes.data_as(ct.c_void_p), len(r),
+                                           out.ctypes.data_as(ct.c_void_p))
+        if st != OK:
+            raise self._err(st, "gabp_svm_kernel_entries")
+        return out
+
+    def predict(self, Xq, stream=None):
+        nq = int(Xq.shape[0])
+        px, mx, kx = _ptr(Xq, np.float32)
+        if mx == MEM_DEVICE:
+            import torch
+            f = torch.empty(nq, dtype=torch.float64, device=Xq.device)
+            pf = ct.c_void_p(f.data_ptr())
+        else:
+            f = np.zeros(nq)
+            pf = f.ctypes.data_as(ct.c_void_p)
+        st = lib().gabp_svm_predict(self._h, px, nq, pf, mx, _stream_of(Xq, stream))
+        del kx
+        if st != OK:
+            raise self._err(st, "gabp_svm_predict")
+        return f

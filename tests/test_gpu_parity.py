@@ -1,0 +1,239 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerance for FP64 and FP32 results (stated as a number):
+    ||alpha - alpha_ref||_inf <= 1e-5 * ||alpha_ref||_inf,
+at convergence and for each of the first 20 sweeps.  The MIXED path is
+reported per result and held to the bounds derived for its Gram (BF16x3:
+the same 1e-5; single BF16: 2e-3, see the BF16 rounding analysis in the
+design notes).
+"""
+import numpy as np
+import pytest
+
+from oracle import gabp_ref as R
+from paper_0810_1648_amd import gabp, inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+def _rel(a, ref):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(ref))) / np.max(np.abs(ref)))
+
+
+def run(torch, wl, device=True, **kw):
+    params = dict(gamma=wl.gamma, C=wl.C, lambda_aug=wl.lam, diag_delta=wl.delta,
+                  precision=wl.precision, tol_abs=wl.tol_abs, tol_rel=wl.tol_rel)
+    params.update(kw)
+    print(f"[case] {wl.name} N={wl.N} m={wl.m} {params}", flush=True)
+    s = gabp.GabpSVM(**params)
+    if device:
+        X = torch.from_numpy(wl.X).cuda()
+        y = torch.from_numpy(wl.y).cuda()
+        st = s.solve(X, y)
+        torch.cuda.synchronize()
+    else:
+        st = s.solve(wl.X, wl.y)
+    return s, st
+
+
+def oracle_traj(wl, sweeps):
+    A, b = R.svm_system(wl.X, wl.y, wl.gamma, wl.C, wl.lam, delta=wl.delta)
+    r = R.gabp_solve(A, b, max_sweeps=sweeps, tol_rel=0.0, keep_trajectory=True)
+    return A, r
+
+
+# ------------------------------------------------------- converged results --
+
+def test_fp64_tiny_workload_matches_oracle(torch, oracle_c):
+    wl = inputs.make_workload("tiny")
+    s, st = run(torch, wl)
+    ref = oracle_c.svm_solve(wl.X, wl.y, wl.gamma, wl.C, wl.lam, tol_abs=wl.tol_abs, tol_rel=0.0)
+    assert st == gabp.OK and s.reason() == "converged"
+    assert abs(s.sweeps() - ref["sweeps"]) <= 1
+    err = _rel(s.alpha(), ref["alpha"])
+    print(f"fp64 tiny: sweeps {s.sweeps()} (oracle {ref['sweeps']}), rel err {err:.2e}")
+    assert err <= TOL
+    np.testing.assert_allclose(s.adiag(), ref["adiag"], rtol=1e-12)
+    np.testing.assert_allclose(s.ptilde(), ref["ptilde"], rtol=1e-9)
+
+
+@pytest.mark.parametrize("n", [255, 256, 257, 1100])
+def test_fp32_letter_shape_matches_cholesky(torch, n):
+    wl = inputs.make_workload("letter", n=n)
+    s, st = run(torch, wl, precision="fp32")
+    A, b = R.svm_system(wl.X, wl.y, wl.gamma, wl.C, wl.lam)
+    exact = R.cholesky_solve(A, b)
+    err = _rel(s.alpha(), exact)
+    print(f"fp32 letter N={n}: status {st} reason {s.reason()} sweeps {s.sweeps()} rel err {err:.2e}")
+    assert st == gabp.OK
+    assert err <= TOL
+    np.testing.assert_allclose(s.adiag(), np.diag(A), rtol=2e-6)
+
+
+@pytest.mark.parametrize("gram,bound", [("bf16x3", TOL), ("bf16", 2e-3)])
+def test_mixed_covertype_shape(torch, gram, bound):
+    wl = inputs.make_workload("covertype", n=1500)
+    s, st = run(torch, wl, precision="mixed", gram=gram)
+    A, b = R.svm_system(wl.X, wl.y, wl.gamma, wl.C, wl.lam)
+    exact = R.cholesky_solve(A, b)
+    err = _rel(s.alpha(), exact)
+    print(f"mixed/{gram} covertype N=1500: status {st} sweeps {s.sweeps()} rel err vs FP64 {err:.2e}")
+    assert st == gabp.OK
+    assert err <= bound
+
+
+# ---------------------------------------------------- sweep-by-sweep parity --
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
+def test_first_twenty_sweeps(torch, prec):
+    wl = inputs.make_workload("tiny", n=700, seed=9)
+    A, ref = oracle_traj(wl, 20)
+    for t in (1, 2, 3, 5, 8, 13, 20):
+        s, st = run(torch, wl, precision=prec, gram="bf16x3", max_sweeps=t, tol_abs=0.0,
+                    tol_rel=0.0, stagnation_window=0)
+        assert st == gabp.E_NOT_CONVERGED and s.sweeps() == t
+        err = _rel(s.alpha(), ref.trajectory[t])
+        assert err <= TOL, (prec, t, err)
+        s.close()
+
+
+def test_max_sweeps_one_is_first_sweep_closed_form(torch):
+    wl = inputs.make_workload("tiny", n=300, seed=3)
+    s, st = run(torch, wl, max_sweeps=1, tol_abs=0.0, tol_rel=0.0)
+    A, b = R.svm_system(wl.X, wl.y, wl.gamma, wl.C, wl.lam)
+    n = wl.N
+    d = np.diag(A)
+    pt = d - ((A - np.diag(d)) ** 2 / d[:, None]).sum(axis=0)
+    sv = 1.0 - ((A - np.diag(d)) / d[:, None]).sum(axis=0)
+    assert st == gabp.E_NOT_CONVERGED and s.reason() == "max_sweeps" and s.sweeps() == 1
+    np.testing.assert_allclose(s.alpha(), sv / pt, rtol=1e-12)
+    assert n == len(s.alpha())
+
+
+# ------------------------------------------------- chosen matrices (K' given) --
+
+def run_kernel(torch, K, y=None, **kw):
+    n = K.shape[0]
+    y = np.ones(n, np.float32) if y is None else y
+    params = dict(kernel="precomputed", precision="fp64", diag_mode="none", tol_rel=1e-14,
+                  stagnation_window=0)
+    params.update(kw)
+    print(f"[case] kernel N={n} {params}", flush=True)
+    s = gabp.GabpSVM(**params)
+    st = s.solve_kernel(torch.from_numpy(np.ascontiguousarray(K)).cuda(), torch.from_numpy(y).cuda())
+    torch.cuda.synchronize()
+    return s, st
+
+
+@pytest.mark.parametrize("n", [17, 300])
+def test_tree_exact_means_and_precisions(torch, n):
+    A = inputs.chain_matrix(n, seed=n)
+    inv = np.linalg.inv(A)
+    s, st = run_kernel(torch, A, max_sweeps=n - 1, tol_rel=0.0)
+    np.testing.assert_allclose(s.alpha(), inv @ np.ones(n), rtol=1e-11, atol=1e-13)
+    np.testing.assert_allclose(s.ptilde(), 1.0 / np.diag(inv), rtol=1e-11)
+
+
+def test_two_nodes_exact(torch):
+    A = np.array([[3.0, -1.25], [-1.25, 2.0]])
+    s, st = run_kernel(torch, A, max_sweeps=1, tol_rel=0.0)
+    exact = np.array([2.0 + 1.25, 3.0 + 1.25]) / (6.0 - 1.25 ** 2)
+    np.testing.assert_allclose(s.alpha(), exact, rtol=1e-15)
+
+
+def test_single_point(torch):
+    s, st = run_kernel(torch, np.array([[2.5]]))
+    assert st == gabp.OK
+    assert s.alpha()[0] == 1.0 / 2.5
+
+
+def test_equicorrelated_diverges(torch):
+    s, st = run_kernel(torch, inputs.equicorrelated(10, 2.0, 0.5), max_sweeps=200, tol_rel=1e-12)
+    assert st in (gabp.E_DIVERGED, gabp.E_NOT_CONVERGED)
+    s2, st2 = run_kernel(torch, inputs.equicorrelated(10, 5.0, 0.5), max_sweeps=500)
+    np.testing.assert_allclose(s2.alpha(), np.linalg.solve(inputs.equicorrelated(10, 5.0, 0.5), np.ones(10)),
+                               rtol=1e-13)
+
+
+def test_signed_kernel_matrix_fp32(torch):
+    A = inputs.random_spd_dominant(600, seed=2, margin=0.2)
+    s, st = run_kernel(torch, A, precision="fp32", tol_rel=1e-7, stagnation_window=10)
+    assert st == gabp.OK
+    assert _rel(s.alpha(), np.linalg.solve(A, np.ones(600))) <= TOL
+
+
+# --------------------------------------------------------------- behaviour --
+
+def test_invalid_inputs_rejected(torch):
+    wl = inputs.make_workload("tiny", n=64)
+    X = wl.X.copy()
+    X[3, 1] = np.nan
+    for dev in (False, True):
+        s = gabp.GabpSVM(gamma=wl.gamma)
+        with pytest.raises(gabp.GabpError) as e:
+            if dev:
+                s.solve(torch.from_numpy(X).cuda(), torch.from_numpy(wl.y).cuda())
+            else:
+                s.solve(X, wl.y)
+        assert e.value.status == gabp.E_INVALID
+        y = wl.y.copy()
+        y[0] = 0.0
+        with pytest.raises(gabp.GabpError):
+            if dev:
+                s.solve(torch.from_numpy(wl.X).cuda(), torch.from_numpy(y).cuda())
+            else:
+                s.solve(wl.X, y)
+
+
+def test_host_device_inputs_and_polling_are_bitwise_identical(torch):
+    wl = inputs.make_workload("letter", n=900)
+    a, _ = run(torch, wl, precision="fp32", device=True, check_every=8)
+    b, _ = run(torch, wl, precision="fp32", device=False, check_every=1)
+    c, _ = run(torch, wl, precision="fp32", device=True, check_every=5)
+    assert np.array_equal(a.alpha(), b.alpha()) and np.array_equal(a.alpha(), c.alpha())
+    assert a.sweeps() == b.sweeps() == c.sweeps()
+
+
+def test_kernel_entries_match_oracle(torch, oracle_c):
+    wl = inputs.make_workload("letter", n=700)
+    rng = np.random.default_rng(0)
+    rows = rng.integers(0, wl.N, 200)
+    cols = (rows + 1 + rng.integers(0, wl.N - 1, 200)) % wl.N
+    ref = np.array([oracle_c.kernel_row(wl.X, wl.gamma, wl.lam, int(i))[j] for i, j in zip(rows, cols)])
+    for prec, bound in (("fp64", 1e-13), ("fp32", 2e-6), ("mixed", 2e-2)):
+        s, _ = run(torch, wl, precision=prec, gram="bf16" if prec == "mixed" else "auto", max_sweeps=1)
+        got = s.kernel_entries(rows, cols)
+        err = float(np.max(np.abs(got - ref) / ref))
+        print(f"K' entries {prec}: max rel err {err:.2e}")
+        assert err <= bound
+
+
+def test_predict_matches_oracle_decision_function(torch):
+    wl = inputs.make_workload("tiny", n=400, seed=8)
+    s, st = run(torch, wl, precision="fp64")
+    Xq = inputs.blobs(50, wl.m, 77)[0]
+    f = s.predict(Xq)
+    ref = R.decision_function(wl.X, wl.y, s.alpha(), Xq, wl.gamma, wl.lam)
+    np.testing.assert_allclose(f, ref, rtol=1e-10, atol=1e-12)
+    fd = s.predict(torch.from_numpy(Xq).cuda()).cpu().numpy()
+    np.testing.assert_allclose(fd, f, rtol=0, atol=0)
+    # bias query: lambda^2 sum alpha y
+    assert s.bias() == pytest.approx(wl.lam ** 2 * float(np.sum(s.alpha() * wl.y)), rel=1e-12)
+
+
+def test_box_clip_and_sv_mask(torch):
+    wl = inputs.make_workload("tiny", n=300, seed=12)
+    s, _ = run(torch, wl, box_mode="clip_output", C=0.05, sv_tau=0.0)
+    a = s.alpha()
+    assert a.min() >= 0.0 and a.max() <= 0.05
+    assert s.sv_count() == int(np.sum(a > 0.0)) and np.array_equal(s.sv_mask(), a > 0.0)
