@@ -34,7 +34,7 @@ def parse():
     ap.add_argument("--workload", default="covertype", choices=["covertype", "letter", "tiny", "large"])
     ap.add_argument("--n", type=int, default=None, help="override N (same recipe)")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp32", "fp64"])
-    ap.add_argument("--gram", default="bf16x3", choices=["bf16", "bf16x3"])
+    ap.add_argument("--gram", default="auto", choices=["auto", "bf16", "bf16x3", "bf16x6"])
     ap.add_argument("--kstore", default="materialise", choices=["materialise", "recompute", "auto"])
     ap.add_argument("--edge", default="stored", choices=["stored", "stateless", "auto"])
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 comparison")
@@ -75,7 +75,7 @@ def cpu_baseline(wl, n_full, sample_n):
     from oracle import oracle_c
     oracle_c.build()
     Xs, ys = wl.X[:sample_n], wl.y[:sample_n]
-    nsw = 4
+    nsw = 6
     r = oracle_c.time_sweeps(Xs, ys, wl.gamma, wl.C, 1.0 / n_full, nsw)
     pairs = sample_n * (sample_n - 1) / 2.0 * nsw
     rate = pairs / r["seconds"]
@@ -150,7 +150,7 @@ def main():
 
     cpu = None
     if not a.no_cpu_baseline:
-        sn = a.cpu_sample_n or min(N, 10000)
+        sn = a.cpu_sample_n or min(N, 20000)
         cpu = cpu_baseline(wl, N, sn)
 
     line = {

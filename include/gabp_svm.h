@@ -98,9 +98,15 @@ typedef enum gabp_kstore {
  * truncation with bound (max|A_ij| / min Q)^depth after). */
 typedef enum gabp_edge { GABP_EDGE_AUTO = 0, GABP_EDGE_STORED = 1, GABP_EDGE_STATELESS = 2 } gabp_edge;
 
-/* Gram of the MIXED path: one BF16 product, or the three-term split
- * hi*hi + hi*lo + lo*hi of x = hi + lo for ~2^-16 relative accuracy. */
-typedef enum gabp_gram { GABP_GRAM_AUTO = 0, GABP_GRAM_BF16 = 1, GABP_GRAM_BF16X3 = 2 } gabp_gram;
+/* Gram of the MIXED path, always BF16 MFMA with FP32 accumulation:
+ *   BF16:   one product of x rounded to BF16 (features perturbed by <= 2^-9
+ *           relative);
+ *   BF16X3: x = hi + lo, products hi*hi + hi*lo + lo*hi (about 2^-17);
+ *   BF16X6: x = hi + lo + lo2, the six products whose order is >= 2^-18
+ *           (about 2^-26, FP32-Gram accuracy).  AUTO = BF16X6. */
+typedef enum gabp_gram {
+    GABP_GRAM_AUTO = 0, GABP_GRAM_BF16 = 1, GABP_GRAM_BF16X3 = 2, GABP_GRAM_BF16X6 = 3
+} gabp_gram;
 
 /* Where the caller's buffers live. */
 typedef enum gabp_mem { GABP_MEM_HOST = 0, GABP_MEM_DEVICE = 1 } gabp_mem;

@@ -15,7 +15,7 @@ constexpr int TT = TILE * TILE;
 constexpr int WG = 256;               // threads per workgroup (4 wave64)
 
 enum Prec : int { PREC_FP64 = 0, PREC_FP32 = 1, PREC_MIXED = 2 };
-enum GramKind : int { GRAM_F32 = 0, GRAM_BF16 = 1, GRAM_BF16X3 = 2, GRAM_F64 = 3 };
+enum GramKind : int { GRAM_F32 = 0, GRAM_BF16 = 1, GRAM_BF16X3 = 2, GRAM_F64 = 3, GRAM_BF16X6 = 4 };
 enum Reason : int { R_NONE = 0, R_CONVERGED = 1, R_MAX_SWEEPS = 2, R_DIVERGED = 3, R_STAGNATED = 4 };
 
 // Device-resident solve status, advanced by k_status once per sweep.  Every
@@ -42,7 +42,8 @@ struct StopRule {
 struct Features {
     const float* f32;        // GRAM_F32: centred FP32
     const uint16_t* hi;      // GRAM_BF16/BF16X3: centred, rounded to BF16
-    const uint16_t* lo;      // GRAM_BF16X3: BF16 of the rounding remainder
+    const uint16_t* lo;      // GRAM_BF16X3/X6: BF16 of the rounding remainder x - hi
+    const uint16_t* lo2;     // GRAM_BF16X6: BF16 of the second remainder x - hi - lo
     const double* f64;       // GRAM_F64: uncentred FP64
     const float* nrm;        // squared norms of the staged rows (FP32)
     int32_t m_pad;
@@ -70,7 +71,7 @@ hipError_t launch_validate(const float* X, const float* y, int64_t N, int64_t m,
 hipError_t launch_colmean(const float* X, int64_t N, int64_t m, double* mean, hipStream_t s);
 hipError_t launch_stage(const float* X, const double* mean, int64_t N, int64_t m,
                         int64_t NPAD, int m_pad, int kind, float* f32, uint16_t* hi,
-                        uint16_t* lo, double* f64, float* nrm, hipStream_t s);
+                        uint16_t* lo, uint16_t* lo2, double* f64, float* nrm, hipStream_t s);
 hipError_t launch_gram(const Features& F, const KernelParams& kp, const uint32_t* tiles,
                        int64_t ntiles, void* Kp, int prec, hipStream_t s);
 hipError_t launch_gather_dense(const double* K, const KernelParams& kp,

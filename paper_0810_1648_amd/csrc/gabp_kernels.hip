@@ -153,7 +153,7 @@ __global__ void k_colmean(const float* __restrict__ X, int64_t N, int64_t m, dou
 // with itself is 0 up to the Gram's own rounding).
 __global__ void k_stage(const float* __restrict__ X, const double* __restrict__ mean, int64_t N,
                         int64_t m, int64_t NPAD, int m_pad, int kind, float* f32, uint16_t* hi,
-                        uint16_t* lo, double* f64, float* nrm) {
+                        uint16_t* lo, uint16_t* lo2, double* f64, float* nrm) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= NPAD) return;
     float acc = 0.0f;
@@ -172,10 +172,16 @@ __global__ void k_stage(const float* __restrict__ X, const double* __restrict__ 
             const uint16_t h = f2bf(xc);
             float v = bf2f(h);
             hi[i * m_pad + k] = h;
-            if (kind == GRAM_BF16X3) {
+            if (kind == GRAM_BF16X3 || kind == GRAM_BF16X6) {
                 const uint16_t l = f2bf(xc - v);
                 lo[i * m_pad + k] = l;
-                v += bf2f(l);
+                if (kind == GRAM_BF16X6) {
+                    const uint16_t l2 = f2bf((xc - v) - bf2f(l));
+                    lo2[i * m_pad + k] = l2;
+                    v += bf2f(l) + bf2f(l2);
+                } else {
+                    v += bf2f(l);
+                }
             }
             acc = fmaf(v, v, acc);
         }
@@ -226,13 +232,21 @@ __global__ __launch_bounds__(WG) void k_gram_mfma(Features F, KernelParams kp,
                 for (int s = 0; s < mp; s += 16) {
                     const bf16x8 a = *reinterpret_cast<const bf16x8*>(pa + s);
                     const bf16x8 b = *reinterpret_cast<const bf16x8*>(pb + s);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
-                    if constexpr (KIND == GRAM_BF16X3) {
+                    if constexpr (KIND == GRAM_BF16X3 || KIND == GRAM_BF16X6) {
+                        // correction terms first, then the leading product
                         const bf16x8 al = *reinterpret_cast<const bf16x8*>(F.lo + rowA * mp + 8 * h + s);
                         const bf16x8 bl = *reinterpret_cast<const bf16x8*>(F.lo + colB * mp + 8 * h + s);
+                        if constexpr (KIND == GRAM_BF16X6) {
+                            const bf16x8 a2 = *reinterpret_cast<const bf16x8*>(F.lo2 + rowA * mp + 8 * h + s);
+                            const bf16x8 b2 = *reinterpret_cast<const bf16x8*>(F.lo2 + colB * mp + 8 * h + s);
+                            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b2, acc, 0, 0, 0);
+                            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, b, acc, 0, 0, 0);
+                            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bl, acc, 0, 0, 0);
+                        }
                         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bl, acc, 0, 0, 0);
                         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, b, acc, 0, 0, 0);
                     }
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
                 }
             }
             const float nj = F.nrm[colB];
@@ -653,10 +667,10 @@ hipError_t launch_colmean(const float* X, int64_t N, int64_t m, double* mean, hi
 }
 
 hipError_t launch_stage(const float* X, const double* mean, int64_t N, int64_t m, int64_t NPAD,
-                        int m_pad, int kind, float* f32, uint16_t* hi, uint16_t* lo, double* f64,
-                        float* nrm, hipStream_t s) {
+                        int m_pad, int kind, float* f32, uint16_t* hi, uint16_t* lo, uint16_t* lo2,
+                        double* f64, float* nrm, hipStream_t s) {
     hipLaunchKernelGGL(k_stage, dim3(grid1(NPAD)), dim3(WG), 0, s, X, mean, N, m, NPAD, m_pad, kind,
-                       f32, hi, lo, f64, nrm);
+                       f32, hi, lo, lo2, f64, nrm);
     return hipGetLastError();
 }
 
@@ -667,6 +681,7 @@ hipError_t launch_gram(const Features& F, const KernelParams& kp, const uint32_t
         case GRAM_F32: hipLaunchKernelGGL(k_gram_mfma<GRAM_F32>, g, b, 0, s, F, kp, tiles, (float*)Kp); break;
         case GRAM_BF16: hipLaunchKernelGGL(k_gram_mfma<GRAM_BF16>, g, b, 0, s, F, kp, tiles, (float*)Kp); break;
         case GRAM_BF16X3: hipLaunchKernelGGL(k_gram_mfma<GRAM_BF16X3>, g, b, 0, s, F, kp, tiles, (float*)Kp); break;
+        case GRAM_BF16X6: hipLaunchKernelGGL(k_gram_mfma<GRAM_BF16X6>, g, b, 0, s, F, kp, tiles, (float*)Kp); break;
         case GRAM_F64: hipLaunchKernelGGL(k_gram_f64, g, b, 0, s, F, kp, tiles, (double*)Kp); break;
         default: return hipErrorInvalidValue;
     }

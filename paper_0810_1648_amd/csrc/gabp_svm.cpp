@@ -70,12 +70,12 @@ struct gabp_svm {
     gabp_timings tm{};
     gabp_plan plan{};
     // device memory owned by the handle
-    DevBuf tiles, Kp, Pf, Pb, Ef, Eb, partP, partE, Xin, yd, mean, xs32, xhi, xlo, x64, nrm, kdiag,
+    DevBuf tiles, Kp, Pf, Pb, Ef, Eb, partP, partE, Xin, yd, mean, xs32, xhi, xlo, xlo2, x64, nrm, kdiag,
         Adiag, Pt, S, alpha_d, blk1, blk2, one, status_d, trace_d, flag, tmp, Kin, q_rows, q_cols,
         q_out;
 
-    DevBuf* all[33] = {&tiles, &Kp, &Pf, &Pb, &Ef, &Eb, &partP, &partE, &Xin, &yd, &mean,
-                       &xs32, &xhi, &xlo, &x64, &nrm, &kdiag, &Adiag, &Pt, &S, &alpha_d,
+    DevBuf* all[34] = {&tiles, &Kp, &Pf, &Pb, &Ef, &Eb, &partP, &partE, &Xin, &yd, &mean,
+                       &xs32, &xhi, &xlo, &xlo2, &x64, &nrm, &kdiag, &Adiag, &Pt, &S, &alpha_d,
                        &blk1, &blk2, &one, &status_d, &trace_d, &flag, &tmp, &Kin, &q_rows,
                        &q_cols, &q_out, nullptr};
     size_t held() const {
@@ -119,7 +119,7 @@ gabp_status check_params(const gabp_svm_params* p, std::string& why) {
     if (p->precision < 0 || p->precision > 2) { why = "unknown precision"; return GABP_E_INVALID; }
     if (p->kstore < 0 || p->kstore > 2) { why = "unknown kstore"; return GABP_E_INVALID; }
     if (p->edge_state < 0 || p->edge_state > 2) { why = "unknown edge_state"; return GABP_E_INVALID; }
-    if (p->gram < 0 || p->gram > 2) { why = "unknown gram"; return GABP_E_INVALID; }
+    if (p->gram < 0 || p->gram > 3) { why = "unknown gram"; return GABP_E_INVALID; }
     if (p->stateless_depth < 0 || p->stateless_depth > 16) { why = "stateless_depth must be in [0, 16]"; return GABP_E_INVALID; }
     return GABP_OK;
 }
@@ -175,7 +175,8 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     const int prec = p.precision;
     int gram = GRAM_F32;
     if (prec == PREC_FP64) gram = GRAM_F64;
-    else if (prec == PREC_MIXED) gram = (p.gram == GABP_GRAM_BF16X3) ? GRAM_BF16X3 : GRAM_BF16;
+    else if (prec == PREC_MIXED)
+        gram = (p.gram == GABP_GRAM_BF16) ? GRAM_BF16 : (p.gram == GABP_GRAM_BF16X3) ? GRAM_BF16X3 : GRAM_BF16X6;
     if (p.kstore == GABP_KSTORE_RECOMPUTE) return fail(h, GABP_E_INVALID, "kstore RECOMPUTE is not available in this build");
     if (p.edge_state == GABP_EDGE_STATELESS) return fail(h, GABP_E_INVALID, "edge_state STATELESS is not available in this build");
     const int NB = (int)((N + TILE - 1) / TILE);
@@ -191,6 +192,7 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
             case GRAM_F32: feat = (size_t)NPAD * m_pad * 4; break;
             case GRAM_BF16: feat = (size_t)NPAD * m_pad * 2; break;
             case GRAM_BF16X3: feat = (size_t)NPAD * m_pad * 4; break;
+            case GRAM_BF16X6: feat = (size_t)NPAD * m_pad * 6; break;
             default: feat = (size_t)NPAD * m_pad * 8; break;
         }
         feat += (size_t)N * m * 4 + (size_t)NPAD * 4 + (size_t)m * 8;
@@ -228,8 +230,9 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     if (rbf) {
         A(h->Xin, (size_t)N * m * 4); A(h->mean, (size_t)m * 8); A(h->nrm, (size_t)NPAD * 4);
         if (gram == GRAM_F32) A(h->xs32, (size_t)NPAD * m_pad * 4);
-        if (gram == GRAM_BF16 || gram == GRAM_BF16X3) A(h->xhi, (size_t)NPAD * m_pad * 2);
-        if (gram == GRAM_BF16X3) A(h->xlo, (size_t)NPAD * m_pad * 2);
+        if (gram == GRAM_BF16 || gram == GRAM_BF16X3 || gram == GRAM_BF16X6) A(h->xhi, (size_t)NPAD * m_pad * 2);
+        if (gram == GRAM_BF16X3 || gram == GRAM_BF16X6) A(h->xlo, (size_t)NPAD * m_pad * 2);
+        if (gram == GRAM_BF16X6) A(h->xlo2, (size_t)NPAD * m_pad * 2);
         if (gram == GRAM_F64) A(h->x64, (size_t)NPAD * m_pad * 8);
     } else if (mem == GABP_MEM_HOST) {
         A(h->Kin, (size_t)N * N * 8);
@@ -282,11 +285,12 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     if (rbf) {
         if (gram != GRAM_F64) HIPCHK(h, launch_colmean(Xd, N, m, h->mean.as<double>(), s));
         HIPCHK(h, launch_stage(Xd, h->mean.as<double>(), N, m, NPAD, m_pad, gram, h->xs32.as<float>(),
-                               h->xhi.as<uint16_t>(), h->xlo.as<uint16_t>(), h->x64.as<double>(),
-                               h->nrm.as<float>(), s));
+                               h->xhi.as<uint16_t>(), h->xlo.as<uint16_t>(), h->xlo2.as<uint16_t>(),
+                               h->x64.as<double>(), h->nrm.as<float>(), s));
         F.f32 = h->xs32.as<float>();
         F.hi = h->xhi.as<uint16_t>();
         F.lo = h->xlo.as<uint16_t>();
+        F.lo2 = h->xlo2.as<uint16_t>();
         F.f64 = h->x64.as<double>();
         F.nrm = h->nrm.as<float>();
     }
@@ -395,7 +399,8 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     h->plan.precision = prec;
     h->plan.kstore = GABP_KSTORE_MATERIALISE;
     h->plan.edge_state = GABP_EDGE_STORED;
-    h->plan.gram = (gram == GRAM_BF16X3) ? GABP_GRAM_BF16X3 : (gram == GRAM_BF16 ? GABP_GRAM_BF16 : GABP_GRAM_AUTO);
+    h->plan.gram = (gram == GRAM_BF16X6) ? GABP_GRAM_BF16X6 : (gram == GRAM_BF16X3) ? GABP_GRAM_BF16X3
+                 : (gram == GRAM_BF16 ? GABP_GRAM_BF16 : GABP_GRAM_AUTO);
     h->plan.tile = TILE;
     h->plan.stateless_depth = 0;
     h->plan.n_blocks = NB;

@@ -24,7 +24,7 @@ BOX = {"none": 0, "clip_output": 1}
 PREC = {"fp64": 0, "fp32": 1, "mixed": 2}
 KSTORE = {"auto": 0, "materialise": 1, "recompute": 2}
 EDGE = {"auto": 0, "stored": 1, "stateless": 2}
-GRAM = {"auto": 0, "bf16": 1, "bf16x3": 2}
+GRAM = {"auto": 0, "bf16": 1, "bf16x3": 2, "bf16x6": 3}
 MEM_HOST, MEM_DEVICE = 0, 1
 REASON = {0: "none", 1: "converged", 2: "max_sweeps", 3: "diverged", 4: "stagnated"}
 Q_N, Q_ALPHA, Q_PTILDE, Q_ADIAG, Q_BIAS, Q_SV_MASK, Q_SV_COUNT, Q_SWEEPS, Q_DELTA, Q_STATUS, \

@@ -3,9 +3,11 @@
 Tolerance for FP64 and FP32 results (stated as a number):
     ||alpha - alpha_ref||_inf <= 1e-5 * ||alpha_ref||_inf,
 at convergence and for each of the first 20 sweeps.  The MIXED path is
-reported per result and held to the bounds derived for its Gram (BF16x3:
-the same 1e-5; single BF16: 2e-3, see the BF16 rounding analysis in the
-design notes).
+reported per result and held to the bounds derived for its Gram: the
+default three-term BF16 split (BF16x6) reaches the same 1e-5; the two-term
+split (BF16x3) and a single BF16 product perturb the features by about
+2^-17 and 2^-9 relative, and are held to 1e-4 and 1e-2 (their measured
+errors are about 2e-5 and 2e-3).
 """
 import numpy as np
 import pytest
@@ -80,7 +82,7 @@ def test_fp32_letter_shape_matches_cholesky(torch, n):
     np.testing.assert_allclose(s.adiag(), np.diag(A), rtol=2e-6)
 
 
-@pytest.mark.parametrize("gram,bound", [("bf16x3", TOL), ("bf16", 2e-3)])
+@pytest.mark.parametrize("gram,bound", [("bf16x6", TOL), ("bf16x3", 1e-4), ("bf16", 1e-2)])
 def test_mixed_covertype_shape(torch, gram, bound):
     wl = inputs.make_workload("covertype", n=1500)
     s, st = run(torch, wl, precision="mixed", gram=gram)
@@ -99,7 +101,7 @@ def test_first_twenty_sweeps(torch, prec):
     wl = inputs.make_workload("tiny", n=700, seed=9)
     A, ref = oracle_traj(wl, 20)
     for t in (1, 2, 3, 5, 8, 13, 20):
-        s, st = run(torch, wl, precision=prec, gram="bf16x3", max_sweeps=t, tol_abs=0.0,
+        s, st = run(torch, wl, precision=prec, max_sweeps=t, tol_abs=0.0,
                     tol_rel=0.0, stagnation_window=0)
         assert st == gabp.E_NOT_CONVERGED and s.sweeps() == t
         err = _rel(s.alpha(), ref.trajectory[t])
@@ -210,11 +212,12 @@ def test_kernel_entries_match_oracle(torch, oracle_c):
     rows = rng.integers(0, wl.N, 200)
     cols = (rows + 1 + rng.integers(0, wl.N - 1, 200)) % wl.N
     ref = np.array([oracle_c.kernel_row(wl.X, wl.gamma, wl.lam, int(i))[j] for i, j in zip(rows, cols)])
-    for prec, bound in (("fp64", 1e-13), ("fp32", 2e-6), ("mixed", 2e-2)):
-        s, _ = run(torch, wl, precision=prec, gram="bf16" if prec == "mixed" else "auto", max_sweeps=1)
+    for prec, gram, bound in (("fp64", "auto", 1e-13), ("fp32", "auto", 2e-6), ("mixed", "bf16x6", 2e-6),
+                              ("mixed", "bf16x3", 1e-4), ("mixed", "bf16", 2e-2)):
+        s, _ = run(torch, wl, precision=prec, gram=gram, max_sweeps=1)
         got = s.kernel_entries(rows, cols)
         err = float(np.max(np.abs(got - ref) / ref))
-        print(f"K' entries {prec}: max rel err {err:.2e}")
+        print(f"K' entries {prec}/{gram}: max rel err {err:.2e}")
         assert err <= bound
 
 
