@@ -172,6 +172,10 @@ typedef struct gabp_plan {
     uint64_t alg_bytes_per_sweep; /* algorithmic HBM bytes of one sweep:
                                      N(N-1)/2 pairs x bytes per pair */
     double alg_bytes_per_pair;
+    double stateless_rho;      /* contraction estimate max_i max_j |K'_ij| / P~_i
+                                  after sweep 1 (auto depth); the truncation of
+                                  the message recursion is bounded by
+                                  rho^stateless_depth */
 } gabp_plan;
 
 /* Query selectors for gabp_svm_query: dst type and size in brackets. */

@@ -16,6 +16,7 @@ constexpr int WG = 256;               // threads per workgroup (4 wave64)
 
 enum Prec : int { PREC_FP64 = 0, PREC_FP32 = 1, PREC_MIXED = 2 };
 enum GramKind : int { GRAM_F32 = 0, GRAM_BF16 = 1, GRAM_BF16X3 = 2, GRAM_F64 = 3, GRAM_BF16X6 = 4 };
+enum KSrc : int { KSRC_PLANE = 0, KSRC_RECOMPUTE = 1 };
 enum Reason : int { R_NONE = 0, R_CONVERGED = 1, R_MAX_SWEEPS = 2, R_DIVERGED = 3, R_STAGNATED = 4 };
 
 // Device-resident solve status, advanced by k_status once per sweep.  Every
@@ -73,36 +74,48 @@ hipError_t launch_stage(const float* X, const double* mean, int64_t N, int64_t m
                         int64_t NPAD, int m_pad, int kind, float* f32, uint16_t* hi,
                         uint16_t* lo, uint16_t* lo2, double* f64, float* nrm, hipStream_t s);
 hipError_t launch_gram(const Features& F, const KernelParams& kp, const uint32_t* tiles,
-                       int64_t ntiles, void* Kp, int prec, hipStream_t s);
+                       int64_t ntiles, void* Kp, hipStream_t s);
 hipError_t launch_gather_dense(const double* K, const KernelParams& kp,
                                const uint32_t* tiles, int64_t ntiles, void* Kp, int prec,
                                double* kdiag, hipStream_t s);
 hipError_t launch_fill_value(double* dst, int64_t n, double v, hipStream_t s);
-hipError_t launch_rowsum(const void* Kp, int prec, const uint32_t* tiles, int64_t ntiles,
-                         int NB, double* partR, hipStream_t s);
-hipError_t launch_diag(int64_t N, int NB, const double* partR, const double* kdiag, int mode,
-                       double C, double delta, double* Adiag, double* scratch_blk,
-                       double* scratch_one, hipStream_t s);
-hipError_t launch_init(int prec, int64_t N, int64_t NPAD, const double* Adiag, const float* y,
+hipError_t launch_rowsum(const void* Kp, int prec, int ksrc, const Features& F,
+                         const KernelParams& kp, const uint32_t* tiles, int64_t ntiles, int NB,
+                         double* psum, double* pmax, hipStream_t s);
+hipError_t launch_diag(int64_t N, int NB, const double* psum, const double* pmax,
+                       const double* kdiag, int mode, double C, double delta, double* Adiag,
+                       double* rowmax, double* scratch_blk, double* scratch_one, hipStream_t s);
+hipError_t launch_init(int prec, int64_t N, int64_t NPAD, int R, const double* Adiag, const float* y,
                        void* Pt, void* S, double* alpha, DevStatus* st, hipStream_t s);
 
-struct SweepBufs {
+// Arguments of one sweep launch.  HP/HS are rings of R aggregate vectors
+// (NPAD entries each); slot_top holds the aggregates of the previous sweep,
+// slot_top - k (mod R) those k sweeps earlier.
+struct SweepArgs {
     const uint32_t* tiles;
     int64_t ntiles;
     int NB;
-    const void* Kp;
-    void *Pf, *Pb, *Ef, *Eb;      // pair planes: P_ij, P_ji, E_ij, E_ji (i < j)
-    const void *Pt, *S;           // aggregates of the previous sweep
+    const void* Kp;               // K' plane (KSRC_PLANE)
+    void *Pf, *Pb, *Ef, *Eb;      // pair planes: P_ij, P_ji, E_ij, E_ji (i < j), stored state
+    const void *HP, *HS;          // aggregate rings
+    int64_t NPAD;
+    int R, slot_top, levels;      // ring depth, top slot, stateless levels in use
     void *partP, *partE;          // [NB][NB+1][TILE] partial sums
     DevStatus* st;
+    Features F;                   // KSRC_RECOMPUTE
+    KernelParams kp;
 };
-hipError_t launch_sweep_stored(int prec, bool first, const SweepBufs& b, hipStream_t s);
+// depth 0 = stored edge state, 1..8 = stateless with up to `depth` levels.
+hipError_t launch_sweep(int prec, int ksrc, int gram, int depth, bool first, const SweepArgs& a,
+                        hipStream_t s);
 hipError_t launch_finalize(int prec, int64_t N, int NB, const void* partP, const void* partE,
                            const double* Adiag, const float* y, void* Pt, void* S,
                            double* alpha, double* blk_delta, double* blk_amax,
                            DevStatus* st, hipStream_t s);
 hipError_t launch_status(int nblk, const double* blk_delta, const double* blk_amax,
                          DevStatus* st, double* trace, StopRule rule, hipStream_t s);
+hipError_t launch_rho(int prec, int64_t N, const double* rowmax, const void* Pt, double* blk,
+                      double* one, hipStream_t s);
 hipError_t launch_kernel_entries(const void* Kp, int prec, int NB, const int64_t* rows,
                                  const int64_t* cols, int64_t n, double* out, hipStream_t s);
 hipError_t launch_predict(const float* Xtr, const float* y, const double* alpha, int64_t N,

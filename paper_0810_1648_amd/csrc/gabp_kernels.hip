@@ -27,9 +27,22 @@
 // across the four lane groups once per tile.  Partial sums go to a
 // [block][slot][TILE] array that a second kernel reduces in a fixed order,
 // so results are bitwise reproducible.
+//
+// K' comes either from the materialised plane (one 16-byte load per lane
+// and row) or is recomputed per 32-row band: each wave forms the Gram
+// products of its 32 x 64 block on MFMA, applies exp, and passes the block
+// through a wave-private LDS buffer into the row layout above.  Messages come
+// either from the pair-record planes (stored edge state) or are rebuilt from
+// a ring of earlier aggregates (stateless edge state): the message i -> j of
+// sweep t needs only the reverse message of sweep t - 1, which needs i -> j
+// of sweep t - 2, and so on, so unrolling L levels from zero reproduces the
+// stored recursion exactly while t <= L and truncates it after.
 #include "gabp_internal.h"
 
 #include <math.h>
+
+#include <algorithm>
+#include <type_traits>
 
 namespace gabp {
 
@@ -106,6 +119,17 @@ __device__ inline uint16_t f2bf(float f) {  // round to nearest even
     return (uint16_t)(u >> 16);
 }
 __device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Reciprocals: v_rcp_f32 (1 ulp) for FP32; for FP64, v_rcp_f64 refined by
+// two Newton steps (the cavity precisions are far from the denormal range).
+__device__ inline float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double rcp_fast(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
 
 struct TileCoord { int I, J; };
 __device__ inline TileCoord tile_of(const uint32_t* tiles) {
@@ -191,11 +215,64 @@ __global__ void k_stage(const float* __restrict__ X, const double* __restrict__ 
 
 // ------------------------------------------------------------ K' build --
 
-// Materialise K' = exp(-gamma d^2) + lambda^2 for one tile with MFMA Gram
-// products: d^2 = n_i + n_j - 2 x_i.x_j.  Wave w computes the 32-row bands
-// w and w + 4, one 32 x 32 sub-block at a time; operands come straight from
-// the staged features (L2-resident).  The inner-product index k is split
-// between the two lane halves so each lane reads contiguous features.
+// One 32 x 32 block of the Gram matrix x_a . x_b on MFMA, for A rows
+// rowA = base_a + lane % 32 and B rows colB = base_b + lane % 32.  The
+// inner-product index is split between the two lane halves so that each lane
+// reads contiguous features.  Output layout of the 32x32 MFMAs: register r of
+// lane l holds row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.
+template <int KIND>
+__device__ inline f32x16 mfma_gram_32x32(const Features& F, int64_t rowA, int64_t colB) {
+    const int l = threadIdx.x & 63, h = l >> 5;
+    const int mp = F.m_pad;
+    f32x16 acc = {};
+    if constexpr (KIND == GRAM_F32) {
+        const int half = mp >> 1;
+        const float* pa = F.f32 + rowA * mp + h * half;
+        const float* pb = F.f32 + colB * mp + h * half;
+        for (int s = 0; s < half; s += 4) {
+            const f32x4v a4 = *reinterpret_cast<const f32x4v*>(pa + s);
+            const f32x4v b4 = *reinterpret_cast<const f32x4v*>(pb + s);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[0], b4[0], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[1], b4[1], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[2], b4[2], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[3], b4[3], acc, 0, 0, 0);
+        }
+    } else {
+        const int64_t oa = rowA * mp + 8 * h, ob = colB * mp + 8 * h;
+        for (int s = 0; s < mp; s += 16) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(F.hi + oa + s);
+            const bf16x8 b = *reinterpret_cast<const bf16x8*>(F.hi + ob + s);
+            if constexpr (KIND == GRAM_BF16X3 || KIND == GRAM_BF16X6) {
+                // correction terms first, then the leading product
+                const bf16x8 al = *reinterpret_cast<const bf16x8*>(F.lo + oa + s);
+                const bf16x8 bl = *reinterpret_cast<const bf16x8*>(F.lo + ob + s);
+                if constexpr (KIND == GRAM_BF16X6) {
+                    const bf16x8 a2 = *reinterpret_cast<const bf16x8*>(F.lo2 + oa + s);
+                    const bf16x8 b2 = *reinterpret_cast<const bf16x8*>(F.lo2 + ob + s);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b2, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, b, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bl, acc, 0, 0, 0);
+                }
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bl, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, b, acc, 0, 0, 0);
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        }
+    }
+    return acc;
+}
+
+// K' = exp(-gamma d^2) + lambda^2 with d^2 = max(0, n_i + n_j - 2 G_ij), zero
+// for pairs that are not strictly upper (i >= j) or are padding (j >= N).
+__device__ inline float kernel_entry(float ni, float nj, float g, int64_t i, int64_t j,
+                                     const KernelParams& kp) {
+    const float d2 = fmaxf(ni + nj - 2.0f * g, 0.0f);
+    const float kv = exp2f(kp.neg_gamma_log2e * d2) + (float)kp.lam2;
+    return (i < j && j < kp.N) ? kv : 0.0f;
+}
+
+// Materialise the K' tiles.  Wave w computes the 32-row bands w and w + 4,
+// one 32 x 32 block at a time, and stores straight from the MFMA layout.
 template <int KIND>
 __global__ __launch_bounds__(WG) void k_gram_mfma(Features F, KernelParams kp,
                                                  const uint32_t* __restrict__ tiles,
@@ -203,8 +280,6 @@ __global__ __launch_bounds__(WG) void k_gram_mfma(Features F, KernelParams kp,
     const TileCoord tc = tile_of(tiles);
     const size_t tbase = (size_t)blockIdx.x * TT;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, h = l >> 5, l32 = l & 31;
-    const int mp = F.m_pad;
-    const float lam2 = (float)kp.lam2;
     for (int band = w; band < TILE / 32; band += 4) {
         const int64_t rowA = (int64_t)tc.I * TILE + band * 32 + l32;
         float ni[16];
@@ -213,55 +288,47 @@ __global__ __launch_bounds__(WG) void k_gram_mfma(Features F, KernelParams kp,
             ni[r] = F.nrm[(int64_t)tc.I * TILE + band * 32 + 8 * (r >> 2) + 4 * h + (r & 3)];
         for (int cb = 0; cb < TILE / 32; ++cb) {
             const int64_t colB = (int64_t)tc.J * TILE + cb * 32 + l32;
-            f32x16 acc = {};
-            if constexpr (KIND == GRAM_F32) {
-                const int half = mp >> 1;
-                const float* pa = F.f32 + rowA * mp + h * half;
-                const float* pb = F.f32 + colB * mp + h * half;
-                for (int s = 0; s < half; s += 4) {
-                    const f32x4v a4 = *reinterpret_cast<const f32x4v*>(pa + s);
-                    const f32x4v b4 = *reinterpret_cast<const f32x4v*>(pb + s);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[0], b4[0], acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[1], b4[1], acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[2], b4[2], acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[3], b4[3], acc, 0, 0, 0);
-                }
-            } else {
-                const uint16_t* pa = F.hi + rowA * mp + 8 * h;
-                const uint16_t* pb = F.hi + colB * mp + 8 * h;
-                for (int s = 0; s < mp; s += 16) {
-                    const bf16x8 a = *reinterpret_cast<const bf16x8*>(pa + s);
-                    const bf16x8 b = *reinterpret_cast<const bf16x8*>(pb + s);
-                    if constexpr (KIND == GRAM_BF16X3 || KIND == GRAM_BF16X6) {
-                        // correction terms first, then the leading product
-                        const bf16x8 al = *reinterpret_cast<const bf16x8*>(F.lo + rowA * mp + 8 * h + s);
-                        const bf16x8 bl = *reinterpret_cast<const bf16x8*>(F.lo + colB * mp + 8 * h + s);
-                        if constexpr (KIND == GRAM_BF16X6) {
-                            const bf16x8 a2 = *reinterpret_cast<const bf16x8*>(F.lo2 + rowA * mp + 8 * h + s);
-                            const bf16x8 b2 = *reinterpret_cast<const bf16x8*>(F.lo2 + colB * mp + 8 * h + s);
-                            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b2, acc, 0, 0, 0);
-                            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, b, acc, 0, 0, 0);
-                            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bl, acc, 0, 0, 0);
-                        }
-                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bl, acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, b, acc, 0, 0, 0);
-                    }
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
-                }
-            }
+            const f32x16 acc = mfma_gram_32x32<KIND>(F, rowA, colB);
             const float nj = F.nrm[colB];
             const int col = cb * 32 + l32;
-            const int64_t j = (int64_t)tc.J * TILE + col;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int row = band * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-                const int64_t i = (int64_t)tc.I * TILE + row;
-                const float d2 = fmaxf(ni[r] + nj - 2.0f * acc[r], 0.0f);
-                const float kv = exp2f(kp.neg_gamma_log2e * d2) + lam2;
-                Kp[tbase + (size_t)row * TILE + col] = (i < j && j < kp.N) ? kv : 0.0f;
+                Kp[tbase + (size_t)row * TILE + col] =
+                    kernel_entry(ni[r], nj, acc[r], (int64_t)tc.I * TILE + row, colB, kp);
             }
         }
     }
+}
+
+// K' for the 32 x 64 band [row0, row0 + 32) x [col0, col0 + 64) of tile
+// (I, J), computed by one wave into its LDS buffer kb[32][64] (row-major).
+template <int KIND>
+__device__ inline void gram_band(const Features& F, const KernelParams& kp, int I, int J, int row0,
+                                 int col0, float* kb) {
+    const int l = threadIdx.x & 63, h = l >> 5, l32 = l & 31;
+    const int64_t rowA = (int64_t)I * TILE + row0 + l32;
+    float ni[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) ni[r] = F.nrm[(int64_t)I * TILE + row0 + 8 * (r >> 2) + 4 * h + (r & 3)];
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+        const int64_t colB = (int64_t)J * TILE + col0 + 32 * cb + l32;
+        const f32x16 acc = mfma_gram_32x32<KIND>(F, rowA, colB);
+        const float nj = F.nrm[colB];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = 8 * (r >> 2) + 4 * h + (r & 3);
+            kb[row * 64 + 32 * cb + l32] =
+                kernel_entry(ni[r], nj, acc[r], (int64_t)I * TILE + row0 + row, colB, kp);
+        }
+    }
+}
+
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // FP64 K' from direct differences (no Gram expansion, no centring).
@@ -331,54 +398,87 @@ __global__ void k_fill_value(double* dst, int64_t n, double v) {
 
 // --------------------------------------------------- diagonal weighting --
 
-// r_i = sum_{j != i} |K'_ij|, as per-tile partial sums (FP64).
-template <class ST>
-__global__ __launch_bounds__(WG) void k_rowsum(const ST* __restrict__ Kp,
+// Partial sums r_i = sum_{j != i} |K'_ij| and maxima max_{j != i} |K'_ij| per
+// tile slot (FP64), from the K' plane or from K' recomputed per band.
+template <class ST, int KSRC, int GK>
+__global__ __launch_bounds__(WG) void k_rowsum(const ST* __restrict__ Kp, Features F, KernelParams kp,
                                               const uint32_t* __restrict__ tiles, int NB,
-                                              double* __restrict__ part) {
+                                              double* __restrict__ psum, double* __restrict__ pmax) {
     const TileCoord tc = tile_of(tiles);
     const size_t tbase = (size_t)blockIdx.x * TT;
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, q = l & 15;
     const int col0 = w * 64 + q * 4;
-    __shared__ double rows[4][TILE];
-    double cs[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int s = 0; s < TILE / 4; ++s) {
-        const int r = 4 * s + g;
-        const V4<ST> k = ld4(Kp + tbase + (size_t)r * TILE + col0);
-        double rs = 0.0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const double a = fabs((double)k.v[c]);
-            cs[c] += a;
-            rs += a;
+    __shared__ double rows[4][TILE], rmax[4][TILE];
+    __shared__ float kband[KSRC == KSRC_RECOMPUTE ? 4 : 1][KSRC == KSRC_RECOMPUTE ? 32 * 64 : 1];
+    double cs[4] = {0.0, 0.0, 0.0, 0.0}, cm[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < TILE / 32; ++b) {
+        if constexpr (KSRC == KSRC_RECOMPUTE) {
+            gram_band<GK>(F, kp, tc.I, tc.J, 32 * b, 64 * w, kband[w]);
+            wave_lds_sync();
         }
-        rs = sum16(rs);
-        if (q == 0) rows[w][r] = rs;
+        for (int s2 = 0; s2 < 8; ++s2) {
+            const int r = 32 * b + 4 * s2 + g;
+            V4<ST> k;
+            if constexpr (KSRC == KSRC_RECOMPUTE) {
+                const float4 kk = *reinterpret_cast<const float4*>(&kband[w][(4 * s2 + g) * 64 + 4 * q]);
+                k = V4<ST>{{(ST)kk.x, (ST)kk.y, (ST)kk.z, (ST)kk.w}};
+            } else {
+                k = ld4(Kp + tbase + (size_t)r * TILE + col0);
+            }
+            double rs = 0.0, rm = 0.0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double a = fabs((double)k.v[c]);
+                cs[c] += a;
+                rs += a;
+                cm[c] = fmax(cm[c], a);
+                rm = fmax(rm, a);
+            }
+            rs = sum16(rs);
+            rm = fmax(rm, dpp<0xB1>(rm));
+            rm = fmax(rm, dpp<0x4E>(rm));
+            rm = fmax(rm, dpp<0x141>(rm));
+            rm = fmax(rm, dpp<0x140>(rm));
+            if (q == 0) { rows[w][r] = rs; rmax[w][r] = rm; }
+        }
+        if constexpr (KSRC == KSRC_RECOMPUTE) wave_lds_sync();
     }
 #pragma unroll
-    for (int c = 0; c < 4; ++c) cs[c] = sum_groups(cs[c]);
+    for (int c = 0; c < 4; ++c) {
+        cs[c] = sum_groups(cs[c]);
+        cm[c] = fmax(cm[c], __shfl_xor(cm[c], 16));
+        cm[c] = fmax(cm[c], __shfl_xor(cm[c], 32));
+    }
     __syncthreads();
-    part[((size_t)tc.I * (NB + 1) + tc.J) * TILE + tid] = (rows[0][tid] + rows[1][tid]) + (rows[2][tid] + rows[3][tid]);
+    const size_t rs_ = ((size_t)tc.I * (NB + 1) + tc.J) * TILE + tid;
+    psum[rs_] = (rows[0][tid] + rows[1][tid]) + (rows[2][tid] + rows[3][tid]);
+    pmax[rs_] = fmax(fmax(rmax[0][tid], rmax[1][tid]), fmax(rmax[2][tid], rmax[3][tid]));
     if (g == 0) {
         const int slot = (tc.I < tc.J) ? tc.I : NB;
-        double* dst = part + ((size_t)tc.J * (NB + 1) + slot) * TILE + col0;
+        const size_t cb = ((size_t)tc.J * (NB + 1) + slot) * TILE + col0;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) dst[c] = cs[c];
+        for (int c = 0; c < 4; ++c) { psum[cb + c] = cs[c]; pmax[cb + c] = cm[c]; }
     }
 }
 
-// Weighted diagonal (subsection "GaBP Algorithm Convergence").  For the
-// uniform rule this kernel leaves A_ii - K'_ii per node and a per-block max.
-__global__ void k_diag(int64_t N, int NB, const double* __restrict__ part,
-                       const double* __restrict__ kdiag, int mode, double C, double delta,
-                       double* __restrict__ Adiag, double* __restrict__ blk) {
+// Weighted diagonal (subsection "GaBP Algorithm Convergence") and the row
+// maxima of |K'|.  For the uniform rule this kernel leaves the per-block max
+// of A_ii - K'_ii for k_diag_shift.
+__global__ void k_diag(int64_t N, int NB, const double* __restrict__ psum,
+                       const double* __restrict__ pmax, const double* __restrict__ kdiag, int mode,
+                       double C, double delta, double* __restrict__ Adiag,
+                       double* __restrict__ rowmax, double* __restrict__ blk) {
     __shared__ double sh4[4];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double wv = -INFINITY;
     if (i < N) {
         const int64_t B = i / TILE, t = i % TILE;
-        double r = 0.0;
-        for (int s = 0; s <= NB; ++s) r += part[((size_t)B * (NB + 1) + s) * TILE + t];
+        double r = 0.0, mx = 0.0;
+        for (int s = 0; s <= NB; ++s) {
+            const size_t o = ((size_t)B * (NB + 1) + s) * TILE + t;
+            r += psum[o];
+            mx = fmax(mx, pmax[o]);
+        }
         const double kii = kdiag[i];
         const double soft = kii + 1.0 / C, dom = (1.0 + delta) * r;
         double a;
@@ -388,6 +488,7 @@ __global__ void k_diag(int64_t N, int NB, const double* __restrict__ part,
             default: a = fmax(soft, dom); break;
         }
         Adiag[i] = a;
+        rowmax[i] = mx;
         wv = a - kii;
     }
     if (mode == 3) {
@@ -410,10 +511,18 @@ __global__ void k_diag_shift(int64_t N, const double* __restrict__ kdiag,
     if (i < N) Adiag[i] = kdiag[i] + *shift;
 }
 
-// Sweep 0: aggregates of all-zero messages, P~ = A_ii, S = b = y.  Padded
-// nodes get P~ = 1, S = 0 so that their (zero) messages stay finite.
+__global__ void k_reset_status(DevStatus* st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->t = 0; st->done = 0; st->reason = R_NONE; st->since_best = 0; st->bad = 0; st->pad = 0;
+        st->delta = 0.0; st->amax = 0.0; st->best_delta = INFINITY;
+    }
+}
+
+// Sweep 0: aggregates of all-zero messages, P~ = A_ii, S = b = y, in ring
+// slot 0.  Padded nodes get P~ = 1, S = 0 so that their (zero) messages stay
+// finite.
 template <class AT>
-__global__ void k_init(int64_t N, int64_t NPAD, const double* __restrict__ Adiag,
+__global__ void k_init(int64_t N, int64_t NPAD, int R, const double* __restrict__ Adiag,
                        const float* __restrict__ y, AT* __restrict__ Pt, AT* __restrict__ S,
                        double* __restrict__ alpha, DevStatus* st) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -425,89 +534,160 @@ __global__ void k_init(int64_t N, int64_t NPAD, const double* __restrict__ Adiag
         alpha[i] = (double)(b / a) * (double)y[i];
         if (!(a > (AT)0) || !isfinite((double)a)) st->bad = 1;
     } else {
-        Pt[i] = (AT)1;
-        S[i] = (AT)0;
-    }
-}
-
-__global__ void k_reset_status(DevStatus* st) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        st->t = 0; st->done = 0; st->reason = R_NONE; st->since_best = 0; st->bad = 0; st->pad = 0;
-        st->delta = 0.0; st->amax = 0.0; st->best_delta = INFINITY;
+        // padding rows are never finalized: set them in every ring slot
+        for (int r = 0; r < R; ++r) {
+            Pt[(int64_t)r * NPAD + i] = (AT)1;
+            S[(int64_t)r * NPAD + i] = (AT)0;
+        }
     }
 }
 
 // ------------------------------------------------------------------ sweep --
 
-template <class ST, class MT, class AT, bool FIRST>
-__global__ __launch_bounds__(WG) void k_sweep_stored(
-    const uint32_t* __restrict__ tiles, int NB, const ST* __restrict__ Kp, ST* __restrict__ Pf,
-    ST* __restrict__ Pb, ST* __restrict__ Ef, ST* __restrict__ Eb, const AT* __restrict__ Pt,
-    const AT* __restrict__ S, AT* __restrict__ partP, AT* __restrict__ partE, DevStatus* st) {
+// One synchronous sweep over all tiles.  Template parameters:
+//   ST storage type of K' and the message planes, MT type of the top-level
+//   update (cavity denominators, reciprocals), AT aggregate type;
+//   KSRC: K' from the materialised plane or recomputed per 32-row band;
+//   GK: Gram kind of the recompute;
+//   D: 0 = stored edge state (pair-record planes read and written);
+//      D >= 1 = stateless: the messages of the previous sweep are rebuilt
+//      from the aggregates of up to D earlier sweeps (runtime depth L <= D),
+//      deeper levels in LT = float (FP32/MIXED) or double (FP64);
+//   FIRST: the stored planes are all zero (sweep 1) and are not read.
+template <class ST, class MT, class AT, int KSRC, int GK, int D, bool FIRST>
+__global__ __launch_bounds__(WG) void k_sweep(SweepArgs a) {
+    DevStatus* st = a.st;
     if (st->done) return;
-    const TileCoord tc = tile_of(tiles);
+    using LT = typename std::conditional<std::is_same<ST, double>::value, double, float>::type;
+    constexpr bool STORED = (D == 0);
+    constexpr int DL = (D > 1) ? D - 1 : 1;   // lower levels held per node
+    const TileCoord tc = tile_of(a.tiles);
+    const int NB = a.NB;
     const size_t tbase = (size_t)blockIdx.x * TT;
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, q = l & 15;
     const int col0 = w * 64 + q * 4;
+    const int L = a.levels;
+    const AT* HP = static_cast<const AT*>(a.HP);
+    const AT* HS = static_cast<const AT*>(a.HS);
+    const ST* Kp = static_cast<const ST*>(a.Kp);
+    ST* Pf = static_cast<ST*>(a.Pf);
+    ST* Pb = static_cast<ST*>(a.Pb);
+    ST* Ef = static_cast<ST*>(a.Ef);
+    ST* Eb = static_cast<ST*>(a.Eb);
 
     __shared__ AT sPt[TILE], sS[TILE];
+    __shared__ LT sPtL[STORED ? 1 : DL][STORED ? 1 : TILE], sSL[STORED ? 1 : DL][STORED ? 1 : TILE];
     __shared__ AT rP[4][TILE], rE[4][TILE];
-    sPt[tid] = Pt[(int64_t)tc.I * TILE + tid];
-    sS[tid] = S[(int64_t)tc.I * TILE + tid];
+    __shared__ float kband[KSRC == KSRC_RECOMPUTE ? 4 : 1][KSRC == KSRC_RECOMPUTE ? 32 * 64 : 1];
+
+    const int64_t top = (int64_t)a.slot_top * a.NPAD;
+    sPt[tid] = HP[top + (int64_t)tc.I * TILE + tid];
+    sS[tid] = HS[top + (int64_t)tc.I * TILE + tid];
     MT ptj[4], sj[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        ptj[c] = (MT)Pt[(int64_t)tc.J * TILE + col0 + c];
-        sj[c] = (MT)S[(int64_t)tc.J * TILE + col0 + c];
+        ptj[c] = (MT)HP[top + (int64_t)tc.J * TILE + col0 + c];
+        sj[c] = (MT)HS[top + (int64_t)tc.J * TILE + col0 + c];
+    }
+    LT ptjL[DL][4], sjL[DL][4];
+    if constexpr (!STORED) {
+#pragma unroll
+        for (int k = 1; k < D; ++k) {
+            if (k < L) {
+                const int64_t base = (int64_t)((a.slot_top - k + a.R) % a.R) * a.NPAD;
+                sPtL[k - 1][tid] = (LT)HP[base + (int64_t)tc.I * TILE + tid];
+                sSL[k - 1][tid] = (LT)HS[base + (int64_t)tc.I * TILE + tid];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    ptjL[k - 1][c] = (LT)HP[base + (int64_t)tc.J * TILE + col0 + c];
+                    sjL[k - 1][c] = (LT)HS[base + (int64_t)tc.J * TILE + col0 + c];
+                }
+            }
+        }
     }
     AT cP[4] = {0, 0, 0, 0}, cE[4] = {0, 0, 0, 0};
     bool bad = false;
     __syncthreads();
 
-    const ST* kp = Kp + tbase + (size_t)g * TILE + col0;
     size_t off = tbase + (size_t)g * TILE + col0;
-    V4<ST> k = ld4(kp);
-    V4<ST> pf{}, pb{}, ef{}, eb{};
-    if (!FIRST) { pf = ld4(Pf + off); pb = ld4(Pb + off); ef = ld4(Ef + off); eb = ld4(Eb + off); }
+    V4<ST> k{}, pf{}, pb{}, ef{}, eb{};
+    if constexpr (KSRC == KSRC_PLANE) k = ld4(Kp + off);
+    if constexpr (STORED && !FIRST) { pf = ld4(Pf + off); pb = ld4(Pb + off); ef = ld4(Ef + off); eb = ld4(Eb + off); }
 
-    for (int s = 0; s < TILE / 4; ++s) {
-        const int r = 4 * s + g;
-        // prefetch the next row of this lane
-        V4<ST> k2{}, pf2{}, pb2{}, ef2{}, eb2{};
-        const size_t off2 = off + 4 * TILE;
-        if (s + 1 < TILE / 4) {
-            k2 = ld4(Kp + off2);
-            if (!FIRST) { pf2 = ld4(Pf + off2); pb2 = ld4(Pb + off2); ef2 = ld4(Ef + off2); eb2 = ld4(Eb + off2); }
+    for (int b = 0; b < TILE / 32; ++b) {
+        if constexpr (KSRC == KSRC_RECOMPUTE) {
+            gram_band<GK>(a.F, a.kp, tc.I, tc.J, 32 * b, 64 * w, kband[w]);
+            wave_lds_sync();
         }
-        const MT pti = (MT)sPt[r], si = (MT)sS[r];
-        AT rp = 0, re = 0;
-        V4<ST> npf, npb, nef, neb;
+        for (int s2 = 0; s2 < 8; ++s2) {
+            const int r = 32 * b + 4 * s2 + g;
+            const bool more = (b * 8 + s2 + 1) < TILE / 4;
+            // prefetch the lane's next row
+            V4<ST> k2{}, pf2{}, pb2{}, ef2{}, eb2{};
+            const size_t off2 = off + 4 * TILE;
+            if (more) {
+                if constexpr (KSRC == KSRC_PLANE) k2 = ld4(Kp + off2);
+                if constexpr (STORED && !FIRST) { pf2 = ld4(Pf + off2); pb2 = ld4(Pb + off2); ef2 = ld4(Ef + off2); eb2 = ld4(Eb + off2); }
+            }
+            if constexpr (KSRC == KSRC_RECOMPUTE) {
+                const float4 kk = *reinterpret_cast<const float4*>(&kband[w][(4 * s2 + g) * 64 + 4 * q]);
+                k = V4<ST>{{(ST)kk.x, (ST)kk.y, (ST)kk.z, (ST)kk.w}};
+            }
+            const MT pti = (MT)sPt[r], si = (MT)sS[r];
+            AT rp = 0, re = 0;
+            V4<ST> npf, npb, nef, neb;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const MT a = (MT)k.v[c];
-            const MT a2 = a * a;
-            const MT qf = pti - (MT)pb.v[c];       // P~_i - P_ji
-            const MT qb = ptj[c] - (MT)pf.v[c];    // P~_j - P_ij
-            bad |= !(qf > (MT)0) | !(qb > (MT)0);
-            const MT rf = (MT)1 / qf, rb = (MT)1 / qb;
-            const ST pij = (ST)(-a2 * rf);
-            const ST eij = (ST)(-a * (si - (MT)eb.v[c]) * rf);
-            const ST pji = (ST)(-a2 * rb);
-            const ST eji = (ST)(-a * (sj[c] - (MT)ef.v[c]) * rb);
-            npf.v[c] = pij; nef.v[c] = eij; npb.v[c] = pji; neb.v[c] = eji;
-            cP[c] += (AT)pij; cE[c] += (AT)eij;     // received by column node j
-            rp += (AT)pji; re += (AT)eji;            // received by row node i
+            for (int c = 0; c < 4; ++c) {
+                const MT av = (MT)k.v[c];
+                // messages of the previous sweep: stored, or rebuilt level by level
+                MT opf, opb, oef, oeb;
+                if constexpr (STORED) {
+                    opf = (MT)pf.v[c]; opb = (MT)pb.v[c]; oef = (MT)ef.v[c]; oeb = (MT)eb.v[c];
+                } else {
+                    const LT al = (LT)k.v[c], a2l = al * al;
+                    LT lpf = 0, lpb = 0, lef = 0, leb = 0;
+#pragma unroll
+                    for (int kk = D - 1; kk >= 1; --kk) {
+                        if (kk < L) {
+                            const LT qf = sPtL[kk - 1][r] - lpb, qb = ptjL[kk - 1][c] - lpf;
+                            bad |= !(qf > (LT)0) | !(qb > (LT)0);
+                            const LT rf = rcp_fast(qf), rb = rcp_fast(qb);
+                            const LT npf_ = -a2l * rf, npb_ = -a2l * rb;
+                            const LT nef_ = -al * (sSL[kk - 1][r] - leb) * rf;
+                            const LT neb_ = -al * (sjL[kk - 1][c] - lef) * rb;
+                            lpf = npf_; lpb = npb_; lef = nef_; leb = neb_;
+                        }
+                    }
+                    opf = (MT)lpf; opb = (MT)lpb; oef = (MT)lef; oeb = (MT)leb;
+                }
+                const MT a2 = av * av;
+                const MT qf = pti - opb;        // P~_i - P_ji
+                const MT qb = ptj[c] - opf;     // P~_j - P_ij
+                bad |= !(qf > (MT)0) | !(qb > (MT)0);
+                const MT rf = rcp_fast(qf), rb = rcp_fast(qb);
+                const ST pij = (ST)(-a2 * rf);
+                const ST eij = (ST)(-av * (si - oeb) * rf);
+                const ST pji = (ST)(-a2 * rb);
+                const ST eji = (ST)(-av * (sj[c] - oef) * rb);
+                npf.v[c] = pij; nef.v[c] = eij; npb.v[c] = pji; neb.v[c] = eji;
+                cP[c] += (AT)pij; cE[c] += (AT)eij;     // received by column node j
+                rp += (AT)pji; re += (AT)eji;            // received by row node i
+            }
+            if constexpr (STORED) { st4(Pf + off, npf); st4(Pb + off, npb); st4(Ef + off, nef); st4(Eb + off, neb); }
+            rp = sum16(rp);
+            re = sum16(re);
+            if (q == 0) { rP[w][r] = rp; rE[w][r] = re; }
+            if constexpr (KSRC == KSRC_PLANE) k = k2;
+            if constexpr (STORED && !FIRST) { pf = pf2; pb = pb2; ef = ef2; eb = eb2; }
+            off = off2;
         }
-        st4(Pf + off, npf); st4(Pb + off, npb); st4(Ef + off, nef); st4(Eb + off, neb);
-        rp = sum16(rp);
-        re = sum16(re);
-        if (q == 0) { rP[w][r] = rp; rE[w][r] = re; }
-        k = k2; pf = pf2; pb = pb2; ef = ef2; eb = eb2;
-        off = off2;
+        if constexpr (KSRC == KSRC_RECOMPUTE) wave_lds_sync();
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) { cP[c] = sum_groups(cP[c]); cE[c] = sum_groups(cE[c]); }
     __syncthreads();
+    AT* partP = static_cast<AT*>(a.partP);
+    AT* partE = static_cast<AT*>(a.partE);
     const size_t rowslot = ((size_t)tc.I * (NB + 1) + tc.J) * TILE + tid;
     partP[rowslot] = (rP[0][tid] + rP[1][tid]) + (rP[2][tid] + rP[3][tid]);
     partE[rowslot] = (rE[0][tid] + rE[1][tid]) + (rE[2][tid] + rE[3][tid]);
@@ -520,8 +700,8 @@ __global__ __launch_bounds__(WG) void k_sweep_stored(
     if (__any(bad) && l == 0) st->bad = 1;
 }
 
-// Aggregates of the new sweep from the partial sums (fixed order), the new
-// alpha and the per-block change / magnitude maxima.
+// Aggregates of the new sweep from the partial sums (fixed order) into ring
+// slot `wslot`, the new alpha and the per-block change / magnitude maxima.
 template <class AT>
 __global__ __launch_bounds__(WG) void k_finalize(int64_t N, int NB, const AT* __restrict__ partP,
                                                 const AT* __restrict__ partE,
@@ -589,6 +769,19 @@ __global__ __launch_bounds__(WG) void k_status(int nblk, const double* __restric
     }
 }
 
+// Contraction estimate of the message recursion, max_i rowmax_i / P~_i,
+// per block (the reverse message enters the next one with a factor A_ij / Q).
+template <class AT>
+__global__ void k_rho(int64_t N, const double* __restrict__ rowmax, const AT* __restrict__ Pt,
+                      double* __restrict__ blk) {
+    __shared__ double sh4[4];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double v = 0.0;
+    if (i < N) v = rowmax[i] / (double)Pt[i];
+    v = block_max(v, sh4);
+    if (threadIdx.x == 0) blk[blockIdx.x] = v;
+}
+
 // ------------------------------------------------------------- queries --
 
 template <class ST>
@@ -654,7 +847,7 @@ hipError_t launch_fill_tiles(uint32_t* tiles, int NB, hipStream_t s) {
 
 hipError_t launch_validate(const float* X, const float* y, int64_t N, int64_t m, int32_t* flag,
                            hipStream_t s) {
-    int64_t n = N * m;
+    int64_t n = std::max<int64_t>(N * m, N);
     unsigned g = (unsigned)std::min<int64_t>((n + WG - 1) / WG, 4096);
     if (g == 0) g = 1;
     hipLaunchKernelGGL(k_validate, dim3(g), dim3(WG), 0, s, X, y, N, m, flag);
@@ -675,7 +868,7 @@ hipError_t launch_stage(const float* X, const double* mean, int64_t N, int64_t m
 }
 
 hipError_t launch_gram(const Features& F, const KernelParams& kp, const uint32_t* tiles,
-                       int64_t ntiles, void* Kp, int prec, hipStream_t s) {
+                       int64_t ntiles, void* Kp, hipStream_t s) {
     const dim3 g((unsigned)ntiles), b(WG);
     switch (F.kind) {
         case GRAM_F32: hipLaunchKernelGGL(k_gram_mfma<GRAM_F32>, g, b, 0, s, F, kp, tiles, (float*)Kp); break;
@@ -685,7 +878,6 @@ hipError_t launch_gram(const Features& F, const KernelParams& kp, const uint32_t
         case GRAM_F64: hipLaunchKernelGGL(k_gram_f64, g, b, 0, s, F, kp, tiles, (double*)Kp); break;
         default: return hipErrorInvalidValue;
     }
-    (void)prec;
     return hipGetLastError();
 }
 
@@ -705,22 +897,33 @@ hipError_t launch_fill_value(double* dst, int64_t n, double v, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_rowsum(const void* Kp, int prec, const uint32_t* tiles, int64_t ntiles, int NB,
-                         double* partR, hipStream_t s) {
+hipError_t launch_rowsum(const void* Kp, int prec, int ksrc, const Features& F, const KernelParams& kp,
+                         const uint32_t* tiles, int64_t ntiles, int NB, double* psum, double* pmax,
+                         hipStream_t s) {
     const dim3 g((unsigned)ntiles), b(WG);
-    if (prec == PREC_FP64)
-        hipLaunchKernelGGL(k_rowsum<double>, g, b, 0, s, (const double*)Kp, tiles, NB, partR);
-    else
-        hipLaunchKernelGGL(k_rowsum<float>, g, b, 0, s, (const float*)Kp, tiles, NB, partR);
+    if (ksrc == KSRC_PLANE) {
+        if (prec == PREC_FP64)
+            hipLaunchKernelGGL((k_rowsum<double, KSRC_PLANE, GRAM_F64>), g, b, 0, s, (const double*)Kp, F, kp, tiles, NB, psum, pmax);
+        else
+            hipLaunchKernelGGL((k_rowsum<float, KSRC_PLANE, GRAM_F32>), g, b, 0, s, (const float*)Kp, F, kp, tiles, NB, psum, pmax);
+    } else {
+        switch (F.kind) {
+            case GRAM_F32: hipLaunchKernelGGL((k_rowsum<float, KSRC_RECOMPUTE, GRAM_F32>), g, b, 0, s, nullptr, F, kp, tiles, NB, psum, pmax); break;
+            case GRAM_BF16: hipLaunchKernelGGL((k_rowsum<float, KSRC_RECOMPUTE, GRAM_BF16>), g, b, 0, s, nullptr, F, kp, tiles, NB, psum, pmax); break;
+            case GRAM_BF16X3: hipLaunchKernelGGL((k_rowsum<float, KSRC_RECOMPUTE, GRAM_BF16X3>), g, b, 0, s, nullptr, F, kp, tiles, NB, psum, pmax); break;
+            case GRAM_BF16X6: hipLaunchKernelGGL((k_rowsum<float, KSRC_RECOMPUTE, GRAM_BF16X6>), g, b, 0, s, nullptr, F, kp, tiles, NB, psum, pmax); break;
+            default: return hipErrorInvalidValue;
+        }
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_diag(int64_t N, int NB, const double* partR, const double* kdiag, int mode,
-                       double C, double delta, double* Adiag, double* scratch_blk,
-                       double* scratch_one, hipStream_t s) {
+hipError_t launch_diag(int64_t N, int NB, const double* psum, const double* pmax, const double* kdiag,
+                       int mode, double C, double delta, double* Adiag, double* rowmax,
+                       double* scratch_blk, double* scratch_one, hipStream_t s) {
     const unsigned nb = grid1(N);
-    hipLaunchKernelGGL(k_diag, dim3(nb), dim3(WG), 0, s, N, NB, partR, kdiag, mode, C, delta, Adiag,
-                       scratch_blk);
+    hipLaunchKernelGGL(k_diag, dim3(nb), dim3(WG), 0, s, N, NB, psum, pmax, kdiag, mode, C, delta, Adiag,
+                       rowmax, scratch_blk);
     if (mode == 3) {
         hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(WG), 0, s, (int)nb, scratch_blk, scratch_one);
         hipLaunchKernelGGL(k_diag_shift, dim3(nb), dim3(WG), 0, s, N, kdiag, scratch_one, Adiag);
@@ -728,39 +931,65 @@ hipError_t launch_diag(int64_t N, int NB, const double* partR, const double* kdi
     return hipGetLastError();
 }
 
-hipError_t launch_init(int prec, int64_t N, int64_t NPAD, const double* Adiag, const float* y,
+hipError_t launch_init(int prec, int64_t N, int64_t NPAD, int R, const double* Adiag, const float* y,
                        void* Pt, void* S, double* alpha, DevStatus* st, hipStream_t s) {
     hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(64), 0, s, st);
     if (prec == PREC_FP32)
-        hipLaunchKernelGGL(k_init<float>, dim3(grid1(NPAD)), dim3(WG), 0, s, N, NPAD, Adiag, y,
+        hipLaunchKernelGGL(k_init<float>, dim3(grid1(NPAD)), dim3(WG), 0, s, N, NPAD, R, Adiag, y,
                            (float*)Pt, (float*)S, alpha, st);
     else
-        hipLaunchKernelGGL(k_init<double>, dim3(grid1(NPAD)), dim3(WG), 0, s, N, NPAD, Adiag, y,
+        hipLaunchKernelGGL(k_init<double>, dim3(grid1(NPAD)), dim3(WG), 0, s, N, NPAD, R, Adiag, y,
                            (double*)Pt, (double*)S, alpha, st);
     return hipGetLastError();
 }
 
-template <class ST, class MT, class AT>
-static void sweep_stored_t(bool first, const SweepBufs& b, hipStream_t s) {
-    const dim3 g((unsigned)b.ntiles), blk(WG);
-    if (first)
-        hipLaunchKernelGGL((k_sweep_stored<ST, MT, AT, true>), g, blk, 0, s, b.tiles, b.NB,
-                           (const ST*)b.Kp, (ST*)b.Pf, (ST*)b.Pb, (ST*)b.Ef, (ST*)b.Eb,
-                           (const AT*)b.Pt, (const AT*)b.S, (AT*)b.partP, (AT*)b.partE, b.st);
-    else
-        hipLaunchKernelGGL((k_sweep_stored<ST, MT, AT, false>), g, blk, 0, s, b.tiles, b.NB,
-                           (const ST*)b.Kp, (ST*)b.Pf, (ST*)b.Pb, (ST*)b.Ef, (ST*)b.Eb,
-                           (const AT*)b.Pt, (const AT*)b.S, (AT*)b.partP, (AT*)b.partE, b.st);
+// ---- sweep dispatch: precision x K' source x Gram kind x depth x first
+template <class ST, class MT, class AT, int KSRC, int GK, int D>
+static void sweep_d(bool first, const SweepArgs& a, hipStream_t s) {
+    const dim3 g((unsigned)a.ntiles), blk(WG);
+    if constexpr (D == 0) {
+        if (first) {
+            hipLaunchKernelGGL((k_sweep<ST, MT, AT, KSRC, GK, D, true>), g, blk, 0, s, a);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_sweep<ST, MT, AT, KSRC, GK, D, false>), g, blk, 0, s, a);
 }
 
-hipError_t launch_sweep_stored(int prec, bool first, const SweepBufs& b, hipStream_t s) {
-    switch (prec) {
-        case PREC_FP32: sweep_stored_t<float, float, float>(first, b, s); break;
-        case PREC_MIXED: sweep_stored_t<float, double, double>(first, b, s); break;
-        case PREC_FP64: sweep_stored_t<double, double, double>(first, b, s); break;
+template <class ST, class MT, class AT, int KSRC, int GK>
+static hipError_t sweep_depth(int depth, bool first, const SweepArgs& a, hipStream_t s) {
+    switch (depth) {
+        case 0: sweep_d<ST, MT, AT, KSRC, GK, 0>(first, a, s); break;
+        case 1: case 2: sweep_d<ST, MT, AT, KSRC, GK, 2>(first, a, s); break;
+        case 3: case 4: sweep_d<ST, MT, AT, KSRC, GK, 4>(first, a, s); break;
+        case 5: case 6: sweep_d<ST, MT, AT, KSRC, GK, 6>(first, a, s); break;
+        case 7: case 8: sweep_d<ST, MT, AT, KSRC, GK, 8>(first, a, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_sweep(int prec, int ksrc, int gram, int depth, bool first, const SweepArgs& a,
+                        hipStream_t s) {
+    if (ksrc == KSRC_PLANE) {
+        switch (prec) {
+            case PREC_FP32: return sweep_depth<float, float, float, KSRC_PLANE, GRAM_F32>(depth, first, a, s);
+            case PREC_MIXED: return sweep_depth<float, double, double, KSRC_PLANE, GRAM_F32>(depth, first, a, s);
+            case PREC_FP64: return sweep_depth<double, double, double, KSRC_PLANE, GRAM_F64>(depth, first, a, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    if (prec == PREC_FP32 && gram == GRAM_F32)
+        return sweep_depth<float, float, float, KSRC_RECOMPUTE, GRAM_F32>(depth, first, a, s);
+    if (prec == PREC_MIXED) {
+        switch (gram) {
+            case GRAM_BF16: return sweep_depth<float, double, double, KSRC_RECOMPUTE, GRAM_BF16>(depth, first, a, s);
+            case GRAM_BF16X3: return sweep_depth<float, double, double, KSRC_RECOMPUTE, GRAM_BF16X3>(depth, first, a, s);
+            case GRAM_BF16X6: return sweep_depth<float, double, double, KSRC_RECOMPUTE, GRAM_BF16X6>(depth, first, a, s);
+            default: break;
+        }
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_finalize(int prec, int64_t N, int NB, const void* partP, const void* partE,
@@ -781,6 +1010,17 @@ hipError_t launch_finalize(int prec, int64_t N, int NB, const void* partP, const
 hipError_t launch_status(int nblk, const double* blk_delta, const double* blk_amax, DevStatus* st,
                          double* trace, StopRule rule, hipStream_t s) {
     hipLaunchKernelGGL(k_status, dim3(1), dim3(WG), 0, s, nblk, blk_delta, blk_amax, st, trace, rule);
+    return hipGetLastError();
+}
+
+hipError_t launch_rho(int prec, int64_t N, const double* rowmax, const void* Pt, double* blk,
+                      double* one, hipStream_t s) {
+    const unsigned nb = grid1(N);
+    if (prec == PREC_FP32)
+        hipLaunchKernelGGL(k_rho<float>, dim3(nb), dim3(WG), 0, s, N, rowmax, (const float*)Pt, blk);
+    else
+        hipLaunchKernelGGL(k_rho<double>, dim3(nb), dim3(WG), 0, s, N, rowmax, (const double*)Pt, blk);
+    hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(WG), 0, s, (int)nb, blk, one);
     return hipGetLastError();
 }
 

@@ -70,12 +70,12 @@ struct gabp_svm {
     gabp_timings tm{};
     gabp_plan plan{};
     // device memory owned by the handle
-    DevBuf tiles, Kp, Pf, Pb, Ef, Eb, partP, partE, Xin, yd, mean, xs32, xhi, xlo, xlo2, x64, nrm, kdiag,
+    DevBuf tiles, Kp, Pf, Pb, Ef, Eb, partP, partE, Xin, yd, mean, xs32, xhi, xlo, xlo2, x64, nrm, kdiag, rowmax,
         Adiag, Pt, S, alpha_d, blk1, blk2, one, status_d, trace_d, flag, tmp, Kin, q_rows, q_cols,
         q_out;
 
-    DevBuf* all[34] = {&tiles, &Kp, &Pf, &Pb, &Ef, &Eb, &partP, &partE, &Xin, &yd, &mean,
-                       &xs32, &xhi, &xlo, &xlo2, &x64, &nrm, &kdiag, &Adiag, &Pt, &S, &alpha_d,
+    DevBuf* all[35] = {&tiles, &Kp, &Pf, &Pb, &Ef, &Eb, &partP, &partE, &Xin, &yd, &mean,
+                       &xs32, &xhi, &xlo, &xlo2, &x64, &nrm, &kdiag, &rowmax, &Adiag, &Pt, &S, &alpha_d,
                        &blk1, &blk2, &one, &status_d, &trace_d, &flag, &tmp, &Kin, &q_rows,
                        &q_cols, &q_out, nullptr};
     size_t held() const {
@@ -177,8 +177,6 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     if (prec == PREC_FP64) gram = GRAM_F64;
     else if (prec == PREC_MIXED)
         gram = (p.gram == GABP_GRAM_BF16) ? GRAM_BF16 : (p.gram == GABP_GRAM_BF16X3) ? GRAM_BF16X3 : GRAM_BF16X6;
-    if (p.kstore == GABP_KSTORE_RECOMPUTE) return fail(h, GABP_E_INVALID, "kstore RECOMPUTE is not available in this build");
-    if (p.edge_state == GABP_EDGE_STATELESS) return fail(h, GABP_E_INVALID, "edge_state STATELESS is not available in this build");
     const int NB = (int)((N + TILE - 1) / TILE);
     const int64_t NPAD = (int64_t)NB * TILE;
     const int64_t nt = n_tiles(NB);
@@ -199,30 +197,52 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     } else if (mem == GABP_MEM_HOST) {
         feat = (size_t)N * N * 8;
     }
-    const size_t vecs = (size_t)NPAD * 8 * 8 + (size_t)nt * 4 + (size_t)p.max_sweeps * 8 + 4096;
-    const size_t need = 5 * plane + 2 * part + feat + vecs;
+    const size_t vecs = (size_t)NPAD * 8 * 10 + (size_t)nt * 4 + (size_t)p.max_sweeps * 8 + 4096;
     size_t free_b = 0, total_b = 0;
     HIPCHK(h, hipSetDevice(p.device));
     HIPCHK(h, hipMemGetInfo(&free_b, &total_b));
     const size_t avail = free_b + h->held();
     const size_t budget = p.hbm_budget_bytes ? (size_t)p.hbm_budget_bytes : (size_t)(0.92 * (double)avail);
-    if (need > budget) {
+    const bool can_recompute = rbf && prec != PREC_FP64;
+    // candidate plans in order of preference: (materialised K', stored edges) first
+    struct Cand { bool kmat, stored; };
+    const Cand cands[4] = {{true, true}, {false, true}, {true, false}, {false, false}};
+    bool have = false, kmat = true, stored = true;
+    size_t need = 0, need_min = SIZE_MAX;
+    for (const Cand& c : cands) {
+        if (p.kstore == GABP_KSTORE_MATERIALISE && !c.kmat) continue;
+        if (p.kstore == GABP_KSTORE_RECOMPUTE && c.kmat) continue;
+        if (p.edge_state == GABP_EDGE_STORED && !c.stored) continue;
+        if (p.edge_state == GABP_EDGE_STATELESS && c.stored) continue;
+        if (!c.kmat && !can_recompute) continue;
+        const int R = c.stored ? 1 : 8;
+        const size_t n_ = (c.stored ? 4 * plane : 0) + (c.kmat ? plane : 0) + 2 * part + feat + vecs +
+                          (size_t)2 * R * NPAD * 8;
+        need_min = std::min(need_min, n_);
+        if (n_ <= budget) { have = true; kmat = c.kmat; stored = c.stored; need = n_; break; }
+    }
+    if (need_min == SIZE_MAX)
+        return fail(h, GABP_E_INVALID, "no plan matches the requested kstore/edge_state/precision "
+                                       "(recompute needs RBF features and FP32 or MIXED precision)");
+    if (!have) {
         char msg[256];
-        snprintf(msg, sizeof msg, "plan needs %.3f GB, budget %.3f GB", need / 1e9, budget / 1e9);
+        snprintf(msg, sizeof msg, "smallest allowed plan needs %.3f GB, budget %.3f GB", need_min / 1e9, budget / 1e9);
         return fail(h, GABP_E_NOMEM, msg);
     }
-    if (need > avail) h->release_all();
+    if (need > free_b) h->release_all();
+    const int R = stored ? 1 : 8;
+    const int ksrc = kmat ? KSRC_PLANE : KSRC_RECOMPUTE;
 
-    auto alloc = [&](DevBuf& b, size_t n) -> hipError_t { return b.ensure(n); };
     hipError_t ae = hipSuccess;
-    auto A = [&](DevBuf& b, size_t n) { if (ae == hipSuccess) ae = alloc(b, n); };
+    auto A = [&](DevBuf& b, size_t n) { if (ae == hipSuccess) ae = b.ensure(n); };
     A(h->tiles, (size_t)nt * 4);
-    A(h->Kp, plane);
-    A(h->Pf, plane); A(h->Pb, plane); A(h->Ef, plane); A(h->Eb, plane);
+    if (kmat) A(h->Kp, plane); else h->Kp.release();
+    if (stored) { A(h->Pf, plane); A(h->Pb, plane); A(h->Ef, plane); A(h->Eb, plane); }
+    else { h->Pf.release(); h->Pb.release(); h->Ef.release(); h->Eb.release(); }
     A(h->partP, part); A(h->partE, part);
     A(h->yd, (size_t)N * 4);
-    A(h->kdiag, (size_t)N * 8); A(h->Adiag, (size_t)N * 8);
-    A(h->Pt, (size_t)NPAD * 8); A(h->S, (size_t)NPAD * 8);
+    A(h->kdiag, (size_t)N * 8); A(h->Adiag, (size_t)N * 8); A(h->rowmax, (size_t)N * 8);
+    A(h->Pt, (size_t)R * NPAD * 8); A(h->S, (size_t)R * NPAD * 8);
     A(h->alpha_d, (size_t)N * 8); A(h->tmp, (size_t)NPAD * 8);
     A(h->blk1, (size_t)(NPAD / WG + 1) * 8); A(h->blk2, (size_t)(NPAD / WG + 1) * 8);
     A(h->one, 64); A(h->status_d, sizeof(DevStatus)); A(h->flag, 64);
@@ -296,10 +316,10 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     }
     HIPCHK(h, hipEventRecord(ev[1], s));
 
-    // ---- K' tiles
+    // ---- K' tiles (materialised plan)
     HIPCHK(h, launch_fill_tiles(h->tiles.as<uint32_t>(), NB, s));
     if (rbf) {
-        HIPCHK(h, launch_gram(F, kp, h->tiles.as<uint32_t>(), nt, h->Kp.p, prec, s));
+        if (kmat) HIPCHK(h, launch_gram(F, kp, h->tiles.as<uint32_t>(), nt, h->Kp.p, s));
         HIPCHK(h, launch_fill_value(h->kdiag.as<double>(), N, 1.0 + lam * lam, s));
     } else {
         HIPCHK(h, launch_gather_dense(Kd, kp, h->tiles.as<uint32_t>(), nt, h->Kp.p, prec,
@@ -308,41 +328,67 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     HIPCHK(h, hipEventRecord(ev[2], s));
 
     // ---- diagonal weighting and sweep 0
-    HIPCHK(h, launch_rowsum(h->Kp.p, prec, h->tiles.as<uint32_t>(), nt, NB, h->partP.as<double>(), s));
-    HIPCHK(h, launch_diag(N, NB, h->partP.as<double>(), h->kdiag.as<double>(), p.diag_mode, p.C,
-                          p.diag_delta, h->Adiag.as<double>(), h->blk1.as<double>(),
-                          h->one.as<double>(), s));
+    HIPCHK(h, launch_rowsum(h->Kp.p, prec, ksrc, F, kp, h->tiles.as<uint32_t>(), nt, NB,
+                            h->partP.as<double>(), h->partE.as<double>(), s));
+    HIPCHK(h, launch_diag(N, NB, h->partP.as<double>(), h->partE.as<double>(), h->kdiag.as<double>(),
+                          p.diag_mode, p.C, p.diag_delta, h->Adiag.as<double>(), h->rowmax.as<double>(),
+                          h->blk1.as<double>(), h->one.as<double>(), s));
     DevStatus* st = h->status_d.as<DevStatus>();
-    HIPCHK(h, launch_init(prec, N, NPAD, h->Adiag.as<double>(), h->yd.as<float>(), h->Pt.p, h->S.p,
+    HIPCHK(h, launch_init(prec, N, NPAD, R, h->Adiag.as<double>(), h->yd.as<float>(), h->Pt.p, h->S.p,
                           h->alpha_d.as<double>(), st, s));
     HIPCHK(h, hipEventRecord(ev[3], s));
 
     // ---- sweeps
-    SweepBufs sb{};
-    sb.tiles = h->tiles.as<uint32_t>();
-    sb.ntiles = nt;
-    sb.NB = NB;
-    sb.Kp = h->Kp.p;
-    sb.Pf = h->Pf.p; sb.Pb = h->Pb.p; sb.Ef = h->Ef.p; sb.Eb = h->Eb.p;
-    sb.Pt = h->Pt.p; sb.S = h->S.p;
-    sb.partP = h->partP.p; sb.partE = h->partE.p;
-    sb.st = st;
+    const size_t agg_bytes = (prec == PREC_FP32) ? 4 : 8;
+    SweepArgs sa{};
+    sa.tiles = h->tiles.as<uint32_t>();
+    sa.ntiles = nt;
+    sa.NB = NB;
+    sa.Kp = h->Kp.p;
+    sa.Pf = h->Pf.p; sa.Pb = h->Pb.p; sa.Ef = h->Ef.p; sa.Eb = h->Eb.p;
+    sa.HP = h->Pt.p; sa.HS = h->S.p;
+    sa.NPAD = NPAD;
+    sa.R = R;
+    sa.partP = h->partP.p; sa.partE = h->partE.p;
+    sa.st = st;
+    sa.F = F;
+    sa.kp = kp;
     StopRule rule{p.tol_abs, p.tol_rel, p.stagnation_rel, p.max_sweeps, p.stagnation_window};
     const int nblk = (int)((N + WG - 1) / WG);
+    // stateless depth: requested, or chosen after sweep 1 from the contraction
+    // estimate rho = max_i max_j |K'_ij| / P~_i so that rho^depth <= eps
+    int depth = stored ? 0 : (p.stateless_depth > 0 ? p.stateless_depth : 2);
+    const bool auto_depth = !stored && p.stateless_depth == 0;
+    double rho = 0.0;
     DevStatus hs{};
     double sweep_kernel_ms = 0.0;
     int64_t launches = 0;
     int polled = 0;
     for (int t = 0; t < p.max_sweeps; ++t) {
         const int slot = t % ce;
+        sa.slot_top = t % R;
+        sa.levels = stored ? 0 : std::min(t + 1, depth);
         if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot], s));
-        HIPCHK(h, launch_sweep_stored(prec, t == 0, sb, s));
+        HIPCHK(h, launch_sweep(prec, ksrc, gram, depth, t == 0, sa, s));
         if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot + 1], s));
+        char* wP = static_cast<char*>(h->Pt.p) + (size_t)((t + 1) % R) * NPAD * agg_bytes;
+        char* wS = static_cast<char*>(h->S.p) + (size_t)((t + 1) % R) * NPAD * agg_bytes;
         HIPCHK(h, launch_finalize(prec, N, NB, h->partP.p, h->partE.p, h->Adiag.as<double>(),
-                                  h->yd.as<float>(), h->Pt.p, h->S.p, h->alpha_d.as<double>(),
+                                  h->yd.as<float>(), wP, wS, h->alpha_d.as<double>(),
                                   h->blk1.as<double>(), h->blk2.as<double>(), st, s));
         HIPCHK(h, launch_status(nblk, h->blk1.as<double>(), h->blk2.as<double>(), st,
                                 h->trace_d.as<double>(), rule, s));
+        if (auto_depth && t == 0) {
+            HIPCHK(h, launch_rho(prec, N, h->rowmax.as<double>(), wP, h->blk1.as<double>(),
+                                 h->one.as<double>(), s));
+            HIPCHK(h, hipMemcpyAsync(&rho, h->one.p, 8, hipMemcpyDeviceToHost, s));
+            HIPCHK(h, hipStreamSynchronize(s));
+            const double eps = (prec == PREC_FP32) ? std::ldexp(1.0, -24) : std::ldexp(1.0, -40);
+            depth = 8;
+            if (rho > 0.0 && rho < 1.0) depth = (int)std::ceil(std::log(eps) / std::log(rho));
+            if (!(rho > 0.0)) depth = 1;
+            depth = std::max(1, std::min(8, depth));
+        }
         if ((t + 1) % ce == 0 || t + 1 == p.max_sweeps) {
             HIPCHK(h, hipMemcpyAsync(&hs, st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
             HIPCHK(h, hipStreamSynchronize(s));
@@ -358,13 +404,15 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
         }
     }
     HIPCHK(h, hipEventRecord(ev[4], s));
+    const int final_slot = std::max(hs.t, 0) % R;
 
     // ---- outputs
     h->alpha.assign((size_t)N, 0.0);
     h->ptilde.assign((size_t)N, 0.0);
     h->adiag.assign((size_t)N, 0.0);
     h->yh.assign((size_t)N, 0.0f);
-    HIPCHK(h, launch_convert_agg(prec, h->Pt.p, h->tmp.as<double>(), N, s));
+    HIPCHK(h, launch_convert_agg(prec, static_cast<char*>(h->Pt.p) + (size_t)final_slot * NPAD * agg_bytes,
+                                 h->tmp.as<double>(), N, s));
     HIPCHK(h, hipMemcpyAsync(h->alpha.data(), h->alpha_d.p, (size_t)N * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipMemcpyAsync(h->ptilde.data(), h->tmp.p, (size_t)N * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipMemcpyAsync(h->adiag.data(), h->Adiag.p, (size_t)N * 8, hipMemcpyDeviceToHost, s));
@@ -397,16 +445,17 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     h->tm.total_ms = now_ms() - t_start;
     h->plan = gabp_plan{};
     h->plan.precision = prec;
-    h->plan.kstore = GABP_KSTORE_MATERIALISE;
-    h->plan.edge_state = GABP_EDGE_STORED;
+    h->plan.kstore = kmat ? GABP_KSTORE_MATERIALISE : GABP_KSTORE_RECOMPUTE;
+    h->plan.edge_state = stored ? GABP_EDGE_STORED : GABP_EDGE_STATELESS;
     h->plan.gram = (gram == GRAM_BF16X6) ? GABP_GRAM_BF16X6 : (gram == GRAM_BF16X3) ? GABP_GRAM_BF16X3
                  : (gram == GRAM_BF16 ? GABP_GRAM_BF16 : GABP_GRAM_AUTO);
     h->plan.tile = TILE;
-    h->plan.stateless_depth = 0;
+    h->plan.stateless_depth = depth;
+    h->plan.stateless_rho = rho;
     h->plan.n_blocks = NB;
     h->plan.n_tiles = nt;
     h->plan.device_bytes = h->held();
-    h->plan.alg_bytes_per_pair = 9.0 * (double)st_bytes;
+    h->plan.alg_bytes_per_pair = (double)st_bytes * ((stored ? 8.0 : 0.0) + (kmat ? 1.0 : 0.0));
     h->plan.alg_bytes_per_sweep = (uint64_t)((double)N * (double)(N - 1) / 2.0 * h->plan.alg_bytes_per_pair);
     h->have_result = true;
     if (h->status != GABP_OK) {
@@ -554,6 +603,7 @@ gabp_status gabp_svm_kernel_entries(const gabp_svm* hc, const int64_t* rows, con
     gabp_svm* h = const_cast<gabp_svm*>(hc);
     if (!h || !rows || !cols || !out || n < 0) return GABP_E_INVALID;
     if (!h->have_result) return GABP_E_STATE;
+    if (h->plan.kstore != GABP_KSTORE_MATERIALISE) return fail(h, GABP_E_STATE, "K' is not materialised in this plan");
     if (n == 0) return GABP_OK;
     for (int64_t k = 0; k < n; ++k)
         if (rows[k] < 0 || cols[k] < 0 || rows[k] >= h->N || cols[k] >= h->N || rows[k] == cols[k])

@@ -58,7 +58,8 @@ class Plan(ct.Structure):
     _fields_ = [("precision", ct.c_int32), ("kstore", ct.c_int32), ("edge_state", ct.c_int32),
                 ("gram", ct.c_int32), ("tile", ct.c_int32), ("stateless_depth", ct.c_int32),
                 ("n_blocks", ct.c_int64), ("n_tiles", ct.c_int64), ("device_bytes", ct.c_uint64),
-                ("alg_bytes_per_sweep", ct.c_uint64), ("alg_bytes_per_pair", ct.c_double)]
+                ("alg_bytes_per_sweep", ct.c_uint64), ("alg_bytes_per_pair", ct.c_double),
+                ("stateless_rho", ct.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

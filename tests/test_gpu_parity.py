@@ -240,3 +240,62 @@ def test_box_clip_and_sv_mask(torch):
     a = s.alpha()
     assert a.min() >= 0.0 and a.max() <= 0.05
     assert s.sv_count() == int(np.sum(a > 0.0)) and np.array_equal(s.sv_mask(), a > 0.0)
+
+
+# ------------------------------------------- K' recomputed / stateless edges --
+
+def test_recompute_matches_materialised(torch):
+    for prec, n in (("fp32", 900), ("mixed", 700)):
+        wl = inputs.make_workload("covertype", n=n, seed=21)
+        a, _ = run(torch, wl, precision=prec, kstore="materialise", edge_state="stored")
+        b, _ = run(torch, wl, precision=prec, kstore="recompute", edge_state="stored")
+        assert b.plan()["kstore"] == gabp.KSTORE["recompute"]
+        np.testing.assert_allclose(b.adiag(), a.adiag(), rtol=1e-12)
+        err = _rel(b.alpha(), a.alpha())
+        print(f"recompute vs materialise {prec}: rel diff {err:.2e}, sweeps {b.sweeps()} vs {a.sweeps()}")
+        assert err <= 1e-6
+
+
+@pytest.mark.parametrize("depth", [1, 3, 6])
+def test_stateless_matches_oracle_truncated_recursion(torch, depth):
+    wl = inputs.make_workload("tiny", n=600, seed=13)
+    A, b = R.svm_system(wl.X, wl.y, wl.gamma, wl.C, wl.lam)
+    ref = R.gabp_solve_stateless(A, b, depth=depth, sweeps=12)
+    for t in (1, depth, depth + 1, 12):
+        for kstore in ("materialise", "recompute"):
+            s, st = run(torch, wl, precision="fp64" if kstore == "materialise" else "mixed",
+                        edge_state="stateless", kstore=kstore, stateless_depth=depth, max_sweeps=t,
+                        tol_abs=0.0, tol_rel=0.0, stagnation_window=0)
+            assert s.plan()["edge_state"] == gabp.EDGE["stateless"] and s.sweeps() == t
+            err = _rel(s.alpha(), ref[t - 1])
+            assert err <= TOL, (depth, t, kstore, err)
+
+
+def test_stateless_auto_depth_converges_to_solution(torch):
+    wl = inputs.make_workload("covertype", n=2600, seed=5)
+    A, b = R.svm_system(wl.X, wl.y, wl.gamma, wl.C, wl.lam)
+    exact = R.cholesky_solve(A, b)
+    for prec, kstore in (("fp32", "materialise"), ("mixed", "materialise"), ("mixed", "recompute"),
+                         ("fp32", "recompute")):
+        s, st = run(torch, wl, precision=prec, edge_state="stateless", kstore=kstore)
+        plan = s.plan()
+        err = _rel(s.alpha(), exact)
+        print(f"stateless {prec}/{kstore}: depth {plan['stateless_depth']} rho {plan['stateless_rho']:.3e} "
+              f"sweeps {s.sweeps()} reason {s.reason()} rel err {err:.2e}")
+        assert st == gabp.OK and err <= TOL
+
+
+def test_plan_follows_memory_budget(torch):
+    wl = inputs.make_workload("letter", n=1800)
+    s, _ = run(torch, wl, precision="fp32", hbm_budget_bytes=int(42e6))
+    p = s.plan()
+    assert p["kstore"] == gabp.KSTORE["recompute"] or p["edge_state"] == gabp.EDGE["stateless"]
+    assert p["device_bytes"] <= 42e6
+    s2 = gabp.GabpSVM(gamma=wl.gamma, precision="fp32", hbm_budget_bytes=1000)
+    with pytest.raises(gabp.GabpError) as e:
+        s2.solve(wl.X, wl.y)
+    assert e.value.status == gabp.E_NOMEM
+    s3 = gabp.GabpSVM(gamma=wl.gamma, precision="fp64", kstore="recompute")
+    with pytest.raises(gabp.GabpError) as e:
+        s3.solve(wl.X, wl.y)
+    assert e.value.status == gabp.E_INVALID
