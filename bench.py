@@ -24,6 +24,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# VALU issue slots: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (FP32 and FP64 FMA
+# both issue at one lane-op per lane per clock on CDNA4; packed FP32 unused)
+VALU_PEAK_GSLOT = 256 * 64 * 2.4
+
+
+def stateless_slots_per_pair(levels):
+    """Algorithmic VALU issue slots per pair of the stateless sweep: each of
+    `levels` levels forms two cavity precisions and two reciprocals and the
+    four new messages (10 arithmetic ops + 2 reciprocals at 4 slots each);
+    the top level adds the four partial-sum accumulations."""
+    return levels * (10 + 2 * 4) + 4
 
 
 def parse():
@@ -35,11 +46,17 @@ def parse():
     ap.add_argument("--n", type=int, default=None, help="override N (same recipe)")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp32", "fp64"])
     ap.add_argument("--gram", default="auto", choices=["auto", "bf16", "bf16x3", "bf16x6"])
-    ap.add_argument("--kstore", default="materialise", choices=["materialise", "recompute", "auto"])
-    ap.add_argument("--edge", default="stored", choices=["stored", "stateless", "auto"])
+    ap.add_argument("--kstore", default="auto", choices=["materialise", "recompute", "auto"])
+    ap.add_argument("--edge", default="auto", choices=["stored", "stateless", "auto"])
+    ap.add_argument("--no-stored", action="store_true", help="skip the stored-state (HBM-bound) comparison")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=0, help="oracle sample size (0 = auto)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-only", action="store_true", help="run only the serving measurement")
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-load", type=float, default=0.8, help="offered load / measured capacity")
+    ap.add_argument("--serve-precision", default="fp32", choices=["fp32", "mixed", "fp64"])
     ap.add_argument("--calib-copy-gb", type=float, default=0.0,
                     help="also run a plain device copy of this many GB (counter calibration)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "sweep_traffic.json"))
@@ -67,6 +84,71 @@ def solve_steps(torch, gabp, wl, X, y, params, steps, warmup):
                 timings=s.timings(), alpha=s.alpha())
     s.close()
     return wall, sweeps, ktime, klaunch, info
+
+
+def serving_bench(gabp, inputs, n_req, load, precision, seq_sample=24):
+    """Serving stream: N log-uniform in [1k, 16k], m in {8, 32, 128}, C in
+    {0.1, 1, 10}, two-blob data with per-request seed, gamma = 1/m.  First the
+    closed-loop capacity (all requests queued at once), then an open loop
+    with Poisson arrivals at `load` x capacity for the latency percentiles,
+    then sequential single solves of a sample for comparison."""
+    import numpy as np
+    stream = inputs.serving_stream(n_req, rate_per_s=1.0, seed=3)
+    kws = [dict(gamma=r.workload.gamma, C=r.workload.C, precision=precision, tol_rel=r.workload.tol_rel,
+                kstore="materialise", edge_state="stored") for r in stream]
+    sp = dict(arena_bytes=int(120e9), max_active=64, steps_per_poll=2)
+    # closed loop
+    with gabp.GabpServer(**sp) as srv:
+        t0 = time.perf_counter()
+        tickets = [srv.submit(r.workload.X, r.workload.y, **kw) for r, kw in zip(stream, kws)]
+        for t in tickets:
+            srv.wait(t)
+        cap_wall = time.perf_counter() - t0
+        closed = srv.stats()
+        sweeps = [srv.result(t)[1]["sweeps"] for t in tickets]
+    capacity = n_req / cap_wall
+    print(f"[bench] serving closed loop: {n_req} solves in {cap_wall:.2f} s", file=sys.stderr, flush=True)
+    # open loop, Poisson arrivals at load x capacity
+    rate = load * capacity
+    rng = np.random.default_rng(11)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
+    with gabp.GabpServer(**sp) as srv:
+        t0 = time.perf_counter()
+        tickets = []
+        for r, kw, ta in zip(stream, kws, arrivals):
+            dt = ta - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            tickets.append(srv.submit(r.workload.X, r.workload.y, **kw))
+        for t in tickets:
+            srv.wait(t)
+        open_wall = time.perf_counter() - t0
+        opened = srv.stats()
+    print(f"[bench] serving open loop at {rate:.1f}/s: {open_wall:.2f} s", file=sys.stderr, flush=True)
+    # sequential single solves (one handle, one request at a time) on a sample
+    k = min(seq_sample, n_req)
+    t0 = time.perf_counter()
+    for r, kw in zip(stream[:k], kws[:k]):
+        h = gabp.GabpSVM(**kw)
+        h.solve(r.workload.X, r.workload.y)
+        h.close()
+    seq_wall = time.perf_counter() - t0
+    work_all = sum(r.workload.N ** 2 for r in stream)
+    work_k = sum(r.workload.N ** 2 for r in stream[:k])
+    seq_rate = k / seq_wall * (work_k / k) / (work_all / n_req)
+    return {"requests": n_req, "precision": precision,
+            "N_range": [int(min(r.workload.N for r in stream)), int(max(r.workload.N for r in stream))],
+            "capacity_solves_per_s": capacity, "offered_rate_per_s": rate, "load": load,
+            "p50_ms": opened["p50_ms"], "p99_ms": opened["p99_ms"], "mean_ms": opened["mean_ms"],
+            "max_ms": opened["max_ms"], "mean_queue_ms": opened["mean_queue_ms"],
+            "throughput_solves_per_s": opened["throughput_per_s"],
+            "mean_active": opened["mean_active"], "max_active_seen": opened["max_active_seen"],
+            "closed_loop_p50_ms": closed["p50_ms"], "closed_loop_p99_ms": closed["p99_ms"],
+            "mean_sweeps": float(np.mean(sweeps)), "failed": opened["failed"] + closed["failed"],
+            "sequential_solves_per_s_est": seq_rate,
+            "sequential_sample": f"first {k} requests solved one at a time on one handle, rate scaled by "
+                                 f"the stream's mean N^2 over the sample's",
+            "batching_speedup": capacity / seq_rate if seq_rate > 0 else None}
 
 
 def cpu_baseline(wl, n_full, sample_n):
@@ -99,6 +181,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if a.serve_only:
+        res = serving_bench(gabp, inputs, a.serve_requests, a.serve_load, a.serve_precision)
+        print(json.dumps({"metric": "served GaBP solves: p50/p99 latency", "value": res["throughput_solves_per_s"],
+                          "unit": "solves/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+                          "serving": res}), flush=True)
+        return
     wl = inputs.make_workload(a.workload, n=a.n)
     N, m = wl.N, wl.m
     X = torch.from_numpy(wl.X).to(dev)
@@ -110,7 +198,8 @@ def main():
                 tol_rel=wl.tol_rel, kstore=a.kstore, edge_state=a.edge, time_sweeps=1)
     params = dict(base, precision=a.precision, gram=a.gram)
     wall, sweeps, ktime, klaunch, info = solve_steps(torch, gabp, wl, X, y, params, a.steps, a.warmup)
-    print(f"[bench] main: {sweeps} sweeps in {wall:.3f} s, reason {info['reason']}", file=sys.stderr, flush=True)
+    print(f"[bench] main: {sweeps} sweeps in {wall:.3f} s, reason {info['reason']}, plan {info['plan']}",
+          file=sys.stderr, flush=True)
 
     plain = None
     if not a.no_plain and a.precision != "fp32":
@@ -119,6 +208,8 @@ def main():
         diff = float(np.max(np.abs(pinfo["alpha"] - info["alpha"])) / np.max(np.abs(info["alpha"])))
         plain = {"sweeps_per_s": ps / pw, "solves_per_s": a.steps / pw, "sweeps_per_solve": pinfo["sweeps_per_solve"],
                  "reason": pinfo["reason"], "sweep_kernel_ms_avg": pk / max(pl, 1),
+                 "edge_state": {1: "stored", 2: "stateless"}.get(pinfo["plan"]["edge_state"]),
+                 "stateless_depth": pinfo["plan"]["stateless_depth"],
                  "rel_diff_alpha_vs_main": diff}
         print(f"[bench] plain fp32: {ps} sweeps in {pw:.3f} s", file=sys.stderr, flush=True)
 
@@ -133,20 +224,55 @@ def main():
 
     plan = info["plan"]
     avg_ms = ktime / max(klaunch, 1)
-    achieved = plan["alg_bytes_per_sweep"] / (avg_ms * 1e-3) / 1e9 if klaunch else None
+    pairs = N * (N - 1) / 2.0
+    stateless = plan["edge_state"] == gabp.EDGE["stateless"]
     traffic = None
     if os.path.exists(a.traffic_json):
         try:
             tj = json.load(open(a.traffic_json))
-            key = f"{wl.name}:{N}:{a.precision}:{a.kstore}:{a.edge}"
+            key = f"{wl.name}:{N}:{a.precision}:{plan['kstore']}:{plan['edge_state']}"
             traffic = tj.get(key)
         except Exception:
             traffic = None
-    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
-            "kernel": "k_sweep_stored", "avg_launch_ms": avg_ms, "launches": klaunch,
-            "alg_bytes_per_launch": plan["alg_bytes_per_sweep"],
-            "alg_bytes_per_pair": plan["alg_bytes_per_pair"]}
+    if stateless:
+        slots = stateless_slots_per_pair(plan["stateless_depth"])
+        achieved = slots * pairs / (avg_ms * 1e-3) / 1e9 if klaunch else None
+        roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_GSLOT, "unit": "Gslot/s",
+                "frac": (achieved / VALU_PEAK_GSLOT) if achieved else None, "traffic": traffic,
+                "kernel": "k_sweep (stateless)", "avg_launch_ms": avg_ms, "launches": klaunch,
+                "alg_slots_per_pair": slots, "stateless_depth": plan["stateless_depth"],
+                "stateless_rho": plan["stateless_rho"],
+                "hbm_alg_bytes_per_launch": plan["alg_bytes_per_sweep"],
+                "hbm_frac": plan["alg_bytes_per_sweep"] / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if klaunch else None}
+    else:
+        achieved = plan["alg_bytes_per_sweep"] / (avg_ms * 1e-3) / 1e9 if klaunch else None
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+                "kernel": "k_sweep (stored)", "avg_launch_ms": avg_ms, "launches": klaunch,
+                "alg_bytes_per_launch": plan["alg_bytes_per_sweep"],
+                "alg_bytes_per_pair": plan["alg_bytes_per_pair"]}
+
+    stored_cmp = None
+    if stateless and not a.no_stored:
+        sw_, ss_, sk_, sl_, sinfo = solve_steps(torch, gabp, wl, X, y, dict(params, edge_state="stored"),
+                                                 a.steps, a.warmup)
+        sp = sinfo["plan"]
+        s_ms = sk_ / max(sl_, 1)
+        s_ach = sp["alg_bytes_per_sweep"] / (s_ms * 1e-3) / 1e9
+        stored_cmp = {"sweeps_per_s": ss_ / sw_, "solves_per_s": a.steps / sw_,
+                      "sweeps_per_solve": sinfo["sweeps_per_solve"], "reason": sinfo["reason"],
+                      "rel_diff_alpha_vs_main": float(np.max(np.abs(sinfo["alpha"] - info["alpha"])) /
+                                                      np.max(np.abs(info["alpha"]))),
+                      "roofline": {"bound": "hbm", "achieved": s_ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                   "frac": s_ach / HBM_PEAK_GBS, "kernel": "k_sweep (stored)",
+                                   "avg_launch_ms": s_ms, "launches": sl_,
+                                   "alg_bytes_per_launch": sp["alg_bytes_per_sweep"],
+                                   "alg_bytes_per_pair": sp["alg_bytes_per_pair"]}}
+        print(f"[bench] stored state: {ss_} sweeps in {sw_:.3f} s", file=sys.stderr, flush=True)
+
+    serving = None
+    if not a.no_serve:
+        serving = serving_bench(gabp, inputs, a.serve_requests, a.serve_load, a.serve_precision)
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -154,7 +280,7 @@ def main():
         cpu = cpu_baseline(wl, N, sn)
 
     line = {
-        "metric": "GaBP sweeps/s (+ solves/s) at N=100k RBF, mixed vs plain FP32",
+        "metric": "GaBP sweeps/s + solves/s at N=100k RBF vs plain FP32; p50/p99 solve latency",
         "value": sweeps / wall,
         "unit": "sweeps/s",
         "n_gpus": 1,
@@ -169,12 +295,16 @@ def main():
         "config": {"workload": f"{wl.name}-like N={N} m={m} RBF gamma={wl.gamma:g} C={wl.C:g} "
                                f"delta={wl.delta:g} tol_rel={wl.tol_rel:g}",
                    "N": N, "m": m, "precision": a.precision, "gram": a.gram if a.precision == "mixed" else None,
-                   "kstore": plan["kstore"], "edge_state": plan["edge_state"], "tile": plan["tile"]},
+                   "kstore": {1: "materialise", 2: "recompute"}.get(plan["kstore"], plan["kstore"]),
+                   "edge_state": {1: "stored", 2: "stateless"}.get(plan["edge_state"], plan["edge_state"]),
+                   "stateless_depth": plan["stateless_depth"] if stateless else None, "tile": plan["tile"]},
         "solves_per_s": a.steps / wall,
         "sweeps_per_solve": info["sweeps_per_solve"],
         "stop_reason": info["reason"],
         "phase_ms": {k: info["timings"][k] for k in ("stage_ms", "kbuild_ms", "diag_ms", "sweep_loop_ms", "d2h_ms")},
         "plain_fp32": plain,
+        "stored_state": stored_cmp,
+        "serving": serving,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -261,6 +261,97 @@ const char *gabp_svm_last_error(const gabp_svm *h);
 /* GABP_ABI_VERSION of the library. */
 int32_t gabp_abi_version(void);
 
+
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of many solves on one device.
+ *
+ * Not part of the paper (which solves one problem at a time); this is the
+ * served form of the same sweep.  A background thread admits queued
+ * requests in FIFO order (with a bounded bypass for smaller requests) when
+ * their device footprint fits the server's memory arena and a slot is free,
+ * keeps their K' tiles and pair-record messages resident, and advances all
+ * active requests together: each step is one persistent sweep launch over
+ * the union of their tiles, one batched finalize and one batched stop rule.
+ * Requests join and leave at step boundaries.  Each request has its own
+ * partial sums and fixed reduction order, so its alpha is bitwise the same
+ * whether it runs alone or in a mix.  Served plans are materialised K' with
+ * stored edge state (kstore / edge_state AUTO or those values).
+ * ------------------------------------------------------------------------ */
+typedef struct gabp_server gabp_server;
+
+typedef struct gabp_server_params {
+    uint32_t struct_size;      /* sizeof(gabp_server_params) */
+    int32_t device;            /* HIP device ordinal */
+    uint64_t arena_bytes;      /* device memory arena for all requests;
+                                  0 = 80% of the free device memory */
+    int32_t max_active;        /* slots: requests resident at once (<= 1024) */
+    int32_t steps_per_poll;    /* sweeps launched between status read-backs */
+    int32_t max_bypass;        /* smaller requests admitted ahead of a queue
+                                  head that does not fit, before the head
+                                  blocks admission */
+    int32_t reserved;
+} gabp_server_params;
+
+/* Outcome of one request (gabp_server_result). */
+typedef struct gabp_request_info {
+    int32_t status;            /* gabp_status of the solve */
+    int32_t reason;            /* gabp_reason */
+    int32_t sweeps;
+    int32_t reserved;
+    int64_t N;
+    double latency_ms;         /* completion - submission (host clock) */
+    double queue_ms;           /* admission - submission */
+    double device_bytes;       /* footprint held while active */
+} gabp_request_info;
+
+/* Aggregate statistics over the requests completed so far. */
+typedef struct gabp_server_stats {
+    int64_t submitted, completed, failed;
+    double p50_ms, p99_ms, mean_ms, max_ms;   /* latency percentiles */
+    double mean_queue_ms;
+    double throughput_per_s;   /* completed / (last completion - first submission) */
+    double mean_active;        /* active requests per step, averaged over steps */
+    int64_t max_active_seen;
+    int64_t steps;             /* batched steps launched */
+} gabp_server_stats;
+
+/* Fills *p with defaults: device 0, arena 0 (80% of free memory),
+ * max_active 64, steps_per_poll 2, max_bypass 8. */
+void gabp_server_params_default(gabp_server_params *p);
+
+/* Creates a server, allocates its arena and starts its scheduler thread.
+ * GABP_E_INVALID for bad parameters, GABP_E_DEVICE without a gfx950
+ * device, GABP_E_NOMEM if the arena cannot be allocated. */
+gabp_status gabp_server_create(const gabp_server_params *params, gabp_server **out);
+
+/* Queues one solve: X (N x m float32, row-major, host), y (N float32, +-1,
+ * host) and the solver parameters (RBF kernel).  Inputs are copied before
+ * the call returns.  *ticket identifies the request.  GABP_E_INVALID for bad
+ * inputs or parameters, GABP_E_NOMEM if the request can never fit the
+ * arena. */
+gabp_status gabp_server_submit(gabp_server *srv, const float *X, const float *y, int64_t N,
+                               int64_t m, const gabp_svm_params *params, uint64_t *ticket);
+
+/* *done = 1 once the request finished (successfully or not). */
+gabp_status gabp_server_poll(gabp_server *srv, uint64_t ticket, int32_t *done);
+
+/* Blocks until the request finished or timeout_s elapsed (< 0: no limit);
+ * GABP_E_STATE on time-out. */
+gabp_status gabp_server_wait(gabp_server *srv, uint64_t ticket, double timeout_s);
+
+/* Copies the finished request's alpha (N float64, box handling applied) to
+ * alpha (host, `bytes` long; NULL skips it) and its outcome to *info (NULL
+ * skips it).  GABP_E_STATE if not finished, GABP_E_BUFSIZE if too small. */
+gabp_status gabp_server_result(gabp_server *srv, uint64_t ticket, double *alpha, size_t bytes,
+                               gabp_request_info *info);
+
+/* Latency / throughput statistics of the completed requests. */
+gabp_status gabp_server_stats_get(gabp_server *srv, gabp_server_stats *out);
+
+/* Stops the scheduler (active and queued requests are abandoned) and frees
+ * everything.  NULL is ignored. */
+void gabp_server_destroy(gabp_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,6 +5,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
+#include "../../include/gabp_svm.h"
+
 namespace gabp {
 
 // Pairs {i, j}, i < j, are processed in TILE x TILE tiles of the upper
@@ -59,6 +63,9 @@ struct KernelParams {
     double lam2;             // lambda^2 added to every RBF entry
 };
 
+// Validates a parameter struct (shared by the solver and the server).
+gabp_status check_params(const gabp_svm_params* p, std::string& why);
+
 inline int64_t n_tiles(int NB) { return (int64_t)NB * (NB + 1) / 2; }
 // Storage index of tile (I, J), I <= J: row-major over the upper triangle.
 __host__ __device__ inline int64_t tile_index(int I, int J, int NB) {
@@ -105,6 +112,28 @@ struct SweepArgs {
     Features F;                   // KSRC_RECOMPUTE
     KernelParams kp;
 };
+// Per-request state of the served form: sweep arguments plus what the
+// finalize and stop-rule steps need.  Aggregates live in sw.HP / sw.HS
+// (ring depth 1: stored edge state, materialised K').
+struct ReqDesc {
+    SweepArgs sw;
+    int64_t N;
+    const double* Adiag;
+    const float* y;
+    double* alpha;
+    double* blk_delta;
+    double* blk_amax;
+    double* trace;
+    StopRule rule;
+    int nblk;
+};
+// One served step for the requests of one precision: batched sweep over the
+// (request, tile) items, batched finalize over the (request, node block)
+// items, batched stop rule for the request slots listed in `slots`, whose
+// statuses are copied to status_out[0..nslots).
+hipError_t launch_served_step(int prec, const ReqDesc* reqs, const uint2* tile_items, int ntile_items,
+                              const uint2* node_items, int nnode_items, const int* slots, int nslots,
+                              DevStatus* status_out, hipStream_t s);
 // depth 0 = stored edge state, 1..8 = stateless with up to `depth` levels.
 hipError_t launch_sweep(int prec, int ksrc, int gram, int depth, bool first, const SweepArgs& a,
                         hipStream_t s);

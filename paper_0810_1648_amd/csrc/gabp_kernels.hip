@@ -555,15 +555,15 @@ __global__ void k_init(int64_t N, int64_t NPAD, int R, const double* __restrict_
 //      deeper levels in LT = float (FP32/MIXED) or double (FP64);
 //   FIRST: the stored planes are all zero (sweep 1) and are not read.
 template <class ST, class MT, class AT, int KSRC, int GK, int D, bool FIRST>
-__global__ __launch_bounds__(WG) void k_sweep(SweepArgs a) {
+__device__ inline void sweep_tile(const SweepArgs& a, int64_t tile) {
     DevStatus* st = a.st;
-    if (st->done) return;
     using LT = typename std::conditional<std::is_same<ST, double>::value, double, float>::type;
     constexpr bool STORED = (D == 0);
     constexpr int DL = (D > 1) ? D - 1 : 1;   // lower levels held per node
-    const TileCoord tc = tile_of(a.tiles);
+    const uint32_t ij = a.tiles[tile];
+    const TileCoord tc{(int)(ij >> 16), (int)(ij & 0xFFFFu)};
     const int NB = a.NB;
-    const size_t tbase = (size_t)blockIdx.x * TT;
+    const size_t tbase = (size_t)tile * TT;
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, q = l & 15;
     const int col0 = w * 64 + q * 4;
     const int L = a.levels;
@@ -700,19 +700,39 @@ __global__ __launch_bounds__(WG) void k_sweep(SweepArgs a) {
     if (__any(bad) && l == 0) st->bad = 1;
 }
 
+template <class ST, class MT, class AT, int KSRC, int GK, int D, bool FIRST>
+__global__ __launch_bounds__(WG) void k_sweep(SweepArgs a) {
+    if (a.st->done) return;
+    sweep_tile<ST, MT, AT, KSRC, GK, D, FIRST>(a, blockIdx.x);
+}
+
+// Served form: one persistent grid walks the union work list of (request,
+// tile) items of every active request; each request keeps its own planes,
+// partial sums and status, so its arithmetic does not depend on the mix.
+template <class ST, class MT, class AT>
+__global__ __launch_bounds__(WG) void k_sweep_batched(const ReqDesc* __restrict__ reqs,
+                                                     const uint2* __restrict__ items, int nitems) {
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const uint2 w = items[it];
+        const ReqDesc& rd = reqs[w.x];
+        if (rd.sw.st->done) continue;
+        sweep_tile<ST, MT, AT, KSRC_PLANE, GRAM_F32, 0, false>(rd.sw, (int64_t)w.y);
+        __syncthreads();
+    }
+}
+
 // Aggregates of the new sweep from the partial sums (fixed order) into ring
 // slot `wslot`, the new alpha and the per-block change / magnitude maxima.
 template <class AT>
-__global__ __launch_bounds__(WG) void k_finalize(int64_t N, int NB, const AT* __restrict__ partP,
-                                                const AT* __restrict__ partE,
-                                                const double* __restrict__ Adiag,
-                                                const float* __restrict__ y, AT* __restrict__ Pt,
-                                                AT* __restrict__ S, double* __restrict__ alpha,
-                                                double* __restrict__ blk_delta,
-                                                double* __restrict__ blk_amax, DevStatus* st) {
-    if (st->done) return;
+__device__ inline void finalize_block(int64_t blk, int64_t N, int NB, const AT* __restrict__ partP,
+                                      const AT* __restrict__ partE,
+                                      const double* __restrict__ Adiag,
+                                      const float* __restrict__ y, AT* __restrict__ Pt,
+                                      AT* __restrict__ S, double* __restrict__ alpha,
+                                      double* __restrict__ blk_delta,
+                                      double* __restrict__ blk_amax, DevStatus* st) {
     __shared__ double sh4[4];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = blk * blockDim.x + threadIdx.x;
     double d = 0.0, am = 0.0;
     bool bad = false;
     if (i < N) {
@@ -734,14 +754,42 @@ __global__ __launch_bounds__(WG) void k_finalize(int64_t N, int NB, const AT* __
     if (__any(bad) && (threadIdx.x & 63) == 0) st->bad = 1;
     d = block_max(d, sh4);
     am = block_max(am, sh4);
-    if (threadIdx.x == 0) { blk_delta[blockIdx.x] = d; blk_amax[blockIdx.x] = am; }
+    if (threadIdx.x == 0) { blk_delta[blk] = d; blk_amax[blk] = am; }
+}
+
+template <class AT>
+__global__ __launch_bounds__(WG) void k_finalize(int64_t N, int NB, const AT* __restrict__ partP,
+                                                const AT* __restrict__ partE,
+                                                const double* __restrict__ Adiag,
+                                                const float* __restrict__ y, AT* __restrict__ Pt,
+                                                AT* __restrict__ S, double* __restrict__ alpha,
+                                                double* __restrict__ blk_delta,
+                                                double* __restrict__ blk_amax, DevStatus* st) {
+    if (st->done) return;
+    finalize_block<AT>(blockIdx.x, N, NB, partP, partE, Adiag, y, Pt, S, alpha, blk_delta, blk_amax, st);
+}
+
+// Served form: items are (request, block of 256 nodes).
+template <class AT>
+__global__ __launch_bounds__(WG) void k_finalize_batched(const ReqDesc* __restrict__ reqs,
+                                                        const uint2* __restrict__ items, int nitems) {
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const uint2 w = items[it];
+        const ReqDesc& rd = reqs[w.x];
+        if (rd.sw.st->done) continue;
+        finalize_block<AT>((int64_t)w.y, rd.N, rd.sw.NB, static_cast<const AT*>(rd.sw.partP),
+                           static_cast<const AT*>(rd.sw.partE), rd.Adiag, rd.y,
+                           static_cast<AT*>(const_cast<void*>(rd.sw.HP)),
+                           static_cast<AT*>(const_cast<void*>(rd.sw.HS)), rd.alpha, rd.blk_delta,
+                           rd.blk_amax, rd.sw.st);
+        __syncthreads();
+    }
 }
 
 // Stop rule (Algorithm 2 step "Check", tested on alpha).
-__global__ __launch_bounds__(WG) void k_status(int nblk, const double* __restrict__ bd,
-                                              const double* __restrict__ ba, DevStatus* st,
-                                              double* __restrict__ trace, StopRule rule) {
-    if (st->done) return;
+__device__ inline void status_update(int nblk, const double* __restrict__ bd,
+                                     const double* __restrict__ ba, DevStatus* st,
+                                     double* __restrict__ trace, const StopRule& rule) {
     __shared__ double sh4[4];
     double d = 0.0, a = 0.0;
     for (int k = threadIdx.x; k < nblk; k += blockDim.x) { d = fmax(d, bd[k]); a = fmax(a, ba[k]); }
@@ -767,6 +815,27 @@ __global__ __launch_bounds__(WG) void k_status(int nblk, const double* __restric
             }
         }
     }
+}
+
+__global__ __launch_bounds__(WG) void k_status(int nblk, const double* __restrict__ bd,
+                                              const double* __restrict__ ba, DevStatus* st,
+                                              double* __restrict__ trace, StopRule rule) {
+    if (st->done) return;
+    status_update(nblk, bd, ba, st, trace, rule);
+}
+
+// Served form: one workgroup per active request; also copies the request's
+// status into a packed array the host reads back in one transfer.
+__global__ __launch_bounds__(WG) void k_status_batched(const ReqDesc* __restrict__ reqs,
+                                                      const int* __restrict__ slots, int n,
+                                                      DevStatus* __restrict__ out) {
+    const int k = blockIdx.x;
+    if (k >= n) return;
+    const ReqDesc& rd = reqs[slots[k]];
+    DevStatus* st = rd.sw.st;
+    if (!st->done) status_update(rd.nblk, rd.blk_delta, rd.blk_amax, st, rd.trace, rd.rule);
+    __syncthreads();
+    if (threadIdx.x == 0) out[k] = *st;
 }
 
 // Contraction estimate of the message recursion, max_i rowmax_i / P~_i,
@@ -990,6 +1059,30 @@ hipError_t launch_sweep(int prec, int ksrc, int gram, int depth, bool first, con
         }
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_served_step(int prec, const ReqDesc* reqs, const uint2* tile_items, int ntile_items,
+                              const uint2* node_items, int nnode_items, const int* slots, int nslots,
+                              DevStatus* status_out, hipStream_t s) {
+    const int gs = std::max(1, std::min(ntile_items, 2048));
+    const int gf = std::max(1, std::min(nnode_items, 2048));
+    switch (prec) {
+        case PREC_FP32:
+            hipLaunchKernelGGL((k_sweep_batched<float, float, float>), dim3(gs), dim3(WG), 0, s, reqs, tile_items, ntile_items);
+            hipLaunchKernelGGL(k_finalize_batched<float>, dim3(gf), dim3(WG), 0, s, reqs, node_items, nnode_items);
+            break;
+        case PREC_MIXED:
+            hipLaunchKernelGGL((k_sweep_batched<float, double, double>), dim3(gs), dim3(WG), 0, s, reqs, tile_items, ntile_items);
+            hipLaunchKernelGGL(k_finalize_batched<double>, dim3(gf), dim3(WG), 0, s, reqs, node_items, nnode_items);
+            break;
+        case PREC_FP64:
+            hipLaunchKernelGGL((k_sweep_batched<double, double, double>), dim3(gs), dim3(WG), 0, s, reqs, tile_items, ntile_items);
+            hipLaunchKernelGGL(k_finalize_batched<double>, dim3(gf), dim3(WG), 0, s, reqs, node_items, nnode_items);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(k_status_batched, dim3(std::max(1, nslots)), dim3(WG), 0, s, reqs, slots, nslots, status_out);
+    return hipGetLastError();
 }
 
 hipError_t launch_finalize(int prec, int64_t N, int NB, const void* partP, const void* partE,

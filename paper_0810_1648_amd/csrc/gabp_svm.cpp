@@ -54,6 +54,29 @@ double now_ms() {
 
 }  // namespace
 
+namespace gabp {
+gabp_status check_params(const gabp_svm_params* p, std::string& why) {
+    if (!p) { why = "params is NULL"; return GABP_E_INVALID; }
+    if (p->struct_size != sizeof(gabp_svm_params)) { why = "params.struct_size mismatch"; return GABP_E_INVALID; }
+    if (p->kernel != GABP_KERNEL_RBF && p->kernel != GABP_KERNEL_PRECOMPUTED) { why = "unknown kernel"; return GABP_E_INVALID; }
+    if (p->kernel == GABP_KERNEL_RBF && !(p->gamma > 0.0 && std::isfinite(p->gamma))) { why = "gamma must be > 0"; return GABP_E_INVALID; }
+    if (!(p->C > 0.0) || !std::isfinite(p->C)) { why = "C must be > 0"; return GABP_E_INVALID; }
+    if (p->diag_mode < 0 || p->diag_mode > 3) { why = "unknown diag_mode"; return GABP_E_INVALID; }
+    if (!(p->diag_delta >= 0.0)) { why = "diag_delta must be >= 0"; return GABP_E_INVALID; }
+    if (p->box_mode < 0 || p->box_mode > 1) { why = "unknown box_mode"; return GABP_E_INVALID; }
+    if (!(p->tol_abs >= 0.0) || !(p->tol_rel >= 0.0)) { why = "tolerances must be >= 0"; return GABP_E_INVALID; }
+    if (p->max_sweeps < 1) { why = "max_sweeps must be >= 1"; return GABP_E_INVALID; }
+    if (p->check_every < 1) { why = "check_every must be >= 1"; return GABP_E_INVALID; }
+    if (p->stagnation_window < 0) { why = "stagnation_window must be >= 0"; return GABP_E_INVALID; }
+    if (p->precision < 0 || p->precision > 2) { why = "unknown precision"; return GABP_E_INVALID; }
+    if (p->kstore < 0 || p->kstore > 2) { why = "unknown kstore"; return GABP_E_INVALID; }
+    if (p->edge_state < 0 || p->edge_state > 2) { why = "unknown edge_state"; return GABP_E_INVALID; }
+    if (p->gram < 0 || p->gram > 3) { why = "unknown gram"; return GABP_E_INVALID; }
+    if (p->stateless_depth < 0 || p->stateless_depth > 16) { why = "stateless_depth must be in [0, 16]"; return GABP_E_INVALID; }
+    return GABP_OK;
+}
+}  // namespace gabp
+
 struct gabp_svm {
     gabp_svm_params p{};
     std::string err;
@@ -102,27 +125,6 @@ gabp_status fail(gabp_svm* h, gabp_status st, const std::string& msg) {
             return fail((h), GABP_E_DEVICE,                                               \
                         std::string(#expr ": ") + hipGetErrorString(e_));                 \
     } while (0)
-
-gabp_status check_params(const gabp_svm_params* p, std::string& why) {
-    if (!p) { why = "params is NULL"; return GABP_E_INVALID; }
-    if (p->struct_size != sizeof(gabp_svm_params)) { why = "params.struct_size mismatch"; return GABP_E_INVALID; }
-    if (p->kernel != GABP_KERNEL_RBF && p->kernel != GABP_KERNEL_PRECOMPUTED) { why = "unknown kernel"; return GABP_E_INVALID; }
-    if (p->kernel == GABP_KERNEL_RBF && !(p->gamma > 0.0 && std::isfinite(p->gamma))) { why = "gamma must be > 0"; return GABP_E_INVALID; }
-    if (!(p->C > 0.0) || !std::isfinite(p->C)) { why = "C must be > 0"; return GABP_E_INVALID; }
-    if (p->diag_mode < 0 || p->diag_mode > 3) { why = "unknown diag_mode"; return GABP_E_INVALID; }
-    if (!(p->diag_delta >= 0.0)) { why = "diag_delta must be >= 0"; return GABP_E_INVALID; }
-    if (p->box_mode < 0 || p->box_mode > 1) { why = "unknown box_mode"; return GABP_E_INVALID; }
-    if (!(p->tol_abs >= 0.0) || !(p->tol_rel >= 0.0)) { why = "tolerances must be >= 0"; return GABP_E_INVALID; }
-    if (p->max_sweeps < 1) { why = "max_sweeps must be >= 1"; return GABP_E_INVALID; }
-    if (p->check_every < 1) { why = "check_every must be >= 1"; return GABP_E_INVALID; }
-    if (p->stagnation_window < 0) { why = "stagnation_window must be >= 0"; return GABP_E_INVALID; }
-    if (p->precision < 0 || p->precision > 2) { why = "unknown precision"; return GABP_E_INVALID; }
-    if (p->kstore < 0 || p->kstore > 2) { why = "unknown kstore"; return GABP_E_INVALID; }
-    if (p->edge_state < 0 || p->edge_state > 2) { why = "unknown edge_state"; return GABP_E_INVALID; }
-    if (p->gram < 0 || p->gram > 3) { why = "unknown gram"; return GABP_E_INVALID; }
-    if (p->stateless_depth < 0 || p->stateless_depth > 16) { why = "stateless_depth must be in [0, 16]"; return GABP_E_INVALID; }
-    return GABP_OK;
-}
 
 struct EventPool {
     std::vector<hipEvent_t> ev;
@@ -230,14 +232,20 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
         return fail(h, GABP_E_NOMEM, msg);
     }
     if (need > free_b) h->release_all();
-    const int R = stored ? 1 : 8;
+    // AUTO edge state with room for stored planes: sweep 1 runs in stateless
+    // form to measure the contraction; the solve stays stateless when the
+    // truncation at depth <= 8 is below the path's own rounding, and
+    // restarts with stored pair records otherwise.
+    const bool probe = stored && p.edge_state == GABP_EDGE_AUTO;
+    const int R = (stored && !probe) ? 1 : 8;
     const int ksrc = kmat ? KSRC_PLANE : KSRC_RECOMPUTE;
 
     hipError_t ae = hipSuccess;
     auto A = [&](DevBuf& b, size_t n) { if (ae == hipSuccess) ae = b.ensure(n); };
     A(h->tiles, (size_t)nt * 4);
     if (kmat) A(h->Kp, plane); else h->Kp.release();
-    if (stored) { A(h->Pf, plane); A(h->Pb, plane); A(h->Ef, plane); A(h->Eb, plane); }
+    // pair-record planes: allocated now for a stored plan, on demand after the probe
+    if (stored && !probe) { A(h->Pf, plane); A(h->Pb, plane); A(h->Ef, plane); A(h->Eb, plane); }
     else { h->Pf.release(); h->Pb.release(); h->Ef.release(); h->Eb.release(); }
     A(h->partP, part); A(h->partE, part);
     A(h->yd, (size_t)N * 4);
@@ -348,63 +356,94 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     sa.Pf = h->Pf.p; sa.Pb = h->Pb.p; sa.Ef = h->Ef.p; sa.Eb = h->Eb.p;
     sa.HP = h->Pt.p; sa.HS = h->S.p;
     sa.NPAD = NPAD;
-    sa.R = R;
     sa.partP = h->partP.p; sa.partE = h->partE.p;
     sa.st = st;
     sa.F = F;
     sa.kp = kp;
     StopRule rule{p.tol_abs, p.tol_rel, p.stagnation_rel, p.max_sweeps, p.stagnation_window};
     const int nblk = (int)((N + WG - 1) / WG);
-    // stateless depth: requested, or chosen after sweep 1 from the contraction
-    // estimate rho = max_i max_j |K'_ij| / P~_i so that rho^depth <= eps
-    int depth = stored ? 0 : (p.stateless_depth > 0 ? p.stateless_depth : 2);
-    const bool auto_depth = !stored && p.stateless_depth == 0;
+    // Stateless depth: requested, or chosen after sweep 1 from the
+    // contraction estimate rho = max_i max_j |K'_ij| / P~_i (with a 1.25
+    // margin) so that rho^depth is below the path's message precision:
+    // 2^-24 (FP32), 2^-30 (MIXED, FP32-stored messages), 2^-50 (FP64).
+    const double eps = (prec == PREC_FP32) ? std::ldexp(1.0, -24)
+                     : (prec == PREC_MIXED) ? std::ldexp(1.0, -30) : std::ldexp(1.0, -50);
+    bool cur_stored = stored && !probe;
+    int depth = cur_stored ? 0 : (p.stateless_depth > 0 ? p.stateless_depth : 1);
+    bool choose_depth = !cur_stored && p.stateless_depth == 0;
     double rho = 0.0;
     DevStatus hs{};
     double sweep_kernel_ms = 0.0;
     int64_t launches = 0;
-    int polled = 0;
-    for (int t = 0; t < p.max_sweeps; ++t) {
-        const int slot = t % ce;
-        sa.slot_top = t % R;
-        sa.levels = stored ? 0 : std::min(t + 1, depth);
-        if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot], s));
-        HIPCHK(h, launch_sweep(prec, ksrc, gram, depth, t == 0, sa, s));
-        if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot + 1], s));
-        char* wP = static_cast<char*>(h->Pt.p) + (size_t)((t + 1) % R) * NPAD * agg_bytes;
-        char* wS = static_cast<char*>(h->S.p) + (size_t)((t + 1) % R) * NPAD * agg_bytes;
-        HIPCHK(h, launch_finalize(prec, N, NB, h->partP.p, h->partE.p, h->Adiag.as<double>(),
-                                  h->yd.as<float>(), wP, wS, h->alpha_d.as<double>(),
-                                  h->blk1.as<double>(), h->blk2.as<double>(), st, s));
-        HIPCHK(h, launch_status(nblk, h->blk1.as<double>(), h->blk2.as<double>(), st,
-                                h->trace_d.as<double>(), rule, s));
-        if (auto_depth && t == 0) {
-            HIPCHK(h, launch_rho(prec, N, h->rowmax.as<double>(), wP, h->blk1.as<double>(),
-                                 h->one.as<double>(), s));
-            HIPCHK(h, hipMemcpyAsync(&rho, h->one.p, 8, hipMemcpyDeviceToHost, s));
-            HIPCHK(h, hipStreamSynchronize(s));
-            const double eps = (prec == PREC_FP32) ? std::ldexp(1.0, -24) : std::ldexp(1.0, -40);
-            depth = 8;
-            if (rho > 0.0 && rho < 1.0) depth = (int)std::ceil(std::log(eps) / std::log(rho));
-            if (!(rho > 0.0)) depth = 1;
-            depth = std::max(1, std::min(8, depth));
-        }
-        if ((t + 1) % ce == 0 || t + 1 == p.max_sweeps) {
-            HIPCHK(h, hipMemcpyAsync(&hs, st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
-            HIPCHK(h, hipStreamSynchronize(s));
-            if (p.time_sweeps) {
-                for (int u = polled; u <= t; ++u) {
-                    if (u >= hs.t) break;
-                    sweep_kernel_ms += elapsed(sev[2 * (u % ce)], sev[2 * (u % ce) + 1]);
-                    ++launches;
+    for (int pass = 0; pass < 2; ++pass) {
+        bool restart = false;
+        int polled = 0;
+        const int Rr = cur_stored ? 1 : R;
+        sweep_kernel_ms = 0.0;
+        launches = 0;
+        for (int t = 0; t < p.max_sweeps; ++t) {
+            const int slot = t % ce;
+            sa.R = Rr;
+            sa.slot_top = t % Rr;
+            sa.levels = cur_stored ? 0 : std::min(t + 1, depth);
+            if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot], s));
+            HIPCHK(h, launch_sweep(prec, ksrc, gram, cur_stored ? 0 : depth, t == 0, sa, s));
+            if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot + 1], s));
+            char* wP = static_cast<char*>(h->Pt.p) + (size_t)((t + 1) % Rr) * NPAD * agg_bytes;
+            char* wS = static_cast<char*>(h->S.p) + (size_t)((t + 1) % Rr) * NPAD * agg_bytes;
+            HIPCHK(h, launch_finalize(prec, N, NB, h->partP.p, h->partE.p, h->Adiag.as<double>(),
+                                      h->yd.as<float>(), wP, wS, h->alpha_d.as<double>(),
+                                      h->blk1.as<double>(), h->blk2.as<double>(), st, s));
+            HIPCHK(h, launch_status(nblk, h->blk1.as<double>(), h->blk2.as<double>(), st,
+                                    h->trace_d.as<double>(), rule, s));
+            if (choose_depth && t == 0) {
+                HIPCHK(h, launch_rho(prec, N, h->rowmax.as<double>(), wP, h->blk1.as<double>(),
+                                     h->one.as<double>(), s));
+                HIPCHK(h, hipMemcpyAsync(&rho, h->one.p, 8, hipMemcpyDeviceToHost, s));
+                HIPCHK(h, hipStreamSynchronize(s));
+                const double r = 1.25 * rho;
+                int d = 9;
+                if (!(r > 0.0)) d = 1;
+                else if (r < 1.0) d = std::max(1, (int)std::ceil(std::log(eps) / std::log(r)));
+                choose_depth = false;
+                if (d <= 8) {
+                    depth = d;
+                } else if (probe) {
+                    restart = true;   // truncation too coarse: use stored pair records
+                    break;
+                } else {
+                    depth = 8;        // stateless was requested: deepest unroll
                 }
             }
-            polled = t + 1;
-            if (hs.done) break;
+            if ((t + 1) % ce == 0 || t + 1 == p.max_sweeps) {
+                HIPCHK(h, hipMemcpyAsync(&hs, st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+                HIPCHK(h, hipStreamSynchronize(s));
+                if (p.time_sweeps) {
+                    for (int u = polled; u <= t; ++u) {
+                        if (u >= hs.t) break;
+                        sweep_kernel_ms += elapsed(sev[2 * (u % ce)], sev[2 * (u % ce) + 1]);
+                        ++launches;
+                    }
+                }
+                polled = t + 1;
+                if (hs.done) break;
+            }
         }
+        if (!restart) break;
+        cur_stored = true;
+        depth = 0;
+        if (h->Pf.ensure(plane) != hipSuccess || h->Pb.ensure(plane) != hipSuccess ||
+            h->Ef.ensure(plane) != hipSuccess || h->Eb.ensure(plane) != hipSuccess) {
+            h->release_all();
+            return fail(h, GABP_E_NOMEM, "device allocation of the pair-record planes failed");
+        }
+        sa.Pf = h->Pf.p; sa.Pb = h->Pb.p; sa.Ef = h->Ef.p; sa.Eb = h->Eb.p;
+        HIPCHK(h, launch_init(prec, N, NPAD, R, h->Adiag.as<double>(), h->yd.as<float>(), h->Pt.p, h->S.p,
+                              h->alpha_d.as<double>(), st, s));
     }
+    stored = cur_stored;
     HIPCHK(h, hipEventRecord(ev[4], s));
-    const int final_slot = std::max(hs.t, 0) % R;
+    const int final_slot = std::max(hs.t, 0) % (stored ? 1 : R);
 
     // ---- outputs
     h->alpha.assign((size_t)N, 0.0);

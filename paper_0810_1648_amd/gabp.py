@@ -301,3 +301,131 @@ class GabpSVM:
         if st != OK:
             raise self._err(st, "gabp_svm_predict")
         return f
+
+
+# ------------------------------------------------------------------ serving --
+
+class ServerParams(ct.Structure):
+    _fields_ = [("struct_size", ct.c_uint32), ("device", ct.c_int32), ("arena_bytes", ct.c_uint64),
+                ("max_active", ct.c_int32), ("steps_per_poll", ct.c_int32), ("max_bypass", ct.c_int32),
+                ("reserved", ct.c_int32)]
+
+
+class RequestInfo(ct.Structure):
+    _fields_ = [("status", ct.c_int32), ("reason", ct.c_int32), ("sweeps", ct.c_int32),
+                ("reserved", ct.c_int32), ("N", ct.c_int64), ("latency_ms", ct.c_double),
+                ("queue_ms", ct.c_double), ("device_bytes", ct.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        d["reason"] = REASON.get(d["reason"], d["reason"])
+        return d
+
+
+class ServerStats(ct.Structure):
+    _fields_ = [("submitted", ct.c_int64), ("completed", ct.c_int64), ("failed", ct.c_int64),
+                ("p50_ms", ct.c_double), ("p99_ms", ct.c_double), ("mean_ms", ct.c_double),
+                ("max_ms", ct.c_double), ("mean_queue_ms", ct.c_double), ("throughput_per_s", ct.c_double),
+                ("mean_active", ct.c_double), ("max_active_seen", ct.c_int64), ("steps", ct.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _server_lib():
+    L = lib()
+    if not getattr(L, "_server_ready", False):
+        vp, i32, i64, u64p = ct.c_void_p, ct.c_int32, ct.c_int64, ct.POINTER(ct.c_uint64)
+        L.gabp_server_params_default.argtypes = [ct.POINTER(ServerParams)]
+        L.gabp_server_params_default.restype = None
+        L.gabp_server_create.argtypes = [ct.POINTER(ServerParams), ct.POINTER(vp)]
+        L.gabp_server_create.restype = i32
+        L.gabp_server_submit.argtypes = [vp, vp, vp, i64, i64, ct.POINTER(Params), u64p]
+        L.gabp_server_submit.restype = i32
+        L.gabp_server_poll.argtypes = [vp, ct.c_uint64, ct.POINTER(i32)]
+        L.gabp_server_poll.restype = i32
+        L.gabp_server_wait.argtypes = [vp, ct.c_uint64, ct.c_double]
+        L.gabp_server_wait.restype = i32
+        L.gabp_server_result.argtypes = [vp, ct.c_uint64, vp, ct.c_size_t, ct.POINTER(RequestInfo)]
+        L.gabp_server_result.restype = i32
+        L.gabp_server_stats_get.argtypes = [vp, ct.POINTER(ServerStats)]
+        L.gabp_server_stats_get.restype = i32
+        L.gabp_server_destroy.argtypes = [vp]
+        L.gabp_server_destroy.restype = None
+        L._server_ready = True
+    return L
+
+
+class GabpServer:
+    """Continuous-batching server (gabp_server_*): submit host arrays, poll,
+    wait, fetch results and latency statistics."""
+
+    def __init__(self, **kw):
+        L = _server_lib()
+        p = ServerParams()
+        L.gabp_server_params_default(ct.byref(p))
+        for k, v in kw.items():
+            if not hasattr(p, k):
+                raise TypeError(f"unknown server parameter {k!r}")
+            setattr(p, k, v)
+        h = ct.c_void_p()
+        st = L.gabp_server_create(ct.byref(p), ct.byref(h))
+        if st != OK:
+            raise GabpError(st, "gabp_server_create failed: " + L.gabp_status_string(st).decode())
+        self._h = h
+        self._n = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _server_lib().gabp_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def submit(self, X, y, params: Params | None = None, **kw) -> int:
+        p = params if params is not None else make_params(**kw)
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        t = ct.c_uint64()
+        st = _server_lib().gabp_server_submit(self._h, X.ctypes.data_as(ct.c_void_p), y.ctypes.data_as(ct.c_void_p),
+                                              X.shape[0], X.shape[1], ct.byref(p), ct.byref(t))
+        if st != OK:
+            raise GabpError(st, "gabp_server_submit: " + lib().gabp_status_string(st).decode())
+        self._n[t.value] = X.shape[0]
+        return t.value
+
+    def poll(self, ticket) -> bool:
+        d = ct.c_int32()
+        st = _server_lib().gabp_server_poll(self._h, ticket, ct.byref(d))
+        if st != OK:
+            raise GabpError(st, "gabp_server_poll")
+        return bool(d.value)
+
+    def wait(self, ticket, timeout_s=-1.0) -> bool:
+        return _server_lib().gabp_server_wait(self._h, ticket, timeout_s) == OK
+
+    def result(self, ticket):
+        a = np.zeros(self._n[ticket])
+        info = RequestInfo()
+        st = _server_lib().gabp_server_result(self._h, ticket, a.ctypes.data_as(ct.c_void_p), a.nbytes,
+                                              ct.byref(info))
+        if st != OK:
+            raise GabpError(st, "gabp_server_result")
+        return a, info.as_dict()
+
+    def stats(self):
+        s = ServerStats()
+        st = _server_lib().gabp_server_stats_get(self._h, ct.byref(s))
+        if st != OK:
+            raise GabpError(st, "gabp_server_stats_get")
+        return s.as_dict()

@@ -1,0 +1,106 @@
+"""Served form: continuous batching of many solves.
+
+Each request's alpha must equal the single-handle solve of the same problem
+bitwise (same kernels, same per-request reduction order), whether the
+request runs alone or in a mix of uneven sizes and precisions; the
+tolerance stated for serving (1e-5 relative to the FP64 oracle) then
+follows from the single-solve parity tests.
+"""
+import numpy as np
+import pytest
+
+from oracle import gabp_ref as R
+from paper_0810_1648_amd import gabp, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+def _mix(n_req, seed, n_min=200, n_max=2600):
+    rng = np.random.default_rng(seed)
+    out = []
+    for r in range(n_req):
+        n = int(np.exp(rng.uniform(np.log(n_min), np.log(n_max))))
+        m = int(rng.choice([8, 32, 128]))
+        C = float(rng.choice([0.1, 1.0, 10.0]))
+        prec = ["fp32", "mixed", "fp64"][r % 3]
+        X, y = inputs.blobs(n, m, 5000 + r)
+        out.append((X, y, dict(gamma=1.0 / m, C=C, precision=prec, tol_rel=1e-7, edge_state="stored",
+                               kstore="materialise")))
+    return out
+
+
+def _single(X, y, kw):
+    s = gabp.GabpSVM(**kw)
+    st = s.solve(X, y)
+    a = s.alpha()
+    sw = s.sweeps()
+    s.close()
+    return st, a, sw
+
+
+def test_served_equals_single_alone_and_in_mix(torch):
+    reqs = _mix(12, seed=1)
+    print(f"[case] serving mix of {len(reqs)} requests, N {[r[0].shape[0] for r in reqs]}", flush=True)
+    single = [_single(X, y, kw) for X, y, kw in reqs]
+    # alone: one request per fresh server
+    with gabp.GabpServer(arena_bytes=int(2e9), max_active=8) as srv:
+        t = srv.submit(reqs[4][0], reqs[4][1], **reqs[4][2])
+        assert srv.wait(t, 120.0)
+        alone, info = srv.result(t)
+    assert np.array_equal(alone, single[4][1])
+    # in a mix, all submitted at once (more requests than slots)
+    with gabp.GabpServer(arena_bytes=int(2e9), max_active=5, steps_per_poll=3) as srv:
+        tickets = [srv.submit(X, y, **kw) for X, y, kw in reqs]
+        for t in tickets:
+            assert srv.wait(t, 300.0)
+        for k, t in enumerate(tickets):
+            a, info = srv.result(t)
+            st, ref, sw = single[k]
+            assert info["status"] == st and info["sweeps"] == sw, (k, info, st, sw)
+            assert np.array_equal(a, ref), k
+        stats = srv.stats()
+    print("serving stats", stats)
+    assert stats["completed"] + stats["failed"] == len(reqs)
+    assert 1 <= stats["max_active_seen"] <= 5
+    assert stats["p50_ms"] <= stats["p99_ms"] <= stats["max_ms"]
+
+
+def test_served_result_matches_oracle(torch):
+    X, y = inputs.blobs(900, 16, 31)
+    with gabp.GabpServer(arena_bytes=int(1e9)) as srv:
+        t = srv.submit(X, y, gamma=1.0 / 16, C=1.0, precision="mixed", tol_rel=1e-9)
+        assert srv.wait(t, 120.0)
+        a, info = srv.result(t)
+    A, b = R.svm_system(X, y, 1.0 / 16, 1.0, 1.0 / 900)
+    exact = R.cholesky_solve(A, b)
+    err = float(np.max(np.abs(a - exact)) / np.max(np.abs(exact)))
+    print(f"served mixed N=900: sweeps {info['sweeps']} rel err {err:.2e}")
+    assert info["status"] == gabp.OK and err <= 1e-5
+
+
+def test_admission_by_footprint(torch):
+    # arena sized for about two of these requests at a time
+    reqs = _mix(6, seed=3, n_min=1500, n_max=1600)
+    reqs = [(X, y, dict(kw, precision="fp32")) for X, y, kw in reqs]
+    one = 5 * 21 * 65536 * 4   # five FP32 planes of a 6-block problem (21 tiles)
+    with gabp.GabpServer(arena_bytes=int(2.6 * one), max_active=8) as srv:
+        tickets = [srv.submit(X, y, **kw) for X, y, kw in reqs]
+        for t in tickets:
+            assert srv.wait(t, 300.0)
+        stats = srv.stats()
+        infos = [srv.result(t)[1] for t in tickets]
+    print("admission stats", stats)
+    assert stats["max_active_seen"] <= 2
+    assert all(i["status"] == gabp.OK for i in infos)
+    with gabp.GabpServer(arena_bytes=int(0.5 * one)) as srv:
+        with pytest.raises(gabp.GabpError) as e:
+            srv.submit(reqs[0][0], reqs[0][1], **reqs[0][2])
+        assert e.value.status == gabp.E_NOMEM
