@@ -29,6 +29,22 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 VALU_PEAK_GSLOT = 256 * 64 * 2.4
 
 
+def counter_traffic(path, key):
+    """HBM bytes per launch from the calibrated FETCH_SIZE + WRITE_SIZE counter
+    runs recorded in profiles/, in GB; None when absent or when the kernel
+    source has changed since the counters were taken."""
+    import hashlib
+    try:
+        tj = json.load(open(path))
+        src = open(os.path.join(ROOT, "paper_0810_1648_amd", "csrc", "gabp_kernels.hip"), "rb").read()
+        if hashlib.sha256(src).hexdigest() != tj["kernel_source_sha256"]:
+            return None
+        e = tj["entries"].get(key)
+        return None if e is None else e["traffic_bytes"] / 1e9
+    except Exception:
+        return None
+
+
 def stateless_slots_per_pair(levels):
     """Algorithmic VALU issue slots per pair of the stateless sweep: each of
     `levels` levels forms two cavity precisions and two reciprocals and the
@@ -226,19 +242,13 @@ def main():
     avg_ms = ktime / max(klaunch, 1)
     pairs = N * (N - 1) / 2.0
     stateless = plan["edge_state"] == gabp.EDGE["stateless"]
-    traffic = None
-    if os.path.exists(a.traffic_json):
-        try:
-            tj = json.load(open(a.traffic_json))
-            key = f"{wl.name}:{N}:{a.precision}:{plan['kstore']}:{plan['edge_state']}"
-            traffic = tj.get(key)
-        except Exception:
-            traffic = None
+    traffic = counter_traffic(a.traffic_json, f"{wl.name}:{N}:{a.precision}:{plan['kstore']}:{plan['edge_state']}")
     if stateless:
         slots = stateless_slots_per_pair(plan["stateless_depth"])
         achieved = slots * pairs / (avg_ms * 1e-3) / 1e9 if klaunch else None
         roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_GSLOT, "unit": "Gslot/s",
                 "frac": (achieved / VALU_PEAK_GSLOT) if achieved else None, "traffic": traffic,
+                "traffic_unit": "GB/launch",
                 "kernel": "k_sweep (stateless)", "avg_launch_ms": avg_ms, "launches": klaunch,
                 "alg_slots_per_pair": slots, "stateless_depth": plan["stateless_depth"],
                 "stateless_rho": plan["stateless_rho"],
@@ -248,6 +258,7 @@ def main():
         achieved = plan["alg_bytes_per_sweep"] / (avg_ms * 1e-3) / 1e9 if klaunch else None
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+                "traffic_unit": "GB/launch",
                 "kernel": "k_sweep (stored)", "avg_launch_ms": avg_ms, "launches": klaunch,
                 "alg_bytes_per_launch": plan["alg_bytes_per_sweep"],
                 "alg_bytes_per_pair": plan["alg_bytes_per_pair"]}
@@ -265,6 +276,8 @@ def main():
                                                       np.max(np.abs(info["alpha"]))),
                       "roofline": {"bound": "hbm", "achieved": s_ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                    "frac": s_ach / HBM_PEAK_GBS, "kernel": "k_sweep (stored)",
+                                   "traffic": counter_traffic(a.traffic_json, f"{wl.name}:{N}:{a.precision}:{sp['kstore']}:{sp['edge_state']}"),
+                                   "traffic_unit": "GB/launch",
                                    "avg_launch_ms": s_ms, "launches": sl_,
                                    "alg_bytes_per_launch": sp["alg_bytes_per_sweep"],
                                    "alg_bytes_per_pair": sp["alg_bytes_per_pair"]}}
