@@ -45,12 +45,21 @@ def counter_traffic(path, key):
         return None
 
 
-def stateless_slots_per_pair(levels):
-    """Algorithmic VALU issue slots per pair of the stateless sweep: each of
-    `levels` levels forms two cavity precisions and two reciprocals and the
-    four new messages (10 arithmetic ops + 2 reciprocals at 4 slots each);
-    the top level adds the four partial-sum accumulations."""
-    return levels * (10 + 2 * 4) + 4
+def stateless_slots_per_pair(levels, series):
+    """Algorithmic VALU issue slots per pair of one stateless sweep with
+    `levels` unrolled levels (two directions per pair).
+    Exact reciprocals: each level forms two cavity precisions, two
+    reciprocals (4 issue slots each: transcendental rate) and four messages
+    (10 arithmetic ops), i.e. 18 slots.
+    Series reciprocals: the deepest level starts from zero messages (4 ops);
+    each middle level forms e = P_rev / P~, the one-term reciprocal and four
+    messages (12 ops); the top level uses the two-term series (14 ops).
+    Plus four partial-sum accumulations."""
+    if not series:
+        return levels * (10 + 2 * 4) + 4
+    if levels <= 1:
+        return 14 + 4
+    return 4 + 12 * (levels - 2) + 14 + 4
 
 
 def parse():
@@ -244,13 +253,14 @@ def main():
     stateless = plan["edge_state"] == gabp.EDGE["stateless"]
     traffic = counter_traffic(a.traffic_json, f"{wl.name}:{N}:{a.precision}:{plan['kstore']}:{plan['edge_state']}")
     if stateless:
-        slots = stateless_slots_per_pair(plan["stateless_depth"])
+        slots = stateless_slots_per_pair(plan["stateless_depth"], bool(plan["series_reciprocal"]))
         achieved = slots * pairs / (avg_ms * 1e-3) / 1e9 if klaunch else None
         roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_GSLOT, "unit": "Gslot/s",
                 "frac": (achieved / VALU_PEAK_GSLOT) if achieved else None, "traffic": traffic,
                 "traffic_unit": "GB/launch",
                 "kernel": "k_sweep (stateless)", "avg_launch_ms": avg_ms, "launches": klaunch,
                 "alg_slots_per_pair": slots, "stateless_depth": plan["stateless_depth"],
+                "series_reciprocal": bool(plan["series_reciprocal"]),
                 "stateless_rho": plan["stateless_rho"],
                 "hbm_alg_bytes_per_launch": plan["alg_bytes_per_sweep"],
                 "hbm_frac": plan["alg_bytes_per_sweep"] / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if klaunch else None}

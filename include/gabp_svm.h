@@ -176,6 +176,9 @@ typedef struct gabp_plan {
                                   after sweep 1 (auto depth); the truncation of
                                   the message recursion is bounded by
                                   rho^stateless_depth */
+    int32_t series_reciprocal; /* 1: stateless reciprocals of the cavity
+                                  precisions by the series around 1/P~ */
+    int32_t reserved;
 } gabp_plan;
 
 /* Query selectors for gabp_svm_query: dst type and size in brackets. */

@@ -554,12 +554,21 @@ __global__ void k_init(int64_t N, int64_t NPAD, int R, const double* __restrict_
 //      from the aggregates of up to D earlier sweeps (runtime depth L <= D),
 //      deeper levels in LT = float (FP32/MIXED) or double (FP64);
 //   FIRST: the stored planes are all zero (sweep 1) and are not read.
-template <class ST, class MT, class AT, int KSRC, int GK, int D, bool FIRST>
+// Work of one tile.  SER (stateless only): the reciprocals of the cavity
+// precisions Q = P~ (1 - e), e = P_reverse / P~, are formed from the
+// per-node 1/P~ by the series 1/Q = (1 + e + e^2 + ...) / P~ (one term at
+// the lower levels, two at the top), valid because |e| <= rho^2 where rho is
+// the contraction estimate; the host enables it only when the neglected terms
+// are below the arithmetic's precision.  The deepest level starts from zero
+// messages and costs four multiplications.
+template <class ST, class MT, class AT, int KSRC, int GK, int D, bool FIRST, bool SER>
 __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile) {
     DevStatus* st = a.st;
     using LT = typename std::conditional<std::is_same<ST, double>::value, double, float>::type;
     constexpr bool STORED = (D == 0);
     constexpr int DL = (D > 1) ? D - 1 : 1;   // lower levels held per node
+    constexpr int NL = STORED ? 1 : DL;
+    constexpr int NT = STORED ? 1 : TILE;
     const uint32_t ij = a.tiles[tile];
     const TileCoord tc{(int)(ij >> 16), (int)(ij & 0xFFFFu)};
     const int NB = a.NB;
@@ -575,32 +584,43 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile) {
     ST* Ef = static_cast<ST*>(a.Ef);
     ST* Eb = static_cast<ST*>(a.Eb);
 
-    __shared__ AT sPt[TILE], sS[TILE];
-    __shared__ LT sPtL[STORED ? 1 : DL][STORED ? 1 : TILE], sSL[STORED ? 1 : DL][STORED ? 1 : TILE];
+    // row-node data: top level (P~ or, with SER, 1/P~) and lower levels
+    __shared__ MT sPt[TILE], sS[TILE];
+    __shared__ LT sPtL[NL][NT], sSL[NL][NT], sSIL[SER ? NL : 1][SER ? NT : 1];
     __shared__ AT rP[4][TILE], rE[4][TILE];
     __shared__ float kband[KSRC == KSRC_RECOMPUTE ? 4 : 1][KSRC == KSRC_RECOMPUTE ? 32 * 64 : 1];
 
     const int64_t top = (int64_t)a.slot_top * a.NPAD;
-    sPt[tid] = HP[top + (int64_t)tc.I * TILE + tid];
-    sS[tid] = HS[top + (int64_t)tc.I * TILE + tid];
+    {
+        const MT p = (MT)HP[top + (int64_t)tc.I * TILE + tid];
+        sPt[tid] = SER ? (MT)1 / p : p;
+        sS[tid] = (MT)HS[top + (int64_t)tc.I * TILE + tid];
+    }
     MT ptj[4], sj[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        ptj[c] = (MT)HP[top + (int64_t)tc.J * TILE + col0 + c];
+        const MT p = (MT)HP[top + (int64_t)tc.J * TILE + col0 + c];
+        ptj[c] = SER ? (MT)1 / p : p;
         sj[c] = (MT)HS[top + (int64_t)tc.J * TILE + col0 + c];
     }
-    LT ptjL[DL][4], sjL[DL][4];
+    LT ptjL[DL][4], sjL[DL][4], sijL[SER ? DL : 1][4];
     if constexpr (!STORED) {
 #pragma unroll
         for (int k = 1; k < D; ++k) {
             if (k < L) {
                 const int64_t base = (int64_t)((a.slot_top - k + a.R) % a.R) * a.NPAD;
-                sPtL[k - 1][tid] = (LT)HP[base + (int64_t)tc.I * TILE + tid];
-                sSL[k - 1][tid] = (LT)HS[base + (int64_t)tc.I * TILE + tid];
+                const LT pr = (LT)HP[base + (int64_t)tc.I * TILE + tid];
+                const LT sr = (LT)HS[base + (int64_t)tc.I * TILE + tid];
+                sPtL[k - 1][tid] = SER ? (LT)1 / pr : pr;
+                sSL[k - 1][tid] = sr;
+                if constexpr (SER) sSIL[k - 1][tid] = sr / pr;
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    ptjL[k - 1][c] = (LT)HP[base + (int64_t)tc.J * TILE + col0 + c];
-                    sjL[k - 1][c] = (LT)HS[base + (int64_t)tc.J * TILE + col0 + c];
+                    const LT pc = (LT)HP[base + (int64_t)tc.J * TILE + col0 + c];
+                    const LT sc = (LT)HS[base + (int64_t)tc.J * TILE + col0 + c];
+                    ptjL[k - 1][c] = SER ? (LT)1 / pc : pc;
+                    sjL[k - 1][c] = sc;
+                    if constexpr (SER) sijL[k - 1][c] = sc / pc;
                 }
             }
         }
@@ -633,7 +653,7 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile) {
                 const float4 kk = *reinterpret_cast<const float4*>(&kband[w][(4 * s2 + g) * 64 + 4 * q]);
                 k = V4<ST>{{(ST)kk.x, (ST)kk.y, (ST)kk.z, (ST)kk.w}};
             }
-            const MT pti = (MT)sPt[r], si = (MT)sS[r];
+            const MT pti = sPt[r], si = sS[r];
             AT rp = 0, re = 0;
             V4<ST> npf, npb, nef, neb;
 #pragma unroll
@@ -643,6 +663,29 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile) {
                 MT opf, opb, oef, oeb;
                 if constexpr (STORED) {
                     opf = (MT)pf.v[c]; opb = (MT)pb.v[c]; oef = (MT)ef.v[c]; oeb = (MT)eb.v[c];
+                } else if constexpr (SER) {
+                    const LT al = (LT)k.v[c], a2l = al * al;
+                    LT lpf = 0, lpb = 0, lef = 0, leb = 0;
+                    const int kd = L - 1;
+#pragma unroll
+                    for (int kk = D - 1; kk >= 1; --kk) {
+                        if (kk == kd) {               // deepest level: reverse messages zero
+                            lpf = -a2l * sPtL[kk - 1][r];
+                            lpb = -a2l * ptjL[kk - 1][c];
+                            lef = -al * sSIL[kk - 1][r];
+                            leb = -al * sijL[kk - 1][c];
+                        } else if (kk < kd) {
+                            const LT ir = sPtL[kk - 1][r], ic = ptjL[kk - 1][c];
+                            const LT e_f = lpb * ir, e_b = lpf * ic;
+                            bad |= !(e_f > (LT)-0.5) | !(e_b > (LT)-0.5);
+                            const LT tf = al * fma(ir, e_f, ir), tb = al * fma(ic, e_b, ic);
+                            const LT npf_ = -al * tf, npb_ = -al * tb;
+                            const LT nef_ = tf * (leb - sSL[kk - 1][r]);
+                            const LT neb_ = tb * (lef - sjL[kk - 1][c]);
+                            lpf = npf_; lpb = npb_; lef = nef_; leb = neb_;
+                        }
+                    }
+                    opf = (MT)lpf; opb = (MT)lpb; oef = (MT)lef; oeb = (MT)leb;
                 } else {
                     const LT al = (LT)k.v[c], a2l = al * al;
                     LT lpf = 0, lpb = 0, lef = 0, leb = 0;
@@ -660,18 +703,37 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile) {
                     }
                     opf = (MT)lpf; opb = (MT)lpb; oef = (MT)lef; oeb = (MT)leb;
                 }
-                const MT a2 = av * av;
-                const MT qf = pti - opb;        // P~_i - P_ji
-                const MT qb = ptj[c] - opf;     // P~_j - P_ij
-                bad |= !(qf > (MT)0) | !(qb > (MT)0);
-                const MT rf = rcp_fast(qf), rb = rcp_fast(qb);
-                const ST pij = (ST)(-a2 * rf);
-                const ST eij = (ST)(-av * (si - oeb) * rf);
-                const ST pji = (ST)(-a2 * rb);
-                const ST eji = (ST)(-av * (sj[c] - oef) * rb);
-                npf.v[c] = pij; nef.v[c] = eij; npb.v[c] = pji; neb.v[c] = eji;
-                cP[c] += (AT)pij; cE[c] += (AT)eij;     // received by column node j
-                rp += (AT)pji; re += (AT)eji;            // received by row node i
+                MT pij_m, eij_m, pji_m, eji_m;
+                if constexpr (SER) {
+                    const MT e_f = opb * pti, e_b = opf * ptj[c];      // P_ji / P~_i, P_ij / P~_j
+                    bad |= !(e_f > (MT)-0.5) | !(e_b > (MT)-0.5);
+                    const MT tf = av * fma(pti, fma(e_f, e_f, e_f), pti);
+                    const MT tb = av * fma(ptj[c], fma(e_b, e_b, e_b), ptj[c]);
+                    pij_m = -av * tf;
+                    pji_m = -av * tb;
+                    eij_m = tf * (oeb - si);
+                    eji_m = tb * (oef - sj[c]);
+                } else {
+                    const MT a2 = av * av;
+                    const MT qf = pti - opb;        // P~_i - P_ji
+                    const MT qb = ptj[c] - opf;     // P~_j - P_ij
+                    bad |= !(qf > (MT)0) | !(qb > (MT)0);
+                    const MT rf = rcp_fast(qf), rb = rcp_fast(qb);
+                    pij_m = -a2 * rf;
+                    eij_m = -av * (si - oeb) * rf;
+                    pji_m = -a2 * rb;
+                    eji_m = -av * (sj[c] - oef) * rb;
+                }
+                if constexpr (STORED) {
+                    // the aggregates add the values as stored
+                    const ST pij = (ST)pij_m, eij = (ST)eij_m, pji = (ST)pji_m, eji = (ST)eji_m;
+                    npf.v[c] = pij; nef.v[c] = eij; npb.v[c] = pji; neb.v[c] = eji;
+                    cP[c] += (AT)pij; cE[c] += (AT)eij;     // received by column node j
+                    rp += (AT)pji; re += (AT)eji;            // received by row node i
+                } else {
+                    cP[c] += (AT)pij_m; cE[c] += (AT)eij_m;
+                    rp += (AT)pji_m; re += (AT)eji_m;
+                }
             }
             if constexpr (STORED) { st4(Pf + off, npf); st4(Pb + off, npb); st4(Ef + off, nef); st4(Eb + off, neb); }
             rp = sum16(rp);
@@ -700,10 +762,10 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile) {
     if (__any(bad) && l == 0) st->bad = 1;
 }
 
-template <class ST, class MT, class AT, int KSRC, int GK, int D, bool FIRST>
+template <class ST, class MT, class AT, int KSRC, int GK, int D, bool FIRST, bool SER>
 __global__ __launch_bounds__(WG) void k_sweep(SweepArgs a) {
     if (a.st->done) return;
-    sweep_tile<ST, MT, AT, KSRC, GK, D, FIRST>(a, blockIdx.x);
+    sweep_tile<ST, MT, AT, KSRC, GK, D, FIRST, SER>(a, blockIdx.x);
 }
 
 // Served form: one persistent grid walks the union work list of (request,
@@ -716,7 +778,7 @@ __global__ __launch_bounds__(WG) void k_sweep_batched(const ReqDesc* __restrict_
         const uint2 w = items[it];
         const ReqDesc& rd = reqs[w.x];
         if (rd.sw.st->done) continue;
-        sweep_tile<ST, MT, AT, KSRC_PLANE, GRAM_F32, 0, false>(rd.sw, (int64_t)w.y);
+        sweep_tile<ST, MT, AT, KSRC_PLANE, GRAM_F32, 0, false, false>(rd.sw, (int64_t)w.y);
         __syncthreads();
     }
 }
@@ -1012,49 +1074,59 @@ hipError_t launch_init(int prec, int64_t N, int64_t NPAD, int R, const double* A
     return hipGetLastError();
 }
 
-// ---- sweep dispatch: precision x K' source x Gram kind x depth x first
-template <class ST, class MT, class AT, int KSRC, int GK, int D>
+// ---- sweep dispatch: precision x K' source x Gram kind x depth x first x series
+template <class ST, class MT, class AT, int KSRC, int GK, int D, bool SER>
 static void sweep_d(bool first, const SweepArgs& a, hipStream_t s) {
     const dim3 g((unsigned)a.ntiles), blk(WG);
     if constexpr (D == 0) {
         if (first) {
-            hipLaunchKernelGGL((k_sweep<ST, MT, AT, KSRC, GK, D, true>), g, blk, 0, s, a);
+            hipLaunchKernelGGL((k_sweep<ST, MT, AT, KSRC, GK, D, true, false>), g, blk, 0, s, a);
             return;
         }
     }
-    hipLaunchKernelGGL((k_sweep<ST, MT, AT, KSRC, GK, D, false>), g, blk, 0, s, a);
+    hipLaunchKernelGGL((k_sweep<ST, MT, AT, KSRC, GK, D, false, SER>), g, blk, 0, s, a);
 }
 
 template <class ST, class MT, class AT, int KSRC, int GK>
-static hipError_t sweep_depth(int depth, bool first, const SweepArgs& a, hipStream_t s) {
+static hipError_t sweep_depth(int depth, bool first, bool ser, const SweepArgs& a, hipStream_t s) {
+    if (ser) {
+        switch (depth) {
+            case 1: case 2: sweep_d<ST, MT, AT, KSRC, GK, 2, true>(first, a, s); break;
+            case 3: case 4: sweep_d<ST, MT, AT, KSRC, GK, 4, true>(first, a, s); break;
+            case 5: case 6: sweep_d<ST, MT, AT, KSRC, GK, 6, true>(first, a, s); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (depth) {
-        case 0: sweep_d<ST, MT, AT, KSRC, GK, 0>(first, a, s); break;
-        case 1: case 2: sweep_d<ST, MT, AT, KSRC, GK, 2>(first, a, s); break;
-        case 3: case 4: sweep_d<ST, MT, AT, KSRC, GK, 4>(first, a, s); break;
-        case 5: case 6: sweep_d<ST, MT, AT, KSRC, GK, 6>(first, a, s); break;
-        case 7: case 8: sweep_d<ST, MT, AT, KSRC, GK, 8>(first, a, s); break;
+        case 0: sweep_d<ST, MT, AT, KSRC, GK, 0, false>(first, a, s); break;
+        case 1: case 2: sweep_d<ST, MT, AT, KSRC, GK, 2, false>(first, a, s); break;
+        case 3: case 4: sweep_d<ST, MT, AT, KSRC, GK, 4, false>(first, a, s); break;
+        case 5: case 6: sweep_d<ST, MT, AT, KSRC, GK, 6, false>(first, a, s); break;
+        case 7: case 8: sweep_d<ST, MT, AT, KSRC, GK, 8, false>(first, a, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(int prec, int ksrc, int gram, int depth, bool first, const SweepArgs& a,
+hipError_t launch_sweep(int prec, int ksrc, int gram, int depth, bool first, bool ser, const SweepArgs& a,
                         hipStream_t s) {
+    if (depth == 0) ser = false;
     if (ksrc == KSRC_PLANE) {
         switch (prec) {
-            case PREC_FP32: return sweep_depth<float, float, float, KSRC_PLANE, GRAM_F32>(depth, first, a, s);
-            case PREC_MIXED: return sweep_depth<float, double, double, KSRC_PLANE, GRAM_F32>(depth, first, a, s);
-            case PREC_FP64: return sweep_depth<double, double, double, KSRC_PLANE, GRAM_F64>(depth, first, a, s);
+            case PREC_FP32: return sweep_depth<float, float, float, KSRC_PLANE, GRAM_F32>(depth, first, ser, a, s);
+            case PREC_MIXED: return sweep_depth<float, double, double, KSRC_PLANE, GRAM_F32>(depth, first, ser, a, s);
+            case PREC_FP64: return sweep_depth<double, double, double, KSRC_PLANE, GRAM_F64>(depth, first, ser, a, s);
             default: return hipErrorInvalidValue;
         }
     }
     if (prec == PREC_FP32 && gram == GRAM_F32)
-        return sweep_depth<float, float, float, KSRC_RECOMPUTE, GRAM_F32>(depth, first, a, s);
+        return sweep_depth<float, float, float, KSRC_RECOMPUTE, GRAM_F32>(depth, first, ser, a, s);
     if (prec == PREC_MIXED) {
         switch (gram) {
-            case GRAM_BF16: return sweep_depth<float, double, double, KSRC_RECOMPUTE, GRAM_BF16>(depth, first, a, s);
-            case GRAM_BF16X3: return sweep_depth<float, double, double, KSRC_RECOMPUTE, GRAM_BF16X3>(depth, first, a, s);
-            case GRAM_BF16X6: return sweep_depth<float, double, double, KSRC_RECOMPUTE, GRAM_BF16X6>(depth, first, a, s);
+            case GRAM_BF16: return sweep_depth<float, double, double, KSRC_RECOMPUTE, GRAM_BF16>(depth, first, ser, a, s);
+            case GRAM_BF16X3: return sweep_depth<float, double, double, KSRC_RECOMPUTE, GRAM_BF16X3>(depth, first, ser, a, s);
+            case GRAM_BF16X6: return sweep_depth<float, double, double, KSRC_RECOMPUTE, GRAM_BF16X6>(depth, first, ser, a, s);
             default: break;
         }
     }

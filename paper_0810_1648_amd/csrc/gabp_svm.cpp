@@ -370,7 +370,8 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
                      : (prec == PREC_MIXED) ? std::ldexp(1.0, -30) : std::ldexp(1.0, -50);
     bool cur_stored = stored && !probe;
     int depth = cur_stored ? 0 : (p.stateless_depth > 0 ? p.stateless_depth : 1);
-    bool choose_depth = !cur_stored && p.stateless_depth == 0;
+    bool choose_depth = !cur_stored;   // rho is measured after sweep 1 of every stateless plan
+    bool ser = false;
     double rho = 0.0;
     DevStatus hs{};
     double sweep_kernel_ms = 0.0;
@@ -387,7 +388,7 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
             sa.slot_top = t % Rr;
             sa.levels = cur_stored ? 0 : std::min(t + 1, depth);
             if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot], s));
-            HIPCHK(h, launch_sweep(prec, ksrc, gram, cur_stored ? 0 : depth, t == 0, sa, s));
+            HIPCHK(h, launch_sweep(prec, ksrc, gram, cur_stored ? 0 : depth, t == 0, ser, sa, s));
             if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot + 1], s));
             char* wP = static_cast<char*>(h->Pt.p) + (size_t)((t + 1) % Rr) * NPAD * agg_bytes;
             char* wS = static_cast<char*>(h->S.p) + (size_t)((t + 1) % Rr) * NPAD * agg_bytes;
@@ -406,7 +407,9 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
                 if (!(r > 0.0)) d = 1;
                 else if (r < 1.0) d = std::max(1, (int)std::ceil(std::log(eps) / std::log(r)));
                 choose_depth = false;
-                if (d <= 8) {
+                if (p.stateless_depth > 0) {
+                    depth = p.stateless_depth;
+                } else if (d <= 8) {
                     depth = d;
                 } else if (probe) {
                     restart = true;   // truncation too coarse: use stored pair records
@@ -414,6 +417,12 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
                 } else {
                     depth = 8;        // stateless was requested: deepest unroll
                 }
+                // Series reciprocals: |e| <= r^2, so the one-term lower levels err by
+                // r^4 (entering the top level scaled by r) and the two-term top level
+                // by r^6; both must stay below the precision of their arithmetic.
+                const double eps_low = (prec == PREC_FP64) ? std::ldexp(1.0, -52) : std::ldexp(1.0, -24);
+                const double eps_top = (prec == PREC_FP32) ? std::ldexp(1.0, -24) : std::ldexp(1.0, -52);
+                ser = depth <= 6 && r < 0.25 && std::pow(r, 5) <= eps_low && std::pow(r, 6) <= eps_top;
             }
             if ((t + 1) % ce == 0 || t + 1 == p.max_sweeps) {
                 HIPCHK(h, hipMemcpyAsync(&hs, st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
@@ -491,6 +500,7 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     h->plan.tile = TILE;
     h->plan.stateless_depth = depth;
     h->plan.stateless_rho = rho;
+    h->plan.series_reciprocal = ser ? 1 : 0;
     h->plan.n_blocks = NB;
     h->plan.n_tiles = nt;
     h->plan.device_bytes = h->held();

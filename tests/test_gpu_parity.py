@@ -299,3 +299,28 @@ def test_plan_follows_memory_budget(torch):
     with pytest.raises(gabp.GabpError) as e:
         s3.solve(wl.X, wl.y)
     assert e.value.status == gabp.E_INVALID
+
+
+def test_stateless_series_reciprocals_match_oracle(torch):
+    """A wide RBF (gamma = 2e-3) gives row sums ~ N and a contraction
+    rho ~ 1/N, small enough for the series reciprocals; the sweeps must
+    still follow the oracle's truncated recursion at the chosen depth."""
+    X, y = inputs.blobs(1500, 8, 71)
+    wl = inputs.Workload("blobs-wide", X, y, gamma=2e-3, C=1.0, lam=1.0 / 1500, precision="mixed",
+                         tol_rel=0.0)
+    A, b = R.svm_system(wl.X, wl.y, wl.gamma, wl.C, wl.lam)
+    exact = R.cholesky_solve(A, b)
+    for prec in ("fp32", "mixed"):
+        for t in (1, 2, 3, 6):
+            s, st = run(torch, wl, precision=prec, edge_state="stateless", kstore="materialise",
+                        max_sweeps=t, tol_abs=0.0, tol_rel=0.0, stagnation_window=0)
+            p = s.plan()
+            assert p["series_reciprocal"] == 1, p
+            ref = R.gabp_solve_stateless(A, b, depth=p["stateless_depth"], sweeps=t)[-1]
+            err = _rel(s.alpha(), ref)
+            assert err <= TOL, (prec, t, p["stateless_depth"], err)
+        s, st = run(torch, wl, precision=prec, edge_state="stateless", tol_rel=1e-9)
+        err = _rel(s.alpha(), exact)
+        print(f"series stateless {prec}: depth {s.plan()['stateless_depth']} rho {s.plan()['stateless_rho']:.2e} "
+              f"sweeps {s.sweeps()} rel err vs Cholesky {err:.2e}")
+        assert st == gabp.OK and err <= TOL
