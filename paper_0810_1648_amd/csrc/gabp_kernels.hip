@@ -71,6 +71,29 @@ __device__ inline void st4(double* p, const V4<double>& v) {
     *reinterpret_cast<double2*>(p + 2) = make_double2(v.v[2], v.v[3]);
 }
 
+// Streaming accesses of the K' and pair-record planes: every element is used
+// once per sweep, so loads and stores carry the non-temporal hint and leave
+// the caches to the aggregates and partial sums.
+__device__ inline V4<float> ld4nt(const float* p) {
+    const f32x4v x = __builtin_nontemporal_load(reinterpret_cast<const f32x4v*>(p));
+    return {{x[0], x[1], x[2], x[3]}};
+}
+__device__ inline void st4nt(float* p, const V4<float>& v) {
+    const f32x4v x = {v.v[0], v.v[1], v.v[2], v.v[3]};
+    __builtin_nontemporal_store(x, reinterpret_cast<f32x4v*>(p));
+}
+typedef double f64x2v __attribute__((ext_vector_type(2)));
+__device__ inline V4<double> ld4nt(const double* p) {
+    const f64x2v a = __builtin_nontemporal_load(reinterpret_cast<const f64x2v*>(p));
+    const f64x2v b = __builtin_nontemporal_load(reinterpret_cast<const f64x2v*>(p + 2));
+    return {{a[0], a[1], b[0], b[1]}};
+}
+__device__ inline void st4nt(double* p, const V4<double>& v) {
+    const f64x2v a = {v.v[0], v.v[1]}, b = {v.v[2], v.v[3]};
+    __builtin_nontemporal_store(a, reinterpret_cast<f64x2v*>(p));
+    __builtin_nontemporal_store(b, reinterpret_cast<f64x2v*>(p + 2));
+}
+
 template <int CTRL> __device__ inline int dpp_i(int v) {
     return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
 }
@@ -631,8 +654,8 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile) {
 
     size_t off = tbase + (size_t)g * TILE + col0;
     V4<ST> k{}, pf{}, pb{}, ef{}, eb{};
-    if constexpr (KSRC == KSRC_PLANE) k = ld4(Kp + off);
-    if constexpr (STORED && !FIRST) { pf = ld4(Pf + off); pb = ld4(Pb + off); ef = ld4(Ef + off); eb = ld4(Eb + off); }
+    if constexpr (KSRC == KSRC_PLANE) k = ld4nt(Kp + off);
+    if constexpr (STORED && !FIRST) { pf = ld4nt(Pf + off); pb = ld4nt(Pb + off); ef = ld4nt(Ef + off); eb = ld4nt(Eb + off); }
 
     for (int b = 0; b < TILE / 32; ++b) {
         if constexpr (KSRC == KSRC_RECOMPUTE) {
@@ -646,8 +669,8 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile) {
             V4<ST> k2{}, pf2{}, pb2{}, ef2{}, eb2{};
             const size_t off2 = off + 4 * TILE;
             if (more) {
-                if constexpr (KSRC == KSRC_PLANE) k2 = ld4(Kp + off2);
-                if constexpr (STORED && !FIRST) { pf2 = ld4(Pf + off2); pb2 = ld4(Pb + off2); ef2 = ld4(Ef + off2); eb2 = ld4(Eb + off2); }
+                if constexpr (KSRC == KSRC_PLANE) k2 = ld4nt(Kp + off2);
+                if constexpr (STORED && !FIRST) { pf2 = ld4nt(Pf + off2); pb2 = ld4nt(Pb + off2); ef2 = ld4nt(Ef + off2); eb2 = ld4nt(Eb + off2); }
             }
             if constexpr (KSRC == KSRC_RECOMPUTE) {
                 const float4 kk = *reinterpret_cast<const float4*>(&kband[w][(4 * s2 + g) * 64 + 4 * q]);
@@ -735,7 +758,7 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile) {
                     rp += (AT)pji_m; re += (AT)eji_m;
                 }
             }
-            if constexpr (STORED) { st4(Pf + off, npf); st4(Pb + off, npb); st4(Ef + off, nef); st4(Eb + off, neb); }
+            if constexpr (STORED) { st4nt(Pf + off, npf); st4nt(Pb + off, npb); st4nt(Ef + off, nef); st4nt(Eb + off, neb); }
             rp = sum16(rp);
             re = sum16(re);
             if (q == 0) { rP[w][r] = rp; rE[w][r] = re; }
