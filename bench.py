@@ -29,6 +29,19 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 VALU_PEAK_GSLOT = 256 * 64 * 2.4
 
 
+def device_source_hash():
+    """SHA-256 over the device sources (every .hip file and gabp_device.h, in
+    name order) of the HIP library."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_0810_1648_amd", "csrc")
+    h = hashlib.sha256()
+    for fn in sorted(os.listdir(d)):
+        if fn.endswith(".hip") or fn == "gabp_device.h":
+            h.update(fn.encode())
+            h.update(open(os.path.join(d, fn), "rb").read())
+    return h.hexdigest()
+
+
 def counter_traffic(path, key):
     """HBM bytes per launch from the calibrated FETCH_SIZE + WRITE_SIZE counter
     runs recorded in profiles/, in GB; None when absent or when the kernel
@@ -36,8 +49,7 @@ def counter_traffic(path, key):
     import hashlib
     try:
         tj = json.load(open(path))
-        src = open(os.path.join(ROOT, "paper_0810_1648_amd", "csrc", "gabp_kernels.hip"), "rb").read()
-        if hashlib.sha256(src).hexdigest() != tj["kernel_source_sha256"]:
+        if device_source_hash() != tj["kernel_source_sha256"]:
             return None
         e = tj["entries"].get(key)
         return None if e is None else e["traffic_bytes"] / 1e9

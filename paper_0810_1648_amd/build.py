@@ -17,7 +17,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libgabp_svm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["gabp_kernels.hip", "gabp_svm.cpp", "gabp_serve.cpp"]
+SOURCES = ["gabp_sweep_mixed.hip", "gabp_sweep_f32.hip", "gabp_sweep_f64.hip", "gabp_kernels.hip",
+           "gabp_svm.cpp", "gabp_serve.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include")]
@@ -35,7 +36,7 @@ def _run(cmd, verbose):
         sys.stderr.write(err + "\n")
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 6) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs = []
     procs = []

@@ -1,0 +1,497 @@
+// Device-side building blocks shared by the HIP translation units of the
+// GaBP SVM solver: vector loads, wave reductions, MFMA Gram tiles, and the
+// sweep of one tile (see gabp_kernels.hip for the data layout).
+#pragma once
+
+#include "gabp_internal.h"
+
+#include <math.h>
+
+#include <algorithm>
+#include <type_traits>
+
+namespace gabp {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+
+// ----------------------------------------------------------------- helpers
+
+template <class T> struct V4 { T v[4]; };
+
+__device__ inline V4<float> ld4(const float* p) {
+    const float4 x = *reinterpret_cast<const float4*>(p);
+    return {{x.x, x.y, x.z, x.w}};
+}
+__device__ inline V4<double> ld4(const double* p) {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    const double2 b = *reinterpret_cast<const double2*>(p + 2);
+    return {{a.x, a.y, b.x, b.y}};
+}
+__device__ inline void st4(float* p, const V4<float>& v) {
+    *reinterpret_cast<float4*>(p) = make_float4(v.v[0], v.v[1], v.v[2], v.v[3]);
+}
+__device__ inline void st4(double* p, const V4<double>& v) {
+    *reinterpret_cast<double2*>(p) = make_double2(v.v[0], v.v[1]);
+    *reinterpret_cast<double2*>(p + 2) = make_double2(v.v[2], v.v[3]);
+}
+
+// Streaming accesses of the K' and pair-record planes: every element is used
+// once per sweep, so loads and stores carry the non-temporal hint and leave
+// the caches to the aggregates and partial sums.
+__device__ inline V4<float> ld4nt(const float* p) {
+    const f32x4v x = __builtin_nontemporal_load(reinterpret_cast<const f32x4v*>(p));
+    return {{x[0], x[1], x[2], x[3]}};
+}
+__device__ inline void st4nt(float* p, const V4<float>& v) {
+    const f32x4v x = {v.v[0], v.v[1], v.v[2], v.v[3]};
+    __builtin_nontemporal_store(x, reinterpret_cast<f32x4v*>(p));
+}
+typedef double f64x2v __attribute__((ext_vector_type(2)));
+__device__ inline V4<double> ld4nt(const double* p) {
+    const f64x2v a = __builtin_nontemporal_load(reinterpret_cast<const f64x2v*>(p));
+    const f64x2v b = __builtin_nontemporal_load(reinterpret_cast<const f64x2v*>(p + 2));
+    return {{a[0], a[1], b[0], b[1]}};
+}
+__device__ inline void st4nt(double* p, const V4<double>& v) {
+    const f64x2v a = {v.v[0], v.v[1]}, b = {v.v[2], v.v[3]};
+    __builtin_nontemporal_store(a, reinterpret_cast<f64x2v*>(p));
+    __builtin_nontemporal_store(b, reinterpret_cast<f64x2v*>(p + 2));
+}
+
+template <int CTRL> __device__ inline int dpp_i(int v) {
+    // every source lane of these patterns exists, so no fill value is needed
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
+}
+template <int CTRL> __device__ inline float dpp(float v) {
+    return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+template <int CTRL> __device__ inline double dpp(double v) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const int lo = dpp_i<CTRL>((int)(unsigned)(u & 0xffffffffull));
+    const int hi = dpp_i<CTRL>((int)(unsigned)(u >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                            (unsigned long long)(unsigned)lo));
+}
+// Sum over the 16 lanes of a DPP row; every lane receives the same bits.
+template <class T> __device__ inline T sum16(T v) {
+    v = v + dpp<0xB1>(v);    // quad_perm(1,0,3,2): pairs
+    v = v + dpp<0x4E>(v);    // quad_perm(2,3,0,1): quads
+    v = v + dpp<0x141>(v);   // row_half_mirror: 8 lanes
+    v = v + dpp<0x140>(v);   // row_mirror: 16 lanes
+    return v;
+}
+// Sum over lanes q, q+16, q+32, q+48 in the fixed order (g0+g1)+(g2+g3).
+template <class T> __device__ inline T sum_groups(T v) {
+    v = v + __shfl_xor(v, 16);
+    v = v + __shfl_xor(v, 32);
+    return v;
+}
+__device__ inline double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+// Block (256 threads) max; result valid in every thread.
+__device__ inline double block_max(double v, double* sh4) {
+    v = wave_max(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh4[w] = v;
+    __syncthreads();
+    v = fmax(fmax(sh4[0], sh4[1]), fmax(sh4[2], sh4[3]));
+    __syncthreads();
+    return v;
+}
+
+__device__ inline uint16_t f2bf(float f) {  // round to nearest even
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Reciprocals: v_rcp_f32 (1 ulp) for FP32; for FP64, v_rcp_f64 refined by
+// two Newton steps (the cavity precisions are far from the denormal range).
+__device__ inline float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double rcp_fast(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+struct TileCoord { int I, J; };
+__device__ inline TileCoord tile_of(const uint32_t* tiles) {
+    const uint32_t ij = tiles[blockIdx.x];
+    return {(int)(ij >> 16), (int)(ij & 0xFFFFu)};
+}
+
+// ------------------------------------------------------------ K' build --
+
+// One 32 x 32 block of the Gram matrix x_a . x_b on MFMA, for A rows
+// rowA = base_a + lane % 32 and B rows colB = base_b + lane % 32.  The
+// inner-product index is split between the two lane halves so that each lane
+// reads contiguous features.  Output layout of the 32x32 MFMAs: register r of
+// lane l holds row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.
+template <int KIND>
+__device__ inline f32x16 mfma_gram_32x32(const Features& F, int64_t rowA, int64_t colB) {
+    const int l = threadIdx.x & 63, h = l >> 5;
+    const int mp = F.m_pad;
+    f32x16 acc = {};
+    if constexpr (KIND == GRAM_F32) {
+        const int half = mp >> 1;
+        const float* pa = F.f32 + rowA * mp + h * half;
+        const float* pb = F.f32 + colB * mp + h * half;
+        for (int s = 0; s < half; s += 4) {
+            const f32x4v a4 = *reinterpret_cast<const f32x4v*>(pa + s);
+            const f32x4v b4 = *reinterpret_cast<const f32x4v*>(pb + s);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[0], b4[0], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[1], b4[1], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[2], b4[2], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4[3], b4[3], acc, 0, 0, 0);
+        }
+    } else {
+        const int64_t oa = rowA * mp + 8 * h, ob = colB * mp + 8 * h;
+        for (int s = 0; s < mp; s += 16) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(F.hi + oa + s);
+            const bf16x8 b = *reinterpret_cast<const bf16x8*>(F.hi + ob + s);
+            if constexpr (KIND == GRAM_BF16X3 || KIND == GRAM_BF16X6) {
+                // correction terms first, then the leading product
+                const bf16x8 al = *reinterpret_cast<const bf16x8*>(F.lo + oa + s);
+                const bf16x8 bl = *reinterpret_cast<const bf16x8*>(F.lo + ob + s);
+                if constexpr (KIND == GRAM_BF16X6) {
+                    const bf16x8 a2 = *reinterpret_cast<const bf16x8*>(F.lo2 + oa + s);
+                    const bf16x8 b2 = *reinterpret_cast<const bf16x8*>(F.lo2 + ob + s);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b2, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, b, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bl, acc, 0, 0, 0);
+                }
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bl, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, b, acc, 0, 0, 0);
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        }
+    }
+    return acc;
+}
+
+// K' = exp(-gamma d^2) + lambda^2 with d^2 = max(0, n_i + n_j - 2 G_ij), zero
+// for pairs that are not strictly upper (i >= j) or are padding (j >= N).
+__device__ inline float kernel_entry(float ni, float nj, float g, int64_t i, int64_t j,
+                                     const KernelParams& kp) {
+    const float d2 = fmaxf(ni + nj - 2.0f * g, 0.0f);
+    const float kv = exp2f(kp.neg_gamma_log2e * d2) + (float)kp.lam2;
+    return (i < j && j < kp.N) ? kv : 0.0f;
+}
+
+// K' for the 32 x 64 band [row0, row0 + 32) x [col0, col0 + 64) of tile
+// (I, J), computed by one wave into its LDS buffer kb[32][64] (row-major).
+template <int KIND>
+__device__ inline void gram_band(const Features& F, const KernelParams& kp, int I, int J, int row0,
+                                 int col0, float* kb) {
+    const int l = threadIdx.x & 63, h = l >> 5, l32 = l & 31;
+    const int64_t rowA = (int64_t)I * TILE + row0 + l32;
+    float ni[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) ni[r] = F.nrm[(int64_t)I * TILE + row0 + 8 * (r >> 2) + 4 * h + (r & 3)];
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+        const int64_t colB = (int64_t)J * TILE + col0 + 32 * cb + l32;
+        const f32x16 acc = mfma_gram_32x32<KIND>(F, rowA, colB);
+        const float nj = F.nrm[colB];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = 8 * (r >> 2) + 4 * h + (r & 3);
+            kb[row * 64 + 32 * cb + l32] =
+                kernel_entry(ni[r], nj, acc[r], (int64_t)I * TILE + row0 + row, colB, kp);
+        }
+    }
+}
+
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ------------------------------------------------------------------ sweep --
+
+// One synchronous sweep over all tiles.  Template parameters:
+//   ST storage type of K' and the message planes, MT type of the top-level
+//   update (cavity denominators, reciprocals), AT aggregate type;
+//   KSRC: K' from the materialised plane or recomputed per 32-row band;
+//   GK: Gram kind of the recompute;
+//   D: 0 = stored edge state (pair-record planes read and written);
+//      D >= 1 = stateless: the messages of the previous sweep are rebuilt
+//      from the aggregates of up to D earlier sweeps (runtime depth L <= D),
+//      deeper levels in LT = float (FP32/MIXED) or double (FP64);
+//   FIRST: the stored planes are all zero (sweep 1) and are not read.
+// Work of one tile.  SER (stateless only): the reciprocals of the cavity
+// precisions Q = P~ (1 - e), e = P_reverse / P~, are formed from the
+// per-node 1/P~ by the series 1/Q = (1 + e + e^2 + ...) / P~ (one term at
+// the lower levels, two at the top), valid because |e| <= rho^2 where rho is
+// the contraction estimate; the host enables it only when the neglected terms
+// are below the arithmetic's precision.  The deepest level starts from zero
+// messages and costs four multiplications.
+template <class ST, class MT, class AT, int KSRC, int GK, int D, bool FIRST, bool SER>
+__device__ inline void sweep_tile(const SweepArgs& a, int64_t tile) {
+    DevStatus* st = a.st;
+    // lower levels: FP32 storage precision; with the series and up to three
+    // levels they run in the top level's type (FP64 FMA issues at the FP32
+    // rate on CDNA4, and no conversions are needed between levels; deeper
+    // unrolls keep FP32 to bound the per-column register history)
+    using LT = typename std::conditional<(SER && D <= 3) || std::is_same<ST, double>::value, MT, float>::type;
+    constexpr bool STORED = (D == 0);
+    constexpr int DL = (D > 1) ? D - 1 : 1;   // lower levels held per node
+    constexpr int NL = STORED ? 1 : DL;
+    constexpr int NT = STORED ? 1 : TILE;
+    const uint32_t ij = a.tiles[tile];
+    const TileCoord tc{(int)(ij >> 16), (int)(ij & 0xFFFFu)};
+    const int NB = a.NB;
+    const size_t tbase = (size_t)tile * TT;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, q = l & 15;
+    const int col0 = w * 64 + q * 4;
+    constexpr int L = D;                      // stateless: levels unrolled in this launch
+    const AT* HP = static_cast<const AT*>(a.HP);
+    const AT* HS = static_cast<const AT*>(a.HS);
+    const ST* Kp = static_cast<const ST*>(a.Kp);
+    ST* Pf = static_cast<ST*>(a.Pf);
+    ST* Pb = static_cast<ST*>(a.Pb);
+    ST* Ef = static_cast<ST*>(a.Ef);
+    ST* Eb = static_cast<ST*>(a.Eb);
+
+    // row-node data: top level (P~ or, with SER, 1/P~) and lower levels
+    __shared__ MT sPt[TILE], sS[TILE];
+    __shared__ LT sPtL[NL][NT], sSL[NL][NT], sSIL[SER ? NL : 1][SER ? NT : 1];
+    __shared__ AT rP[4][TILE], rE[4][TILE];
+    __shared__ float kband[KSRC == KSRC_RECOMPUTE ? 4 : 1][KSRC == KSRC_RECOMPUTE ? 32 * 64 : 1];
+
+    const int64_t top = (int64_t)a.slot_top * a.NPAD;
+    {
+        const MT p = (MT)HP[top + (int64_t)tc.I * TILE + tid];
+        sPt[tid] = SER ? (MT)1 / p : p;
+        sS[tid] = (MT)HS[top + (int64_t)tc.I * TILE + tid];
+    }
+    MT ptj[4], sj[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const MT p = (MT)HP[top + (int64_t)tc.J * TILE + col0 + c];
+        ptj[c] = SER ? (MT)1 / p : p;
+        sj[c] = (MT)HS[top + (int64_t)tc.J * TILE + col0 + c];
+    }
+    LT ptjL[DL][4], sjL[DL][4], sijL[SER ? DL : 1][4];
+    if constexpr (!STORED) {
+#pragma unroll
+        for (int k = 1; k < D; ++k) {
+            if (k < L) {
+                const int64_t base = (int64_t)((a.slot_top - k + a.R) % a.R) * a.NPAD;
+                const LT pr = (LT)HP[base + (int64_t)tc.I * TILE + tid];
+                const LT sr = (LT)HS[base + (int64_t)tc.I * TILE + tid];
+                sPtL[k - 1][tid] = SER ? (LT)1 / pr : pr;
+                sSL[k - 1][tid] = sr;
+                if constexpr (SER) sSIL[k - 1][tid] = sr / pr;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const LT pc = (LT)HP[base + (int64_t)tc.J * TILE + col0 + c];
+                    const LT sc = (LT)HS[base + (int64_t)tc.J * TILE + col0 + c];
+                    ptjL[k - 1][c] = SER ? (LT)1 / pc : pc;
+                    sjL[k - 1][c] = sc;
+                    if constexpr (SER) sijL[k - 1][c] = sc / pc;
+                }
+            }
+        }
+    }
+    AT cP[4] = {0, 0, 0, 0}, cE[4] = {0, 0, 0, 0};
+    bool bad = false;
+    MT emin = 0;       // series: smallest e = P_reverse / P~ seen (valid while > -1/2)
+    __syncthreads();
+
+    size_t off = tbase + (size_t)g * TILE + col0;
+    V4<ST> k{}, pf{}, pb{}, ef{}, eb{};
+    if constexpr (KSRC == KSRC_PLANE) k = ld4nt(Kp + off);
+    if constexpr (STORED && !FIRST) { pf = ld4nt(Pf + off); pb = ld4nt(Pb + off); ef = ld4nt(Ef + off); eb = ld4nt(Eb + off); }
+
+    for (int b = 0; b < TILE / 32; ++b) {
+        if constexpr (KSRC == KSRC_RECOMPUTE) {
+            gram_band<GK>(a.F, a.kp, tc.I, tc.J, 32 * b, 64 * w, kband[w]);
+            wave_lds_sync();
+        }
+#pragma unroll 1
+        for (int s2 = 0; s2 < 8; ++s2) {
+            const int r = 32 * b + 4 * s2 + g;
+            // prefetch the lane's next row (the last row re-reads itself: the
+            // offset stays inside the tile and no branch is needed)
+            const bool more = (b * 8 + s2 + 1) < TILE / 4;
+            const size_t off2 = more ? off + 4 * TILE : off;
+            V4<ST> k2, pf2, pb2, ef2, eb2;
+            if constexpr (KSRC == KSRC_PLANE) k2 = ld4nt(Kp + off2);
+            if constexpr (STORED && !FIRST) { pf2 = ld4nt(Pf + off2); pb2 = ld4nt(Pb + off2); ef2 = ld4nt(Ef + off2); eb2 = ld4nt(Eb + off2); }
+            if constexpr (KSRC == KSRC_RECOMPUTE) {
+                const float4 kk = *reinterpret_cast<const float4*>(&kband[w][(4 * s2 + g) * 64 + 4 * q]);
+                k = V4<ST>{{(ST)kk.x, (ST)kk.y, (ST)kk.z, (ST)kk.w}};
+            }
+            const MT pti = sPt[r], si = sS[r];
+            AT rp = 0, re = 0;
+            V4<ST> npf, npb, nef, neb;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const MT av = (MT)k.v[c];
+                // messages of the previous sweep: stored, or rebuilt level by level
+                MT opf, opb, oef, oeb;
+                if constexpr (STORED) {
+                    opf = (MT)pf.v[c]; opb = (MT)pb.v[c]; oef = (MT)ef.v[c]; oeb = (MT)eb.v[c];
+                } else if constexpr (SER) {
+                    const LT al = (LT)k.v[c], a2l = al * al;
+                    LT lpf = 0, lpb = 0, lef = 0, leb = 0;
+                    constexpr int kd = L - 1;
+#pragma unroll
+                    for (int kk = D - 1; kk >= 1; --kk) {
+                        if (kk == kd) {               // deepest level: reverse messages zero
+                            lpf = -a2l * sPtL[kk - 1][r];
+                            lpb = -a2l * ptjL[kk - 1][c];
+                            lef = -al * sSIL[kk - 1][r];
+                            leb = -al * sijL[kk - 1][c];
+                        } else if (kk < kd) {
+                            const LT ir = sPtL[kk - 1][r], ic = ptjL[kk - 1][c];
+                            const LT e_f = lpb * ir, e_b = lpf * ic;
+                            const LT tf = al * fma(ir, e_f, ir), tb = al * fma(ic, e_b, ic);
+                            const LT npf_ = -al * tf, npb_ = -al * tb;
+                            const LT nef_ = tf * (leb - sSL[kk - 1][r]);
+                            const LT neb_ = tb * (lef - sjL[kk - 1][c]);
+                            lpf = npf_; lpb = npb_; lef = nef_; leb = neb_;
+                        }
+                    }
+                    opf = (MT)lpf; opb = (MT)lpb; oef = (MT)lef; oeb = (MT)leb;
+                } else {
+                    const LT al = (LT)k.v[c], a2l = al * al;
+                    LT lpf = 0, lpb = 0, lef = 0, leb = 0;
+#pragma unroll
+                    for (int kk = D - 1; kk >= 1; --kk) {
+                        if (kk < L) {
+                            const LT qf = sPtL[kk - 1][r] - lpb, qb = ptjL[kk - 1][c] - lpf;
+                            bad |= !(qf > (LT)0) | !(qb > (LT)0);
+                            const LT rf = rcp_fast(qf), rb = rcp_fast(qb);
+                            const LT npf_ = -a2l * rf, npb_ = -a2l * rb;
+                            const LT nef_ = -al * (sSL[kk - 1][r] - leb) * rf;
+                            const LT neb_ = -al * (sjL[kk - 1][c] - lef) * rb;
+                            lpf = npf_; lpb = npb_; lef = nef_; leb = neb_;
+                        }
+                    }
+                    opf = (MT)lpf; opb = (MT)lpb; oef = (MT)lef; oeb = (MT)leb;
+                }
+                MT pij_m, eij_m, pji_m, eji_m;
+                if constexpr (SER) {
+                    const MT e_f = opb * pti, e_b = opf * ptj[c];      // P_ji / P~_i, P_ij / P~_j
+                    emin = fmin(emin, fmin(e_f, e_b));
+                    const MT tf = av * fma(pti, fma(e_f, e_f, e_f), pti);
+                    const MT tb = av * fma(ptj[c], fma(e_b, e_b, e_b), ptj[c]);
+                    pij_m = -av * tf;
+                    pji_m = -av * tb;
+                    eij_m = tf * (oeb - si);
+                    eji_m = tb * (oef - sj[c]);
+                } else {
+                    const MT a2 = av * av;
+                    const MT qf = pti - opb;        // P~_i - P_ji
+                    const MT qb = ptj[c] - opf;     // P~_j - P_ij
+                    bad |= !(qf > (MT)0) | !(qb > (MT)0);
+                    const MT rf = rcp_fast(qf), rb = rcp_fast(qb);
+                    pij_m = -a2 * rf;
+                    eij_m = -av * (si - oeb) * rf;
+                    pji_m = -a2 * rb;
+                    eji_m = -av * (sj[c] - oef) * rb;
+                }
+                if constexpr (STORED) {
+                    // the aggregates add the values as stored
+                    const ST pij = (ST)pij_m, eij = (ST)eij_m, pji = (ST)pji_m, eji = (ST)eji_m;
+                    npf.v[c] = pij; nef.v[c] = eij; npb.v[c] = pji; neb.v[c] = eji;
+                    cP[c] += (AT)pij; cE[c] += (AT)eij;     // received by column node j
+                    rp += (AT)pji; re += (AT)eji;            // received by row node i
+                } else {
+                    cP[c] += (AT)pij_m; cE[c] += (AT)eij_m;
+                    rp += (AT)pji_m; re += (AT)eji_m;
+                }
+            }
+            if constexpr (STORED) { st4nt(Pf + off, npf); st4nt(Pb + off, npb); st4nt(Ef + off, nef); st4nt(Eb + off, neb); }
+            rp = sum16(rp);
+            re = sum16(re);
+            if (q == 0) { rP[w][r] = rp; rE[w][r] = re; }
+            if constexpr (KSRC == KSRC_PLANE) k = k2;
+            if constexpr (STORED && !FIRST) { pf = pf2; pb = pb2; ef = ef2; eb = eb2; }
+            off = off2;
+        }
+        if constexpr (KSRC == KSRC_RECOMPUTE) wave_lds_sync();
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) { cP[c] = sum_groups(cP[c]); cE[c] = sum_groups(cE[c]); }
+    __syncthreads();
+    AT* partP = static_cast<AT*>(a.partP);
+    AT* partE = static_cast<AT*>(a.partE);
+    const size_t rowslot = ((size_t)tc.I * (NB + 1) + tc.J) * TILE + tid;
+    partP[rowslot] = (rP[0][tid] + rP[1][tid]) + (rP[2][tid] + rP[3][tid]);
+    partE[rowslot] = (rE[0][tid] + rE[1][tid]) + (rE[2][tid] + rE[3][tid]);
+    if (g == 0) {
+        const int slot = (tc.I < tc.J) ? tc.I : NB;
+        const size_t cb = ((size_t)tc.J * (NB + 1) + slot) * TILE + col0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) { partP[cb + c] = cP[c]; partE[cb + c] = cE[c]; }
+    }
+    if constexpr (SER) bad |= !(emin > (MT)-0.5);
+    if (__any(bad) && l == 0) st->bad = 1;
+}
+
+template <class ST, class MT, class AT, int KSRC, int GK, int D, bool FIRST, bool SER>
+__global__ __launch_bounds__(WG) void k_sweep(SweepArgs a) {
+    if (a.st->done) return;
+    sweep_tile<ST, MT, AT, KSRC, GK, D, FIRST, SER>(a, blockIdx.x);
+}
+
+// ---- sweep dispatch: precision x K' source x Gram kind x depth x first x series
+template <class ST, class MT, class AT, int KSRC, int GK, int D, bool SER>
+inline void sweep_d(bool first, const SweepArgs& a, hipStream_t s) {
+    const dim3 g((unsigned)a.ntiles), blk(WG);
+    if constexpr (D == 0) {
+        if (first) {
+            hipLaunchKernelGGL((k_sweep<ST, MT, AT, KSRC, GK, D, true, false>), g, blk, 0, s, a);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_sweep<ST, MT, AT, KSRC, GK, D, false, SER>), g, blk, 0, s, a);
+}
+
+// `levels` = 0: stored edge state; >= 1: stateless with exactly that many
+// levels (each count is its own instantiation, so the level loops are
+// fully unrolled and branch-free).
+template <class ST, class MT, class AT, int KSRC, int GK>
+inline hipError_t sweep_depth(int levels, bool first, bool ser, const SweepArgs& a, hipStream_t s) {
+    if (levels == 0) {
+        sweep_d<ST, MT, AT, KSRC, GK, 0, false>(first, a, s);
+        return hipGetLastError();
+    }
+    if (ser) {
+        switch (levels) {
+            case 1: sweep_d<ST, MT, AT, KSRC, GK, 1, true>(first, a, s); break;
+            case 2: sweep_d<ST, MT, AT, KSRC, GK, 2, true>(first, a, s); break;
+            case 3: sweep_d<ST, MT, AT, KSRC, GK, 3, true>(first, a, s); break;
+            case 4: sweep_d<ST, MT, AT, KSRC, GK, 4, true>(first, a, s); break;
+            case 5: sweep_d<ST, MT, AT, KSRC, GK, 5, true>(first, a, s); break;
+            case 6: sweep_d<ST, MT, AT, KSRC, GK, 6, true>(first, a, s); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    switch (levels) {
+        case 1: sweep_d<ST, MT, AT, KSRC, GK, 1, false>(first, a, s); break;
+        case 2: sweep_d<ST, MT, AT, KSRC, GK, 2, false>(first, a, s); break;
+        case 3: sweep_d<ST, MT, AT, KSRC, GK, 3, false>(first, a, s); break;
+        case 4: sweep_d<ST, MT, AT, KSRC, GK, 4, false>(first, a, s); break;
+        case 5: sweep_d<ST, MT, AT, KSRC, GK, 5, false>(first, a, s); break;
+        case 6: sweep_d<ST, MT, AT, KSRC, GK, 6, false>(first, a, s); break;
+        case 7: sweep_d<ST, MT, AT, KSRC, GK, 7, false>(first, a, s); break;
+        case 8: sweep_d<ST, MT, AT, KSRC, GK, 8, false>(first, a, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gabp

@@ -135,9 +135,16 @@ hipError_t launch_served_step(int prec, const ReqDesc* reqs, const uint2* tile_i
                               const uint2* node_items, int nnode_items, const int* slots, int nslots,
                               DevStatus* status_out, hipStream_t s);
 // depth 0 = stored edge state, 1..8 = stateless with up to `depth` levels.
-// ser: stateless reciprocals by the series around 1/P~ (see sweep_tile).
-hipError_t launch_sweep(int prec, int ksrc, int gram, int depth, bool first, bool ser, const SweepArgs& a,
+// levels: 0 = stored edge state, >= 1 = stateless with that many levels in
+// this launch; ser: stateless reciprocals by the series around 1/P~.
+hipError_t launch_sweep(int prec, int ksrc, int gram, int levels, bool first, bool ser, const SweepArgs& a,
                         hipStream_t s);
+hipError_t launch_sweep_f32(int ksrc, int gram, int levels, bool first, bool ser, const SweepArgs& a,
+                            hipStream_t s);
+hipError_t launch_sweep_mixed(int ksrc, int gram, int levels, bool first, bool ser, const SweepArgs& a,
+                              hipStream_t s);
+hipError_t launch_sweep_f64(int ksrc, int gram, int levels, bool first, bool ser, const SweepArgs& a,
+                            hipStream_t s);
 hipError_t launch_finalize(int prec, int64_t N, int NB, const void* partP, const void* partE,
                            const double* Adiag, const float* y, void* Pt, void* S,
                            double* alpha, double* blk_delta, double* blk_amax,

@@ -388,7 +388,7 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
             sa.slot_top = t % Rr;
             sa.levels = cur_stored ? 0 : std::min(t + 1, depth);
             if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot], s));
-            HIPCHK(h, launch_sweep(prec, ksrc, gram, cur_stored ? 0 : depth, t == 0, ser, sa, s));
+            HIPCHK(h, launch_sweep(prec, ksrc, gram, sa.levels, t == 0, ser, sa, s));
             if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot + 1], s));
             char* wP = static_cast<char*>(h->Pt.p) + (size_t)((t + 1) % Rr) * NPAD * agg_bytes;
             char* wS = static_cast<char*>(h->S.p) + (size_t)((t + 1) % Rr) * NPAD * agg_bytes;

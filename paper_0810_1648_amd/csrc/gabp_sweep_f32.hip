@@ -1,0 +1,15 @@
+// Sweep instantiations of the FP32 (plain) path: stored pair records, or
+// stateless with 1..8 levels (1..6 with series reciprocals), over the
+// materialised or recomputed K'.
+#include "gabp_device.h"
+
+namespace gabp {
+
+hipError_t launch_sweep_f32(int ksrc, int gram, int levels, bool first, bool ser, const SweepArgs& a,
+                              hipStream_t s) {
+    if (ksrc == KSRC_PLANE) return sweep_depth<float, float, float, KSRC_PLANE, GRAM_F32>(levels, first, ser, a, s);
+    if (gram == GRAM_F32) return sweep_depth<float, float, float, KSRC_RECOMPUTE, GRAM_F32>(levels, first, ser, a, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace gabp

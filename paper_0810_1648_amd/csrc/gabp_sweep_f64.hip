@@ -1,0 +1,15 @@
+// Sweep instantiations of the FP64 path: stored pair records, or
+// stateless with 1..8 levels (1..6 with series reciprocals), over the
+// materialised or recomputed K'.
+#include "gabp_device.h"
+
+namespace gabp {
+
+hipError_t launch_sweep_f64(int ksrc, int gram, int levels, bool first, bool ser, const SweepArgs& a,
+                              hipStream_t s) {
+    if (ksrc == KSRC_PLANE) return sweep_depth<double, double, double, KSRC_PLANE, GRAM_F64>(levels, first, ser, a, s);
+    (void)gram;
+    return hipErrorInvalidValue;   // FP64 K' is always materialised
+}
+
+}  // namespace gabp

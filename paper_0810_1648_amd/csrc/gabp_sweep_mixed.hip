@@ -1,0 +1,19 @@
+// Sweep instantiations of the MIXED (BF16 Gram, FP32 storage, FP64 top level and aggregates) path: stored pair records, or
+// stateless with 1..8 levels (1..6 with series reciprocals), over the
+// materialised or recomputed K'.
+#include "gabp_device.h"
+
+namespace gabp {
+
+hipError_t launch_sweep_mixed(int ksrc, int gram, int levels, bool first, bool ser, const SweepArgs& a,
+                              hipStream_t s) {
+    if (ksrc == KSRC_PLANE) return sweep_depth<float, double, double, KSRC_PLANE, GRAM_F32>(levels, first, ser, a, s);
+    switch (gram) {
+        case GRAM_BF16: return sweep_depth<float, double, double, KSRC_RECOMPUTE, GRAM_BF16>(levels, first, ser, a, s);
+        case GRAM_BF16X3: return sweep_depth<float, double, double, KSRC_RECOMPUTE, GRAM_BF16X3>(levels, first, ser, a, s);
+        case GRAM_BF16X6: return sweep_depth<float, double, double, KSRC_RECOMPUTE, GRAM_BF16X6>(levels, first, ser, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace gabp
