@@ -132,7 +132,7 @@ def serving_bench(gabp, inputs, n_req, load, precision, seq_sample=24):
     import numpy as np
     stream = inputs.serving_stream(n_req, rate_per_s=1.0, seed=3)
     kws = [dict(gamma=r.workload.gamma, C=r.workload.C, precision=precision, tol_rel=r.workload.tol_rel,
-                kstore="materialise", edge_state="stored") for r in stream]
+                kstore="materialise", edge_state="auto") for r in stream]
     sp = dict(arena_bytes=int(120e9), max_active=64, steps_per_poll=2)
     # closed loop
     with gabp.GabpServer(**sp) as srv:
@@ -142,7 +142,12 @@ def serving_bench(gabp, inputs, n_req, load, precision, seq_sample=24):
             srv.wait(t)
         cap_wall = time.perf_counter() - t0
         closed = srv.stats()
-        sweeps = [srv.result(t)[1]["sweeps"] for t in tickets]
+        infos = [srv.result(t)[1] for t in tickets]
+        sweeps = [i["sweeps"] for i in infos]
+        plan_mix = {}
+        for i in infos:
+            key = "stored" if i["stateless_levels"] == 0 else f"stateless_{i['stateless_levels']}"
+            plan_mix[key] = plan_mix.get(key, 0) + 1
     capacity = n_req / cap_wall
     print(f"[bench] serving closed loop: {n_req} solves in {cap_wall:.2f} s", file=sys.stderr, flush=True)
     # open loop, Poisson arrivals at load x capacity
@@ -181,7 +186,8 @@ def serving_bench(gabp, inputs, n_req, load, precision, seq_sample=24):
             "throughput_solves_per_s": opened["throughput_per_s"],
             "mean_active": opened["mean_active"], "max_active_seen": opened["max_active_seen"],
             "closed_loop_p50_ms": closed["p50_ms"], "closed_loop_p99_ms": closed["p99_ms"],
-            "mean_sweeps": float(np.mean(sweeps)), "failed": opened["failed"] + closed["failed"],
+            "mean_sweeps": float(np.mean(sweeps)), "plan_mix": plan_mix,
+            "failed": opened["failed"] + closed["failed"],
             "sequential_solves_per_s_est": seq_rate,
             "sequential_sample": f"first {k} requests solved one at a time on one handle, rate scaled by "
                                  f"the stream's mean N^2 over the sample's",

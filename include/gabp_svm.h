@@ -277,8 +277,10 @@ int32_t gabp_abi_version(void);
  * the union of their tiles, one batched finalize and one batched stop rule.
  * Requests join and leave at step boundaries.  Each request has its own
  * partial sums and fixed reduction order, so its alpha is bitwise the same
- * whether it runs alone or in a mix.  Served plans are materialised K' with
- * stored edge state (kstore / edge_state AUTO or those values).
+ * whether it runs alone or in a mix.  Served plans materialise K'; the edge
+ * state (stored pair records or stateless) is chosen per request by the same
+ * rule as gabp_svm_solve, and requests of the same precision and level count
+ * share a launch.
  * ------------------------------------------------------------------------ */
 typedef struct gabp_server gabp_server;
 
@@ -300,7 +302,7 @@ typedef struct gabp_request_info {
     int32_t status;            /* gabp_status of the solve */
     int32_t reason;            /* gabp_reason */
     int32_t sweeps;
-    int32_t reserved;
+    int32_t stateless_levels;  /* 0: stored pair records; >= 1: stateless levels */
     int64_t N;
     double latency_ms;         /* completion - submission (host clock) */
     double queue_ms;           /* admission - submission */

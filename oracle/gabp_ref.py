@@ -374,6 +374,59 @@ def varah_bound(A, alpha, b):
     return float(np.max(np.abs(np.asarray(b) - A @ alpha)) / gap)
 
 
+def message_contraction(A, sweeps: int):
+    """Largest factor |A_ij| / Q_ij with which a reverse message enters the
+    next message (Algorithm 2 in information form, Q_ij = P~_i - P_ji), per
+    sweep 1 .. sweeps.  The precisions do not depend on b, so only they are
+    iterated; sweep t uses the aggregates of sweep t-1 (sweep 0: zero
+    messages).  Returns a list of floats (inf once some Q_ij <= 0)."""
+    A = np.asarray(A, dtype=np.float64)
+    n = A.shape[0]
+    off = ~np.eye(n, dtype=bool)
+    Aoff = np.where(off, A, 0.0)
+    P = np.zeros((n, n))
+    Pt = np.diag(A).copy()
+    out = []
+    for _ in range(sweeps):
+        Q = np.where(off, Pt[:, None] - P.T, 1.0)
+        if not np.all(Q > 0.0):
+            out.append(np.inf)
+            break
+        out.append(float(np.max(np.abs(Aoff) / Q)) if n > 1 else 0.0)
+        P = np.where(off, -Aoff * Aoff / Q, 0.0)
+        Pt = np.diag(A) + P.sum(axis=0)
+    return out
+
+
+def contraction_bound(A):
+    """A-priori bound on message_contraction over every sweep (not in the
+    paper; it decides how many levels the stateless form unrolls).
+
+    Messages stay non-positive while every Q > 0, so Q_ij >= P~_i and
+    P~_i >= A_ii - sum_k A_ik^2 / min_k P~_k >= A_ii - c_i / m with
+    c_i = max_k |A_ik| * sum_{k != i} |A_ik| and m a lower bound of the
+    previous aggregates.  m* = min_i of the larger root of m^2 - A_ii m + c_i
+    is such a bound for every sweep when every lo_i = A_ii - c_i / m* is at
+    least m* (induction from P~^0 = A_ii).  Then |A_ij| / Q_ij <=
+    max_k |A_ik| / lo_i.  Returns (m*, rho), rho = inf when the bound fails.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    n = A.shape[0]
+    off = ~np.eye(n, dtype=bool)
+    absoff = np.where(off, np.abs(A), 0.0)
+    d = np.diag(A)
+    rowmax = absoff.max(axis=1) if n > 1 else np.zeros(n)
+    c = rowmax * absoff.sum(axis=1)
+    disc = d * d - 4.0 * c
+    if np.any(disc < 0.0) or np.any(d <= 0.0):
+        return 0.0, np.inf
+    mstar = float(np.min(0.5 * (d + np.sqrt(disc))))
+    lo = d - c / mstar
+    if np.any(lo < mstar * (1.0 - 1e-12)):
+        return mstar, np.inf
+    return mstar, float(np.max(rowmax / lo))
+
+
 def box_qp_bruteforce(A, C: float):
     """max 1'h - 1/2 h'Ah s.t. 0 <= h <= C, by enumerating the 3^N
     active sets (lower bound, upper bound, free) and keeping the KKT point

@@ -118,7 +118,8 @@ __device__ inline double rcp_fast(double x) {
     double e = fma(-x, r, 1.0);
     r = fma(r, e, r);
     e = fma(-x, r, 1.0);
-    return fma(r, e, r);
+    r = fma(r, e, r);
+    return __builtin_isinf(x) ? 0.0 : r;    // 1/inf = 0 (Newton would give NaN)
 }
 
 struct TileCoord { int I, J; };
@@ -224,8 +225,9 @@ __device__ inline void wave_lds_sync() {
 //   GK: Gram kind of the recompute;
 //   D: 0 = stored edge state (pair-record planes read and written);
 //      D >= 1 = stateless: the messages of the previous sweep are rebuilt
-//      from the aggregates of up to D earlier sweeps (runtime depth L <= D),
-//      deeper levels in LT = float (FP32/MIXED) or double (FP64);
+//      from the aggregates of the D - 1 earlier sweeps held in the ring (a
+//      slot from before sweep 0 holds P~ = inf, S = 0 and yields exactly zero
+//      messages), lower levels in LT (see below);
 //   FIRST: the stored planes are all zero (sweep 1) and are not read.
 // Work of one tile.  SER (stateless only): the reciprocals of the cavity
 // precisions Q = P~ (1 - e), e = P_reverse / P~, are formed from the
@@ -235,7 +237,7 @@ __device__ inline void wave_lds_sync() {
 // are below the arithmetic's precision.  The deepest level starts from zero
 // messages and costs four multiplications.
 template <class ST, class MT, class AT, int KSRC, int GK, int D, bool FIRST, bool SER>
-__device__ inline void sweep_tile(const SweepArgs& a, int64_t tile) {
+__device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top) {
     DevStatus* st = a.st;
     // lower levels: FP32 storage precision; with the series and up to three
     // levels they run in the top level's type (FP64 FMA issues at the FP32
@@ -267,7 +269,7 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile) {
     __shared__ AT rP[4][TILE], rE[4][TILE];
     __shared__ float kband[KSRC == KSRC_RECOMPUTE ? 4 : 1][KSRC == KSRC_RECOMPUTE ? 32 * 64 : 1];
 
-    const int64_t top = (int64_t)a.slot_top * a.NPAD;
+    const int64_t top = (int64_t)slot_top * a.NPAD;
     {
         const MT p = (MT)HP[top + (int64_t)tc.I * TILE + tid];
         sPt[tid] = SER ? (MT)1 / p : p;
@@ -285,7 +287,7 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile) {
 #pragma unroll
         for (int k = 1; k < D; ++k) {
             if (k < L) {
-                const int64_t base = (int64_t)((a.slot_top - k + a.R) % a.R) * a.NPAD;
+                const int64_t base = (int64_t)((slot_top - k + a.R) % a.R) * a.NPAD;
                 const LT pr = (LT)HP[base + (int64_t)tc.I * TILE + tid];
                 const LT sr = (LT)HS[base + (int64_t)tc.I * TILE + tid];
                 sPtL[k - 1][tid] = SER ? (LT)1 / pr : pr;
@@ -443,7 +445,64 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile) {
 template <class ST, class MT, class AT, int KSRC, int GK, int D, bool FIRST, bool SER>
 __global__ __launch_bounds__(WG) void k_sweep(SweepArgs a) {
     if (a.st->done) return;
-    sweep_tile<ST, MT, AT, KSRC, GK, D, FIRST, SER>(a, blockIdx.x);
+    sweep_tile<ST, MT, AT, KSRC, GK, D, FIRST, SER>(a, blockIdx.x, a.slot_top);
+}
+
+// Served form: one persistent grid walks the union work list of (request,
+// tile) items of the active requests of one group (same precision, edge
+// state and level count).  Each request keeps its own planes or aggregate
+// ring, partial sums and status, so its arithmetic does not depend on the
+// mix; the ring slot of the previous sweep follows from the request's own
+// sweep count (ring slots of the sweeps before sweep 0 hold P~ = inf, S = 0,
+// so a fixed level count is exact from the first sweep).
+template <class ST, class MT, class AT, int D, bool SER>
+__global__ __launch_bounds__(WG) void k_sweep_batched(const ReqDesc* __restrict__ reqs,
+                                                     const uint2* __restrict__ items, int nitems) {
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const uint2 w = items[it];
+        const ReqDesc& rd = reqs[w.x];
+        const DevStatus* st = rd.sw.st;
+        if (st->done) continue;
+        sweep_tile<ST, MT, AT, KSRC_PLANE, GRAM_F32, D, false, SER>(rd.sw, (int64_t)w.y, st->t % rd.sw.R);
+        __syncthreads();
+    }
+}
+
+template <class ST, class MT, class AT, int D, bool SER>
+inline void served_d(const ReqDesc* reqs, const uint2* items, int n, hipStream_t s) {
+    const int g = std::max(1, std::min(n, 2048));
+    hipLaunchKernelGGL((k_sweep_batched<ST, MT, AT, D, SER>), dim3(g), dim3(WG), 0, s, reqs, items, n);
+}
+
+// levels 0: stored pair records; 1..8 stateless (1..6 with series).
+template <class ST, class MT, class AT>
+inline hipError_t served_sweep(int levels, bool ser, const ReqDesc* reqs, const uint2* items, int n,
+                               hipStream_t s) {
+    if (levels == 0) { served_d<ST, MT, AT, 0, false>(reqs, items, n, s); return hipGetLastError(); }
+    if (ser) {
+        switch (levels) {
+            case 1: served_d<ST, MT, AT, 1, true>(reqs, items, n, s); break;
+            case 2: served_d<ST, MT, AT, 2, true>(reqs, items, n, s); break;
+            case 3: served_d<ST, MT, AT, 3, true>(reqs, items, n, s); break;
+            case 4: served_d<ST, MT, AT, 4, true>(reqs, items, n, s); break;
+            case 5: served_d<ST, MT, AT, 5, true>(reqs, items, n, s); break;
+            case 6: served_d<ST, MT, AT, 6, true>(reqs, items, n, s); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    switch (levels) {
+        case 1: served_d<ST, MT, AT, 1, false>(reqs, items, n, s); break;
+        case 2: served_d<ST, MT, AT, 2, false>(reqs, items, n, s); break;
+        case 3: served_d<ST, MT, AT, 3, false>(reqs, items, n, s); break;
+        case 4: served_d<ST, MT, AT, 4, false>(reqs, items, n, s); break;
+        case 5: served_d<ST, MT, AT, 5, false>(reqs, items, n, s); break;
+        case 6: served_d<ST, MT, AT, 6, false>(reqs, items, n, s); break;
+        case 7: served_d<ST, MT, AT, 7, false>(reqs, items, n, s); break;
+        case 8: served_d<ST, MT, AT, 8, false>(reqs, items, n, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 // ---- sweep dispatch: precision x K' source x Gram kind x depth x first x series

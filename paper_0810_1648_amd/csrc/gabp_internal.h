@@ -91,7 +91,8 @@ hipError_t launch_rowsum(const void* Kp, int prec, int ksrc, const Features& F,
                          double* psum, double* pmax, hipStream_t s);
 hipError_t launch_diag(int64_t N, int NB, const double* psum, const double* pmax,
                        const double* kdiag, int mode, double C, double delta, double* Adiag,
-                       double* rowmax, double* scratch_blk, double* scratch_one, hipStream_t s);
+                       double* rowmax, double* rsum, double* scratch_blk, double* scratch_one,
+                       hipStream_t s);
 hipError_t launch_init(int prec, int64_t N, int64_t NPAD, int R, const double* Adiag, const float* y,
                        void* Pt, void* S, double* alpha, DevStatus* st, hipStream_t s);
 
@@ -113,8 +114,9 @@ struct SweepArgs {
     KernelParams kp;
 };
 // Per-request state of the served form: sweep arguments plus what the
-// finalize and stop-rule steps need.  Aggregates live in sw.HP / sw.HS
-// (ring depth 1: stored edge state, materialised K').
+// finalize and stop-rule steps need.  Aggregates live in sw.HP / sw.HS (ring
+// of sw.R slots: 1 for stored pair records, 8 for the stateless form; the
+// slot of a sweep follows from the request's sweep count).
 struct ReqDesc {
     SweepArgs sw;
     int64_t N;
@@ -127,13 +129,20 @@ struct ReqDesc {
     StopRule rule;
     int nblk;
 };
-// One served step for the requests of one precision: batched sweep over the
-// (request, tile) items, batched finalize over the (request, node block)
-// items, batched stop rule for the request slots listed in `slots`, whose
-// statuses are copied to status_out[0..nslots).
-hipError_t launch_served_step(int prec, const ReqDesc* reqs, const uint2* tile_items, int ntile_items,
-                              const uint2* node_items, int nnode_items, const int* slots, int nslots,
-                              DevStatus* status_out, hipStream_t s);
+// One served step for the requests of one group (precision, level count:
+// 0 = stored pair records, >= 1 stateless; series reciprocals): batched sweep
+// over the (request, tile) items, batched finalize over the (request, node
+// block) items, batched stop rule for the request slots listed in `slots`,
+// whose statuses are copied to status_out[0..nslots).
+hipError_t launch_served_step(int prec, int levels, bool ser, const ReqDesc* reqs, const uint2* tile_items,
+                              int ntile_items, const uint2* node_items, int nnode_items, const int* slots,
+                              int nslots, DevStatus* status_out, hipStream_t s);
+hipError_t launch_served_sweep_f32(int levels, bool ser, const ReqDesc* reqs, const uint2* items, int n,
+                                   hipStream_t s);
+hipError_t launch_served_sweep_mixed(int levels, bool ser, const ReqDesc* reqs, const uint2* items, int n,
+                                     hipStream_t s);
+hipError_t launch_served_sweep_f64(int levels, bool ser, const ReqDesc* reqs, const uint2* items, int n,
+                                   hipStream_t s);
 // depth 0 = stored edge state, 1..8 = stateless with up to `depth` levels.
 // levels: 0 = stored edge state, >= 1 = stateless with that many levels in
 // this launch; ser: stateless reciprocals by the series around 1/P~.
@@ -151,8 +160,10 @@ hipError_t launch_finalize(int prec, int64_t N, int NB, const void* partP, const
                            DevStatus* st, hipStream_t s);
 hipError_t launch_status(int nblk, const double* blk_delta, const double* blk_amax,
                          DevStatus* st, double* trace, StopRule rule, hipStream_t s);
-hipError_t launch_rho(int prec, int64_t N, const double* rowmax, const void* Pt, double* blk,
-                      double* one, hipStream_t s);
+// A-priori contraction bound: one[0] = -m* (minus the aggregate lower
+// bound), one[1] = rho (+inf when no bound exists).
+hipError_t launch_rho_bound(int64_t N, const double* Adiag, const double* rowmax, const double* rsum,
+                            double* blk, double* one, hipStream_t s);
 hipError_t launch_kernel_entries(const void* Kp, int prec, int NB, const int64_t* rows,
                                  const int64_t* cols, int64_t n, double* out, hipStream_t s);
 hipError_t launch_predict(const float* Xtr, const float* y, const double* alpha, int64_t N,

@@ -283,7 +283,7 @@ __global__ __launch_bounds__(WG) void k_rowsum(const ST* __restrict__ Kp, Featur
 __global__ void k_diag(int64_t N, int NB, const double* __restrict__ psum,
                        const double* __restrict__ pmax, const double* __restrict__ kdiag, int mode,
                        double C, double delta, double* __restrict__ Adiag,
-                       double* __restrict__ rowmax, double* __restrict__ blk) {
+                       double* __restrict__ rowmax, double* __restrict__ rsum, double* __restrict__ blk) {
     __shared__ double sh4[4];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double wv = -INFINITY;
@@ -305,6 +305,7 @@ __global__ void k_diag(int64_t N, int NB, const double* __restrict__ psum,
         }
         Adiag[i] = a;
         rowmax[i] = mx;
+        rsum[i] = r;
         wv = a - kii;
     }
     if (mode == 3) {
@@ -349,27 +350,20 @@ __global__ void k_init(int64_t N, int64_t NPAD, int R, const double* __restrict_
         S[i] = b;
         alpha[i] = (double)(b / a) * (double)y[i];
         if (!(a > (AT)0) || !isfinite((double)a)) st->bad = 1;
+        // slots of the sweeps before sweep 0 (stateless ring): P~ = +inf and
+        // S = 0 make every message rebuilt from them exactly zero, which is
+        // what the messages of sweep 0 are, so a fixed number of levels is
+        // exact from sweep 1 on
+        for (int r = 1; r < R; ++r) {
+            Pt[(int64_t)r * NPAD + i] = (AT)INFINITY;
+            S[(int64_t)r * NPAD + i] = (AT)0;
+        }
     } else {
         // padding rows are never finalized: set them in every ring slot
         for (int r = 0; r < R; ++r) {
             Pt[(int64_t)r * NPAD + i] = (AT)1;
             S[(int64_t)r * NPAD + i] = (AT)0;
         }
-    }
-}
-
-// Served form: one persistent grid walks the union work list of (request,
-// tile) items of every active request; each request keeps its own planes,
-// partial sums and status, so its arithmetic does not depend on the mix.
-template <class ST, class MT, class AT>
-__global__ __launch_bounds__(WG) void k_sweep_batched(const ReqDesc* __restrict__ reqs,
-                                                     const uint2* __restrict__ items, int nitems) {
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const uint2 w = items[it];
-        const ReqDesc& rd = reqs[w.x];
-        if (rd.sw.st->done) continue;
-        sweep_tile<ST, MT, AT, KSRC_PLANE, GRAM_F32, 0, false, false>(rd.sw, (int64_t)w.y);
-        __syncthreads();
     }
 }
 
@@ -429,10 +423,11 @@ __global__ __launch_bounds__(WG) void k_finalize_batched(const ReqDesc* __restri
         const uint2 w = items[it];
         const ReqDesc& rd = reqs[w.x];
         if (rd.sw.st->done) continue;
+        const int64_t wslot = (int64_t)((rd.sw.st->t + 1) % rd.sw.R) * rd.sw.NPAD;
         finalize_block<AT>((int64_t)w.y, rd.N, rd.sw.NB, static_cast<const AT*>(rd.sw.partP),
                            static_cast<const AT*>(rd.sw.partE), rd.Adiag, rd.y,
-                           static_cast<AT*>(const_cast<void*>(rd.sw.HP)),
-                           static_cast<AT*>(const_cast<void*>(rd.sw.HS)), rd.alpha, rd.blk_delta,
+                           static_cast<AT*>(const_cast<void*>(rd.sw.HP)) + wslot,
+                           static_cast<AT*>(const_cast<void*>(rd.sw.HS)) + wslot, rd.alpha, rd.blk_delta,
                            rd.blk_amax, rd.sw.st);
         __syncthreads();
     }
@@ -490,15 +485,41 @@ __global__ __launch_bounds__(WG) void k_status_batched(const ReqDesc* __restrict
     if (threadIdx.x == 0) out[k] = *st;
 }
 
-// Contraction estimate of the message recursion, max_i rowmax_i / P~_i,
-// per block (the reverse message enters the next one with a factor A_ij / Q).
-template <class AT>
-__global__ void k_rho(int64_t N, const double* __restrict__ rowmax, const AT* __restrict__ Pt,
-                      double* __restrict__ blk) {
+// A-priori bound on the contraction of the message recursion.  With
+// c_i = max_j |A_ij| * sum_{j != i} |A_ij|, every cavity precision satisfies
+// Q_ij >= P~_i^(t-1) (messages are non-positive while Q > 0) and, by
+// induction over sweeps, P~_i^t >= lo_i = A_ii - c_i / m* where
+// m* = min_i (A_ii + sqrt(A_ii^2 - 4 c_i)) / 2 (the larger root of
+// m^2 - A_ii m + c_i).  The induction needs every lo_i >= m* (then m* bounds
+// every aggregate from below, P~^0 = A_ii included); lo_i equals m* at the
+// node that defines it, so the comparison allows a 1e-12 relative rounding
+// margin.  The reverse message enters the next one with a factor
+// |A_ij| / Q_ij <= rowmax_i / lo_i, whose maximum is returned as rho (+inf if
+// the bound does not exist).
+__global__ void k_bound_root(int64_t N, const double* __restrict__ Adiag, const double* __restrict__ rowmax,
+                             const double* __restrict__ rsum, double* __restrict__ blk) {
     __shared__ double sh4[4];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double v = -INFINITY;   // holds -root, so the block max is -(min root)
+    if (i < N) {
+        const double A = Adiag[i], c = rowmax[i] * rsum[i], disc = A * A - 4.0 * c;
+        v = (disc >= 0.0 && A > 0.0) ? -0.5 * (A + sqrt(disc)) : INFINITY;
+    }
+    v = block_max(v, sh4);
+    if (threadIdx.x == 0) blk[blockIdx.x] = v;
+}
+
+__global__ void k_bound_rho(int64_t N, const double* __restrict__ Adiag, const double* __restrict__ rowmax,
+                            const double* __restrict__ rsum, const double* __restrict__ neg_mstar,
+                            double* __restrict__ blk) {
+    __shared__ double sh4[4];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double m = -*neg_mstar;
     double v = 0.0;
-    if (i < N) v = rowmax[i] / (double)Pt[i];
+    if (i < N) {
+        const double lo = Adiag[i] - rowmax[i] * rsum[i] / m;
+        v = (m > 0.0 && lo >= m * (1.0 - 1e-12)) ? rowmax[i] / lo : INFINITY;
+    }
     v = block_max(v, sh4);
     if (threadIdx.x == 0) blk[blockIdx.x] = v;
 }
@@ -640,11 +661,11 @@ hipError_t launch_rowsum(const void* Kp, int prec, int ksrc, const Features& F, 
 }
 
 hipError_t launch_diag(int64_t N, int NB, const double* psum, const double* pmax, const double* kdiag,
-                       int mode, double C, double delta, double* Adiag, double* rowmax,
+                       int mode, double C, double delta, double* Adiag, double* rowmax, double* rsum,
                        double* scratch_blk, double* scratch_one, hipStream_t s) {
     const unsigned nb = grid1(N);
     hipLaunchKernelGGL(k_diag, dim3(nb), dim3(WG), 0, s, N, NB, psum, pmax, kdiag, mode, C, delta, Adiag,
-                       rowmax, scratch_blk);
+                       rowmax, rsum, scratch_blk);
     if (mode == 3) {
         hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(WG), 0, s, (int)nb, scratch_blk, scratch_one);
         hipLaunchKernelGGL(k_diag_shift, dim3(nb), dim3(WG), 0, s, N, kdiag, scratch_one, Adiag);
@@ -676,26 +697,22 @@ hipError_t launch_sweep(int prec, int ksrc, int gram, int levels, bool first, bo
     }
 }
 
-hipError_t launch_served_step(int prec, const ReqDesc* reqs, const uint2* tile_items, int ntile_items,
-                              const uint2* node_items, int nnode_items, const int* slots, int nslots,
-                              DevStatus* status_out, hipStream_t s) {
-    const int gs = std::max(1, std::min(ntile_items, 2048));
-    const int gf = std::max(1, std::min(nnode_items, 2048));
+hipError_t launch_served_step(int prec, int levels, bool ser, const ReqDesc* reqs, const uint2* tile_items,
+                              int ntile_items, const uint2* node_items, int nnode_items, const int* slots,
+                              int nslots, DevStatus* status_out, hipStream_t s) {
+    hipError_t e;
     switch (prec) {
-        case PREC_FP32:
-            hipLaunchKernelGGL((k_sweep_batched<float, float, float>), dim3(gs), dim3(WG), 0, s, reqs, tile_items, ntile_items);
-            hipLaunchKernelGGL(k_finalize_batched<float>, dim3(gf), dim3(WG), 0, s, reqs, node_items, nnode_items);
-            break;
-        case PREC_MIXED:
-            hipLaunchKernelGGL((k_sweep_batched<float, double, double>), dim3(gs), dim3(WG), 0, s, reqs, tile_items, ntile_items);
-            hipLaunchKernelGGL(k_finalize_batched<double>, dim3(gf), dim3(WG), 0, s, reqs, node_items, nnode_items);
-            break;
-        case PREC_FP64:
-            hipLaunchKernelGGL((k_sweep_batched<double, double, double>), dim3(gs), dim3(WG), 0, s, reqs, tile_items, ntile_items);
-            hipLaunchKernelGGL(k_finalize_batched<double>, dim3(gf), dim3(WG), 0, s, reqs, node_items, nnode_items);
-            break;
+        case PREC_FP32: e = launch_served_sweep_f32(levels, ser, reqs, tile_items, ntile_items, s); break;
+        case PREC_MIXED: e = launch_served_sweep_mixed(levels, ser, reqs, tile_items, ntile_items, s); break;
+        case PREC_FP64: e = launch_served_sweep_f64(levels, ser, reqs, tile_items, ntile_items, s); break;
         default: return hipErrorInvalidValue;
     }
+    if (e != hipSuccess) return e;
+    const int gf = std::max(1, std::min(nnode_items, 2048));
+    if (prec == PREC_FP32)
+        hipLaunchKernelGGL(k_finalize_batched<float>, dim3(gf), dim3(WG), 0, s, reqs, node_items, nnode_items);
+    else
+        hipLaunchKernelGGL(k_finalize_batched<double>, dim3(gf), dim3(WG), 0, s, reqs, node_items, nnode_items);
     hipLaunchKernelGGL(k_status_batched, dim3(std::max(1, nslots)), dim3(WG), 0, s, reqs, slots, nslots, status_out);
     return hipGetLastError();
 }
@@ -721,14 +738,13 @@ hipError_t launch_status(int nblk, const double* blk_delta, const double* blk_am
     return hipGetLastError();
 }
 
-hipError_t launch_rho(int prec, int64_t N, const double* rowmax, const void* Pt, double* blk,
-                      double* one, hipStream_t s) {
+hipError_t launch_rho_bound(int64_t N, const double* Adiag, const double* rowmax, const double* rsum,
+                            double* blk, double* one, hipStream_t s) {
     const unsigned nb = grid1(N);
-    if (prec == PREC_FP32)
-        hipLaunchKernelGGL(k_rho<float>, dim3(nb), dim3(WG), 0, s, N, rowmax, (const float*)Pt, blk);
-    else
-        hipLaunchKernelGGL(k_rho<double>, dim3(nb), dim3(WG), 0, s, N, rowmax, (const double*)Pt, blk);
+    hipLaunchKernelGGL(k_bound_root, dim3(nb), dim3(WG), 0, s, N, Adiag, rowmax, rsum, blk);
     hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(WG), 0, s, (int)nb, blk, one);
+    hipLaunchKernelGGL(k_bound_rho, dim3(nb), dim3(WG), 0, s, N, Adiag, rowmax, rsum, one, blk);
+    hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(WG), 0, s, (int)nb, blk, one + 1);
     return hipGetLastError();
 }
 

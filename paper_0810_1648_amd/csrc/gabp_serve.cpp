@@ -114,7 +114,7 @@ private:
 // Device buffers of one request, in a fixed order.
 enum Buf {
     B_TILES, B_KP, B_PF, B_PB, B_EF, B_EB, B_PARTP, B_PARTE, B_X, B_Y, B_MEAN, B_X32, B_XHI, B_XLO,
-    B_XLO2, B_X64, B_NRM, B_KDIAG, B_ADIAG, B_ROWMAX, B_PT, B_S, B_ALPHA, B_BLK1, B_BLK2, B_ONE,
+    B_XLO2, B_X64, B_NRM, B_KDIAG, B_ADIAG, B_ROWMAX, B_RSUM, B_PT, B_S, B_ALPHA, B_BLK1, B_BLK2, B_ONE,
     B_STATUS, B_TRACE, B_COUNT
 };
 
@@ -135,7 +135,12 @@ struct Req {
     size_t footprint = 0;
     int slot = -1;
     int bypassed = 0;
+    int levels = 0;      // 0: stored pair records; >= 1: stateless levels
+    bool ser = false;    // stateless reciprocals by the series around 1/P~
+    double rho = 0.0;    // contraction bound
 };
+
+constexpr int kRing = 8;   // aggregate ring slots (stateless form)
 
 void plan_sizes(Req& r) {
     const size_t st = (r.prec == PREC_FP64) ? 8 : 4;
@@ -155,8 +160,8 @@ void plan_sizes(Req& r) {
     if (r.gram == GRAM_BF16X6) z[B_XLO2] = fe * 2;
     if (r.gram == GRAM_F64) z[B_X64] = fe * 8;
     z[B_NRM] = (size_t)r.NPAD * 4;
-    z[B_KDIAG] = z[B_ADIAG] = z[B_ROWMAX] = z[B_ALPHA] = (size_t)r.N * 8;
-    z[B_PT] = z[B_S] = (size_t)r.NPAD * 8;
+    z[B_KDIAG] = z[B_ADIAG] = z[B_ROWMAX] = z[B_RSUM] = z[B_ALPHA] = (size_t)r.N * 8;
+    z[B_PT] = z[B_S] = (size_t)kRing * r.NPAD * 8;
     z[B_BLK1] = z[B_BLK2] = (size_t)(r.NPAD / WG + 1) * 8;
     z[B_ONE] = 64;
     z[B_STATUS] = sizeof(DevStatus);
@@ -186,13 +191,17 @@ struct gabp_server {
     ReqDesc* h_reqs = nullptr;
     DevStatus* d_stat = nullptr;
     DevStatus* h_stat = nullptr;
+    // launch groups: requests sharing precision, level count and series flag
     struct Group {
+        int prec = 0, levels = 0;
+        bool ser = false;
         uint2* d_tiles = nullptr; uint2* h_tiles = nullptr; size_t cap_tiles = 0;
         uint2* d_nodes = nullptr; uint2* h_nodes = nullptr; size_t cap_nodes = 0;
         int* d_slots = nullptr; int* h_slots = nullptr;
         int ntiles = 0, nnodes = 0, nslots = 0;
         std::vector<int> slot_list;
-    } groups[3];
+    };
+    std::map<int, Group> groups;
     // statistics
     std::vector<double> lat_ms, queue_ms;
     int64_t submitted = 0, completed = 0, failed = 0, steps = 0, active_sum = 0, max_active_seen = 0;
@@ -255,10 +264,40 @@ hipError_t setup_request(gabp_server* S, Req& r) {
                      (double*)P(B_PARTP), (double*)P(B_PARTE), s));
     CK(launch_diag(r.N, r.NB, (double*)P(B_PARTP), (double*)P(B_PARTE), (double*)P(B_KDIAG),
                    r.p.diag_mode, r.p.C, r.p.diag_delta, (double*)P(B_ADIAG), (double*)P(B_ROWMAX),
-                   (double*)P(B_BLK1), (double*)P(B_ONE), s));
-    CK(launch_init(r.prec, r.N, r.NPAD, 1, (double*)P(B_ADIAG), (float*)P(B_Y), P(B_PT), P(B_S),
+                   (double*)P(B_RSUM), (double*)P(B_BLK1), (double*)P(B_ONE), s));
+    // edge state from the contraction bound (same rule as a single solve)
+    CK(launch_rho_bound(r.N, (double*)P(B_ADIAG), (double*)P(B_ROWMAX), (double*)P(B_RSUM),
+                        (double*)P(B_BLK1), (double*)P(B_ONE), s));
+    double hb[2] = {0.0, 0.0};
+    CK(hipMemcpyAsync(hb, P(B_ONE), 16, hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    r.rho = hb[1];
+    const double eps = (r.prec == PREC_FP32) ? std::ldexp(1.0, -24)
+                     : (r.prec == PREC_MIXED) ? std::ldexp(1.0, -30) : std::ldexp(1.0, -50);
+    const double rr = 1.25 * r.rho;
+    int dneed = 9;
+    if (rr == 0.0) dneed = 1;
+    else if (rr < 1.0) dneed = std::max(1, (int)std::ceil(std::log(eps) / std::log(rr)));
+    bool stateless = false;
+    if (r.p.edge_state == GABP_EDGE_STATELESS) stateless = true;
+    else if (r.p.edge_state == GABP_EDGE_AUTO) stateless = dneed <= 8;
+    r.levels = stateless ? (r.p.stateless_depth > 0 ? r.p.stateless_depth : std::min(dneed, 8)) : 0;
+    const double eps_low = (r.prec == PREC_FP64) ? std::ldexp(1.0, -52) : std::ldexp(1.0, -24);
+    const double eps_top = (r.prec == PREC_FP32) ? std::ldexp(1.0, -24) : std::ldexp(1.0, -52);
+    r.ser = stateless && r.levels <= 6 && rr < 0.25 && std::pow(rr, 5) <= eps_low && std::pow(rr, 6) <= eps_top;
+    if (stateless) {
+        // the pair-record planes are not needed: give them back to the arena
+        const std::vector<int> planes = {B_PF, B_PB, B_EF, B_EB};
+        std::vector<size_t> sz, of;
+        for (int b : planes) { sz.push_back(r.sizes[b]); of.push_back(r.offs[b]); r.offs[b] = SIZE_MAX; }
+        S->arena.release_all(sz, of);
+        for (int b : planes) { r.footprint -= align_up(r.sizes[b]); r.sizes[b] = 0; }
+    }
+    const int R = stateless ? kRing : 1;
+    CK(launch_init(r.prec, r.N, r.NPAD, R, (double*)P(B_ADIAG), (float*)P(B_Y), P(B_PT), P(B_S),
                    (double*)P(B_ALPHA), (DevStatus*)P(B_STATUS), s));
-    for (int b : {B_PF, B_PB, B_EF, B_EB}) CK(hipMemsetAsync(P(b), 0, r.sizes[b], s));
+    if (!stateless)
+        for (int b : {B_PF, B_PB, B_EF, B_EB}) CK(hipMemsetAsync(P(b), 0, r.sizes[b], s));
     ReqDesc& d = S->h_reqs[r.slot];
     d = ReqDesc{};
     d.sw.tiles = (uint32_t*)P(B_TILES);
@@ -268,9 +307,9 @@ hipError_t setup_request(gabp_server* S, Req& r) {
     d.sw.Pf = P(B_PF); d.sw.Pb = P(B_PB); d.sw.Ef = P(B_EF); d.sw.Eb = P(B_EB);
     d.sw.HP = P(B_PT); d.sw.HS = P(B_S);
     d.sw.NPAD = r.NPAD;
-    d.sw.R = 1;
+    d.sw.R = R;
     d.sw.slot_top = 0;
-    d.sw.levels = 0;
+    d.sw.levels = r.levels;
     d.sw.partP = P(B_PARTP); d.sw.partE = P(B_PARTE);
     d.sw.st = (DevStatus*)P(B_STATUS);
     d.sw.F = F;
@@ -289,20 +328,32 @@ hipError_t setup_request(gabp_server* S, Req& r) {
     return hipSuccess;
 }
 
-// Rebuilds the per-precision work lists from the active slots.
+inline int group_key(const Req& r) { return r.prec * 100 + (r.ser ? 10 : 0) + r.levels; }
+
+// Rebuilds the per-group work lists from the active slots.
 hipError_t rebuild_lists(gabp_server* S) {
     hipError_t e;
-    int stat_base = 0;
-    for (int g = 0; g < 3; ++g) {
-        auto& G = S->groups[g];
-        G.slot_list.clear();
+    for (auto& kv : S->groups) kv.second.slot_list.clear();
+    for (size_t k = 0; k < S->slots.size(); ++k) {
+        Req* r = S->slots[k];
+        if (!r) continue;
+        auto& G = S->groups[group_key(*r)];
+        G.prec = r->prec;
+        G.levels = r->levels;
+        G.ser = r->ser;
+        G.slot_list.push_back((int)k);
+    }
+    for (auto& kv : S->groups) {
+        auto& G = kv.second;
+        if (!G.d_slots) {
+            const size_t A = S->slots.size();
+            if ((e = hipMalloc((void**)&G.d_slots, A * sizeof(int))) != hipSuccess) return e;
+            if ((e = hipHostMalloc((void**)&G.h_slots, A * sizeof(int), hipHostMallocDefault)) != hipSuccess) return e;
+        }
         size_t nt = 0, nn = 0;
-        for (size_t k = 0; k < S->slots.size(); ++k) {
-            Req* r = S->slots[k];
-            if (!r || r->prec != g) continue;
-            G.slot_list.push_back((int)k);
-            nt += (size_t)r->nt;
-            nn += (size_t)((r->N + WG - 1) / WG);
+        for (int k : G.slot_list) {
+            nt += (size_t)S->slots[k]->nt;
+            nn += (size_t)((S->slots[k]->N + WG - 1) / WG);
         }
         if ((e = grow(G.d_tiles, G.h_tiles, G.cap_tiles, std::max<size_t>(nt, 1))) != hipSuccess) return e;
         if ((e = grow(G.d_nodes, G.h_nodes, G.cap_nodes, std::max<size_t>(nn, 1))) != hipSuccess) return e;
@@ -322,9 +373,7 @@ hipError_t rebuild_lists(gabp_server* S) {
             if ((e = hipMemcpyAsync(G.d_nodes, G.h_nodes, in * sizeof(uint2), hipMemcpyHostToDevice, S->stream)) != hipSuccess) return e;
             if ((e = hipMemcpyAsync(G.d_slots, G.h_slots, G.slot_list.size() * sizeof(int), hipMemcpyHostToDevice, S->stream)) != hipSuccess) return e;
         }
-        stat_base += G.nslots;
     }
-    (void)stat_base;
     return hipSuccess;
 }
 
@@ -416,16 +465,16 @@ void worker_loop(gabp_server* S) {
             lists_dirty = false;
         }
         int nactive = 0;
-        for (int g = 0; g < 3; ++g) nactive += S->groups[g].nslots;
+        for (auto& kv : S->groups) nactive += kv.second.nslots;
         if (nactive == 0) continue;
         hipError_t e = hipSuccess;
         for (int k = 0; k < S->p.steps_per_poll && e == hipSuccess; ++k) {
             int base = 0;
-            for (int g = 0; g < 3 && e == hipSuccess; ++g) {
-                auto& G = S->groups[g];
-                if (G.nslots)
-                    e = launch_served_step(g, S->d_reqs, G.d_tiles, G.ntiles, G.d_nodes, G.nnodes, G.d_slots,
-                                           G.nslots, S->d_stat + base, S->stream);
+            for (auto& kv : S->groups) {
+                auto& G = kv.second;
+                if (G.nslots && e == hipSuccess)
+                    e = launch_served_step(G.prec, G.levels, G.ser, S->d_reqs, G.d_tiles, G.ntiles, G.d_nodes,
+                                           G.nnodes, G.d_slots, G.nslots, S->d_stat + base, S->stream);
                 base += G.nslots;
             }
         }
@@ -436,8 +485,8 @@ void worker_loop(gabp_server* S) {
         // retire finished requests
         std::vector<std::pair<Req*, DevStatus>> done;
         int base = 0;
-        for (int g = 0; g < 3; ++g) {
-            auto& G = S->groups[g];
+        for (auto& kv : S->groups) {
+            auto& G = kv.second;
             for (int q = 0; q < G.nslots; ++q) {
                 const DevStatus& ds = S->h_stat[base + q];
                 if (ds.done) done.emplace_back(S->slots[G.slot_list[q]], ds);
@@ -523,10 +572,7 @@ gabp_status gabp_server_create(const gabp_server_params* params, gabp_server** o
     ok = ok && hipHostMalloc((void**)&S->h_reqs, (size_t)A * sizeof(ReqDesc), hipHostMallocDefault) == hipSuccess;
     ok = ok && hipMalloc((void**)&S->d_stat, (size_t)A * sizeof(DevStatus)) == hipSuccess;
     ok = ok && hipHostMalloc((void**)&S->h_stat, (size_t)A * sizeof(DevStatus), hipHostMallocDefault) == hipSuccess;
-    for (int g = 0; g < 3 && ok; ++g) {
-        ok = ok && hipMalloc((void**)&S->groups[g].d_slots, (size_t)A * sizeof(int)) == hipSuccess;
-        ok = ok && hipHostMalloc((void**)&S->groups[g].h_slots, (size_t)A * sizeof(int), hipHostMallocDefault) == hipSuccess;
-    }
+
     if (!ok) {
         (void)hipGetLastError();
         gabp_server_destroy(S);
@@ -544,7 +590,7 @@ gabp_status gabp_server_submit(gabp_server* S, const float* X, const float* y, i
     std::string why;
     if (check_params(params, why) != GABP_OK) return GABP_E_INVALID;
     if (params->kernel != GABP_KERNEL_RBF) return GABP_E_INVALID;
-    if (params->kstore == GABP_KSTORE_RECOMPUTE || params->edge_state == GABP_EDGE_STATELESS) return GABP_E_INVALID;
+    if (params->kstore == GABP_KSTORE_RECOMPUTE) return GABP_E_INVALID;
     if (N > (int64_t)TILE * 65535) return GABP_E_INVALID;
     for (int64_t k = 0; k < N * m; ++k)
         if (!std::isfinite(X[k])) return GABP_E_INVALID;
@@ -617,7 +663,7 @@ gabp_status gabp_server_result(gabp_server* S, uint64_t ticket, double* alpha, s
         info->status = r->status;
         info->reason = r->reason;
         info->sweeps = r->sweeps;
-        info->reserved = 0;
+        info->stateless_levels = r->levels;
         info->N = r->N;
         info->latency_ms = (r->t_done - r->t_submit) * 1e3;
         info->queue_ms = (r->t_admit - r->t_submit) * 1e3;
@@ -667,7 +713,8 @@ void gabp_server_destroy(gabp_server* S) {
     if (S->worker.joinable()) S->worker.join();
     (void)hipSetDevice(S->p.device);
     if (S->stream) (void)hipStreamSynchronize(S->stream);
-    for (auto& G : S->groups) {
+    for (auto& kv : S->groups) {
+        auto& G = kv.second;
         if (G.d_tiles) (void)hipFree(G.d_tiles);
         if (G.h_tiles) (void)hipHostFree(G.h_tiles);
         if (G.d_nodes) (void)hipFree(G.d_nodes);

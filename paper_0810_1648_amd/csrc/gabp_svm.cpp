@@ -93,12 +93,12 @@ struct gabp_svm {
     gabp_timings tm{};
     gabp_plan plan{};
     // device memory owned by the handle
-    DevBuf tiles, Kp, Pf, Pb, Ef, Eb, partP, partE, Xin, yd, mean, xs32, xhi, xlo, xlo2, x64, nrm, kdiag, rowmax,
+    DevBuf tiles, Kp, Pf, Pb, Ef, Eb, partP, partE, Xin, yd, mean, xs32, xhi, xlo, xlo2, x64, nrm, kdiag, rowmax, rsum,
         Adiag, Pt, S, alpha_d, blk1, blk2, one, status_d, trace_d, flag, tmp, Kin, q_rows, q_cols,
         q_out;
 
-    DevBuf* all[35] = {&tiles, &Kp, &Pf, &Pb, &Ef, &Eb, &partP, &partE, &Xin, &yd, &mean,
-                       &xs32, &xhi, &xlo, &xlo2, &x64, &nrm, &kdiag, &rowmax, &Adiag, &Pt, &S, &alpha_d,
+    DevBuf* all[36] = {&tiles, &Kp, &Pf, &Pb, &Ef, &Eb, &partP, &partE, &Xin, &yd, &mean,
+                       &xs32, &xhi, &xlo, &xlo2, &x64, &nrm, &kdiag, &rowmax, &rsum, &Adiag, &Pt, &S, &alpha_d,
                        &blk1, &blk2, &one, &status_d, &trace_d, &flag, &tmp, &Kin, &q_rows,
                        &q_cols, &q_out, nullptr};
     size_t held() const {
@@ -232,10 +232,9 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
         return fail(h, GABP_E_NOMEM, msg);
     }
     if (need > free_b) h->release_all();
-    // AUTO edge state with room for stored planes: sweep 1 runs in stateless
-    // form to measure the contraction; the solve stays stateless when the
-    // truncation at depth <= 8 is below the path's own rounding, and
-    // restarts with stored pair records otherwise.
+    // AUTO edge state with room for stored planes: the choice between stored
+    // and stateless waits for the contraction bound computed after the
+    // diagonal weighting; the planes are allocated only if stored wins.
     const bool probe = stored && p.edge_state == GABP_EDGE_AUTO;
     const int R = (stored && !probe) ? 1 : 8;
     const int ksrc = kmat ? KSRC_PLANE : KSRC_RECOMPUTE;
@@ -250,6 +249,7 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     A(h->partP, part); A(h->partE, part);
     A(h->yd, (size_t)N * 4);
     A(h->kdiag, (size_t)N * 8); A(h->Adiag, (size_t)N * 8); A(h->rowmax, (size_t)N * 8);
+    A(h->rsum, (size_t)N * 8);
     A(h->Pt, (size_t)R * NPAD * 8); A(h->S, (size_t)R * NPAD * 8);
     A(h->alpha_d, (size_t)N * 8); A(h->tmp, (size_t)NPAD * 8);
     A(h->blk1, (size_t)(NPAD / WG + 1) * 8); A(h->blk2, (size_t)(NPAD / WG + 1) * 8);
@@ -340,14 +340,56 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
                             h->partP.as<double>(), h->partE.as<double>(), s));
     HIPCHK(h, launch_diag(N, NB, h->partP.as<double>(), h->partE.as<double>(), h->kdiag.as<double>(),
                           p.diag_mode, p.C, p.diag_delta, h->Adiag.as<double>(), h->rowmax.as<double>(),
-                          h->blk1.as<double>(), h->one.as<double>(), s));
+                          h->rsum.as<double>(), h->blk1.as<double>(), h->one.as<double>(), s));
     DevStatus* st = h->status_d.as<DevStatus>();
     HIPCHK(h, launch_init(prec, N, NPAD, R, h->Adiag.as<double>(), h->yd.as<float>(), h->Pt.p, h->S.p,
                           h->alpha_d.as<double>(), st, s));
     HIPCHK(h, hipEventRecord(ev[3], s));
 
+    // ---- plan of the edge state from the contraction bound
+    // rho bounds |A_ij| / Q_ij, the factor with which a reverse message enters
+    // the next one, so unrolling `depth` levels truncates the recursion by
+    // about rho^depth.  Stateless depth: requested, or the smallest with
+    // (1.25 rho)^depth below the path's message precision: 2^-24 (FP32),
+    // 2^-30 (MIXED, FP32-stored messages), 2^-50 (FP64), at most 8.
+    double rho = INFINITY;
+    {
+        double hb[2] = {0.0, 0.0};
+        HIPCHK(h, launch_rho_bound(N, h->Adiag.as<double>(), h->rowmax.as<double>(), h->rsum.as<double>(),
+                                   h->blk1.as<double>(), h->one.as<double>(), s));
+        HIPCHK(h, hipMemcpyAsync(hb, h->one.p, 16, hipMemcpyDeviceToHost, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+        rho = hb[1];
+    }
+    const double eps = (prec == PREC_FP32) ? std::ldexp(1.0, -24)
+                     : (prec == PREC_MIXED) ? std::ldexp(1.0, -30) : std::ldexp(1.0, -50);
+    const double rr = 1.25 * rho;
+    int dneed = 9;
+    if (rr == 0.0) dneed = 1;
+    else if (rr < 1.0) dneed = std::max(1, (int)std::ceil(std::log(eps) / std::log(rr)));
+    bool cur_stored = stored;
+    int depth = 0;
+    if (probe) cur_stored = dneed > 8;
+    if (!cur_stored) depth = (p.stateless_depth > 0) ? p.stateless_depth : std::min(dneed, 8);
+    // Series reciprocals: |e| <= rr^2, so the one-term lower levels err by
+    // rr^4 (entering the top level scaled by rr) and the two-term top level by
+    // rr^6; both must stay below the precision of their arithmetic.
+    const double eps_low = (prec == PREC_FP64) ? std::ldexp(1.0, -52) : std::ldexp(1.0, -24);
+    const double eps_top = (prec == PREC_FP32) ? std::ldexp(1.0, -24) : std::ldexp(1.0, -52);
+    const bool ser = !cur_stored && depth <= 6 && rr < 0.25 && std::pow(rr, 5) <= eps_low &&
+                     std::pow(rr, 6) <= eps_top;
+    if (probe && cur_stored) {
+        if (h->Pf.ensure(plane) != hipSuccess || h->Pb.ensure(plane) != hipSuccess ||
+            h->Ef.ensure(plane) != hipSuccess || h->Eb.ensure(plane) != hipSuccess) {
+            h->release_all();
+            return fail(h, GABP_E_NOMEM, "device allocation of the pair-record planes failed");
+        }
+    }
+    if (!cur_stored) { h->Pf.release(); h->Pb.release(); h->Ef.release(); h->Eb.release(); }
+
     // ---- sweeps
     const size_t agg_bytes = (prec == PREC_FP32) ? 4 : 8;
+    const int Rr = cur_stored ? 1 : R;
     SweepArgs sa{};
     sa.tiles = h->tiles.as<uint32_t>();
     sa.ntiles = nt;
@@ -356,99 +398,46 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     sa.Pf = h->Pf.p; sa.Pb = h->Pb.p; sa.Ef = h->Ef.p; sa.Eb = h->Eb.p;
     sa.HP = h->Pt.p; sa.HS = h->S.p;
     sa.NPAD = NPAD;
+    sa.R = Rr;
     sa.partP = h->partP.p; sa.partE = h->partE.p;
     sa.st = st;
     sa.F = F;
     sa.kp = kp;
     StopRule rule{p.tol_abs, p.tol_rel, p.stagnation_rel, p.max_sweeps, p.stagnation_window};
     const int nblk = (int)((N + WG - 1) / WG);
-    // Stateless depth: requested, or chosen after sweep 1 from the
-    // contraction estimate rho = max_i max_j |K'_ij| / P~_i (with a 1.25
-    // margin) so that rho^depth is below the path's message precision:
-    // 2^-24 (FP32), 2^-30 (MIXED, FP32-stored messages), 2^-50 (FP64).
-    const double eps = (prec == PREC_FP32) ? std::ldexp(1.0, -24)
-                     : (prec == PREC_MIXED) ? std::ldexp(1.0, -30) : std::ldexp(1.0, -50);
-    bool cur_stored = stored && !probe;
-    int depth = cur_stored ? 0 : (p.stateless_depth > 0 ? p.stateless_depth : 1);
-    bool choose_depth = !cur_stored;   // rho is measured after sweep 1 of every stateless plan
-    bool ser = false;
-    double rho = 0.0;
     DevStatus hs{};
     double sweep_kernel_ms = 0.0;
     int64_t launches = 0;
-    for (int pass = 0; pass < 2; ++pass) {
-        bool restart = false;
-        int polled = 0;
-        const int Rr = cur_stored ? 1 : R;
-        sweep_kernel_ms = 0.0;
-        launches = 0;
-        for (int t = 0; t < p.max_sweeps; ++t) {
-            const int slot = t % ce;
-            sa.R = Rr;
-            sa.slot_top = t % Rr;
-            sa.levels = cur_stored ? 0 : std::min(t + 1, depth);
-            if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot], s));
-            HIPCHK(h, launch_sweep(prec, ksrc, gram, sa.levels, t == 0, ser, sa, s));
-            if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot + 1], s));
-            char* wP = static_cast<char*>(h->Pt.p) + (size_t)((t + 1) % Rr) * NPAD * agg_bytes;
-            char* wS = static_cast<char*>(h->S.p) + (size_t)((t + 1) % Rr) * NPAD * agg_bytes;
-            HIPCHK(h, launch_finalize(prec, N, NB, h->partP.p, h->partE.p, h->Adiag.as<double>(),
-                                      h->yd.as<float>(), wP, wS, h->alpha_d.as<double>(),
-                                      h->blk1.as<double>(), h->blk2.as<double>(), st, s));
-            HIPCHK(h, launch_status(nblk, h->blk1.as<double>(), h->blk2.as<double>(), st,
-                                    h->trace_d.as<double>(), rule, s));
-            if (choose_depth && t == 0) {
-                HIPCHK(h, launch_rho(prec, N, h->rowmax.as<double>(), wP, h->blk1.as<double>(),
-                                     h->one.as<double>(), s));
-                HIPCHK(h, hipMemcpyAsync(&rho, h->one.p, 8, hipMemcpyDeviceToHost, s));
-                HIPCHK(h, hipStreamSynchronize(s));
-                const double r = 1.25 * rho;
-                int d = 9;
-                if (!(r > 0.0)) d = 1;
-                else if (r < 1.0) d = std::max(1, (int)std::ceil(std::log(eps) / std::log(r)));
-                choose_depth = false;
-                if (p.stateless_depth > 0) {
-                    depth = p.stateless_depth;
-                } else if (d <= 8) {
-                    depth = d;
-                } else if (probe) {
-                    restart = true;   // truncation too coarse: use stored pair records
-                    break;
-                } else {
-                    depth = 8;        // stateless was requested: deepest unroll
+    int polled = 0;
+    for (int t = 0; t < p.max_sweeps; ++t) {
+        const int slot = t % ce;
+        sa.slot_top = t % Rr;
+        // every stateless sweep unrolls `depth` levels: the ring slots before
+        // sweep 0 hold P~ = inf, S = 0, whose messages are exactly zero
+        sa.levels = cur_stored ? 0 : depth;
+        if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot], s));
+        HIPCHK(h, launch_sweep(prec, ksrc, gram, sa.levels, t == 0, ser, sa, s));
+        if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot + 1], s));
+        char* wP = static_cast<char*>(h->Pt.p) + (size_t)((t + 1) % Rr) * NPAD * agg_bytes;
+        char* wS = static_cast<char*>(h->S.p) + (size_t)((t + 1) % Rr) * NPAD * agg_bytes;
+        HIPCHK(h, launch_finalize(prec, N, NB, h->partP.p, h->partE.p, h->Adiag.as<double>(),
+                                  h->yd.as<float>(), wP, wS, h->alpha_d.as<double>(),
+                                  h->blk1.as<double>(), h->blk2.as<double>(), st, s));
+        HIPCHK(h, launch_status(nblk, h->blk1.as<double>(), h->blk2.as<double>(), st,
+                                h->trace_d.as<double>(), rule, s));
+        if ((t + 1) % ce == 0 || t + 1 == p.max_sweeps) {
+            HIPCHK(h, hipMemcpyAsync(&hs, st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+            HIPCHK(h, hipStreamSynchronize(s));
+            if (p.time_sweeps) {
+                for (int u = polled; u <= t; ++u) {
+                    if (u >= hs.t) break;
+                    sweep_kernel_ms += elapsed(sev[2 * (u % ce)], sev[2 * (u % ce) + 1]);
+                    ++launches;
                 }
-                // Series reciprocals: |e| <= r^2, so the one-term lower levels err by
-                // r^4 (entering the top level scaled by r) and the two-term top level
-                // by r^6; both must stay below the precision of their arithmetic.
-                const double eps_low = (prec == PREC_FP64) ? std::ldexp(1.0, -52) : std::ldexp(1.0, -24);
-                const double eps_top = (prec == PREC_FP32) ? std::ldexp(1.0, -24) : std::ldexp(1.0, -52);
-                ser = depth <= 6 && r < 0.25 && std::pow(r, 5) <= eps_low && std::pow(r, 6) <= eps_top;
             }
-            if ((t + 1) % ce == 0 || t + 1 == p.max_sweeps) {
-                HIPCHK(h, hipMemcpyAsync(&hs, st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
-                HIPCHK(h, hipStreamSynchronize(s));
-                if (p.time_sweeps) {
-                    for (int u = polled; u <= t; ++u) {
-                        if (u >= hs.t) break;
-                        sweep_kernel_ms += elapsed(sev[2 * (u % ce)], sev[2 * (u % ce) + 1]);
-                        ++launches;
-                    }
-                }
-                polled = t + 1;
-                if (hs.done) break;
-            }
+            polled = t + 1;
+            if (hs.done) break;
         }
-        if (!restart) break;
-        cur_stored = true;
-        depth = 0;
-        if (h->Pf.ensure(plane) != hipSuccess || h->Pb.ensure(plane) != hipSuccess ||
-            h->Ef.ensure(plane) != hipSuccess || h->Eb.ensure(plane) != hipSuccess) {
-            h->release_all();
-            return fail(h, GABP_E_NOMEM, "device allocation of the pair-record planes failed");
-        }
-        sa.Pf = h->Pf.p; sa.Pb = h->Pb.p; sa.Ef = h->Ef.p; sa.Eb = h->Eb.p;
-        HIPCHK(h, launch_init(prec, N, NPAD, R, h->Adiag.as<double>(), h->yd.as<float>(), h->Pt.p, h->S.p,
-                              h->alpha_d.as<double>(), st, s));
     }
     stored = cur_stored;
     HIPCHK(h, hipEventRecord(ev[4], s));

@@ -12,4 +12,9 @@ hipError_t launch_sweep_f32(int ksrc, int gram, int levels, bool first, bool ser
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_served_sweep_f32(int levels, bool ser, const ReqDesc* reqs, const uint2* items, int n,
+                                     hipStream_t s) {
+    return served_sweep<float, float, float>(levels, ser, reqs, items, n, s);
+}
+
 }  // namespace gabp

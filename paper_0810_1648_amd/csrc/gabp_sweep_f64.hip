@@ -12,4 +12,9 @@ hipError_t launch_sweep_f64(int ksrc, int gram, int levels, bool first, bool ser
     return hipErrorInvalidValue;   // FP64 K' is always materialised
 }
 
+hipError_t launch_served_sweep_f64(int levels, bool ser, const ReqDesc* reqs, const uint2* items, int n,
+                                     hipStream_t s) {
+    return served_sweep<double, double, double>(levels, ser, reqs, items, n, s);
+}
+
 }  // namespace gabp

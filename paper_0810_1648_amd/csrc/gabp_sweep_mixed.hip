@@ -16,4 +16,9 @@ hipError_t launch_sweep_mixed(int ksrc, int gram, int levels, bool first, bool s
     }
 }
 
+hipError_t launch_served_sweep_mixed(int levels, bool ser, const ReqDesc* reqs, const uint2* items, int n,
+                                     hipStream_t s) {
+    return served_sweep<float, double, double>(levels, ser, reqs, items, n, s);
+}
+
 }  // namespace gabp

@@ -313,11 +313,11 @@ class ServerParams(ct.Structure):
 
 class RequestInfo(ct.Structure):
     _fields_ = [("status", ct.c_int32), ("reason", ct.c_int32), ("sweeps", ct.c_int32),
-                ("reserved", ct.c_int32), ("N", ct.c_int64), ("latency_ms", ct.c_double),
+                ("stateless_levels", ct.c_int32), ("N", ct.c_int64), ("latency_ms", ct.c_double),
                 ("queue_ms", ct.c_double), ("device_bytes", ct.c_double)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
         d["reason"] = REASON.get(d["reason"], d["reason"])
         return d
 

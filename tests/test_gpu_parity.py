@@ -324,3 +324,22 @@ def test_stateless_series_reciprocals_match_oracle(torch):
         print(f"series stateless {prec}: depth {s.plan()['stateless_depth']} rho {s.plan()['stateless_rho']:.2e} "
               f"sweeps {s.sweeps()} rel err vs Cholesky {err:.2e}")
         assert st == gabp.OK and err <= TOL
+
+
+@pytest.mark.parametrize("gamma", [2e-3, 1.0 / 8, 1.0])
+def test_contraction_bound_matches_oracle(torch, gamma):
+    """The plan's contraction bound (computed on the device from the weighted
+    diagonal, the row maxima and the row sums of K') equals the oracle's
+    bound on the same system, and bounds the contraction the sweeps reach."""
+    X, y = inputs.blobs(700, 8, 93)
+    wl = inputs.Workload("blobs-rho", X, y, gamma=gamma, C=1.0, lam=1.0 / 700, precision="fp64",
+                         tol_rel=1e-9)
+    A, b = R.svm_system(wl.X, wl.y, wl.gamma, wl.C, wl.lam)
+    mstar, rho_ref = R.contraction_bound(A)
+    reached = max(R.message_contraction(A, 30))
+    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-5)):
+        s, st = run(torch, wl, precision=prec, kstore="materialise")
+        rho = s.plan()["stateless_rho"]
+        print(f"gamma {gamma} {prec}: rho {rho:.6e} oracle {rho_ref:.6e} reached {reached:.6e}")
+        assert abs(rho - rho_ref) <= tol * rho_ref
+        assert reached <= rho * (1 + 1e-9)

@@ -104,3 +104,36 @@ def test_admission_by_footprint(torch):
         with pytest.raises(gabp.GabpError) as e:
             srv.submit(reqs[0][0], reqs[0][1], **reqs[0][2])
         assert e.value.status == gabp.E_NOMEM
+
+
+def test_served_stateless_plans_equal_single(torch):
+    # edge state chosen per request from the contraction bound (AUTO): the
+    # stateless requests run in launches grouped by precision and level
+    # count, next to stored ones, and still match the single solve bitwise
+    reqs = []
+    for r in range(9):
+        n = [300, 700, 1300][r % 3]
+        X, y = inputs.blobs(n, 16, 7100 + r)
+        gamma = [2e-3, 1.0 / 16, 0.5][r % 3]        # from strongly to weakly contracting
+        prec = ["fp32", "mixed", "fp64"][(r // 3) % 3]
+        reqs.append((X, y, dict(gamma=gamma, C=1.0, precision=prec, tol_rel=1e-7, kstore="materialise")))
+    print(f"[case] stateless serving mix of {len(reqs)} requests", flush=True)
+    single = []
+    for X, y, kw in reqs:
+        s = gabp.GabpSVM(**kw)
+        st = s.solve(X, y)
+        single.append((st, s.alpha(), s.sweeps(), s.plan()["stateless_depth"]))
+        s.close()
+    levels = [d for _, _, _, d in single]
+    print("single-solve levels", levels)
+    assert any(d > 0 for d in levels) and len(set(levels)) >= 2
+    with gabp.GabpServer(arena_bytes=int(2e9), max_active=6, steps_per_poll=2) as srv:
+        tickets = [srv.submit(X, y, **kw) for X, y, kw in reqs]
+        for t in tickets:
+            assert srv.wait(t, 300.0)
+        for k, t in enumerate(tickets):
+            a, info = srv.result(t)
+            st, ref, sw, d = single[k]
+            assert info["stateless_levels"] == d, (k, info, d)
+            assert info["status"] == st and info["sweeps"] == sw, (k, info, st, sw)
+            assert np.array_equal(a, ref), k

@@ -311,3 +311,48 @@ def test_stateless_exact_while_within_depth_and_bounded_after():
     e3 = _rel(R.gabp_solve_stateless(A, b, 3, 20)[-1], ref.trajectory[20])
     e6 = _rel(R.gabp_solve_stateless(A, b, 6, 20)[-1], ref.trajectory[20])
     assert e6 < e3
+
+
+def test_message_contraction_closed_forms():
+    # two nodes: Q_12 = P~_1 - P_21 = A_11 at every sweep
+    a, c, o = 3.0, 5.0, -1.5
+    tr = R.message_contraction(np.array([[a, o], [o, c]]), 6)
+    assert tr == [max(abs(o) / a, abs(o) / c)] * 6
+    # 3-node chain (a tree): sweep 1 divides by the diagonal, from sweep 2 on
+    # the cavity precisions of the leaves' neighbours exclude the leaf
+    a, b, c, o1, o2 = 2.0, 3.0, 2.5, 0.8, -1.1
+    A = np.array([[a, o1, 0.0], [o1, b, o2], [0.0, o2, c]])
+    tr = R.message_contraction(A, 5)
+    s1 = max(abs(o1) / a, abs(o1) / b, abs(o2) / b, abs(o2) / c)
+    s2 = max(abs(o1) / a, abs(o1) / (b - o2 * o2 / c), abs(o2) / (b - o1 * o1 / a), abs(o2) / c)
+    assert tr[0] == pytest.approx(s1, rel=1e-15)
+    for v in tr[1:]:
+        assert v == pytest.approx(s2, rel=1e-15)
+
+
+def test_contraction_bound_closed_forms():
+    # no couplings: nothing is passed on
+    assert R.contraction_bound(np.diag([1.0, 2.0, 3.0]))[1] == 0.0
+    # two nodes [[a, o], [o, c]]: c_i = o^2, m* = min larger roots, lo_i = A_ii - o^2 / m*
+    a, c, o = 3.0, 5.0, 1.0
+    m = min((a + np.sqrt(a * a - 4 * o * o)) / 2, (c + np.sqrt(c * c - 4 * o * o)) / 2)
+    mstar, rho = R.contraction_bound(np.array([[a, o], [o, c]]))
+    assert mstar == pytest.approx(m, rel=1e-15)
+    assert rho == pytest.approx(max(o / (a - o * o / m), o / (c - o * o / m)), rel=1e-15)
+    # no real root: no bound
+    assert R.contraction_bound(np.array([[1.0, 0.9], [0.9, 1.0]]))[1] == np.inf
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_contraction_bound_holds_along_trajectory(case):
+    if case < 3:
+        A = inputs.random_spd_dominant(60 + 20 * case, seed=80 + case, margin=[0.1, 0.5, 2.0][case])
+    else:
+        X, y = inputs.blobs(150, 8, 90 + case)
+        A, _ = R.svm_system(X, y, [2e-3, 1.0 / 8, 1.0][case - 3], 1.0, 1.0 / 150)
+    mstar, rho = R.contraction_bound(A)
+    tr = R.message_contraction(A, 40)
+    assert np.isfinite(rho) and np.all(np.isfinite(tr))
+    assert max(tr) <= rho * (1 + 1e-12), (max(tr), rho)
+    # the bound is useful: within a small factor of what the sweeps reach
+    assert rho <= 2.0 * max(tr)
