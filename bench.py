@@ -27,6 +27,12 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # VALU issue slots: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (FP32 and FP64 FMA
 # both issue at one lane-op per lane per clock on CDNA4; packed FP32 unused)
 VALU_PEAK_GSLOT = 256 * 64 * 2.4
+# dense MFMA peaks (MI355X, no sparsity)
+MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}
+# decision function, VALU slots per (query, training point) pair: distance
+# from the Gram (add, fma), clamp, scale, exp2 (a transcendental: 4 slots),
+# conversion to FP64 and the FP64 accumulation
+PREDICT_SLOTS_PER_PAIR = 10
 
 
 def device_source_hash():
@@ -90,6 +96,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=0, help="oracle sample size (0 = auto)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-predict", action="store_true", help="skip the held-out decision-function measurement")
+    ap.add_argument("--predict-n", type=int, default=100000, help="held-out queries of the predict leg")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving measurement")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-load", type=float, default=0.8, help="offered load / measured capacity")
@@ -192,6 +200,53 @@ def serving_bench(gabp, inputs, n_req, load, precision, seq_sample=24):
             "sequential_sample": f"first {k} requests solved one at a time on one handle, rate scaled by "
                                  f"the stream's mean N^2 over the sample's",
             "batching_speedup": capacity / seq_rate if seq_rate > 0 else None}
+
+
+def predict_bench(torch, gabp, inputs, wl, X, y, params, n_test, reps=5):
+    """Decision function of the trained machine on n_test held-out points of
+    the same generator and teacher (device-resident queries): predictions/s
+    over the whole call, the decision kernel's own time, held-out accuracy."""
+    import numpy as np
+    _, Xt, yt = inputs.holdout(wl.name, n_test, n=wl.N)
+    Xq = torch.from_numpy(Xt).cuda()
+    s = gabp.GabpSVM(**params)
+    s.solve(X, y)
+    plan = s.plan()
+    f = s.predict(Xq)
+    torch.cuda.synchronize()
+    walls, kms = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        f = s.predict(Xq)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        kms.append(s.timings()["predict_kernel_ms"])
+    s.close()
+    fh = f.cpu().numpy()
+    acc = float(np.mean(np.where(fh >= 0, 1.0, -1.0) == yt))
+    wall = float(np.median(walls))
+    kms_med = float(np.median(kms))
+    pairs = float(wl.N) * n_test
+    m_pad = (wl.m + 15) // 16 * 16
+    # plan gram (gabp_gram): 0 = FP32 Gram (FP32 precision), 1..3 = BF16 split kinds
+    gram = {0: "f32", 1: "bf16", 2: "bf16x3", 3: "bf16x6"}[plan["gram"]]
+    products = {"bf16": 1, "bf16x3": 3, "bf16x6": 6, "f32": 1}[gram]
+    alg_flops = 2.0 * wl.m * pairs                  # the Gram dot products
+    issued = 2.0 * m_pad * products * pairs         # MFMA work as issued (padding, split products)
+    mfma_peak = MFMA_PEAK_TFLOPS["f32" if gram == "f32" else "bf16"]
+    slots = PREDICT_SLOTS_PER_PAIR
+    print(f"[bench] predict: {n_test} queries in {wall * 1e3:.2f} ms (kernel {kms_med:.2f} ms), "
+          f"held-out accuracy {acc:.4f}", file=sys.stderr, flush=True)
+    return {"queries": n_test, "train_N": wl.N, "gram": gram, "predictions_per_s": n_test / wall,
+            "call_ms": wall * 1e3, "kernel_ms": kms_med, "held_out_accuracy": acc,
+            "kernel": "k_predict_mfma",
+            "roofline": {"bound": "mfma", "unit": "TFLOP/s", "peak": mfma_peak,
+                         "achieved": alg_flops / (kms_med * 1e-3) / 1e12,
+                         "frac": alg_flops / (kms_med * 1e-3) / 1e12 / mfma_peak,
+                         "alg_flops_per_pair": 2.0 * wl.m, "issued_mfma_flops_per_pair": 2.0 * m_pad * products,
+                         "issued_frac": issued / (kms_med * 1e-3) / 1e12 / mfma_peak,
+                         "valu_slots_per_pair": slots,
+                         "valu_frac": slots * pairs / (kms_med * 1e-3) / 1e9 / VALU_PEAK_GSLOT}}
 
 
 def cpu_baseline(wl, n_full, sample_n):
@@ -311,6 +366,10 @@ def main():
                                    "alg_bytes_per_pair": sp["alg_bytes_per_pair"]}}
         print(f"[bench] stored state: {ss_} sweeps in {sw_:.3f} s", file=sys.stderr, flush=True)
 
+    predict = None
+    if not a.no_predict:
+        predict = predict_bench(torch, gabp, inputs, wl, X, y, params, a.predict_n)
+
     serving = None
     if not a.no_serve:
         serving = serving_bench(gabp, inputs, a.serve_requests, a.serve_load, a.serve_precision)
@@ -346,6 +405,7 @@ def main():
         "plain_fp32": plain,
         "stored_state": stored_cmp,
         "serving": serving,
+        "predict": predict,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

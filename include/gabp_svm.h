@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define GABP_ABI_VERSION 1
+#define GABP_ABI_VERSION 2
 
 /* Opaque solver handle; owns every device buffer it allocates. */
 typedef struct gabp_svm gabp_svm;
@@ -159,6 +159,9 @@ typedef struct gabp_timings {
     int64_t sweep_launches;    /* sweep-kernel launches that did work */
     double d2h_ms;             /* alpha download (host output) */
     double total_ms;           /* whole solve call, host wall clock */
+    double predict_kernel_ms;  /* last gabp_svm_predict: time of the decision-
+                                  function kernel launches (time_sweeps) */
+    int64_t predict_queries;   /* queries of that call */
 } gabp_timings;
 
 /* The memory plan chosen for the last solve. */

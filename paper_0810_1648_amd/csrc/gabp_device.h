@@ -135,15 +135,17 @@ __device__ inline TileCoord tile_of(const uint32_t* tiles) {
 // inner-product index is split between the two lane halves so that each lane
 // reads contiguous features.  Output layout of the 32x32 MFMAs: register r of
 // lane l holds row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.
+// The A rows come from FA and the B rows from FB (the same staging: m_pad
+// and kind are taken from FA).
 template <int KIND>
-__device__ inline f32x16 mfma_gram_32x32(const Features& F, int64_t rowA, int64_t colB) {
+__device__ inline f32x16 mfma_gram_32x32(const Features& FA, int64_t rowA, const Features& FB, int64_t colB) {
     const int l = threadIdx.x & 63, h = l >> 5;
-    const int mp = F.m_pad;
+    const int mp = FA.m_pad;
     f32x16 acc = {};
     if constexpr (KIND == GRAM_F32) {
         const int half = mp >> 1;
-        const float* pa = F.f32 + rowA * mp + h * half;
-        const float* pb = F.f32 + colB * mp + h * half;
+        const float* pa = FA.f32 + rowA * mp + h * half;
+        const float* pb = FB.f32 + colB * mp + h * half;
         for (int s = 0; s < half; s += 4) {
             const f32x4v a4 = *reinterpret_cast<const f32x4v*>(pa + s);
             const f32x4v b4 = *reinterpret_cast<const f32x4v*>(pb + s);
@@ -155,15 +157,15 @@ __device__ inline f32x16 mfma_gram_32x32(const Features& F, int64_t rowA, int64_
     } else {
         const int64_t oa = rowA * mp + 8 * h, ob = colB * mp + 8 * h;
         for (int s = 0; s < mp; s += 16) {
-            const bf16x8 a = *reinterpret_cast<const bf16x8*>(F.hi + oa + s);
-            const bf16x8 b = *reinterpret_cast<const bf16x8*>(F.hi + ob + s);
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(FA.hi + oa + s);
+            const bf16x8 b = *reinterpret_cast<const bf16x8*>(FB.hi + ob + s);
             if constexpr (KIND == GRAM_BF16X3 || KIND == GRAM_BF16X6) {
                 // correction terms first, then the leading product
-                const bf16x8 al = *reinterpret_cast<const bf16x8*>(F.lo + oa + s);
-                const bf16x8 bl = *reinterpret_cast<const bf16x8*>(F.lo + ob + s);
+                const bf16x8 al = *reinterpret_cast<const bf16x8*>(FA.lo + oa + s);
+                const bf16x8 bl = *reinterpret_cast<const bf16x8*>(FB.lo + ob + s);
                 if constexpr (KIND == GRAM_BF16X6) {
-                    const bf16x8 a2 = *reinterpret_cast<const bf16x8*>(F.lo2 + oa + s);
-                    const bf16x8 b2 = *reinterpret_cast<const bf16x8*>(F.lo2 + ob + s);
+                    const bf16x8 a2 = *reinterpret_cast<const bf16x8*>(FA.lo2 + oa + s);
+                    const bf16x8 b2 = *reinterpret_cast<const bf16x8*>(FB.lo2 + ob + s);
                     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b2, acc, 0, 0, 0);
                     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, b, acc, 0, 0, 0);
                     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bl, acc, 0, 0, 0);
@@ -175,6 +177,11 @@ __device__ inline f32x16 mfma_gram_32x32(const Features& F, int64_t rowA, int64_
         }
     }
     return acc;
+}
+
+template <int KIND>
+__device__ inline f32x16 mfma_gram_32x32(const Features& F, int64_t rowA, int64_t colB) {
+    return mfma_gram_32x32<KIND>(F, rowA, F, colB);
 }
 
 // K' = exp(-gamma d^2) + lambda^2 with d^2 = max(0, n_i + n_j - 2 G_ij), zero

@@ -166,9 +166,21 @@ hipError_t launch_rho_bound(int64_t N, const double* Adiag, const double* rowmax
                             double* blk, double* one, hipStream_t s);
 hipError_t launch_kernel_entries(const void* Kp, int prec, int NB, const int64_t* rows,
                                  const int64_t* cols, int64_t n, double* out, hipStream_t s);
-hipError_t launch_predict(const float* Xtr, const float* y, const double* alpha, int64_t N,
-                          int64_t m, const float* Xq, int64_t nq, double gamma, double lam2,
-                          bool fp64, double* f, hipStream_t s);
+// Decision function (gabp_predict.hip).  Queries are padded to
+// predict_query_pad(nq) rows; the MFMA form splits the training rows into
+// nchunk chunks of bpc 32-row blocks (predict_chunks) and writes
+// part[nchunk][NQPAD]; the direct FP64 form writes part[nq].
+int64_t predict_query_pad(int64_t nq);
+void predict_chunks(int64_t NPAD, int64_t NQPAD, int* nchunk, int* bpc);
+hipError_t launch_predict_weights(const double* alpha, const float* y, int64_t N, int64_t NPAD, bool box,
+                                  double C, double* w, double* blk, double* wsum, hipStream_t s);
+hipError_t launch_predict_direct(const float* Xtr, const double* w, int64_t N, int64_t m, const float* Xq,
+                                 int64_t nq, double gamma, double* part, hipStream_t s);
+hipError_t launch_predict_mfma(const Features& Ft, const Features& Fq, const double* w, int64_t NPAD,
+                               int64_t NQPAD, float neg_gamma_log2e, int nchunk, int bpc, double* part,
+                               hipStream_t s);
+hipError_t launch_predict_reduce(const double* part, int nchunk, int64_t stride, int64_t nq, const double* wsum,
+                                 double lam2, double* f, hipStream_t s);
 hipError_t launch_convert_agg(int prec, const void* src, double* dst, int64_t n, hipStream_t s);
 
 }  // namespace gabp

@@ -543,41 +543,6 @@ __global__ void k_convert(const AT* __restrict__ src, double* __restrict__ dst, 
     if (i < n) dst[i] = (double)src[i];
 }
 
-// f(x_q) = sum_i alpha_i y_i (K(x_i, x_q) + lambda^2), one workgroup per query,
-// direct differences; FP64 sum in a fixed order.
-__global__ __launch_bounds__(WG) void k_predict(const float* __restrict__ Xtr,
-                                               const float* __restrict__ y,
-                                               const double* __restrict__ alpha, int64_t N,
-                                               int64_t m, const float* __restrict__ Xq,
-                                               double gamma, double lam2, int fp64,
-                                               double* __restrict__ f) {
-    __shared__ double sh[WG];
-    const int64_t qi = blockIdx.x;
-    const float* xq = Xq + qi * m;
-    double acc = 0.0;
-    for (int64_t i = threadIdx.x; i < N; i += WG) {
-        const float* xi = Xtr + i * m;
-        double kv;
-        if (fp64) {
-            double d2 = 0.0;
-            for (int64_t k = 0; k < m; ++k) { const double d = (double)xi[k] - (double)xq[k]; d2 = fma(d, d, d2); }
-            kv = exp(-gamma * d2);
-        } else {
-            float d2 = 0.0f;
-            for (int64_t k = 0; k < m; ++k) { const float d = xi[k] - xq[k]; d2 = fmaf(d, d, d2); }
-            kv = (double)expf(-(float)gamma * d2);
-        }
-        acc += alpha[i] * (double)y[i] * (kv + lam2);
-    }
-    sh[threadIdx.x] = acc;
-    __syncthreads();
-    for (int o = WG / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) f[qi] = sh[0];
-}
-
 // ----------------------------------------------------------- launchers --
 
 static inline unsigned grid1(int64_t n) { return (unsigned)((n + WG - 1) / WG); }
@@ -756,14 +721,6 @@ hipError_t launch_kernel_entries(const void* Kp, int prec, int NB, const int64_t
     else
         hipLaunchKernelGGL(k_entries<float>, dim3(grid1(n)), dim3(WG), 0, s, (const float*)Kp, NB,
                            rows, cols, n, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_predict(const float* Xtr, const float* y, const double* alpha, int64_t N, int64_t m,
-                          const float* Xq, int64_t nq, double gamma, double lam2, bool fp64,
-                          double* f, hipStream_t s) {
-    hipLaunchKernelGGL(k_predict, dim3((unsigned)nq), dim3(WG), 0, s, Xtr, y, alpha, N, m, Xq, gamma,
-                       lam2, fp64 ? 1 : 0, f);
     return hipGetLastError();
 }
 

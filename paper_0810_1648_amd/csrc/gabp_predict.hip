@@ -1,0 +1,289 @@
+// Decision function of the trained machine on new points (section
+// "Classification Using Support Vector Machines": the classifier is the sign
+// of sum_i alpha_i y_i K(x_i, x) + b; with the bias absorbed by the constant
+// feature lambda, b = lambda^2 sum_i alpha_i y_i, so that
+//   f(x_q) = sum_i w_i K(x_i, x_q) + lambda^2 sum_i w_i,   w_i = alpha_i y_i.
+//
+// FP32 and MIXED handles form K(x_i, x_q) from the same staged features and
+// Gram kind as the solve's K' (centred with the training column means, which
+// leaves RBF distances unchanged): an MFMA 32 x 32 Gram block per wave step,
+// then exp2 of the clamped distance, folded into per-query FP64 sums.  FP64
+// handles take direct FP64 differences.  Partial sums per training chunk are
+// reduced in a fixed order, so f does not depend on the launch shape's
+// timing.
+#include "gabp_device.h"
+
+namespace gabp {
+
+namespace {
+
+constexpr int QB = 128;   // queries per workgroup: four waves of 32
+
+// w_i = alpha_i y_i (alpha clipped to [0, C] with the box option), zero on
+// padded rows; per-block sums of w in a fixed tree order.
+__global__ __launch_bounds__(WG) void k_predict_weights(const double* __restrict__ alpha,
+                                                        const float* __restrict__ y, int64_t N,
+                                                        int64_t NPAD, int box, double C,
+                                                        double* __restrict__ w, double* __restrict__ blk) {
+    __shared__ double sh[WG];
+    const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+    double v = 0.0;
+    if (i < N) {
+        double a = alpha[i];
+        if (box) a = fmin(fmax(a, 0.0), C);
+        v = a * (double)y[i];
+    }
+    if (i < NPAD) w[i] = v;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = WG / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) blk[blockIdx.x] = sh[0];
+}
+
+// One workgroup: out[0] = sum of v[0 .. n) in a fixed order.
+__global__ __launch_bounds__(WG) void k_sum_fixed(const double* __restrict__ v, int64_t n,
+                                                  double* __restrict__ out) {
+    __shared__ double sh[WG];
+    double acc = 0.0;
+    for (int64_t k = threadIdx.x; k < n; k += WG) acc += v[k];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = WG / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// FP64: one workgroup per query, direct differences of the raw features.
+__global__ __launch_bounds__(WG) void k_predict_direct(const float* __restrict__ Xtr,
+                                                       const double* __restrict__ w, int64_t N,
+                                                       int64_t m, const float* __restrict__ Xq,
+                                                       double gamma, double* __restrict__ part) {
+    __shared__ double sh[WG];
+    const int64_t qi = blockIdx.x;
+    const float* xq = Xq + qi * m;
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < N; i += WG) {
+        const float* xi = Xtr + i * m;
+        double d2 = 0.0;
+        for (int64_t k = 0; k < m; ++k) {
+            const double d = (double)xi[k] - (double)xq[k];
+            d2 = fma(d, d, d2);
+        }
+        acc = fma(w[i], exp(-gamma * d2), acc);
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = WG / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[qi] = sh[0];
+}
+
+// A operand (32 query rows) of the MFMA Gram, held in registers for the whole
+// chunk when m_pad <= MP; MP = 0 reloads it every block.
+template <int KIND, int MP> struct QueryFrag {
+    static constexpr int NS = (KIND == GRAM_F32) ? MP / 8 : MP / 16;
+    static constexpr int NSA = NS > 0 ? NS : 1;
+    f32x4v f[KIND == GRAM_F32 ? NSA : 1];
+    bf16x8 hi[KIND == GRAM_F32 ? 1 : NSA];
+    bf16x8 lo[(KIND == GRAM_BF16X3 || KIND == GRAM_BF16X6) ? NSA : 1];
+    bf16x8 lo2[KIND == GRAM_BF16X6 ? NSA : 1];
+
+    __device__ void load(const Features& Fq, int64_t rowA) {
+        if constexpr (MP > 0) {
+            const int l = threadIdx.x & 63, h = l >> 5, mp = Fq.m_pad;
+            if constexpr (KIND == GRAM_F32) {
+                const int half = mp >> 1;
+                const float* pa = Fq.f32 + rowA * mp + h * half;
+#pragma unroll
+                for (int s = 0; s < NS; ++s)
+                    if (4 * s < half) f[s] = *reinterpret_cast<const f32x4v*>(pa + 4 * s);
+            } else {
+                const int64_t oa = rowA * mp + 8 * h;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    if (16 * s >= mp) continue;
+                    hi[s] = *reinterpret_cast<const bf16x8*>(Fq.hi + oa + 16 * s);
+                    if constexpr (KIND == GRAM_BF16X3 || KIND == GRAM_BF16X6)
+                        lo[s] = *reinterpret_cast<const bf16x8*>(Fq.lo + oa + 16 * s);
+                    if constexpr (KIND == GRAM_BF16X6)
+                        lo2[s] = *reinterpret_cast<const bf16x8*>(Fq.lo2 + oa + 16 * s);
+                }
+            }
+        }
+    }
+
+    // Gram block of the wave's 32 queries with training rows colB (one per lane % 32).
+    __device__ f32x16 gram(const Features& Fq, int64_t rowA, const Features& Ft, int64_t colB) const {
+        if constexpr (MP == 0) {
+            return mfma_gram_32x32<KIND>(Fq, rowA, Ft, colB);
+        } else {
+            const int l = threadIdx.x & 63, h = l >> 5, mp = Ft.m_pad;
+            f32x16 acc = {};
+            if constexpr (KIND == GRAM_F32) {
+                const int half = mp >> 1;
+                const float* pb = Ft.f32 + colB * mp + h * half;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    if (4 * s >= half) continue;
+                    const f32x4v b4 = *reinterpret_cast<const f32x4v*>(pb + 4 * s);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(f[s][0], b4[0], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(f[s][1], b4[1], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(f[s][2], b4[2], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(f[s][3], b4[3], acc, 0, 0, 0);
+                }
+            } else {
+                const int64_t ob = colB * mp + 8 * h;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    if (16 * s >= mp) continue;
+                    const bf16x8 b = *reinterpret_cast<const bf16x8*>(Ft.hi + ob + 16 * s);
+                    if constexpr (KIND == GRAM_BF16X3 || KIND == GRAM_BF16X6) {
+                        const bf16x8 bl = *reinterpret_cast<const bf16x8*>(Ft.lo + ob + 16 * s);
+                        if constexpr (KIND == GRAM_BF16X6) {
+                            const bf16x8 b2 = *reinterpret_cast<const bf16x8*>(Ft.lo2 + ob + 16 * s);
+                            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi[s], b2, acc, 0, 0, 0);
+                            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo2[s], b, acc, 0, 0, 0);
+                            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo[s], bl, acc, 0, 0, 0);
+                        }
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi[s], bl, acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo[s], b, acc, 0, 0, 0);
+                    }
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi[s], b, acc, 0, 0, 0);
+                }
+            }
+            return acc;
+        }
+    }
+};
+
+// Workgroup (x, y): queries [128 x, 128 x + 128), training blocks of 32 rows
+// [bpc y, bpc (y + 1)).  Wave v owns queries 32 v .. 32 v + 31; lane l's
+// MFMA output register r is query row 8 (r / 4) + 4 (l / 32) + r % 4 and
+// training row l % 32 of the block.  part[y][q] receives the chunk's sum.
+template <int KIND, int MP>
+__global__ __launch_bounds__(WG) void k_predict_mfma(Features Ft, Features Fq, const double* __restrict__ w,
+                                                     int64_t nblk32, int bpc, float neg_gamma_log2e,
+                                                     int64_t NQPAD, double* __restrict__ part) {
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, h = l >> 5, l32 = l & 31;
+    const int64_t q0 = (int64_t)blockIdx.x * QB + wv * 32;
+    const int64_t rowA = q0 + l32;
+    float ni[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) ni[r] = Fq.nrm[q0 + 8 * (r >> 2) + 4 * h + (r & 3)];
+    QueryFrag<KIND, MP> qa;
+    qa.load(Fq, rowA);
+    double acc[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+    const int64_t b0 = (int64_t)blockIdx.y * bpc;
+    const int64_t b1 = (b0 + bpc < nblk32) ? b0 + bpc : nblk32;
+    for (int64_t b = b0; b < b1; ++b) {
+        const int64_t colB = b * 32 + l32;
+        const f32x16 g = qa.gram(Fq, rowA, Ft, colB);
+        const float nj = Ft.nrm[colB];
+        const double wj = w[colB];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const float d2 = fmaxf(ni[r] + nj - 2.0f * g[r], 0.0f);
+            acc[r] = fma((double)exp2f(neg_gamma_log2e * d2), wj, acc[r]);
+        }
+    }
+    // sum over the 32 training rows held by lanes l % 32 of each half
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        double v = sum16(acc[r]);
+        v = v + __shfl_xor(v, 16);
+        acc[r] = v;
+    }
+    if (l32 == 0) {
+        double* out = part + (int64_t)blockIdx.y * NQPAD + q0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) out[8 * (r >> 2) + 4 * h + (r & 3)] = acc[r];
+    }
+}
+
+// f_q = sum over chunks (in order) of part[c][q] + lambda^2 sum_i w_i.
+__global__ void k_predict_reduce(const double* __restrict__ part, int nchunk, int64_t stride, int64_t nq,
+                                 const double* __restrict__ wsum, double lam2, double* __restrict__ f) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    double acc = 0.0;
+    for (int c = 0; c < nchunk; ++c) acc += part[(int64_t)c * stride + q];
+    f[q] = acc + lam2 * wsum[0];
+}
+
+template <int KIND>
+void predict_kind(int mp, dim3 grid, const Features& Ft, const Features& Fq, const double* w, int64_t nblk32,
+                  int bpc, float c, int64_t NQPAD, double* part, hipStream_t s) {
+    if (mp <= 32)
+        hipLaunchKernelGGL((k_predict_mfma<KIND, 32>), grid, dim3(WG), 0, s, Ft, Fq, w, nblk32, bpc, c, NQPAD, part);
+    else if (mp <= 64)
+        hipLaunchKernelGGL((k_predict_mfma<KIND, 64>), grid, dim3(WG), 0, s, Ft, Fq, w, nblk32, bpc, c, NQPAD, part);
+    else if (mp <= 128)
+        hipLaunchKernelGGL((k_predict_mfma<KIND, 128>), grid, dim3(WG), 0, s, Ft, Fq, w, nblk32, bpc, c, NQPAD, part);
+    else
+        hipLaunchKernelGGL((k_predict_mfma<KIND, 0>), grid, dim3(WG), 0, s, Ft, Fq, w, nblk32, bpc, c, NQPAD, part);
+}
+
+inline unsigned blocks_of(int64_t n) { return (unsigned)((n + WG - 1) / WG); }
+
+}  // namespace
+
+int64_t predict_query_pad(int64_t nq) { return (nq + QB - 1) / QB * QB; }
+
+void predict_chunks(int64_t NPAD, int64_t NQPAD, int* nchunk, int* bpc) {
+    const int64_t nblk32 = NPAD / 32, nqb = NQPAD / QB;
+    // enough workgroups to fill the chip several times over
+    int64_t want = (4096 + nqb - 1) / nqb;
+    want = std::max<int64_t>(1, std::min<int64_t>(want, nblk32));
+    const int64_t per = (nblk32 + want - 1) / want;
+    *bpc = (int)per;
+    *nchunk = (int)((nblk32 + per - 1) / per);
+}
+
+hipError_t launch_predict_weights(const double* alpha, const float* y, int64_t N, int64_t NPAD, bool box,
+                                  double C, double* w, double* blk, double* wsum, hipStream_t s) {
+    const unsigned nb = blocks_of(NPAD);
+    hipLaunchKernelGGL(k_predict_weights, dim3(nb), dim3(WG), 0, s, alpha, y, N, NPAD, box ? 1 : 0, C, w, blk);
+    hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(WG), 0, s, blk, (int64_t)nb, wsum);
+    return hipGetLastError();
+}
+
+hipError_t launch_predict_direct(const float* Xtr, const double* w, int64_t N, int64_t m, const float* Xq,
+                                 int64_t nq, double gamma, double* part, hipStream_t s) {
+    hipLaunchKernelGGL(k_predict_direct, dim3((unsigned)nq), dim3(WG), 0, s, Xtr, w, N, m, Xq, gamma, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_predict_mfma(const Features& Ft, const Features& Fq, const double* w, int64_t NPAD,
+                               int64_t NQPAD, float neg_gamma_log2e, int nchunk, int bpc, double* part,
+                               hipStream_t s) {
+    if (NQPAD % QB != 0 || NPAD % 32 != 0 || Ft.m_pad != Fq.m_pad || Ft.kind != Fq.kind)
+        return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(NQPAD / QB), (unsigned)nchunk);
+    const int64_t nblk32 = NPAD / 32;
+    switch (Ft.kind) {
+        case GRAM_F32: predict_kind<GRAM_F32>(Ft.m_pad, grid, Ft, Fq, w, nblk32, bpc, neg_gamma_log2e, NQPAD, part, s); break;
+        case GRAM_BF16: predict_kind<GRAM_BF16>(Ft.m_pad, grid, Ft, Fq, w, nblk32, bpc, neg_gamma_log2e, NQPAD, part, s); break;
+        case GRAM_BF16X3: predict_kind<GRAM_BF16X3>(Ft.m_pad, grid, Ft, Fq, w, nblk32, bpc, neg_gamma_log2e, NQPAD, part, s); break;
+        case GRAM_BF16X6: predict_kind<GRAM_BF16X6>(Ft.m_pad, grid, Ft, Fq, w, nblk32, bpc, neg_gamma_log2e, NQPAD, part, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_predict_reduce(const double* part, int nchunk, int64_t stride, int64_t nq, const double* wsum,
+                                 double lam2, double* f, hipStream_t s) {
+    hipLaunchKernelGGL(k_predict_reduce, dim3(blocks_of(nq)), dim3(WG), 0, s, part, nchunk, stride, nq, wsum,
+                       lam2, f);
+    return hipGetLastError();
+}
+
+}  // namespace gabp

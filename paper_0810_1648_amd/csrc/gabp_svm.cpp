@@ -661,39 +661,102 @@ gabp_status gabp_svm_kernel_entries(const gabp_svm* hc, const int64_t* rows, con
 gabp_status gabp_svm_predict(gabp_svm* h, const float* Xq, int64_t nq, double* f_out, int32_t mem,
                              void* stream) {
     if (!h || !Xq || !f_out || nq < 0) return GABP_E_INVALID;
+    if (mem != GABP_MEM_HOST && mem != GABP_MEM_DEVICE) return GABP_E_INVALID;
     if (!h->have_result || !h->rbf) return fail(h, GABP_E_STATE, "predict needs a finished RBF solve");
     if (nq == 0) return GABP_OK;
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(h, hipSetDevice(h->p.device));
-    const size_t m = (size_t)h->m;
-    DevBuf xq, fo, al;
+    const int64_t m = h->m, N = h->N, NPAD = h->NPAD;
     if (mem == GABP_MEM_HOST) {
-        for (int64_t k = 0; k < nq * (int64_t)m; ++k)
+        for (int64_t k = 0; k < nq * m; ++k)
             if (!std::isfinite(Xq[k])) return fail(h, GABP_E_INVALID, "Xq has a non-finite entry");
     }
-    if (xq.ensure((size_t)nq * m * 4) != hipSuccess || fo.ensure((size_t)nq * 8) != hipSuccess ||
-        al.ensure((size_t)h->N * 8) != hipSuccess) {
-        xq.release(); fo.release(); al.release();
-        return fail(h, GABP_E_NOMEM, "device allocation failed");
+    // queries are processed in batches of at most QMAX rows
+    const int64_t QMAX = int64_t(1) << 18;
+    const int64_t qb = std::min(nq, QMAX);
+    const int64_t QPAD = predict_query_pad(qb);
+    const bool f64 = h->prec == PREC_FP64;
+    const int gram = h->gram, mp = h->m_pad;
+    // partial-sum rows: the largest over the full batches and the last one
+    size_t part_elems = (size_t)qb;
+    if (!f64) {
+        int nc = 1, bp = 1;
+        predict_chunks(NPAD, QPAD, &nc, &bp);
+        part_elems = (size_t)nc * QPAD;
+        const int64_t last = nq % QMAX;
+        if (last) {
+            const int64_t lpad = predict_query_pad(last);
+            predict_chunks(NPAD, lpad, &nc, &bp);
+            part_elems = std::max(part_elems, (size_t)nc * lpad);
+        }
     }
-    auto a = boxed_alpha(h);
-    gabp_status rc = GABP_OK;
-    do {
-        if (hipMemcpyAsync(al.p, a.data(), (size_t)h->N * 8, hipMemcpyHostToDevice, s) != hipSuccess) { rc = GABP_E_DEVICE; break; }
-        const float* xqd = Xq;
+    const size_t fe = (size_t)QPAD * mp;
+    DevBuf xq, fo, w, blk, wsum, part, qf32, qhi, qlo, qlo2, qnrm;
+    bool ok = w.ensure((size_t)NPAD * 8) == hipSuccess && blk.ensure((size_t)(NPAD / WG + 1) * 8) == hipSuccess &&
+              wsum.ensure(64) == hipSuccess &&
+              part.ensure(part_elems * 8) == hipSuccess;
+    if (ok && mem == GABP_MEM_HOST) ok = xq.ensure((size_t)qb * m * 4) == hipSuccess && fo.ensure((size_t)qb * 8) == hipSuccess;
+    if (ok && !f64) {
+        ok = qnrm.ensure((size_t)QPAD * 4) == hipSuccess;
+        if (ok && gram == GRAM_F32) ok = qf32.ensure(fe * 4) == hipSuccess;
+        if (ok && gram != GRAM_F32) ok = qhi.ensure(fe * 2) == hipSuccess;
+        if (ok && (gram == GRAM_BF16X3 || gram == GRAM_BF16X6)) ok = qlo.ensure(fe * 2) == hipSuccess;
+        if (ok && gram == GRAM_BF16X6) ok = qlo2.ensure(fe * 2) == hipSuccess;
+    }
+    if (!ok) return fail(h, GABP_E_NOMEM, "device allocation for predict failed");
+    Features Ft{}, Fq{};
+    Ft.f32 = h->xs32.as<float>(); Ft.hi = h->xhi.as<uint16_t>(); Ft.lo = h->xlo.as<uint16_t>();
+    Ft.lo2 = h->xlo2.as<uint16_t>(); Ft.nrm = h->nrm.as<float>(); Ft.m_pad = mp; Ft.kind = gram;
+    Fq.f32 = qf32.as<float>(); Fq.hi = qhi.as<uint16_t>(); Fq.lo = qlo.as<uint16_t>();
+    Fq.lo2 = qlo2.as<uint16_t>(); Fq.nrm = qnrm.as<float>(); Fq.m_pad = mp; Fq.kind = gram;
+    const double lam2 = h->lam * h->lam;
+    const float c = (float)(-h->p.gamma * 1.4426950408889634);
+    const bool timed = h->p.time_sweeps != 0;
+    const int64_t nbatch = (nq + QMAX - 1) / QMAX;
+    EventPool pev;
+    if (timed) HIPCHK(h, pev.make((size_t)(2 * nbatch)));
+    HIPCHK(h, launch_predict_weights(h->alpha_d.as<double>(), h->yd.as<float>(), N, NPAD,
+                                     h->p.box_mode == GABP_BOX_CLIP_OUTPUT, h->p.C, w.as<double>(),
+                                     blk.as<double>(), wsum.as<double>(), s));
+    for (int64_t q0 = 0; q0 < nq; q0 += QMAX) {
+        const int64_t nb = std::min(QMAX, nq - q0);
+        const float* xqd = Xq + q0 * m;
         if (mem == GABP_MEM_HOST) {
-            if (hipMemcpyAsync(xq.p, Xq, (size_t)nq * m * 4, hipMemcpyHostToDevice, s) != hipSuccess) { rc = GABP_E_DEVICE; break; }
+            HIPCHK(h, hipMemcpyAsync(xq.p, xqd, (size_t)nb * m * 4, hipMemcpyHostToDevice, s));
             xqd = xq.as<float>();
         }
-        double* fd = (mem == GABP_MEM_HOST) ? fo.as<double>() : f_out;
-        if (launch_predict(h->Xin.as<float>(), h->yd.as<float>(), al.as<double>(), h->N, (int64_t)m, xqd,
-                           nq, h->p.gamma, h->lam * h->lam, h->prec == PREC_FP64, fd, s) != hipSuccess) { rc = GABP_E_DEVICE; break; }
-        if (mem == GABP_MEM_HOST &&
-            hipMemcpyAsync(f_out, fo.p, (size_t)nq * 8, hipMemcpyDeviceToHost, s) != hipSuccess) { rc = GABP_E_DEVICE; break; }
-        if (hipStreamSynchronize(s) != hipSuccess) { rc = GABP_E_DEVICE; break; }
-    } while (0);
-    xq.release(); fo.release(); al.release();
-    if (rc != GABP_OK) return fail(h, rc, "predict failed on the device");
+        double* fd = (mem == GABP_MEM_HOST) ? fo.as<double>() : f_out + q0;
+        const int64_t bi = q0 / QMAX;
+        if (f64) {
+            if (timed) HIPCHK(h, hipEventRecord(pev.ev[2 * bi], s));
+            HIPCHK(h, launch_predict_direct(h->Xin.as<float>(), w.as<double>(), N, m, xqd, nb, h->p.gamma,
+                                            part.as<double>(), s));
+            if (timed) HIPCHK(h, hipEventRecord(pev.ev[2 * bi + 1], s));
+            HIPCHK(h, launch_predict_reduce(part.as<double>(), 1, nb, nb, wsum.as<double>(), lam2, fd, s));
+        } else {
+            const int64_t qpad = predict_query_pad(nb);
+            int nc = 1, bp = 1;
+            predict_chunks(NPAD, qpad, &nc, &bp);
+            HIPCHK(h, launch_stage(xqd, h->mean.as<double>(), nb, m, qpad, mp, gram, qf32.as<float>(),
+                                   qhi.as<uint16_t>(), qlo.as<uint16_t>(), qlo2.as<uint16_t>(), nullptr,
+                                   qnrm.as<float>(), s));
+            if (timed) HIPCHK(h, hipEventRecord(pev.ev[2 * bi], s));   // after the query staging
+            HIPCHK(h, launch_predict_mfma(Ft, Fq, w.as<double>(), NPAD, qpad, c, nc, bp, part.as<double>(), s));
+            if (timed) HIPCHK(h, hipEventRecord(pev.ev[2 * bi + 1], s));
+            HIPCHK(h, launch_predict_reduce(part.as<double>(), nc, qpad, nb, wsum.as<double>(), lam2, fd, s));
+        }
+        if (mem == GABP_MEM_HOST)
+            HIPCHK(h, hipMemcpyAsync(f_out + q0, fo.p, (size_t)nb * 8, hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(h, hipStreamSynchronize(s));
+    h->tm.predict_queries = nq;
+    h->tm.predict_kernel_ms = 0.0;
+    if (timed)
+        for (int64_t b = 0; b < nbatch; ++b) {
+            float ms = 0.0f;
+            HIPCHK(h, hipEventElapsedTime(&ms, pev.ev[2 * b], pev.ev[2 * b + 1]));
+            h->tm.predict_kernel_ms += ms;
+        }
     return GABP_OK;
 }
 

@@ -48,7 +48,8 @@ class Params(ct.Structure):
 class Timings(ct.Structure):
     _fields_ = [("stage_ms", ct.c_double), ("kbuild_ms", ct.c_double), ("diag_ms", ct.c_double),
                 ("sweep_loop_ms", ct.c_double), ("sweep_kernel_ms", ct.c_double),
-                ("sweep_launches", ct.c_int64), ("d2h_ms", ct.c_double), ("total_ms", ct.c_double)]
+                ("sweep_launches", ct.c_int64), ("d2h_ms", ct.c_double), ("total_ms", ct.c_double),
+                ("predict_kernel_ms", ct.c_double), ("predict_queries", ct.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -72,6 +73,7 @@ class GabpError(RuntimeError):
 
 
 _lib = None
+ABI_VERSION = 2     # GABP_ABI_VERSION the structures above describe
 
 
 def lib():
@@ -104,6 +106,9 @@ def lib():
         L.gabp_svm_last_error.restype = ct.c_char_p
         L.gabp_abi_version.argtypes = []
         L.gabp_abi_version.restype = i32
+        if L.gabp_abi_version() != ABI_VERSION:
+            raise RuntimeError(f"{LIB_PATH} has ABI version {L.gabp_abi_version()}, the binding expects "
+                               f"{ABI_VERSION}: rebuild with __graft_entry__.build()")
         _lib = L
     return _lib
 

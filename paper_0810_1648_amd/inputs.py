@@ -50,66 +50,104 @@ def _balanced_labels(rng: np.random.Generator, n: int) -> np.ndarray:
     return y
 
 
-def blobs(n: int, m: int, seed: int, spread: float = 1.5):
+def blobs(n: int, m: int, seed: int, spread: float = 1.5, n_test: int = 0):
     """Two isotropic Gaussian blobs with means +-1 on every axis.
 
     ceil(n/2) points carry label +1, the rest -1 (shuffled);
-    x = y * 1 + spread * N(0, I).
+    x = y * 1 + spread * N(0, I).  With n_test > 0, a held-out set drawn
+    the same way from the same stream follows (returned as a second pair).
     """
     rng = np.random.default_rng(seed)
     y = _balanced_labels(rng, n)
     X = y[:, None].astype(np.float64) + spread * rng.standard_normal((n, m))
-    return X.astype(np.float32), y
+    if n_test <= 0:
+        return X.astype(np.float32), y
+    yt = _balanced_labels(rng, n_test)
+    Xt = yt[:, None].astype(np.float64) + spread * rng.standard_normal((n_test, m))
+    return X.astype(np.float32), y, Xt.astype(np.float32), yt
 
 
-def linear_teacher(n: int, m: int, seed: int, noise: float = 0.3):
-    """x ~ N(0, I); y = sign(w.x + noise * eps) with a unit-norm random w."""
+def linear_teacher(n: int, m: int, seed: int, noise: float = 0.3, n_test: int = 0):
+    """x ~ N(0, I); y = sign(w.x + noise * eps) with a unit-norm random w.
+    With n_test > 0, held-out points of the same teacher follow."""
     rng = np.random.default_rng(seed)
     X = rng.standard_normal((n, m))
     w = rng.standard_normal(m)
     w /= np.linalg.norm(w)
     s = X @ w + noise * rng.standard_normal(n)
     y = np.where(s >= 0.0, 1.0, -1.0).astype(np.float32)
-    return X.astype(np.float32), y
+    if n_test <= 0:
+        return X.astype(np.float32), y
+    Xt = rng.standard_normal((n_test, m))
+    st = Xt @ w + noise * rng.standard_normal(n_test)
+    yt = np.where(st >= 0.0, 1.0, -1.0).astype(np.float32)
+    return X.astype(np.float32), y, Xt.astype(np.float32), yt
 
 
 def covertype_like(n: int, m: int, seed: int, onehot_frac: float = 0.2,
-                   n_centres: int = 50, flip: float = 0.05):
+                   n_centres: int = 50, flip: float = 0.05, n_test: int = 0):
     """Uniform [0,1] columns plus a one-hot block, labels from a random
     RBF teacher, then an exact fraction of label flips.
 
     The one-hot block has round(onehot_frac * m) columns, exactly one of
     which is 1 per row (category drawn uniformly).  The teacher is
     f(x) = sum_c beta_c exp(-0.5 ||x - z_c||^2) over n_centres data points
-    z_c with beta ~ N(0, 1); y = sign(f - median f).
+    z_c with beta ~ N(0, 1); y = sign(f - median f).  With n_test > 0,
+    held-out points follow: same columns, same teacher and threshold, the
+    same fraction of flips.
     """
     rng = np.random.default_rng(seed)
     n_hot = int(round(onehot_frac * m))
     n_cont = m - n_hot
-    X = np.zeros((n, m), dtype=np.float64)
-    X[:, :n_cont] = rng.random((n, n_cont))
-    cat = rng.integers(0, n_hot, size=n)
-    X[np.arange(n), n_cont + cat] = 1.0
+
+    def draw(k):
+        Z = np.zeros((k, m), dtype=np.float64)
+        Z[:, :n_cont] = rng.random((k, n_cont))
+        cat = rng.integers(0, n_hot, size=k)
+        Z[np.arange(k), n_cont + cat] = 1.0
+        return Z
+
+    def teacher(Z):
+        f = np.zeros(Z.shape[0])
+        for c in range(n_centres):
+            f += beta[c] * np.exp(-0.5 * ((Z - centres[c]) ** 2).sum(axis=1))
+        return f
+
+    def flipped(lab, k):
+        idx = rng.choice(k, size=int(round(flip * k)), replace=False)
+        lab[idx] = -lab[idx]
+        return lab
+
+    X = draw(n)
     centres = X[rng.choice(n, size=n_centres, replace=False)]
     beta = rng.standard_normal(n_centres)
-    f = np.zeros(n)
-    for c in range(n_centres):
-        f += beta[c] * np.exp(-0.5 * ((X - centres[c]) ** 2).sum(axis=1))
-    y = np.where(f - np.median(f) >= 0.0, 1.0, -1.0)
-    flip_idx = rng.choice(n, size=int(round(flip * n)), replace=False)
-    y[flip_idx] = -y[flip_idx]
-    return X.astype(np.float32), y.astype(np.float32)
+    f = teacher(X)
+    thr = np.median(f)
+    y = flipped(np.where(f - thr >= 0.0, 1.0, -1.0), n)
+    if n_test <= 0:
+        return X.astype(np.float32), y.astype(np.float32)
+    Xt = draw(n_test)
+    yt = flipped(np.where(teacher(Xt) - thr >= 0.0, 1.0, -1.0), n_test)
+    return X.astype(np.float32), y.astype(np.float32), Xt.astype(np.float32), yt.astype(np.float32)
 
 
-def cluster_mixture(n: int, m: int, seed: int, per_class: int = 3):
+def cluster_mixture(n: int, m: int, seed: int, per_class: int = 3, n_test: int = 0):
     """Balanced classes, each a mixture of `per_class` unit Gaussians whose
-    centres are drawn from N(0, I); the cluster of a point is uniform."""
+    centres are drawn from N(0, I); the cluster of a point is uniform.
+    With n_test > 0, held-out points of the same mixture follow."""
     rng = np.random.default_rng(seed)
     centres = rng.standard_normal((2 * per_class, m))
-    y = _balanced_labels(rng, n)
-    k = rng.integers(0, per_class, size=n) + np.where(y > 0, 0, per_class)
-    X = centres[k] + rng.standard_normal((n, m))
-    return X.astype(np.float32), y
+
+    def draw(k_pts):
+        lab = _balanced_labels(rng, k_pts)
+        k = rng.integers(0, per_class, size=k_pts) + np.where(lab > 0, 0, per_class)
+        return (centres[k] + rng.standard_normal((k_pts, m))).astype(np.float32), lab
+
+    X, y = draw(n)
+    if n_test <= 0:
+        return X, y
+    Xt, yt = draw(n_test)
+    return X, y, Xt, yt
 
 
 # The five workloads.  Sizes, dimensions and hyper-parameters of the
@@ -141,6 +179,20 @@ def make_workload(name: str, n: int | None = None, seed: int | None = None) -> W
         return Workload(name, X, y, gamma=0.05, C=1.0, lam=1.0 / n,
                         precision="mixed", tol_rel=1e-7)
     raise ValueError(f"unknown workload {name!r}")
+
+
+def holdout(name: str, n_test: int, n: int | None = None, seed: int | None = None):
+    """The workload `name` (same training set as make_workload) and a
+    held-out set of n_test points from the same generator and teacher."""
+    wl = make_workload(name, n=n, seed=seed)
+    gen = {"tiny": lambda k, s: blobs(k, 10, s, n_test=n_test),
+           "letter": lambda k, s: linear_teacher(k, 100, s, n_test=n_test),
+           "covertype": lambda k, s: covertype_like(k, 54, s, n_test=n_test),
+           "large": lambda k, s: cluster_mixture(k, 20, s, n_test=n_test)}[name]
+    seed0 = {"tiny": 0, "letter": 1, "covertype": 2, "large": 4}[name]
+    X, y, Xt, yt = gen(wl.N, seed0 if seed is None else seed)
+    assert np.array_equal(X, wl.X) and np.array_equal(y, wl.y)
+    return wl, Xt, yt
 
 
 @dataclass

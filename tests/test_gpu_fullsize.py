@@ -73,6 +73,26 @@ def test_covertype_full_mixed(torch, oracle_c, edge):
     s, st = _solve(torch, wl, edge_state=edge)
     assert st == gabp.OK
     _check_rows(s, wl, oracle_c)
+    if edge == "auto":
+        _check_predict(s, wl)
+
+
+def _check_predict(s, wl, n_test=20000, nsample=48):
+    """Decision function on held-out points of the same generator: sampled
+    queries against the oracle's FP64 sum over all N training points, to
+    1e-5 of sum |alpha| (K' <= 1 + lambda^2); held-out accuracy reported."""
+    from oracle import gabp_ref as R
+    wl2, Xt, yt = inputs.holdout(wl.name, n_test, n=wl.N)
+    f = s.predict(Xt)
+    alpha = s.alpha()
+    idx = np.sort(np.random.default_rng(5).choice(n_test, size=nsample, replace=False))
+    ref = R.decision_function(wl.X, wl.y, alpha, Xt[idx], wl.gamma, wl.lam)
+    err = float(np.max(np.abs(f[idx] - ref))) / float(np.sum(np.abs(alpha)))
+    acc = float(np.mean(np.where(f >= 0, 1.0, -1.0) == yt))
+    print(f"{wl.name}: predict {n_test} held-out points, max |f - f_ref| / sum|alpha| = {err:.2e}, "
+          f"held-out accuracy {acc:.4f}")
+    assert err <= TOL
+    assert acc >= 0.8
 
 
 def test_large_full_stateless_recompute(torch, oracle_c):

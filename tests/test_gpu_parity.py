@@ -343,3 +343,54 @@ def test_contraction_bound_matches_oracle(torch, gamma):
         print(f"gamma {gamma} {prec}: rho {rho:.6e} oracle {rho_ref:.6e} reached {reached:.6e}")
         assert abs(rho - rho_ref) <= tol * rho_ref
         assert reached <= rho * (1 + 1e-9)
+
+
+# --------------------------------------------------- decision function (MFMA) --
+
+@pytest.mark.parametrize("prec,gram,m,bound", [
+    ("fp32", "auto", 54, TOL), ("mixed", "bf16x6", 54, TOL), ("mixed", "bf16x6", 10, TOL),
+    ("fp32", "auto", 130, TOL), ("mixed", "bf16x3", 20, 1e-4), ("mixed", "bf16", 130, 1e-2),
+    ("fp64", "auto", 54, 1e-10)])
+def test_predict_matches_oracle_on_held_out_points(torch, prec, gram, m, bound):
+    """f(x_q) on held-out points against the oracle's decision function with
+    the same alpha: |f - f_ref| <= bound * sum_i |alpha_i| (every K' entry is
+    at most 1 + lambda^2, so this is the kernel's relative accuracy).  N and
+    the query count are ragged against the 32-row blocks and the 128-query
+    workgroups; m = 10, 20, 54, 130 cover register-held query fragments of
+    32, 64 and 128 features and the reloading form beyond."""
+    X, y, Xt, yt = inputs.covertype_like(1100, m, 51 + m, n_test=1000)
+    wl = inputs.Workload("covertype-holdout", X, y, gamma=27.0 / m, C=1.0, lam=1.0 / 1100,
+                         precision=prec, tol_rel=1e-9)
+    s, st = run(torch, wl, gram=gram)
+    assert st == gabp.OK
+    alpha = s.alpha()
+    f = s.predict(Xt)
+    ref = R.decision_function(wl.X, wl.y, alpha, Xt, wl.gamma, wl.lam)
+    scale = float(np.sum(np.abs(alpha)))
+    err = float(np.max(np.abs(f - ref))) / scale
+    sure = np.abs(ref) > 2 * bound * scale
+    agree = np.mean(np.sign(f[sure]) == np.sign(ref[sure]))
+    acc = np.mean(np.where(f >= 0, 1.0, -1.0) == yt)
+    print(f"predict {prec}/{gram} m={m}: max |f - f_ref| / sum|alpha| = {err:.2e}; "
+          f"sign agreement {agree:.4f} on {int(sure.sum())}; held-out accuracy {acc:.3f}")
+    assert err <= bound
+    # labels agree wherever the oracle's f is farther from 0 than twice the bound
+    assert not sure.any() or agree == 1.0
+    if bound <= 1e-4:
+        assert sure.sum() >= 100
+    fd = s.predict(torch.from_numpy(Xt).cuda()).cpu().numpy()
+    assert np.array_equal(fd, f)
+    # one query, and the last partial workgroup alone
+    assert np.array_equal(s.predict(Xt[5:6]), f[5:6])
+    assert np.array_equal(s.predict(Xt[-7:]), f[-7:])
+
+
+def test_predict_box_clip_uses_clipped_alpha(torch):
+    wl = inputs.make_workload("covertype", n=900, seed=23)
+    s, st = run(torch, wl, precision="mixed", box_mode="clip_output", C=0.002)
+    a = s.alpha()
+    assert a.max() <= 0.002 and a.min() >= 0.0
+    Xq = inputs.make_workload("covertype", n=300, seed=24).X
+    f = s.predict(Xq)
+    ref = R.decision_function(wl.X, wl.y, a, Xq, wl.gamma, wl.lam)
+    assert float(np.max(np.abs(f - ref))) <= TOL * float(np.sum(np.abs(a)))
