@@ -318,6 +318,155 @@ def gabp_solve_stateless(A, b, depth: int, sweeps: int):
 
 
 # --------------------------------------------------------------------------
+# Grouped (block Gauss-Seidel) schedule
+# --------------------------------------------------------------------------
+#
+# Algorithm 2 leaves the message schedule open, and the section on
+# asynchronous settings reports faster convergence when messages do not wait
+# for a global round.  The deterministic schedule used here splits the nodes
+# into ordered groups; a sweep visits the groups in order, and the visit of
+# group g recomputes every message INTO a node of g from the current
+# aggregates and reverse messages (messages inside g see each other's
+# previous values), then refreshes the aggregates of g.  One group is the
+# synchronous schedule.
+
+
+def gabp_solve_grouped(A, b, groups, max_sweeps: int = 1000, tol_abs: float = 0.0,
+                       tol_rel: float = 1e-12, keep_trajectory: bool = False) -> GabpResult:
+    """Grouped schedule with stored messages (information form).  `groups`
+    is a list of index arrays partitioning 0..n-1, visited in list order.
+    Stop rule and failure flags as gabp_solve, tested after each sweep."""
+    A = np.asarray(A, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    n = len(b)
+    off = ~np.eye(n, dtype=bool)
+    Aoff = np.where(off, A, 0.0)
+    A2 = Aoff * Aoff
+    P = np.zeros((n, n))          # P[i, j]: message i -> j
+    E = np.zeros((n, n))
+    Pt = np.diag(A).copy()
+    S = b.copy()
+    alpha = S / Pt
+    traj = [alpha.copy()] if keep_trajectory else None
+    deltas = []
+    status = NOT_CONVERGED
+    t = 0
+    for t in range(1, max_sweeps + 1):
+        bad = False
+        for g in groups:
+            g = np.asarray(g)
+            # Q[i, j] = P~_i - P_ji for the targets j in g
+            Q = Pt[:, None] - P[g, :].T
+            Qok = np.where(off[:, g], Q, 1.0)
+            if not (np.all(np.isfinite(Qok)) and np.all(Qok > 0.0)):
+                bad = True
+                break
+            Pn = np.where(off[:, g], -A2[:, g] / Qok, 0.0)
+            En = np.where(off[:, g], -Aoff[:, g] * (S[:, None] - E[g, :].T) / Qok, 0.0)
+            P[:, g] = Pn
+            E[:, g] = En
+            Pt[g] = np.diag(A)[g] + P[:, g].sum(axis=0)
+            S[g] = b[g] + E[:, g].sum(axis=0)
+        if bad:
+            status = DIVERGED
+            t -= 1
+            break
+        if not (np.all(np.isfinite(Pt)) and np.all(Pt > 0.0) and np.all(np.isfinite(S))):
+            status = DIVERGED
+            break
+        new = S / Pt
+        d = float(np.max(np.abs(new - alpha)))
+        alpha = new
+        deltas.append(d)
+        if keep_trajectory:
+            traj.append(alpha.copy())
+        if d <= tol_abs + tol_rel * float(np.max(np.abs(alpha))):
+            status = CONVERGED
+            break
+    return GabpResult(alpha, Pt, t, status, deltas, traj)
+
+
+def gabp_solve_grouped_stateless(A, b, groups, depth: int, sweeps: int):
+    """Grouped schedule where each message is rebuilt from the history of
+    aggregates instead of stored messages.
+
+    Visits are numbered tau = t G + g (sweep t, group g).  The message s -> d
+    computed at visit tau uses the aggregates of s as they stand at tau
+    (version = number of visits of s's group before tau) and the reverse
+    message d -> s as last computed, i.e. at the latest visit of s's group
+    strictly before tau (none: zero).  Following that chain `depth` levels
+    and replacing the next reverse message by zero gives the rebuilt
+    message; it equals the stored schedule while the chain reaches the zero
+    start.  Returns alpha after each of the `sweeps` sweeps."""
+    A = np.asarray(A, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    n = len(b)
+    G = len(groups)
+    grp = np.empty(n, dtype=np.int64)
+    for k, g in enumerate(groups):
+        grp[np.asarray(g)] = k
+    def visits_before(gs, tau):
+        # visits u G + gs < tau, u >= 0
+        return np.where(tau > gs, (tau - gs + G - 1) // G, 0)
+
+    def last_visit_before(gs, tau):
+        v = visits_before(gs, tau)
+        return np.where(v > 0, (v - 1) * G + gs, -1)
+
+    # per node, aggregates after each of its versions
+    node_hist_P = [[float(A[k, k])] for k in range(n)]
+    node_hist_S = [[float(b[k])] for k in range(n)]
+
+    def agg_nodes(nodes, versions):
+        Pv = np.array([node_hist_P[k][v] for k, v in zip(nodes.ravel(), versions.ravel())]).reshape(nodes.shape)
+        Sv = np.array([node_hist_S[k][v] for k, v in zip(nodes.ravel(), versions.ravel())]).reshape(nodes.shape)
+        return Pv, Sv
+
+    out = []
+    for t in range(sweeps):
+        for gi, g in enumerate(groups):
+            g = np.asarray(g)
+            tau0 = t * G + gi
+            # chains for all (source s, target d in g), s != d
+            S_idx, D_idx = np.meshgrid(np.arange(n), g, indexing="ij")
+            mask = S_idx != D_idx
+            src, dst = S_idx[mask], D_idx[mask]
+            a = A[src, dst]
+            # walk the chain down: level k message goes from x_k to y_k at visit tau_k
+            taus, xs, ys = [np.full(src.shape, tau0)], [src], [dst]
+            for k in range(1, depth):
+                tau_prev = taus[-1]
+                x_prev, y_prev = xs[-1], ys[-1]
+                # reverse of (x -> y) at tau: (y -> x) at the last visit of grp[x] before tau
+                taus.append(np.where(tau_prev >= 0, last_visit_before(grp[x_prev], tau_prev), -1))
+                xs.append(y_prev)
+                ys.append(x_prev)
+            # deepest level's reverse message is zero; undefined visits give zero messages
+            Pm = np.zeros(src.shape)
+            Em = np.zeros(src.shape)
+            for k in range(depth - 1, -1, -1):
+                tau_k, x_k = taus[k], xs[k]
+                live = tau_k >= 0
+                v = np.where(live, visits_before(grp[x_k], np.maximum(tau_k, 0)), 0)
+                Pv, Sv = agg_nodes(x_k, v)
+                Q = Pv - Pm
+                Pn = np.where(live, -a * a / np.where(live, Q, 1.0), 0.0)
+                En = np.where(live, -a * (Sv - Em) / np.where(live, Q, 1.0), 0.0)
+                Pm, Em = Pn, En
+            Pin = np.zeros((n, len(g)))
+            Ein = np.zeros((n, len(g)))
+            Pin[mask] = Pm
+            Ein[mask] = Em
+            newP = np.diag(A)[g] + Pin.sum(axis=0)
+            newS = b[g] + Ein.sum(axis=0)
+            for q, k in enumerate(g):
+                node_hist_P[k].append(float(newP[q]))
+                node_hist_S[k].append(float(newS[q]))
+        out.append(np.array([node_hist_S[k][-1] / node_hist_P[k][-1] for k in range(n)]))
+    return out
+
+
+# --------------------------------------------------------------------------
 # Closed forms, library solves and bounds used as pins
 # --------------------------------------------------------------------------
 

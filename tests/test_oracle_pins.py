@@ -356,3 +356,81 @@ def test_contraction_bound_holds_along_trajectory(case):
     assert max(tr) <= rho * (1 + 1e-12), (max(tr), rho)
     # the bound is useful: within a small factor of what the sweeps reach
     assert rho <= 2.0 * max(tr)
+
+
+# ------------------------------------------------- grouped (Gauss-Seidel) schedule --
+
+def _tiny_system(n=120, seed=3):
+    wl = inputs.make_workload("tiny", n=n, seed=seed)
+    return R.svm_system(wl.X, wl.y, wl.gamma, wl.C, wl.lam)
+
+
+def test_grouped_with_one_group_is_the_synchronous_schedule():
+    A, b = _tiny_system()
+    n = len(b)
+    r1 = R.gabp_solve(A, b, max_sweeps=8, tol_rel=0.0, keep_trajectory=True)
+    r2 = R.gabp_solve_grouped(A, b, [np.arange(n)], max_sweeps=8, tol_rel=0.0, keep_trajectory=True)
+    for x, y in zip(r1.trajectory, r2.trajectory):
+        assert _rel(y, x) <= 1e-15
+    s1 = R.gabp_solve_stateless(A, b, 3, 8)
+    s2 = R.gabp_solve_grouped_stateless(A, b, [np.arange(n)], 3, 8)
+    for x, y in zip(s1, s2):
+        assert _rel(y, x) <= 1e-15
+
+
+def test_grouped_two_nodes_exact_after_one_sweep():
+    A = np.array([[3.0, -1.2], [-1.2, 2.0]])
+    b = np.array([1.0, 1.0])
+    r = R.gabp_solve_grouped(A, b, [np.array([0]), np.array([1])], max_sweeps=1, tol_rel=0.0)
+    np.testing.assert_allclose(r.alpha, np.linalg.solve(A, b), rtol=1e-15)
+
+
+def test_grouped_serial_chain_first_sweep_is_forward_elimination():
+    # serial order on a chain: after one sweep the last node holds the exact
+    # solution and the exact marginal precision (Gaussian elimination)
+    A = inputs.chain_matrix(6, seed=31)
+    b = np.linspace(1.0, 2.0, 6)
+    r = R.gabp_solve_grouped(A, b, [np.array([k]) for k in range(6)], max_sweeps=1, tol_rel=0.0)
+    x = np.linalg.solve(A, b)
+    assert r.alpha[5] == pytest.approx(x[5], rel=1e-14)
+    assert r.ptilde[5] == pytest.approx(1.0 / np.linalg.inv(A)[5, 5], rel=1e-14)
+    # three nodes, written out
+    a00, a11, a22, a01, a12 = 2.0, 3.0, 2.5, 0.8, -1.1
+    A3 = np.array([[a00, a01, 0.0], [a01, a11, a12], [0.0, a12, a22]])
+    b3 = np.array([1.0, 2.0, 3.0])
+    r3 = R.gabp_solve_grouped(A3, b3, [np.array([0]), np.array([1]), np.array([2])], max_sweeps=1, tol_rel=0.0)
+    p0 = a00 - a01 ** 2 / a11
+    s0 = b3[0] - a01 * b3[1] / a11
+    p1 = a11 - a01 ** 2 / a00 - a12 ** 2 / a22
+    s1 = b3[1] - a01 * b3[0] / a00 - a12 * b3[2] / a22
+    q12 = a11 - a01 ** 2 / a00
+    p2 = a22 - a12 ** 2 / q12
+    s2 = b3[2] - a12 * (b3[1] - a01 * b3[0] / a00) / q12
+    np.testing.assert_allclose(r3.ptilde, [p0, p1, p2], rtol=1e-15)
+    np.testing.assert_allclose(r3.alpha, [s0 / p0, s1 / p1, s2 / p2], rtol=1e-15)
+    assert r3.alpha[2] == pytest.approx(np.linalg.solve(A3, b3)[2], rel=1e-14)
+
+
+@pytest.mark.parametrize("G", [2, 4, 7])
+def test_grouped_fixed_point_is_cholesky_and_comes_sooner(G):
+    A, b = _tiny_system(n=300, seed=5)
+    groups = np.array_split(np.arange(300), G)
+    r = R.gabp_solve_grouped(A, b, groups, max_sweeps=400, tol_rel=1e-13)
+    sync = R.gabp_solve(A, b, max_sweeps=400, tol_rel=1e-13)
+    assert r.status == R.CONVERGED and sync.status == R.CONVERGED
+    assert _rel(r.alpha, R.cholesky_solve(A, b)) <= 1e-10
+    assert 3 * r.sweeps <= sync.sweeps, (r.sweeps, sync.sweeps)
+
+
+def test_grouped_stateless_equals_stored_while_the_chain_reaches_the_start():
+    A, b = _tiny_system()
+    groups = np.array_split(np.arange(len(b)), 4)
+    ref = R.gabp_solve_grouped(A, b, groups, max_sweeps=6, tol_rel=0.0, keep_trajectory=True)
+    errs = {}
+    for depth in (3, 6, 13):
+        st = R.gabp_solve_grouped_stateless(A, b, groups, depth, 6)
+        e = [_rel(st[t - 1], ref.trajectory[t]) for t in range(1, 7)]
+        # each level reaches back half a sweep: exact through sweep depth // 2
+        assert max(e[:depth // 2]) <= 1e-14, (depth, e)
+        errs[depth] = e[-1]
+    assert errs[3] > errs[6] > errs[13] and errs[13] <= 1e-14
