@@ -97,6 +97,7 @@ def parse():
     ap.add_argument("--cpu-sample-n", type=int, default=0, help="oracle sample size (0 = auto)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-predict", action="store_true", help="skip the held-out decision-function measurement")
+    ap.add_argument("--no-grouped", action="store_true", help="skip the grouped-schedule solve")
     ap.add_argument("--predict-n", type=int, default=100000, help="held-out queries of the predict leg")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving measurement")
     ap.add_argument("--serve-requests", type=int, default=512)
@@ -366,6 +367,23 @@ def main():
                                    "alg_bytes_per_pair": sp["alg_bytes_per_pair"]}}
         print(f"[bench] stored state: {ss_} sweeps in {sw_:.3f} s", file=sys.stderr, flush=True)
 
+    grouped = None
+    if not a.no_grouped:
+        gw, gsw, gk, gl, ginfo = solve_steps(torch, gabp, wl, X, y, dict(params, schedule="grouped"),
+                                             a.steps, a.warmup)
+        gp = ginfo["plan"]
+        grouped = {"schedule": "grouped (block Gauss-Seidel)", "groups": gp["sched_groups"],
+                   "sweeps_per_s": gsw / gw, "solves_per_s": a.steps / gw,
+                   "sweeps_per_solve": ginfo["sweeps_per_solve"], "reason": ginfo["reason"],
+                   "sweep_ms_avg": gk / max(gl, 1),
+                   "edge_state": {1: "stored", 2: "stateless"}.get(gp["edge_state"]),
+                   "stateless_depth": gp["stateless_depth"],
+                   "rel_diff_alpha_vs_main": float(np.max(np.abs(ginfo["alpha"] - info["alpha"])) /
+                                                   np.max(np.abs(info["alpha"]))),
+                   "solve_speedup_vs_sync": (a.steps / gw) / (a.steps / wall)}
+        print(f"[bench] grouped schedule: {gsw} sweeps in {gw:.3f} s ({gp['sched_groups']} groups)",
+              file=sys.stderr, flush=True)
+
     predict = None
     if not a.no_predict:
         predict = predict_bench(torch, gabp, inputs, wl, X, y, params, a.predict_n)
@@ -405,6 +423,7 @@ def main():
         "plain_fp32": plain,
         "stored_state": stored_cmp,
         "serving": serving,
+        "grouped_schedule": grouped,
         "predict": predict,
         "roofline": roof,
         "cpu_baseline": cpu,

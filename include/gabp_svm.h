@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define GABP_ABI_VERSION 2
+#define GABP_ABI_VERSION 3
 
 /* Opaque solver handle; owns every device buffer it allocates. */
 typedef struct gabp_svm gabp_svm;
@@ -108,6 +108,16 @@ typedef enum gabp_gram {
     GABP_GRAM_AUTO = 0, GABP_GRAM_BF16 = 1, GABP_GRAM_BF16X3 = 2, GABP_GRAM_BF16X6 = 3
 } gabp_gram;
 
+/* Message schedule (Algorithm 2 leaves it open; section "Convergence in
+ * Asynchronous Settings" reports faster convergence without global rounds):
+ *   SYNC:    every message of sweep t from the values of sweep t-1;
+ *   GROUPED: the points are split into sched_groups ordered groups of whole
+ *            256-point blocks; a sweep visits the groups in order and each
+ *            visit recomputes every message into the group from the current
+ *            aggregates, then refreshes the group's aggregates (block
+ *            Gauss-Seidel).  Same fixed point, far fewer sweeps. */
+typedef enum gabp_sched { GABP_SCHED_SYNC = 0, GABP_SCHED_GROUPED = 1 } gabp_sched;
+
 /* Where the caller's buffers live. */
 typedef enum gabp_mem { GABP_MEM_HOST = 0, GABP_MEM_DEVICE = 1 } gabp_mem;
 
@@ -140,11 +150,14 @@ typedef struct gabp_svm_params {
     int32_t kstore;            /* gabp_kstore */
     int32_t edge_state;        /* gabp_edge */
     int32_t gram;              /* gabp_gram (MIXED only) */
-    int32_t stateless_depth;   /* STATELESS unroll depth; 0 = from the bound */
+    int32_t stateless_depth;   /* STATELESS unroll depth 1..8; 0 = from the bound */
     int32_t device;            /* HIP device ordinal */
     uint64_t hbm_budget_bytes; /* 0 = 90% of the device's free memory */
     int32_t time_sweeps;       /* 1: bracket every sweep kernel with HIP
                                   events (GABP_Q_TIMINGS.sweep_kernel_ms) */
+    int32_t schedule;          /* gabp_sched, default SYNC */
+    int32_t sched_groups;      /* GROUPED: number of node groups (whole
+                                  256-point blocks); 0 = 4 */
     int32_t reserved;
 } gabp_svm_params;
 
@@ -181,7 +194,7 @@ typedef struct gabp_plan {
                                   rho^stateless_depth */
     int32_t series_reciprocal; /* 1: stateless reciprocals of the cavity
                                   precisions by the series around 1/P~ */
-    int32_t reserved;
+    int32_t sched_groups;      /* groups of the GROUPED schedule; 0 = SYNC */
 } gabp_plan;
 
 /* Query selectors for gabp_svm_query: dst type and size in brackets. */
@@ -333,10 +346,10 @@ void gabp_server_params_default(gabp_server_params *p);
 gabp_status gabp_server_create(const gabp_server_params *params, gabp_server **out);
 
 /* Queues one solve: X (N x m float32, row-major, host), y (N float32, +-1,
- * host) and the solver parameters (RBF kernel).  Inputs are copied before
- * the call returns.  *ticket identifies the request.  GABP_E_INVALID for bad
- * inputs or parameters, GABP_E_NOMEM if the request can never fit the
- * arena. */
+ * host) and the solver parameters (RBF kernel, K' materialised, SYNC
+ * schedule).  Inputs are copied before the call returns.  *ticket identifies
+ * the request.  GABP_E_INVALID for bad inputs or parameters, GABP_E_NOMEM if
+ * the request can never fit the arena. */
 gabp_status gabp_server_submit(gabp_server *srv, const float *X, const float *y, int64_t N,
                                int64_t m, const gabp_svm_params *params, uint64_t *ticket);
 

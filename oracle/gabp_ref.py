@@ -413,14 +413,11 @@ def gabp_solve_grouped_stateless(A, b, groups, depth: int, sweeps: int):
         v = visits_before(gs, tau)
         return np.where(v > 0, (v - 1) * G + gs, -1)
 
-    # per node, aggregates after each of its versions
-    node_hist_P = [[float(A[k, k])] for k in range(n)]
-    node_hist_S = [[float(b[k])] for k in range(n)]
-
-    def agg_nodes(nodes, versions):
-        Pv = np.array([node_hist_P[k][v] for k, v in zip(nodes.ravel(), versions.ravel())]).reshape(nodes.shape)
-        Sv = np.array([node_hist_S[k][v] for k, v in zip(nodes.ravel(), versions.ravel())]).reshape(nodes.shape)
-        return Pv, Sv
+    # hist_P[k, v], hist_S[k, v]: aggregates of node k at its version v
+    hist_P = np.zeros((n, sweeps + 1))
+    hist_S = np.zeros((n, sweeps + 1))
+    hist_P[:, 0] = np.diag(A)
+    hist_S[:, 0] = b
 
     out = []
     for t in range(sweeps):
@@ -448,7 +445,7 @@ def gabp_solve_grouped_stateless(A, b, groups, depth: int, sweeps: int):
                 tau_k, x_k = taus[k], xs[k]
                 live = tau_k >= 0
                 v = np.where(live, visits_before(grp[x_k], np.maximum(tau_k, 0)), 0)
-                Pv, Sv = agg_nodes(x_k, v)
+                Pv, Sv = hist_P[x_k, v], hist_S[x_k, v]
                 Q = Pv - Pm
                 Pn = np.where(live, -a * a / np.where(live, Q, 1.0), 0.0)
                 En = np.where(live, -a * (Sv - Em) / np.where(live, Q, 1.0), 0.0)
@@ -459,10 +456,9 @@ def gabp_solve_grouped_stateless(A, b, groups, depth: int, sweeps: int):
             Ein[mask] = Em
             newP = np.diag(A)[g] + Pin.sum(axis=0)
             newS = b[g] + Ein.sum(axis=0)
-            for q, k in enumerate(g):
-                node_hist_P[k].append(float(newP[q]))
-                node_hist_S[k].append(float(newS[q]))
-        out.append(np.array([node_hist_S[k][-1] / node_hist_P[k][-1] for k in range(n)]))
+            hist_P[g, t + 1] = newP
+            hist_S[g, t + 1] = newS
+        out.append(hist_S[:, t + 1] / hist_P[:, t + 1])
     return out
 
 

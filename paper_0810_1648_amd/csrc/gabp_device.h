@@ -455,6 +455,280 @@ __global__ __launch_bounds__(WG) void k_sweep(SweepArgs a) {
     sweep_tile<ST, MT, AT, KSRC, GK, D, FIRST, SER>(a, blockIdx.x, a.slot_top);
 }
 
+// ------------------------------------------------ grouped (Gauss-Seidel) --
+//
+// Grouped schedule: the block rows are split into G ordered groups and a
+// sweep visits them in order; the visit of group g recomputes every message
+// INTO a node of g and then refreshes g's aggregates.  One launch per visit
+// walks a list of (tile, direction) entries (GE_* bits): FWD = the messages
+// i -> j into the column block J, BWD = j -> i into the row block I.
+
+// Version of the source aggregates used at chain level k (k = 0: the message
+// computed now; level k + 1: the reverse message it consumes) for a visit in
+// sweep t, as an offset from t.  A message computed at a visit uses its
+// source's aggregates as they stand then, and the reverse message as last
+// computed, at the latest earlier visit of the source's group:
+//   FWD across groups (row group earlier): row t+1, col t, row t, col t-1, ...
+//   BWD across groups (column group later): col t, row t, col t-1, row t-1, ...
+//   inside the group (Jacobi within g): t, t-1, t-2, ... as in the
+//   synchronous schedule.
+__device__ inline int level_version_offset(bool fwd, bool within, int k) {
+    if (within) return -k;
+    return fwd ? ((k & 1) ? -((k - 1) >> 1) : 1 - (k >> 1)) : -(k >> 1);
+}
+// Sweep of the visit that computed the level-k message, as an offset from t
+// (FWD across: t, t, t-1, t-1, ...; BWD across: t, t-1, t-1, t-2, ...;
+// inside: t - k).  A level whose visit precedes sweep 0 carries the zero
+// start message; across groups its source version can still be 0, so the
+// ring's pre-sweep slots alone do not make it zero.
+__device__ inline int level_visit_offset(bool fwd, bool within, int k) {
+    if (within) return -k;
+    return fwd ? -(k >> 1) : -((k + 1) >> 1);
+}
+
+// LDS of one single-direction visit, declared by the kernel so that both
+// directions share it.
+template <class MT, class LT, class AT, int NRL, int RECOMP>
+struct DirSmem {
+    MT topP[TILE], topS[TILE];            // row source at level 0 (FWD)
+    LT lowP[NRL][TILE], lowS[NRL][TILE];  // row source at lower levels
+    LT lowSI[NRL][TILE];                  // series: S / P~
+    AT rP[4][TILE], rE[4][TILE];          // BWD row partials per wave strip
+    float kband[RECOMP ? 4 : 1][RECOMP ? 32 * 64 : 1];
+};
+
+template <class ST, class MT, class AT, int D, bool SER>
+struct DirTypes {
+    using LT = typename std::conditional<(SER && D <= 3) || std::is_same<ST, double>::value, MT, float>::type;
+    static constexpr int NRL = (D / 2 > 0) ? D / 2 : 1;   // lower row-side levels
+    static constexpr int NCL = (D / 2 > 0) ? D / 2 : 1;   // lower column-side levels
+};
+
+// One direction of one tile.  D = 0: stored pair records (the reverse
+// message is read from its plane, the new one written to the other);
+// D >= 1: the chain of D levels is rebuilt from the aggregate ring, the
+// reverse message below the deepest level taken as zero.  The source's
+// aggregates at version v sit in ring slot v mod R (R = 1 for stored
+// records: every read is the node's latest value).
+template <class ST, class MT, class AT, int KSRC, int GK, int D, bool SER, bool FWD, class SM>
+__device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool within, int t, SM& sm) {
+    using DT = DirTypes<ST, MT, AT, D, SER>;
+    using LT = typename DT::LT;
+    constexpr bool STORED = (D == 0);
+    constexpr int L = STORED ? 1 : D;
+    DevStatus* st = a.st;
+    const uint32_t ij = a.tiles[tile];
+    const TileCoord tc{(int)(ij >> 16), (int)(ij & 0xFFFFu)};
+    const int NB = a.NB;
+    const size_t tbase = (size_t)tile * TT;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, q = l & 15;
+    const int col0 = w * 64 + q * 4;
+    const AT* HP = static_cast<const AT*>(a.HP);
+    const AT* HS = static_cast<const AT*>(a.HS);
+    const ST* Kp = static_cast<const ST*>(a.Kp);
+    auto slot_of = [&](int k) -> int64_t {
+        if constexpr (STORED) return 0;
+        const int v = t + level_version_offset(FWD, within, k);
+        return (int64_t)(((v % a.R) + a.R) % a.R) * a.NPAD;
+    };
+
+    // source data per level: row side in LDS (per row), column side in
+    // registers (the lane's four columns)
+    MT ctP[4], ctS[4];                           // column source at level 0 (BWD)
+    LT clP[DT::NCL][4], clS[DT::NCL][4], clSI[SER ? DT::NCL : 1][4];
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        const bool row_side = FWD ? !(k & 1) : (k & 1);
+        const int64_t base = slot_of(k);
+        // levels computed before sweep 0: P~ = inf, S = 0 give exactly zero messages
+        const bool live = STORED || t + level_visit_offset(FWD, within, k) >= 0;
+        if (row_side) {
+            AT p = HP[base + (int64_t)tc.I * TILE + tid], s = HS[base + (int64_t)tc.I * TILE + tid];
+            if (!live) { p = (AT)INFINITY; s = 0; }
+            if (k == 0) {
+                sm.topP[tid] = SER ? (MT)1 / (MT)p : (MT)p;
+                sm.topS[tid] = (MT)s;
+            } else {
+                const int m = FWD ? (k >> 1) - 1 : (k >> 1);
+                sm.lowP[m][tid] = SER ? (LT)1 / (LT)p : (LT)p;
+                sm.lowS[m][tid] = (LT)s;
+                if constexpr (SER) sm.lowSI[m][tid] = (LT)s / (LT)p;
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                AT p = HP[base + (int64_t)tc.J * TILE + col0 + c];
+                AT s = HS[base + (int64_t)tc.J * TILE + col0 + c];
+                if (!live) { p = (AT)INFINITY; s = 0; }
+                if (k == 0) {
+                    ctP[c] = SER ? (MT)1 / (MT)p : (MT)p;
+                    ctS[c] = (MT)s;
+                } else {
+                    const int m = FWD ? (k >> 1) : (k >> 1) - 1;
+                    clP[m][c] = SER ? (LT)1 / (LT)p : (LT)p;
+                    clS[m][c] = (LT)s;
+                    if constexpr (SER) clSI[m][c] = (LT)s / (LT)p;
+                }
+            }
+        }
+    }
+    AT cP[4] = {0, 0, 0, 0}, cE[4] = {0, 0, 0, 0};
+    bool bad = false;
+    MT emin = 0;
+    __syncthreads();
+
+    // stored records: FWD reads the reverse plane (P_ji, E_ji) and writes
+    // the forward one; BWD the other way round
+    ST* Prd = static_cast<ST*>(FWD ? a.Pb : a.Pf);
+    ST* Erd = static_cast<ST*>(FWD ? a.Eb : a.Ef);
+    ST* Pwr = static_cast<ST*>(FWD ? a.Pf : a.Pb);
+    ST* Ewr = static_cast<ST*>(FWD ? a.Ef : a.Eb);
+
+    size_t off = tbase + (size_t)g * TILE + col0;
+    V4<ST> k4{}, pr{}, er{};
+    if constexpr (KSRC == KSRC_PLANE) k4 = ld4nt(Kp + off);
+    if constexpr (STORED) { pr = ld4nt(Prd + off); er = ld4nt(Erd + off); }
+
+    for (int b = 0; b < TILE / 32; ++b) {
+        if constexpr (KSRC == KSRC_RECOMPUTE) {
+            gram_band<GK>(a.F, a.kp, tc.I, tc.J, 32 * b, 64 * w, sm.kband[w]);
+            wave_lds_sync();
+        }
+#pragma unroll 1
+        for (int s2 = 0; s2 < 8; ++s2) {
+            const int r = 32 * b + 4 * s2 + g;
+            const bool more = (b * 8 + s2 + 1) < TILE / 4;
+            const size_t off2 = more ? off + 4 * TILE : off;
+            V4<ST> k2, pr2, er2;
+            if constexpr (KSRC == KSRC_PLANE) k2 = ld4nt(Kp + off2);
+            if constexpr (STORED) { pr2 = ld4nt(Prd + off2); er2 = ld4nt(Erd + off2); }
+            if constexpr (KSRC == KSRC_RECOMPUTE) {
+                const float4 kk = *reinterpret_cast<const float4*>(&sm.kband[w][(4 * s2 + g) * 64 + 4 * q]);
+                k4 = V4<ST>{{(ST)kk.x, (ST)kk.y, (ST)kk.z, (ST)kk.w}};
+            }
+            AT rp = 0, re = 0;
+            V4<ST> np, ne;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const MT av = (MT)k4.v[c];
+                // reverse message consumed by the top level
+                MT opr, oer;
+                if constexpr (STORED) {
+                    opr = (MT)pr.v[c]; oer = (MT)er.v[c];
+                } else {
+                    const LT al = (LT)k4.v[c], a2l = al * al;
+                    LT lp = 0, le = 0;
+#pragma unroll
+                    for (int k = L - 1; k >= 1; --k) {
+                        const bool row_side = FWD ? !(k & 1) : (k & 1);
+                        const int mr = FWD ? (k >> 1) - 1 : (k >> 1);
+                        const int mc = FWD ? (k >> 1) : (k >> 1) - 1;
+                        const LT pv = row_side ? sm.lowP[mr][r] : clP[mc][c];
+                        const LT sv = row_side ? sm.lowS[mr][r] : clS[mc][c];
+                        if constexpr (SER) {
+                            if (k == L - 1) {            // deepest: reverse message zero
+                                const LT siv = row_side ? sm.lowSI[mr][r] : clSI[mc][c];
+                                lp = -a2l * pv;
+                                le = -al * siv;
+                            } else {
+                                const LT e = lp * pv;
+                                const LT tf = al * fma(pv, e, pv);
+                                const LT np_ = -al * tf;
+                                const LT ne_ = tf * (le - sv);
+                                lp = np_; le = ne_;
+                            }
+                        } else {
+                            const LT qv = pv - lp;
+                            bad |= !(qv > (LT)0);
+                            const LT rv = rcp_fast(qv);
+                            const LT np_ = -a2l * rv;
+                            const LT ne_ = -al * (sv - le) * rv;
+                            lp = np_; le = ne_;
+                        }
+                    }
+                    opr = (MT)lp; oer = (MT)le;
+                }
+                // top level: the message into the target, from the source at level 0
+                const MT pt = FWD ? sm.topP[r] : ctP[c];
+                const MT sv = FWD ? sm.topS[r] : ctS[c];
+                MT pm, em;
+                if constexpr (SER) {
+                    const MT e = opr * pt;
+                    emin = fmin(emin, e);
+                    const MT tf = av * fma(pt, fma(e, e, e), pt);
+                    pm = -av * tf;
+                    em = tf * (oer - sv);
+                } else {
+                    const MT qv = pt - opr;
+                    bad |= !(qv > (MT)0);
+                    const MT rv = rcp_fast(qv);
+                    pm = -(av * av) * rv;
+                    em = -av * (sv - oer) * rv;
+                }
+                if constexpr (STORED) {
+                    const ST ps = (ST)pm, es = (ST)em;
+                    np.v[c] = ps; ne.v[c] = es;
+                    if constexpr (FWD) { cP[c] += (AT)ps; cE[c] += (AT)es; }
+                    else { rp += (AT)ps; re += (AT)es; }
+                } else {
+                    if constexpr (FWD) { cP[c] += (AT)pm; cE[c] += (AT)em; }
+                    else { rp += (AT)pm; re += (AT)em; }
+                }
+            }
+            if constexpr (STORED) { st4nt(Pwr + off, np); st4nt(Ewr + off, ne); }
+            if constexpr (!FWD) {
+                rp = sum16(rp);
+                re = sum16(re);
+                if (q == 0) { sm.rP[w][r] = rp; sm.rE[w][r] = re; }
+            }
+            if constexpr (KSRC == KSRC_PLANE) k4 = k2;
+            if constexpr (STORED) { pr = pr2; er = er2; }
+            off = off2;
+        }
+        if constexpr (KSRC == KSRC_RECOMPUTE) wave_lds_sync();
+    }
+    AT* partP = static_cast<AT*>(a.partP);
+    AT* partE = static_cast<AT*>(a.partE);
+    if constexpr (FWD) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) { cP[c] = sum_groups(cP[c]); cE[c] = sum_groups(cE[c]); }
+        if (g == 0) {
+            const int slot = (tc.I < tc.J) ? tc.I : NB;
+            const size_t cb = ((size_t)tc.J * (NB + 1) + slot) * TILE + col0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) { partP[cb + c] = cP[c]; partE[cb + c] = cE[c]; }
+        }
+    } else {
+        __syncthreads();
+        const size_t rowslot = ((size_t)tc.I * (NB + 1) + tc.J) * TILE + tid;
+        partP[rowslot] = (sm.rP[0][tid] + sm.rP[1][tid]) + (sm.rP[2][tid] + sm.rP[3][tid]);
+        partE[rowslot] = (sm.rE[0][tid] + sm.rE[1][tid]) + (sm.rE[2][tid] + sm.rE[3][tid]);
+    }
+    if constexpr (SER) bad |= !(emin > (MT)-0.5);
+    if (__any(bad) && l == 0) st->bad = 1;
+}
+
+// One visit of the grouped schedule over the entries list[0, n).
+template <class ST, class MT, class AT, int KSRC, int GK, int D, bool SER>
+__global__ __launch_bounds__(WG) void k_sweep_dir(SweepArgs a, const uint32_t* __restrict__ list, int t) {
+    using DT = DirTypes<ST, MT, AT, D, SER>;
+    __shared__ DirSmem<MT, typename DT::LT, AT, DT::NRL, KSRC == KSRC_RECOMPUTE> sm;
+    if (a.st->done) return;
+    const uint32_t e = list[blockIdx.x];
+    const int64_t tile = (int64_t)(e & GE_TILE);
+    const bool within = (e & GE_WITHIN) != 0;
+    if (e & GE_BWD) sweep_tile_dir<ST, MT, AT, KSRC, GK, D, SER, false>(a, tile, within, t, sm);
+    else sweep_tile_dir<ST, MT, AT, KSRC, GK, D, SER, true>(a, tile, within, t, sm);
+}
+
+// Stored records inside a group: both directions from the previous values
+// (Jacobi within the group), over the listed tiles.
+template <class ST, class MT, class AT, int KSRC, int GK>
+__global__ __launch_bounds__(WG) void k_sweep_listed(SweepArgs a, const uint32_t* __restrict__ list) {
+    if (a.st->done) return;
+    sweep_tile<ST, MT, AT, KSRC, GK, 0, false, false>(a, (int64_t)(list[blockIdx.x] & GE_TILE), 0);
+}
+
 // Served form: one persistent grid walks the union work list of (request,
 // tile) items of the active requests of one group (same precision, edge
 // state and level count).  Each request keeps its own planes or aggregate
@@ -555,6 +829,51 @@ inline hipError_t sweep_depth(int levels, bool first, bool ser, const SweepArgs&
         case 6: sweep_d<ST, MT, AT, KSRC, GK, 6, false>(first, a, s); break;
         case 7: sweep_d<ST, MT, AT, KSRC, GK, 7, false>(first, a, s); break;
         case 8: sweep_d<ST, MT, AT, KSRC, GK, 8, false>(first, a, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---- grouped schedule dispatch: one group visit
+template <class ST, class MT, class AT, int KSRC, int GK, int D, bool SER>
+inline void grouped_d(const SweepArgs& a, const uint32_t* list, int n, int t, hipStream_t s) {
+    if (n > 0)
+        hipLaunchKernelGGL((k_sweep_dir<ST, MT, AT, KSRC, GK, D, SER>), dim3((unsigned)n), dim3(WG), 0, s, a, list, t);
+}
+
+// Stored records (levels 0): the tiles inside the group in `within` (both
+// directions), the others in `dir`; stateless: every entry in `dir`.
+template <class ST, class MT, class AT, int KSRC, int GK>
+inline hipError_t sweep_grouped(int levels, bool ser, const SweepArgs& a, const uint32_t* within, int nwithin,
+                                const uint32_t* dir, int ndir, int t, hipStream_t s) {
+    if (levels == 0) {
+        if (nwithin > 0)
+            hipLaunchKernelGGL((k_sweep_listed<ST, MT, AT, KSRC, GK>), dim3((unsigned)nwithin), dim3(WG), 0, s, a,
+                               within);
+        grouped_d<ST, MT, AT, KSRC, GK, 0, false>(a, dir, ndir, t, s);
+        return hipGetLastError();
+    }
+    if (ser) {
+        switch (levels) {
+            case 1: grouped_d<ST, MT, AT, KSRC, GK, 1, true>(a, dir, ndir, t, s); break;
+            case 2: grouped_d<ST, MT, AT, KSRC, GK, 2, true>(a, dir, ndir, t, s); break;
+            case 3: grouped_d<ST, MT, AT, KSRC, GK, 3, true>(a, dir, ndir, t, s); break;
+            case 4: grouped_d<ST, MT, AT, KSRC, GK, 4, true>(a, dir, ndir, t, s); break;
+            case 5: grouped_d<ST, MT, AT, KSRC, GK, 5, true>(a, dir, ndir, t, s); break;
+            case 6: grouped_d<ST, MT, AT, KSRC, GK, 6, true>(a, dir, ndir, t, s); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    switch (levels) {
+        case 1: grouped_d<ST, MT, AT, KSRC, GK, 1, false>(a, dir, ndir, t, s); break;
+        case 2: grouped_d<ST, MT, AT, KSRC, GK, 2, false>(a, dir, ndir, t, s); break;
+        case 3: grouped_d<ST, MT, AT, KSRC, GK, 3, false>(a, dir, ndir, t, s); break;
+        case 4: grouped_d<ST, MT, AT, KSRC, GK, 4, false>(a, dir, ndir, t, s); break;
+        case 5: grouped_d<ST, MT, AT, KSRC, GK, 5, false>(a, dir, ndir, t, s); break;
+        case 6: grouped_d<ST, MT, AT, KSRC, GK, 6, false>(a, dir, ndir, t, s); break;
+        case 7: grouped_d<ST, MT, AT, KSRC, GK, 7, false>(a, dir, ndir, t, s); break;
+        case 8: grouped_d<ST, MT, AT, KSRC, GK, 8, false>(a, dir, ndir, t, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

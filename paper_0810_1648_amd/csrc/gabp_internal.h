@@ -67,6 +67,10 @@ struct KernelParams {
 gabp_status check_params(const gabp_svm_params* p, std::string& why);
 
 inline int64_t n_tiles(int NB) { return (int64_t)NB * (NB + 1) / 2; }
+// Entries of the grouped schedule's visit lists: bit 31 = messages into the
+// row block (BWD; clear: into the column block), bit 30 = both blocks lie in
+// the visited group, low 30 bits = tile index.
+constexpr uint32_t GE_BWD = 0x80000000u, GE_WITHIN = 0x40000000u, GE_TILE = 0x3FFFFFFFu;
 // Storage index of tile (I, J), I <= J: row-major over the upper triangle.
 __host__ __device__ inline int64_t tile_index(int I, int J, int NB) {
     return (int64_t)I * NB - (int64_t)I * (I - 1) / 2 + (J - I);
@@ -158,6 +162,26 @@ hipError_t launch_finalize(int prec, int64_t N, int NB, const void* partP, const
                            const double* Adiag, const float* y, void* Pt, void* S,
                            double* alpha, double* blk_delta, double* blk_amax,
                            DevStatus* st, hipStream_t s);
+// Grouped schedule: one group visit.  `within` lists the stored-record tiles
+// inside the group (both directions), `dir` the single-direction entries
+// (tile index | GE_BWD | GE_WITHIN bits, see gabp_device.h); t = sweep index.
+hipError_t launch_sweep_grouped(int prec, int ksrc, int gram, int levels, bool ser, const SweepArgs& a,
+                                const uint32_t* within, int nwithin, const uint32_t* dir, int ndir, int t,
+                                hipStream_t s);
+hipError_t launch_sweep_grouped_f32(int ksrc, int gram, int levels, bool ser, const SweepArgs& a,
+                                    const uint32_t* within, int nwithin, const uint32_t* dir, int ndir, int t,
+                                    hipStream_t s);
+hipError_t launch_sweep_grouped_mixed(int ksrc, int gram, int levels, bool ser, const SweepArgs& a,
+                                      const uint32_t* within, int nwithin, const uint32_t* dir, int ndir, int t,
+                                      hipStream_t s);
+hipError_t launch_sweep_grouped_f64(int ksrc, int gram, int levels, bool ser, const SweepArgs& a,
+                                    const uint32_t* within, int nwithin, const uint32_t* dir, int ndir, int t,
+                                    hipStream_t s);
+// Finalize of the node blocks [b0, b0 + nb) only (the group just visited).
+hipError_t launch_finalize_range(int prec, int64_t b0, int64_t nb, int64_t N, int NB, const void* partP,
+                                 const void* partE, const double* Adiag, const float* y, void* Pt, void* S,
+                                 double* alpha, double* blk_delta, double* blk_amax, DevStatus* st,
+                                 hipStream_t s);
 hipError_t launch_status(int nblk, const double* blk_delta, const double* blk_amax,
                          DevStatus* st, double* trace, StopRule rule, hipStream_t s);
 // A-priori contraction bound: one[0] = -m* (minus the aggregate lower

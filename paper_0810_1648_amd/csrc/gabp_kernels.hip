@@ -415,6 +415,19 @@ __global__ __launch_bounds__(WG) void k_finalize(int64_t N, int NB, const AT* __
     finalize_block<AT>(blockIdx.x, N, NB, partP, partE, Adiag, y, Pt, S, alpha, blk_delta, blk_amax, st);
 }
 
+// Grouped schedule: the node blocks [b0, b0 + gridDim.x) of one group.
+template <class AT>
+__global__ __launch_bounds__(WG) void k_finalize_range(int64_t b0, int64_t N, int NB, const AT* __restrict__ partP,
+                                                      const AT* __restrict__ partE,
+                                                      const double* __restrict__ Adiag,
+                                                      const float* __restrict__ y, AT* __restrict__ Pt,
+                                                      AT* __restrict__ S, double* __restrict__ alpha,
+                                                      double* __restrict__ blk_delta,
+                                                      double* __restrict__ blk_amax, DevStatus* st) {
+    if (st->done) return;
+    finalize_block<AT>(b0 + blockIdx.x, N, NB, partP, partE, Adiag, y, Pt, S, alpha, blk_delta, blk_amax, st);
+}
+
 // Served form: items are (request, block of 256 nodes).
 template <class AT>
 __global__ __launch_bounds__(WG) void k_finalize_batched(const ReqDesc* __restrict__ reqs,
@@ -662,6 +675,18 @@ hipError_t launch_sweep(int prec, int ksrc, int gram, int levels, bool first, bo
     }
 }
 
+hipError_t launch_sweep_grouped(int prec, int ksrc, int gram, int levels, bool ser, const SweepArgs& a,
+                                const uint32_t* within, int nwithin, const uint32_t* dir, int ndir, int t,
+                                hipStream_t s) {
+    if (levels == 0) ser = false;
+    switch (prec) {
+        case PREC_FP32: return launch_sweep_grouped_f32(ksrc, gram, levels, ser, a, within, nwithin, dir, ndir, t, s);
+        case PREC_MIXED: return launch_sweep_grouped_mixed(ksrc, gram, levels, ser, a, within, nwithin, dir, ndir, t, s);
+        case PREC_FP64: return launch_sweep_grouped_f64(ksrc, gram, levels, ser, a, within, nwithin, dir, ndir, t, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_served_step(int prec, int levels, bool ser, const ReqDesc* reqs, const uint2* tile_items,
                               int ntile_items, const uint2* node_items, int nnode_items, const int* slots,
                               int nslots, DevStatus* status_out, hipStream_t s) {
@@ -694,6 +719,22 @@ hipError_t launch_finalize(int prec, int64_t N, int NB, const void* partP, const
         hipLaunchKernelGGL(k_finalize<double>, g, b, 0, s, N, NB, (const double*)partP,
                            (const double*)partE, Adiag, y, (double*)Pt, (double*)S, alpha,
                            blk_delta, blk_amax, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_range(int prec, int64_t b0, int64_t nb, int64_t N, int NB, const void* partP,
+                                 const void* partE, const double* Adiag, const float* y, void* Pt, void* S,
+                                 double* alpha, double* blk_delta, double* blk_amax, DevStatus* st,
+                                 hipStream_t s) {
+    if (nb <= 0) return hipSuccess;
+    const dim3 g((unsigned)nb), b(WG);
+    if (prec == PREC_FP32)
+        hipLaunchKernelGGL(k_finalize_range<float>, g, b, 0, s, b0, N, NB, (const float*)partP,
+                           (const float*)partE, Adiag, y, (float*)Pt, (float*)S, alpha, blk_delta, blk_amax, st);
+    else
+        hipLaunchKernelGGL(k_finalize_range<double>, g, b, 0, s, b0, N, NB, (const double*)partP,
+                           (const double*)partE, Adiag, y, (double*)Pt, (double*)S, alpha, blk_delta, blk_amax,
+                           st);
     return hipGetLastError();
 }
 

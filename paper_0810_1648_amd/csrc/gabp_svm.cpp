@@ -72,7 +72,9 @@ gabp_status check_params(const gabp_svm_params* p, std::string& why) {
     if (p->kstore < 0 || p->kstore > 2) { why = "unknown kstore"; return GABP_E_INVALID; }
     if (p->edge_state < 0 || p->edge_state > 2) { why = "unknown edge_state"; return GABP_E_INVALID; }
     if (p->gram < 0 || p->gram > 3) { why = "unknown gram"; return GABP_E_INVALID; }
-    if (p->stateless_depth < 0 || p->stateless_depth > 16) { why = "stateless_depth must be in [0, 16]"; return GABP_E_INVALID; }
+    if (p->stateless_depth < 0 || p->stateless_depth > 8) { why = "stateless_depth must be in [0, 8]"; return GABP_E_INVALID; }
+    if (p->schedule < 0 || p->schedule > 1) { why = "unknown schedule"; return GABP_E_INVALID; }
+    if (p->sched_groups < 0 || p->sched_groups > 4096) { why = "sched_groups must be in [0, 4096]"; return GABP_E_INVALID; }
     return GABP_OK;
 }
 }  // namespace gabp
@@ -95,12 +97,12 @@ struct gabp_svm {
     // device memory owned by the handle
     DevBuf tiles, Kp, Pf, Pb, Ef, Eb, partP, partE, Xin, yd, mean, xs32, xhi, xlo, xlo2, x64, nrm, kdiag, rowmax, rsum,
         Adiag, Pt, S, alpha_d, blk1, blk2, one, status_d, trace_d, flag, tmp, Kin, q_rows, q_cols,
-        q_out;
+        q_out, glist;
 
-    DevBuf* all[36] = {&tiles, &Kp, &Pf, &Pb, &Ef, &Eb, &partP, &partE, &Xin, &yd, &mean,
+    DevBuf* all[37] = {&tiles, &Kp, &Pf, &Pb, &Ef, &Eb, &partP, &partE, &Xin, &yd, &mean,
                        &xs32, &xhi, &xlo, &xlo2, &x64, &nrm, &kdiag, &rowmax, &rsum, &Adiag, &Pt, &S, &alpha_d,
                        &blk1, &blk2, &one, &status_d, &trace_d, &flag, &tmp, &Kin, &q_rows,
-                       &q_cols, &q_out, nullptr};
+                       &q_cols, &q_out, &glist, nullptr};
     size_t held() const {
         size_t b = 0;
         for (int k = 0; all[k]; ++k) b += all[k]->bytes;
@@ -405,6 +407,59 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     sa.kp = kp;
     StopRule rule{p.tol_abs, p.tol_rel, p.stagnation_rel, p.max_sweeps, p.stagnation_window};
     const int nblk = (int)((N + WG - 1) / WG);
+
+    // grouped schedule: groups of whole block rows, block I in group I G / NB;
+    // per group the single-direction entries (stateless: every message into
+    // the group; stored: the tiles crossing the group boundary) and, for
+    // stored records, the tiles inside the group
+    const bool grouped = p.schedule == GABP_SCHED_GROUPED;
+    const int G = grouped ? std::min(p.sched_groups > 0 ? p.sched_groups : 4, NB) : 1;
+    std::vector<int64_t> g_within_off(G + 1, 0), g_dir_off(G + 1, 0), g_b0(G + 1, 0);
+    if (grouped) {
+        auto grp = [&](int I) { return (int)((int64_t)I * G / NB); };
+        std::vector<std::vector<uint32_t>> wl(G), dl(G);
+        for (int I = 0; I < NB; ++I)
+            for (int J = I; J < NB; ++J) {
+                const uint32_t k = (uint32_t)tile_index(I, J, NB);
+                const int gi = grp(I), gj = grp(J);
+                if (cur_stored) {
+                    if (gi == gj) wl[gi].push_back(k);
+                    else { dl[gj].push_back(k); dl[gi].push_back(k | GE_BWD); }
+                } else {
+                    const uint32_t in = (gi == gj) ? GE_WITHIN : 0u;
+                    dl[gj].push_back(k | in);
+                    dl[gi].push_back(k | GE_BWD | in);
+                }
+            }
+        std::vector<uint32_t> flat;
+        for (int g = 0; g < G; ++g) {
+            g_within_off[g] = (int64_t)flat.size();
+            flat.insert(flat.end(), wl[g].begin(), wl[g].end());
+            g_within_off[g + 1] = (int64_t)flat.size();
+        }
+        const int64_t nwithin_all = (int64_t)flat.size();
+        for (int g = 0; g < G; ++g) {
+            g_dir_off[g] = (int64_t)flat.size();
+            flat.insert(flat.end(), dl[g].begin(), dl[g].end());
+        }
+        g_dir_off[G] = (int64_t)flat.size();
+        (void)nwithin_all;
+        int gcur = 0;
+        for (int I = 0; I < NB; ++I)
+            while (gcur <= G && grp(I) >= gcur) g_b0[gcur++] = I;
+        while (gcur <= G) g_b0[gcur++] = NB;
+        if (h->glist.ensure(flat.size() * 4) != hipSuccess) {
+            h->release_all();
+            return fail(h, GABP_E_NOMEM, "device allocation of the group lists failed");
+        }
+        HIPCHK(h, hipMemcpyAsync(h->glist.p, flat.data(), flat.size() * 4, hipMemcpyHostToDevice, s));
+        // stored records: a visit reads the reverse message before any
+        // sweep has written it, so the planes start at zero
+        if (cur_stored)
+            for (DevBuf* pl : {&h->Pf, &h->Pb, &h->Ef, &h->Eb})
+                HIPCHK(h, hipMemsetAsync(pl->p, 0, plane, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+    }
     DevStatus hs{};
     double sweep_kernel_ms = 0.0;
     int64_t launches = 0;
@@ -415,14 +470,31 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
         // every stateless sweep unrolls `depth` levels: the ring slots before
         // sweep 0 hold P~ = inf, S = 0, whose messages are exactly zero
         sa.levels = cur_stored ? 0 : depth;
-        if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot], s));
-        HIPCHK(h, launch_sweep(prec, ksrc, gram, sa.levels, t == 0, ser, sa, s));
-        if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot + 1], s));
         char* wP = static_cast<char*>(h->Pt.p) + (size_t)((t + 1) % Rr) * NPAD * agg_bytes;
         char* wS = static_cast<char*>(h->S.p) + (size_t)((t + 1) % Rr) * NPAD * agg_bytes;
-        HIPCHK(h, launch_finalize(prec, N, NB, h->partP.p, h->partE.p, h->Adiag.as<double>(),
-                                  h->yd.as<float>(), wP, wS, h->alpha_d.as<double>(),
-                                  h->blk1.as<double>(), h->blk2.as<double>(), st, s));
+        if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot], s));
+        if (!grouped) {
+            HIPCHK(h, launch_sweep(prec, ksrc, gram, sa.levels, t == 0, ser, sa, s));
+            if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot + 1], s));
+            HIPCHK(h, launch_finalize(prec, N, NB, h->partP.p, h->partE.p, h->Adiag.as<double>(),
+                                      h->yd.as<float>(), wP, wS, h->alpha_d.as<double>(),
+                                      h->blk1.as<double>(), h->blk2.as<double>(), st, s));
+        } else {
+            // one visit per group: its messages, then its aggregates (the
+            // timed span covers the visits and their group finalizes)
+            const uint32_t* gl = h->glist.as<uint32_t>();
+            for (int g = 0; g < G; ++g) {
+                HIPCHK(h, launch_sweep_grouped(prec, ksrc, gram, sa.levels, ser, sa, gl + g_within_off[g],
+                                               (int)(g_within_off[g + 1] - g_within_off[g]), gl + g_dir_off[g],
+                                               (int)(g_dir_off[g + 1] - g_dir_off[g]), t, s));
+                const int64_t b0 = g_b0[g], b1 = std::min<int64_t>(g_b0[g + 1], nblk);
+                HIPCHK(h, launch_finalize_range(prec, b0, b1 - b0, N, NB, h->partP.p, h->partE.p,
+                                                h->Adiag.as<double>(), h->yd.as<float>(), wP, wS,
+                                                h->alpha_d.as<double>(), h->blk1.as<double>(),
+                                                h->blk2.as<double>(), st, s));
+            }
+            if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot + 1], s));
+        }
         HIPCHK(h, launch_status(nblk, h->blk1.as<double>(), h->blk2.as<double>(), st,
                                 h->trace_d.as<double>(), rule, s));
         if ((t + 1) % ce == 0 || t + 1 == p.max_sweeps) {
@@ -490,6 +562,7 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     h->plan.stateless_depth = depth;
     h->plan.stateless_rho = rho;
     h->plan.series_reciprocal = ser ? 1 : 0;
+    h->plan.sched_groups = grouped ? G : 0;
     h->plan.n_blocks = NB;
     h->plan.n_tiles = nt;
     h->plan.device_bytes = h->held();

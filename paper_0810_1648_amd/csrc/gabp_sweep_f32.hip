@@ -17,4 +17,15 @@ hipError_t launch_served_sweep_f32(int levels, bool ser, const ReqDesc* reqs, co
     return served_sweep<float, float, float>(levels, ser, reqs, items, n, s);
 }
 
+hipError_t launch_sweep_grouped_f32(int ksrc, int gram, int levels, bool ser, const SweepArgs& a,
+                                   const uint32_t* within, int nwithin, const uint32_t* dir, int ndir, int t,
+                                   hipStream_t s) {
+    if (ksrc == KSRC_PLANE)
+        return sweep_grouped<float, float, float, KSRC_PLANE, GRAM_F32>(levels, ser, a, within, nwithin, dir, ndir, t, s);
+    switch (gram) {
+        case GRAM_F32: return sweep_grouped<float, float, float, KSRC_RECOMPUTE, GRAM_F32>(levels, ser, a, within, nwithin, dir, ndir, t, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace gabp

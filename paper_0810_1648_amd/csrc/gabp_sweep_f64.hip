@@ -17,4 +17,12 @@ hipError_t launch_served_sweep_f64(int levels, bool ser, const ReqDesc* reqs, co
     return served_sweep<double, double, double>(levels, ser, reqs, items, n, s);
 }
 
+hipError_t launch_sweep_grouped_f64(int ksrc, int gram, int levels, bool ser, const SweepArgs& a,
+                                   const uint32_t* within, int nwithin, const uint32_t* dir, int ndir, int t,
+                                   hipStream_t s) {
+    if (ksrc == KSRC_PLANE)
+        return sweep_grouped<double, double, double, KSRC_PLANE, GRAM_F64>(levels, ser, a, within, nwithin, dir, ndir, t, s);
+    return hipErrorInvalidValue;
+}
+
 }  // namespace gabp

@@ -21,4 +21,17 @@ hipError_t launch_served_sweep_mixed(int levels, bool ser, const ReqDesc* reqs, 
     return served_sweep<float, double, double>(levels, ser, reqs, items, n, s);
 }
 
+hipError_t launch_sweep_grouped_mixed(int ksrc, int gram, int levels, bool ser, const SweepArgs& a,
+                                   const uint32_t* within, int nwithin, const uint32_t* dir, int ndir, int t,
+                                   hipStream_t s) {
+    if (ksrc == KSRC_PLANE)
+        return sweep_grouped<float, double, double, KSRC_PLANE, GRAM_F32>(levels, ser, a, within, nwithin, dir, ndir, t, s);
+    switch (gram) {
+        case GRAM_BF16: return sweep_grouped<float, double, double, KSRC_RECOMPUTE, GRAM_BF16>(levels, ser, a, within, nwithin, dir, ndir, t, s);
+        case GRAM_BF16X3: return sweep_grouped<float, double, double, KSRC_RECOMPUTE, GRAM_BF16X3>(levels, ser, a, within, nwithin, dir, ndir, t, s);
+        case GRAM_BF16X6: return sweep_grouped<float, double, double, KSRC_RECOMPUTE, GRAM_BF16X6>(levels, ser, a, within, nwithin, dir, ndir, t, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace gabp

@@ -25,6 +25,7 @@ PREC = {"fp64": 0, "fp32": 1, "mixed": 2}
 KSTORE = {"auto": 0, "materialise": 1, "recompute": 2}
 EDGE = {"auto": 0, "stored": 1, "stateless": 2}
 GRAM = {"auto": 0, "bf16": 1, "bf16x3": 2, "bf16x6": 3}
+SCHED = {"sync": 0, "grouped": 1}
 MEM_HOST, MEM_DEVICE = 0, 1
 REASON = {0: "none", 1: "converged", 2: "max_sweeps", 3: "diverged", 4: "stagnated"}
 Q_N, Q_ALPHA, Q_PTILDE, Q_ADIAG, Q_BIAS, Q_SV_MASK, Q_SV_COUNT, Q_SWEEPS, Q_DELTA, Q_STATUS, \
@@ -41,7 +42,7 @@ class Params(ct.Structure):
         ("stagnation_rel", ct.c_double), ("precision", ct.c_int32), ("kstore", ct.c_int32),
         ("edge_state", ct.c_int32), ("gram", ct.c_int32), ("stateless_depth", ct.c_int32),
         ("device", ct.c_int32), ("hbm_budget_bytes", ct.c_uint64), ("time_sweeps", ct.c_int32),
-        ("reserved", ct.c_int32),
+        ("schedule", ct.c_int32), ("sched_groups", ct.c_int32), ("reserved", ct.c_int32),
     ]
 
 
@@ -60,7 +61,7 @@ class Plan(ct.Structure):
                 ("gram", ct.c_int32), ("tile", ct.c_int32), ("stateless_depth", ct.c_int32),
                 ("n_blocks", ct.c_int64), ("n_tiles", ct.c_int64), ("device_bytes", ct.c_uint64),
                 ("alg_bytes_per_sweep", ct.c_uint64), ("alg_bytes_per_pair", ct.c_double),
-                ("stateless_rho", ct.c_double), ("series_reciprocal", ct.c_int32), ("reserved", ct.c_int32)]
+                ("stateless_rho", ct.c_double), ("series_reciprocal", ct.c_int32), ("sched_groups", ct.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -73,7 +74,7 @@ class GabpError(RuntimeError):
 
 
 _lib = None
-ABI_VERSION = 2     # GABP_ABI_VERSION the structures above describe
+ABI_VERSION = 3     # GABP_ABI_VERSION the structures above describe
 
 
 def lib():
@@ -124,7 +125,7 @@ def make_params(**kw) -> Params:
     accept the lower-case names of the header (e.g. precision="fp32")."""
     p = default_params()
     maps = {"diag_mode": DIAG, "box_mode": BOX, "precision": PREC, "kstore": KSTORE,
-            "edge_state": EDGE, "gram": GRAM}
+            "edge_state": EDGE, "gram": GRAM, "schedule": SCHED}
     for k, v in kw.items():
         if k in maps and isinstance(v, str):
             v = maps[k][v]

@@ -77,6 +77,15 @@ def test_covertype_full_mixed(torch, oracle_c, edge):
         _check_predict(s, wl)
 
 
+def test_covertype_full_grouped_schedule(torch, oracle_c):
+    """The grouped (block Gauss-Seidel) schedule at the full size, in the plan
+    the benchmark times: same residual-row bound as the synchronous solve."""
+    wl = inputs.make_workload("covertype")
+    s, st = _solve(torch, wl, schedule="grouped")
+    assert st == gabp.OK and s.plan()["sched_groups"] >= 2
+    _check_rows(s, wl, oracle_c, seed=3)
+
+
 def _check_predict(s, wl, n_test=20000, nsample=48):
     """Decision function on held-out points of the same generator: sampled
     queries against the oracle's FP64 sum over all N training points, to

@@ -394,3 +394,57 @@ def test_predict_box_clip_uses_clipped_alpha(torch):
     f = s.predict(Xq)
     ref = R.decision_function(wl.X, wl.y, a, Xq, wl.gamma, wl.lam)
     assert float(np.max(np.abs(f - ref))) <= TOL * float(np.sum(np.abs(a)))
+
+
+# ------------------------------------------------ grouped (Gauss-Seidel) schedule --
+
+def _block_groups(n, G):
+    """The library's groups: 256-point block I belongs to group I G / NB."""
+    NB = (n + 255) // 256
+    G = min(G, NB)
+    blk = np.arange(n) // 256
+    gid = blk * G // NB
+    return [np.nonzero(gid == g)[0] for g in range(G)]
+
+
+@pytest.mark.parametrize("prec,edge,G", [("fp64", "stored", 3), ("fp64", "stateless", 2), ("fp32", "stored", 5),
+                                         ("fp32", "stateless", 3), ("mixed", "stateless", 5), ("mixed", "stored", 2)])
+def test_grouped_schedule_matches_oracle_sweep_by_sweep(torch, prec, edge, G):
+    """Each sweep of the grouped schedule against the oracle's grouped
+    schedule (stored messages, or the same chains rebuilt from the aggregate
+    history at the plan's depth); N = 1100 spans five blocks with a ragged
+    last one, so groups of one, two and uneven block counts occur."""
+    wl = inputs.make_workload("covertype", n=1100, seed=41)
+    A, b = R.svm_system(wl.X, wl.y, wl.gamma, wl.C, wl.lam)
+    groups = _block_groups(1100, G)
+    depth = 3 if edge == "stateless" else 0
+    ref_stored = R.gabp_solve_grouped(A, b, groups, max_sweeps=8, tol_rel=0.0, keep_trajectory=True)
+    ref_sl = R.gabp_solve_grouped_stateless(A, b, groups, depth, 8) if depth else None
+    for t in (1, 2, 3, 5, 8):
+        kw = dict(precision=prec, edge_state=edge, kstore="materialise", schedule="grouped", sched_groups=G,
+                  max_sweeps=t, tol_abs=0.0, tol_rel=0.0, stagnation_window=0)
+        if depth:
+            kw["stateless_depth"] = depth
+        s, st = run(torch, wl, **kw)
+        assert s.sweeps() == t and s.plan()["sched_groups"] == G
+        ref = ref_sl[t - 1] if depth else ref_stored.trajectory[t]
+        err = _rel(s.alpha(), ref)
+        tol = 1e-12 if prec == "fp64" else TOL
+        assert err <= tol, (prec, edge, G, t, err)
+
+
+@pytest.mark.parametrize("prec,kstore", [("fp64", "materialise"), ("fp32", "materialise"), ("mixed", "materialise"),
+                                         ("mixed", "recompute"), ("fp32", "recompute")])
+def test_grouped_schedule_converges_to_the_solution_in_fewer_sweeps(torch, prec, kstore):
+    wl = inputs.make_workload("covertype", n=2600, seed=43)
+    A, b = R.svm_system(wl.X, wl.y, wl.gamma, wl.C, wl.lam)
+    exact = R.cholesky_solve(A, b)
+    out = {}
+    for sched in ("sync", "grouped"):
+        s, st = run(torch, wl, precision=prec, kstore=kstore, schedule=sched, tol_rel=1e-9)
+        assert st == gabp.OK
+        out[sched] = (s.sweeps(), _rel(s.alpha(), exact), s.plan())
+    print(f"{prec}/{kstore}: sync {out['sync'][:2]}, grouped {out['grouped'][:2]} "
+          f"(edge {out['grouped'][2]['edge_state']}, depth {out['grouped'][2]['stateless_depth']})")
+    assert out["grouped"][1] <= TOL
+    assert 3 * out["grouped"][0] <= out["sync"][0]
