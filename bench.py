@@ -63,21 +63,29 @@ def counter_traffic(path, key):
         return None
 
 
-def stateless_slots_per_pair(levels, series):
+def stateless_slots_per_pair(levels, series, precision="mixed"):
     """Algorithmic VALU issue slots per pair of one stateless sweep with
-    `levels` unrolled levels (two directions per pair).
-    Exact reciprocals: each level forms two cavity precisions, two
-    reciprocals (4 issue slots each: transcendental rate) and four messages
-    (10 arithmetic ops), i.e. 18 slots.
-    Series reciprocals: the deepest level starts from zero messages (4 ops);
-    each middle level forms e = P_rev / P~, the one-term reciprocal and four
-    messages (12 ops); the top level uses the two-term series (14 ops).
-    Plus four partial-sum accumulations."""
-    if not series:
-        return levels * (10 + 2 * 4) + 4
-    if levels <= 1:
-        return 14 + 4
-    return 4 + 12 * (levels - 2) + 14 + 4
+    `levels` unrolled levels (both directions of the pair), counting a
+    multiply-add as one slot (fused, as the hardware issues it) and a
+    transcendental as four.  Shared: the conversion of K' to the top level's
+    type (MIXED only) and a^2.
+    Series reciprocals: the deepest level starts from zero messages
+    (4 products); each middle level forms, per direction, e = P_rev / P~, the
+    one-term reciprocal (2), the new P (1) and E (2): 12; the top level forms,
+    per direction, e, the two-term series (2), the scale (1), and the
+    accumulation of P (1, fused) and of E (2, one fused): 14.
+    Exact reciprocals: per direction and level the cavity precision (1), the
+    reciprocal (FP32: 4; FP64: 4 + two Newton steps of 2 FMAs = 8) and the
+    messages (4; 3 at the top, where the accumulations fuse)."""
+    cvt = 1 if precision == "mixed" else 0
+    if series:
+        if levels <= 1:
+            return cvt + 2 * 3
+        return cvt + 1 + 4 + 12 * (levels - 2) + 14
+    r_top = 4 if precision == "fp32" else 8
+    low_double = precision == "fp64" or (series and levels <= 3)
+    r_low = 8 if low_double else 4
+    return cvt + 1 + 2 * (levels - 1) * (1 + r_low + 4) + 2 * (1 + r_top + 3)
 
 
 def parse():
@@ -327,7 +335,7 @@ def main():
     stateless = plan["edge_state"] == gabp.EDGE["stateless"]
     traffic = counter_traffic(a.traffic_json, f"{wl.name}:{N}:{a.precision}:{plan['kstore']}:{plan['edge_state']}")
     if stateless:
-        slots = stateless_slots_per_pair(plan["stateless_depth"], bool(plan["series_reciprocal"]))
+        slots = stateless_slots_per_pair(plan["stateless_depth"], bool(plan["series_reciprocal"]), a.precision)
         achieved = slots * pairs / (avg_ms * 1e-3) / 1e9 if klaunch else None
         roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_GSLOT, "unit": "Gslot/s",
                 "frac": (achieved / VALU_PEAK_GSLOT) if achieved else None, "traffic": traffic,

@@ -239,9 +239,10 @@ __device__ inline void wave_lds_sync() {
 // Work of one tile.  SER (stateless only): the reciprocals of the cavity
 // precisions Q = P~ (1 - e), e = P_reverse / P~, are formed from the
 // per-node 1/P~ by the series 1/Q = (1 + e + e^2 + ...) / P~ (one term at
-// the lower levels, two at the top), valid because |e| <= rho^2 where rho is
-// the contraction estimate; the host enables it only when the neglected terms
-// are below the arithmetic's precision.  The deepest level starts from zero
+// the lower levels, two at the top).  |e| <= rho^2 holds for every message by
+// the a-priori contraction bound (no run-time check is needed); the host
+// enables the series only when the neglected terms are below the
+// arithmetic's precision.  The deepest level starts from zero
 // messages and costs four multiplications.
 template <class ST, class MT, class AT, int KSRC, int GK, int D, bool FIRST, bool SER>
 __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top) {
@@ -275,6 +276,10 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
     __shared__ LT sPtL[NL][NT], sSL[NL][NT], sSIL[SER ? NL : 1][SER ? NT : 1];
     __shared__ AT rP[4][TILE], rE[4][TILE];
     __shared__ float kband[KSRC == KSRC_RECOMPUTE ? 4 : 1][KSRC == KSRC_RECOMPUTE ? 32 * 64 : 1];
+    // stateless: per-lane row partials of two row steps, reduced over the 16
+    // column lanes through LDS once per two steps (a DPP tree per row step
+    // costs 24 VALU slots in FP64; this costs about 5)
+    __shared__ AT red[STORED ? 1 : 4][2][2][64];
 
     const int64_t top = (int64_t)slot_top * a.NPAD;
     {
@@ -313,7 +318,6 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
     }
     AT cP[4] = {0, 0, 0, 0}, cE[4] = {0, 0, 0, 0};
     bool bad = false;
-    MT emin = 0;       // series: smallest e = P_reverse / P~ seen (valid while > -1/2)
     __syncthreads();
 
     size_t off = tbase + (size_t)g * TILE + col0;
@@ -392,7 +396,6 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
                 MT pij_m, eij_m, pji_m, eji_m;
                 if constexpr (SER) {
                     const MT e_f = opb * pti, e_b = opf * ptj[c];      // P_ji / P~_i, P_ij / P~_j
-                    emin = fmin(emin, fmin(e_f, e_b));
                     const MT tf = av * fma(pti, fma(e_f, e_f, e_f), pti);
                     const MT tb = av * fma(ptj[c], fma(e_b, e_b, e_b), ptj[c]);
                     pij_m = -av * tf;
@@ -421,10 +424,33 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
                     rp += (AT)pji_m; re += (AT)eji_m;
                 }
             }
-            if constexpr (STORED) { st4nt(Pf + off, npf); st4nt(Pb + off, npb); st4nt(Ef + off, nef); st4nt(Eb + off, neb); }
-            rp = sum16(rp);
-            re = sum16(re);
-            if (q == 0) { rP[w][r] = rp; rE[w][r] = re; }
+            if constexpr (STORED) {
+                st4nt(Pf + off, npf); st4nt(Pb + off, npb); st4nt(Ef + off, nef); st4nt(Eb + off, neb);
+                rp = sum16(rp);
+                re = sum16(re);
+                if (q == 0) { rP[w][r] = rp; rE[w][r] = re; }
+            } else {
+                red[w][0][s2 & 1][l] = rp;
+                red[w][1][s2 & 1][l] = re;
+                if (s2 & 1) {
+                    // lane l sums quantity l / 32 of row step (l % 32) / 16 and
+                    // row group ((l % 32) / 4) % 4 over the column lanes
+                    // 4 (l % 4) .. +3; the quad then adds its four parts (the
+                    // same sum in every lane: IEEE addition commutes)
+                    wave_lds_sync();
+                    const int qty = l >> 5, idx = l & 31, stp = idx >> 4, gg = (idx >> 2) & 3, pt = idx & 3;
+                    const AT* src = &red[w][qty][stp][16 * gg + 4 * pt];
+                    AT v = (src[0] + src[1]) + (src[2] + src[3]);
+                    v = v + dpp<0xB1>(v);
+                    v = v + dpp<0x4E>(v);
+                    const int row = 32 * b + 4 * ((s2 & 6) + stp) + gg;
+                    if (pt == 0) {
+                        if (qty == 0) rP[w][row] = v;
+                        else rE[w][row] = v;
+                    }
+                    wave_lds_sync();
+                }
+            }
             if constexpr (KSRC == KSRC_PLANE) k = k2;
             if constexpr (STORED && !FIRST) { pf = pf2; pb = pb2; ef = ef2; eb = eb2; }
             off = off2;
@@ -445,7 +471,6 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
 #pragma unroll
         for (int c = 0; c < 4; ++c) { partP[cb + c] = cP[c]; partE[cb + c] = cE[c]; }
     }
-    if constexpr (SER) bad |= !(emin > (MT)-0.5);
     if (__any(bad) && l == 0) st->bad = 1;
 }
 
@@ -494,6 +519,7 @@ struct DirSmem {
     LT lowP[NRL][TILE], lowS[NRL][TILE];  // row source at lower levels
     LT lowSI[NRL][TILE];                  // series: S / P~
     AT rP[4][TILE], rE[4][TILE];          // BWD row partials per wave strip
+    AT red[4][2][2][64];                  // BWD stateless: two row steps of lane partials
     float kband[RECOMP ? 4 : 1][RECOMP ? 32 * 64 : 1];
 };
 
@@ -574,7 +600,6 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
     }
     AT cP[4] = {0, 0, 0, 0}, cE[4] = {0, 0, 0, 0};
     bool bad = false;
-    MT emin = 0;
     __syncthreads();
 
     // stored records: FWD reads the reverse plane (P_ji, E_ji) and writes
@@ -654,7 +679,6 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
                 MT pm, em;
                 if constexpr (SER) {
                     const MT e = opr * pt;
-                    emin = fmin(emin, e);
                     const MT tf = av * fma(pt, fma(e, e, e), pt);
                     pm = -av * tf;
                     em = tf * (oer - sv);
@@ -676,10 +700,29 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
                 }
             }
             if constexpr (STORED) { st4nt(Pwr + off, np); st4nt(Ewr + off, ne); }
-            if constexpr (!FWD) {
+            if constexpr (!FWD && STORED) {
                 rp = sum16(rp);
                 re = sum16(re);
                 if (q == 0) { sm.rP[w][r] = rp; sm.rE[w][r] = re; }
+            } else if constexpr (!FWD) {
+                // row sums over the 16 column lanes through LDS every two row
+                // steps (same scheme as the synchronous stateless sweep)
+                sm.red[w][0][s2 & 1][l] = rp;
+                sm.red[w][1][s2 & 1][l] = re;
+                if (s2 & 1) {
+                    wave_lds_sync();
+                    const int qty = l >> 5, idx = l & 31, stp = idx >> 4, gg = (idx >> 2) & 3, pt = idx & 3;
+                    const AT* src = &sm.red[w][qty][stp][16 * gg + 4 * pt];
+                    AT v = (src[0] + src[1]) + (src[2] + src[3]);
+                    v = v + dpp<0xB1>(v);
+                    v = v + dpp<0x4E>(v);
+                    const int row = 32 * b + 4 * ((s2 & 6) + stp) + gg;
+                    if (pt == 0) {
+                        if (qty == 0) sm.rP[w][row] = v;
+                        else sm.rE[w][row] = v;
+                    }
+                    wave_lds_sync();
+                }
             }
             if constexpr (KSRC == KSRC_PLANE) k4 = k2;
             if constexpr (STORED) { pr = pr2; er = er2; }
@@ -704,7 +747,6 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
         partP[rowslot] = (sm.rP[0][tid] + sm.rP[1][tid]) + (sm.rP[2][tid] + sm.rP[3][tid]);
         partE[rowslot] = (sm.rE[0][tid] + sm.rE[1][tid]) + (sm.rE[2][tid] + sm.rE[3][tid]);
     }
-    if constexpr (SER) bad |= !(emin > (MT)-0.5);
     if (__any(bad) && l == 0) st->bad = 1;
 }
 
