@@ -184,6 +184,84 @@ __device__ inline f32x16 mfma_gram_32x32(const Features& F, int64_t rowA, int64_
     return mfma_gram_32x32<KIND>(F, rowA, F, colB);
 }
 
+// A operand (32 rows) of the MFMA Gram, held in registers while a wave walks
+// many 32-row B blocks, when m_pad <= MP; MP = 0 reloads it every block.
+template <int KIND, int MP> struct RowFrag {
+    static constexpr int NS = (KIND == GRAM_F32) ? MP / 8 : MP / 16;
+    static constexpr int NSA = NS > 0 ? NS : 1;
+    f32x4v f[KIND == GRAM_F32 ? NSA : 1];
+    bf16x8 hi[KIND == GRAM_F32 ? 1 : NSA];
+    bf16x8 lo[(KIND == GRAM_BF16X3 || KIND == GRAM_BF16X6) ? NSA : 1];
+    bf16x8 lo2[KIND == GRAM_BF16X6 ? NSA : 1];
+
+    __device__ void load(const Features& Fq, int64_t rowA) {
+        if constexpr (MP > 0) {
+            const int l = threadIdx.x & 63, h = l >> 5, mp = Fq.m_pad;
+            if constexpr (KIND == GRAM_F32) {
+                const int half = mp >> 1;
+                const float* pa = Fq.f32 + rowA * mp + h * half;
+#pragma unroll
+                for (int s = 0; s < NS; ++s)
+                    if (4 * s < half) f[s] = *reinterpret_cast<const f32x4v*>(pa + 4 * s);
+            } else {
+                const int64_t oa = rowA * mp + 8 * h;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    if (16 * s >= mp) continue;
+                    hi[s] = *reinterpret_cast<const bf16x8*>(Fq.hi + oa + 16 * s);
+                    if constexpr (KIND == GRAM_BF16X3 || KIND == GRAM_BF16X6)
+                        lo[s] = *reinterpret_cast<const bf16x8*>(Fq.lo + oa + 16 * s);
+                    if constexpr (KIND == GRAM_BF16X6)
+                        lo2[s] = *reinterpret_cast<const bf16x8*>(Fq.lo2 + oa + 16 * s);
+                }
+            }
+        }
+    }
+
+    // Gram block of the 32 A rows with the B rows colB (one per lane % 32).
+    __device__ f32x16 gram(const Features& Fq, int64_t rowA, const Features& Ft, int64_t colB) const {
+        if constexpr (MP == 0) {
+            return mfma_gram_32x32<KIND>(Fq, rowA, Ft, colB);
+        } else {
+            const int l = threadIdx.x & 63, h = l >> 5, mp = Ft.m_pad;
+            f32x16 acc = {};
+            if constexpr (KIND == GRAM_F32) {
+                const int half = mp >> 1;
+                const float* pb = Ft.f32 + colB * mp + h * half;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    if (4 * s >= half) continue;
+                    const f32x4v b4 = *reinterpret_cast<const f32x4v*>(pb + 4 * s);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(f[s][0], b4[0], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(f[s][1], b4[1], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(f[s][2], b4[2], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(f[s][3], b4[3], acc, 0, 0, 0);
+                }
+            } else {
+                const int64_t ob = colB * mp + 8 * h;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    if (16 * s >= mp) continue;
+                    const bf16x8 b = *reinterpret_cast<const bf16x8*>(Ft.hi + ob + 16 * s);
+                    if constexpr (KIND == GRAM_BF16X3 || KIND == GRAM_BF16X6) {
+                        const bf16x8 bl = *reinterpret_cast<const bf16x8*>(Ft.lo + ob + 16 * s);
+                        if constexpr (KIND == GRAM_BF16X6) {
+                            const bf16x8 b2 = *reinterpret_cast<const bf16x8*>(Ft.lo2 + ob + 16 * s);
+                            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi[s], b2, acc, 0, 0, 0);
+                            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo2[s], b, acc, 0, 0, 0);
+                            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo[s], bl, acc, 0, 0, 0);
+                        }
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi[s], bl, acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo[s], b, acc, 0, 0, 0);
+                    }
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi[s], b, acc, 0, 0, 0);
+                }
+            }
+            return acc;
+        }
+    }
+};
+
 // K' = exp(-gamma d^2) + lambda^2 with d^2 = max(0, n_i + n_j - 2 G_ij), zero
 // for pairs that are not strictly upper (i >= j) or are padding (j >= N).
 __device__ inline float kernel_entry(float ni, float nj, float g, int64_t i, int64_t j,

@@ -147,6 +147,109 @@ __global__ __launch_bounds__(WG) void k_gram_mfma(Features F, KernelParams kp,
     }
 }
 
+// Materialise the K' tiles and, in the same pass, the partial row and column
+// sums and maxima of K' (>= 0) that the diagonal weighting needs, in the
+// layout of k_rowsum.  Wave w computes the 32-row bands w and w + 4 with the
+// band's A fragments in registers, walking the eight 32-column blocks.  Each
+// 32 x 32 block goes through LDS once: column sums come from the MFMA layout
+// (a lane holds 16 rows of one column), row sums and the 16-byte row stores
+// from the transposed read (eight lanes per row).  All sums in a fixed order.
+template <int KIND, int MP>
+__global__ __launch_bounds__(WG) void k_gram_sums(Features F, KernelParams kp, const uint32_t* __restrict__ tiles,
+                                                 float* __restrict__ Kp, int NB, double* __restrict__ psum,
+                                                 double* __restrict__ pmax) {
+    const TileCoord tc = tile_of(tiles);
+    const size_t tbase = (size_t)blockIdx.x * TT;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, h = l >> 5, l32 = l & 31;
+    __shared__ double csum[4][TILE];
+    __shared__ float cmax[4][TILE];
+    __shared__ float blk[4][32][33];
+    const int64_t i0 = (int64_t)tc.I * TILE, j0 = (int64_t)tc.J * TILE;
+    const int rr = l >> 3, cq = 4 * (l & 7);       // transposed read: row rr + 8 k, columns cq .. cq + 3
+#pragma unroll 1
+    for (int pass = 0; pass < 2; ++pass) {
+        const int band = w + 4 * pass;
+        const int64_t rowA = i0 + band * 32 + l32;
+        float ni[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) ni[r] = F.nrm[i0 + band * 32 + 8 * (r >> 2) + 4 * h + (r & 3)];
+        RowFrag<KIND, MP> fa;
+        fa.load(F, rowA);
+        double rs[4] = {0.0, 0.0, 0.0, 0.0};
+        float rm[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 1
+        for (int cb = 0; cb < TILE / 32; ++cb) {
+            const int64_t colB = j0 + cb * 32 + l32;
+            const f32x16 acc = fa.gram(F, rowA, F, colB);
+            const float nj = F.nrm[colB];
+            double cs = 0.0;
+            float cm = 0.0f;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = 8 * (r >> 2) + 4 * h + (r & 3);
+                const float kv = kernel_entry(ni[r], nj, acc[r], i0 + band * 32 + row, colB, kp);
+                blk[w][row][l32] = kv;
+                cs += (double)kv;
+                cm = fmaxf(cm, kv);
+            }
+            // the column's 32 rows of this band: both lane halves
+            cs = cs + __shfl_xor(cs, 32);
+            cm = fmaxf(cm, __shfl_xor(cm, 32));
+            const int col = cb * 32 + l32;
+            if (h == 0) {
+                if (pass == 0) { csum[w][col] = cs; cmax[w][col] = cm; }
+                else { csum[w][col] += cs; cmax[w][col] = fmaxf(cmax[w][col], cm); }
+            }
+            wave_lds_sync();
+            float* dst = Kp + tbase + (size_t)(band * 32 + rr) * TILE + cb * 32 + cq;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float* src = &blk[w][rr + 8 * k][cq];
+                const f32x4v v = {src[0], src[1], src[2], src[3]};
+                __builtin_nontemporal_store(v, reinterpret_cast<f32x4v*>(dst + (size_t)8 * k * TILE));
+                rs[k] += ((double)v[0] + (double)v[1]) + ((double)v[2] + (double)v[3]);
+                rm[k] = fmaxf(rm[k], fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3])));
+            }
+            wave_lds_sync();
+        }
+        // rows rr + 8 k: the eight lanes of each row add their column quads
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            double v = rs[k];
+            v = v + dpp<0xB1>(v);
+            v = v + dpp<0x4E>(v);
+            v = v + dpp<0x141>(v);
+            float mv = rm[k];
+            mv = fmaxf(mv, dpp<0xB1>(mv));
+            mv = fmaxf(mv, dpp<0x4E>(mv));
+            mv = fmaxf(mv, dpp<0x141>(mv));
+            if ((l & 7) == 0) {
+                const size_t o = ((size_t)tc.I * (NB + 1) + tc.J) * TILE + band * 32 + rr + 8 * k;
+                psum[o] = v;
+                pmax[o] = (double)mv;
+            }
+        }
+    }
+    __syncthreads();
+    const int slot = (tc.I < tc.J) ? tc.I : NB;
+    const size_t cb = ((size_t)tc.J * (NB + 1) + slot) * TILE + tid;
+    psum[cb] = (csum[0][tid] + csum[1][tid]) + (csum[2][tid] + csum[3][tid]);
+    pmax[cb] = (double)fmaxf(fmaxf(cmax[0][tid], cmax[1][tid]), fmaxf(cmax[2][tid], cmax[3][tid]));
+}
+
+template <int KIND>
+void gram_sums_kind(int mp, dim3 g, const Features& F, const KernelParams& kp, const uint32_t* tiles, float* Kp,
+                    int NB, double* psum, double* pmax, hipStream_t s) {
+    if (mp <= 32)
+        hipLaunchKernelGGL((k_gram_sums<KIND, 32>), g, dim3(WG), 0, s, F, kp, tiles, Kp, NB, psum, pmax);
+    else if (mp <= 64)
+        hipLaunchKernelGGL((k_gram_sums<KIND, 64>), g, dim3(WG), 0, s, F, kp, tiles, Kp, NB, psum, pmax);
+    else if (mp <= 128)
+        hipLaunchKernelGGL((k_gram_sums<KIND, 128>), g, dim3(WG), 0, s, F, kp, tiles, Kp, NB, psum, pmax);
+    else
+        hipLaunchKernelGGL((k_gram_sums<KIND, 0>), g, dim3(WG), 0, s, F, kp, tiles, Kp, NB, psum, pmax);
+}
+
 // FP64 K' from direct differences (no Gram expansion, no centring).
 __global__ __launch_bounds__(WG) void k_gram_f64(Features F, KernelParams kp,
                                                 const uint32_t* __restrict__ tiles,
@@ -596,6 +699,20 @@ hipError_t launch_gram(const Features& F, const KernelParams& kp, const uint32_t
         case GRAM_BF16X3: hipLaunchKernelGGL(k_gram_mfma<GRAM_BF16X3>, g, b, 0, s, F, kp, tiles, (float*)Kp); break;
         case GRAM_BF16X6: hipLaunchKernelGGL(k_gram_mfma<GRAM_BF16X6>, g, b, 0, s, F, kp, tiles, (float*)Kp); break;
         case GRAM_F64: hipLaunchKernelGGL(k_gram_f64, g, b, 0, s, F, kp, tiles, (double*)Kp); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_sums(const Features& F, const KernelParams& kp, const uint32_t* tiles, int64_t ntiles,
+                            void* Kp, int NB, double* psum, double* pmax, hipStream_t s) {
+    const dim3 g((unsigned)ntiles);
+    float* K = (float*)Kp;
+    switch (F.kind) {
+        case GRAM_F32: gram_sums_kind<GRAM_F32>(F.m_pad, g, F, kp, tiles, K, NB, psum, pmax, s); break;
+        case GRAM_BF16: gram_sums_kind<GRAM_BF16>(F.m_pad, g, F, kp, tiles, K, NB, psum, pmax, s); break;
+        case GRAM_BF16X3: gram_sums_kind<GRAM_BF16X3>(F.m_pad, g, F, kp, tiles, K, NB, psum, pmax, s); break;
+        case GRAM_BF16X6: gram_sums_kind<GRAM_BF16X6>(F.m_pad, g, F, kp, tiles, K, NB, psum, pmax, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

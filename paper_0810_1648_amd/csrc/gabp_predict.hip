@@ -85,84 +85,6 @@ __global__ __launch_bounds__(WG) void k_predict_direct(const float* __restrict__
     if (threadIdx.x == 0) part[qi] = sh[0];
 }
 
-// A operand (32 query rows) of the MFMA Gram, held in registers for the whole
-// chunk when m_pad <= MP; MP = 0 reloads it every block.
-template <int KIND, int MP> struct QueryFrag {
-    static constexpr int NS = (KIND == GRAM_F32) ? MP / 8 : MP / 16;
-    static constexpr int NSA = NS > 0 ? NS : 1;
-    f32x4v f[KIND == GRAM_F32 ? NSA : 1];
-    bf16x8 hi[KIND == GRAM_F32 ? 1 : NSA];
-    bf16x8 lo[(KIND == GRAM_BF16X3 || KIND == GRAM_BF16X6) ? NSA : 1];
-    bf16x8 lo2[KIND == GRAM_BF16X6 ? NSA : 1];
-
-    __device__ void load(const Features& Fq, int64_t rowA) {
-        if constexpr (MP > 0) {
-            const int l = threadIdx.x & 63, h = l >> 5, mp = Fq.m_pad;
-            if constexpr (KIND == GRAM_F32) {
-                const int half = mp >> 1;
-                const float* pa = Fq.f32 + rowA * mp + h * half;
-#pragma unroll
-                for (int s = 0; s < NS; ++s)
-                    if (4 * s < half) f[s] = *reinterpret_cast<const f32x4v*>(pa + 4 * s);
-            } else {
-                const int64_t oa = rowA * mp + 8 * h;
-#pragma unroll
-                for (int s = 0; s < NS; ++s) {
-                    if (16 * s >= mp) continue;
-                    hi[s] = *reinterpret_cast<const bf16x8*>(Fq.hi + oa + 16 * s);
-                    if constexpr (KIND == GRAM_BF16X3 || KIND == GRAM_BF16X6)
-                        lo[s] = *reinterpret_cast<const bf16x8*>(Fq.lo + oa + 16 * s);
-                    if constexpr (KIND == GRAM_BF16X6)
-                        lo2[s] = *reinterpret_cast<const bf16x8*>(Fq.lo2 + oa + 16 * s);
-                }
-            }
-        }
-    }
-
-    // Gram block of the wave's 32 queries with training rows colB (one per lane % 32).
-    __device__ f32x16 gram(const Features& Fq, int64_t rowA, const Features& Ft, int64_t colB) const {
-        if constexpr (MP == 0) {
-            return mfma_gram_32x32<KIND>(Fq, rowA, Ft, colB);
-        } else {
-            const int l = threadIdx.x & 63, h = l >> 5, mp = Ft.m_pad;
-            f32x16 acc = {};
-            if constexpr (KIND == GRAM_F32) {
-                const int half = mp >> 1;
-                const float* pb = Ft.f32 + colB * mp + h * half;
-#pragma unroll
-                for (int s = 0; s < NS; ++s) {
-                    if (4 * s >= half) continue;
-                    const f32x4v b4 = *reinterpret_cast<const f32x4v*>(pb + 4 * s);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(f[s][0], b4[0], acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(f[s][1], b4[1], acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(f[s][2], b4[2], acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(f[s][3], b4[3], acc, 0, 0, 0);
-                }
-            } else {
-                const int64_t ob = colB * mp + 8 * h;
-#pragma unroll
-                for (int s = 0; s < NS; ++s) {
-                    if (16 * s >= mp) continue;
-                    const bf16x8 b = *reinterpret_cast<const bf16x8*>(Ft.hi + ob + 16 * s);
-                    if constexpr (KIND == GRAM_BF16X3 || KIND == GRAM_BF16X6) {
-                        const bf16x8 bl = *reinterpret_cast<const bf16x8*>(Ft.lo + ob + 16 * s);
-                        if constexpr (KIND == GRAM_BF16X6) {
-                            const bf16x8 b2 = *reinterpret_cast<const bf16x8*>(Ft.lo2 + ob + 16 * s);
-                            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi[s], b2, acc, 0, 0, 0);
-                            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo2[s], b, acc, 0, 0, 0);
-                            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo[s], bl, acc, 0, 0, 0);
-                        }
-                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi[s], bl, acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo[s], b, acc, 0, 0, 0);
-                    }
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi[s], b, acc, 0, 0, 0);
-                }
-            }
-            return acc;
-        }
-    }
-};
-
 // Workgroup (x, y): queries [128 x, 128 x + 128), training blocks of 32 rows
 // [bpc y, bpc (y + 1)).  Wave v owns queries 32 v .. 32 v + 31; lane l's
 // MFMA output register r is query row 8 (r / 4) + 4 (l / 32) + r % 4 and
@@ -177,7 +99,7 @@ __global__ __launch_bounds__(WG) void k_predict_mfma(Features Ft, Features Fq, c
     float ni[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) ni[r] = Fq.nrm[q0 + 8 * (r >> 2) + 4 * h + (r & 3)];
-    QueryFrag<KIND, MP> qa;
+    RowFrag<KIND, MP> qa;
     qa.load(Fq, rowA);
     double acc[16];
 #pragma unroll

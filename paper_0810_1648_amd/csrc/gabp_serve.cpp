@@ -258,10 +258,17 @@ hipError_t setup_request(gabp_server* S, Req& r) {
                     (float*)P(B_X32), (uint16_t*)P(B_XHI), (uint16_t*)P(B_XLO), (uint16_t*)P(B_XLO2),
                     (double*)P(B_X64), (float*)P(B_NRM), s));
     CK(launch_fill_tiles((uint32_t*)P(B_TILES), r.NB, s));
-    CK(launch_gram(F, kp, (uint32_t*)P(B_TILES), r.nt, P(B_KP), s));
+    // same build as the single solve: FP32-stored K' with the row-sum partials
+    // in one pass, FP64 K' followed by its own row-sum pass
+    if (r.gram != GRAM_F64) {
+        CK(launch_gram_sums(F, kp, (uint32_t*)P(B_TILES), r.nt, P(B_KP), r.NB, (double*)P(B_PARTP),
+                            (double*)P(B_PARTE), s));
+    } else {
+        CK(launch_gram(F, kp, (uint32_t*)P(B_TILES), r.nt, P(B_KP), s));
+        CK(launch_rowsum(P(B_KP), r.prec, KSRC_PLANE, F, kp, (uint32_t*)P(B_TILES), r.nt, r.NB,
+                         (double*)P(B_PARTP), (double*)P(B_PARTE), s));
+    }
     CK(launch_fill_value((double*)P(B_KDIAG), r.N, 1.0 + r.lam * r.lam, s));
-    CK(launch_rowsum(P(B_KP), r.prec, KSRC_PLANE, F, kp, (uint32_t*)P(B_TILES), r.nt, r.NB,
-                     (double*)P(B_PARTP), (double*)P(B_PARTE), s));
     CK(launch_diag(r.N, r.NB, (double*)P(B_PARTP), (double*)P(B_PARTE), (double*)P(B_KDIAG),
                    r.p.diag_mode, r.p.C, r.p.diag_delta, (double*)P(B_ADIAG), (double*)P(B_ROWMAX),
                    (double*)P(B_RSUM), (double*)P(B_BLK1), (double*)P(B_ONE), s));

@@ -328,8 +328,14 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
 
     // ---- K' tiles (materialised plan)
     HIPCHK(h, launch_fill_tiles(h->tiles.as<uint32_t>(), NB, s));
+    // FP32-stored K' is built together with the row-sum partials (fused_sums)
+    const bool fused_sums = rbf && kmat && gram != GRAM_F64;
     if (rbf) {
-        if (kmat) HIPCHK(h, launch_gram(F, kp, h->tiles.as<uint32_t>(), nt, h->Kp.p, s));
+        if (fused_sums)
+            HIPCHK(h, launch_gram_sums(F, kp, h->tiles.as<uint32_t>(), nt, h->Kp.p, NB, h->partP.as<double>(),
+                                       h->partE.as<double>(), s));
+        else if (kmat)
+            HIPCHK(h, launch_gram(F, kp, h->tiles.as<uint32_t>(), nt, h->Kp.p, s));
         HIPCHK(h, launch_fill_value(h->kdiag.as<double>(), N, 1.0 + lam * lam, s));
     } else {
         HIPCHK(h, launch_gather_dense(Kd, kp, h->tiles.as<uint32_t>(), nt, h->Kp.p, prec,
@@ -338,8 +344,9 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     HIPCHK(h, hipEventRecord(ev[2], s));
 
     // ---- diagonal weighting and sweep 0
-    HIPCHK(h, launch_rowsum(h->Kp.p, prec, ksrc, F, kp, h->tiles.as<uint32_t>(), nt, NB,
-                            h->partP.as<double>(), h->partE.as<double>(), s));
+    if (!fused_sums)
+        HIPCHK(h, launch_rowsum(h->Kp.p, prec, ksrc, F, kp, h->tiles.as<uint32_t>(), nt, NB,
+                                h->partP.as<double>(), h->partE.as<double>(), s));
     HIPCHK(h, launch_diag(N, NB, h->partP.as<double>(), h->partE.as<double>(), h->kdiag.as<double>(),
                           p.diag_mode, p.C, p.diag_delta, h->Adiag.as<double>(), h->rowmax.as<double>(),
                           h->rsum.as<double>(), h->blk1.as<double>(), h->one.as<double>(), s));
