@@ -434,3 +434,66 @@ def test_grouped_stateless_equals_stored_while_the_chain_reaches_the_start():
         assert max(e[:depth // 2]) <= 1e-14, (depth, e)
         errs[depth] = e[-1]
     assert errs[3] > errs[6] > errs[13] and errs[13] <= 1e-14
+
+
+# ------------------------------------------------------------ sparsified kernel --
+
+def test_sparse_kernel_limits():
+    X, y = inputs.blobs(60, 5, 61)
+    A_dense, b = R.svm_system(X, y, 0.2, 1.0, 1.0 / 60)
+    # a threshold below every kernel value keeps every pair: the dense system
+    D2 = R.pair_sq_distances(X)
+    tau_all = 0.5 * float(np.exp(-0.2 * D2.max()))
+    A_sp, _ = R.sparse_svm_system(X, y, 0.2, 1.0, 1.0 / 60, tau_all)
+    np.testing.assert_array_equal(A_sp, A_dense)
+    # a cut below the smallest distance keeps no pair: diagonal system
+    off = D2[~np.eye(60, dtype=bool)]
+    tau_none = float(np.exp(-0.2 * 0.5 * off.min()))
+    A0, b0 = R.sparse_svm_system(X, y, 0.2, 1.0, 1.0 / 60, tau_none)
+    assert np.count_nonzero(A0 - np.diag(np.diag(A0))) == 0
+    np.testing.assert_allclose(np.diag(A0), 1.0 + (1.0 / 60) ** 2 + 1.0, rtol=1e-15)
+    assert len(R.sparse_edges(X, 0.2, tau_none)) == 0
+
+
+def test_sparse_edges_brute_force():
+    X, _ = inputs.blobs(30, 4, 62)
+    gamma, tau = 0.3, 0.05
+    cut = -np.log(tau) / gamma
+    want = []
+    for i in range(30):
+        for j in range(i + 1, 30):
+            d2 = sum((float(X[i, k]) - float(X[j, k])) ** 2 for k in range(4))
+            if d2 <= cut:
+                want.append((i, j))
+    got = [tuple(e) for e in R.sparse_edges(X, gamma, tau)]
+    assert got == want and 0 < len(want) < 30 * 29 // 2
+
+
+def test_sparse_separated_clusters_decouple():
+    # two clusters far apart and a cut between the intra- and inter-cluster
+    # distances: the system is block diagonal and each block solves alone
+    rng = np.random.default_rng(63)
+    Xa = rng.standard_normal((40, 3))
+    Xb = rng.standard_normal((35, 3)) + 50.0
+    X = np.vstack([Xa, Xb]).astype(np.float32)
+    y = np.where(rng.random(75) < 0.5, 1.0, -1.0).astype(np.float32)
+    gamma, lam, tau = 0.05, 1.0 / 75, 1e-6
+    A, b = R.sparse_svm_system(X, y, gamma, 1.0, lam, tau)
+    assert np.count_nonzero(A[:40, 40:]) == 0
+    full = R.cholesky_solve(A, b)
+    Aa, ba = R.sparse_svm_system(X[:40], y[:40], gamma, 1.0, lam, tau)
+    Ab, bb = R.sparse_svm_system(X[40:], y[40:], gamma, 1.0, lam, tau)
+    np.testing.assert_allclose(full[:40], R.cholesky_solve(Aa, ba), rtol=1e-12)
+    np.testing.assert_allclose(full[40:], R.cholesky_solve(Ab, bb), rtol=1e-12)
+    r = R.gabp_solve(A, b, max_sweeps=500, tol_rel=1e-13)
+    assert r.status == R.CONVERGED and _rel(r.alpha, full) <= 1e-10
+
+
+def test_sparse_threshold_gap():
+    X, _ = inputs.blobs(200, 6, 64)
+    tau, cut = R.sparse_tau_with_gap(X, 0.1, mean_degree=12)
+    D2 = R.pair_sq_distances(X)[np.triu_indices(200, k=1)]
+    assert np.min(np.abs(D2 - cut)) > 1e-3 * cut
+    assert tau == pytest.approx(np.exp(-0.1 * cut), rel=1e-15)
+    deg = 2 * np.count_nonzero(D2 <= cut) / 200
+    assert 6 <= deg <= 24
