@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define GABP_ABI_VERSION 3
+#define GABP_ABI_VERSION 4
 
 /* Opaque solver handle; owns every device buffer it allocates. */
 typedef struct gabp_svm gabp_svm;
@@ -57,8 +57,15 @@ typedef enum gabp_status {
 
 /* Kernel K(x, z).  RBF: exp(-gamma ||x - z||^2), the kernel of every
  * experiment in section "Experimental Results".  PRECOMPUTED: the caller
- * passes the N x N matrix K' itself (gabp_svm_solve_kernel). */
-typedef enum gabp_kernel { GABP_KERNEL_RBF = 0, GABP_KERNEL_PRECOMPUTED = 2 } gabp_kernel;
+ * passes the N x N matrix K' itself (gabp_svm_solve_kernel).  RBF_SPARSE:
+ * the RBF kernel sparsified by a threshold, the route to millions of points
+ * that the closing discussion names: only the pairs with
+ * exp(-gamma ||x_i - x_j||^2) >= sparse_tau are kept (K'_ij = K_ij +
+ * lambda^2 on them, 0 elsewhere); GaBP runs on that graph with the pair
+ * records stored per edge (gabp_svm_solve; FP32 or MIXED, SYNC schedule). */
+typedef enum gabp_kernel {
+    GABP_KERNEL_RBF = 0, GABP_KERNEL_PRECOMPUTED = 2, GABP_KERNEL_RBF_SPARSE = 3
+} gabp_kernel;
 
 /* Diagonal weighting (subsection "GaBP Algorithm Convergence"), with
  * r_i = sum_{j != i} |K'_ij|:
@@ -159,6 +166,7 @@ typedef struct gabp_svm_params {
     int32_t sched_groups;      /* GROUPED: number of node groups (whole
                                   256-point blocks); 0 = 4 */
     int32_t reserved;
+    double sparse_tau;         /* RBF_SPARSE: kernel threshold in (0, 1] */
 } gabp_svm_params;
 
 /* Per-phase device times of the last solve, in milliseconds (HIP events on
@@ -188,13 +196,14 @@ typedef struct gabp_plan {
     uint64_t alg_bytes_per_sweep; /* algorithmic HBM bytes of one sweep:
                                      N(N-1)/2 pairs x bytes per pair */
     double alg_bytes_per_pair;
-    double stateless_rho;      /* contraction estimate max_i max_j |K'_ij| / P~_i
-                                  after sweep 1 (auto depth); the truncation of
-                                  the message recursion is bounded by
+    double stateless_rho;      /* a-priori bound on |A_ij| / Q_ij over every
+                                  sweep (computed before sweep 1); the truncation
+                                  of the message recursion is bounded by about
                                   rho^stateless_depth */
     int32_t series_reciprocal; /* 1: stateless reciprocals of the cavity
                                   precisions by the series around 1/P~ */
     int32_t sched_groups;      /* groups of the GROUPED schedule; 0 = SYNC */
+    int64_t n_edges;           /* RBF_SPARSE: kept pairs (graph edges); else 0 */
 } gabp_plan;
 
 /* Query selectors for gabp_svm_query: dst type and size in brackets. */
@@ -212,7 +221,9 @@ enum {
     GABP_Q_TIMINGS = 10,   /* [gabp_timings] */
     GABP_Q_TRACE = 11,     /* [double sweeps] change per sweep, t = 1..sweeps */
     GABP_Q_PLAN = 12,      /* [gabp_plan] */
-    GABP_Q_REASON = 13     /* [int32_t] gabp_reason */
+    GABP_Q_REASON = 13,    /* [int32_t] gabp_reason */
+    GABP_Q_EDGES = 14      /* [int64_t 2 x n_edges] RBF_SPARSE: kept pairs
+                              (i, j), i < j, in lexicographic order */
 };
 
 /* Fills *p with the defaults: RBF, gamma 1, C 1, lambda 1/N, DOMINANT_ROW
@@ -263,7 +274,7 @@ gabp_status gabp_svm_kernel_entries(const gabp_svm *h, const int64_t *rows,
  * f(x) = sum_i alpha_i y_i (K(x_i, x) + lambda^2) for the nq query points
  * Xq (nq x m float32, row-major; m of the last solve); f_out receives nq
  * float64 values; the class is sign(f) with sign(0) = +1.  mem applies to
- * Xq and f_out alike.  RBF solves only (GABP_E_STATE otherwise). */
+ * Xq and f_out alike.  Dense RBF solves only (GABP_E_STATE otherwise). */
 gabp_status gabp_svm_predict(gabp_svm *h, const float *Xq, int64_t nq,
                              double *f_out, int32_t mem, void *stream);
 

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libgabp_svm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["gabp_sweep_mixed.hip", "gabp_sweep_f32.hip", "gabp_sweep_f64.hip", "gabp_kernels.hip",
-           "gabp_predict.hip", "gabp_svm.cpp", "gabp_serve.cpp"]
+           "gabp_predict.hip", "gabp_sparse.hip", "gabp_svm.cpp", "gabp_serve.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include")]

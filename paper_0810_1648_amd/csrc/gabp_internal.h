@@ -181,6 +181,27 @@ hipError_t launch_sweep_grouped_mixed(int ksrc, int gram, int levels, bool ser, 
 hipError_t launch_sweep_grouped_f64(int ksrc, int gram, int levels, bool ser, const SweepArgs& a,
                                     const uint32_t* within, int nwithin, const uint32_t* dir, int ndir, int t,
                                     hipStream_t s);
+// Sparsified kernel (gabp_sparse.hip): build passes, sorts and scans (the
+// temporary storage size comes back in *bytes when tmp is NULL), and the
+// sweep (edge update + per-node gather into one partial per node).
+hipError_t launch_sp_count(const Features& F, const uint32_t* tiles, int64_t ntiles, int64_t N, float cut,
+                           int32_t* counts, hipStream_t s);
+hipError_t launch_sp_fill(const Features& F, const uint32_t* tiles, int64_t ntiles, int64_t N, float cut,
+                          float neg_gamma_log2e, float lam2, const int64_t* offsets, const int32_t* counts,
+                          uint64_t* keys, float* kv, int32_t* flag, hipStream_t s);
+hipError_t sp_scan(void* tmp, size_t* bytes, const int32_t* in, int64_t* out, int64_t n, hipStream_t s);
+hipError_t sp_sort_keys(void* tmp, size_t* bytes, const uint64_t* kin, uint64_t* kout, const float* vin,
+                        float* vout, int64_t n, hipStream_t s);
+hipError_t sp_sort_ids(void* tmp, size_t* bytes, const uint64_t* kin, uint64_t* kout, const int32_t* vin,
+                       int32_t* vout, int64_t n, hipStream_t s);
+hipError_t launch_sp_unpack(const uint64_t* keys, int64_t E, int32_t* ei, int32_t* ej, int32_t* deg_i,
+                            int32_t* deg_j, uint64_t* keys_t, int32_t* ids, hipStream_t s);
+hipError_t launch_sp_rowsum(int64_t N, const int64_t* off_i, const int64_t* off_j, const int32_t* perm,
+                            const float* kv, double* psum, double* pmax, hipStream_t s);
+hipError_t launch_sp_sweep(int prec, int64_t E, int64_t N, const int32_t* ei, const int32_t* ej, const float* kv,
+                           const void* Pt, const void* S, void* Pf, void* Pb, void* Ef, void* Eb,
+                           const int64_t* off_i, const int64_t* off_j, const int32_t* perm, void* partP,
+                           void* partE, DevStatus* st, hipStream_t s);
 // Finalize of the node blocks [b0, b0 + nb) only (the group just visited).
 hipError_t launch_finalize_range(int prec, int64_t b0, int64_t nb, int64_t N, int NB, const void* partP,
                                  const void* partE, const double* Adiag, const float* y, void* Pt, void* S,

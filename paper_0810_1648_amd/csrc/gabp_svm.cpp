@@ -58,8 +58,13 @@ namespace gabp {
 gabp_status check_params(const gabp_svm_params* p, std::string& why) {
     if (!p) { why = "params is NULL"; return GABP_E_INVALID; }
     if (p->struct_size != sizeof(gabp_svm_params)) { why = "params.struct_size mismatch"; return GABP_E_INVALID; }
-    if (p->kernel != GABP_KERNEL_RBF && p->kernel != GABP_KERNEL_PRECOMPUTED) { why = "unknown kernel"; return GABP_E_INVALID; }
-    if (p->kernel == GABP_KERNEL_RBF && !(p->gamma > 0.0 && std::isfinite(p->gamma))) { why = "gamma must be > 0"; return GABP_E_INVALID; }
+    if (p->kernel != GABP_KERNEL_RBF && p->kernel != GABP_KERNEL_PRECOMPUTED && p->kernel != GABP_KERNEL_RBF_SPARSE) { why = "unknown kernel"; return GABP_E_INVALID; }
+    if (p->kernel != GABP_KERNEL_PRECOMPUTED && !(p->gamma > 0.0 && std::isfinite(p->gamma))) { why = "gamma must be > 0"; return GABP_E_INVALID; }
+    if (p->kernel == GABP_KERNEL_RBF_SPARSE) {
+        if (!(p->sparse_tau > 0.0 && p->sparse_tau <= 1.0)) { why = "sparse_tau must be in (0, 1]"; return GABP_E_INVALID; }
+        if (p->precision == GABP_PREC_FP64) { why = "the sparsified kernel runs in FP32 or MIXED precision"; return GABP_E_INVALID; }
+        if (p->schedule != GABP_SCHED_SYNC) { why = "the sparsified kernel runs the SYNC schedule"; return GABP_E_INVALID; }
+    }
     if (!(p->C > 0.0) || !std::isfinite(p->C)) { why = "C must be > 0"; return GABP_E_INVALID; }
     if (p->diag_mode < 0 || p->diag_mode > 3) { why = "unknown diag_mode"; return GABP_E_INVALID; }
     if (!(p->diag_delta >= 0.0)) { why = "diag_delta must be >= 0"; return GABP_E_INVALID; }
@@ -98,11 +103,19 @@ struct gabp_svm {
     DevBuf tiles, Kp, Pf, Pb, Ef, Eb, partP, partE, Xin, yd, mean, xs32, xhi, xlo, xlo2, x64, nrm, kdiag, rowmax, rsum,
         Adiag, Pt, S, alpha_d, blk1, blk2, one, status_d, trace_d, flag, tmp, Kin, q_rows, q_cols,
         q_out, glist;
+    // sparsified kernel: tile counts and offsets, keys, K' per edge, edge
+    // ends, degrees and offsets of the i-end and j-end lists, permutation
+    DevBuf sp_cnt, sp_toff, sp_keys, sp_keys2, sp_kv, sp_kv2, sp_ei, sp_ej, sp_degi, sp_degj, sp_offi,
+        sp_offj, sp_ids, sp_perm, sp_tmp;
+    bool sparse = false;
+    int64_t n_edges = 0;
 
-    DevBuf* all[37] = {&tiles, &Kp, &Pf, &Pb, &Ef, &Eb, &partP, &partE, &Xin, &yd, &mean,
+    DevBuf* all[52] = {&tiles, &Kp, &Pf, &Pb, &Ef, &Eb, &partP, &partE, &Xin, &yd, &mean,
                        &xs32, &xhi, &xlo, &xlo2, &x64, &nrm, &kdiag, &rowmax, &rsum, &Adiag, &Pt, &S, &alpha_d,
                        &blk1, &blk2, &one, &status_d, &trace_d, &flag, &tmp, &Kin, &q_rows,
-                       &q_cols, &q_out, &glist, nullptr};
+                       &q_cols, &q_out, &glist, &sp_cnt, &sp_toff, &sp_keys, &sp_keys2, &sp_kv, &sp_kv2,
+                       &sp_ei, &sp_ej, &sp_degi, &sp_degj, &sp_offi, &sp_offj, &sp_ids, &sp_perm, &sp_tmp,
+                       nullptr};
     size_t held() const {
         size_t b = 0;
         for (int k = 0; all[k]; ++k) b += all[k]->bytes;
@@ -575,7 +588,275 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     h->plan.device_bytes = h->held();
     h->plan.alg_bytes_per_pair = (double)st_bytes * ((stored ? 8.0 : 0.0) + (kmat ? 1.0 : 0.0));
     h->plan.alg_bytes_per_sweep = (uint64_t)((double)N * (double)(N - 1) / 2.0 * h->plan.alg_bytes_per_pair);
+    h->sparse = false;
+    h->n_edges = 0;
     h->have_result = true;
+    if (h->status != GABP_OK) {
+        h->err = (h->status == GABP_E_DIVERGED) ? "GaBP diverged: a cavity precision became <= 0 or non-finite"
+                                                : "max_sweeps reached before the stop rule held";
+    }
+    return (gabp_status)h->status;
+}
+
+// Sparsified RBF kernel: graph build on the device, then synchronous GaBP on
+// the kept pairs with stored records per edge (see gabp_sparse.hip).
+gabp_status solve_sparse_impl(gabp_svm* h, const float* X, const float* y, int64_t N, int64_t m, int32_t mem,
+                              hipStream_t s) {
+    const double t_start = now_ms();
+    h->have_result = false;
+    h->status = GABP_E_STATE;
+    const gabp_svm_params& p = h->p;
+    if (N < 1 || m < 1 || !y) return fail(h, GABP_E_INVALID, "N >= 1, m >= 1 and y are required");
+    if (mem != GABP_MEM_HOST && mem != GABP_MEM_DEVICE) return fail(h, GABP_E_INVALID, "unknown mem kind");
+    if (N > (int64_t)TILE * 65535) return fail(h, GABP_E_INVALID, "N too large for 16-bit tile coordinates");
+    if (mem == GABP_MEM_HOST) {
+        for (int64_t k = 0; k < N * m; ++k)
+            if (!std::isfinite(X[k])) return fail(h, GABP_E_INVALID, "X has a non-finite entry");
+        for (int64_t k = 0; k < N; ++k)
+            if (!(y[k] == 1.0f || y[k] == -1.0f)) return fail(h, GABP_E_INVALID, "labels must be +1 or -1");
+    }
+    const int prec = p.precision;
+    const int gram = (prec == PREC_FP32) ? GRAM_F32
+                   : (p.gram == GABP_GRAM_BF16) ? GRAM_BF16 : (p.gram == GABP_GRAM_BF16X3) ? GRAM_BF16X3 : GRAM_BF16X6;
+    const int NB = (int)((N + TILE - 1) / TILE);
+    const int64_t NPAD = (int64_t)NB * TILE;
+    const int64_t nt = n_tiles(NB);
+    const int m_pad = (int)((m + 15) / 16 * 16);
+    const size_t agg = (prec == PREC_FP32) ? 4 : 8;
+    const double lam = (p.lambda_aug < 0.0) ? 1.0 / (double)N : p.lambda_aug;
+    const double cut = -std::log(p.sparse_tau) / p.gamma;
+    HIPCHK(h, hipSetDevice(p.device));
+    h->release_all();
+
+    hipError_t ae = hipSuccess;
+    auto A = [&](DevBuf& b, size_t n) { if (ae == hipSuccess) ae = b.ensure(std::max<size_t>(n, 16)); };
+    A(h->tiles, (size_t)nt * 4);
+    A(h->Xin, (size_t)N * m * 4); A(h->mean, (size_t)m * 8); A(h->nrm, (size_t)NPAD * 4);
+    if (gram == GRAM_F32) A(h->xs32, (size_t)NPAD * m_pad * 4);
+    else {
+        A(h->xhi, (size_t)NPAD * m_pad * 2);
+        if (gram != GRAM_BF16) A(h->xlo, (size_t)NPAD * m_pad * 2);
+        if (gram == GRAM_BF16X6) A(h->xlo2, (size_t)NPAD * m_pad * 2);
+    }
+    A(h->yd, (size_t)N * 4);
+    A(h->sp_cnt, (size_t)nt * 4); A(h->sp_toff, (size_t)nt * 8);
+    A(h->partP, (size_t)NPAD * 8); A(h->partE, (size_t)NPAD * 8);
+    A(h->kdiag, (size_t)N * 8); A(h->Adiag, (size_t)N * 8); A(h->rowmax, (size_t)N * 8);
+    A(h->rsum, (size_t)N * 8);
+    A(h->Pt, (size_t)NPAD * 8); A(h->S, (size_t)NPAD * 8);
+    A(h->alpha_d, (size_t)N * 8); A(h->tmp, (size_t)NPAD * 8);
+    A(h->blk1, (size_t)(NPAD / WG + 1) * 8); A(h->blk2, (size_t)(NPAD / WG + 1) * 8);
+    A(h->one, 64); A(h->status_d, sizeof(DevStatus)); A(h->flag, 64);
+    A(h->trace_d, (size_t)p.max_sweeps * 8);
+    A(h->sp_degi, (size_t)(N + 1) * 4); A(h->sp_degj, (size_t)(N + 1) * 4);
+    A(h->sp_offi, (size_t)(N + 1) * 8); A(h->sp_offj, (size_t)(N + 1) * 8);
+    if (ae != hipSuccess) {
+        h->release_all();
+        return fail(h, GABP_E_NOMEM, std::string("device allocation failed: ") + hipGetErrorString(ae));
+    }
+    EventPool evp;
+    const int ce = p.check_every;
+    HIPCHK(h, evp.make(6 + 2 * (size_t)ce));
+    hipEvent_t* ev = evp.ev.data();
+    hipEvent_t* sev = ev + 6;
+
+    // ---- inputs and staging (as the dense RBF solve)
+    HIPCHK(h, hipEventRecord(ev[0], s));
+    const hipMemcpyKind kind = (mem == GABP_MEM_HOST) ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    HIPCHK(h, hipMemcpyAsync(h->yd.p, y, (size_t)N * 4, kind, s));
+    HIPCHK(h, hipMemcpyAsync(h->Xin.p, X, (size_t)N * m * 4, kind, s));
+    const float* Xd = h->Xin.as<float>();
+    if (mem == GABP_MEM_DEVICE) {
+        HIPCHK(h, hipMemsetAsync(h->flag.p, 0, 4, s));
+        HIPCHK(h, launch_validate(Xd, h->yd.as<float>(), N, m, h->flag.as<int32_t>(), s));
+        int32_t fl = 0;
+        HIPCHK(h, hipMemcpyAsync(&fl, h->flag.p, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+        if (fl & 1) return fail(h, GABP_E_INVALID, "X has a non-finite entry");
+        if (fl & 2) return fail(h, GABP_E_INVALID, "labels must be +1 or -1");
+    }
+    Features F{};
+    F.m_pad = m_pad;
+    F.kind = gram;
+    HIPCHK(h, launch_colmean(Xd, N, m, h->mean.as<double>(), s));
+    HIPCHK(h, launch_stage(Xd, h->mean.as<double>(), N, m, NPAD, m_pad, gram, h->xs32.as<float>(),
+                           h->xhi.as<uint16_t>(), h->xlo.as<uint16_t>(), h->xlo2.as<uint16_t>(), nullptr,
+                           h->nrm.as<float>(), s));
+    F.f32 = h->xs32.as<float>(); F.hi = h->xhi.as<uint16_t>(); F.lo = h->xlo.as<uint16_t>();
+    F.lo2 = h->xlo2.as<uint16_t>(); F.nrm = h->nrm.as<float>();
+    HIPCHK(h, hipEventRecord(ev[1], s));
+
+    // ---- graph: count per tile, offsets, fill, sort by (i, j), transposed order
+    HIPCHK(h, launch_fill_tiles(h->tiles.as<uint32_t>(), NB, s));
+    const float cutf = (float)cut;
+    HIPCHK(h, launch_sp_count(F, h->tiles.as<uint32_t>(), nt, N, cutf, h->sp_cnt.as<int32_t>(), s));
+    size_t tb = 0;
+    HIPCHK(h, sp_scan(nullptr, &tb, h->sp_cnt.as<int32_t>(), h->sp_toff.as<int64_t>(), nt, s));
+    if (h->sp_tmp.ensure(tb) != hipSuccess) { h->release_all(); return fail(h, GABP_E_NOMEM, "scan storage"); }
+    HIPCHK(h, sp_scan(h->sp_tmp.p, &tb, h->sp_cnt.as<int32_t>(), h->sp_toff.as<int64_t>(), nt, s));
+    int64_t last_off = 0;
+    int32_t last_cnt = 0;
+    HIPCHK(h, hipMemcpyAsync(&last_off, h->sp_toff.as<int64_t>() + (nt - 1), 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipMemcpyAsync(&last_cnt, h->sp_cnt.as<int32_t>() + (nt - 1), 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    const int64_t E = last_off + last_cnt;
+    if (E >= (int64_t)1 << 31) return fail(h, GABP_E_INVALID, "more than 2^31 - 1 kept pairs: raise sparse_tau");
+    const size_t st_bytes = 4;   // records and K' per edge in FP32 storage
+    A(h->sp_keys, (size_t)E * 8); A(h->sp_keys2, (size_t)E * 8);
+    A(h->sp_kv, (size_t)E * 4); A(h->sp_kv2, (size_t)E * 4);
+    A(h->sp_ei, (size_t)E * 4); A(h->sp_ej, (size_t)E * 4);
+    A(h->sp_ids, (size_t)E * 4); A(h->sp_perm, (size_t)E * 4);
+    A(h->Pf, (size_t)E * st_bytes); A(h->Pb, (size_t)E * st_bytes);
+    A(h->Ef, (size_t)E * st_bytes); A(h->Eb, (size_t)E * st_bytes);
+    if (ae != hipSuccess) {
+        h->release_all();
+        return fail(h, GABP_E_NOMEM, std::string("device allocation of the edge arrays failed: ") +
+                                         hipGetErrorString(ae));
+    }
+    const float c = (float)(-p.gamma * 1.4426950408889634);
+    HIPCHK(h, hipMemsetAsync(h->flag.p, 0, 4, s));
+    HIPCHK(h, launch_sp_fill(F, h->tiles.as<uint32_t>(), nt, N, cutf, c, (float)(lam * lam),
+                             h->sp_toff.as<int64_t>(), h->sp_cnt.as<int32_t>(), h->sp_keys.as<uint64_t>(),
+                             h->sp_kv.as<float>(), h->flag.as<int32_t>(), s));
+    {
+        int32_t fl = 0;
+        HIPCHK(h, hipMemcpyAsync(&fl, h->flag.p, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+        if (fl) return fail(h, GABP_E_DEVICE, "the count and fill passes of the sparse graph disagree");
+    }
+    size_t sb = 0, sb2 = 0;
+    HIPCHK(h, sp_sort_keys(nullptr, &sb, h->sp_keys.as<uint64_t>(), h->sp_keys2.as<uint64_t>(), h->sp_kv.as<float>(),
+                           h->sp_kv2.as<float>(), E, s));
+    HIPCHK(h, sp_sort_ids(nullptr, &sb2, h->sp_keys.as<uint64_t>(), h->sp_keys2.as<uint64_t>(),
+                          h->sp_ids.as<int32_t>(), h->sp_perm.as<int32_t>(), E, s));
+    size_t sb3 = 0;
+    HIPCHK(h, sp_scan(nullptr, &sb3, h->sp_degi.as<int32_t>(), h->sp_offi.as<int64_t>(), N + 1, s));
+    if (h->sp_tmp.ensure(std::max(std::max(sb, sb2), std::max(sb3, tb))) != hipSuccess) {
+        h->release_all();
+        return fail(h, GABP_E_NOMEM, "sort storage");
+    }
+    // edges in (i, j) order: keys2 / kv2 (K' per edge from here on)
+    HIPCHK(h, sp_sort_keys(h->sp_tmp.p, &sb, h->sp_keys.as<uint64_t>(), h->sp_keys2.as<uint64_t>(),
+                           h->sp_kv.as<float>(), h->sp_kv2.as<float>(), E, s));
+    HIPCHK(h, hipMemsetAsync(h->sp_degi.p, 0, (size_t)(N + 1) * 4, s));
+    HIPCHK(h, hipMemsetAsync(h->sp_degj.p, 0, (size_t)(N + 1) * 4, s));
+    // ends and degrees; keys of the transposed order (j, i) into keys
+    HIPCHK(h, launch_sp_unpack(h->sp_keys2.as<uint64_t>(), E, h->sp_ei.as<int32_t>(), h->sp_ej.as<int32_t>(),
+                               h->sp_degi.as<int32_t>(), h->sp_degj.as<int32_t>(), h->sp_keys.as<uint64_t>(),
+                               h->sp_ids.as<int32_t>(), s));
+    // perm: edge ids in (j, i) order
+    HIPCHK(h, sp_sort_ids(h->sp_tmp.p, &sb2, h->sp_keys.as<uint64_t>(), h->sp_keys2.as<uint64_t>(),
+                          h->sp_ids.as<int32_t>(), h->sp_perm.as<int32_t>(), E, s));
+    HIPCHK(h, sp_scan(h->sp_tmp.p, &sb3, h->sp_degi.as<int32_t>(), h->sp_offi.as<int64_t>(), N + 1, s));
+    HIPCHK(h, sp_scan(h->sp_tmp.p, &sb3, h->sp_degj.as<int32_t>(), h->sp_offj.as<int64_t>(), N + 1, s));
+    HIPCHK(h, hipEventRecord(ev[2], s));
+
+    // ---- diagonal weighting from the sparse row sums (one partial per node)
+    HIPCHK(h, hipMemsetAsync(h->partP.p, 0, (size_t)NPAD * 8, s));
+    HIPCHK(h, hipMemsetAsync(h->partE.p, 0, (size_t)NPAD * 8, s));
+    HIPCHK(h, launch_sp_rowsum(N, h->sp_offi.as<int64_t>(), h->sp_offj.as<int64_t>(), h->sp_perm.as<int32_t>(),
+                               h->sp_kv2.as<float>(), h->partP.as<double>(), h->partE.as<double>(), s));
+    HIPCHK(h, launch_fill_value(h->kdiag.as<double>(), N, 1.0 + lam * lam, s));
+    HIPCHK(h, launch_diag(N, 0, h->partP.as<double>(), h->partE.as<double>(), h->kdiag.as<double>(),
+                          p.diag_mode, p.C, p.diag_delta, h->Adiag.as<double>(), h->rowmax.as<double>(),
+                          h->rsum.as<double>(), h->blk1.as<double>(), h->one.as<double>(), s));
+    DevStatus* st = h->status_d.as<DevStatus>();
+    HIPCHK(h, launch_init(prec, N, NPAD, 1, h->Adiag.as<double>(), h->yd.as<float>(), h->Pt.p, h->S.p,
+                          h->alpha_d.as<double>(), st, s));
+    for (DevBuf* b : {&h->Pf, &h->Pb, &h->Ef, &h->Eb}) HIPCHK(h, hipMemsetAsync(b->p, 0, (size_t)E * st_bytes, s));
+    HIPCHK(h, hipEventRecord(ev[3], s));
+
+    // ---- sweeps: edge update + per-node gather, finalize, stop rule
+    StopRule rule{p.tol_abs, p.tol_rel, p.stagnation_rel, p.max_sweeps, p.stagnation_window};
+    const int nblk = (int)((N + WG - 1) / WG);
+    DevStatus hs{};
+    double sweep_kernel_ms = 0.0;
+    int64_t launches = 0;
+    int polled = 0;
+    for (int t = 0; t < p.max_sweeps; ++t) {
+        const int slot = t % ce;
+        if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot], s));
+        HIPCHK(h, launch_sp_sweep(prec, E, N, h->sp_ei.as<int32_t>(), h->sp_ej.as<int32_t>(), h->sp_kv2.as<float>(),
+                                  h->Pt.p, h->S.p, h->Pf.p, h->Pb.p, h->Ef.p, h->Eb.p, h->sp_offi.as<int64_t>(),
+                                  h->sp_offj.as<int64_t>(), h->sp_perm.as<int32_t>(), h->partP.p, h->partE.p,
+                                  st, s));
+        if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot + 1], s));
+        HIPCHK(h, launch_finalize(prec, N, 0, h->partP.p, h->partE.p, h->Adiag.as<double>(), h->yd.as<float>(),
+                                  h->Pt.p, h->S.p, h->alpha_d.as<double>(), h->blk1.as<double>(),
+                                  h->blk2.as<double>(), st, s));
+        HIPCHK(h, launch_status(nblk, h->blk1.as<double>(), h->blk2.as<double>(), st, h->trace_d.as<double>(),
+                                rule, s));
+        if ((t + 1) % ce == 0 || t + 1 == p.max_sweeps) {
+            HIPCHK(h, hipMemcpyAsync(&hs, st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+            HIPCHK(h, hipStreamSynchronize(s));
+            if (p.time_sweeps) {
+                for (int u = polled; u <= t; ++u) {
+                    if (u >= hs.t) break;
+                    sweep_kernel_ms += elapsed(sev[2 * (u % ce)], sev[2 * (u % ce) + 1]);
+                    ++launches;
+                }
+            }
+            polled = t + 1;
+            if (hs.done) break;
+        }
+    }
+    HIPCHK(h, hipEventRecord(ev[4], s));
+
+    // ---- outputs
+    h->alpha.assign((size_t)N, 0.0);
+    h->ptilde.assign((size_t)N, 0.0);
+    h->adiag.assign((size_t)N, 0.0);
+    h->yh.assign((size_t)N, 0.0f);
+    HIPCHK(h, launch_convert_agg(prec, h->Pt.p, h->tmp.as<double>(), N, s));
+    HIPCHK(h, hipMemcpyAsync(h->alpha.data(), h->alpha_d.p, (size_t)N * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipMemcpyAsync(h->ptilde.data(), h->tmp.p, (size_t)N * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipMemcpyAsync(h->adiag.data(), h->Adiag.p, (size_t)N * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipMemcpyAsync(h->yh.data(), h->yd.p, (size_t)N * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipMemcpyAsync(&hs, st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipEventRecord(ev[5], s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    h->trace.assign((size_t)std::max(hs.t, 0), 0.0);
+    if (hs.t > 0)
+        HIPCHK(h, hipMemcpy(h->trace.data(), h->trace_d.p, (size_t)hs.t * 8, hipMemcpyDeviceToHost));
+
+    h->N = N; h->m = m; h->NB = NB; h->NPAD = NPAD; h->ntiles = nt; h->m_pad = m_pad;
+    h->prec = prec; h->gram = gram; h->lam = lam; h->rbf = true;
+    h->sparse = true;
+    h->n_edges = E;
+    h->sweeps = hs.t;
+    h->delta = hs.delta;
+    h->reason = hs.reason;
+    switch (hs.reason) {
+        case R_CONVERGED: case R_STAGNATED: h->status = GABP_OK; break;
+        case R_DIVERGED: h->status = GABP_E_DIVERGED; break;
+        default: h->status = GABP_E_NOT_CONVERGED; break;
+    }
+    h->tm = gabp_timings{};
+    h->tm.stage_ms = elapsed(ev[0], ev[1]);
+    h->tm.kbuild_ms = elapsed(ev[1], ev[2]);
+    h->tm.diag_ms = elapsed(ev[2], ev[3]);
+    h->tm.sweep_loop_ms = elapsed(ev[3], ev[4]);
+    h->tm.sweep_kernel_ms = sweep_kernel_ms;
+    h->tm.sweep_launches = launches;
+    h->tm.d2h_ms = elapsed(ev[4], ev[5]);
+    h->tm.total_ms = now_ms() - t_start;
+    h->plan = gabp_plan{};
+    h->plan.precision = prec;
+    h->plan.kstore = GABP_KSTORE_AUTO;      // K' kept per edge, not as tiles
+    h->plan.edge_state = GABP_EDGE_STORED;
+    h->plan.gram = (gram == GRAM_BF16X6) ? GABP_GRAM_BF16X6 : (gram == GRAM_BF16X3) ? GABP_GRAM_BF16X3
+                 : (gram == GRAM_BF16 ? GABP_GRAM_BF16 : GABP_GRAM_AUTO);
+    h->plan.tile = TILE;
+    h->plan.n_blocks = NB;
+    h->plan.n_tiles = nt;
+    h->plan.n_edges = E;
+    h->plan.device_bytes = h->held();
+    // per edge and sweep: ends (8 B), K' (4 B), records read and written
+    // (8 x 4 B), the gather's record reads (4 x 4 B) and permutation (4 B)
+    h->plan.alg_bytes_per_pair = 8.0 + 4.0 + 8.0 * st_bytes + 4.0 * st_bytes + 4.0;
+    h->plan.alg_bytes_per_sweep = (uint64_t)((double)E * h->plan.alg_bytes_per_pair);
+    h->have_result = true;
+    (void)agg;
     if (h->status != GABP_OK) {
         h->err = (h->status == GABP_E_DIVERGED) ? "GaBP diverged: a cavity precision became <= 0 or non-finite"
                                                 : "max_sweeps reached before the stop rule held";
@@ -636,6 +917,9 @@ void gabp_svm_params_default(gabp_svm_params* p) {
     p->device = 0;
     p->hbm_budget_bytes = 0;
     p->time_sweeps = 0;
+    p->schedule = GABP_SCHED_SYNC;
+    p->sched_groups = 0;
+    p->sparse_tau = 1e-3;
 }
 
 gabp_status gabp_svm_create(const gabp_svm_params* params, gabp_svm** out) {
@@ -661,6 +945,7 @@ gabp_status gabp_svm_solve(gabp_svm* h, const float* X, const float* y, int64_t 
                            int32_t mem, void* stream) {
     if (!h) return GABP_E_INVALID;
     if (!X) return fail(h, GABP_E_INVALID, "X is NULL");
+    if (h->p.kernel == GABP_KERNEL_RBF_SPARSE) return solve_sparse_impl(h, X, y, N, m, mem, (hipStream_t)stream);
     return solve_impl(h, X, nullptr, y, N, m, mem, (hipStream_t)stream);
 }
 
@@ -712,6 +997,18 @@ gabp_status gabp_svm_query(const gabp_svm* h, int32_t what, void* dst, size_t by
         case GABP_Q_TRACE: return put(h->trace.data(), h->trace.size() * 8);
         case GABP_Q_PLAN: return put(&h->plan, sizeof h->plan);
         case GABP_Q_REASON: return put(&h->reason, sizeof h->reason);
+        case GABP_Q_EDGES: {
+            if (!h->sparse) return GABP_E_STATE;
+            const size_t E = (size_t)h->n_edges;
+            if (bytes < E * 16) return GABP_E_BUFSIZE;
+            std::vector<int32_t> a(E), b(E);
+            if (E && (hipMemcpy(a.data(), h->sp_ei.p, E * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+                      hipMemcpy(b.data(), h->sp_ej.p, E * 4, hipMemcpyDeviceToHost) != hipSuccess))
+                return GABP_E_DEVICE;
+            int64_t* o = static_cast<int64_t*>(dst);
+            for (size_t e = 0; e < E; ++e) { o[2 * e] = a[e]; o[2 * e + 1] = b[e]; }
+            return GABP_OK;
+        }
         default: return GABP_E_INVALID;
     }
 }
@@ -742,7 +1039,7 @@ gabp_status gabp_svm_predict(gabp_svm* h, const float* Xq, int64_t nq, double* f
                              void* stream) {
     if (!h || !Xq || !f_out || nq < 0) return GABP_E_INVALID;
     if (mem != GABP_MEM_HOST && mem != GABP_MEM_DEVICE) return GABP_E_INVALID;
-    if (!h->have_result || !h->rbf) return fail(h, GABP_E_STATE, "predict needs a finished RBF solve");
+    if (!h->have_result || !h->rbf || h->sparse) return fail(h, GABP_E_STATE, "predict needs a finished dense RBF solve");
     if (nq == 0) return GABP_OK;
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(h, hipSetDevice(h->p.device));

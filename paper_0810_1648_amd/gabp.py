@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libgabp_svm.so")
 
 # enums (mirrors of the header)
 OK, E_INVALID, E_NOMEM, E_NOT_CONVERGED, E_DIVERGED, E_DEVICE, E_STATE, E_BUFSIZE = range(8)
-KERNEL_RBF, KERNEL_PRECOMPUTED = 0, 2
+KERNEL_RBF, KERNEL_PRECOMPUTED, KERNEL_RBF_SPARSE = 0, 2, 3
+KERNEL = {"rbf": KERNEL_RBF, "precomputed": KERNEL_PRECOMPUTED, "rbf_sparse": KERNEL_RBF_SPARSE}
 DIAG = {"none": 0, "softmargin": 1, "dominant_row": 2, "dominant_uniform": 3}
 BOX = {"none": 0, "clip_output": 1}
 PREC = {"fp64": 0, "fp32": 1, "mixed": 2}
@@ -29,7 +30,7 @@ SCHED = {"sync": 0, "grouped": 1}
 MEM_HOST, MEM_DEVICE = 0, 1
 REASON = {0: "none", 1: "converged", 2: "max_sweeps", 3: "diverged", 4: "stagnated"}
 Q_N, Q_ALPHA, Q_PTILDE, Q_ADIAG, Q_BIAS, Q_SV_MASK, Q_SV_COUNT, Q_SWEEPS, Q_DELTA, Q_STATUS, \
-    Q_TIMINGS, Q_TRACE, Q_PLAN, Q_REASON = range(14)
+    Q_TIMINGS, Q_TRACE, Q_PLAN, Q_REASON, Q_EDGES = range(15)
 
 
 class Params(ct.Structure):
@@ -43,6 +44,7 @@ class Params(ct.Structure):
         ("edge_state", ct.c_int32), ("gram", ct.c_int32), ("stateless_depth", ct.c_int32),
         ("device", ct.c_int32), ("hbm_budget_bytes", ct.c_uint64), ("time_sweeps", ct.c_int32),
         ("schedule", ct.c_int32), ("sched_groups", ct.c_int32), ("reserved", ct.c_int32),
+        ("sparse_tau", ct.c_double),
     ]
 
 
@@ -61,7 +63,8 @@ class Plan(ct.Structure):
                 ("gram", ct.c_int32), ("tile", ct.c_int32), ("stateless_depth", ct.c_int32),
                 ("n_blocks", ct.c_int64), ("n_tiles", ct.c_int64), ("device_bytes", ct.c_uint64),
                 ("alg_bytes_per_sweep", ct.c_uint64), ("alg_bytes_per_pair", ct.c_double),
-                ("stateless_rho", ct.c_double), ("series_reciprocal", ct.c_int32), ("sched_groups", ct.c_int32)]
+                ("stateless_rho", ct.c_double), ("series_reciprocal", ct.c_int32), ("sched_groups", ct.c_int32),
+                ("n_edges", ct.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -74,7 +77,7 @@ class GabpError(RuntimeError):
 
 
 _lib = None
-ABI_VERSION = 3     # GABP_ABI_VERSION the structures above describe
+ABI_VERSION = 4     # GABP_ABI_VERSION the structures above describe
 
 
 def lib():
@@ -130,7 +133,7 @@ def make_params(**kw) -> Params:
         if k in maps and isinstance(v, str):
             v = maps[k][v]
         if k == "kernel" and isinstance(v, str):
-            v = KERNEL_RBF if v == "rbf" else KERNEL_PRECOMPUTED
+            v = KERNEL[v]
         if not hasattr(p, k):
             raise TypeError(f"unknown parameter {k!r}")
         setattr(p, k, v)
@@ -280,6 +283,11 @@ class GabpSVM:
 
     def plan(self):
         return self._qs(Q_PLAN, Plan()).as_dict()
+
+    def edges(self):
+        """Kept pairs (i, j), i < j, of a sparsified solve (int64, E x 2)."""
+        E = int(self.plan()["n_edges"])
+        return self._q(Q_EDGES, np.zeros((E, 2), np.int64))
 
     def kernel_entries(self, rows, cols):
         r = np.ascontiguousarray(rows, dtype=np.int64)
