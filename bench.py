@@ -106,6 +106,9 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-predict", action="store_true", help="skip the held-out decision-function measurement")
     ap.add_argument("--no-grouped", action="store_true", help="skip the grouped-schedule solve")
+    ap.add_argument("--no-sparse", action="store_true", help="skip the sparsified-kernel solve")
+    ap.add_argument("--sparse-n", type=int, default=1000000)
+    ap.add_argument("--sparse-tau", type=float, default=0.55)
     ap.add_argument("--predict-n", type=int, default=100000, help="held-out queries of the predict leg")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving measurement")
     ap.add_argument("--serve-requests", type=int, default=512)
@@ -258,6 +261,32 @@ def predict_bench(torch, gabp, inputs, wl, X, y, params, n_test, reps=5):
                          "valu_frac": slots * pairs / (kms_med * 1e-3) / 1e9 / VALU_PEAK_GSLOT}}
 
 
+def sparse_bench(torch, gabp, inputs, n, tau, steps=2, warmup=1):
+    """Sparsified kernel at millions of points: the large workload's recipe
+    (six unit clusters in 20 dimensions, gamma 0.05, MIXED) at N = n, pairs
+    kept where exp(-gamma d^2) >= tau."""
+    import numpy as np
+    wl = inputs.make_workload("large", n=n)
+    X = torch.from_numpy(wl.X).cuda()
+    y = torch.from_numpy(wl.y).cuda()
+    params = dict(kernel="rbf_sparse", sparse_tau=tau, gamma=wl.gamma, C=wl.C, lambda_aug=wl.lam,
+                  diag_delta=wl.delta, precision="mixed", tol_rel=wl.tol_rel, time_sweeps=1)
+    wall, sweeps, ktime, klaunch, info = solve_steps(torch, gabp, wl, X, y, params, steps, warmup)
+    plan, tm = info["plan"], info["timings"]
+    E = plan["n_edges"]
+    avg = ktime / max(klaunch, 1)
+    ach = plan["alg_bytes_per_sweep"] / (avg * 1e-3) / 1e9 if klaunch else None
+    print(f"[bench] sparse: N={n} edges={E} {sweeps} sweeps in {wall:.3f} s", file=sys.stderr, flush=True)
+    return {"workload": f"large-like N={n} m={wl.m} gamma={wl.gamma:g}, kernel threshold {tau:g}, MIXED",
+            "edges": E, "mean_degree": 2.0 * E / n, "sweeps_per_s": sweeps / wall, "solves_per_s": steps / wall,
+            "sweeps_per_solve": info["sweeps_per_solve"], "reason": info["reason"],
+            "graph_build_ms": tm["kbuild_ms"], "sweep_loop_ms": tm["sweep_loop_ms"],
+            "roofline": {"bound": "hbm", "kernel": "k_sp_sweep + k_sp_gather", "achieved": ach,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS if ach else None,
+                         "avg_launch_ms": avg, "alg_bytes_per_edge": plan["alg_bytes_per_pair"],
+                         "alg_bytes_per_launch": plan["alg_bytes_per_sweep"]}}
+
+
 def cpu_baseline(wl, n_full, sample_n):
     """Times the FP64 oracle's synchronous sweep on the first sample_n points
     of the same workload and scales its pair rate to N = n_full."""
@@ -396,6 +425,10 @@ def main():
     if not a.no_predict:
         predict = predict_bench(torch, gabp, inputs, wl, X, y, params, a.predict_n)
 
+    sparse = None
+    if not a.no_sparse:
+        sparse = sparse_bench(torch, gabp, inputs, a.sparse_n, a.sparse_tau)
+
     serving = None
     if not a.no_serve:
         serving = serving_bench(gabp, inputs, a.serve_requests, a.serve_load, a.serve_precision)
@@ -432,6 +465,7 @@ def main():
         "stored_state": stored_cmp,
         "serving": serving,
         "grouped_schedule": grouped,
+        "sparse": sparse,
         "predict": predict,
         "roofline": roof,
         "cpu_baseline": cpu,

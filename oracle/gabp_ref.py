@@ -667,6 +667,76 @@ def box_qp_bruteforce(A, C: float):
     return best[0]
 
 
+def box_qp_projected_gauss_seidel(A, C: float, tol: float = 1e-15, max_iter: int = 100000):
+    """max 1'h - 1/2 h'Ah s.t. 0 <= h <= C by projected Gauss-Seidel
+    (coordinate ascent: h_i <- clip((1 - sum_{j != i} A_ij h_j) / A_ii, 0, C)
+    in index order), which converges to the unique optimum for SPD A.  For
+    sizes beyond the brute force."""
+    A = np.asarray(A, dtype=np.float64)
+    n = A.shape[0]
+    h = np.zeros(n)
+    d = np.diag(A)
+    for _ in range(max_iter):
+        old = h.copy()
+        for i in range(n):
+            g = 1.0 - A[i] @ h + d[i] * h[i]
+            h[i] = min(max(g / d[i], 0.0), C)
+        if np.max(np.abs(h - old)) <= tol * max(np.max(np.abs(h)), 1e-300):
+            break
+    return h
+
+
+def gabp_solve_box(A, b, C: float, max_sweeps: int = 1000, tol_abs: float = 0.0,
+                   tol_rel: float = 1e-12, keep_trajectory: bool = False) -> GabpResult:
+    """Algorithm 2 (information form, synchronous) with the box constraint
+    0 <= h <= C (eq. cons1) restored, which the paper drops: after every
+    aggregate step (and for the initial aggregates) the belief mean
+    S_i / P~_i is clipped to [0, C] and the node broadcasts S_i = P~_i times
+    the clipped mean, so the next messages see the projected mean.  Not the
+    paper's method; its fixed point is compared with the box QP."""
+    A = np.asarray(A, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    n = len(b)
+    off = ~np.eye(n, dtype=bool)
+    Aoff = np.where(off, A, 0.0)
+    A2 = Aoff * Aoff
+    P = np.zeros((n, n))
+    E = np.zeros((n, n))
+    Pt = np.diag(A).copy()
+    alpha = np.clip(b / Pt, 0.0, C)
+    S = Pt * alpha
+    traj = [alpha.copy()] if keep_trajectory else None
+    deltas = []
+    status = NOT_CONVERGED
+    t = 0
+    for t in range(1, max_sweeps + 1):
+        Q = Pt[:, None] - P.T
+        Qok = np.where(off, Q, 1.0)
+        if not (np.all(np.isfinite(Qok)) and np.all(Qok > 0.0)):
+            status = DIVERGED
+            t -= 1
+            break
+        Pn = np.where(off, -A2 / Qok, 0.0)
+        En = np.where(off, -Aoff * (S[:, None] - E.T) / Qok, 0.0)
+        P, E = Pn, En
+        Pt = np.diag(A) + P.sum(axis=0)
+        S = b + E.sum(axis=0)
+        if not (np.all(np.isfinite(Pt)) and np.all(Pt > 0.0) and np.all(np.isfinite(S))):
+            status = DIVERGED
+            break
+        new = np.clip(S / Pt, 0.0, C)
+        S = Pt * new
+        d = float(np.max(np.abs(new - alpha)))
+        alpha = new
+        deltas.append(d)
+        if keep_trajectory:
+            traj.append(alpha.copy())
+        if d <= tol_abs + tol_rel * float(np.max(np.abs(alpha))):
+            status = CONVERGED
+            break
+    return GabpResult(alpha, Pt, t, status, deltas, traj)
+
+
 def decision_function(Xtr, y, alpha, Xq, gamma: float, lam: float):
     """f(x) = sum_i alpha_i y_i (K(x_i, x) + lam^2) (section "Classification
     Using Support Vector Machines": the sign of f classifies x, with the bias

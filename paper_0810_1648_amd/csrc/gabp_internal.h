@@ -198,10 +198,12 @@ hipError_t launch_sp_unpack(const uint64_t* keys, int64_t E, int32_t* ei, int32_
                             int32_t* deg_j, uint64_t* keys_t, int32_t* ids, hipStream_t s);
 hipError_t launch_sp_rowsum(int64_t N, const int64_t* off_i, const int64_t* off_j, const int32_t* perm,
                             const float* kv, double* psum, double* pmax, hipStream_t s);
+// PS: 2 N aggregates packed (P~, S); RF / RB: 2 E records packed (P, E) of
+// the messages i -> j / j -> i of every edge.
 hipError_t launch_sp_sweep(int prec, int64_t E, int64_t N, const int32_t* ei, const int32_t* ej, const float* kv,
-                           const void* Pt, const void* S, void* Pf, void* Pb, void* Ef, void* Eb,
-                           const int64_t* off_i, const int64_t* off_j, const int32_t* perm, void* partP,
-                           void* partE, DevStatus* st, hipStream_t s);
+                           const void* Pt, const void* S, void* PS, void* RF, void* RB, const int64_t* off_i,
+                           const int64_t* off_j, const int32_t* perm, void* partP, void* partE, DevStatus* st,
+                           hipStream_t s);
 // Finalize of the node blocks [b0, b0 + nb) only (the group just visited).
 hipError_t launch_finalize_range(int prec, int64_t b0, int64_t nb, int64_t N, int NB, const void* partP,
                                  const void* partE, const double* Adiag, const float* y, void* Pt, void* S,

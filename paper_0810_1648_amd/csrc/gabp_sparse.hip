@@ -127,72 +127,99 @@ __global__ void k_sp_unpack(const uint64_t* __restrict__ keys, int64_t E, int32_
 }
 
 // Row sums and maxima of K' over each node's edges (the sparse r_i), written
-// as one partial per node (the dense layout with a single slot).
-__global__ void k_sp_rowsum(int64_t N, const int64_t* __restrict__ off_i, const int64_t* __restrict__ off_j,
-                            const int32_t* __restrict__ perm, const float* __restrict__ kv,
-                            double* __restrict__ psum, double* __restrict__ pmax) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= N) return;
+// as one partial per node (the dense layout with a single slot); sixteen
+// lanes per node as in k_sp_gather.
+__global__ __launch_bounds__(WG) void k_sp_rowsum(int64_t N, const int64_t* __restrict__ off_i,
+                                                  const int64_t* __restrict__ off_j,
+                                                  const int32_t* __restrict__ perm, const float* __restrict__ kv,
+                                                  double* __restrict__ psum, double* __restrict__ pmax) {
+    const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    const int q = threadIdx.x & 15;
     double s = 0.0, m = 0.0;
-    for (int64_t e = off_i[k]; e < off_i[k + 1]; ++e) { s += (double)kv[e]; m = fmax(m, (double)kv[e]); }
-    for (int64_t t = off_j[k]; t < off_j[k + 1]; ++t) {
-        const float v = kv[perm[t]];
-        s += (double)v;
-        m = fmax(m, (double)v);
+    if (k < N) {
+        for (int64_t e = off_i[k] + q; e < off_i[k + 1]; e += 16) { s += (double)kv[e]; m = fmax(m, (double)kv[e]); }
+        for (int64_t t = off_j[k] + q; t < off_j[k + 1]; t += 16) {
+            const double v = (double)kv[perm[t]];
+            s += v;
+            m = fmax(m, v);
+        }
     }
-    psum[k] = s;
-    pmax[k] = m;
+    s = sum16(s);
+    m = fmax(m, dpp<0xB1>(m));
+    m = fmax(m, dpp<0x4E>(m));
+    m = fmax(m, dpp<0x141>(m));
+    m = fmax(m, dpp<0x140>(m));
+    if (k < N && q == 0) { psum[k] = s; pmax[k] = m; }
+}
+
+// Aggregates of every node packed as (P~, S) pairs, so that the sweep's
+// reads of a random neighbour fetch one 8- or 16-byte item.
+template <class AT>
+__global__ void k_sp_pack(int64_t N, const AT* __restrict__ Pt, const AT* __restrict__ S, AT* __restrict__ PS,
+                          const DevStatus* st) {
+    if (st->done) return;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < N) { PS[2 * k] = Pt[k]; PS[2 * k + 1] = S[k]; }
 }
 
 // One synchronous sweep over the edges: both directions of edge (i, j) from
-// the previous records (ST) and aggregates (AT), in MT.
+// the previous records and aggregates.  Records are (P, E) pairs: RF[e] the
+// message i -> j, RB[e] the message j -> i (ST), aggregates (P~, S) pairs
+// (AT), arithmetic in MT.
 template <class ST, class MT, class AT>
 __global__ __launch_bounds__(WG) void k_sp_sweep(int64_t E, const int32_t* __restrict__ ei,
                                                  const int32_t* __restrict__ ej, const float* __restrict__ kv,
-                                                 const AT* __restrict__ Pt, const AT* __restrict__ S,
-                                                 ST* __restrict__ Pf, ST* __restrict__ Pb, ST* __restrict__ Ef,
-                                                 ST* __restrict__ Eb, DevStatus* st) {
+                                                 const AT* __restrict__ PS, ST* __restrict__ RF,
+                                                 ST* __restrict__ RB, DevStatus* st) {
     if (st->done) return;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool bad = false;
     if (e < E) {
         const int32_t i = ei[e], j = ej[e];
         const MT a = (MT)kv[e];
-        const MT pf = (MT)Pf[e], pb = (MT)Pb[e], ef = (MT)Ef[e], eb = (MT)Eb[e];
-        const MT qf = (MT)Pt[i] - pb;      // P~_i - P_ji
-        const MT qb = (MT)Pt[j] - pf;      // P~_j - P_ij
+        const MT pf = (MT)RF[2 * e], ef = (MT)RF[2 * e + 1], pb = (MT)RB[2 * e], eb = (MT)RB[2 * e + 1];
+        const MT Pi = (MT)PS[2 * (int64_t)i], Si = (MT)PS[2 * (int64_t)i + 1];
+        const MT Pj = (MT)PS[2 * (int64_t)j], Sj = (MT)PS[2 * (int64_t)j + 1];
+        const MT qf = Pi - pb;      // P~_i - P_ji
+        const MT qb = Pj - pf;      // P~_j - P_ij
         bad = !(qf > (MT)0) || !(qb > (MT)0);
         const MT rf = rcp_fast(qf), rb = rcp_fast(qb);
         const MT a2 = a * a;
-        Pf[e] = (ST)(-a2 * rf);
-        Ef[e] = (ST)(-a * ((MT)S[i] - eb) * rf);
-        Pb[e] = (ST)(-a2 * rb);
-        Eb[e] = (ST)(-a * ((MT)S[j] - ef) * rb);
+        RF[2 * e] = (ST)(-a2 * rf);
+        RF[2 * e + 1] = (ST)(-a * (Si - eb) * rf);
+        RB[2 * e] = (ST)(-a2 * rb);
+        RB[2 * e + 1] = (ST)(-a * (Sj - ef) * rb);
     }
     if (__any(bad) && (threadIdx.x & 63) == 0) st->bad = 1;
 }
 
-// Incoming messages of every node, in a fixed order: its i-end edges (the
-// reverse records P_ji, E_ji), then its j-end edges (P_ij, E_ij).
+// Incoming messages of every node: sixteen lanes (one DPP row) per node
+// stride over its i-end edges (the reverse records j -> i) and its j-end
+// edges (the records i -> j), then add their partial sums in a fixed tree,
+// so every result is reproducible and the reads of a segment coalesce.
 template <class ST, class AT>
 __global__ __launch_bounds__(WG) void k_sp_gather(int64_t N, const int64_t* __restrict__ off_i,
                                                   const int64_t* __restrict__ off_j,
-                                                  const int32_t* __restrict__ perm, const ST* __restrict__ Pf,
-                                                  const ST* __restrict__ Pb, const ST* __restrict__ Ef,
-                                                  const ST* __restrict__ Eb, AT* __restrict__ partP,
+                                                  const int32_t* __restrict__ perm, const ST* __restrict__ RF,
+                                                  const ST* __restrict__ RB, AT* __restrict__ partP,
                                                   AT* __restrict__ partE, const DevStatus* st) {
     if (st->done) return;
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= N) return;
-    AT p = 0, q = 0;
-    for (int64_t e = off_i[k]; e < off_i[k + 1]; ++e) { p += (AT)Pb[e]; q += (AT)Eb[e]; }
-    for (int64_t t = off_j[k]; t < off_j[k + 1]; ++t) {
-        const int32_t e = perm[t];
-        p += (AT)Pf[e];
-        q += (AT)Ef[e];
+    const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    const int q = threadIdx.x & 15;
+    AT p = 0, e = 0;
+    if (k < N) {
+        const int64_t a0 = off_i[k], a1 = off_i[k + 1];
+        for (int64_t t = a0 + q; t < a1; t += 16) { p += (AT)RB[2 * t]; e += (AT)RB[2 * t + 1]; }
+        const int64_t b0 = off_j[k], b1 = off_j[k + 1];
+        for (int64_t t = b0 + q; t < b1; t += 16) {
+            const int64_t x = perm[t];
+            p += (AT)RF[2 * x];
+            e += (AT)RF[2 * x + 1];
+        }
     }
-    partP[k] = p;
-    partE[k] = q;
+    p = sum16(p);
+    e = sum16(e);
+    if (k < N && q == 0) { partP[k] = p; partE[k] = e; }
 }
 
 template <int KIND>
@@ -267,28 +294,30 @@ hipError_t launch_sp_unpack(const uint64_t* keys, int64_t E, int32_t* ei, int32_
 
 hipError_t launch_sp_rowsum(int64_t N, const int64_t* off_i, const int64_t* off_j, const int32_t* perm,
                             const float* kv, double* psum, double* pmax, hipStream_t s) {
-    hipLaunchKernelGGL(k_sp_rowsum, dim3(blocks(N)), dim3(WG), 0, s, N, off_i, off_j, perm, kv, psum, pmax);
+    hipLaunchKernelGGL(k_sp_rowsum, dim3(blocks(16 * N)), dim3(WG), 0, s, N, off_i, off_j, perm, kv, psum, pmax);
     return hipGetLastError();
 }
 
 hipError_t launch_sp_sweep(int prec, int64_t E, int64_t N, const int32_t* ei, const int32_t* ej, const float* kv,
-                           const void* Pt, const void* S, void* Pf, void* Pb, void* Ef, void* Eb,
-                           const int64_t* off_i, const int64_t* off_j, const int32_t* perm, void* partP,
-                           void* partE, DevStatus* st, hipStream_t s) {
-    const dim3 ge(blocks(std::max<int64_t>(E, 1))), gn(blocks(N)), b(WG);
+                           const void* Pt, const void* S, void* PS, void* RF, void* RB, const int64_t* off_i,
+                           const int64_t* off_j, const int32_t* perm, void* partP, void* partE, DevStatus* st,
+                           hipStream_t s) {
+    const dim3 ge(blocks(std::max<int64_t>(E, 1))), gn(blocks(16 * N)), g1(blocks(N)), b(WG);
     switch (prec) {
         case PREC_FP32:
-            hipLaunchKernelGGL((k_sp_sweep<float, float, float>), ge, b, 0, s, E, ei, ej, kv, (const float*)Pt,
-                               (const float*)S, (float*)Pf, (float*)Pb, (float*)Ef, (float*)Eb, st);
-            hipLaunchKernelGGL((k_sp_gather<float, float>), gn, b, 0, s, N, off_i, off_j, perm, (const float*)Pf,
-                               (const float*)Pb, (const float*)Ef, (const float*)Eb, (float*)partP, (float*)partE, st);
+            hipLaunchKernelGGL(k_sp_pack<float>, g1, b, 0, s, N, (const float*)Pt, (const float*)S, (float*)PS, st);
+            hipLaunchKernelGGL((k_sp_sweep<float, float, float>), ge, b, 0, s, E, ei, ej, kv, (const float*)PS,
+                               (float*)RF, (float*)RB, st);
+            hipLaunchKernelGGL((k_sp_gather<float, float>), gn, b, 0, s, N, off_i, off_j, perm, (const float*)RF,
+                               (const float*)RB, (float*)partP, (float*)partE, st);
             break;
         case PREC_MIXED:
-            hipLaunchKernelGGL((k_sp_sweep<float, double, double>), ge, b, 0, s, E, ei, ej, kv, (const double*)Pt,
-                               (const double*)S, (float*)Pf, (float*)Pb, (float*)Ef, (float*)Eb, st);
-            hipLaunchKernelGGL((k_sp_gather<float, double>), gn, b, 0, s, N, off_i, off_j, perm, (const float*)Pf,
-                               (const float*)Pb, (const float*)Ef, (const float*)Eb, (double*)partP,
-                               (double*)partE, st);
+            hipLaunchKernelGGL(k_sp_pack<double>, g1, b, 0, s, N, (const double*)Pt, (const double*)S,
+                               (double*)PS, st);
+            hipLaunchKernelGGL((k_sp_sweep<float, double, double>), ge, b, 0, s, E, ei, ej, kv, (const double*)PS,
+                               (float*)RF, (float*)RB, st);
+            hipLaunchKernelGGL((k_sp_gather<float, double>), gn, b, 0, s, N, off_i, off_j, perm, (const float*)RF,
+                               (const float*)RB, (double*)partP, (double*)partE, st);
             break;
         default: return hipErrorInvalidValue;
     }

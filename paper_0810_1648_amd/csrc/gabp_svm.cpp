@@ -706,8 +706,9 @@ gabp_status solve_sparse_impl(gabp_svm* h, const float* X, const float* y, int64
     A(h->sp_kv, (size_t)E * 4); A(h->sp_kv2, (size_t)E * 4);
     A(h->sp_ei, (size_t)E * 4); A(h->sp_ej, (size_t)E * 4);
     A(h->sp_ids, (size_t)E * 4); A(h->sp_perm, (size_t)E * 4);
-    A(h->Pf, (size_t)E * st_bytes); A(h->Pb, (size_t)E * st_bytes);
-    A(h->Ef, (size_t)E * st_bytes); A(h->Eb, (size_t)E * st_bytes);
+    // records: (P, E) pairs per edge and direction; packed aggregates
+    A(h->Pf, (size_t)2 * E * st_bytes); A(h->Pb, (size_t)2 * E * st_bytes);
+    A(h->Ef, (size_t)2 * NPAD * 8);
     if (ae != hipSuccess) {
         h->release_all();
         return fail(h, GABP_E_NOMEM, std::string("device allocation of the edge arrays failed: ") +
@@ -763,7 +764,7 @@ gabp_status solve_sparse_impl(gabp_svm* h, const float* X, const float* y, int64
     DevStatus* st = h->status_d.as<DevStatus>();
     HIPCHK(h, launch_init(prec, N, NPAD, 1, h->Adiag.as<double>(), h->yd.as<float>(), h->Pt.p, h->S.p,
                           h->alpha_d.as<double>(), st, s));
-    for (DevBuf* b : {&h->Pf, &h->Pb, &h->Ef, &h->Eb}) HIPCHK(h, hipMemsetAsync(b->p, 0, (size_t)E * st_bytes, s));
+    for (DevBuf* b : {&h->Pf, &h->Pb}) HIPCHK(h, hipMemsetAsync(b->p, 0, (size_t)2 * E * st_bytes, s));
     HIPCHK(h, hipEventRecord(ev[3], s));
 
     // ---- sweeps: edge update + per-node gather, finalize, stop rule
@@ -777,7 +778,7 @@ gabp_status solve_sparse_impl(gabp_svm* h, const float* X, const float* y, int64
         const int slot = t % ce;
         if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot], s));
         HIPCHK(h, launch_sp_sweep(prec, E, N, h->sp_ei.as<int32_t>(), h->sp_ej.as<int32_t>(), h->sp_kv2.as<float>(),
-                                  h->Pt.p, h->S.p, h->Pf.p, h->Pb.p, h->Ef.p, h->Eb.p, h->sp_offi.as<int64_t>(),
+                                  h->Pt.p, h->S.p, h->Ef.p, h->Pf.p, h->Pb.p, h->sp_offi.as<int64_t>(),
                                   h->sp_offj.as<int64_t>(), h->sp_perm.as<int32_t>(), h->partP.p, h->partE.p,
                                   st, s));
         if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot + 1], s));
@@ -852,7 +853,8 @@ gabp_status solve_sparse_impl(gabp_svm* h, const float* X, const float* y, int64
     h->plan.n_edges = E;
     h->plan.device_bytes = h->held();
     // per edge and sweep: ends (8 B), K' (4 B), records read and written
-    // (8 x 4 B), the gather's record reads (4 x 4 B) and permutation (4 B)
+    // (8 x 4 B), the gather's record reads (4 x 4 B) and permutation (4 B);
+    // the packed aggregates (16 N B) are not counted
     h->plan.alg_bytes_per_pair = 8.0 + 4.0 + 8.0 * st_bytes + 4.0 * st_bytes + 4.0;
     h->plan.alg_bytes_per_sweep = (uint64_t)((double)E * h->plan.alg_bytes_per_pair);
     h->have_result = true;

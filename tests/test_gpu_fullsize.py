@@ -111,3 +111,53 @@ def test_large_full_stateless_recompute(torch, oracle_c):
     assert p["kstore"] == gabp.KSTORE["recompute"] and p["edge_state"] == gabp.EDGE["stateless"]
     assert st == gabp.OK
     _check_rows(s, wl, oracle_c, nrows=32)
+
+
+def test_large_sparse_full(torch):
+    """Sparsified kernel at N = 300,000 (the large workload's points, kernel
+    threshold 0.55): for sampled rows the oracle's FP64 distances decide
+    every pair farther than 1e-3 (relative) from the cut, which must match
+    the device's edge list; the weighted diagonal and the residual row are
+    checked with the undecided pairs bounding the difference."""
+    from oracle import gabp_ref as R
+    wl = inputs.make_workload("large")
+    tau = 0.55
+    s, st = _solve(torch, wl, kernel="rbf_sparse", sparse_tau=tau)
+    assert st == gabp.OK
+    E = s.plan()["n_edges"]
+    edges = s.edges()
+    assert edges.shape == (E, 2) and E > wl.N
+    assert np.all(edges[:, 0] < edges[:, 1])
+    assert np.all(np.diff(edges[:, 0] * wl.N + edges[:, 1]) > 0)
+    alpha, adiag, y = s.alpha(), s.adiag(), wl.y.astype(np.float64)
+    cut = R.sparse_threshold_d2(wl.gamma, tau)
+    X = wl.X.astype(np.float64)
+    rng = np.random.default_rng(11)
+    rows = rng.choice(wl.N, size=24, replace=False)
+    worst = 0.0
+    for i in rows:
+        d2 = ((X - X[i]) ** 2).sum(axis=1)
+        d2[i] = np.inf
+        sure_in = d2 < cut * (1 - 1e-3)
+        sure_out = d2 > cut * (1 + 1e-3)
+        unsure = ~(sure_in | sure_out)
+        unsure[i] = False
+        a = np.searchsorted(edges[:, 0], i, side="left")
+        b = np.searchsorted(edges[:, 0], i, side="right")
+        nb = np.concatenate([edges[a:b, 1], edges[edges[:, 1] == i, 0]])
+        got = np.zeros(wl.N, bool)
+        got[nb] = True
+        assert np.all(got[sure_in]) and not np.any(got[sure_out]), i
+        k = np.exp(-wl.gamma * np.where(np.isfinite(d2), d2, 0.0)) + wl.lam ** 2
+        r_lo, r_hi = k[sure_in].sum(), k[sure_in].sum() + k[unsure].sum()
+        a_lo = max(1.0 + wl.lam ** 2 + 1.0 / wl.C, 1.1 * r_lo)
+        a_hi = max(1.0 + wl.lam ** 2 + 1.0 / wl.C, 1.1 * r_hi)
+        assert a_lo * (1 - 2e-6) <= adiag[i] <= a_hi * (1 + 2e-6)
+        # residual of row i in the solved system (alpha = y g, labels folded)
+        res = 1.0 - (adiag[i] * alpha[i] + y[i] * np.sum(k[got] * y[got] * alpha[got]))
+        unsure_mass = np.sum(k[unsure] * np.abs(alpha[unsure]))
+        bound = 2.0 * adiag[i] * TOL * np.max(np.abs(alpha)) + unsure_mass
+        worst = max(worst, abs(res) / bound)
+    print(f"large sparse: N={wl.N} edges={E} sweeps={s.sweeps()} build {s.timings()['kbuild_ms']:.1f} ms "
+          f"max |r_i| / bound = {worst:.3f}")
+    assert worst <= 1.0

@@ -497,3 +497,62 @@ def test_sparse_threshold_gap():
     assert tau == pytest.approx(np.exp(-0.1 * cut), rel=1e-15)
     deg = 2 * np.count_nonzero(D2 <= cut) / 200
     assert 6 <= deg <= 24
+
+
+# ----------------------------------------------------------- box-projected sweep --
+
+def _obj(A, h):
+    return float(np.sum(h) - 0.5 * h @ A @ h)
+
+
+def test_box_projection_with_a_loose_box_is_plain_gabp():
+    # a dominant matrix with non-positive couplings keeps every iterate
+    # positive, so a box above the solution never clips
+    A = -np.abs(inputs.random_spd_dominant(150, seed=9, margin=0.5))
+    A[np.diag_indices(150)] *= -1.0
+    b = np.ones(150)
+    r = R.gabp_solve(A, b, max_sweeps=12, tol_rel=0.0, keep_trajectory=True)
+    C = 10.0 * float(np.max(np.abs(R.cholesky_solve(A, b))))
+    rb = R.gabp_solve_box(A, b, C, max_sweeps=12, tol_rel=0.0, keep_trajectory=True)
+    # while no mean leaves the box the sweeps agree up to the rounding of
+    # S = P~ (S / P~)
+    checked = 0
+    for t in range(13):
+        if not np.all(r.trajectory[t] > 0.0):
+            break
+        assert _rel(rb.trajectory[t], r.trajectory[t]) <= 1e-13
+        checked += 1
+    assert checked == 13
+
+
+@pytest.mark.parametrize("case", range(12))
+def test_box_projected_fixed_point_is_the_box_qp_optimum(case):
+    # brute force over the 3^N active sets (N = 7) pins the projected sweep
+    rng = np.random.default_rng(200 + case)
+    X, y = inputs.blobs(7, 3, 300 + case)
+    C = float(rng.choice([0.05, 0.2, 1.0]))
+    A, b = R.svm_system(X, y, 0.5, C, 1.0 / 7)
+    h = R.box_qp_bruteforce(A, C)
+    r = R.gabp_solve_box(A, b, C, max_sweeps=2000, tol_rel=1e-14)
+    assert r.status == R.CONVERGED
+    np.testing.assert_allclose(r.alpha, h, rtol=0, atol=1e-12 * max(1.0, float(np.max(h))))
+    assert abs(_obj(A, r.alpha) - _obj(A, h)) <= 1e-12 * abs(_obj(A, h))
+
+
+def test_projected_gauss_seidel_pins():
+    # against brute force on small systems, and the KKT conditions at size
+    for case in range(4):
+        X, y = inputs.blobs(8, 3, 400 + case)
+        A, _ = R.svm_system(X, y, 0.5, 0.1, 1.0 / 8)
+        np.testing.assert_allclose(R.box_qp_projected_gauss_seidel(A, 0.1), R.box_qp_bruteforce(A, 0.1),
+                                   atol=1e-12)
+    X, y = inputs.blobs(300, 5, 410)
+    A, _ = R.svm_system(X, y, 0.2, 0.01, 1.0 / 300)
+    h = R.box_qp_projected_gauss_seidel(A, 0.01)
+    g = 1.0 - A @ h
+    lo, hi = h <= 0.0, h >= 0.01
+    fr = ~(lo | hi)
+    assert hi.sum() > 0 and fr.sum() > 0
+    assert np.max(np.abs(g[fr])) <= 1e-10 and np.all(g[lo] <= 1e-10) and np.all(g[hi] >= -1e-10)
+    r = R.gabp_solve_box(A, np.ones(300), 0.01, max_sweeps=2000, tol_rel=1e-14)
+    assert r.status == R.CONVERGED and np.max(np.abs(r.alpha - h)) <= 1e-12
