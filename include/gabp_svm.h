@@ -81,9 +81,15 @@ typedef enum gabp_diag {
 } gabp_diag;
 
 /* Box constraint 0 <= alpha <= C (eq. cons1).  The paper drops it; NONE
- * reports alpha as solved, CLIP_OUTPUT reports clip(alpha, 0, C) (the sweep
- * itself is never projected). */
-typedef enum gabp_box { GABP_BOX_NONE = 0, GABP_BOX_CLIP_OUTPUT = 1 } gabp_box;
+ * reports alpha as solved, CLIP_OUTPUT reports clip(alpha, 0, C) without
+ * touching the sweep.  PROJECT (not the paper's method) restores it inside
+ * the sweep: after every aggregate step the belief mean of each node is
+ * clipped to [0, C] and the node broadcasts P~ times the clipped mean; the
+ * fixed point is the optimum of the box-constrained dual QP (verified
+ * against the QP).  PROJECT is not available in the server. */
+typedef enum gabp_box {
+    GABP_BOX_NONE = 0, GABP_BOX_CLIP_OUTPUT = 1, GABP_BOX_PROJECT = 2
+} gabp_box;
 
 /* Arithmetic of the sweep.
  *   FP64:  FP64 kernel entries, messages, aggregates.

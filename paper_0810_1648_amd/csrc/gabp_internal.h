@@ -101,8 +101,10 @@ hipError_t launch_diag(int64_t N, int NB, const double* psum, const double* pmax
                        const double* kdiag, int mode, double C, double delta, double* Adiag,
                        double* rowmax, double* rsum, double* scratch_blk, double* scratch_one,
                        hipStream_t s);
+// boxC > 0 (here and in the finalize launchers): belief means projected
+// onto [0, boxC] (the box-projected variant); 0: no projection.
 hipError_t launch_init(int prec, int64_t N, int64_t NPAD, int R, const double* Adiag, const float* y,
-                       void* Pt, void* S, double* alpha, DevStatus* st, hipStream_t s);
+                       void* Pt, void* S, double* alpha, DevStatus* st, hipStream_t s, double boxC = 0.0);
 
 // Arguments of one sweep launch.  HP/HS are rings of R aggregate vectors
 // (NPAD entries each); slot_top holds the aggregates of the previous sweep,
@@ -165,7 +167,7 @@ hipError_t launch_sweep_f64(int ksrc, int gram, int levels, bool first, bool ser
 hipError_t launch_finalize(int prec, int64_t N, int NB, const void* partP, const void* partE,
                            const double* Adiag, const float* y, void* Pt, void* S,
                            double* alpha, double* blk_delta, double* blk_amax,
-                           DevStatus* st, hipStream_t s);
+                           DevStatus* st, hipStream_t s, double boxC = 0.0);
 // Grouped schedule: one group visit.  `within` lists the stored-record tiles
 // inside the group (both directions), `dir` the single-direction entries
 // (tile index | GE_BWD | GE_WITHIN bits, see gabp_device.h); t = sweep index.
@@ -208,7 +210,7 @@ hipError_t launch_sp_sweep(int prec, int64_t E, int64_t N, const int32_t* ei, co
 hipError_t launch_finalize_range(int prec, int64_t b0, int64_t nb, int64_t N, int NB, const void* partP,
                                  const void* partE, const double* Adiag, const float* y, void* Pt, void* S,
                                  double* alpha, double* blk_delta, double* blk_amax, DevStatus* st,
-                                 hipStream_t s);
+                                 hipStream_t s, double boxC = 0.0);
 hipError_t launch_status(int nblk, const double* blk_delta, const double* blk_amax,
                          DevStatus* st, double* trace, StopRule rule, hipStream_t s);
 // A-priori contraction bound: one[0] = -m* (minus the aggregate lower

@@ -444,14 +444,20 @@ __global__ void k_reset_status(DevStatus* st) {
 template <class AT>
 __global__ void k_init(int64_t N, int64_t NPAD, int R, const double* __restrict__ Adiag,
                        const float* __restrict__ y, AT* __restrict__ Pt, AT* __restrict__ S,
-                       double* __restrict__ alpha, DevStatus* st) {
+                       double* __restrict__ alpha, DevStatus* st, double boxC) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= NPAD) return;
     if (i < N) {
-        const AT a = (AT)Adiag[i], b = (AT)y[i];
+        const AT a = (AT)Adiag[i];
+        AT b = (AT)y[i];
+        double an = (double)(b / a) * (double)y[i];
+        if (boxC > 0.0) {              // box projection of the initial means
+            an = fmin(fmax(an, 0.0), boxC);
+            b = a * (AT)(an * (double)y[i]);
+        }
         Pt[i] = a;
         S[i] = b;
-        alpha[i] = (double)(b / a) * (double)y[i];
+        alpha[i] = an;
         if (!(a > (AT)0) || !isfinite((double)a)) st->bad = 1;
         // slots of the sweeps before sweep 0 (stateless ring): P~ = +inf and
         // S = 0 make every message rebuilt from them exactly zero, which is
@@ -472,6 +478,8 @@ __global__ void k_init(int64_t N, int64_t NPAD, int R, const double* __restrict_
 
 // Aggregates of the new sweep from the partial sums (fixed order) into ring
 // slot `wslot`, the new alpha and the per-block change / magnitude maxima.
+// boxC > 0: the belief mean is clipped to [0, boxC] (alpha space) and S is
+// replaced by P~ times the clipped mean.
 template <class AT>
 __device__ inline void finalize_block(int64_t blk, int64_t N, int NB, const AT* __restrict__ partP,
                                       const AT* __restrict__ partE,
@@ -479,7 +487,7 @@ __device__ inline void finalize_block(int64_t blk, int64_t N, int NB, const AT* 
                                       const float* __restrict__ y, AT* __restrict__ Pt,
                                       AT* __restrict__ S, double* __restrict__ alpha,
                                       double* __restrict__ blk_delta,
-                                      double* __restrict__ blk_amax, DevStatus* st) {
+                                      double* __restrict__ blk_amax, DevStatus* st, double boxC) {
     __shared__ double sh4[4];
     const int64_t i = blk * blockDim.x + threadIdx.x;
     double d = 0.0, am = 0.0;
@@ -492,10 +500,14 @@ __device__ inline void finalize_block(int64_t blk, int64_t N, int NB, const AT* 
             p += partP[o];
             e += partE[o];
         }
+        double an = (double)(e / p) * (double)y[i];
+        bad = !(p > (AT)0) || !isfinite((double)p) || !isfinite((double)e);
+        if (boxC > 0.0) {
+            an = fmin(fmax(an, 0.0), boxC);
+            e = p * (AT)(an * (double)y[i]);
+        }
         Pt[i] = p;
         S[i] = e;
-        const double an = (double)(e / p) * (double)y[i];
-        bad = !(p > (AT)0) || !isfinite((double)p) || !isfinite((double)e);
         d = fabs(an - alpha[i]);
         am = fabs(an);
         alpha[i] = an;
@@ -513,9 +525,9 @@ __global__ __launch_bounds__(WG) void k_finalize(int64_t N, int NB, const AT* __
                                                 const float* __restrict__ y, AT* __restrict__ Pt,
                                                 AT* __restrict__ S, double* __restrict__ alpha,
                                                 double* __restrict__ blk_delta,
-                                                double* __restrict__ blk_amax, DevStatus* st) {
+                                                double* __restrict__ blk_amax, DevStatus* st, double boxC) {
     if (st->done) return;
-    finalize_block<AT>(blockIdx.x, N, NB, partP, partE, Adiag, y, Pt, S, alpha, blk_delta, blk_amax, st);
+    finalize_block<AT>(blockIdx.x, N, NB, partP, partE, Adiag, y, Pt, S, alpha, blk_delta, blk_amax, st, boxC);
 }
 
 // Grouped schedule: the node blocks [b0, b0 + gridDim.x) of one group.
@@ -526,9 +538,10 @@ __global__ __launch_bounds__(WG) void k_finalize_range(int64_t b0, int64_t N, in
                                                       const float* __restrict__ y, AT* __restrict__ Pt,
                                                       AT* __restrict__ S, double* __restrict__ alpha,
                                                       double* __restrict__ blk_delta,
-                                                      double* __restrict__ blk_amax, DevStatus* st) {
+                                                      double* __restrict__ blk_amax, DevStatus* st, double boxC) {
     if (st->done) return;
-    finalize_block<AT>(b0 + blockIdx.x, N, NB, partP, partE, Adiag, y, Pt, S, alpha, blk_delta, blk_amax, st);
+    finalize_block<AT>(b0 + blockIdx.x, N, NB, partP, partE, Adiag, y, Pt, S, alpha, blk_delta, blk_amax, st,
+                       boxC);
 }
 
 // Served form: items are (request, block of 256 nodes).
@@ -544,7 +557,7 @@ __global__ __launch_bounds__(WG) void k_finalize_batched(const ReqDesc* __restri
                            static_cast<const AT*>(rd.sw.partE), rd.Adiag, rd.y,
                            static_cast<AT*>(const_cast<void*>(rd.sw.HP)) + wslot,
                            static_cast<AT*>(const_cast<void*>(rd.sw.HS)) + wslot, rd.alpha, rd.blk_delta,
-                           rd.blk_amax, rd.sw.st);
+                           rd.blk_amax, rd.sw.st, 0.0);
         __syncthreads();
     }
 }
@@ -769,14 +782,14 @@ hipError_t launch_diag(int64_t N, int NB, const double* psum, const double* pmax
 }
 
 hipError_t launch_init(int prec, int64_t N, int64_t NPAD, int R, const double* Adiag, const float* y,
-                       void* Pt, void* S, double* alpha, DevStatus* st, hipStream_t s) {
+                       void* Pt, void* S, double* alpha, DevStatus* st, hipStream_t s, double boxC) {
     hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(64), 0, s, st);
     if (prec == PREC_FP32)
         hipLaunchKernelGGL(k_init<float>, dim3(grid1(NPAD)), dim3(WG), 0, s, N, NPAD, R, Adiag, y,
-                           (float*)Pt, (float*)S, alpha, st);
+                           (float*)Pt, (float*)S, alpha, st, boxC);
     else
         hipLaunchKernelGGL(k_init<double>, dim3(grid1(NPAD)), dim3(WG), 0, s, N, NPAD, R, Adiag, y,
-                           (double*)Pt, (double*)S, alpha, st);
+                           (double*)Pt, (double*)S, alpha, st, boxC);
     return hipGetLastError();
 }
 
@@ -826,32 +839,33 @@ hipError_t launch_served_step(int prec, int levels, bool ser, const ReqDesc* req
 
 hipError_t launch_finalize(int prec, int64_t N, int NB, const void* partP, const void* partE,
                            const double* Adiag, const float* y, void* Pt, void* S, double* alpha,
-                           double* blk_delta, double* blk_amax, DevStatus* st, hipStream_t s) {
+                           double* blk_delta, double* blk_amax, DevStatus* st, hipStream_t s, double boxC) {
     const dim3 g(grid1(N)), b(WG);
     if (prec == PREC_FP32)
         hipLaunchKernelGGL(k_finalize<float>, g, b, 0, s, N, NB, (const float*)partP,
                            (const float*)partE, Adiag, y, (float*)Pt, (float*)S, alpha, blk_delta,
-                           blk_amax, st);
+                           blk_amax, st, boxC);
     else
         hipLaunchKernelGGL(k_finalize<double>, g, b, 0, s, N, NB, (const double*)partP,
                            (const double*)partE, Adiag, y, (double*)Pt, (double*)S, alpha,
-                           blk_delta, blk_amax, st);
+                           blk_delta, blk_amax, st, boxC);
     return hipGetLastError();
 }
 
 hipError_t launch_finalize_range(int prec, int64_t b0, int64_t nb, int64_t N, int NB, const void* partP,
                                  const void* partE, const double* Adiag, const float* y, void* Pt, void* S,
                                  double* alpha, double* blk_delta, double* blk_amax, DevStatus* st,
-                                 hipStream_t s) {
+                                 hipStream_t s, double boxC) {
     if (nb <= 0) return hipSuccess;
     const dim3 g((unsigned)nb), b(WG);
     if (prec == PREC_FP32)
         hipLaunchKernelGGL(k_finalize_range<float>, g, b, 0, s, b0, N, NB, (const float*)partP,
-                           (const float*)partE, Adiag, y, (float*)Pt, (float*)S, alpha, blk_delta, blk_amax, st);
+                           (const float*)partE, Adiag, y, (float*)Pt, (float*)S, alpha, blk_delta, blk_amax, st,
+                           boxC);
     else
         hipLaunchKernelGGL(k_finalize_range<double>, g, b, 0, s, b0, N, NB, (const double*)partP,
                            (const double*)partE, Adiag, y, (double*)Pt, (double*)S, alpha, blk_delta, blk_amax,
-                           st);
+                           st, boxC);
     return hipGetLastError();
 }
 

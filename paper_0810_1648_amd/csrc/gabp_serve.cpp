@@ -597,7 +597,9 @@ gabp_status gabp_server_submit(gabp_server* S, const float* X, const float* y, i
     std::string why;
     if (check_params(params, why) != GABP_OK) return GABP_E_INVALID;
     if (params->kernel != GABP_KERNEL_RBF) return GABP_E_INVALID;
-    if (params->kstore == GABP_KSTORE_RECOMPUTE || params->schedule != GABP_SCHED_SYNC) return GABP_E_INVALID;
+    if (params->kstore == GABP_KSTORE_RECOMPUTE || params->schedule != GABP_SCHED_SYNC ||
+        params->box_mode == GABP_BOX_PROJECT)
+        return GABP_E_INVALID;
     if (N > (int64_t)TILE * 65535) return GABP_E_INVALID;
     for (int64_t k = 0; k < N * m; ++k)
         if (!std::isfinite(X[k])) return GABP_E_INVALID;

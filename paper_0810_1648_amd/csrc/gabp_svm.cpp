@@ -68,7 +68,7 @@ gabp_status check_params(const gabp_svm_params* p, std::string& why) {
     if (!(p->C > 0.0) || !std::isfinite(p->C)) { why = "C must be > 0"; return GABP_E_INVALID; }
     if (p->diag_mode < 0 || p->diag_mode > 3) { why = "unknown diag_mode"; return GABP_E_INVALID; }
     if (!(p->diag_delta >= 0.0)) { why = "diag_delta must be >= 0"; return GABP_E_INVALID; }
-    if (p->box_mode < 0 || p->box_mode > 1) { why = "unknown box_mode"; return GABP_E_INVALID; }
+    if (p->box_mode < 0 || p->box_mode > 2) { why = "unknown box_mode"; return GABP_E_INVALID; }
     if (!(p->tol_abs >= 0.0) || !(p->tol_rel >= 0.0)) { why = "tolerances must be >= 0"; return GABP_E_INVALID; }
     if (p->max_sweeps < 1) { why = "max_sweeps must be >= 1"; return GABP_E_INVALID; }
     if (p->check_every < 1) { why = "check_every must be >= 1"; return GABP_E_INVALID; }
@@ -364,8 +364,9 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
                           p.diag_mode, p.C, p.diag_delta, h->Adiag.as<double>(), h->rowmax.as<double>(),
                           h->rsum.as<double>(), h->blk1.as<double>(), h->one.as<double>(), s));
     DevStatus* st = h->status_d.as<DevStatus>();
+    const double boxC = (p.box_mode == GABP_BOX_PROJECT) ? p.C : 0.0;
     HIPCHK(h, launch_init(prec, N, NPAD, R, h->Adiag.as<double>(), h->yd.as<float>(), h->Pt.p, h->S.p,
-                          h->alpha_d.as<double>(), st, s));
+                          h->alpha_d.as<double>(), st, s, boxC));
     HIPCHK(h, hipEventRecord(ev[3], s));
 
     // ---- plan of the edge state from the contraction bound
@@ -498,7 +499,7 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
             if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot + 1], s));
             HIPCHK(h, launch_finalize(prec, N, NB, h->partP.p, h->partE.p, h->Adiag.as<double>(),
                                       h->yd.as<float>(), wP, wS, h->alpha_d.as<double>(),
-                                      h->blk1.as<double>(), h->blk2.as<double>(), st, s));
+                                      h->blk1.as<double>(), h->blk2.as<double>(), st, s, boxC));
         } else {
             // one visit per group: its messages, then its aggregates (the
             // timed span covers the visits and their group finalizes)
@@ -511,7 +512,7 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
                 HIPCHK(h, launch_finalize_range(prec, b0, b1 - b0, N, NB, h->partP.p, h->partE.p,
                                                 h->Adiag.as<double>(), h->yd.as<float>(), wP, wS,
                                                 h->alpha_d.as<double>(), h->blk1.as<double>(),
-                                                h->blk2.as<double>(), st, s));
+                                                h->blk2.as<double>(), st, s, boxC));
             }
             if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot + 1], s));
         }
@@ -762,8 +763,9 @@ gabp_status solve_sparse_impl(gabp_svm* h, const float* X, const float* y, int64
                           p.diag_mode, p.C, p.diag_delta, h->Adiag.as<double>(), h->rowmax.as<double>(),
                           h->rsum.as<double>(), h->blk1.as<double>(), h->one.as<double>(), s));
     DevStatus* st = h->status_d.as<DevStatus>();
+    const double boxC = (p.box_mode == GABP_BOX_PROJECT) ? p.C : 0.0;
     HIPCHK(h, launch_init(prec, N, NPAD, 1, h->Adiag.as<double>(), h->yd.as<float>(), h->Pt.p, h->S.p,
-                          h->alpha_d.as<double>(), st, s));
+                          h->alpha_d.as<double>(), st, s, boxC));
     for (DevBuf* b : {&h->Pf, &h->Pb}) HIPCHK(h, hipMemsetAsync(b->p, 0, (size_t)2 * E * st_bytes, s));
     HIPCHK(h, hipEventRecord(ev[3], s));
 
@@ -784,7 +786,7 @@ gabp_status solve_sparse_impl(gabp_svm* h, const float* X, const float* y, int64
         if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot + 1], s));
         HIPCHK(h, launch_finalize(prec, N, 0, h->partP.p, h->partE.p, h->Adiag.as<double>(), h->yd.as<float>(),
                                   h->Pt.p, h->S.p, h->alpha_d.as<double>(), h->blk1.as<double>(),
-                                  h->blk2.as<double>(), st, s));
+                                  h->blk2.as<double>(), st, s, boxC));
         HIPCHK(h, launch_status(nblk, h->blk1.as<double>(), h->blk2.as<double>(), st, h->trace_d.as<double>(),
                                 rule, s));
         if ((t + 1) % ce == 0 || t + 1 == p.max_sweeps) {

@@ -21,7 +21,7 @@ OK, E_INVALID, E_NOMEM, E_NOT_CONVERGED, E_DIVERGED, E_DEVICE, E_STATE, E_BUFSIZ
 KERNEL_RBF, KERNEL_PRECOMPUTED, KERNEL_RBF_SPARSE = 0, 2, 3
 KERNEL = {"rbf": KERNEL_RBF, "precomputed": KERNEL_PRECOMPUTED, "rbf_sparse": KERNEL_RBF_SPARSE}
 DIAG = {"none": 0, "softmargin": 1, "dominant_row": 2, "dominant_uniform": 3}
-BOX = {"none": 0, "clip_output": 1}
+BOX = {"none": 0, "clip_output": 1, "project": 2}
 PREC = {"fp64": 0, "fp32": 1, "mixed": 2}
 KSTORE = {"auto": 0, "materialise": 1, "recompute": 2}
 EDGE = {"auto": 0, "stored": 1, "stateless": 2}

@@ -161,3 +161,29 @@ def test_large_sparse_full(torch):
     print(f"large sparse: N={wl.N} edges={E} sweeps={s.sweeps()} build {s.timings()['kbuild_ms']:.1f} ms "
           f"max |r_i| / bound = {worst:.3f}")
     assert worst <= 1.0
+
+
+def test_covertype_full_box_projected(torch, oracle_c):
+    """The box-projected variant at N = 100,000 with C at about the 80th
+    percentile of the unconstrained alpha: sampled rows satisfy the KKT
+    conditions of the box QP (free: |r_i| within the residual bound; at 0:
+    r_i <= bound; at C: r_i >= -bound, with r_i = 1 - (A alpha)_i)."""
+    wl = inputs.make_workload("covertype")
+    s0, _ = _solve(torch, wl)
+    C = float(np.quantile(s0.alpha(), 0.8))
+    s, st = _solve(torch, wl, C=C, box_mode="project", tol_rel=1e-9)
+    assert st == gabp.OK
+    a = s.alpha()
+    assert a.min() >= 0.0 and a.max() <= C and np.sum(a >= C) > 0
+    rng = np.random.default_rng(21)
+    at_c = np.nonzero(a >= C)[0]
+    free = np.nonzero((a > 0) & (a < C))[0]
+    rows = np.sort(np.concatenate([rng.choice(at_c, 24, replace=False), rng.choice(free, 24, replace=False)]))
+    res, ad = oracle_c.residual_rows(wl.X, wl.y, wl.gamma, C, wl.lam, a, rows)
+    bound = 2.0 * ad * TOL * np.max(np.abs(a))
+    for k, i in enumerate(rows):
+        if a[i] >= C:
+            assert res[k] >= -bound[k], (i, res[k], bound[k])
+        else:
+            assert abs(res[k]) <= bound[k], (i, res[k], bound[k])
+    print(f"box-projected covertype: C={C:.4g}, {np.sum(a >= C)} at C, {np.sum(a <= 0)} at 0, {s.sweeps()} sweeps")

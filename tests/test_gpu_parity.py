@@ -448,3 +448,48 @@ def test_grouped_schedule_converges_to_the_solution_in_fewer_sweeps(torch, prec,
           f"(edge {out['grouped'][2]['edge_state']}, depth {out['grouped'][2]['stateless_depth']})")
     assert out["grouped"][1] <= TOL
     assert 3 * out["grouped"][0] <= out["sync"][0]
+
+
+# ------------------------------------------------------- box-projected variant --
+
+def _box_case(name, seed, q):
+    wl = inputs.make_workload(name, n=1100, seed=seed)
+    A, b = R.svm_system(wl.X, wl.y, wl.gamma, wl.C, wl.lam)
+    C = float(np.quantile(R.cholesky_solve(A, b), q))
+    return wl, A, b, C
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
+def test_box_projected_sweeps_match_oracle(torch, prec):
+    """The projected sweep (belief means clipped to [0, C] every sweep)
+    against the oracle's projected sweep, sweep by sweep; the tiny workload
+    has negative unconstrained alphas, so both bounds bind."""
+    wl, _, _, C = _box_case("tiny", 52, 0.9)
+    A, b = R.svm_system(wl.X, wl.y, wl.gamma, C, wl.lam)     # C also enters the diagonal
+    ref = R.gabp_solve_box(A, b, C, max_sweeps=8, tol_rel=0.0, keep_trajectory=True)
+    for t in (1, 2, 3, 5, 8):
+        s, st = run(torch, wl, precision=prec, C=C, box_mode="project", edge_state="stored",
+                    max_sweeps=t, tol_abs=0.0, tol_rel=0.0, stagnation_window=0)
+        err = _rel(s.alpha(), ref.trajectory[t])
+        assert err <= (1e-12 if prec == "fp64" else TOL), (prec, t, err)
+        a = s.alpha()
+        assert a.min() >= 0.0 and a.max() <= C
+
+
+@pytest.mark.parametrize("name,seed,q,kw", [
+    ("tiny", 52, 0.9, dict(precision="fp64")),
+    ("covertype", 51, 0.8, dict(precision="mixed")),
+    ("covertype", 51, 0.8, dict(precision="mixed", schedule="grouped")),
+    ("covertype", 51, 0.8, dict(precision="fp32", edge_state="stateless"))])
+def test_box_projected_solution_is_the_qp_optimum(torch, name, seed, q, kw):
+    """At convergence the projected sweep gives the optimum of the
+    box-constrained dual QP (projected Gauss-Seidel oracle), in every form:
+    stored or stateless edges, synchronous or grouped schedule."""
+    wl, _, _, C = _box_case(name, seed, q)
+    A, b = R.svm_system(wl.X, wl.y, wl.gamma, C, wl.lam)
+    h = R.box_qp_projected_gauss_seidel(A, C)
+    s, st = run(torch, wl, C=C, box_mode="project", tol_rel=1e-10, **kw)
+    err = float(np.max(np.abs(s.alpha() - h)) / np.max(h))
+    n_lo, n_hi = int(np.sum(h <= 0.0)), int(np.sum(h >= C))
+    print(f"box {name} {kw}: {s.sweeps()} sweeps, at 0: {n_lo}, at C: {n_hi}, rel err vs QP {err:.2e}")
+    assert st == gabp.OK and err <= TOL and n_lo + n_hi > 0
