@@ -218,6 +218,59 @@ template <int KIND, int MP> struct RowFrag {
         }
     }
 
+    // Two A blocks (a0, a1) against the same B rows: each B fragment is
+    // loaded once for both MFMA chains.
+    __device__ static void gram2(const RowFrag& a0, const RowFrag& a1, const Features& Fq, int64_t rowA0,
+                                 int64_t rowA1, const Features& Ft, int64_t colB, f32x16& acc0, f32x16& acc1) {
+        if constexpr (MP == 0) {
+            acc0 = mfma_gram_32x32<KIND>(Fq, rowA0, Ft, colB);
+            acc1 = mfma_gram_32x32<KIND>(Fq, rowA1, Ft, colB);
+        } else {
+            const int l = threadIdx.x & 63, h = l >> 5, mp = Ft.m_pad;
+            acc0 = f32x16{};
+            acc1 = f32x16{};
+            if constexpr (KIND == GRAM_F32) {
+                const int half = mp >> 1;
+                const float* pb = Ft.f32 + colB * mp + h * half;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    if (4 * s >= half) continue;
+                    const f32x4v b4 = *reinterpret_cast<const f32x4v*>(pb + 4 * s);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.f[s][e], b4[e], acc0, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.f[s][e], b4[e], acc1, 0, 0, 0);
+                    }
+                }
+            } else {
+                const int64_t ob = colB * mp + 8 * h;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    if (16 * s >= mp) continue;
+                    const bf16x8 b = *reinterpret_cast<const bf16x8*>(Ft.hi + ob + 16 * s);
+                    if constexpr (KIND == GRAM_BF16X3 || KIND == GRAM_BF16X6) {
+                        const bf16x8 bl = *reinterpret_cast<const bf16x8*>(Ft.lo + ob + 16 * s);
+                        if constexpr (KIND == GRAM_BF16X6) {
+                            const bf16x8 b2 = *reinterpret_cast<const bf16x8*>(Ft.lo2 + ob + 16 * s);
+                            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0.hi[s], b2, acc0, 0, 0, 0);
+                            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1.hi[s], b2, acc1, 0, 0, 0);
+                            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0.lo2[s], b, acc0, 0, 0, 0);
+                            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1.lo2[s], b, acc1, 0, 0, 0);
+                            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0.lo[s], bl, acc0, 0, 0, 0);
+                            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1.lo[s], bl, acc1, 0, 0, 0);
+                        }
+                        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0.hi[s], bl, acc0, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1.hi[s], bl, acc1, 0, 0, 0);
+                        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0.lo[s], b, acc0, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1.lo[s], b, acc1, 0, 0, 0);
+                    }
+                    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0.hi[s], b, acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1.hi[s], b, acc1, 0, 0, 0);
+                }
+            }
+        }
+    }
+
     // Gram block of the 32 A rows with the B rows colB (one per lane % 32).
     __device__ f32x16 gram(const Features& Fq, int64_t rowA, const Features& Ft, int64_t colB) const {
         if constexpr (MP == 0) {
@@ -261,6 +314,40 @@ template <int KIND, int MP> struct RowFrag {
         }
     }
 };
+
+// acc += A B^T for register-held fragments of 32 A rows and 32 B rows (both
+// loaded with RowFrag::load; MP > 0), in the products order of
+// mfma_gram_32x32 (correction terms first).  Loading the next B fragment
+// before this call hides its latency behind the MFMA chain.
+template <int KIND, int MP>
+__device__ inline void frag_mma(const RowFrag<KIND, MP>& a, const RowFrag<KIND, MP>& b, f32x16& acc, int mp) {
+    static_assert(MP > 0, "register fragments only");
+    constexpr int NS = RowFrag<KIND, MP>::NS;
+    if constexpr (KIND == GRAM_F32) {
+        const int half = mp >> 1;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (4 * s >= half) continue;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.f[s][e], b.f[s][e], acc, 0, 0, 0);
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (16 * s >= mp) continue;
+            if constexpr (KIND == GRAM_BF16X3 || KIND == GRAM_BF16X6) {
+                if constexpr (KIND == GRAM_BF16X6) {
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.hi[s], b.lo2[s], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.lo2[s], b.hi[s], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.lo[s], b.lo[s], acc, 0, 0, 0);
+                }
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.hi[s], b.lo[s], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.lo[s], b.hi[s], acc, 0, 0, 0);
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.hi[s], b.hi[s], acc, 0, 0, 0);
+        }
+    }
+}
 
 // K' = exp(-gamma d^2) + lambda^2 with d^2 = max(0, n_i + n_j - 2 G_ij), zero
 // for pairs that are not strictly upper (i >= j) or are padding (j >= N).

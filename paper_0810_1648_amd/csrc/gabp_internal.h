@@ -192,6 +192,19 @@ hipError_t launch_sp_fill(const Features& F, const uint32_t* tiles, int64_t ntil
                           float neg_gamma_log2e, float lam2, const int64_t* offsets, const int32_t* counts,
                           uint64_t* keys, float* kv, int32_t* flag, hipStream_t s);
 hipError_t sp_scan(void* tmp, size_t* bytes, const int32_t* in, int64_t* out, int64_t n, hipStream_t s);
+// Locality order: nearest of the K landmark points lm[] for every point
+// (key = landmark << 32 | point, ids = point), rows permuted into that order,
+// block centroids / radii and the tiles that may hold kept pairs, compaction
+// of the tile list, and per-node arrays back to input order.
+hipError_t launch_sp_order(const float* X, int64_t N, int64_t m, const int32_t* lm, int K, uint64_t* key,
+                           int32_t* ids, hipStream_t s);
+hipError_t launch_sp_permute(const float* X, const float* y, int64_t N, int64_t m, const int32_t* order, float* Xp,
+                             float* yp, hipStream_t s);
+hipError_t launch_sp_prune(const float* Xp, int64_t N, int64_t m, int NB, const uint32_t* tiles, int64_t nt,
+                           double cut, double* cent, double* rad, uint8_t* keep, hipStream_t s);
+hipError_t sp_select(void* tmp, size_t* bytes, const uint32_t* in, const uint8_t* flags, uint32_t* out,
+                     int64_t* nsel, int64_t n, hipStream_t s);
+hipError_t launch_sp_unpermute(const double* in, const int32_t* order, int64_t N, double* out, hipStream_t s);
 hipError_t sp_sort_keys(void* tmp, size_t* bytes, const uint64_t* kin, uint64_t* kout, const float* vin,
                         float* vout, int64_t n, hipStream_t s);
 hipError_t sp_sort_ids(void* tmp, size_t* bytes, const uint64_t* kin, uint64_t* kout, const int32_t* vin,

@@ -23,38 +23,64 @@ namespace gabp {
 
 namespace {
 
-// Thresholded distances of one tile on MFMA.  Wave w walks the 32-row bands
-// w and w + 4 and the eight 32-column blocks; `visit(i, j, d2)` is called for
-// every kept pair i < j < N with lane-uniform control flow.
+// Thresholded distances of one tile on MFMA.  Wave w computes the 32-row
+// bands w and w + 4 together (their A fragments in registers, each B
+// fragment loaded once for both) and walks the eight 32-column blocks.  For
+// every block, `visit(k0, k1, i0r, jcol, d2a, d2b)` receives the ballots of
+// kept pairs of both bands per output register (k0[r], k1[r]) and the
+// distances; blocks without any kept pair cost one ballot per register.
+// The keep test is one explicit FMA and a compare, identical in every pass.
 template <int KIND, int MP, class Visit>
 __device__ inline void sp_tile(const Features& F, const TileCoord& tc, int64_t N, float cut, Visit&& visit) {
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6, h = l >> 5, l32 = l & 31;
     const int64_t i0 = (int64_t)tc.I * TILE, j0 = (int64_t)tc.J * TILE;
-#pragma unroll 1
-    for (int pass = 0; pass < 2; ++pass) {
-        const int band = w + 4 * pass;
-        const int64_t rowA = i0 + band * 32 + l32;
-        float ni[16];
+    const int64_t rowA0 = i0 + w * 32 + l32, rowA1 = i0 + (w + 4) * 32 + l32;
+    float ni0[16], ni1[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) ni[r] = F.nrm[i0 + band * 32 + 8 * (r >> 2) + 4 * h + (r & 3)];
-        RowFrag<KIND, MP> fa;
-        fa.load(F, rowA);
+    for (int r = 0; r < 16; ++r) {
+        ni0[r] = F.nrm[i0 + w * 32 + 8 * (r >> 2) + 4 * h + (r & 3)];
+        ni1[r] = F.nrm[i0 + (w + 4) * 32 + 8 * (r >> 2) + 4 * h + (r & 3)];
+    }
+    RowFrag<KIND, MP> fa0, fa1, fb;
+    fa0.load(F, rowA0);
+    fa1.load(F, rowA1);
+    // first column block with a pair i < j for the lower band
+    int cb0 = 0;
+    while (cb0 < TILE / 32 && j0 + cb0 * 32 + 31 < i0 + w * 32) ++cb0;
+    if constexpr (MP > 0) fb.load(F, j0 + cb0 * 32 + l32);
 #pragma unroll 1
-        for (int cb = 0; cb < TILE / 32; ++cb) {
-            // blocks wholly below the diagonal hold no pair i < j
-            if (j0 + cb * 32 + 31 < i0 + band * 32) continue;
-            const int64_t j = j0 + cb * 32 + l32;
-            const f32x16 acc = fa.gram(F, rowA, F, j);
-            const float nj = F.nrm[j];
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t i = i0 + band * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-                // one explicit FMA: the count and fill passes round identically
-                const float d2 = fmaxf(fmaf(-2.0f, acc[r], ni[r] + nj), 0.0f);
-                const bool keep = (i < j) && (j < N) && (d2 <= cut);
-                visit(keep, i, j, d2);
-            }
+    for (int cb = cb0; cb < TILE / 32; ++cb) {
+        const int64_t j = j0 + cb * 32 + l32;
+        f32x16 g0 = {}, g1 = {};
+        if constexpr (MP > 0) {
+            // the next block's B fragment is in flight while this one's MFMAs run
+            RowFrag<KIND, MP> fn;
+            fn.load(F, j0 + (cb + 1 < TILE / 32 ? cb + 1 : cb) * 32 + l32);
+            frag_mma(fa0, fb, g0, F.m_pad);
+            frag_mma(fa1, fb, g1, F.m_pad);
+            fb = fn;
+        } else {
+            RowFrag<KIND, MP>::gram2(fa0, fa1, F, rowA0, rowA1, F, j, g0, g1);
         }
+        const float nj = F.nrm[j];
+        // the index tests matter only on diagonal tiles and in the last column block
+        const bool plain = (tc.I < tc.J) && (j0 + cb * 32 + 31 < N);
+        uint64_t k0[16], k1[16], any = 0;
+        float d0[16], d1[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t ia = i0 + w * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+            const int64_t ib = ia + 128;
+            d0[r] = fmaxf(fmaf(-2.0f, g0[r], ni0[r] + nj), 0.0f);
+            d1[r] = fmaxf(fmaf(-2.0f, g1[r], ni1[r] + nj), 0.0f);
+            const bool c0 = d0[r] <= cut && (plain || (ia < j && j < N));
+            const bool c1 = d1[r] <= cut && (plain || (ib < j && j < N));
+            k0[r] = __ballot(c0);
+            k1[r] = __ballot(c1);
+            any |= k0[r] | k1[r];
+        }
+        if (any == 0) continue;
+        visit(k0, k1, i0 + w * 32, j, d0, d1);
     }
 }
 
@@ -63,10 +89,12 @@ __global__ __launch_bounds__(WG) void k_sp_count(Features F, const uint32_t* __r
                                                  float cut, int32_t* __restrict__ counts) {
     __shared__ int wsum[4];
     const TileCoord tc = tile_of(tiles);
-    int c = 0;
-    sp_tile<KIND, MP>(F, tc, N, cut, [&](bool keep, int64_t, int64_t, float) { c += keep ? 1 : 0; });
-    // wave sum, then workgroup sum (integer: order does not matter)
-    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    int c = 0;   // wave-uniform
+    sp_tile<KIND, MP>(F, tc, N, cut, [&](const uint64_t* k0, const uint64_t* k1, int64_t, int64_t, const float*,
+                                         const float*) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) c += __popcll(k0[r]) + __popcll(k1[r]);
+    });
     if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
     __syncthreads();
     if (threadIdx.x == 0) counts[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
@@ -87,22 +115,31 @@ __global__ __launch_bounds__(WG) void k_sp_fill(Features F, const uint32_t* __re
     __syncthreads();
     const int64_t base = offsets[blockIdx.x];
     const int cap = counts[blockIdx.x];
-    const int l = threadIdx.x & 63;
-    sp_tile<KIND, MP>(F, tc, N, cut, [&](bool keep, int64_t i, int64_t j, float d2) {
-        // one LDS atomic per wave and register: the wave's kept lanes take
-        // consecutive slots in lane order
-        const uint64_t mask = __ballot(keep);
-        if (mask == 0) return;
-        int first = 0;
-        if (l == __builtin_ctzll(mask)) first = atomicAdd(&cursor, __popcll(mask));
-        first = __shfl(first, __builtin_ctzll(mask));
-        if (keep) {
-            const int slot = first + __popcll(mask & ((1ull << l) - 1ull));
-            if (slot < cap) {
-                keys[base + slot] = ((uint64_t)i << 32) | (uint64_t)j;
-                kv[base + slot] = exp2f(neg_gamma_log2e * d2) + lam2;
-            } else {
-                atomicOr(flag, 1);
+    const int l = threadIdx.x & 63, h = l >> 5;
+    sp_tile<KIND, MP>(F, tc, N, cut, [&](const uint64_t* k0, const uint64_t* k1, int64_t ib, int64_t j,
+                                         const float* d0, const float* d1) {
+        // per register with kept pairs: one LDS atomic for the wave, kept
+        // lanes take consecutive slots in lane order
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const uint64_t mask = half ? k1[r] : k0[r];
+                if (mask == 0) continue;
+                int first = 0;
+                if (l == 0) first = atomicAdd(&cursor, __popcll(mask));
+                first = __shfl(first, 0);
+                if ((mask >> l) & 1ull) {
+                    const int slot = first + __popcll(mask & ((1ull << l) - 1ull));
+                    const int64_t i = ib + 128 * half + 8 * (r >> 2) + 4 * h + (r & 3);
+                    const float d2 = half ? d1[r] : d0[r];
+                    if (slot < cap) {
+                        keys[base + slot] = ((uint64_t)i << 32) | (uint64_t)j;
+                        kv[base + slot] = exp2f(neg_gamma_log2e * d2) + lam2;
+                    } else {
+                        atomicOr(flag, 1);
+                    }
+                }
             }
         }
     });
@@ -222,6 +259,116 @@ __global__ __launch_bounds__(WG) void k_sp_gather(int64_t N, const int64_t* __re
     if (k < N && q == 0) { partP[k] = p; partE[k] = e; }
 }
 
+// ---- locality order and tile pruning
+//
+// Points are reordered so that each 256-point block is compact: every point
+// goes to its nearest landmark (landmarks: K evenly spaced input points;
+// ties to the smaller landmark index) and points are sorted by (landmark,
+// input index).  Then a tile whose blocks are provably farther apart than
+// the cut is skipped by the build (triangle inequality on block centroids
+// and radii), and the neighbours of a node sit in few cache lines during the
+// sweep.  GaBP is equivariant under the relabelling; results are returned in
+// input order.
+
+// Nearest landmark of every point by direct FP32 differences; landmarks are
+// staged through LDS in chunks.  key = (landmark << 32) | point.
+__global__ __launch_bounds__(WG) void k_sp_assign(const float* __restrict__ X, int64_t N, int64_t m,
+                                                  const int32_t* __restrict__ lm, int K, uint64_t* __restrict__ key,
+                                                  int32_t* __restrict__ ids) {
+    extern __shared__ float sl[];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int chunk = (int)(8192 / m) > 0 ? (int)(8192 / m) : 1;
+    float best = INFINITY;
+    int arg = 0;
+    for (int k0 = 0; k0 < K; k0 += chunk) {
+        const int kc = (K - k0 < chunk) ? K - k0 : chunk;
+        __syncthreads();
+        for (int64_t t = threadIdx.x; t < (int64_t)kc * m; t += blockDim.x)
+            sl[t] = X[(int64_t)lm[k0 + t / m] * m + t % m];
+        __syncthreads();
+        if (i < N) {
+            for (int k = 0; k < kc; ++k) {
+                float d2 = 0.0f;
+                for (int64_t c = 0; c < m; ++c) {
+                    const float d = X[i * m + c] - sl[(int64_t)k * m + c];
+                    d2 = fmaf(d, d, d2);
+                }
+                if (d2 < best) { best = d2; arg = k0 + k; }
+            }
+        }
+    }
+    if (i < N) {
+        key[i] = ((uint64_t)(uint32_t)arg << 32) | (uint64_t)i;
+        ids[i] = (int32_t)i;
+    }
+}
+
+// Rows of X and labels in the new order: Xp[r] = X[order[r]].
+__global__ void k_sp_permute(const float* __restrict__ X, const float* __restrict__ y, int64_t N, int64_t m,
+                             const int32_t* __restrict__ order, float* __restrict__ Xp, float* __restrict__ yp) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * m) return;
+    const int64_t r = t / m, c = t % m;
+    Xp[t] = X[(int64_t)order[r] * m + c];
+    if (c == 0) yp[r] = y[order[r]];
+}
+
+// Centroid (FP64) and radius (max distance to it, FP64) of each block of
+// 256 reordered points; one workgroup per block.
+__global__ __launch_bounds__(WG) void k_sp_block_bounds(const float* __restrict__ Xp, int64_t N, int64_t m,
+                                                        double* __restrict__ cent, double* __restrict__ rad) {
+    __shared__ double sh[WG];
+    __shared__ double sh4[4];
+    const int64_t b = blockIdx.x;
+    const int64_t r0 = b * TILE;
+    const int64_t nr = (N - r0 < TILE) ? N - r0 : TILE;
+    for (int64_t c = 0; c < m; ++c) {
+        double v = (threadIdx.x < nr) ? (double)Xp[(r0 + threadIdx.x) * m + c] : 0.0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = WG / 2; o > 0; o >>= 1) {
+            if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) cent[b * m + c] = sh[0] / (double)nr;
+        __syncthreads();
+    }
+    double d2 = 0.0;
+    if (threadIdx.x < nr)
+        for (int64_t c = 0; c < m; ++c) {
+            const double d = (double)Xp[(r0 + threadIdx.x) * m + c] - cent[b * m + c];
+            d2 += d * d;
+        }
+    d2 = block_max(threadIdx.x < nr ? d2 : 0.0, sh4);
+    if (threadIdx.x == 0) rad[b] = sqrt(d2);
+}
+
+// keep[t] = 1 unless every pair of tile t is provably beyond the cut:
+// ||x_i - x_j|| >= ||c_I - c_J|| - r_I - r_J.  The margin makes the test
+// conservative against the rounding of the bounds and of the device's own
+// distances (a skipped pair has d^2 > 1.001 cut).
+__global__ void k_sp_prune(const uint32_t* __restrict__ tiles, int64_t nt, int64_t m, const double* __restrict__ cent,
+                           const double* __restrict__ rad, double cut, uint8_t* __restrict__ keep) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    const uint32_t ij = tiles[t];
+    const int I = (int)(ij >> 16), J = (int)(ij & 0xFFFFu);
+    double dc2 = 0.0;
+    for (int64_t c = 0; c < m; ++c) {
+        const double d = cent[(int64_t)I * m + c] - cent[(int64_t)J * m + c];
+        dc2 += d * d;
+    }
+    const double gap = sqrt(dc2) - (rad[I] + rad[J]) * (1.0 + 1e-6) - 1e-6;
+    keep[t] = (gap > 0.0 && gap * gap > 1.001 * cut) ? 0 : 1;
+}
+
+// out[order[r]] = in[r]: a per-node array back to input order.
+__global__ void k_sp_unpermute(const double* __restrict__ in, const int32_t* __restrict__ order, int64_t N,
+                               double* __restrict__ out) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < N) out[order[r]] = in[r];
+}
+
 template <int KIND>
 void sp_build_kind(bool fill, int mp, dim3 g, const Features& F, const uint32_t* tiles, int64_t N, float cut,
                    float c, float lam2, int32_t* counts, const int64_t* offsets, uint64_t* keys, float* kv,
@@ -234,9 +381,10 @@ void sp_build_kind(bool fill, int mp, dim3 g, const Features& F, const uint32_t*
         else                                                                                                 \
             hipLaunchKernelGGL((k_sp_count<KIND, MPV>), g, dim3(WG), 0, s, F, tiles, N, cut, counts);        \
     } while (0)
+    // register-held fragments of two bands plus the prefetched B fragment
+    // fit up to 64 features; beyond, fragments are reloaded per block
     if (mp <= 32) GABP_SP_LAUNCH(32);
     else if (mp <= 64) GABP_SP_LAUNCH(64);
-    else if (mp <= 128) GABP_SP_LAUNCH(128);
     else GABP_SP_LAUNCH(0);
 #undef GABP_SP_LAUNCH
 }
@@ -269,6 +417,37 @@ hipError_t launch_sp_fill(const Features& F, const uint32_t* tiles, int64_t ntil
                           uint64_t* keys, float* kv, int32_t* flag, hipStream_t s) {
     return sp_build(true, F, tiles, ntiles, N, cut, neg_gamma_log2e, lam2, const_cast<int32_t*>(counts), offsets,
                     keys, kv, flag, s);
+}
+
+hipError_t launch_sp_order(const float* X, int64_t N, int64_t m, const int32_t* lm, int K, uint64_t* key,
+                           int32_t* ids, hipStream_t s) {
+    const int chunk = (int)(8192 / m) > 0 ? (int)(8192 / m) : 1;
+    const size_t lds = (size_t)std::min<int64_t>(chunk, K) * m * sizeof(float);
+    hipLaunchKernelGGL(k_sp_assign, dim3(blocks(N)), dim3(WG), lds, s, X, N, m, lm, K, key, ids);
+    return hipGetLastError();
+}
+
+hipError_t launch_sp_permute(const float* X, const float* y, int64_t N, int64_t m, const int32_t* order, float* Xp,
+                             float* yp, hipStream_t s) {
+    hipLaunchKernelGGL(k_sp_permute, dim3(blocks(N * m)), dim3(WG), 0, s, X, y, N, m, order, Xp, yp);
+    return hipGetLastError();
+}
+
+hipError_t launch_sp_prune(const float* Xp, int64_t N, int64_t m, int NB, const uint32_t* tiles, int64_t nt,
+                           double cut, double* cent, double* rad, uint8_t* keep, hipStream_t s) {
+    hipLaunchKernelGGL(k_sp_block_bounds, dim3((unsigned)NB), dim3(WG), 0, s, Xp, N, m, cent, rad);
+    hipLaunchKernelGGL(k_sp_prune, dim3(blocks(nt)), dim3(WG), 0, s, tiles, nt, m, cent, rad, cut, keep);
+    return hipGetLastError();
+}
+
+hipError_t sp_select(void* tmp, size_t* bytes, const uint32_t* in, const uint8_t* flags, uint32_t* out,
+                     int64_t* nsel, int64_t n, hipStream_t s) {
+    return hipcub::DeviceSelect::Flagged(tmp, *bytes, in, flags, out, nsel, (int)n, s);
+}
+
+hipError_t launch_sp_unpermute(const double* in, const int32_t* order, int64_t N, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_sp_unpermute, dim3(blocks(N)), dim3(WG), 0, s, in, order, N, out);
+    return hipGetLastError();
 }
 
 hipError_t sp_scan(void* tmp, size_t* bytes, const int32_t* in, int64_t* out, int64_t n, hipStream_t s) {

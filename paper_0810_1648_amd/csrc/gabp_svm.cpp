@@ -106,16 +106,16 @@ struct gabp_svm {
     // sparsified kernel: tile counts and offsets, keys, K' per edge, edge
     // ends, degrees and offsets of the i-end and j-end lists, permutation
     DevBuf sp_cnt, sp_toff, sp_keys, sp_keys2, sp_kv, sp_kv2, sp_ei, sp_ej, sp_degi, sp_degj, sp_offi,
-        sp_offj, sp_ids, sp_perm, sp_tmp;
+        sp_offj, sp_ids, sp_perm, sp_tmp, sp_order, sp_Xp, sp_cent, sp_rad, sp_keep, sp_tsel, sp_nsel;
     bool sparse = false;
     int64_t n_edges = 0;
 
-    DevBuf* all[52] = {&tiles, &Kp, &Pf, &Pb, &Ef, &Eb, &partP, &partE, &Xin, &yd, &mean,
+    DevBuf* all[59] = {&tiles, &Kp, &Pf, &Pb, &Ef, &Eb, &partP, &partE, &Xin, &yd, &mean,
                        &xs32, &xhi, &xlo, &xlo2, &x64, &nrm, &kdiag, &rowmax, &rsum, &Adiag, &Pt, &S, &alpha_d,
                        &blk1, &blk2, &one, &status_d, &trace_d, &flag, &tmp, &Kin, &q_rows,
                        &q_cols, &q_out, &glist, &sp_cnt, &sp_toff, &sp_keys, &sp_keys2, &sp_kv, &sp_kv2,
                        &sp_ei, &sp_ej, &sp_degi, &sp_degj, &sp_offi, &sp_offj, &sp_ids, &sp_perm, &sp_tmp,
-                       nullptr};
+                       &sp_order, &sp_Xp, &sp_cent, &sp_rad, &sp_keep, &sp_tsel, &sp_nsel, nullptr};
     size_t held() const {
         size_t b = 0;
         for (int k = 0; all[k]; ++k) b += all[k]->bytes;
@@ -651,6 +651,9 @@ gabp_status solve_sparse_impl(gabp_svm* h, const float* X, const float* y, int64
     A(h->trace_d, (size_t)p.max_sweeps * 8);
     A(h->sp_degi, (size_t)(N + 1) * 4); A(h->sp_degj, (size_t)(N + 1) * 4);
     A(h->sp_offi, (size_t)(N + 1) * 8); A(h->sp_offj, (size_t)(N + 1) * 8);
+    A(h->sp_order, (size_t)N * 4); A(h->sp_Xp, (size_t)N * m * 4);
+    A(h->sp_cent, (size_t)NB * m * 8); A(h->sp_rad, (size_t)NB * 8);
+    A(h->sp_keep, (size_t)nt); A(h->sp_tsel, (size_t)nt * 4); A(h->sp_nsel, 8);
     if (ae != hipSuccess) {
         h->release_all();
         return fail(h, GABP_E_NOMEM, std::string("device allocation failed: ") + hipGetErrorString(ae));
@@ -676,11 +679,38 @@ gabp_status solve_sparse_impl(gabp_svm* h, const float* X, const float* y, int64
         if (fl & 1) return fail(h, GABP_E_INVALID, "X has a non-finite entry");
         if (fl & 2) return fail(h, GABP_E_INVALID, "labels must be +1 or -1");
     }
+    // locality order: nearest of K evenly spaced landmark points, then sort
+    // by (landmark, input index); every later step works on the reordered
+    // points, and the outputs go back to input order
+    const int K = (int)std::max<int64_t>(1, std::min<int64_t>(4096, N / 2048));
+    {
+        std::vector<int32_t> lm((size_t)K);
+        for (int k = 0; k < K; ++k) lm[(size_t)k] = (int32_t)((int64_t)k * N / K);
+        if (h->sp_ids.ensure((size_t)N * 4) != hipSuccess || h->sp_perm.ensure((size_t)K * 4) != hipSuccess ||
+            h->sp_keys.ensure((size_t)N * 8) != hipSuccess || h->sp_keys2.ensure((size_t)N * 8) != hipSuccess) {
+            h->release_all();
+            return fail(h, GABP_E_NOMEM, "device allocation of the ordering arrays failed");
+        }
+        HIPCHK(h, hipMemcpyAsync(h->sp_perm.p, lm.data(), (size_t)K * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(h, launch_sp_order(Xd, N, m, h->sp_perm.as<int32_t>(), K, h->sp_keys.as<uint64_t>(),
+                                  h->sp_ids.as<int32_t>(), s));
+        size_t ob = 0;
+        HIPCHK(h, sp_sort_ids(nullptr, &ob, h->sp_keys.as<uint64_t>(), h->sp_keys2.as<uint64_t>(),
+                              h->sp_ids.as<int32_t>(), h->sp_order.as<int32_t>(), N, s));
+        if (h->sp_tmp.ensure(ob) != hipSuccess) { h->release_all(); return fail(h, GABP_E_NOMEM, "sort storage"); }
+        HIPCHK(h, sp_sort_ids(h->sp_tmp.p, &ob, h->sp_keys.as<uint64_t>(), h->sp_keys2.as<uint64_t>(),
+                              h->sp_ids.as<int32_t>(), h->sp_order.as<int32_t>(), N, s));
+        // labels in the new order go to yd (the sweep's b); the input order stays in Xin / the caller's y
+        HIPCHK(h, hipMemcpyAsync(h->tmp.p, h->yd.p, (size_t)N * 4, hipMemcpyDeviceToDevice, s));
+        HIPCHK(h, launch_sp_permute(Xd, h->tmp.as<float>(), N, m, h->sp_order.as<int32_t>(), h->sp_Xp.as<float>(),
+                                    h->yd.as<float>(), s));
+    }
+    const float* Xp = h->sp_Xp.as<float>();
     Features F{};
     F.m_pad = m_pad;
     F.kind = gram;
-    HIPCHK(h, launch_colmean(Xd, N, m, h->mean.as<double>(), s));
-    HIPCHK(h, launch_stage(Xd, h->mean.as<double>(), N, m, NPAD, m_pad, gram, h->xs32.as<float>(),
+    HIPCHK(h, launch_colmean(Xp, N, m, h->mean.as<double>(), s));
+    HIPCHK(h, launch_stage(Xp, h->mean.as<double>(), N, m, NPAD, m_pad, gram, h->xs32.as<float>(),
                            h->xhi.as<uint16_t>(), h->xlo.as<uint16_t>(), h->xlo2.as<uint16_t>(), nullptr,
                            h->nrm.as<float>(), s));
     F.f32 = h->xs32.as<float>(); F.hi = h->xhi.as<uint16_t>(); F.lo = h->xlo.as<uint16_t>();
@@ -689,24 +719,40 @@ gabp_status solve_sparse_impl(gabp_svm* h, const float* X, const float* y, int64
 
     // ---- graph: count per tile, offsets, fill, sort by (i, j), transposed order
     HIPCHK(h, launch_fill_tiles(h->tiles.as<uint32_t>(), NB, s));
-    const float cutf = (float)cut;
-    HIPCHK(h, launch_sp_count(F, h->tiles.as<uint32_t>(), nt, N, cutf, h->sp_cnt.as<int32_t>(), s));
-    size_t tb = 0;
-    HIPCHK(h, sp_scan(nullptr, &tb, h->sp_cnt.as<int32_t>(), h->sp_toff.as<int64_t>(), nt, s));
-    if (h->sp_tmp.ensure(tb) != hipSuccess) { h->release_all(); return fail(h, GABP_E_NOMEM, "scan storage"); }
-    HIPCHK(h, sp_scan(h->sp_tmp.p, &tb, h->sp_cnt.as<int32_t>(), h->sp_toff.as<int64_t>(), nt, s));
-    int64_t last_off = 0;
-    int32_t last_cnt = 0;
-    HIPCHK(h, hipMemcpyAsync(&last_off, h->sp_toff.as<int64_t>() + (nt - 1), 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(h, hipMemcpyAsync(&last_cnt, h->sp_cnt.as<int32_t>() + (nt - 1), 4, hipMemcpyDeviceToHost, s));
+    // tiles that may hold kept pairs (the others are provably beyond the cut)
+    HIPCHK(h, launch_sp_prune(Xp, N, m, NB, h->tiles.as<uint32_t>(), nt, cut, h->sp_cent.as<double>(),
+                              h->sp_rad.as<double>(), h->sp_keep.as<uint8_t>(), s));
+    size_t pb = 0;
+    HIPCHK(h, sp_select(nullptr, &pb, h->tiles.as<uint32_t>(), h->sp_keep.as<uint8_t>(), h->sp_tsel.as<uint32_t>(),
+                        h->sp_nsel.as<int64_t>(), nt, s));
+    if (h->sp_tmp.ensure(pb) != hipSuccess) { h->release_all(); return fail(h, GABP_E_NOMEM, "select storage"); }
+    HIPCHK(h, sp_select(h->sp_tmp.p, &pb, h->tiles.as<uint32_t>(), h->sp_keep.as<uint8_t>(), h->sp_tsel.as<uint32_t>(),
+                        h->sp_nsel.as<int64_t>(), nt, s));
+    int64_t nts = 0;
+    HIPCHK(h, hipMemcpyAsync(&nts, h->sp_nsel.p, 8, hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));
-    const int64_t E = last_off + last_cnt;
+    const uint32_t* tsel = h->sp_tsel.as<uint32_t>();
+    const float cutf = (float)cut;
+    int64_t E = 0;
+    size_t tb = 0;
+    if (nts > 0) {
+        HIPCHK(h, launch_sp_count(F, tsel, nts, N, cutf, h->sp_cnt.as<int32_t>(), s));
+        HIPCHK(h, sp_scan(nullptr, &tb, h->sp_cnt.as<int32_t>(), h->sp_toff.as<int64_t>(), nts, s));
+        if (h->sp_tmp.ensure(tb) != hipSuccess) { h->release_all(); return fail(h, GABP_E_NOMEM, "scan storage"); }
+        HIPCHK(h, sp_scan(h->sp_tmp.p, &tb, h->sp_cnt.as<int32_t>(), h->sp_toff.as<int64_t>(), nts, s));
+        int64_t last_off = 0;
+        int32_t last_cnt = 0;
+        HIPCHK(h, hipMemcpyAsync(&last_off, h->sp_toff.as<int64_t>() + (nts - 1), 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(h, hipMemcpyAsync(&last_cnt, h->sp_cnt.as<int32_t>() + (nts - 1), 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+        E = last_off + last_cnt;
+    }
     if (E >= (int64_t)1 << 31) return fail(h, GABP_E_INVALID, "more than 2^31 - 1 kept pairs: raise sparse_tau");
     const size_t st_bytes = 4;   // records and K' per edge in FP32 storage
     A(h->sp_keys, (size_t)E * 8); A(h->sp_keys2, (size_t)E * 8);
     A(h->sp_kv, (size_t)E * 4); A(h->sp_kv2, (size_t)E * 4);
     A(h->sp_ei, (size_t)E * 4); A(h->sp_ej, (size_t)E * 4);
-    A(h->sp_ids, (size_t)E * 4); A(h->sp_perm, (size_t)E * 4);
+    A(h->sp_ids, (size_t)std::max(E, N) * 4); A(h->sp_perm, (size_t)E * 4);
     // records: (P, E) pairs per edge and direction; packed aggregates
     A(h->Pf, (size_t)2 * E * st_bytes); A(h->Pb, (size_t)2 * E * st_bytes);
     A(h->Ef, (size_t)2 * NPAD * 8);
@@ -717,7 +763,8 @@ gabp_status solve_sparse_impl(gabp_svm* h, const float* X, const float* y, int64
     }
     const float c = (float)(-p.gamma * 1.4426950408889634);
     HIPCHK(h, hipMemsetAsync(h->flag.p, 0, 4, s));
-    HIPCHK(h, launch_sp_fill(F, h->tiles.as<uint32_t>(), nt, N, cutf, c, (float)(lam * lam),
+    if (nts > 0)
+        HIPCHK(h, launch_sp_fill(F, tsel, nts, N, cutf, c, (float)(lam * lam),
                              h->sp_toff.as<int64_t>(), h->sp_cnt.as<int32_t>(), h->sp_keys.as<uint64_t>(),
                              h->sp_kv.as<float>(), h->flag.as<int32_t>(), s));
     {
@@ -805,16 +852,24 @@ gabp_status solve_sparse_impl(gabp_svm* h, const float* X, const float* y, int64
     }
     HIPCHK(h, hipEventRecord(ev[4], s));
 
-    // ---- outputs
+    // ---- outputs, back in input order (through partP as scratch)
     h->alpha.assign((size_t)N, 0.0);
     h->ptilde.assign((size_t)N, 0.0);
     h->adiag.assign((size_t)N, 0.0);
     h->yh.assign((size_t)N, 0.0f);
+    double* scr = h->partP.as<double>();
+    const int32_t* ord = h->sp_order.as<int32_t>();
+    HIPCHK(h, launch_sp_unpermute(h->alpha_d.as<double>(), ord, N, scr, s));
+    HIPCHK(h, hipMemcpyAsync(h->alpha.data(), scr, (size_t)N * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
     HIPCHK(h, launch_convert_agg(prec, h->Pt.p, h->tmp.as<double>(), N, s));
-    HIPCHK(h, hipMemcpyAsync(h->alpha.data(), h->alpha_d.p, (size_t)N * 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(h, hipMemcpyAsync(h->ptilde.data(), h->tmp.p, (size_t)N * 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(h, hipMemcpyAsync(h->adiag.data(), h->Adiag.p, (size_t)N * 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(h, hipMemcpyAsync(h->yh.data(), h->yd.p, (size_t)N * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, launch_sp_unpermute(h->tmp.as<double>(), ord, N, scr, s));
+    HIPCHK(h, hipMemcpyAsync(h->ptilde.data(), scr, (size_t)N * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    HIPCHK(h, launch_sp_unpermute(h->Adiag.as<double>(), ord, N, scr, s));
+    HIPCHK(h, hipMemcpyAsync(h->adiag.data(), scr, (size_t)N * 8, hipMemcpyDeviceToHost, s));
+    if (mem == GABP_MEM_HOST) std::copy(y, y + N, h->yh.begin());
+    else HIPCHK(h, hipMemcpyAsync(h->yh.data(), y, (size_t)N * 4, hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipMemcpyAsync(&hs, st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipEventRecord(ev[5], s));
     HIPCHK(h, hipStreamSynchronize(s));
@@ -1005,12 +1060,20 @@ gabp_status gabp_svm_query(const gabp_svm* h, int32_t what, void* dst, size_t by
             if (!h->sparse) return GABP_E_STATE;
             const size_t E = (size_t)h->n_edges;
             if (bytes < E * 16) return GABP_E_BUFSIZE;
-            std::vector<int32_t> a(E), b(E);
+            std::vector<int32_t> a(E), b(E), ord(N);
             if (E && (hipMemcpy(a.data(), h->sp_ei.p, E * 4, hipMemcpyDeviceToHost) != hipSuccess ||
-                      hipMemcpy(b.data(), h->sp_ej.p, E * 4, hipMemcpyDeviceToHost) != hipSuccess))
+                      hipMemcpy(b.data(), h->sp_ej.p, E * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+                      hipMemcpy(ord.data(), h->sp_order.p, N * 4, hipMemcpyDeviceToHost) != hipSuccess))
                 return GABP_E_DEVICE;
+            // input labels, i < j, lexicographic
+            std::vector<uint64_t> keys(E);
+            for (size_t e = 0; e < E; ++e) {
+                const uint64_t u = (uint64_t)ord[(size_t)a[e]], v = (uint64_t)ord[(size_t)b[e]];
+                keys[e] = (std::min(u, v) << 32) | std::max(u, v);
+            }
+            std::sort(keys.begin(), keys.end());
             int64_t* o = static_cast<int64_t*>(dst);
-            for (size_t e = 0; e < E; ++e) { o[2 * e] = a[e]; o[2 * e + 1] = b[e]; }
+            for (size_t e = 0; e < E; ++e) { o[2 * e] = (int64_t)(keys[e] >> 32); o[2 * e + 1] = (int64_t)(keys[e] & 0xFFFFFFFFull); }
             return GABP_OK;
         }
         default: return GABP_E_INVALID;
