@@ -66,25 +66,29 @@ def counter_traffic(path, key):
 def stateless_slots_per_pair(levels, series, precision="mixed"):
     """Algorithmic VALU issue slots per pair of one stateless sweep with
     `levels` unrolled levels (both directions of the pair), counting a
-    multiply-add as one slot (fused, as the hardware issues it) and a
-    transcendental as four.  Shared: the conversion of K' to the top level's
-    type (MIXED only) and a^2.
-    Series reciprocals: the deepest level starts from zero messages
-    (4 products); each middle level forms, per direction, e = P_rev / P~, the
-    one-term reciprocal (2), the new P (1) and E (2): 12; the top level forms,
-    per direction, e, the two-term series (2), the scale (1), and the
-    accumulation of P (1, fused) and of E (2, one fused): 14.
+    multiply-add as one slot (contracted, as the compiler emits it) and a
+    transcendental as four.
+    Series reciprocals (every precision; MIXED computes these messages in
+    FP32 from FP32 K', so no conversion): a^2 (1); the deepest level starts
+    from zero messages: the two P products (2; its E products fold into the
+    next level's S - E_rev by a multiply-add); each middle level forms, per
+    direction, e = P_rev / P~ (1), the one-term reciprocal (1), the scale by
+    a (1), the new P (1) and the new E (1, its product folding into the next
+    level): 10; the top level forms, per direction, e (1), the two-term
+    series (2), the scale (1), S - E_rev (1) and the accumulations of P and E
+    (2, each fused with its product): 14.  With one level the top level
+    alone runs from zero reverse messages: 6.
     Exact reciprocals: per direction and level the cavity precision (1), the
     reciprocal (FP32: 4; FP64: 4 + two Newton steps of 2 FMAs = 8) and the
-    messages (4; 3 at the top, where the accumulations fuse)."""
-    cvt = 1 if precision == "mixed" else 0
+    messages (4; 3 at the top, where the accumulations fuse); MIXED adds the
+    conversion of K' to FP64 (1)."""
     if series:
         if levels <= 1:
-            return cvt + 2 * 3
-        return cvt + 1 + 4 + 12 * (levels - 2) + 14
+            return 2 * 3
+        return 1 + 2 + 10 * (levels - 2) + 14
+    cvt = 1 if precision == "mixed" else 0
     r_top = 4 if precision == "fp32" else 8
-    low_double = precision == "fp64" or (series and levels <= 3)
-    r_low = 8 if low_double else 4
+    r_low = 8 if precision == "fp64" else 4
     return cvt + 1 + 2 * (levels - 1) * (1 + r_low + 4) + 2 * (1 + r_top + 3)
 
 

@@ -390,6 +390,19 @@ __device__ inline void wave_lds_sync() {
 
 // ------------------------------------------------------------------ sweep --
 
+// Type of the message arithmetic.  The MIXED path (FP32 storage, FP64
+// aggregates) with series reciprocals computes its messages in FP32: the
+// cavity denominator P~ - P_reverse is never formed (the series factor
+// 1 + e + e^2 has |e| <= rho^2, bounded a priori, so nothing cancels), the
+// per-node 1/P~ and S/P~ are rounded once from FP64, and FP32 sums of a few
+// messages are added into the FP64 aggregates.  Every other path computes
+// its messages in MT.
+template <class ST, class MT, class AT, bool SER>
+struct MsgT {
+    static constexpr bool F32 = SER && std::is_same<ST, float>::value && std::is_same<AT, double>::value;
+    using T = typename std::conditional<F32, float, MT>::type;
+};
+
 // One synchronous sweep over all tiles.  Template parameters:
 //   ST storage type of K' and the message planes, MT type of the top-level
 //   update (cavity denominators, reciprocals), AT aggregate type;
@@ -416,7 +429,9 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
     // levels they run in the top level's type (FP64 FMA issues at the FP32
     // rate on CDNA4, and no conversions are needed between levels; deeper
     // unrolls keep FP32 to bound the per-column register history)
-    using LT = typename std::conditional<(SER && D <= 3) || std::is_same<ST, double>::value, MT, float>::type;
+    using XT = typename MsgT<ST, MT, AT, SER>::T;
+    constexpr bool XF = MsgT<ST, MT, AT, SER>::F32;
+    using LT = typename std::conditional<(SER && D <= 3) || std::is_same<ST, double>::value, XT, float>::type;
     constexpr bool STORED = (D == 0);
     constexpr int DL = (D > 1) ? D - 1 : 1;   // lower levels held per node
     constexpr int NL = STORED ? 1 : DL;
@@ -437,27 +452,29 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
     ST* Eb = static_cast<ST*>(a.Eb);
 
     // row-node data: top level (P~ or, with SER, 1/P~) and lower levels
-    __shared__ MT sPt[TILE], sS[TILE];
+    __shared__ XT sPt[TILE], sS[TILE];
     __shared__ LT sPtL[NL][NT], sSL[NL][NT], sSIL[SER ? NL : 1][SER ? NT : 1];
-    __shared__ AT rP[4][TILE], rE[4][TILE];
+    // row partials per wave strip (XF: FP32 sums of 64 messages; exact in AT)
+    using RT = typename std::conditional<XF, XT, AT>::type;
+    __shared__ RT rP[4][TILE], rE[4][TILE];
     __shared__ float kband[KSRC == KSRC_RECOMPUTE ? 4 : 1][KSRC == KSRC_RECOMPUTE ? 32 * 64 : 1];
     // stateless: per-lane row partials of two row steps, reduced over the 16
     // column lanes through LDS once per two steps (a DPP tree per row step
-    // costs 24 VALU slots in FP64; this costs about 5)
-    __shared__ AT red[STORED ? 1 : 4][2][2][64];
+    // costs 24 VALU slots in FP64; this costs about 5); XF reduces in FP32
+    __shared__ RT red[STORED ? 1 : 4][2][2][64];
 
     const int64_t top = (int64_t)slot_top * a.NPAD;
     {
-        const MT p = (MT)HP[top + (int64_t)tc.I * TILE + tid];
-        sPt[tid] = SER ? (MT)1 / p : p;
-        sS[tid] = (MT)HS[top + (int64_t)tc.I * TILE + tid];
+        const AT p = HP[top + (int64_t)tc.I * TILE + tid];
+        sPt[tid] = SER ? (XT)((AT)1 / p) : (XT)p;
+        sS[tid] = (XT)HS[top + (int64_t)tc.I * TILE + tid];
     }
-    MT ptj[4], sj[4];
+    XT ptj[4], sj[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        const MT p = (MT)HP[top + (int64_t)tc.J * TILE + col0 + c];
-        ptj[c] = SER ? (MT)1 / p : p;
-        sj[c] = (MT)HS[top + (int64_t)tc.J * TILE + col0 + c];
+        const AT p = HP[top + (int64_t)tc.J * TILE + col0 + c];
+        ptj[c] = SER ? (XT)((AT)1 / p) : (XT)p;
+        sj[c] = (XT)HS[top + (int64_t)tc.J * TILE + col0 + c];
     }
     LT ptjL[DL][4], sjL[DL][4], sijL[SER ? DL : 1][4];
     if constexpr (!STORED) {
@@ -465,23 +482,24 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
         for (int k = 1; k < D; ++k) {
             if (k < L) {
                 const int64_t base = (int64_t)((slot_top - k + a.R) % a.R) * a.NPAD;
-                const LT pr = (LT)HP[base + (int64_t)tc.I * TILE + tid];
-                const LT sr = (LT)HS[base + (int64_t)tc.I * TILE + tid];
-                sPtL[k - 1][tid] = SER ? (LT)1 / pr : pr;
-                sSL[k - 1][tid] = sr;
-                if constexpr (SER) sSIL[k - 1][tid] = sr / pr;
+                const AT pr = HP[base + (int64_t)tc.I * TILE + tid];
+                const AT sr = HS[base + (int64_t)tc.I * TILE + tid];
+                sPtL[k - 1][tid] = SER ? (LT)((AT)1 / pr) : (LT)pr;
+                sSL[k - 1][tid] = (LT)sr;
+                if constexpr (SER) sSIL[k - 1][tid] = (LT)(sr / pr);
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    const LT pc = (LT)HP[base + (int64_t)tc.J * TILE + col0 + c];
-                    const LT sc = (LT)HS[base + (int64_t)tc.J * TILE + col0 + c];
-                    ptjL[k - 1][c] = SER ? (LT)1 / pc : pc;
-                    sjL[k - 1][c] = sc;
-                    if constexpr (SER) sijL[k - 1][c] = sc / pc;
+                    const AT pc = HP[base + (int64_t)tc.J * TILE + col0 + c];
+                    const AT sc = HS[base + (int64_t)tc.J * TILE + col0 + c];
+                    ptjL[k - 1][c] = SER ? (LT)((AT)1 / pc) : (LT)pc;
+                    sjL[k - 1][c] = (LT)sc;
+                    if constexpr (SER) sijL[k - 1][c] = (LT)(sc / pc);
                 }
             }
         }
     }
     AT cP[4] = {0, 0, 0, 0}, cE[4] = {0, 0, 0, 0};
+    XT cPm[4] = {0, 0, 0, 0}, cEm[4] = {0, 0, 0, 0};   // XF: FP32 column sums over the tile's 256 rows
     bool bad = false;
     __syncthreads();
 
@@ -509,16 +527,17 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
                 const float4 kk = *reinterpret_cast<const float4*>(&kband[w][(4 * s2 + g) * 64 + 4 * q]);
                 k = V4<ST>{{(ST)kk.x, (ST)kk.y, (ST)kk.z, (ST)kk.w}};
             }
-            const MT pti = sPt[r], si = sS[r];
+            const XT pti = sPt[r], si = sS[r];
             AT rp = 0, re = 0;
+            XT rpm = 0, rem = 0;                         // XF: FP32 row sums (4 columns, then 64 per wave)
             V4<ST> npf, npb, nef, neb;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const MT av = (MT)k.v[c];
+                const XT av = (XT)k.v[c];
                 // messages of the previous sweep: stored, or rebuilt level by level
-                MT opf, opb, oef, oeb;
+                XT opf, opb, oef, oeb;
                 if constexpr (STORED) {
-                    opf = (MT)pf.v[c]; opb = (MT)pb.v[c]; oef = (MT)ef.v[c]; oeb = (MT)eb.v[c];
+                    opf = (XT)pf.v[c]; opb = (XT)pb.v[c]; oef = (XT)ef.v[c]; oeb = (XT)eb.v[c];
                 } else if constexpr (SER) {
                     const LT al = (LT)k.v[c], a2l = al * al;
                     LT lpf = 0, lpb = 0, lef = 0, leb = 0;
@@ -540,7 +559,7 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
                             lpf = npf_; lpb = npb_; lef = nef_; leb = neb_;
                         }
                     }
-                    opf = (MT)lpf; opb = (MT)lpb; oef = (MT)lef; oeb = (MT)leb;
+                    opf = (XT)lpf; opb = (XT)lpb; oef = (XT)lef; oeb = (XT)leb;
                 } else {
                     const LT al = (LT)k.v[c], a2l = al * al;
                     LT lpf = 0, lpb = 0, lef = 0, leb = 0;
@@ -556,23 +575,23 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
                             lpf = npf_; lpb = npb_; lef = nef_; leb = neb_;
                         }
                     }
-                    opf = (MT)lpf; opb = (MT)lpb; oef = (MT)lef; oeb = (MT)leb;
+                    opf = (XT)lpf; opb = (XT)lpb; oef = (XT)lef; oeb = (XT)leb;
                 }
-                MT pij_m, eij_m, pji_m, eji_m;
+                XT pij_m, eij_m, pji_m, eji_m;
                 if constexpr (SER) {
-                    const MT e_f = opb * pti, e_b = opf * ptj[c];      // P_ji / P~_i, P_ij / P~_j
-                    const MT tf = av * fma(pti, fma(e_f, e_f, e_f), pti);
-                    const MT tb = av * fma(ptj[c], fma(e_b, e_b, e_b), ptj[c]);
+                    const XT e_f = opb * pti, e_b = opf * ptj[c];      // P_ji / P~_i, P_ij / P~_j
+                    const XT tf = av * fma(pti, fma(e_f, e_f, e_f), pti);
+                    const XT tb = av * fma(ptj[c], fma(e_b, e_b, e_b), ptj[c]);
                     pij_m = -av * tf;
                     pji_m = -av * tb;
                     eij_m = tf * (oeb - si);
                     eji_m = tb * (oef - sj[c]);
                 } else {
-                    const MT a2 = av * av;
-                    const MT qf = pti - opb;        // P~_i - P_ji
-                    const MT qb = ptj[c] - opf;     // P~_j - P_ij
-                    bad |= !(qf > (MT)0) | !(qb > (MT)0);
-                    const MT rf = rcp_fast(qf), rb = rcp_fast(qb);
+                    const XT a2 = av * av;
+                    const XT qf = pti - opb;        // P~_i - P_ji
+                    const XT qb = ptj[c] - opf;     // P~_j - P_ij
+                    bad |= !(qf > (XT)0) | !(qb > (XT)0);
+                    const XT rf = rcp_fast(qf), rb = rcp_fast(qb);
                     pij_m = -a2 * rf;
                     eij_m = -av * (si - oeb) * rf;
                     pji_m = -a2 * rb;
@@ -584,6 +603,9 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
                     npf.v[c] = pij; nef.v[c] = eij; npb.v[c] = pji; neb.v[c] = eji;
                     cP[c] += (AT)pij; cE[c] += (AT)eij;     // received by column node j
                     rp += (AT)pji; re += (AT)eji;            // received by row node i
+                } else if constexpr (XF) {
+                    cPm[c] += pij_m; cEm[c] += eij_m;
+                    rpm += pji_m; rem += eji_m;
                 } else {
                     cP[c] += (AT)pij_m; cE[c] += (AT)eij_m;
                     rp += (AT)pji_m; re += (AT)eji_m;
@@ -595,8 +617,8 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
                 re = sum16(re);
                 if (q == 0) { rP[w][r] = rp; rE[w][r] = re; }
             } else {
-                red[w][0][s2 & 1][l] = rp;
-                red[w][1][s2 & 1][l] = re;
+                red[w][0][s2 & 1][l] = XF ? (RT)rpm : (RT)rp;
+                red[w][1][s2 & 1][l] = XF ? (RT)rem : (RT)re;
                 if (s2 & 1) {
                     // lane l sums quantity l / 32 of row step (l % 32) / 16 and
                     // row group ((l % 32) / 4) % 4 over the column lanes
@@ -604,8 +626,8 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
                     // same sum in every lane: IEEE addition commutes)
                     wave_lds_sync();
                     const int qty = l >> 5, idx = l & 31, stp = idx >> 4, gg = (idx >> 2) & 3, pt = idx & 3;
-                    const AT* src = &red[w][qty][stp][16 * gg + 4 * pt];
-                    AT v = (src[0] + src[1]) + (src[2] + src[3]);
+                    const RT* src = &red[w][qty][stp][16 * gg + 4 * pt];
+                    RT v = (src[0] + src[1]) + (src[2] + src[3]);
                     v = v + dpp<0xB1>(v);
                     v = v + dpp<0x4E>(v);
                     const int row = 32 * b + 4 * ((s2 & 6) + stp) + gg;
@@ -622,14 +644,18 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
         }
         if constexpr (KSRC == KSRC_RECOMPUTE) wave_lds_sync();
     }
+    if constexpr (XF) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) { cP[c] = (AT)cPm[c]; cE[c] = (AT)cEm[c]; }
+    }
 #pragma unroll
     for (int c = 0; c < 4; ++c) { cP[c] = sum_groups(cP[c]); cE[c] = sum_groups(cE[c]); }
     __syncthreads();
     AT* partP = static_cast<AT*>(a.partP);
     AT* partE = static_cast<AT*>(a.partE);
     const size_t rowslot = ((size_t)tc.I * (NB + 1) + tc.J) * TILE + tid;
-    partP[rowslot] = (rP[0][tid] + rP[1][tid]) + (rP[2][tid] + rP[3][tid]);
-    partE[rowslot] = (rE[0][tid] + rE[1][tid]) + (rE[2][tid] + rE[3][tid]);
+    partP[rowslot] = ((AT)rP[0][tid] + (AT)rP[1][tid]) + ((AT)rP[2][tid] + (AT)rP[3][tid]);
+    partE[rowslot] = ((AT)rE[0][tid] + (AT)rE[1][tid]) + ((AT)rE[2][tid] + (AT)rE[3][tid]);
     if (g == 0) {
         const int slot = (tc.I < tc.J) ? tc.I : NB;
         const size_t cb = ((size_t)tc.J * (NB + 1) + slot) * TILE + col0;
@@ -678,19 +704,22 @@ __device__ inline int level_visit_offset(bool fwd, bool within, int k) {
 
 // LDS of one single-direction visit, declared by the kernel so that both
 // directions share it.
-template <class MT, class LT, class AT, int NRL, int RECOMP>
+template <class MT, class LT, class AT, class RT, int NRL, int RECOMP>
 struct DirSmem {
     MT topP[TILE], topS[TILE];            // row source at level 0 (FWD)
     LT lowP[NRL][TILE], lowS[NRL][TILE];  // row source at lower levels
     LT lowSI[NRL][TILE];                  // series: S / P~
-    AT rP[4][TILE], rE[4][TILE];          // BWD row partials per wave strip
-    AT red[4][2][2][64];                  // BWD stateless: two row steps of lane partials
+    RT rP[4][TILE], rE[4][TILE];          // BWD row partials per wave strip (exact in AT)
+    RT red[4][2][2][64];                  // BWD stateless: two row steps of lane partials
     float kband[RECOMP ? 4 : 1][RECOMP ? 32 * 64 : 1];
 };
 
 template <class ST, class MT, class AT, int D, bool SER>
 struct DirTypes {
-    using LT = typename std::conditional<(SER && D <= 3) || std::is_same<ST, double>::value, MT, float>::type;
+    using XT = typename MsgT<ST, MT, AT, SER>::T;
+    static constexpr bool XF = MsgT<ST, MT, AT, SER>::F32;
+    using LT = typename std::conditional<(SER && D <= 3) || std::is_same<ST, double>::value, XT, float>::type;
+    using RT = typename std::conditional<XF, XT, AT>::type;    // row reduction type
     static constexpr int NRL = (D / 2 > 0) ? D / 2 : 1;   // lower row-side levels
     static constexpr int NCL = (D / 2 > 0) ? D / 2 : 1;   // lower column-side levels
 };
@@ -705,6 +734,8 @@ template <class ST, class MT, class AT, int KSRC, int GK, int D, bool SER, bool 
 __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool within, int t, SM& sm) {
     using DT = DirTypes<ST, MT, AT, D, SER>;
     using LT = typename DT::LT;
+    using XT = typename DT::XT;
+    constexpr bool XF = DT::XF;
     constexpr bool STORED = (D == 0);
     constexpr int L = STORED ? 1 : D;
     DevStatus* st = a.st;
@@ -725,7 +756,7 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
 
     // source data per level: row side in LDS (per row), column side in
     // registers (the lane's four columns)
-    MT ctP[4], ctS[4];                           // column source at level 0 (BWD)
+    XT ctP[4], ctS[4];                           // column source at level 0 (BWD)
     LT clP[DT::NCL][4], clS[DT::NCL][4], clSI[SER ? DT::NCL : 1][4];
 #pragma unroll
     for (int k = 0; k < L; ++k) {
@@ -737,13 +768,13 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
             AT p = HP[base + (int64_t)tc.I * TILE + tid], s = HS[base + (int64_t)tc.I * TILE + tid];
             if (!live) { p = (AT)INFINITY; s = 0; }
             if (k == 0) {
-                sm.topP[tid] = SER ? (MT)1 / (MT)p : (MT)p;
-                sm.topS[tid] = (MT)s;
+                sm.topP[tid] = SER ? (XT)((AT)1 / p) : (XT)p;
+                sm.topS[tid] = (XT)s;
             } else {
                 const int m = FWD ? (k >> 1) - 1 : (k >> 1);
-                sm.lowP[m][tid] = SER ? (LT)1 / (LT)p : (LT)p;
+                sm.lowP[m][tid] = SER ? (LT)((AT)1 / p) : (LT)p;
                 sm.lowS[m][tid] = (LT)s;
-                if constexpr (SER) sm.lowSI[m][tid] = (LT)s / (LT)p;
+                if constexpr (SER) sm.lowSI[m][tid] = (LT)(s / p);
             }
         } else {
 #pragma unroll
@@ -752,18 +783,19 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
                 AT s = HS[base + (int64_t)tc.J * TILE + col0 + c];
                 if (!live) { p = (AT)INFINITY; s = 0; }
                 if (k == 0) {
-                    ctP[c] = SER ? (MT)1 / (MT)p : (MT)p;
-                    ctS[c] = (MT)s;
+                    ctP[c] = SER ? (XT)((AT)1 / p) : (XT)p;
+                    ctS[c] = (XT)s;
                 } else {
                     const int m = FWD ? (k >> 1) : (k >> 1) - 1;
-                    clP[m][c] = SER ? (LT)1 / (LT)p : (LT)p;
+                    clP[m][c] = SER ? (LT)((AT)1 / p) : (LT)p;
                     clS[m][c] = (LT)s;
-                    if constexpr (SER) clSI[m][c] = (LT)s / (LT)p;
+                    if constexpr (SER) clSI[m][c] = (LT)(s / p);
                 }
             }
         }
     }
     AT cP[4] = {0, 0, 0, 0}, cE[4] = {0, 0, 0, 0};
+    XT cPm[4] = {0, 0, 0, 0}, cEm[4] = {0, 0, 0, 0};   // XF: FP32 column sums over the tile's 256 rows
     bool bad = false;
     __syncthreads();
 
@@ -797,14 +829,15 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
                 k4 = V4<ST>{{(ST)kk.x, (ST)kk.y, (ST)kk.z, (ST)kk.w}};
             }
             AT rp = 0, re = 0;
+            XT rpm = 0, rem = 0;                         // XF: FP32 row sums (4 columns, then 64 per wave)
             V4<ST> np, ne;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const MT av = (MT)k4.v[c];
+                const XT av = (XT)k4.v[c];
                 // reverse message consumed by the top level
-                MT opr, oer;
+                XT opr, oer;
                 if constexpr (STORED) {
-                    opr = (MT)pr.v[c]; oer = (MT)er.v[c];
+                    opr = (XT)pr.v[c]; oer = (XT)er.v[c];
                 } else {
                     const LT al = (LT)k4.v[c], a2l = al * al;
                     LT lp = 0, le = 0;
@@ -836,21 +869,21 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
                             lp = np_; le = ne_;
                         }
                     }
-                    opr = (MT)lp; oer = (MT)le;
+                    opr = (XT)lp; oer = (XT)le;
                 }
                 // top level: the message into the target, from the source at level 0
-                const MT pt = FWD ? sm.topP[r] : ctP[c];
-                const MT sv = FWD ? sm.topS[r] : ctS[c];
-                MT pm, em;
+                const XT pt = FWD ? sm.topP[r] : ctP[c];
+                const XT sv = FWD ? sm.topS[r] : ctS[c];
+                XT pm, em;
                 if constexpr (SER) {
-                    const MT e = opr * pt;
-                    const MT tf = av * fma(pt, fma(e, e, e), pt);
+                    const XT e = opr * pt;
+                    const XT tf = av * fma(pt, fma(e, e, e), pt);
                     pm = -av * tf;
                     em = tf * (oer - sv);
                 } else {
-                    const MT qv = pt - opr;
-                    bad |= !(qv > (MT)0);
-                    const MT rv = rcp_fast(qv);
+                    const XT qv = pt - opr;
+                    bad |= !(qv > (XT)0);
+                    const XT rv = rcp_fast(qv);
                     pm = -(av * av) * rv;
                     em = -av * (sv - oer) * rv;
                 }
@@ -859,6 +892,9 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
                     np.v[c] = ps; ne.v[c] = es;
                     if constexpr (FWD) { cP[c] += (AT)ps; cE[c] += (AT)es; }
                     else { rp += (AT)ps; re += (AT)es; }
+                } else if constexpr (XF) {
+                    if constexpr (FWD) { cPm[c] += pm; cEm[c] += em; }
+                    else { rpm += pm; rem += em; }
                 } else {
                     if constexpr (FWD) { cP[c] += (AT)pm; cE[c] += (AT)em; }
                     else { rp += (AT)pm; re += (AT)em; }
@@ -872,13 +908,14 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
             } else if constexpr (!FWD) {
                 // row sums over the 16 column lanes through LDS every two row
                 // steps (same scheme as the synchronous stateless sweep)
-                sm.red[w][0][s2 & 1][l] = rp;
-                sm.red[w][1][s2 & 1][l] = re;
+                using RT = typename DT::RT;
+                sm.red[w][0][s2 & 1][l] = XF ? (RT)rpm : (RT)rp;
+                sm.red[w][1][s2 & 1][l] = XF ? (RT)rem : (RT)re;
                 if (s2 & 1) {
                     wave_lds_sync();
                     const int qty = l >> 5, idx = l & 31, stp = idx >> 4, gg = (idx >> 2) & 3, pt = idx & 3;
-                    const AT* src = &sm.red[w][qty][stp][16 * gg + 4 * pt];
-                    AT v = (src[0] + src[1]) + (src[2] + src[3]);
+                    const RT* src = &sm.red[w][qty][stp][16 * gg + 4 * pt];
+                    RT v = (src[0] + src[1]) + (src[2] + src[3]);
                     v = v + dpp<0xB1>(v);
                     v = v + dpp<0x4E>(v);
                     const int row = 32 * b + 4 * ((s2 & 6) + stp) + gg;
@@ -898,6 +935,10 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
     AT* partP = static_cast<AT*>(a.partP);
     AT* partE = static_cast<AT*>(a.partE);
     if constexpr (FWD) {
+        if constexpr (XF) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) { cP[c] = (AT)cPm[c]; cE[c] = (AT)cEm[c]; }
+        }
 #pragma unroll
         for (int c = 0; c < 4; ++c) { cP[c] = sum_groups(cP[c]); cE[c] = sum_groups(cE[c]); }
         if (g == 0) {
@@ -909,8 +950,8 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
     } else {
         __syncthreads();
         const size_t rowslot = ((size_t)tc.I * (NB + 1) + tc.J) * TILE + tid;
-        partP[rowslot] = (sm.rP[0][tid] + sm.rP[1][tid]) + (sm.rP[2][tid] + sm.rP[3][tid]);
-        partE[rowslot] = (sm.rE[0][tid] + sm.rE[1][tid]) + (sm.rE[2][tid] + sm.rE[3][tid]);
+        partP[rowslot] = ((AT)sm.rP[0][tid] + (AT)sm.rP[1][tid]) + ((AT)sm.rP[2][tid] + (AT)sm.rP[3][tid]);
+        partE[rowslot] = ((AT)sm.rE[0][tid] + (AT)sm.rE[1][tid]) + ((AT)sm.rE[2][tid] + (AT)sm.rE[3][tid]);
     }
     if (__any(bad) && l == 0) st->bad = 1;
 }
@@ -919,7 +960,7 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
 template <class ST, class MT, class AT, int KSRC, int GK, int D, bool SER>
 __global__ __launch_bounds__(WG) void k_sweep_dir(SweepArgs a, const uint32_t* __restrict__ list, int t) {
     using DT = DirTypes<ST, MT, AT, D, SER>;
-    __shared__ DirSmem<MT, typename DT::LT, AT, DT::NRL, KSRC == KSRC_RECOMPUTE> sm;
+    __shared__ DirSmem<typename DT::XT, typename DT::LT, AT, typename DT::RT, DT::NRL, KSRC == KSRC_RECOMPUTE> sm;
     if (a.st->done) return;
     const uint32_t e = list[blockIdx.x];
     const int64_t tile = (int64_t)(e & GE_TILE);
