@@ -445,6 +445,12 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
     constexpr int L = D;                      // stateless: levels unrolled in this launch
     const AT* HP = static_cast<const AT*>(a.HP);
     const AT* HS = static_cast<const AT*>(a.HS);
+    // series: 1/P~ and S/P~ from the rings when the finalize formed them
+    // (the same IEEE quotients as here)
+    const AT* HI = static_cast<const AT*>(a.HI);
+    const AT* HM = static_cast<const AT*>(a.HM);
+    auto inv_at = [&](int64_t o) -> AT { return HI ? HI[o] : (AT)1 / HP[o]; };
+    auto mean_at = [&](int64_t o) -> AT { return HM ? HM[o] : HS[o] / HP[o]; };
     const ST* Kp = static_cast<const ST*>(a.Kp);
     ST* Pf = static_cast<ST*>(a.Pf);
     ST* Pb = static_cast<ST*>(a.Pb);
@@ -465,16 +471,16 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
 
     const int64_t top = (int64_t)slot_top * a.NPAD;
     {
-        const AT p = HP[top + (int64_t)tc.I * TILE + tid];
-        sPt[tid] = SER ? (XT)((AT)1 / p) : (XT)p;
-        sS[tid] = (XT)HS[top + (int64_t)tc.I * TILE + tid];
+        const int64_t o = top + (int64_t)tc.I * TILE + tid;
+        sPt[tid] = SER ? (XT)inv_at(o) : (XT)HP[o];
+        sS[tid] = (XT)HS[o];
     }
     XT ptj[4], sj[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        const AT p = HP[top + (int64_t)tc.J * TILE + col0 + c];
-        ptj[c] = SER ? (XT)((AT)1 / p) : (XT)p;
-        sj[c] = (XT)HS[top + (int64_t)tc.J * TILE + col0 + c];
+        const int64_t o = top + (int64_t)tc.J * TILE + col0 + c;
+        ptj[c] = SER ? (XT)inv_at(o) : (XT)HP[o];
+        sj[c] = (XT)HS[o];
     }
     LT ptjL[DL][4], sjL[DL][4], sijL[SER ? DL : 1][4];
     if constexpr (!STORED) {
@@ -482,18 +488,16 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
         for (int k = 1; k < D; ++k) {
             if (k < L) {
                 const int64_t base = (int64_t)((slot_top - k + a.R) % a.R) * a.NPAD;
-                const AT pr = HP[base + (int64_t)tc.I * TILE + tid];
-                const AT sr = HS[base + (int64_t)tc.I * TILE + tid];
-                sPtL[k - 1][tid] = SER ? (LT)((AT)1 / pr) : (LT)pr;
-                sSL[k - 1][tid] = (LT)sr;
-                if constexpr (SER) sSIL[k - 1][tid] = (LT)(sr / pr);
+                const int64_t o = base + (int64_t)tc.I * TILE + tid;
+                sPtL[k - 1][tid] = SER ? (LT)inv_at(o) : (LT)HP[o];
+                sSL[k - 1][tid] = (LT)HS[o];
+                if constexpr (SER) sSIL[k - 1][tid] = (LT)mean_at(o);
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    const AT pc = HP[base + (int64_t)tc.J * TILE + col0 + c];
-                    const AT sc = HS[base + (int64_t)tc.J * TILE + col0 + c];
-                    ptjL[k - 1][c] = SER ? (LT)((AT)1 / pc) : (LT)pc;
-                    sjL[k - 1][c] = (LT)sc;
-                    if constexpr (SER) sijL[k - 1][c] = (LT)(sc / pc);
+                    const int64_t o = base + (int64_t)tc.J * TILE + col0 + c;
+                    ptjL[k - 1][c] = SER ? (LT)inv_at(o) : (LT)HP[o];
+                    sjL[k - 1][c] = (LT)HS[o];
+                    if constexpr (SER) sijL[k - 1][c] = (LT)mean_at(o);
                 }
             }
         }
@@ -747,6 +751,8 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
     const int col0 = w * 64 + q * 4;
     const AT* HP = static_cast<const AT*>(a.HP);
     const AT* HS = static_cast<const AT*>(a.HS);
+    const AT* HI = static_cast<const AT*>(a.HI);
+    const AT* HM = static_cast<const AT*>(a.HM);
     const ST* Kp = static_cast<const ST*>(a.Kp);
     auto slot_of = [&](int k) -> int64_t {
         if constexpr (STORED) return 0;
@@ -764,32 +770,45 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
         const int64_t base = slot_of(k);
         // levels computed before sweep 0: P~ = inf, S = 0 give exactly zero messages
         const bool live = STORED || t + level_visit_offset(FWD, within, k) >= 0;
-        if (row_side) {
-            AT p = HP[base + (int64_t)tc.I * TILE + tid], s = HS[base + (int64_t)tc.I * TILE + tid];
+        // per node: P~ (or, series, 1/P~), S and (series) S/P~; the rings'
+        // 1/P~ and S/P~ when the finalize formed them (the same quotients)
+        auto node = [&](int64_t o, AT& pv, AT& sv, AT& mv) {
+            AT p = HP[o], s = HS[o];
             if (!live) { p = (AT)INFINITY; s = 0; }
+            sv = s;
+            if constexpr (SER) {
+                pv = (HI && live) ? HI[o] : (AT)1 / p;
+                mv = (HM && live) ? HM[o] : s / p;
+            } else {
+                pv = p;
+                mv = 0;
+            }
+        };
+        if (row_side) {
+            AT pv, sv, mv;
+            node(base + (int64_t)tc.I * TILE + tid, pv, sv, mv);
             if (k == 0) {
-                sm.topP[tid] = SER ? (XT)((AT)1 / p) : (XT)p;
-                sm.topS[tid] = (XT)s;
+                sm.topP[tid] = (XT)pv;
+                sm.topS[tid] = (XT)sv;
             } else {
                 const int m = FWD ? (k >> 1) - 1 : (k >> 1);
-                sm.lowP[m][tid] = SER ? (LT)((AT)1 / p) : (LT)p;
-                sm.lowS[m][tid] = (LT)s;
-                if constexpr (SER) sm.lowSI[m][tid] = (LT)(s / p);
+                sm.lowP[m][tid] = (LT)pv;
+                sm.lowS[m][tid] = (LT)sv;
+                if constexpr (SER) sm.lowSI[m][tid] = (LT)mv;
             }
         } else {
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                AT p = HP[base + (int64_t)tc.J * TILE + col0 + c];
-                AT s = HS[base + (int64_t)tc.J * TILE + col0 + c];
-                if (!live) { p = (AT)INFINITY; s = 0; }
+                AT pv, sv, mv;
+                node(base + (int64_t)tc.J * TILE + col0 + c, pv, sv, mv);
                 if (k == 0) {
-                    ctP[c] = SER ? (XT)((AT)1 / p) : (XT)p;
-                    ctS[c] = (XT)s;
+                    ctP[c] = (XT)pv;
+                    ctS[c] = (XT)sv;
                 } else {
                     const int m = FWD ? (k >> 1) : (k >> 1) - 1;
-                    clP[m][c] = SER ? (LT)((AT)1 / p) : (LT)p;
-                    clS[m][c] = (LT)s;
-                    if constexpr (SER) clSI[m][c] = (LT)(s / p);
+                    clP[m][c] = (LT)pv;
+                    clS[m][c] = (LT)sv;
+                    if constexpr (SER) clSI[m][c] = (LT)mv;
                 }
             }
         }

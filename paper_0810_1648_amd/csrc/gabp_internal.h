@@ -116,6 +116,7 @@ struct SweepArgs {
     const void* Kp;               // K' plane (KSRC_PLANE)
     void *Pf, *Pb, *Ef, *Eb;      // pair planes: P_ij, P_ji, E_ij, E_ji (i < j), stored state
     const void *HP, *HS;          // aggregate rings
+    const void *HI, *HM;          // series: rings of 1/P~ and S/P~ (null: formed in the tile)
     int64_t NPAD;
     int R, slot_top, levels;      // ring depth, top slot, stateless levels in use
     void *partP, *partE;          // [NB][NB+1][TILE] partial sums
@@ -164,10 +165,16 @@ hipError_t launch_sweep_mixed(int ksrc, int gram, int levels, bool first, bool s
                               hipStream_t s);
 hipError_t launch_sweep_f64(int ksrc, int gram, int levels, bool first, bool ser, const SweepArgs& a,
                             hipStream_t s);
+// Inv / Mean (optional, with Pt / S): the new 1/P~ and S/P~ of the series
+// sweeps, formed once per node here instead of in every tile.
 hipError_t launch_finalize(int prec, int64_t N, int NB, const void* partP, const void* partE,
                            const double* Adiag, const float* y, void* Pt, void* S,
                            double* alpha, double* blk_delta, double* blk_amax,
-                           DevStatus* st, hipStream_t s, double boxC = 0.0);
+                           DevStatus* st, hipStream_t s, double boxC = 0.0, void* Inv = nullptr,
+                           void* Mean = nullptr);
+// Inv / Mean of every ring slot from Pt / S (R slots of NPAD entries).
+hipError_t launch_ring_recip(int prec, int64_t NPAD, int R, const void* Pt, const void* S, void* Inv, void* Mean,
+                             hipStream_t s);
 // Grouped schedule: one group visit.  `within` lists the stored-record tiles
 // inside the group (both directions), `dir` the single-direction entries
 // (tile index | GE_BWD | GE_WITHIN bits, see gabp_device.h); t = sweep index.
@@ -223,7 +230,7 @@ hipError_t launch_sp_sweep(int prec, int64_t E, int64_t N, const int32_t* ei, co
 hipError_t launch_finalize_range(int prec, int64_t b0, int64_t nb, int64_t N, int NB, const void* partP,
                                  const void* partE, const double* Adiag, const float* y, void* Pt, void* S,
                                  double* alpha, double* blk_delta, double* blk_amax, DevStatus* st,
-                                 hipStream_t s, double boxC = 0.0);
+                                 hipStream_t s, double boxC = 0.0, void* Inv = nullptr, void* Mean = nullptr);
 hipError_t launch_status(int nblk, const double* blk_delta, const double* blk_amax,
                          DevStatus* st, double* trace, StopRule rule, hipStream_t s);
 // A-priori contraction bound: one[0] = -m* (minus the aggregate lower

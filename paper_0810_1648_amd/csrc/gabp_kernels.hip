@@ -487,7 +487,8 @@ __device__ inline void finalize_block(int64_t blk, int64_t N, int NB, const AT* 
                                       const float* __restrict__ y, AT* __restrict__ Pt,
                                       AT* __restrict__ S, double* __restrict__ alpha,
                                       double* __restrict__ blk_delta,
-                                      double* __restrict__ blk_amax, DevStatus* st, double boxC) {
+                                      double* __restrict__ blk_amax, DevStatus* st, double boxC,
+                                      AT* __restrict__ Inv, AT* __restrict__ Mean) {
     __shared__ double sh4[4];
     const int64_t i = blk * blockDim.x + threadIdx.x;
     double d = 0.0, am = 0.0;
@@ -508,6 +509,7 @@ __device__ inline void finalize_block(int64_t blk, int64_t N, int NB, const AT* 
         }
         Pt[i] = p;
         S[i] = e;
+        if (Inv) { Inv[i] = (AT)1 / p; Mean[i] = e / p; }
         d = fabs(an - alpha[i]);
         am = fabs(an);
         alpha[i] = an;
@@ -525,9 +527,22 @@ __global__ __launch_bounds__(WG) void k_finalize(int64_t N, int NB, const AT* __
                                                 const float* __restrict__ y, AT* __restrict__ Pt,
                                                 AT* __restrict__ S, double* __restrict__ alpha,
                                                 double* __restrict__ blk_delta,
-                                                double* __restrict__ blk_amax, DevStatus* st, double boxC) {
+                                                double* __restrict__ blk_amax, DevStatus* st, double boxC,
+                                                AT* __restrict__ Inv, AT* __restrict__ Mean) {
     if (st->done) return;
-    finalize_block<AT>(blockIdx.x, N, NB, partP, partE, Adiag, y, Pt, S, alpha, blk_delta, blk_amax, st, boxC);
+    finalize_block<AT>(blockIdx.x, N, NB, partP, partE, Adiag, y, Pt, S, alpha, blk_delta, blk_amax, st, boxC,
+                       Inv, Mean);
+}
+
+// 1/P~ and S/P~ of every ring slot (series sweeps): P~ = +inf, S = 0 give 0
+// and 0, the values a tile would form from them.
+template <class AT>
+__global__ void k_ring_recip(int64_t n, const AT* __restrict__ Pt, const AT* __restrict__ S,
+                             AT* __restrict__ Inv, AT* __restrict__ Mean) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Inv[i] = (AT)1 / Pt[i];
+    Mean[i] = S[i] / Pt[i];
 }
 
 // Grouped schedule: the node blocks [b0, b0 + gridDim.x) of one group.
@@ -538,10 +553,11 @@ __global__ __launch_bounds__(WG) void k_finalize_range(int64_t b0, int64_t N, in
                                                       const float* __restrict__ y, AT* __restrict__ Pt,
                                                       AT* __restrict__ S, double* __restrict__ alpha,
                                                       double* __restrict__ blk_delta,
-                                                      double* __restrict__ blk_amax, DevStatus* st, double boxC) {
+                                                      double* __restrict__ blk_amax, DevStatus* st, double boxC,
+                                                      AT* __restrict__ Inv, AT* __restrict__ Mean) {
     if (st->done) return;
     finalize_block<AT>(b0 + blockIdx.x, N, NB, partP, partE, Adiag, y, Pt, S, alpha, blk_delta, blk_amax, st,
-                       boxC);
+                       boxC, Inv, Mean);
 }
 
 // Served form: items are (request, block of 256 nodes).
@@ -557,7 +573,7 @@ __global__ __launch_bounds__(WG) void k_finalize_batched(const ReqDesc* __restri
                            static_cast<const AT*>(rd.sw.partE), rd.Adiag, rd.y,
                            static_cast<AT*>(const_cast<void*>(rd.sw.HP)) + wslot,
                            static_cast<AT*>(const_cast<void*>(rd.sw.HS)) + wslot, rd.alpha, rd.blk_delta,
-                           rd.blk_amax, rd.sw.st, 0.0);
+                           rd.blk_amax, rd.sw.st, 0.0, nullptr, nullptr);
         __syncthreads();
     }
 }
@@ -839,33 +855,48 @@ hipError_t launch_served_step(int prec, int levels, bool ser, const ReqDesc* req
 
 hipError_t launch_finalize(int prec, int64_t N, int NB, const void* partP, const void* partE,
                            const double* Adiag, const float* y, void* Pt, void* S, double* alpha,
-                           double* blk_delta, double* blk_amax, DevStatus* st, hipStream_t s, double boxC) {
+                           double* blk_delta, double* blk_amax, DevStatus* st, hipStream_t s, double boxC,
+                           void* Inv, void* Mean) {
+    if ((Inv == nullptr) != (Mean == nullptr)) return hipErrorInvalidValue;
     const dim3 g(grid1(N)), b(WG);
     if (prec == PREC_FP32)
         hipLaunchKernelGGL(k_finalize<float>, g, b, 0, s, N, NB, (const float*)partP,
                            (const float*)partE, Adiag, y, (float*)Pt, (float*)S, alpha, blk_delta,
-                           blk_amax, st, boxC);
+                           blk_amax, st, boxC, (float*)Inv, (float*)Mean);
     else
         hipLaunchKernelGGL(k_finalize<double>, g, b, 0, s, N, NB, (const double*)partP,
                            (const double*)partE, Adiag, y, (double*)Pt, (double*)S, alpha,
-                           blk_delta, blk_amax, st, boxC);
+                           blk_delta, blk_amax, st, boxC, (double*)Inv, (double*)Mean);
+    return hipGetLastError();
+}
+
+hipError_t launch_ring_recip(int prec, int64_t NPAD, int R, const void* Pt, const void* S, void* Inv, void* Mean,
+                             hipStream_t s) {
+    const int64_t n = NPAD * (int64_t)R;
+    if (prec == PREC_FP32)
+        hipLaunchKernelGGL(k_ring_recip<float>, dim3(grid1(n)), dim3(WG), 0, s, n, (const float*)Pt,
+                           (const float*)S, (float*)Inv, (float*)Mean);
+    else
+        hipLaunchKernelGGL(k_ring_recip<double>, dim3(grid1(n)), dim3(WG), 0, s, n, (const double*)Pt,
+                           (const double*)S, (double*)Inv, (double*)Mean);
     return hipGetLastError();
 }
 
 hipError_t launch_finalize_range(int prec, int64_t b0, int64_t nb, int64_t N, int NB, const void* partP,
                                  const void* partE, const double* Adiag, const float* y, void* Pt, void* S,
                                  double* alpha, double* blk_delta, double* blk_amax, DevStatus* st,
-                                 hipStream_t s, double boxC) {
+                                 hipStream_t s, double boxC, void* Inv, void* Mean) {
     if (nb <= 0) return hipSuccess;
+    if ((Inv == nullptr) != (Mean == nullptr)) return hipErrorInvalidValue;
     const dim3 g((unsigned)nb), b(WG);
     if (prec == PREC_FP32)
         hipLaunchKernelGGL(k_finalize_range<float>, g, b, 0, s, b0, N, NB, (const float*)partP,
                            (const float*)partE, Adiag, y, (float*)Pt, (float*)S, alpha, blk_delta, blk_amax, st,
-                           boxC);
+                           boxC, (float*)Inv, (float*)Mean);
     else
         hipLaunchKernelGGL(k_finalize_range<double>, g, b, 0, s, b0, N, NB, (const double*)partP,
                            (const double*)partE, Adiag, y, (double*)Pt, (double*)S, alpha, blk_delta, blk_amax,
-                           st, boxC);
+                           st, boxC, (double*)Inv, (double*)Mean);
     return hipGetLastError();
 }
 

@@ -102,7 +102,7 @@ struct gabp_svm {
     // device memory owned by the handle
     DevBuf tiles, Kp, Pf, Pb, Ef, Eb, partP, partE, Xin, yd, mean, xs32, xhi, xlo, xlo2, x64, nrm, kdiag, rowmax, rsum,
         Adiag, Pt, S, alpha_d, blk1, blk2, one, status_d, trace_d, flag, tmp, Kin, q_rows, q_cols,
-        q_out, glist;
+        q_out, glist, HI, HM;
     // sparsified kernel: tile counts and offsets, keys, K' per edge, edge
     // ends, degrees and offsets of the i-end and j-end lists, permutation
     DevBuf sp_cnt, sp_toff, sp_keys, sp_keys2, sp_kv, sp_kv2, sp_ei, sp_ej, sp_degi, sp_degj, sp_offi,
@@ -110,12 +110,12 @@ struct gabp_svm {
     bool sparse = false;
     int64_t n_edges = 0;
 
-    DevBuf* all[59] = {&tiles, &Kp, &Pf, &Pb, &Ef, &Eb, &partP, &partE, &Xin, &yd, &mean,
+    DevBuf* all[61] = {&tiles, &Kp, &Pf, &Pb, &Ef, &Eb, &partP, &partE, &Xin, &yd, &mean,
                        &xs32, &xhi, &xlo, &xlo2, &x64, &nrm, &kdiag, &rowmax, &rsum, &Adiag, &Pt, &S, &alpha_d,
                        &blk1, &blk2, &one, &status_d, &trace_d, &flag, &tmp, &Kin, &q_rows,
                        &q_cols, &q_out, &glist, &sp_cnt, &sp_toff, &sp_keys, &sp_keys2, &sp_kv, &sp_kv2,
                        &sp_ei, &sp_ej, &sp_degi, &sp_degj, &sp_offi, &sp_offj, &sp_ids, &sp_perm, &sp_tmp,
-                       &sp_order, &sp_Xp, &sp_cent, &sp_rad, &sp_keep, &sp_tsel, &sp_nsel, nullptr};
+                       &sp_order, &sp_Xp, &sp_cent, &sp_rad, &sp_keep, &sp_tsel, &sp_nsel, &HI, &HM, nullptr};
     size_t held() const {
         size_t b = 0;
         for (int k = 0; all[k]; ++k) b += all[k]->bytes;
@@ -413,6 +413,19 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     // ---- sweeps
     const size_t agg_bytes = (prec == PREC_FP32) ? 4 : 8;
     const int Rr = cur_stored ? 1 : R;
+    // series sweeps: per-node 1/P~ and S/P~ rings, formed by the finalize
+    // once per node (without them every tile forms the same quotients)
+    void* hinv = nullptr;
+    void* hmean = nullptr;
+    if (ser && h->HI.ensure((size_t)Rr * NPAD * agg_bytes) == hipSuccess &&
+        h->HM.ensure((size_t)Rr * NPAD * agg_bytes) == hipSuccess) {
+        hinv = h->HI.p;
+        hmean = h->HM.p;
+        HIPCHK(h, launch_ring_recip(prec, NPAD, Rr, h->Pt.p, h->S.p, hinv, hmean, s));
+    } else {
+        (void)hipGetLastError();
+        h->HI.release(); h->HM.release();
+    }
     SweepArgs sa{};
     sa.tiles = h->tiles.as<uint32_t>();
     sa.ntiles = nt;
@@ -420,6 +433,7 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     sa.Kp = h->Kp.p;
     sa.Pf = h->Pf.p; sa.Pb = h->Pb.p; sa.Ef = h->Ef.p; sa.Eb = h->Eb.p;
     sa.HP = h->Pt.p; sa.HS = h->S.p;
+    sa.HI = hinv; sa.HM = hmean;
     sa.NPAD = NPAD;
     sa.R = Rr;
     sa.partP = h->partP.p; sa.partE = h->partE.p;
@@ -493,13 +507,15 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
         sa.levels = cur_stored ? 0 : depth;
         char* wP = static_cast<char*>(h->Pt.p) + (size_t)((t + 1) % Rr) * NPAD * agg_bytes;
         char* wS = static_cast<char*>(h->S.p) + (size_t)((t + 1) % Rr) * NPAD * agg_bytes;
+        char* wI = hinv ? static_cast<char*>(hinv) + (size_t)((t + 1) % Rr) * NPAD * agg_bytes : nullptr;
+        char* wM = hmean ? static_cast<char*>(hmean) + (size_t)((t + 1) % Rr) * NPAD * agg_bytes : nullptr;
         if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot], s));
         if (!grouped) {
             HIPCHK(h, launch_sweep(prec, ksrc, gram, sa.levels, t == 0, ser, sa, s));
             if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot + 1], s));
             HIPCHK(h, launch_finalize(prec, N, NB, h->partP.p, h->partE.p, h->Adiag.as<double>(),
                                       h->yd.as<float>(), wP, wS, h->alpha_d.as<double>(),
-                                      h->blk1.as<double>(), h->blk2.as<double>(), st, s, boxC));
+                                      h->blk1.as<double>(), h->blk2.as<double>(), st, s, boxC, wI, wM));
         } else {
             // one visit per group: its messages, then its aggregates (the
             // timed span covers the visits and their group finalizes)
@@ -512,7 +528,7 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
                 HIPCHK(h, launch_finalize_range(prec, b0, b1 - b0, N, NB, h->partP.p, h->partE.p,
                                                 h->Adiag.as<double>(), h->yd.as<float>(), wP, wS,
                                                 h->alpha_d.as<double>(), h->blk1.as<double>(),
-                                                h->blk2.as<double>(), st, s, boxC));
+                                                h->blk2.as<double>(), st, s, boxC, wI, wM));
             }
             if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot + 1], s));
         }
