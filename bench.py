@@ -68,24 +68,24 @@ def stateless_slots_per_pair(levels, series, precision="mixed"):
     `levels` unrolled levels (both directions of the pair), counting a
     multiply-add as one slot (contracted, as the compiler emits it) and a
     transcendental as four.
-    Series reciprocals (every precision; MIXED computes these messages in
-    FP32 from FP32 K', so no conversion): a^2 (1); the deepest level starts
-    from zero messages: the two P products (2; its E products fold into the
-    next level's S - E_rev by a multiply-add); each middle level forms, per
-    direction, e = P_rev / P~ (1), the one-term reciprocal (1), the scale by
-    a (1), the new P (1) and the new E (1, its product folding into the next
-    level): 10; the top level forms, per direction, e (1), the two-term
-    series (2), the scale (1), S - E_rev (1) and the accumulations of P and E
-    (2, each fused with its product): 14.  With one level the top level
-    alone runs from zero reverse messages: 6.
+    Series reciprocals (`series` = number of terms at the top level; MIXED
+    computes these messages in FP32 from FP32 K', so no conversion): a^2
+    (1); the lower levels carry G = P / (-a^2) and F = E / a: the deepest
+    level is G = 1/P~, F = -S/P~ of its source (free), each middle level
+    forms, per direction, a^2 u^2 (1), G = u - a^2 u^2 G_rev (1),
+    a F_rev - S (1) and F (1): 8; the top level forms, per direction,
+    e = -a^2 G_rev u (2), the series (1 or 2), the accumulation of P (1,
+    fused), a G (1), a F_rev - S (1) and the accumulation of E (1, fused):
+    14 or 16.  With one level the top level runs from zero reverse
+    messages: 7.
     Exact reciprocals: per direction and level the cavity precision (1), the
     reciprocal (FP32: 4; FP64: 4 + two Newton steps of 2 FMAs = 8) and the
     messages (4; 3 at the top, where the accumulations fuse); MIXED adds the
     conversion of K' to FP64 (1)."""
     if series:
         if levels <= 1:
-            return 2 * 3
-        return 1 + 2 + 10 * (levels - 2) + 14
+            return 7
+        return 1 + 8 * (levels - 2) + 2 * (6 + int(series))
     cvt = 1 if precision == "mixed" else 0
     r_top = 4 if precision == "fp32" else 8
     r_low = 8 if precision == "fp64" else 4
@@ -368,14 +368,14 @@ def main():
     stateless = plan["edge_state"] == gabp.EDGE["stateless"]
     traffic = counter_traffic(a.traffic_json, f"{wl.name}:{N}:{a.precision}:{plan['kstore']}:{plan['edge_state']}")
     if stateless:
-        slots = stateless_slots_per_pair(plan["stateless_depth"], bool(plan["series_reciprocal"]), a.precision)
+        slots = stateless_slots_per_pair(plan["stateless_depth"], int(plan["series_reciprocal"]), a.precision)
         achieved = slots * pairs / (avg_ms * 1e-3) / 1e9 if klaunch else None
         roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_GSLOT, "unit": "Gslot/s",
                 "frac": (achieved / VALU_PEAK_GSLOT) if achieved else None, "traffic": traffic,
                 "traffic_unit": "GB/launch",
                 "kernel": "k_sweep (stateless)", "avg_launch_ms": avg_ms, "launches": klaunch,
                 "alg_slots_per_pair": slots, "stateless_depth": plan["stateless_depth"],
-                "series_reciprocal": bool(plan["series_reciprocal"]),
+                "series_reciprocal": int(plan["series_reciprocal"]),
                 "stateless_rho": plan["stateless_rho"],
                 "hbm_alg_bytes_per_launch": plan["alg_bytes_per_sweep"],
                 "hbm_frac": plan["alg_bytes_per_sweep"] / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if klaunch else None}

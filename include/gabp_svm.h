@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define GABP_ABI_VERSION 4
+#define GABP_ABI_VERSION 5
 
 /* Opaque solver handle; owns every device buffer it allocates. */
 typedef struct gabp_svm gabp_svm;
@@ -206,8 +206,10 @@ typedef struct gabp_plan {
                                   sweep (computed before sweep 1); the truncation
                                   of the message recursion is bounded by about
                                   rho^stateless_depth */
-    int32_t series_reciprocal; /* 1: stateless reciprocals of the cavity
-                                  precisions by the series around 1/P~ */
+    int32_t series_reciprocal; /* stateless reciprocals of the cavity
+                                  precisions: 0 exact; 1 / 2 by the series
+                                  around 1/P~ with a one- / two-term top
+                                  level (one term at the lower levels) */
     int32_t sched_groups;      /* groups of the GROUPED schedule; 0 = SYNC */
     int64_t n_edges;           /* RBF_SPARSE: kept pairs (graph edges); else 0 */
 } gabp_plan;

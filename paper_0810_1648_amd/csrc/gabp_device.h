@@ -60,6 +60,14 @@ __device__ inline void st4nt(double* p, const V4<double>& v) {
     __builtin_nontemporal_store(b, reinterpret_cast<f64x2v*>(p + 2));
 }
 
+// Address of a lane's element from a wave-uniform base (scalar registers)
+// and a 32-bit lane offset: loads and stores then take the scalar-base form
+// and the per-step address arithmetic stays off the vector ALU.
+template <class T> __device__ inline T* lane_ptr(T* base, uint32_t elems) {
+    using C = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return reinterpret_cast<T*>(reinterpret_cast<C*>(base) + elems * (uint32_t)sizeof(T));
+}
+
 template <int CTRL> __device__ inline int dpp_i(int v) {
     // every source lane of these patterns exists, so no fill value is needed
     return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
@@ -397,7 +405,7 @@ __device__ inline void wave_lds_sync() {
 // per-node 1/P~ and S/P~ are rounded once from FP64, and FP32 sums of a few
 // messages are added into the FP64 aggregates.  Every other path computes
 // its messages in MT.
-template <class ST, class MT, class AT, bool SER>
+template <class ST, class MT, class AT, int SER>
 struct MsgT {
     static constexpr bool F32 = SER && std::is_same<ST, float>::value && std::is_same<AT, double>::value;
     using T = typename std::conditional<F32, float, MT>::type;
@@ -414,15 +422,18 @@ struct MsgT {
 //      slot from before sweep 0 holds P~ = inf, S = 0 and yields exactly zero
 //      messages), lower levels in LT (see below);
 //   FIRST: the stored planes are all zero (sweep 1) and are not read.
-// Work of one tile.  SER (stateless only): the reciprocals of the cavity
-// precisions Q = P~ (1 - e), e = P_reverse / P~, are formed from the
-// per-node 1/P~ by the series 1/Q = (1 + e + e^2 + ...) / P~ (one term at
-// the lower levels, two at the top).  |e| <= rho^2 holds for every message by
-// the a-priori contraction bound (no run-time check is needed); the host
-// enables the series only when the neglected terms are below the
-// arithmetic's precision.  The deepest level starts from zero
-// messages and costs four multiplications.
-template <class ST, class MT, class AT, int KSRC, int GK, int D, bool FIRST, bool SER>
+// Work of one tile.  SER (stateless only; 0 = exact reciprocals): the
+// reciprocals of the cavity precisions Q = P~ (1 - e), e = P_reverse / P~,
+// are formed from the per-node u = 1/P~ by the series
+// 1/Q = (1 + e + e^2 + ...) u, one term at the lower levels and SER terms at
+// the top.  |e| <= rho^2 holds for every message by the a-priori contraction
+// bound (no run-time check is needed); the host picks the series only when
+// the neglected terms are below the arithmetic's precision.  The lower
+// levels carry G = P / (-a^2) and F = E / a, which the one-term series turns
+// into G_ij = u_i - a^2 u_i^2 G_ji and F_ij = G_ij (a F_ji - S_i): the
+// deepest level (reverse messages zero) is G = u, F = -S/P~ of its source
+// and costs nothing, a middle level costs four operations per direction.
+template <class ST, class MT, class AT, int KSRC, int GK, int D, bool FIRST, int SER>
 __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top) {
     DevStatus* st = a.st;
     // lower levels: FP32 storage precision; with the series and up to three
@@ -459,7 +470,7 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
 
     // row-node data: top level (P~ or, with SER, 1/P~) and lower levels
     __shared__ XT sPt[TILE], sS[TILE];
-    __shared__ LT sPtL[NL][NT], sSL[NL][NT], sSIL[SER ? NL : 1][SER ? NT : 1];
+    __shared__ LT sPtL[NL][NT], sSL[NL][NT], sSIL[SER ? NL : 1][SER ? NT : 1], sUQL[SER ? NL : 1][SER ? NT : 1];
     // row partials per wave strip (XF: FP32 sums of 64 messages; exact in AT)
     using RT = typename std::conditional<XF, XT, AT>::type;
     __shared__ RT rP[4][TILE], rE[4][TILE];
@@ -482,22 +493,36 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
         ptj[c] = SER ? (XT)inv_at(o) : (XT)HP[o];
         sj[c] = (XT)HS[o];
     }
-    LT ptjL[DL][4], sjL[DL][4], sijL[SER ? DL : 1][4];
+    // lower levels per node: P~ (exact) or u = 1/P~ (series), S, and for
+    // the series S/P~ (deepest level) and u^2 (middle levels)
+    LT ptjL[DL][4], sjL[DL][4], sijL[SER ? DL : 1][4], cuqL[SER ? DL : 1][4];
     if constexpr (!STORED) {
 #pragma unroll
         for (int k = 1; k < D; ++k) {
             if (k < L) {
                 const int64_t base = (int64_t)((slot_top - k + a.R) % a.R) * a.NPAD;
                 const int64_t o = base + (int64_t)tc.I * TILE + tid;
-                sPtL[k - 1][tid] = SER ? (LT)inv_at(o) : (LT)HP[o];
+                if constexpr (SER) {
+                    const AT u = inv_at(o);
+                    sPtL[k - 1][tid] = (LT)u;
+                    sUQL[k - 1][tid] = (LT)(u * u);
+                    sSIL[k - 1][tid] = (LT)mean_at(o);
+                } else {
+                    sPtL[k - 1][tid] = (LT)HP[o];
+                }
                 sSL[k - 1][tid] = (LT)HS[o];
-                if constexpr (SER) sSIL[k - 1][tid] = (LT)mean_at(o);
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const int64_t o = base + (int64_t)tc.J * TILE + col0 + c;
-                    ptjL[k - 1][c] = SER ? (LT)inv_at(o) : (LT)HP[o];
+                    if constexpr (SER) {
+                        const AT u = inv_at(o);
+                        ptjL[k - 1][c] = (LT)u;
+                        cuqL[k - 1][c] = (LT)(u * u);
+                        sijL[k - 1][c] = (LT)mean_at(o);
+                    } else {
+                        ptjL[k - 1][c] = (LT)HP[o];
+                    }
                     sjL[k - 1][c] = (LT)HS[o];
-                    if constexpr (SER) sijL[k - 1][c] = (LT)mean_at(o);
                 }
             }
         }
@@ -507,10 +532,16 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
     bool bad = false;
     __syncthreads();
 
-    size_t off = tbase + (size_t)g * TILE + col0;
+    // row offset (wave-uniform: tile base plus 4 TILE per row step) and the
+    // lane's offset inside a row group
+    size_t off = tbase;
+    const uint32_t lo = (uint32_t)(g * TILE + col0);
     V4<ST> k{}, pf{}, pb{}, ef{}, eb{};
-    if constexpr (KSRC == KSRC_PLANE) k = ld4nt(Kp + off);
-    if constexpr (STORED && !FIRST) { pf = ld4nt(Pf + off); pb = ld4nt(Pb + off); ef = ld4nt(Ef + off); eb = ld4nt(Eb + off); }
+    if constexpr (KSRC == KSRC_PLANE) k = ld4nt(lane_ptr(Kp + off, lo));
+    if constexpr (STORED && !FIRST) {
+        pf = ld4nt(lane_ptr(Pf + off, lo)); pb = ld4nt(lane_ptr(Pb + off, lo));
+        ef = ld4nt(lane_ptr(Ef + off, lo)); eb = ld4nt(lane_ptr(Eb + off, lo));
+    }
 
     for (int b = 0; b < TILE / 32; ++b) {
         if constexpr (KSRC == KSRC_RECOMPUTE) {
@@ -525,8 +556,11 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
             const bool more = (b * 8 + s2 + 1) < TILE / 4;
             const size_t off2 = more ? off + 4 * TILE : off;
             V4<ST> k2, pf2, pb2, ef2, eb2;
-            if constexpr (KSRC == KSRC_PLANE) k2 = ld4nt(Kp + off2);
-            if constexpr (STORED && !FIRST) { pf2 = ld4nt(Pf + off2); pb2 = ld4nt(Pb + off2); ef2 = ld4nt(Ef + off2); eb2 = ld4nt(Eb + off2); }
+            if constexpr (KSRC == KSRC_PLANE) k2 = ld4nt(lane_ptr(Kp + off2, lo));
+            if constexpr (STORED && !FIRST) {
+                pf2 = ld4nt(lane_ptr(Pf + off2, lo)); pb2 = ld4nt(lane_ptr(Pb + off2, lo));
+                ef2 = ld4nt(lane_ptr(Ef + off2, lo)); eb2 = ld4nt(lane_ptr(Eb + off2, lo));
+            }
             if constexpr (KSRC == KSRC_RECOMPUTE) {
                 const float4 kk = *reinterpret_cast<const float4*>(&kband[w][(4 * s2 + g) * 64 + 4 * q]);
                 k = V4<ST>{{(ST)kk.x, (ST)kk.y, (ST)kk.z, (ST)kk.w}};
@@ -543,27 +577,27 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
                 if constexpr (STORED) {
                     opf = (XT)pf.v[c]; opb = (XT)pb.v[c]; oef = (XT)ef.v[c]; oeb = (XT)eb.v[c];
                 } else if constexpr (SER) {
+                    // G = P / (-a^2), F = E / a of the previous sweep's messages,
+                    // rebuilt from the deepest level up (XT = LT on this path)
                     const LT al = (LT)k.v[c], a2l = al * al;
-                    LT lpf = 0, lpb = 0, lef = 0, leb = 0;
+                    LT gf = 0, gb = 0, ff = 0, fb = 0;
                     constexpr int kd = L - 1;
 #pragma unroll
                     for (int kk = D - 1; kk >= 1; --kk) {
                         if (kk == kd) {               // deepest level: reverse messages zero
-                            lpf = -a2l * sPtL[kk - 1][r];
-                            lpb = -a2l * ptjL[kk - 1][c];
-                            lef = -al * sSIL[kk - 1][r];
-                            leb = -al * sijL[kk - 1][c];
+                            gf = sPtL[kk - 1][r];
+                            gb = ptjL[kk - 1][c];
+                            ff = -sSIL[kk - 1][r];
+                            fb = -sijL[kk - 1][c];
                         } else if (kk < kd) {
-                            const LT ir = sPtL[kk - 1][r], ic = ptjL[kk - 1][c];
-                            const LT e_f = lpb * ir, e_b = lpf * ic;
-                            const LT tf = al * fma(ir, e_f, ir), tb = al * fma(ic, e_b, ic);
-                            const LT npf_ = -al * tf, npb_ = -al * tb;
-                            const LT nef_ = tf * (leb - sSL[kk - 1][r]);
-                            const LT neb_ = tb * (lef - sjL[kk - 1][c]);
-                            lpf = npf_; lpb = npb_; lef = nef_; leb = neb_;
+                            const LT ngf = fma(-a2l * sUQL[kk - 1][r], gb, sPtL[kk - 1][r]);
+                            const LT ngb = fma(-a2l * cuqL[kk - 1][c], gf, ptjL[kk - 1][c]);
+                            const LT nff = ngf * fma(al, fb, -sSL[kk - 1][r]);
+                            const LT nfb = ngb * fma(al, ff, -sjL[kk - 1][c]);
+                            gf = ngf; gb = ngb; ff = nff; fb = nfb;
                         }
                     }
-                    opf = (XT)lpf; opb = (XT)lpb; oef = (XT)lef; oeb = (XT)leb;
+                    opf = (XT)gf; opb = (XT)gb; oef = (XT)ff; oeb = (XT)fb;
                 } else {
                     const LT al = (LT)k.v[c], a2l = al * al;
                     LT lpf = 0, lpb = 0, lef = 0, leb = 0;
@@ -583,13 +617,21 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
                 }
                 XT pij_m, eij_m, pji_m, eji_m;
                 if constexpr (SER) {
-                    const XT e_f = opb * pti, e_b = opf * ptj[c];      // P_ji / P~_i, P_ij / P~_j
-                    const XT tf = av * fma(pti, fma(e_f, e_f, e_f), pti);
-                    const XT tb = av * fma(ptj[c], fma(e_b, e_b, e_b), ptj[c]);
-                    pij_m = -av * tf;
-                    pji_m = -av * tb;
-                    eij_m = tf * (oeb - si);
-                    eji_m = tb * (oef - sj[c]);
+                    // opf, opb, oef, oeb hold G_ij, G_ji, F_ij, F_ji here
+                    const XT a2 = av * av;
+                    const XT e_f = -(a2 * opb) * pti, e_b = -(a2 * opf) * ptj[c];   // P_ji / P~_i, P_ij / P~_j
+                    XT gt_f, gt_b;                                                  // (1 + e + ...) / P~
+                    if constexpr (SER >= 2) {
+                        gt_f = fma(pti, fma(e_f, e_f, e_f), pti);
+                        gt_b = fma(ptj[c], fma(e_b, e_b, e_b), ptj[c]);
+                    } else {
+                        gt_f = fma(pti, e_f, pti);
+                        gt_b = fma(ptj[c], e_b, ptj[c]);
+                    }
+                    pij_m = -a2 * gt_f;
+                    pji_m = -a2 * gt_b;
+                    eij_m = (av * gt_f) * fma(av, oeb, -si);      // a G (E_ji - S_i)
+                    eji_m = (av * gt_b) * fma(av, oef, -sj[c]);
                 } else {
                     const XT a2 = av * av;
                     const XT qf = pti - opb;        // P~_i - P_ji
@@ -616,7 +658,8 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
                 }
             }
             if constexpr (STORED) {
-                st4nt(Pf + off, npf); st4nt(Pb + off, npb); st4nt(Ef + off, nef); st4nt(Eb + off, neb);
+                st4nt(lane_ptr(Pf + off, lo), npf); st4nt(lane_ptr(Pb + off, lo), npb);
+                st4nt(lane_ptr(Ef + off, lo), nef); st4nt(lane_ptr(Eb + off, lo), neb);
                 rp = sum16(rp);
                 re = sum16(re);
                 if (q == 0) { rP[w][r] = rp; rE[w][r] = re; }
@@ -669,7 +712,7 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
     if (__any(bad) && l == 0) st->bad = 1;
 }
 
-template <class ST, class MT, class AT, int KSRC, int GK, int D, bool FIRST, bool SER>
+template <class ST, class MT, class AT, int KSRC, int GK, int D, bool FIRST, int SER>
 __global__ __launch_bounds__(WG) void k_sweep(SweepArgs a) {
     if (a.st->done) return;
     sweep_tile<ST, MT, AT, KSRC, GK, D, FIRST, SER>(a, blockIdx.x, a.slot_top);
@@ -713,12 +756,13 @@ struct DirSmem {
     MT topP[TILE], topS[TILE];            // row source at level 0 (FWD)
     LT lowP[NRL][TILE], lowS[NRL][TILE];  // row source at lower levels
     LT lowSI[NRL][TILE];                  // series: S / P~
+    LT lowUQ[NRL][TILE];                  // series: (1/P~)^2
     RT rP[4][TILE], rE[4][TILE];          // BWD row partials per wave strip (exact in AT)
     RT red[4][2][2][64];                  // BWD stateless: two row steps of lane partials
     float kband[RECOMP ? 4 : 1][RECOMP ? 32 * 64 : 1];
 };
 
-template <class ST, class MT, class AT, int D, bool SER>
+template <class ST, class MT, class AT, int D, int SER>
 struct DirTypes {
     using XT = typename MsgT<ST, MT, AT, SER>::T;
     static constexpr bool XF = MsgT<ST, MT, AT, SER>::F32;
@@ -734,7 +778,7 @@ struct DirTypes {
 // reverse message below the deepest level taken as zero.  The source's
 // aggregates at version v sit in ring slot v mod R (R = 1 for stored
 // records: every read is the node's latest value).
-template <class ST, class MT, class AT, int KSRC, int GK, int D, bool SER, bool FWD, class SM>
+template <class ST, class MT, class AT, int KSRC, int GK, int D, int SER, bool FWD, class SM>
 __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool within, int t, SM& sm) {
     using DT = DirTypes<ST, MT, AT, D, SER>;
     using LT = typename DT::LT;
@@ -763,7 +807,7 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
     // source data per level: row side in LDS (per row), column side in
     // registers (the lane's four columns)
     XT ctP[4], ctS[4];                           // column source at level 0 (BWD)
-    LT clP[DT::NCL][4], clS[DT::NCL][4], clSI[SER ? DT::NCL : 1][4];
+    LT clP[DT::NCL][4], clS[DT::NCL][4], clSI[SER ? DT::NCL : 1][4], clUQ[SER ? DT::NCL : 1][4];
 #pragma unroll
     for (int k = 0; k < L; ++k) {
         const bool row_side = FWD ? !(k & 1) : (k & 1);
@@ -794,7 +838,7 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
                 const int m = FWD ? (k >> 1) - 1 : (k >> 1);
                 sm.lowP[m][tid] = (LT)pv;
                 sm.lowS[m][tid] = (LT)sv;
-                if constexpr (SER) sm.lowSI[m][tid] = (LT)mv;
+                if constexpr (SER) { sm.lowSI[m][tid] = (LT)mv; sm.lowUQ[m][tid] = (LT)(pv * pv); }
             }
         } else {
 #pragma unroll
@@ -808,7 +852,7 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
                     const int m = FWD ? (k >> 1) : (k >> 1) - 1;
                     clP[m][c] = (LT)pv;
                     clS[m][c] = (LT)sv;
-                    if constexpr (SER) clSI[m][c] = (LT)mv;
+                    if constexpr (SER) { clSI[m][c] = (LT)mv; clUQ[m][c] = (LT)(pv * pv); }
                 }
             }
         }
@@ -825,10 +869,11 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
     ST* Pwr = static_cast<ST*>(FWD ? a.Pf : a.Pb);
     ST* Ewr = static_cast<ST*>(FWD ? a.Ef : a.Eb);
 
-    size_t off = tbase + (size_t)g * TILE + col0;
+    size_t off = tbase;                                   // wave-uniform row offset
+    const uint32_t lo = (uint32_t)(g * TILE + col0);      // lane offset inside a row group
     V4<ST> k4{}, pr{}, er{};
-    if constexpr (KSRC == KSRC_PLANE) k4 = ld4nt(Kp + off);
-    if constexpr (STORED) { pr = ld4nt(Prd + off); er = ld4nt(Erd + off); }
+    if constexpr (KSRC == KSRC_PLANE) k4 = ld4nt(lane_ptr(Kp + off, lo));
+    if constexpr (STORED) { pr = ld4nt(lane_ptr(Prd + off, lo)); er = ld4nt(lane_ptr(Erd + off, lo)); }
 
     for (int b = 0; b < TILE / 32; ++b) {
         if constexpr (KSRC == KSRC_RECOMPUTE) {
@@ -841,8 +886,8 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
             const bool more = (b * 8 + s2 + 1) < TILE / 4;
             const size_t off2 = more ? off + 4 * TILE : off;
             V4<ST> k2, pr2, er2;
-            if constexpr (KSRC == KSRC_PLANE) k2 = ld4nt(Kp + off2);
-            if constexpr (STORED) { pr2 = ld4nt(Prd + off2); er2 = ld4nt(Erd + off2); }
+            if constexpr (KSRC == KSRC_PLANE) k2 = ld4nt(lane_ptr(Kp + off2, lo));
+            if constexpr (STORED) { pr2 = ld4nt(lane_ptr(Prd + off2, lo)); er2 = ld4nt(lane_ptr(Erd + off2, lo)); }
             if constexpr (KSRC == KSRC_RECOMPUTE) {
                 const float4 kk = *reinterpret_cast<const float4*>(&sm.kband[w][(4 * s2 + g) * 64 + 4 * q]);
                 k4 = V4<ST>{{(ST)kk.x, (ST)kk.y, (ST)kk.z, (ST)kk.w}};
@@ -868,16 +913,16 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
                         const LT pv = row_side ? sm.lowP[mr][r] : clP[mc][c];
                         const LT sv = row_side ? sm.lowS[mr][r] : clS[mc][c];
                         if constexpr (SER) {
+                            // G = P / (-a^2) and F = E / a (as in the synchronous sweep)
                             if (k == L - 1) {            // deepest: reverse message zero
                                 const LT siv = row_side ? sm.lowSI[mr][r] : clSI[mc][c];
-                                lp = -a2l * pv;
-                                le = -al * siv;
+                                lp = pv;
+                                le = -siv;
                             } else {
-                                const LT e = lp * pv;
-                                const LT tf = al * fma(pv, e, pv);
-                                const LT np_ = -al * tf;
-                                const LT ne_ = tf * (le - sv);
-                                lp = np_; le = ne_;
+                                const LT uq = row_side ? sm.lowUQ[mr][r] : clUQ[mc][c];
+                                const LT ng = fma(-a2l * uq, lp, pv);
+                                const LT nf = ng * fma(al, le, -sv);
+                                lp = ng; le = nf;
                             }
                         } else {
                             const LT qv = pv - lp;
@@ -895,10 +940,14 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
                 const XT sv = FWD ? sm.topS[r] : ctS[c];
                 XT pm, em;
                 if constexpr (SER) {
-                    const XT e = opr * pt;
-                    const XT tf = av * fma(pt, fma(e, e, e), pt);
-                    pm = -av * tf;
-                    em = tf * (oer - sv);
+                    // opr, oer hold G, F of the reverse message here
+                    const XT a2 = av * av;
+                    const XT e = -(a2 * opr) * pt;
+                    XT gt;
+                    if constexpr (SER >= 2) gt = fma(pt, fma(e, e, e), pt);
+                    else gt = fma(pt, e, pt);
+                    pm = -a2 * gt;
+                    em = (av * gt) * fma(av, oer, -sv);
                 } else {
                     const XT qv = pt - opr;
                     bad |= !(qv > (XT)0);
@@ -919,7 +968,7 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
                     else { rp += (AT)pm; re += (AT)em; }
                 }
             }
-            if constexpr (STORED) { st4nt(Pwr + off, np); st4nt(Ewr + off, ne); }
+            if constexpr (STORED) { st4nt(lane_ptr(Pwr + off, lo), np); st4nt(lane_ptr(Ewr + off, lo), ne); }
             if constexpr (!FWD && STORED) {
                 rp = sum16(rp);
                 re = sum16(re);
@@ -976,7 +1025,7 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
 }
 
 // One visit of the grouped schedule over the entries list[0, n).
-template <class ST, class MT, class AT, int KSRC, int GK, int D, bool SER>
+template <class ST, class MT, class AT, int KSRC, int GK, int D, int SER>
 __global__ __launch_bounds__(WG) void k_sweep_dir(SweepArgs a, const uint32_t* __restrict__ list, int t) {
     using DT = DirTypes<ST, MT, AT, D, SER>;
     __shared__ DirSmem<typename DT::XT, typename DT::LT, AT, typename DT::RT, DT::NRL, KSRC == KSRC_RECOMPUTE> sm;
@@ -993,7 +1042,7 @@ __global__ __launch_bounds__(WG) void k_sweep_dir(SweepArgs a, const uint32_t* _
 template <class ST, class MT, class AT, int KSRC, int GK>
 __global__ __launch_bounds__(WG) void k_sweep_listed(SweepArgs a, const uint32_t* __restrict__ list) {
     if (a.st->done) return;
-    sweep_tile<ST, MT, AT, KSRC, GK, 0, false, false>(a, (int64_t)(list[blockIdx.x] & GE_TILE), 0);
+    sweep_tile<ST, MT, AT, KSRC, GK, 0, false, 0>(a, (int64_t)(list[blockIdx.x] & GE_TILE), 0);
 }
 
 // Served form: one persistent grid walks the union work list of (request,
@@ -1003,7 +1052,7 @@ __global__ __launch_bounds__(WG) void k_sweep_listed(SweepArgs a, const uint32_t
 // mix; the ring slot of the previous sweep follows from the request's own
 // sweep count (ring slots of the sweeps before sweep 0 hold P~ = inf, S = 0,
 // so a fixed level count is exact from the first sweep).
-template <class ST, class MT, class AT, int D, bool SER>
+template <class ST, class MT, class AT, int D, int SER>
 __global__ __launch_bounds__(WG) void k_sweep_batched(const ReqDesc* __restrict__ reqs,
                                                      const uint2* __restrict__ items, int nitems) {
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -1016,50 +1065,48 @@ __global__ __launch_bounds__(WG) void k_sweep_batched(const ReqDesc* __restrict_
     }
 }
 
-template <class ST, class MT, class AT, int D, bool SER>
+// Run-time (levels, reciprocal form) of a stateless launch to the
+// compile-time pair (D, SER): exact reciprocals up to 8 levels, the series
+// (one- or two-term top level) up to 6.  Every pair is its own
+// instantiation, so the level loops are fully unrolled and branch-free.
+template <class F>
+inline hipError_t with_stateless(int levels, int ser, F&& f) {
+    using std::integral_constant;
+#define GABP_SL(S_, L_) \
+    case S_ * 16 + L_: f(integral_constant<int, L_>{}, integral_constant<int, S_>{}); return hipSuccess;
+    switch (ser * 16 + levels) {
+        GABP_SL(0, 1) GABP_SL(0, 2) GABP_SL(0, 3) GABP_SL(0, 4) GABP_SL(0, 5) GABP_SL(0, 6) GABP_SL(0, 7) GABP_SL(0, 8)
+        GABP_SL(1, 1) GABP_SL(1, 2) GABP_SL(1, 3) GABP_SL(1, 4) GABP_SL(1, 5) GABP_SL(1, 6)
+        GABP_SL(2, 1) GABP_SL(2, 2) GABP_SL(2, 3) GABP_SL(2, 4) GABP_SL(2, 5) GABP_SL(2, 6)
+        default: return hipErrorInvalidValue;
+    }
+#undef GABP_SL
+}
+
+template <class ST, class MT, class AT, int D, int SER>
 inline void served_d(const ReqDesc* reqs, const uint2* items, int n, hipStream_t s) {
     const int g = std::max(1, std::min(n, 2048));
     hipLaunchKernelGGL((k_sweep_batched<ST, MT, AT, D, SER>), dim3(g), dim3(WG), 0, s, reqs, items, n);
 }
 
-// levels 0: stored pair records; 1..8 stateless (1..6 with series).
+// levels 0: stored pair records; 1..8 stateless (1..6 with the series).
 template <class ST, class MT, class AT>
-inline hipError_t served_sweep(int levels, bool ser, const ReqDesc* reqs, const uint2* items, int n,
+inline hipError_t served_sweep(int levels, int ser, const ReqDesc* reqs, const uint2* items, int n,
                                hipStream_t s) {
-    if (levels == 0) { served_d<ST, MT, AT, 0, false>(reqs, items, n, s); return hipGetLastError(); }
-    if (ser) {
-        switch (levels) {
-            case 1: served_d<ST, MT, AT, 1, true>(reqs, items, n, s); break;
-            case 2: served_d<ST, MT, AT, 2, true>(reqs, items, n, s); break;
-            case 3: served_d<ST, MT, AT, 3, true>(reqs, items, n, s); break;
-            case 4: served_d<ST, MT, AT, 4, true>(reqs, items, n, s); break;
-            case 5: served_d<ST, MT, AT, 5, true>(reqs, items, n, s); break;
-            case 6: served_d<ST, MT, AT, 6, true>(reqs, items, n, s); break;
-            default: return hipErrorInvalidValue;
-        }
-        return hipGetLastError();
-    }
-    switch (levels) {
-        case 1: served_d<ST, MT, AT, 1, false>(reqs, items, n, s); break;
-        case 2: served_d<ST, MT, AT, 2, false>(reqs, items, n, s); break;
-        case 3: served_d<ST, MT, AT, 3, false>(reqs, items, n, s); break;
-        case 4: served_d<ST, MT, AT, 4, false>(reqs, items, n, s); break;
-        case 5: served_d<ST, MT, AT, 5, false>(reqs, items, n, s); break;
-        case 6: served_d<ST, MT, AT, 6, false>(reqs, items, n, s); break;
-        case 7: served_d<ST, MT, AT, 7, false>(reqs, items, n, s); break;
-        case 8: served_d<ST, MT, AT, 8, false>(reqs, items, n, s); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    if (levels == 0) { served_d<ST, MT, AT, 0, 0>(reqs, items, n, s); return hipGetLastError(); }
+    const hipError_t e = with_stateless(levels, ser, [&](auto L_, auto S_) {
+        served_d<ST, MT, AT, decltype(L_)::value, decltype(S_)::value>(reqs, items, n, s);
+    });
+    return e != hipSuccess ? e : hipGetLastError();
 }
 
 // ---- sweep dispatch: precision x K' source x Gram kind x depth x first x series
-template <class ST, class MT, class AT, int KSRC, int GK, int D, bool SER>
+template <class ST, class MT, class AT, int KSRC, int GK, int D, int SER>
 inline void sweep_d(bool first, const SweepArgs& a, hipStream_t s) {
     const dim3 g((unsigned)a.ntiles), blk(WG);
     if constexpr (D == 0) {
         if (first) {
-            hipLaunchKernelGGL((k_sweep<ST, MT, AT, KSRC, GK, D, true, false>), g, blk, 0, s, a);
+            hipLaunchKernelGGL((k_sweep<ST, MT, AT, KSRC, GK, D, true, 0>), g, blk, 0, s, a);
             return;
         }
     }
@@ -1067,42 +1114,22 @@ inline void sweep_d(bool first, const SweepArgs& a, hipStream_t s) {
 }
 
 // `levels` = 0: stored edge state; >= 1: stateless with exactly that many
-// levels (each count is its own instantiation, so the level loops are
-// fully unrolled and branch-free).
+// levels; `ser`: 0 exact reciprocals, 1 / 2 series with a one- / two-term
+// top level.
 template <class ST, class MT, class AT, int KSRC, int GK>
-inline hipError_t sweep_depth(int levels, bool first, bool ser, const SweepArgs& a, hipStream_t s) {
+inline hipError_t sweep_depth(int levels, bool first, int ser, const SweepArgs& a, hipStream_t s) {
     if (levels == 0) {
-        sweep_d<ST, MT, AT, KSRC, GK, 0, false>(first, a, s);
+        sweep_d<ST, MT, AT, KSRC, GK, 0, 0>(first, a, s);
         return hipGetLastError();
     }
-    if (ser) {
-        switch (levels) {
-            case 1: sweep_d<ST, MT, AT, KSRC, GK, 1, true>(first, a, s); break;
-            case 2: sweep_d<ST, MT, AT, KSRC, GK, 2, true>(first, a, s); break;
-            case 3: sweep_d<ST, MT, AT, KSRC, GK, 3, true>(first, a, s); break;
-            case 4: sweep_d<ST, MT, AT, KSRC, GK, 4, true>(first, a, s); break;
-            case 5: sweep_d<ST, MT, AT, KSRC, GK, 5, true>(first, a, s); break;
-            case 6: sweep_d<ST, MT, AT, KSRC, GK, 6, true>(first, a, s); break;
-            default: return hipErrorInvalidValue;
-        }
-        return hipGetLastError();
-    }
-    switch (levels) {
-        case 1: sweep_d<ST, MT, AT, KSRC, GK, 1, false>(first, a, s); break;
-        case 2: sweep_d<ST, MT, AT, KSRC, GK, 2, false>(first, a, s); break;
-        case 3: sweep_d<ST, MT, AT, KSRC, GK, 3, false>(first, a, s); break;
-        case 4: sweep_d<ST, MT, AT, KSRC, GK, 4, false>(first, a, s); break;
-        case 5: sweep_d<ST, MT, AT, KSRC, GK, 5, false>(first, a, s); break;
-        case 6: sweep_d<ST, MT, AT, KSRC, GK, 6, false>(first, a, s); break;
-        case 7: sweep_d<ST, MT, AT, KSRC, GK, 7, false>(first, a, s); break;
-        case 8: sweep_d<ST, MT, AT, KSRC, GK, 8, false>(first, a, s); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    const hipError_t e = with_stateless(levels, ser, [&](auto L_, auto S_) {
+        sweep_d<ST, MT, AT, KSRC, GK, decltype(L_)::value, decltype(S_)::value>(first, a, s);
+    });
+    return e != hipSuccess ? e : hipGetLastError();
 }
 
 // ---- grouped schedule dispatch: one group visit
-template <class ST, class MT, class AT, int KSRC, int GK, int D, bool SER>
+template <class ST, class MT, class AT, int KSRC, int GK, int D, int SER>
 inline void grouped_d(const SweepArgs& a, const uint32_t* list, int n, int t, hipStream_t s) {
     if (n > 0)
         hipLaunchKernelGGL((k_sweep_dir<ST, MT, AT, KSRC, GK, D, SER>), dim3((unsigned)n), dim3(WG), 0, s, a, list, t);
@@ -1111,39 +1138,19 @@ inline void grouped_d(const SweepArgs& a, const uint32_t* list, int n, int t, hi
 // Stored records (levels 0): the tiles inside the group in `within` (both
 // directions), the others in `dir`; stateless: every entry in `dir`.
 template <class ST, class MT, class AT, int KSRC, int GK>
-inline hipError_t sweep_grouped(int levels, bool ser, const SweepArgs& a, const uint32_t* within, int nwithin,
+inline hipError_t sweep_grouped(int levels, int ser, const SweepArgs& a, const uint32_t* within, int nwithin,
                                 const uint32_t* dir, int ndir, int t, hipStream_t s) {
     if (levels == 0) {
         if (nwithin > 0)
             hipLaunchKernelGGL((k_sweep_listed<ST, MT, AT, KSRC, GK>), dim3((unsigned)nwithin), dim3(WG), 0, s, a,
                                within);
-        grouped_d<ST, MT, AT, KSRC, GK, 0, false>(a, dir, ndir, t, s);
+        grouped_d<ST, MT, AT, KSRC, GK, 0, 0>(a, dir, ndir, t, s);
         return hipGetLastError();
     }
-    if (ser) {
-        switch (levels) {
-            case 1: grouped_d<ST, MT, AT, KSRC, GK, 1, true>(a, dir, ndir, t, s); break;
-            case 2: grouped_d<ST, MT, AT, KSRC, GK, 2, true>(a, dir, ndir, t, s); break;
-            case 3: grouped_d<ST, MT, AT, KSRC, GK, 3, true>(a, dir, ndir, t, s); break;
-            case 4: grouped_d<ST, MT, AT, KSRC, GK, 4, true>(a, dir, ndir, t, s); break;
-            case 5: grouped_d<ST, MT, AT, KSRC, GK, 5, true>(a, dir, ndir, t, s); break;
-            case 6: grouped_d<ST, MT, AT, KSRC, GK, 6, true>(a, dir, ndir, t, s); break;
-            default: return hipErrorInvalidValue;
-        }
-        return hipGetLastError();
-    }
-    switch (levels) {
-        case 1: grouped_d<ST, MT, AT, KSRC, GK, 1, false>(a, dir, ndir, t, s); break;
-        case 2: grouped_d<ST, MT, AT, KSRC, GK, 2, false>(a, dir, ndir, t, s); break;
-        case 3: grouped_d<ST, MT, AT, KSRC, GK, 3, false>(a, dir, ndir, t, s); break;
-        case 4: grouped_d<ST, MT, AT, KSRC, GK, 4, false>(a, dir, ndir, t, s); break;
-        case 5: grouped_d<ST, MT, AT, KSRC, GK, 5, false>(a, dir, ndir, t, s); break;
-        case 6: grouped_d<ST, MT, AT, KSRC, GK, 6, false>(a, dir, ndir, t, s); break;
-        case 7: grouped_d<ST, MT, AT, KSRC, GK, 7, false>(a, dir, ndir, t, s); break;
-        case 8: grouped_d<ST, MT, AT, KSRC, GK, 8, false>(a, dir, ndir, t, s); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    const hipError_t e = with_stateless(levels, ser, [&](auto L_, auto S_) {
+        grouped_d<ST, MT, AT, KSRC, GK, decltype(L_)::value, decltype(S_)::value>(a, dir, ndir, t, s);
+    });
+    return e != hipSuccess ? e : hipGetLastError();
 }
 
 }  // namespace gabp

@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <cmath>
+
 #include <string>
 
 #include "../../include/gabp_svm.h"
@@ -67,6 +70,33 @@ struct KernelParams {
 gabp_status check_params(const gabp_svm_params* p, std::string& why);
 
 inline int64_t n_tiles(int NB) { return (int64_t)NB * (NB + 1) / 2; }
+
+// Stateless plan from the contraction bound.  rr = 1.25 rho bounds
+// |A_ij| / Q_ij, the factor with which a reverse message enters the next
+// one, so unrolling `levels` levels truncates the recursion by about
+// rr^levels.  Levels needed: the smallest count with rr^levels below the
+// path's message precision, 2^-24 (FP32), 2^-30 (MIXED, FP32-stored
+// messages), 2^-50 (FP64); 9 when no count up to 8 suffices.
+inline int stateless_levels_needed(int prec, double rr) {
+    const double eps = (prec == PREC_FP32) ? std::ldexp(1.0, -24)
+                     : (prec == PREC_MIXED) ? std::ldexp(1.0, -30) : std::ldexp(1.0, -50);
+    if (rr == 0.0) return 1;
+    if (!(rr < 1.0)) return 9;
+    return std::max(1, (int)std::ceil(std::log(eps) / std::log(rr)));
+}
+// Reciprocal form of a stateless plan: 0 exact reciprocals; 1 / 2 series
+// around 1/P~ with a one- / two-term top level.  |e| <= rr^2, so the
+// one-term lower levels err by rr^4, entering the top level scaled by rr,
+// and the top level errs by rr^4 (one term) or rr^6 (two terms); each must
+// stay below the precision of its arithmetic (FP32 messages: FP32 and
+// MIXED; FP64 messages: FP64).
+inline int stateless_series_form(int prec, int levels, double rr) {
+    const double eps = (prec == PREC_FP64) ? std::ldexp(1.0, -52) : std::ldexp(1.0, -24);
+    if (levels < 1 || levels > 6 || !(rr < 0.25) || std::pow(rr, 5) > eps) return 0;
+    if (std::pow(rr, 4) <= eps) return 1;
+    if (std::pow(rr, 6) <= eps) return 2;
+    return 0;
+}
 // Entries of the grouped schedule's visit lists: bit 31 = messages into the
 // row block (BWD; clear: into the column block), bit 30 = both blocks lie in
 // the visited group, low 30 bits = tile index.
@@ -145,25 +175,25 @@ struct ReqDesc {
 // over the (request, tile) items, batched finalize over the (request, node
 // block) items, batched stop rule for the request slots listed in `slots`,
 // whose statuses are copied to status_out[0..nslots).
-hipError_t launch_served_step(int prec, int levels, bool ser, const ReqDesc* reqs, const uint2* tile_items,
+hipError_t launch_served_step(int prec, int levels, int ser, const ReqDesc* reqs, const uint2* tile_items,
                               int ntile_items, const uint2* node_items, int nnode_items, const int* slots,
                               int nslots, DevStatus* status_out, hipStream_t s);
-hipError_t launch_served_sweep_f32(int levels, bool ser, const ReqDesc* reqs, const uint2* items, int n,
+hipError_t launch_served_sweep_f32(int levels, int ser, const ReqDesc* reqs, const uint2* items, int n,
                                    hipStream_t s);
-hipError_t launch_served_sweep_mixed(int levels, bool ser, const ReqDesc* reqs, const uint2* items, int n,
+hipError_t launch_served_sweep_mixed(int levels, int ser, const ReqDesc* reqs, const uint2* items, int n,
                                      hipStream_t s);
-hipError_t launch_served_sweep_f64(int levels, bool ser, const ReqDesc* reqs, const uint2* items, int n,
+hipError_t launch_served_sweep_f64(int levels, int ser, const ReqDesc* reqs, const uint2* items, int n,
                                    hipStream_t s);
 // depth 0 = stored edge state, 1..8 = stateless with up to `depth` levels.
 // levels: 0 = stored edge state, >= 1 = stateless with that many levels in
 // this launch; ser: stateless reciprocals by the series around 1/P~.
-hipError_t launch_sweep(int prec, int ksrc, int gram, int levels, bool first, bool ser, const SweepArgs& a,
+hipError_t launch_sweep(int prec, int ksrc, int gram, int levels, bool first, int ser, const SweepArgs& a,
                         hipStream_t s);
-hipError_t launch_sweep_f32(int ksrc, int gram, int levels, bool first, bool ser, const SweepArgs& a,
+hipError_t launch_sweep_f32(int ksrc, int gram, int levels, bool first, int ser, const SweepArgs& a,
                             hipStream_t s);
-hipError_t launch_sweep_mixed(int ksrc, int gram, int levels, bool first, bool ser, const SweepArgs& a,
+hipError_t launch_sweep_mixed(int ksrc, int gram, int levels, bool first, int ser, const SweepArgs& a,
                               hipStream_t s);
-hipError_t launch_sweep_f64(int ksrc, int gram, int levels, bool first, bool ser, const SweepArgs& a,
+hipError_t launch_sweep_f64(int ksrc, int gram, int levels, bool first, int ser, const SweepArgs& a,
                             hipStream_t s);
 // Inv / Mean (optional, with Pt / S): the new 1/P~ and S/P~ of the series
 // sweeps, formed once per node here instead of in every tile.
@@ -178,16 +208,16 @@ hipError_t launch_ring_recip(int prec, int64_t NPAD, int R, const void* Pt, cons
 // Grouped schedule: one group visit.  `within` lists the stored-record tiles
 // inside the group (both directions), `dir` the single-direction entries
 // (tile index | GE_BWD | GE_WITHIN bits, see gabp_device.h); t = sweep index.
-hipError_t launch_sweep_grouped(int prec, int ksrc, int gram, int levels, bool ser, const SweepArgs& a,
+hipError_t launch_sweep_grouped(int prec, int ksrc, int gram, int levels, int ser, const SweepArgs& a,
                                 const uint32_t* within, int nwithin, const uint32_t* dir, int ndir, int t,
                                 hipStream_t s);
-hipError_t launch_sweep_grouped_f32(int ksrc, int gram, int levels, bool ser, const SweepArgs& a,
+hipError_t launch_sweep_grouped_f32(int ksrc, int gram, int levels, int ser, const SweepArgs& a,
                                     const uint32_t* within, int nwithin, const uint32_t* dir, int ndir, int t,
                                     hipStream_t s);
-hipError_t launch_sweep_grouped_mixed(int ksrc, int gram, int levels, bool ser, const SweepArgs& a,
+hipError_t launch_sweep_grouped_mixed(int ksrc, int gram, int levels, int ser, const SweepArgs& a,
                                       const uint32_t* within, int nwithin, const uint32_t* dir, int ndir, int t,
                                       hipStream_t s);
-hipError_t launch_sweep_grouped_f64(int ksrc, int gram, int levels, bool ser, const SweepArgs& a,
+hipError_t launch_sweep_grouped_f64(int ksrc, int gram, int levels, int ser, const SweepArgs& a,
                                     const uint32_t* within, int nwithin, const uint32_t* dir, int ndir, int t,
                                     hipStream_t s);
 // Sparsified kernel (gabp_sparse.hip): build passes, sorts and scans (the

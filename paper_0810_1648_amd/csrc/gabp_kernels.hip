@@ -810,9 +810,9 @@ hipError_t launch_init(int prec, int64_t N, int64_t NPAD, int R, const double* A
 }
 
 // Per-precision sweep dispatch lives in gabp_sweep_{f32,mixed,f64}.hip.
-hipError_t launch_sweep(int prec, int ksrc, int gram, int levels, bool first, bool ser, const SweepArgs& a,
+hipError_t launch_sweep(int prec, int ksrc, int gram, int levels, bool first, int ser, const SweepArgs& a,
                         hipStream_t s) {
-    if (levels == 0) ser = false;
+    if (levels == 0) ser = 0;
     switch (prec) {
         case PREC_FP32: return launch_sweep_f32(ksrc, gram, levels, first, ser, a, s);
         case PREC_MIXED: return launch_sweep_mixed(ksrc, gram, levels, first, ser, a, s);
@@ -821,10 +821,10 @@ hipError_t launch_sweep(int prec, int ksrc, int gram, int levels, bool first, bo
     }
 }
 
-hipError_t launch_sweep_grouped(int prec, int ksrc, int gram, int levels, bool ser, const SweepArgs& a,
+hipError_t launch_sweep_grouped(int prec, int ksrc, int gram, int levels, int ser, const SweepArgs& a,
                                 const uint32_t* within, int nwithin, const uint32_t* dir, int ndir, int t,
                                 hipStream_t s) {
-    if (levels == 0) ser = false;
+    if (levels == 0) ser = 0;
     switch (prec) {
         case PREC_FP32: return launch_sweep_grouped_f32(ksrc, gram, levels, ser, a, within, nwithin, dir, ndir, t, s);
         case PREC_MIXED: return launch_sweep_grouped_mixed(ksrc, gram, levels, ser, a, within, nwithin, dir, ndir, t, s);
@@ -833,7 +833,7 @@ hipError_t launch_sweep_grouped(int prec, int ksrc, int gram, int levels, bool s
     }
 }
 
-hipError_t launch_served_step(int prec, int levels, bool ser, const ReqDesc* reqs, const uint2* tile_items,
+hipError_t launch_served_step(int prec, int levels, int ser, const ReqDesc* reqs, const uint2* tile_items,
                               int ntile_items, const uint2* node_items, int nnode_items, const int* slots,
                               int nslots, DevStatus* status_out, hipStream_t s) {
     hipError_t e;

@@ -136,7 +136,7 @@ struct Req {
     int slot = -1;
     int bypassed = 0;
     int levels = 0;      // 0: stored pair records; >= 1: stateless levels
-    bool ser = false;    // stateless reciprocals by the series around 1/P~
+    int ser = 0;         // stateless reciprocals: 0 exact, 1 / 2 series (top-level terms)
     double rho = 0.0;    // contraction bound
 };
 
@@ -194,7 +194,7 @@ struct gabp_server {
     // launch groups: requests sharing precision, level count and series flag
     struct Group {
         int prec = 0, levels = 0;
-        bool ser = false;
+        int ser = 0;
         uint2* d_tiles = nullptr; uint2* h_tiles = nullptr; size_t cap_tiles = 0;
         uint2* d_nodes = nullptr; uint2* h_nodes = nullptr; size_t cap_nodes = 0;
         int* d_slots = nullptr; int* h_slots = nullptr;
@@ -279,19 +279,13 @@ hipError_t setup_request(gabp_server* S, Req& r) {
     CK(hipMemcpyAsync(hb, P(B_ONE), 16, hipMemcpyDeviceToHost, s));
     CK(hipStreamSynchronize(s));
     r.rho = hb[1];
-    const double eps = (r.prec == PREC_FP32) ? std::ldexp(1.0, -24)
-                     : (r.prec == PREC_MIXED) ? std::ldexp(1.0, -30) : std::ldexp(1.0, -50);
     const double rr = 1.25 * r.rho;
-    int dneed = 9;
-    if (rr == 0.0) dneed = 1;
-    else if (rr < 1.0) dneed = std::max(1, (int)std::ceil(std::log(eps) / std::log(rr)));
+    const int dneed = stateless_levels_needed(r.prec, rr);
     bool stateless = false;
     if (r.p.edge_state == GABP_EDGE_STATELESS) stateless = true;
     else if (r.p.edge_state == GABP_EDGE_AUTO) stateless = dneed <= 8;
     r.levels = stateless ? (r.p.stateless_depth > 0 ? r.p.stateless_depth : std::min(dneed, 8)) : 0;
-    const double eps_low = (r.prec == PREC_FP64) ? std::ldexp(1.0, -52) : std::ldexp(1.0, -24);
-    const double eps_top = (r.prec == PREC_FP32) ? std::ldexp(1.0, -24) : std::ldexp(1.0, -52);
-    r.ser = stateless && r.levels <= 6 && rr < 0.25 && std::pow(rr, 5) <= eps_low && std::pow(rr, 6) <= eps_top;
+    r.ser = stateless ? stateless_series_form(r.prec, r.levels, rr) : 0;
     if (stateless) {
         // the pair-record planes are not needed: give them back to the arena
         const std::vector<int> planes = {B_PF, B_PB, B_EF, B_EB};
@@ -335,7 +329,7 @@ hipError_t setup_request(gabp_server* S, Req& r) {
     return hipSuccess;
 }
 
-inline int group_key(const Req& r) { return r.prec * 100 + (r.ser ? 10 : 0) + r.levels; }
+inline int group_key(const Req& r) { return r.prec * 100 + r.ser * 10 + r.levels; }
 
 // Rebuilds the per-group work lists from the active slots.
 hipError_t rebuild_lists(gabp_server* S) {

@@ -369,12 +369,9 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
                           h->alpha_d.as<double>(), st, s, boxC));
     HIPCHK(h, hipEventRecord(ev[3], s));
 
-    // ---- plan of the edge state from the contraction bound
-    // rho bounds |A_ij| / Q_ij, the factor with which a reverse message enters
-    // the next one, so unrolling `depth` levels truncates the recursion by
-    // about rho^depth.  Stateless depth: requested, or the smallest with
-    // (1.25 rho)^depth below the path's message precision: 2^-24 (FP32),
-    // 2^-30 (MIXED, FP32-stored messages), 2^-50 (FP64), at most 8.
+    // ---- plan of the edge state from the contraction bound (rho bounds
+    // |A_ij| / Q_ij; stateless_levels_needed and stateless_series_form give
+    // the level count and the reciprocal form)
     double rho = INFINITY;
     {
         double hb[2] = {0.0, 0.0};
@@ -384,23 +381,13 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
         HIPCHK(h, hipStreamSynchronize(s));
         rho = hb[1];
     }
-    const double eps = (prec == PREC_FP32) ? std::ldexp(1.0, -24)
-                     : (prec == PREC_MIXED) ? std::ldexp(1.0, -30) : std::ldexp(1.0, -50);
     const double rr = 1.25 * rho;
-    int dneed = 9;
-    if (rr == 0.0) dneed = 1;
-    else if (rr < 1.0) dneed = std::max(1, (int)std::ceil(std::log(eps) / std::log(rr)));
+    const int dneed = stateless_levels_needed(prec, rr);
     bool cur_stored = stored;
     int depth = 0;
     if (probe) cur_stored = dneed > 8;
     if (!cur_stored) depth = (p.stateless_depth > 0) ? p.stateless_depth : std::min(dneed, 8);
-    // Series reciprocals: |e| <= rr^2, so the one-term lower levels err by
-    // rr^4 (entering the top level scaled by rr) and the two-term top level by
-    // rr^6; both must stay below the precision of their arithmetic.
-    const double eps_low = (prec == PREC_FP64) ? std::ldexp(1.0, -52) : std::ldexp(1.0, -24);
-    const double eps_top = (prec == PREC_FP32) ? std::ldexp(1.0, -24) : std::ldexp(1.0, -52);
-    const bool ser = !cur_stored && depth <= 6 && rr < 0.25 && std::pow(rr, 5) <= eps_low &&
-                     std::pow(rr, 6) <= eps_top;
+    const int ser = cur_stored ? 0 : stateless_series_form(prec, depth, rr);
     if (probe && cur_stored) {
         if (h->Pf.ensure(plane) != hipSuccess || h->Pb.ensure(plane) != hipSuccess ||
             h->Ef.ensure(plane) != hipSuccess || h->Eb.ensure(plane) != hipSuccess) {
@@ -417,7 +404,7 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     // once per node (without them every tile forms the same quotients)
     void* hinv = nullptr;
     void* hmean = nullptr;
-    if (ser && h->HI.ensure((size_t)Rr * NPAD * agg_bytes) == hipSuccess &&
+    if (ser > 0 && h->HI.ensure((size_t)Rr * NPAD * agg_bytes) == hipSuccess &&
         h->HM.ensure((size_t)Rr * NPAD * agg_bytes) == hipSuccess) {
         hinv = h->HI.p;
         hmean = h->HM.p;
@@ -598,7 +585,7 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     h->plan.tile = TILE;
     h->plan.stateless_depth = depth;
     h->plan.stateless_rho = rho;
-    h->plan.series_reciprocal = ser ? 1 : 0;
+    h->plan.series_reciprocal = ser;
     h->plan.sched_groups = grouped ? G : 0;
     h->plan.n_blocks = NB;
     h->plan.n_tiles = nt;

@@ -5,19 +5,19 @@
 
 namespace gabp {
 
-hipError_t launch_sweep_f64(int ksrc, int gram, int levels, bool first, bool ser, const SweepArgs& a,
+hipError_t launch_sweep_f64(int ksrc, int gram, int levels, bool first, int ser, const SweepArgs& a,
                               hipStream_t s) {
     if (ksrc == KSRC_PLANE) return sweep_depth<double, double, double, KSRC_PLANE, GRAM_F64>(levels, first, ser, a, s);
     (void)gram;
     return hipErrorInvalidValue;   // FP64 K' is always materialised
 }
 
-hipError_t launch_served_sweep_f64(int levels, bool ser, const ReqDesc* reqs, const uint2* items, int n,
+hipError_t launch_served_sweep_f64(int levels, int ser, const ReqDesc* reqs, const uint2* items, int n,
                                      hipStream_t s) {
     return served_sweep<double, double, double>(levels, ser, reqs, items, n, s);
 }
 
-hipError_t launch_sweep_grouped_f64(int ksrc, int gram, int levels, bool ser, const SweepArgs& a,
+hipError_t launch_sweep_grouped_f64(int ksrc, int gram, int levels, int ser, const SweepArgs& a,
                                    const uint32_t* within, int nwithin, const uint32_t* dir, int ndir, int t,
                                    hipStream_t s) {
     if (ksrc == KSRC_PLANE)

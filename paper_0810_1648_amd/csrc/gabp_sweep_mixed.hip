@@ -5,7 +5,7 @@
 
 namespace gabp {
 
-hipError_t launch_sweep_mixed(int ksrc, int gram, int levels, bool first, bool ser, const SweepArgs& a,
+hipError_t launch_sweep_mixed(int ksrc, int gram, int levels, bool first, int ser, const SweepArgs& a,
                               hipStream_t s) {
     if (ksrc == KSRC_PLANE) return sweep_depth<float, double, double, KSRC_PLANE, GRAM_F32>(levels, first, ser, a, s);
     switch (gram) {
@@ -16,12 +16,12 @@ hipError_t launch_sweep_mixed(int ksrc, int gram, int levels, bool first, bool s
     }
 }
 
-hipError_t launch_served_sweep_mixed(int levels, bool ser, const ReqDesc* reqs, const uint2* items, int n,
+hipError_t launch_served_sweep_mixed(int levels, int ser, const ReqDesc* reqs, const uint2* items, int n,
                                      hipStream_t s) {
     return served_sweep<float, double, double>(levels, ser, reqs, items, n, s);
 }
 
-hipError_t launch_sweep_grouped_mixed(int ksrc, int gram, int levels, bool ser, const SweepArgs& a,
+hipError_t launch_sweep_grouped_mixed(int ksrc, int gram, int levels, int ser, const SweepArgs& a,
                                    const uint32_t* within, int nwithin, const uint32_t* dir, int ndir, int t,
                                    hipStream_t s) {
     if (ksrc == KSRC_PLANE)

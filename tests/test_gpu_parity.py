@@ -301,29 +301,39 @@ def test_plan_follows_memory_budget(torch):
     assert e.value.status == gabp.E_INVALID
 
 
-def test_stateless_series_reciprocals_match_oracle(torch):
-    """A wide RBF (gamma = 2e-3) gives row sums ~ N and a contraction
-    rho ~ 1/N, small enough for the series reciprocals; the sweeps must
-    still follow the oracle's truncated recursion at the chosen depth."""
-    X, y = inputs.blobs(1500, 8, 71)
-    wl = inputs.Workload("blobs-wide", X, y, gamma=2e-3, C=1.0, lam=1.0 / 1500, precision="mixed",
-                         tol_rel=0.0)
+# (N, gamma, precision, series form): wide RBFs give row sums ~ N and a
+# contraction rho ~ 1/N; FP32 messages (FP32, MIXED) take the one-term top
+# level while rho^4 is below 2^-24 and the two-term one up to rho^6, FP64
+# needs rho^5 below 2^-52 for any series
+SERIES_CASES = [(1500, 2e-3, "fp32", 1), (1500, 2e-3, "mixed", 1), (600, 0.05, "fp32", 2),
+                (600, 0.05, "mixed", 2), (2000, 2e-3, "fp64", 2)]
+
+
+@pytest.mark.parametrize("n,gamma,prec,form", SERIES_CASES)
+def test_stateless_series_reciprocals_match_oracle(torch, n, gamma, prec, form):
+    """The sweeps with series reciprocals follow the oracle's truncated
+    recursion (exact reciprocals) at the chosen depth: the series error is
+    below the arithmetic's precision by the plan's rule."""
+    X, y = inputs.blobs(n, 8, 71)
+    wl = inputs.Workload("blobs-wide", X, y, gamma=gamma, C=1.0, lam=1.0 / n, precision=prec, tol_rel=0.0)
     A, b = R.svm_system(wl.X, wl.y, wl.gamma, wl.C, wl.lam)
+    tol = 1e-11 if prec == "fp64" else TOL
+    print(f"[case] series n={n} gamma={gamma} {prec}", flush=True)
+    for t in (1, 2, 3, 6):
+        s, st = run(torch, wl, precision=prec, edge_state="stateless", kstore="materialise",
+                    max_sweeps=t, tol_abs=0.0, tol_rel=0.0, stagnation_window=0)
+        p = s.plan()
+        assert p["series_reciprocal"] == form, p
+        ref = R.gabp_solve_stateless(A, b, depth=p["stateless_depth"], sweeps=t)[-1]
+        err = _rel(s.alpha(), ref)
+        assert err <= tol, (prec, t, p["stateless_depth"], err)
     exact = R.cholesky_solve(A, b)
-    for prec in ("fp32", "mixed"):
-        for t in (1, 2, 3, 6):
-            s, st = run(torch, wl, precision=prec, edge_state="stateless", kstore="materialise",
-                        max_sweeps=t, tol_abs=0.0, tol_rel=0.0, stagnation_window=0)
-            p = s.plan()
-            assert p["series_reciprocal"] == 1, p
-            ref = R.gabp_solve_stateless(A, b, depth=p["stateless_depth"], sweeps=t)[-1]
-            err = _rel(s.alpha(), ref)
-            assert err <= TOL, (prec, t, p["stateless_depth"], err)
-        s, st = run(torch, wl, precision=prec, edge_state="stateless", tol_rel=1e-9)
-        err = _rel(s.alpha(), exact)
-        print(f"series stateless {prec}: depth {s.plan()['stateless_depth']} rho {s.plan()['stateless_rho']:.2e} "
-              f"sweeps {s.sweeps()} rel err vs Cholesky {err:.2e}")
-        assert st == gabp.OK and err <= TOL
+    s, st = run(torch, wl, precision=prec, edge_state="stateless", tol_rel=1e-9)
+    err = _rel(s.alpha(), exact)
+    print(f"series stateless {prec}: depth {s.plan()['stateless_depth']} form {s.plan()['series_reciprocal']} "
+          f"rho {s.plan()['stateless_rho']:.2e} sweeps {s.sweeps()} rel err vs Cholesky {err:.2e}")
+    # the stop rule (change below 1e-9 relative) bounds the distance left
+    assert st == gabp.OK and err <= (1e-8 if prec == "fp64" else TOL)
 
 
 @pytest.mark.parametrize("gamma", [2e-3, 1.0 / 8, 1.0])
