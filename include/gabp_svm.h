@@ -170,7 +170,8 @@ typedef struct gabp_svm_params {
                                   events (GABP_Q_TIMINGS.sweep_kernel_ms) */
     int32_t schedule;          /* gabp_sched, default SYNC */
     int32_t sched_groups;      /* GROUPED: number of node groups (whole
-                                  256-point blocks); 0 = 4 */
+                                  256-point blocks, at most the block
+                                  count); 0 = 16 */
     int32_t reserved;
     double sparse_tau;         /* RBF_SPARSE: kernel threshold in (0, 1] */
 } gabp_svm_params;

@@ -490,17 +490,31 @@ __device__ inline void finalize_block(int64_t blk, int64_t N, int NB, const AT* 
                                       double* __restrict__ blk_amax, DevStatus* st, double boxC,
                                       AT* __restrict__ Inv, AT* __restrict__ Mean) {
     __shared__ double sh4[4];
+    __shared__ AT shp[4][TILE], she[4][TILE];
+    // the NB + 1 partial slots of the block, split into four contiguous
+    // ranges, one per wave; each lane sums four nodes (64 apart) over its
+    // wave's range, so every wave keeps eight independent loads in flight
+    {
+        const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+        const int S1 = NB + 1, qn = (S1 + 3) / 4;
+        const int s0 = w * qn, s1 = (s0 + qn < S1) ? s0 + qn : S1;
+        AT ap[4] = {0, 0, 0, 0}, ae[4] = {0, 0, 0, 0};
+        for (int s = s0; s < s1; ++s) {
+            const size_t o = ((size_t)blk * S1 + s) * TILE + l;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) { ap[k] += partP[o + 64 * k]; ae[k] += partE[o + 64 * k]; }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) { shp[w][l + 64 * k] = ap[k]; she[w][l + 64 * k] = ae[k]; }
+    }
+    __syncthreads();
     const int64_t i = blk * blockDim.x + threadIdx.x;
     double d = 0.0, am = 0.0;
     bool bad = false;
     if (i < N) {
-        const int64_t B = i / TILE, t = i % TILE;
-        AT p = (AT)Adiag[i], e = (AT)y[i];
-        for (int s = 0; s <= NB; ++s) {
-            const size_t o = ((size_t)B * (NB + 1) + s) * TILE + t;
-            p += partP[o];
-            e += partE[o];
-        }
+        const int t = threadIdx.x;
+        AT p = (AT)Adiag[i] + ((shp[0][t] + shp[1][t]) + (shp[2][t] + shp[3][t]));
+        AT e = (AT)y[i] + ((she[0][t] + she[1][t]) + (she[2][t] + she[3][t]));
         double an = (double)(e / p) * (double)y[i];
         bad = !(p > (AT)0) || !isfinite((double)p) || !isfinite((double)e);
         if (boxC > 0.0) {

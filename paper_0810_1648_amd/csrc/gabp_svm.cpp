@@ -435,7 +435,7 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     // the group; stored: the tiles crossing the group boundary) and, for
     // stored records, the tiles inside the group
     const bool grouped = p.schedule == GABP_SCHED_GROUPED;
-    const int G = grouped ? std::min(p.sched_groups > 0 ? p.sched_groups : 4, NB) : 1;
+    const int G = grouped ? std::min(p.sched_groups > 0 ? p.sched_groups : 16, NB) : 1;
     std::vector<int64_t> g_within_off(G + 1, 0), g_dir_off(G + 1, 0), g_b0(G + 1, 0);
     if (grouped) {
         auto grp = [&](int I) { return (int)((int64_t)I * G / NB); };
