@@ -359,10 +359,17 @@ __device__ inline void frag_mma(const RowFrag<KIND, MP>& a, const RowFrag<KIND, 
 
 // K' = exp(-gamma d^2) + lambda^2 with d^2 = max(0, n_i + n_j - 2 G_ij), zero
 // for pairs that are not strictly upper (i >= j) or are padding (j >= N).
+// K' from a Gram entry: exp2 of the scaled, clamped distance on the
+// hardware exp2 (v_exp_f32; results below 2^-126 flush to zero, which the
+// lambda^2 added next absorbs), plus lambda^2.
+__device__ inline float kernel_value(float ni, float nj, float g, const KernelParams& kp) {
+    const float d2 = fmaxf(ni + nj - 2.0f * g, 0.0f);
+    return __builtin_amdgcn_exp2f(kp.neg_gamma_log2e * d2) + (float)kp.lam2;
+}
+// ... and zero outside the strict upper triangle and past N.
 __device__ inline float kernel_entry(float ni, float nj, float g, int64_t i, int64_t j,
                                      const KernelParams& kp) {
-    const float d2 = fmaxf(ni + nj - 2.0f * g, 0.0f);
-    const float kv = exp2f(kp.neg_gamma_log2e * d2) + (float)kp.lam2;
+    const float kv = kernel_value(ni, nj, g, kp);
     return (i < j && j < kp.N) ? kv : 0.0f;
 }
 
@@ -376,16 +383,24 @@ __device__ inline void gram_band(const Features& F, const KernelParams& kp, int 
     float ni[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) ni[r] = F.nrm[(int64_t)I * TILE + row0 + 8 * (r >> 2) + 4 * h + (r & 3)];
-#pragma unroll
+    // the index test matters only on diagonal tiles and in the last column block
+    const bool plain = (I < J) && ((int64_t)J * TILE + col0 + 64 <= kp.N);
+#pragma unroll 1
     for (int cb = 0; cb < 2; ++cb) {
         const int64_t colB = (int64_t)J * TILE + col0 + 32 * cb + l32;
         const f32x16 acc = mfma_gram_32x32<KIND>(F, rowA, colB);
         const float nj = F.nrm[colB];
+        if (plain) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int row = 8 * (r >> 2) + 4 * h + (r & 3);
-            kb[row * 64 + 32 * cb + l32] =
-                kernel_entry(ni[r], nj, acc[r], (int64_t)I * TILE + row0 + row, colB, kp);
+            for (int r = 0; r < 16; ++r)
+                kb[(8 * (r >> 2) + 4 * h + (r & 3)) * 64 + 32 * cb + l32] = kernel_value(ni[r], nj, acc[r], kp);
+        } else {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = 8 * (r >> 2) + 4 * h + (r & 3);
+                kb[row * 64 + 32 * cb + l32] =
+                    kernel_entry(ni[r], nj, acc[r], (int64_t)I * TILE + row0 + row, colB, kp);
+            }
         }
     }
 }

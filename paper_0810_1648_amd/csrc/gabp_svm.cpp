@@ -246,12 +246,24 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
         snprintf(msg, sizeof msg, "smallest allowed plan needs %.3f GB, budget %.3f GB", need_min / 1e9, budget / 1e9);
         return fail(h, GABP_E_NOMEM, msg);
     }
-    if (need > free_b) h->release_all();
     // AUTO edge state with room for stored planes: the choice between stored
     // and stateless waits for the contraction bound computed after the
     // diagonal weighting; the planes are allocated only if stored wins.
     const bool probe = stored && p.edge_state == GABP_EDGE_AUTO;
     const int R = (stored && !probe) ? 1 : 8;
+    {
+        // buffers of the previous solve are reused where large enough (a
+        // repeated solve of the same shape allocates nothing); everything is
+        // released first only when the large buffers that must grow do not
+        // fit in the free memory
+        auto grow = [](const DevBuf& b, size_t n) -> size_t { return (n == 0 || (b.p && b.bytes >= n)) ? 0 : n; };
+        const size_t ring = (size_t)R * NPAD * 8;
+        size_t extra = grow(h->Kp, kmat ? plane : 0) + 2 * grow(h->partP, part) + grow(h->Pt, ring) +
+                       grow(h->S, ring) + feat + vecs;
+        if (stored && !probe)
+            extra += grow(h->Pf, plane) + grow(h->Pb, plane) + grow(h->Ef, plane) + grow(h->Eb, plane);
+        if (extra > free_b) h->release_all();
+    }
     const int ksrc = kmat ? KSRC_PLANE : KSRC_RECOMPUTE;
 
     hipError_t ae = hipSuccess;
