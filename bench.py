@@ -29,6 +29,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 VALU_PEAK_GSLOT = 256 * 64 * 2.4
 # dense MFMA peaks (MI355X, no sparsity)
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}
+# K' of one pair recomputed inside the sweep, beyond the MFMA Gram: the
+# distance (norm sum, -2 g, clamp: 3), the scale (1), exp2 (a transcendental:
+# 4) and + lambda^2 (1)
+RECOMPUTE_SLOTS_PER_PAIR = 9
 # decision function, VALU slots per (query, training point) pair: distance
 # from the Gram (add, fma), clamp, scale, exp2 (a transcendental: 4 slots),
 # conversion to FP64 and the FP64 accumulation
@@ -367,8 +371,11 @@ def main():
     pairs = N * (N - 1) / 2.0
     stateless = plan["edge_state"] == gabp.EDGE["stateless"]
     traffic = counter_traffic(a.traffic_json, f"{wl.name}:{N}:{a.precision}:{plan['kstore']}:{plan['edge_state']}")
+    recompute = plan["kstore"] == gabp.KSTORE["recompute"]
     if stateless:
         slots = stateless_slots_per_pair(plan["stateless_depth"], int(plan["series_reciprocal"]), a.precision)
+        if recompute:
+            slots += RECOMPUTE_SLOTS_PER_PAIR
         achieved = slots * pairs / (avg_ms * 1e-3) / 1e9 if klaunch else None
         roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_GSLOT, "unit": "Gslot/s",
                 "frac": (achieved / VALU_PEAK_GSLOT) if achieved else None, "traffic": traffic,
@@ -379,6 +386,15 @@ def main():
                 "stateless_rho": plan["stateless_rho"],
                 "hbm_alg_bytes_per_launch": plan["alg_bytes_per_sweep"],
                 "hbm_frac": plan["alg_bytes_per_sweep"] / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if klaunch else None}
+        if recompute and klaunch:
+            # the Gram of every pair on MFMA, as issued (padded features, split products)
+            gname = {1: "bf16", 2: "bf16x3", 3: "bf16x6"}.get(plan["gram"], "f32")
+            products = {"bf16": 1, "bf16x3": 3, "bf16x6": 6, "f32": 1}[gname]
+            m_pad = (m + 15) // 16 * 16
+            mf = 2.0 * m_pad * products * pairs / (avg_ms * 1e-3) / 1e12
+            roof.update({"kstore": "recompute", "recompute_slots_per_pair": RECOMPUTE_SLOTS_PER_PAIR,
+                         "mfma_gram": gname, "mfma_issued_tflops": mf,
+                         "mfma_frac": mf / MFMA_PEAK_TFLOPS["f32" if gname == "f32" else "bf16"]})
     else:
         achieved = plan["alg_bytes_per_sweep"] / (avg_ms * 1e-3) / 1e9 if klaunch else None
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

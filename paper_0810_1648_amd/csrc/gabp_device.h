@@ -462,6 +462,12 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
     constexpr int DL = (D > 1) ? D - 1 : 1;   // lower levels held per node
     constexpr int NL = STORED ? 1 : DL;
     constexpr int NT = STORED ? 1 : TILE;
+    // series: S and u^2 only at the middle levels 1 .. D - 2, S/P~ only at
+    // the deepest level D - 1; exact reciprocals: S at every lower level
+    constexpr int NSL = SER ? ((D > 2) ? D - 2 : 1) : NL;
+    constexpr int NTS = (SER && D <= 2) ? 1 : NT;
+    constexpr int NTQ = (SER && D > 2) ? NT : 1;
+    constexpr int NTD = (SER && D >= 2) ? NT : 1;
     const uint32_t ij = a.tiles[tile];
     const TileCoord tc{(int)(ij >> 16), (int)(ij & 0xFFFFu)};
     const int NB = a.NB;
@@ -485,7 +491,7 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
 
     // row-node data: top level (P~ or, with SER, 1/P~) and lower levels
     __shared__ XT sPt[TILE], sS[TILE];
-    __shared__ LT sPtL[NL][NT], sSL[NL][NT], sSIL[SER ? NL : 1][SER ? NT : 1], sUQL[SER ? NL : 1][SER ? NT : 1];
+    __shared__ LT sPtL[NL][NT], sSL[NSL][NTS], sUQL[NSL][NTQ], sSIL[NTD];
     // row partials per wave strip (XF: FP32 sums of 64 messages; exact in AT)
     using RT = typename std::conditional<XF, XT, AT>::type;
     __shared__ RT rP[4][TILE], rE[4][TILE];
@@ -508,9 +514,10 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
         ptj[c] = SER ? (XT)inv_at(o) : (XT)HP[o];
         sj[c] = (XT)HS[o];
     }
-    // lower levels per node: P~ (exact) or u = 1/P~ (series), S, and for
-    // the series S/P~ (deepest level) and u^2 (middle levels)
-    LT ptjL[DL][4], sjL[DL][4], sijL[SER ? DL : 1][4], cuqL[SER ? DL : 1][4];
+    // lower levels per node: P~ (exact) or u = 1/P~ (series) at every level;
+    // exact: S at every level; series: S and u^2 at the middle levels, S/P~
+    // at the deepest
+    LT ptjL[DL][4], sjL[NSL][4], cuqL[NSL][4], sijL[4];
     if constexpr (!STORED) {
 #pragma unroll
         for (int k = 1; k < D; ++k) {
@@ -520,24 +527,32 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
                 if constexpr (SER) {
                     const AT u = inv_at(o);
                     sPtL[k - 1][tid] = (LT)u;
-                    sUQL[k - 1][tid] = (LT)(u * u);
-                    sSIL[k - 1][tid] = (LT)mean_at(o);
+                    if (k == D - 1) {
+                        sSIL[tid] = (LT)mean_at(o);
+                    } else {
+                        sUQL[k - 1][tid] = (LT)(u * u);
+                        sSL[k - 1][tid] = (LT)HS[o];
+                    }
                 } else {
                     sPtL[k - 1][tid] = (LT)HP[o];
+                    sSL[k - 1][tid] = (LT)HS[o];
                 }
-                sSL[k - 1][tid] = (LT)HS[o];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const int64_t o = base + (int64_t)tc.J * TILE + col0 + c;
                     if constexpr (SER) {
                         const AT u = inv_at(o);
                         ptjL[k - 1][c] = (LT)u;
-                        cuqL[k - 1][c] = (LT)(u * u);
-                        sijL[k - 1][c] = (LT)mean_at(o);
+                        if (k == D - 1) {
+                            sijL[c] = (LT)mean_at(o);
+                        } else {
+                            cuqL[k - 1][c] = (LT)(u * u);
+                            sjL[k - 1][c] = (LT)HS[o];
+                        }
                     } else {
                         ptjL[k - 1][c] = (LT)HP[o];
+                        sjL[k - 1][c] = (LT)HS[o];
                     }
-                    sjL[k - 1][c] = (LT)HS[o];
                 }
             }
         }
@@ -602,8 +617,8 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
                         if (kk == kd) {               // deepest level: reverse messages zero
                             gf = sPtL[kk - 1][r];
                             gb = ptjL[kk - 1][c];
-                            ff = -sSIL[kk - 1][r];
-                            fb = -sijL[kk - 1][c];
+                            ff = -sSIL[r];
+                            fb = -sijL[c];
                         } else if (kk < kd) {
                             const LT ngf = fma(-a2l * sUQL[kk - 1][r], gb, sPtL[kk - 1][r]);
                             const LT ngb = fma(-a2l * cuqL[kk - 1][c], gf, ptjL[kk - 1][c]);
@@ -731,6 +746,16 @@ template <class ST, class MT, class AT, int KSRC, int GK, int D, bool FIRST, int
 __global__ __launch_bounds__(WG) void k_sweep(SweepArgs a) {
     if (a.st->done) return;
     sweep_tile<ST, MT, AT, KSRC, GK, D, FIRST, SER>(a, blockIdx.x, a.slot_top);
+}
+
+// Stateless sweep with K' recomputed per band: the Gram fragments, the
+// band's K' (LDS) and the recursion's per-column state share the registers;
+// at least three waves per SIMD keep the band computations of some waves
+// overlapping the message steps of others.
+template <class ST, class MT, class AT, int GK, int D, int SER>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_sweep_rc(SweepArgs a) {
+    if (a.st->done) return;
+    sweep_tile<ST, MT, AT, KSRC_RECOMPUTE, GK, D, false, SER>(a, blockIdx.x, a.slot_top);
 }
 
 // ------------------------------------------------ grouped (Gauss-Seidel) --
@@ -1125,7 +1150,10 @@ inline void sweep_d(bool first, const SweepArgs& a, hipStream_t s) {
             return;
         }
     }
-    hipLaunchKernelGGL((k_sweep<ST, MT, AT, KSRC, GK, D, false, SER>), g, blk, 0, s, a);
+    if constexpr (KSRC == KSRC_RECOMPUTE && D >= 1)
+        hipLaunchKernelGGL((k_sweep_rc<ST, MT, AT, GK, D, SER>), g, blk, 0, s, a);
+    else
+        hipLaunchKernelGGL((k_sweep<ST, MT, AT, KSRC, GK, D, false, SER>), g, blk, 0, s, a);
 }
 
 // `levels` = 0: stored edge state; >= 1: stateless with exactly that many
