@@ -131,6 +131,126 @@ __global__ __launch_bounds__(WG) void k_predict_mfma(Features Ft, Features Fq, c
     }
 }
 
+// BF16 Gram kinds with m_pad <= MP: the workgroup's four waves share every
+// 32-row training block, so the block's B fragments (all split planes) are
+// staged once in LDS, in fragment order (chunk (plane, step, lane) holds the
+// 16 bytes lane `lane` feeds the MFMA at k-step `step`), together with the
+// block's norms and weights.  The next block's chunks are loaded into
+// registers while the current block is multiplied, then stored into the
+// other buffer (one barrier per block).  A workgroup covers at most eight
+// training blocks (the chunk): each lane sums its training points' terms in
+// FP32 (at most eight per query), then the 32 training lanes are added in
+// FP64.
+template <int KIND, int MP>
+__global__ __launch_bounds__(WG) void k_predict_lds(Features Ft, Features Fq, const double* __restrict__ w,
+                                                    int64_t nblk32, int bpc, float neg_gamma_log2e,
+                                                    int64_t NQPAD, double* __restrict__ part) {
+    constexpr int NP = (KIND == GRAM_BF16X6) ? 3 : (KIND == GRAM_BF16X3) ? 2 : 1;   // split planes
+    constexpr int NS = MP / 16;                                                       // k-steps
+    constexpr int CH = NP * NS * 64;                                                  // 16-byte chunks
+    constexpr int PR = (CH + WG - 1) / WG;                                            // per thread
+    __shared__ bf16x8 sb[2][CH];
+    __shared__ float snj[2][32];
+    __shared__ double swj[2][32];
+    const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63, h = l >> 5, l32 = l & 31;
+    const int mp = Fq.m_pad, ns = mp / 16, ch = NP * ns * 64;
+    const int64_t q0 = (int64_t)blockIdx.x * QB + wv * 32;
+    const int64_t rowA = q0 + l32;
+    float ni[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) ni[r] = Fq.nrm[q0 + 8 * (r >> 2) + 4 * h + (r & 3)];
+    RowFrag<KIND, MP> qa;
+    qa.load(Fq, rowA);
+    float accf[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) accf[r] = 0.0f;
+    const int64_t b0 = (int64_t)blockIdx.y * bpc;
+    const int64_t b1 = (b0 + bpc < nblk32) ? b0 + bpc : nblk32;
+    // chunk k of block b: plane k / (64 ns), row and 16-byte column of the
+    // row-major features; its fragment-order slot
+    auto chunk_src = [&](int64_t b, int k) -> const bf16x8* {
+        const int pl = k / (64 * ns), rem = k - pl * 64 * ns, row = rem / (2 * ns), cc = rem - row * 2 * ns;
+        const uint16_t* base = (pl == 0) ? Ft.hi : (pl == 1) ? Ft.lo : Ft.lo2;
+        return reinterpret_cast<const bf16x8*>(base + (b * 32 + row) * mp + 8 * cc);
+    };
+    auto chunk_dst = [&](int k) -> int {
+        const int pl = k / (64 * ns), rem = k - pl * 64 * ns, row = rem / (2 * ns), cc = rem - row * 2 * ns;
+        return (pl * ns + (cc >> 1)) * 64 + (cc & 1) * 32 + row;
+    };
+    if (b0 < b1) {
+#pragma unroll
+        for (int i = 0; i < PR; ++i) {
+            const int k = tid + WG * i;
+            if (k < ch) sb[0][chunk_dst(k)] = *chunk_src(b0, k);
+        }
+        if (tid < 32) { snj[0][tid] = Ft.nrm[b0 * 32 + tid]; swj[0][tid] = w[b0 * 32 + tid]; }
+    }
+    __syncthreads();
+    for (int64_t b = b0; b < b1; ++b) {
+        const int cur = (int)((b - b0) & 1);
+        const bool more = b + 1 < b1;
+        bf16x8 pre[PR];
+        float pn = 0.0f;
+        double pw = 0.0;
+        if (more) {
+#pragma unroll
+            for (int i = 0; i < PR; ++i) {
+                const int k = tid + WG * i;
+                if (k < ch) pre[i] = *chunk_src(b + 1, k);
+            }
+            if (tid < 32) { pn = Ft.nrm[(b + 1) * 32 + tid]; pw = w[(b + 1) * 32 + tid]; }
+        }
+        // the products of frag_mma, step by step with B read from LDS
+        f32x16 g = {};
+#pragma unroll
+        for (int st = 0; st < NS; ++st) {
+            if (st >= ns) continue;
+            const bf16x8 bh = sb[cur][(0 * ns + st) * 64 + l];
+            if constexpr (NP >= 2) {
+                const bf16x8 bl = sb[cur][(1 * ns + st) * 64 + l];
+                if constexpr (NP >= 3) {
+                    const bf16x8 bl2 = sb[cur][(2 * ns + st) * 64 + l];
+                    g = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa.hi[st], bl2, g, 0, 0, 0);
+                    g = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa.lo2[st], bh, g, 0, 0, 0);
+                    g = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa.lo[st], bl, g, 0, 0, 0);
+                }
+                g = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa.hi[st], bl, g, 0, 0, 0);
+                g = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa.lo[st], bh, g, 0, 0, 0);
+            }
+            g = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa.hi[st], bh, g, 0, 0, 0);
+        }
+        const float nj = snj[cur][l32];
+        const float wj = (float)swj[cur][l32];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const float d2 = fmaxf(ni[r] + nj - 2.0f * g[r], 0.0f);
+            accf[r] = fmaf(__builtin_amdgcn_exp2f(neg_gamma_log2e * d2), wj, accf[r]);
+        }
+        if (more) {
+#pragma unroll
+            for (int i = 0; i < PR; ++i) {
+                const int k = tid + WG * i;
+                if (k < ch) sb[cur ^ 1][chunk_dst(k)] = pre[i];
+            }
+            if (tid < 32) { snj[cur ^ 1][tid] = pn; swj[cur ^ 1][tid] = pw; }
+        }
+        __syncthreads();
+    }
+    // sum over the 32 training rows held by lanes l % 32 of each half
+    double acc[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        double v = sum16((double)accf[r]);
+        v = v + __shfl_xor(v, 16);
+        acc[r] = v;
+    }
+    if (l32 == 0) {
+        double* out = part + (int64_t)blockIdx.y * NQPAD + q0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) out[8 * (r >> 2) + 4 * h + (r & 3)] = acc[r];
+    }
+}
+
 // f_q = sum over chunks (in order) of part[c][q] + lambda^2 sum_i w_i.
 __global__ void k_predict_reduce(const double* __restrict__ part, int nchunk, int64_t stride, int64_t nq,
                                  const double* __restrict__ wsum, double lam2, double* __restrict__ f) {
@@ -144,6 +264,16 @@ __global__ void k_predict_reduce(const double* __restrict__ part, int nchunk, in
 template <int KIND>
 void predict_kind(int mp, dim3 grid, const Features& Ft, const Features& Fq, const double* w, int64_t nblk32,
                   int bpc, float c, int64_t NQPAD, double* part, hipStream_t s) {
+    if constexpr (KIND != GRAM_F32) {
+        if (mp <= 32) {
+            hipLaunchKernelGGL((k_predict_lds<KIND, 32>), grid, dim3(WG), 0, s, Ft, Fq, w, nblk32, bpc, c, NQPAD, part);
+            return;
+        }
+        if (mp <= 64) {
+            hipLaunchKernelGGL((k_predict_lds<KIND, 64>), grid, dim3(WG), 0, s, Ft, Fq, w, nblk32, bpc, c, NQPAD, part);
+            return;
+        }
+    }
     if (mp <= 32)
         hipLaunchKernelGGL((k_predict_mfma<KIND, 32>), grid, dim3(WG), 0, s, Ft, Fq, w, nblk32, bpc, c, NQPAD, part);
     else if (mp <= 64)
@@ -162,8 +292,10 @@ int64_t predict_query_pad(int64_t nq) { return (nq + QB - 1) / QB * QB; }
 
 void predict_chunks(int64_t NPAD, int64_t NQPAD, int* nchunk, int* bpc) {
     const int64_t nblk32 = NPAD / 32, nqb = NQPAD / QB;
-    // enough workgroups to fill the chip several times over
+    // at most eight training blocks per workgroup (the FP32 partial sums of
+    // the staged kernel), and enough workgroups to fill the chip
     int64_t want = (4096 + nqb - 1) / nqb;
+    want = std::max<int64_t>(want, (nblk32 + 7) / 8);
     want = std::max<int64_t>(1, std::min<int64_t>(want, nblk32));
     const int64_t per = (nblk32 + want - 1) / want;
     *bpc = (int)per;

@@ -246,9 +246,30 @@ __global__ __launch_bounds__(WG) void k_sp_gather(int64_t N, const int64_t* __re
     AT p = 0, e = 0;
     if (k < N) {
         const int64_t a0 = off_i[k], a1 = off_i[k + 1];
-        for (int64_t t = a0 + q; t < a1; t += 16) { p += (AT)RB[2 * t]; e += (AT)RB[2 * t + 1]; }
+        int64_t u = a0 + q;
+        for (; u + 48 < a1; u += 64) {
+            const ST p0 = RB[2 * u], e0 = RB[2 * u + 1], p1 = RB[2 * u + 32], e1 = RB[2 * u + 33];
+            const ST p2 = RB[2 * u + 64], e2 = RB[2 * u + 65], p3 = RB[2 * u + 96], e3 = RB[2 * u + 97];
+            p += (AT)p0; e += (AT)e0;
+            p += (AT)p1; e += (AT)e1;
+            p += (AT)p2; e += (AT)e2;
+            p += (AT)p3; e += (AT)e3;
+        }
+        for (; u < a1; u += 16) { p += (AT)RB[2 * u]; e += (AT)RB[2 * u + 1]; }
         const int64_t b0 = off_j[k], b1 = off_j[k + 1];
-        for (int64_t t = b0 + q; t < b1; t += 16) {
+        // four edge ids, then their four records, in flight at once; the
+        // additions keep the edge order
+        int64_t t = b0 + q;
+        for (; t + 48 < b1; t += 64) {
+            const int64_t x0 = perm[t], x1 = perm[t + 16], x2 = perm[t + 32], x3 = perm[t + 48];
+            const ST p0 = RF[2 * x0], e0 = RF[2 * x0 + 1], p1 = RF[2 * x1], e1 = RF[2 * x1 + 1];
+            const ST p2 = RF[2 * x2], e2 = RF[2 * x2 + 1], p3 = RF[2 * x3], e3 = RF[2 * x3 + 1];
+            p += (AT)p0; e += (AT)e0;
+            p += (AT)p1; e += (AT)e1;
+            p += (AT)p2; e += (AT)e2;
+            p += (AT)p3; e += (AT)e3;
+        }
+        for (; t < b1; t += 16) {
             const int64_t x = perm[t];
             p += (AT)RF[2 * x];
             e += (AT)RF[2 * x + 1];
