@@ -28,8 +28,11 @@ namespace {
 // fragment loaded once for both) and walks the eight 32-column blocks.  For
 // every block, `visit(k0, k1, i0r, jcol, d2a, d2b)` receives the ballots of
 // kept pairs of both bands per output register (k0[r], k1[r]) and the
-// distances; blocks without any kept pair cost one ballot per register.
-// The keep test is one explicit FMA and a compare, identical in every pass.
+// distances (formed only where the visitor uses them); blocks without any
+// kept pair cost one ballot per register.  The keep test
+// d^2 = n_i + n_j - 2 g <= cut is evaluated as 2 g - n_i >= n_j - cut: one
+// explicit FMA and the compare that forms the ballot, identical in every
+// pass.
 template <int KIND, int MP, class Visit>
 __device__ inline void sp_tile(const Features& F, const TileCoord& tc, int64_t N, float cut, Visit&& visit) {
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6, h = l >> 5, l32 = l & 31;
@@ -62,7 +65,7 @@ __device__ inline void sp_tile(const Features& F, const TileCoord& tc, int64_t N
         } else {
             RowFrag<KIND, MP>::gram2(fa0, fa1, F, rowA0, rowA1, F, j, g0, g1);
         }
-        const float nj = F.nrm[j];
+        const float nj = F.nrm[j], cj = nj - cut;
         // the index tests matter only on diagonal tiles and in the last column block
         const bool plain = (tc.I < tc.J) && (j0 + cb * 32 + 31 < N);
         uint64_t k0[16], k1[16], any = 0;
@@ -73,8 +76,8 @@ __device__ inline void sp_tile(const Features& F, const TileCoord& tc, int64_t N
             const int64_t ib = ia + 128;
             d0[r] = fmaxf(fmaf(-2.0f, g0[r], ni0[r] + nj), 0.0f);
             d1[r] = fmaxf(fmaf(-2.0f, g1[r], ni1[r] + nj), 0.0f);
-            const bool c0 = d0[r] <= cut && (plain || (ia < j && j < N));
-            const bool c1 = d1[r] <= cut && (plain || (ib < j && j < N));
+            const bool c0 = fmaf(2.0f, g0[r], -ni0[r]) >= cj && (plain || (ia < j && j < N));
+            const bool c1 = fmaf(2.0f, g1[r], -ni1[r]) >= cj && (plain || (ib < j && j < N));
             k0[r] = __ballot(c0);
             k1[r] = __ballot(c1);
             any |= k0[r] | k1[r];
@@ -135,7 +138,7 @@ __global__ __launch_bounds__(WG) void k_sp_fill(Features F, const uint32_t* __re
                     const float d2 = half ? d1[r] : d0[r];
                     if (slot < cap) {
                         keys[base + slot] = ((uint64_t)i << 32) | (uint64_t)j;
-                        kv[base + slot] = exp2f(neg_gamma_log2e * d2) + lam2;
+                        kv[base + slot] = __builtin_amdgcn_exp2f(neg_gamma_log2e * d2) + lam2;
                     } else {
                         atomicOr(flag, 1);
                     }
