@@ -357,6 +357,48 @@ __device__ inline void frag_mma(const RowFrag<KIND, MP>& a, const RowFrag<KIND, 
     }
 }
 
+// B fragments of a 32-row block staged in LDS (BF16 splits), shared by the
+// waves of a workgroup.  Chunk k of a block (k < planes x 64 x ns, ns =
+// m_pad / 16) is 16 bytes of one staged row: plane k / (64 ns), row and
+// 16-byte column of the row-major features, so that consecutive threads load
+// consecutive bytes; its slot is the fragment order (plane, k-step, lane),
+// lane = 32 (column / 2 parity) + row, so that a wave reads the operand of
+// k-step s as 64 consecutive chunks.
+template <int KIND> struct BStage {
+    static constexpr int NP = (KIND == GRAM_BF16X6) ? 3 : (KIND == GRAM_BF16X3) ? 2 : 1;
+    __device__ static const bf16x8* src(const Features& F, int64_t row0, int ns, int k) {
+        const int pl = k / (64 * ns), rem = k - pl * 64 * ns, row = rem / (2 * ns), cc = rem - row * 2 * ns;
+        const uint16_t* base = (pl == 0) ? F.hi : (pl == 1) ? F.lo : F.lo2;
+        return reinterpret_cast<const bf16x8*>(base + (row0 + row) * F.m_pad + 8 * cc);
+    }
+    __device__ static int dst(int ns, int k) {
+        const int pl = k / (64 * ns), rem = k - pl * 64 * ns, row = rem / (2 * ns), cc = rem - row * 2 * ns;
+        return (pl * ns + (cc >> 1)) * 64 + (cc & 1) * 32 + row;
+    }
+    // acc += A B^T with A in registers and B staged at sb (the products of
+    // frag_mma, in its order)
+    template <int MP>
+    __device__ static void mma(const RowFrag<KIND, MP>& a, const bf16x8* sb, int ns, int l, f32x16& acc) {
+#pragma unroll
+        for (int st = 0; st < MP / 16; ++st) {
+            if (st >= ns) continue;
+            const bf16x8 bh = sb[(0 * ns + st) * 64 + l];
+            if constexpr (NP >= 2) {
+                const bf16x8 bl = sb[(1 * ns + st) * 64 + l];
+                if constexpr (NP >= 3) {
+                    const bf16x8 bl2 = sb[(2 * ns + st) * 64 + l];
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.hi[st], bl2, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.lo2[st], bh, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.lo[st], bl, acc, 0, 0, 0);
+                }
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.hi[st], bl, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.lo[st], bh, acc, 0, 0, 0);
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.hi[st], bh, acc, 0, 0, 0);
+        }
+    }
+};
+
 // K' = exp(-gamma d^2) + lambda^2 with d^2 = max(0, n_i + n_j - 2 G_ij), zero
 // for pairs that are not strictly upper (i >= j) or are padding (j >= N).
 // K' from a Gram entry: exp2 of the scaled, clamped distance on the

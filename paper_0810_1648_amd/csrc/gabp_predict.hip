@@ -145,7 +145,8 @@ template <int KIND, int MP>
 __global__ __launch_bounds__(WG) void k_predict_lds(Features Ft, Features Fq, const double* __restrict__ w,
                                                     int64_t nblk32, int bpc, float neg_gamma_log2e,
                                                     int64_t NQPAD, double* __restrict__ part) {
-    constexpr int NP = (KIND == GRAM_BF16X6) ? 3 : (KIND == GRAM_BF16X3) ? 2 : 1;   // split planes
+    using BS = BStage<KIND>;
+    constexpr int NP = BS::NP;                                                        // split planes
     constexpr int NS = MP / 16;                                                       // k-steps
     constexpr int CH = NP * NS * 64;                                                  // 16-byte chunks
     constexpr int PR = (CH + WG - 1) / WG;                                            // per thread
@@ -166,22 +167,11 @@ __global__ __launch_bounds__(WG) void k_predict_lds(Features Ft, Features Fq, co
     for (int r = 0; r < 16; ++r) accf[r] = 0.0f;
     const int64_t b0 = (int64_t)blockIdx.y * bpc;
     const int64_t b1 = (b0 + bpc < nblk32) ? b0 + bpc : nblk32;
-    // chunk k of block b: plane k / (64 ns), row and 16-byte column of the
-    // row-major features; its fragment-order slot
-    auto chunk_src = [&](int64_t b, int k) -> const bf16x8* {
-        const int pl = k / (64 * ns), rem = k - pl * 64 * ns, row = rem / (2 * ns), cc = rem - row * 2 * ns;
-        const uint16_t* base = (pl == 0) ? Ft.hi : (pl == 1) ? Ft.lo : Ft.lo2;
-        return reinterpret_cast<const bf16x8*>(base + (b * 32 + row) * mp + 8 * cc);
-    };
-    auto chunk_dst = [&](int k) -> int {
-        const int pl = k / (64 * ns), rem = k - pl * 64 * ns, row = rem / (2 * ns), cc = rem - row * 2 * ns;
-        return (pl * ns + (cc >> 1)) * 64 + (cc & 1) * 32 + row;
-    };
     if (b0 < b1) {
 #pragma unroll
         for (int i = 0; i < PR; ++i) {
             const int k = tid + WG * i;
-            if (k < ch) sb[0][chunk_dst(k)] = *chunk_src(b0, k);
+            if (k < ch) sb[0][BS::dst(ns, k)] = *BS::src(Ft, b0 * 32, ns, k);
         }
         if (tid < 32) { snj[0][tid] = Ft.nrm[b0 * 32 + tid]; swj[0][tid] = w[b0 * 32 + tid]; }
     }
@@ -196,29 +186,12 @@ __global__ __launch_bounds__(WG) void k_predict_lds(Features Ft, Features Fq, co
 #pragma unroll
             for (int i = 0; i < PR; ++i) {
                 const int k = tid + WG * i;
-                if (k < ch) pre[i] = *chunk_src(b + 1, k);
+                if (k < ch) pre[i] = *BS::src(Ft, (b + 1) * 32, ns, k);
             }
             if (tid < 32) { pn = Ft.nrm[(b + 1) * 32 + tid]; pw = w[(b + 1) * 32 + tid]; }
         }
-        // the products of frag_mma, step by step with B read from LDS
         f32x16 g = {};
-#pragma unroll
-        for (int st = 0; st < NS; ++st) {
-            if (st >= ns) continue;
-            const bf16x8 bh = sb[cur][(0 * ns + st) * 64 + l];
-            if constexpr (NP >= 2) {
-                const bf16x8 bl = sb[cur][(1 * ns + st) * 64 + l];
-                if constexpr (NP >= 3) {
-                    const bf16x8 bl2 = sb[cur][(2 * ns + st) * 64 + l];
-                    g = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa.hi[st], bl2, g, 0, 0, 0);
-                    g = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa.lo2[st], bh, g, 0, 0, 0);
-                    g = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa.lo[st], bl, g, 0, 0, 0);
-                }
-                g = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa.hi[st], bl, g, 0, 0, 0);
-                g = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa.lo[st], bh, g, 0, 0, 0);
-            }
-            g = __builtin_amdgcn_mfma_f32_32x32x16_bf16(qa.hi[st], bh, g, 0, 0, 0);
-        }
+        BS::template mma<MP>(qa, sb[cur], ns, l, g);
         const float nj = snj[cur][l32];
         const float wj = (float)swj[cur][l32];
 #pragma unroll
@@ -230,7 +203,7 @@ __global__ __launch_bounds__(WG) void k_predict_lds(Features Ft, Features Fq, co
 #pragma unroll
             for (int i = 0; i < PR; ++i) {
                 const int k = tid + WG * i;
-                if (k < ch) sb[cur ^ 1][chunk_dst(k)] = pre[i];
+                if (k < ch) sb[cur ^ 1][BS::dst(ns, k)] = pre[i];
             }
             if (tid < 32) { snj[cur ^ 1][tid] = pn; swj[cur ^ 1][tid] = pw; }
         }
