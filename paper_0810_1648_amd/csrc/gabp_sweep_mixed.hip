@@ -1,6 +1,7 @@
-// Sweep instantiations of the MIXED (BF16 Gram, FP32 storage, FP64 top level and aggregates) path: stored pair records, or
-// stateless with 1..8 levels (1..6 with series reciprocals), over the
-// materialised or recomputed K'.
+// Sweep instantiations of the MIXED path (BF16 Gram, FP32 storage, FP64
+// aggregates; messages in FP64 with exact reciprocals, in FP32 with series
+// reciprocals): stored pair records, or stateless with 1..8 levels (1..6
+// with series reciprocals), over the materialised or recomputed K'.
 #include "gabp_device.h"
 
 namespace gabp {

@@ -503,3 +503,32 @@ def test_box_projected_solution_is_the_qp_optimum(torch, name, seed, q, kw):
     n_lo, n_hi = int(np.sum(h <= 0.0)), int(np.sum(h >= C))
     print(f"box {name} {kw}: {s.sweeps()} sweeps, at 0: {n_lo}, at C: {n_hi}, rel err vs QP {err:.2e}")
     assert st == gabp.OK and err <= TOL and n_lo + n_hi > 0
+
+
+@pytest.mark.parametrize("edge", ["stored", "stateless"])
+def test_repeated_solves_on_one_handle_reuse_buffers(torch, edge):
+    """A handle keeps its device buffers between solves and reuses them when
+    they are large enough: the same problem twice, a smaller one after it and
+    the larger one again all give bitwise the alpha of a fresh handle."""
+    X1, y1 = inputs.blobs(1100, 16, 501)
+    X2, y2 = inputs.blobs(600, 16, 502)
+    kw = dict(gamma=1.0 / 16, C=1.0, precision="mixed", tol_rel=1e-7, edge_state=edge, kstore="materialise")
+    print(f"[case] repeated solves, {edge} edges", flush=True)
+
+    def fresh(X, y):
+        s = gabp.GabpSVM(**kw)
+        assert s.solve(X, y) == gabp.OK
+        a = s.alpha()
+        s.close()
+        return a
+
+    ref1, ref2 = fresh(X1, y1), fresh(X2, y2)
+    s = gabp.GabpSVM(**kw)
+    held = []
+    for X, y, ref in ((X1, y1, ref1), (X1, y1, ref1), (X2, y2, ref2), (X1, y1, ref1)):
+        assert s.solve(X, y) == gabp.OK
+        assert np.array_equal(s.alpha(), ref)
+        held.append(s.plan()["device_bytes"])
+    s.close()
+    # the second solve of the same shape holds what the first held
+    assert held[1] == held[0]
