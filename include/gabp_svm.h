@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define GABP_ABI_VERSION 5
+#define GABP_ABI_VERSION 6
 
 /* Opaque solver handle; owns every device buffer it allocates. */
 typedef struct gabp_svm gabp_svm;
@@ -172,7 +172,12 @@ typedef struct gabp_svm_params {
     int32_t sched_groups;      /* GROUPED: number of node groups (whole
                                   256-point blocks, at most the block
                                   count); 0 = 16 */
-    int32_t reserved;
+    int32_t sparse_edges_hint; /* RBF_SPARSE: expected number of kept pairs,
+                                  >= 0; it sizes the edge list that the
+                                  build's single pass over the tiles fills
+                                  (0 = estimated from every 32nd tile).  A
+                                  hint below the true number costs a second
+                                  pass; the graph is the same either way */
     double sparse_tau;         /* RBF_SPARSE: kernel threshold in (0, 1] */
 } gabp_svm_params;
 

@@ -223,11 +223,14 @@ hipError_t launch_sweep_grouped_f64(int ksrc, int gram, int levels, int ser, con
 // Sparsified kernel (gabp_sparse.hip): build passes, sorts and scans (the
 // temporary storage size comes back in *bytes when tmp is NULL), and the
 // sweep (edge update + per-node gather into one partial per node).
-hipError_t launch_sp_count(const Features& F, const uint32_t* tiles, int64_t ntiles, int64_t N, float cut,
-                           int32_t* counts, hipStream_t s);
+// count: kept pairs of tiles[0], tiles[stride], ... (ntiles launched);
+// fill: every listed tile's kept pairs appended at *cursor (slots >= cap
+// counted, not written).
+hipError_t launch_sp_count(const Features& F, const uint32_t* tiles, int64_t ntiles, int64_t stride, int64_t N,
+                           float cut, int32_t* counts, hipStream_t s);
 hipError_t launch_sp_fill(const Features& F, const uint32_t* tiles, int64_t ntiles, int64_t N, float cut,
-                          float neg_gamma_log2e, float lam2, const int64_t* offsets, const int32_t* counts,
-                          uint64_t* keys, float* kv, int32_t* flag, hipStream_t s);
+                          float neg_gamma_log2e, float lam2, int64_t cap, unsigned long long* cursor, uint64_t* keys,
+                          float* kv, hipStream_t s);
 hipError_t sp_scan(void* tmp, size_t* bytes, const int32_t* in, int64_t* out, int64_t n, hipStream_t s);
 // Locality order: nearest of the K landmark points lm[] for every point
 // (key = landmark << 32 | point, ids = point), rows permuted into that order,

@@ -5,9 +5,11 @@
 // with N(i) the kept neighbours); the pair records live in edge order.
 //
 // Build (every pair is examined once, on MFMA, as for the dense K'):
-//   k_sp_count  per 256 x 256 tile: kept pairs i < j;
-//   k_sp_fill   per tile: 64-bit keys (i << 32 | j) and K' at the tile's
-//               offset (order inside a tile is arbitrary);
+//   k_sp_count  kept pairs i < j of a strided sample of the tiles: an
+//               estimate that sizes the fill's output;
+//   k_sp_fill   per tile: 64-bit keys (i << 32 | j) and K' appended at a
+//               global cursor (arbitrary order); a second pass runs only if
+//               the estimate fell short;
 //   radix sort of the keys: edges in (i, j) order, so every node's edges
 //   with the node as i-end are contiguous; a second sort by (j, i) gives
 //   the permutation listing each node's edges as j-end.
@@ -87,11 +89,14 @@ __device__ inline void sp_tile(const Features& F, const TileCoord& tc, int64_t N
     }
 }
 
+// Kept pairs of every stride-th listed tile (stride 1: all of them), one
+// count per launched tile; the host sums a strided sample to size the fill.
 template <int KIND, int MP>
-__global__ __launch_bounds__(WG) void k_sp_count(Features F, const uint32_t* __restrict__ tiles, int64_t N,
-                                                 float cut, int32_t* __restrict__ counts) {
+__global__ __launch_bounds__(WG) void k_sp_count(Features F, const uint32_t* __restrict__ tiles, int64_t stride,
+                                                 int64_t N, float cut, int32_t* __restrict__ counts) {
     __shared__ int wsum[4];
-    const TileCoord tc = tile_of(tiles);
+    const uint32_t ij = tiles[(int64_t)blockIdx.x * stride];
+    const TileCoord tc{(int)(ij >> 16), (int)(ij & 0xFFFFu)};
     int c = 0;   // wave-uniform
     sp_tile<KIND, MP>(F, tc, N, cut, [&](const uint64_t* k0, const uint64_t* k1, int64_t, int64_t, const float*,
                                          const float*) {
@@ -103,51 +108,49 @@ __global__ __launch_bounds__(WG) void k_sp_count(Features F, const uint32_t* __r
     if (threadIdx.x == 0) counts[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
-// Writes never leave the tile's range [offsets[t], offsets[t] + counts[t]);
-// a pass that keeps a different number of pairs than the count pass sets
-// *flag (the host then stops with an error instead of using the graph).
+// Kept pairs appended at a global cursor: one atomic per wave and 32-column
+// block with kept pairs reserves the block's slots, and a kept lane takes
+// the block's base plus the kept pairs before it (register by register, then
+// lane order).  The order across blocks, waves and tiles is arbitrary: the
+// (i, j) sort that follows fixes it, and every pair's key and K' value do
+// not depend on it.  Slots at or beyond cap are not written but still
+// counted, so the cursor ends at the exact number of kept pairs and the host
+// repeats the pass with room for all of them.
 template <int KIND, int MP>
 __global__ __launch_bounds__(WG) void k_sp_fill(Features F, const uint32_t* __restrict__ tiles, int64_t N,
-                                                float cut, float neg_gamma_log2e, float lam2,
-                                                const int64_t* __restrict__ offsets,
-                                                const int32_t* __restrict__ counts, uint64_t* __restrict__ keys,
-                                                float* __restrict__ kv, int32_t* __restrict__ flag) {
-    __shared__ int cursor;
+                                                float cut, float neg_gamma_log2e, float lam2, int64_t cap,
+                                                unsigned long long* __restrict__ cursor,
+                                                uint64_t* __restrict__ keys, float* __restrict__ kv) {
     const TileCoord tc = tile_of(tiles);
-    if (threadIdx.x == 0) cursor = 0;
-    __syncthreads();
-    const int64_t base = offsets[blockIdx.x];
-    const int cap = counts[blockIdx.x];
     const int l = threadIdx.x & 63, h = l >> 5;
+    const uint64_t below = (1ull << l) - 1ull;
     sp_tile<KIND, MP>(F, tc, N, cut, [&](const uint64_t* k0, const uint64_t* k1, int64_t ib, int64_t j,
                                          const float* d0, const float* d1) {
-        // per register with kept pairs: one LDS atomic for the wave, kept
-        // lanes take consecutive slots in lane order
+        unsigned long long tot = 0;   // wave-uniform
+#pragma unroll
+        for (int r = 0; r < 16; ++r) tot += __popcll(k0[r]) + __popcll(k1[r]);
+        unsigned long long first = 0;
+        if (l == 0) first = atomicAdd(cursor, tot);
+        int64_t pos = (int64_t)__shfl(first, 0);
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const uint64_t mask = half ? k1[r] : k0[r];
                 if (mask == 0) continue;
-                int first = 0;
-                if (l == 0) first = atomicAdd(&cursor, __popcll(mask));
-                first = __shfl(first, 0);
                 if ((mask >> l) & 1ull) {
-                    const int slot = first + __popcll(mask & ((1ull << l) - 1ull));
-                    const int64_t i = ib + 128 * half + 8 * (r >> 2) + 4 * h + (r & 3);
-                    const float d2 = half ? d1[r] : d0[r];
+                    const int64_t slot = pos + __popcll(mask & below);
                     if (slot < cap) {
-                        keys[base + slot] = ((uint64_t)i << 32) | (uint64_t)j;
-                        kv[base + slot] = __builtin_amdgcn_exp2f(neg_gamma_log2e * d2) + lam2;
-                    } else {
-                        atomicOr(flag, 1);
+                        const int64_t i = ib + 128 * half + 8 * (r >> 2) + 4 * h + (r & 3);
+                        const float d2 = half ? d1[r] : d0[r];
+                        keys[slot] = ((uint64_t)i << 32) | (uint64_t)j;
+                        kv[slot] = __builtin_amdgcn_exp2f(neg_gamma_log2e * d2) + lam2;
                     }
                 }
+                pos += __popcll(mask);
             }
         }
     });
-    __syncthreads();
-    if (threadIdx.x == 0 && cursor != cap) atomicOr(flag, 2);
 }
 
 // i, j of every sorted edge; node degrees as i-end and as j-end.
@@ -394,16 +397,16 @@ __global__ void k_sp_unpermute(const double* __restrict__ in, const int32_t* __r
 }
 
 template <int KIND>
-void sp_build_kind(bool fill, int mp, dim3 g, const Features& F, const uint32_t* tiles, int64_t N, float cut,
-                   float c, float lam2, int32_t* counts, const int64_t* offsets, uint64_t* keys, float* kv,
-                   int32_t* flag, hipStream_t s) {
+void sp_build_kind(bool fill, int mp, dim3 g, const Features& F, const uint32_t* tiles, int64_t stride, int64_t N,
+                   float cut, float c, float lam2, int32_t* counts, int64_t cap, unsigned long long* cursor,
+                   uint64_t* keys, float* kv, hipStream_t s) {
 #define GABP_SP_LAUNCH(MPV)                                                                                  \
     do {                                                                                                     \
         if (fill)                                                                                            \
-            hipLaunchKernelGGL((k_sp_fill<KIND, MPV>), g, dim3(WG), 0, s, F, tiles, N, cut, c, lam2, offsets, \
-                               counts, keys, kv, flag);                                                      \
+            hipLaunchKernelGGL((k_sp_fill<KIND, MPV>), g, dim3(WG), 0, s, F, tiles, N, cut, c, lam2, cap,     \
+                               cursor, keys, kv);                                                            \
         else                                                                                                 \
-            hipLaunchKernelGGL((k_sp_count<KIND, MPV>), g, dim3(WG), 0, s, F, tiles, N, cut, counts);        \
+            hipLaunchKernelGGL((k_sp_count<KIND, MPV>), g, dim3(WG), 0, s, F, tiles, stride, N, cut, counts); \
     } while (0)
     // register-held fragments of two bands plus the prefetched B fragment
     // fit up to 64 features; beyond, fragments are reloaded per block
@@ -413,15 +416,15 @@ void sp_build_kind(bool fill, int mp, dim3 g, const Features& F, const uint32_t*
 #undef GABP_SP_LAUNCH
 }
 
-hipError_t sp_build(bool fill, const Features& F, const uint32_t* tiles, int64_t ntiles, int64_t N, float cut,
-                    float c, float lam2, int32_t* counts, const int64_t* offsets, uint64_t* keys, float* kv,
-                    int32_t* flag, hipStream_t s) {
+hipError_t sp_build(bool fill, const Features& F, const uint32_t* tiles, int64_t ntiles, int64_t stride, int64_t N,
+                    float cut, float c, float lam2, int32_t* counts, int64_t cap, unsigned long long* cursor,
+                    uint64_t* keys, float* kv, hipStream_t s) {
     const dim3 g((unsigned)ntiles);
     switch (F.kind) {
-        case GRAM_F32: sp_build_kind<GRAM_F32>(fill, F.m_pad, g, F, tiles, N, cut, c, lam2, counts, offsets, keys, kv, flag, s); break;
-        case GRAM_BF16: sp_build_kind<GRAM_BF16>(fill, F.m_pad, g, F, tiles, N, cut, c, lam2, counts, offsets, keys, kv, flag, s); break;
-        case GRAM_BF16X3: sp_build_kind<GRAM_BF16X3>(fill, F.m_pad, g, F, tiles, N, cut, c, lam2, counts, offsets, keys, kv, flag, s); break;
-        case GRAM_BF16X6: sp_build_kind<GRAM_BF16X6>(fill, F.m_pad, g, F, tiles, N, cut, c, lam2, counts, offsets, keys, kv, flag, s); break;
+        case GRAM_F32: sp_build_kind<GRAM_F32>(fill, F.m_pad, g, F, tiles, stride, N, cut, c, lam2, counts, cap, cursor, keys, kv, s); break;
+        case GRAM_BF16: sp_build_kind<GRAM_BF16>(fill, F.m_pad, g, F, tiles, stride, N, cut, c, lam2, counts, cap, cursor, keys, kv, s); break;
+        case GRAM_BF16X3: sp_build_kind<GRAM_BF16X3>(fill, F.m_pad, g, F, tiles, stride, N, cut, c, lam2, counts, cap, cursor, keys, kv, s); break;
+        case GRAM_BF16X6: sp_build_kind<GRAM_BF16X6>(fill, F.m_pad, g, F, tiles, stride, N, cut, c, lam2, counts, cap, cursor, keys, kv, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -431,16 +434,17 @@ inline unsigned blocks(int64_t n) { return (unsigned)((n + WG - 1) / WG); }
 
 }  // namespace
 
-hipError_t launch_sp_count(const Features& F, const uint32_t* tiles, int64_t ntiles, int64_t N, float cut,
-                           int32_t* counts, hipStream_t s) {
-    return sp_build(false, F, tiles, ntiles, N, cut, 0.0f, 0.0f, counts, nullptr, nullptr, nullptr, nullptr, s);
+hipError_t launch_sp_count(const Features& F, const uint32_t* tiles, int64_t ntiles, int64_t stride, int64_t N,
+                           float cut, int32_t* counts, hipStream_t s) {
+    if (ntiles <= 0) return hipSuccess;
+    return sp_build(false, F, tiles, ntiles, stride, N, cut, 0.0f, 0.0f, counts, 0, nullptr, nullptr, nullptr, s);
 }
 
 hipError_t launch_sp_fill(const Features& F, const uint32_t* tiles, int64_t ntiles, int64_t N, float cut,
-                          float neg_gamma_log2e, float lam2, const int64_t* offsets, const int32_t* counts,
-                          uint64_t* keys, float* kv, int32_t* flag, hipStream_t s) {
-    return sp_build(true, F, tiles, ntiles, N, cut, neg_gamma_log2e, lam2, const_cast<int32_t*>(counts), offsets,
-                    keys, kv, flag, s);
+                          float neg_gamma_log2e, float lam2, int64_t cap, unsigned long long* cursor, uint64_t* keys,
+                          float* kv, hipStream_t s) {
+    if (ntiles <= 0) return hipSuccess;
+    return sp_build(true, F, tiles, ntiles, 1, N, cut, neg_gamma_log2e, lam2, nullptr, cap, cursor, keys, kv, s);
 }
 
 hipError_t launch_sp_order(const float* X, int64_t N, int64_t m, const int32_t* lm, int K, uint64_t* key,

@@ -64,6 +64,7 @@ gabp_status check_params(const gabp_svm_params* p, std::string& why) {
         if (!(p->sparse_tau > 0.0 && p->sparse_tau <= 1.0)) { why = "sparse_tau must be in (0, 1]"; return GABP_E_INVALID; }
         if (p->precision == GABP_PREC_FP64) { why = "the sparsified kernel runs in FP32 or MIXED precision"; return GABP_E_INVALID; }
         if (p->schedule != GABP_SCHED_SYNC) { why = "the sparsified kernel runs the SYNC schedule"; return GABP_E_INVALID; }
+        if (p->sparse_edges_hint < 0) { why = "sparse_edges_hint must be >= 0"; return GABP_E_INVALID; }
     }
     if (!(p->C > 0.0) || !std::isfinite(p->C)) { why = "C must be > 0"; return GABP_E_INVALID; }
     if (p->diag_mode < 0 || p->diag_mode > 3) { why = "unknown diag_mode"; return GABP_E_INVALID; }
@@ -655,7 +656,7 @@ gabp_status solve_sparse_impl(gabp_svm* h, const float* X, const float* y, int64
         if (gram == GRAM_BF16X6) A(h->xlo2, (size_t)NPAD * m_pad * 2);
     }
     A(h->yd, (size_t)N * 4);
-    A(h->sp_cnt, (size_t)nt * 4); A(h->sp_toff, (size_t)nt * 8);
+    A(h->sp_cnt, (size_t)(nt / 32 + 1) * 4); A(h->sp_toff, (size_t)(nt / 32 + 1) * 8);   // sampled tiles
     A(h->partP, (size_t)NPAD * 8); A(h->partE, (size_t)NPAD * 8);
     A(h->kdiag, (size_t)N * 8); A(h->Adiag, (size_t)N * 8); A(h->rowmax, (size_t)N * 8);
     A(h->rsum, (size_t)N * 8);
@@ -668,7 +669,8 @@ gabp_status solve_sparse_impl(gabp_svm* h, const float* X, const float* y, int64
     A(h->sp_offi, (size_t)(N + 1) * 8); A(h->sp_offj, (size_t)(N + 1) * 8);
     A(h->sp_order, (size_t)N * 4); A(h->sp_Xp, (size_t)N * m * 4);
     A(h->sp_cent, (size_t)NB * m * 8); A(h->sp_rad, (size_t)NB * 8);
-    A(h->sp_keep, (size_t)nt); A(h->sp_tsel, (size_t)nt * 4); A(h->sp_nsel, 8);
+    A(h->sp_keep, (size_t)nt); A(h->sp_tsel, (size_t)nt * 4);
+    A(h->sp_nsel, 16);   // [0] tiles selected by the pruning, [1] the fill cursor
     if (ae != hipSuccess) {
         h->release_all();
         return fail(h, GABP_E_NOMEM, std::string("device allocation failed: ") + hipGetErrorString(ae));
@@ -748,21 +750,50 @@ gabp_status solve_sparse_impl(gabp_svm* h, const float* X, const float* y, int64
     HIPCHK(h, hipStreamSynchronize(s));
     const uint32_t* tsel = h->sp_tsel.as<uint32_t>();
     const float cutf = (float)cut;
+    const float c = (float)(-p.gamma * 1.4426950408889634);
     int64_t E = 0;
     size_t tb = 0;
     if (nts > 0) {
-        HIPCHK(h, launch_sp_count(F, tsel, nts, N, cutf, h->sp_cnt.as<int32_t>(), s));
-        HIPCHK(h, sp_scan(nullptr, &tb, h->sp_cnt.as<int32_t>(), h->sp_toff.as<int64_t>(), nts, s));
-        if (h->sp_tmp.ensure(tb) != hipSuccess) { h->release_all(); return fail(h, GABP_E_NOMEM, "scan storage"); }
-        HIPCHK(h, sp_scan(h->sp_tmp.p, &tb, h->sp_cnt.as<int32_t>(), h->sp_toff.as<int64_t>(), nts, s));
-        int64_t last_off = 0;
-        int32_t last_cnt = 0;
-        HIPCHK(h, hipMemcpyAsync(&last_off, h->sp_toff.as<int64_t>() + (nts - 1), 8, hipMemcpyDeviceToHost, s));
-        HIPCHK(h, hipMemcpyAsync(&last_cnt, h->sp_cnt.as<int32_t>() + (nts - 1), 4, hipMemcpyDeviceToHost, s));
-        HIPCHK(h, hipStreamSynchronize(s));
-        E = last_off + last_cnt;
+        // capacity of the fill's output: the caller's hint, else 1.5 x the
+        // kept pairs of every 32nd tile scaled to all tiles, plus 2^20; a
+        // capacity that falls short costs a second fill pass, never a
+        // different graph
+        const int64_t emax = ((int64_t)1 << 31) - 1;
+        int64_t cap = p.sparse_edges_hint;
+        if (cap == 0) {
+            const int64_t stride = 32, ns = (nts + stride - 1) / stride;
+            HIPCHK(h, launch_sp_count(F, tsel, ns, stride, N, cutf, h->sp_cnt.as<int32_t>(), s));
+            HIPCHK(h, sp_scan(nullptr, &tb, h->sp_cnt.as<int32_t>(), h->sp_toff.as<int64_t>(), ns, s));
+            if (h->sp_tmp.ensure(tb) != hipSuccess) { h->release_all(); return fail(h, GABP_E_NOMEM, "scan storage"); }
+            HIPCHK(h, sp_scan(h->sp_tmp.p, &tb, h->sp_cnt.as<int32_t>(), h->sp_toff.as<int64_t>(), ns, s));
+            int64_t last_off = 0;
+            int32_t last_cnt = 0;
+            HIPCHK(h, hipMemcpyAsync(&last_off, h->sp_toff.as<int64_t>() + (ns - 1), 8, hipMemcpyDeviceToHost, s));
+            HIPCHK(h, hipMemcpyAsync(&last_cnt, h->sp_cnt.as<int32_t>() + (ns - 1), 4, hipMemcpyDeviceToHost, s));
+            HIPCHK(h, hipStreamSynchronize(s));
+            const double est = (double)(last_off + last_cnt) * ((double)nts / (double)ns);
+            cap = std::min<int64_t>(emax, (int64_t)(1.5 * est) + ((int64_t)1 << 20));
+        }
+        unsigned long long* cursor = reinterpret_cast<unsigned long long*>(h->sp_nsel.as<int64_t>() + 1);
+        for (int pass = 0; pass < 2; ++pass) {
+            A(h->sp_keys, (size_t)cap * 8); A(h->sp_kv, (size_t)cap * 4);
+            if (ae != hipSuccess) {
+                h->release_all();
+                return fail(h, GABP_E_NOMEM, std::string("device allocation of the edge list failed: ") +
+                                                 hipGetErrorString(ae));
+            }
+            HIPCHK(h, hipMemsetAsync(cursor, 0, 8, s));
+            HIPCHK(h, launch_sp_fill(F, tsel, nts, N, cutf, c, (float)(lam * lam), cap, cursor,
+                                     h->sp_keys.as<uint64_t>(), h->sp_kv.as<float>(), s));
+            unsigned long long total = 0;
+            HIPCHK(h, hipMemcpyAsync(&total, cursor, 8, hipMemcpyDeviceToHost, s));
+            HIPCHK(h, hipStreamSynchronize(s));
+            if ((int64_t)total > emax) return fail(h, GABP_E_INVALID, "more than 2^31 - 1 kept pairs: raise sparse_tau");
+            if ((int64_t)total <= cap) { E = (int64_t)total; break; }
+            if (pass == 1) return fail(h, GABP_E_DEVICE, "two fill passes of the sparse graph disagree");
+            cap = (int64_t)total;
+        }
     }
-    if (E >= (int64_t)1 << 31) return fail(h, GABP_E_INVALID, "more than 2^31 - 1 kept pairs: raise sparse_tau");
     const size_t st_bytes = 4;   // records and K' per edge in FP32 storage
     A(h->sp_keys, (size_t)E * 8); A(h->sp_keys2, (size_t)E * 8);
     A(h->sp_kv, (size_t)E * 4); A(h->sp_kv2, (size_t)E * 4);
@@ -775,18 +806,6 @@ gabp_status solve_sparse_impl(gabp_svm* h, const float* X, const float* y, int64
         h->release_all();
         return fail(h, GABP_E_NOMEM, std::string("device allocation of the edge arrays failed: ") +
                                          hipGetErrorString(ae));
-    }
-    const float c = (float)(-p.gamma * 1.4426950408889634);
-    HIPCHK(h, hipMemsetAsync(h->flag.p, 0, 4, s));
-    if (nts > 0)
-        HIPCHK(h, launch_sp_fill(F, tsel, nts, N, cutf, c, (float)(lam * lam),
-                             h->sp_toff.as<int64_t>(), h->sp_cnt.as<int32_t>(), h->sp_keys.as<uint64_t>(),
-                             h->sp_kv.as<float>(), h->flag.as<int32_t>(), s));
-    {
-        int32_t fl = 0;
-        HIPCHK(h, hipMemcpyAsync(&fl, h->flag.p, 4, hipMemcpyDeviceToHost, s));
-        HIPCHK(h, hipStreamSynchronize(s));
-        if (fl) return fail(h, GABP_E_DEVICE, "the count and fill passes of the sparse graph disagree");
     }
     size_t sb = 0, sb2 = 0;
     HIPCHK(h, sp_sort_keys(nullptr, &sb, h->sp_keys.as<uint64_t>(), h->sp_keys2.as<uint64_t>(), h->sp_kv.as<float>(),
@@ -993,6 +1012,7 @@ void gabp_svm_params_default(gabp_svm_params* p) {
     p->time_sweeps = 0;
     p->schedule = GABP_SCHED_SYNC;
     p->sched_groups = 0;
+    p->sparse_edges_hint = 0;
     p->sparse_tau = 1e-3;
 }
 

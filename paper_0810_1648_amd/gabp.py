@@ -43,7 +43,7 @@ class Params(ct.Structure):
         ("stagnation_rel", ct.c_double), ("precision", ct.c_int32), ("kstore", ct.c_int32),
         ("edge_state", ct.c_int32), ("gram", ct.c_int32), ("stateless_depth", ct.c_int32),
         ("device", ct.c_int32), ("hbm_budget_bytes", ct.c_uint64), ("time_sweeps", ct.c_int32),
-        ("schedule", ct.c_int32), ("sched_groups", ct.c_int32), ("reserved", ct.c_int32),
+        ("schedule", ct.c_int32), ("sched_groups", ct.c_int32), ("sparse_edges_hint", ct.c_int32),
         ("sparse_tau", ct.c_double),
     ]
 
@@ -77,7 +77,7 @@ class GabpError(RuntimeError):
 
 
 _lib = None
-ABI_VERSION = 5     # GABP_ABI_VERSION the structures above describe
+ABI_VERSION = 6     # GABP_ABI_VERSION the structures above describe
 
 
 def lib():

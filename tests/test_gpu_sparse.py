@@ -87,9 +87,25 @@ def test_sparse_device_inputs_bitwise_and_limits(torch):
     np.testing.assert_allclose(z.alpha(), 1.0 / z.adiag(), rtol=1e-12)
 
 
+@pytest.mark.parametrize("hint", [1, "short", "exact", 10**7])
+def test_sparse_fill_capacity_hint_gives_the_same_graph(torch, hint):
+    """The build fills the edge list in one pass sized by an estimate or the
+    caller's hint; a capacity below the number of kept pairs costs a second
+    pass.  Either way the edges and alpha are bitwise those of the default."""
+    X, y, gamma, tau = _case(n=900, seed=75)
+    a, _ = _solve(X, y, gamma, tau)
+    E = a.plan()["n_edges"]
+    assert E > 1
+    h = {"short": E - 1, "exact": E}.get(hint, hint)
+    s, st = _solve(X, y, gamma, tau, sparse_edges_hint=h)
+    assert st == gabp.OK and s.plan()["n_edges"] == E
+    assert np.array_equal(s.edges(), a.edges()) and np.array_equal(s.alpha(), a.alpha())
+
+
 def test_sparse_invalid_parameters(torch):
     X, y, gamma, tau = _case(n=300, seed=74)
-    for t, kw in ((tau, dict(precision="fp64")), (0.0, {}), (1.5, {}), (tau, dict(schedule="grouped"))):
+    for t, kw in ((tau, dict(precision="fp64")), (0.0, {}), (1.5, {}), (tau, dict(schedule="grouped")),
+                  (tau, dict(sparse_edges_hint=-1))):
         with pytest.raises(gabp.GabpError) as e:
             _solve(X, y, gamma, t, **kw)
         assert e.value.status == gabp.E_INVALID
