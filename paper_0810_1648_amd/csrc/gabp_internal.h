@@ -232,6 +232,10 @@ hipError_t launch_sp_fill(const Features& F, const uint32_t* tiles, int64_t ntil
                           float neg_gamma_log2e, float lam2, int64_t cap, unsigned long long* cursor, uint64_t* keys,
                           float* kv, hipStream_t s);
 hipError_t sp_scan(void* tmp, size_t* bytes, const int32_t* in, int64_t* out, int64_t n, hipStream_t s);
+// The tile list in super-blocked order (S x S tiles per super-block, NB
+// blocks per side), through the key buffers k0, k1 (nt entries each).
+hipError_t sp_tile_order(void* tmp, size_t* bytes, uint32_t* tiles, int64_t nt, int S, int NB, uint64_t* k0,
+                         uint64_t* k1, hipStream_t s);
 // Locality order: nearest of the K landmark points lm[] for every point
 // (key = landmark << 32 | point, ids = point), rows permuted into that order,
 // block centroids / radii and the tiles that may hold kept pairs, compaction

@@ -25,6 +25,15 @@ namespace gabp {
 
 namespace {
 
+// Workgroups go to the eight XCDs in turn (workgroup b to XCD b mod 8).
+// This index of workgroup b in [0, n) (n = the grid) gives every XCD one
+// contiguous range instead, so that work items sharing data (neighbouring
+// nodes and edges, tiles of one super-block) meet in the same L2.
+__device__ inline int64_t xcd_contiguous(int64_t b, int64_t n) {
+    const int64_t x = b & 7, q = b >> 3, base = n >> 3, rem = n & 7;
+    return x * base + (x < rem ? x : rem) + q;
+}
+
 // Thresholded distances of one tile on MFMA.  Wave w computes the 32-row
 // bands w and w + 4 together (their A fragments in registers, each B
 // fragment loaded once for both) and walks the eight 32-column blocks.  For
@@ -121,7 +130,8 @@ __global__ __launch_bounds__(WG) void k_sp_fill(Features F, const uint32_t* __re
                                                 float cut, float neg_gamma_log2e, float lam2, int64_t cap,
                                                 unsigned long long* __restrict__ cursor,
                                                 uint64_t* __restrict__ keys, float* __restrict__ kv) {
-    const TileCoord tc = tile_of(tiles);
+    const uint32_t ij = tiles[xcd_contiguous(blockIdx.x, gridDim.x)];
+    const TileCoord tc{(int)(ij >> 16), (int)(ij & 0xFFFFu)};
     const int l = threadIdx.x & 63, h = l >> 5;
     const uint64_t below = (1ull << l) - 1ull;
     sp_tile<KIND, MP>(F, tc, N, cut, [&](const uint64_t* k0, const uint64_t* k1, int64_t ib, int64_t j,
@@ -215,7 +225,7 @@ __global__ __launch_bounds__(WG) void k_sp_sweep(int64_t E, const int32_t* __res
                                                  const AT* __restrict__ PS, ST* __restrict__ RF,
                                                  ST* __restrict__ RB, DevStatus* st) {
     if (st->done) return;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t e = xcd_contiguous(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     bool bad = false;
     if (e < E) {
         const int32_t i = ei[e], j = ej[e];
@@ -247,7 +257,7 @@ __global__ __launch_bounds__(WG) void k_sp_gather(int64_t N, const int64_t* __re
                                                   const ST* __restrict__ RB, AT* __restrict__ partP,
                                                   AT* __restrict__ partE, const DevStatus* st) {
     if (st->done) return;
-    const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    const int64_t k = (xcd_contiguous(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 4;
     const int q = threadIdx.x & 15;
     AT p = 0, e = 0;
     if (k < N) {
@@ -328,6 +338,24 @@ __global__ __launch_bounds__(WG) void k_sp_assign(const float* __restrict__ X, i
         key[i] = ((uint64_t)(uint32_t)arg << 32) | (uint64_t)i;
         ids[i] = (int32_t)i;
     }
+}
+
+// Super-blocked order of the tile list: key = (super-block of (I, J), tile
+// code), super-blocks of S x S tiles in row-major order, tiles inside one in
+// row-major order.  With the XCD-contiguous workgroup index, the tiles of a
+// super-block run on one XCD and share its L2 for their 2 S row fragments.
+__global__ void k_sp_tile_keys(const uint32_t* __restrict__ tiles, int64_t nt, int S, int NSB,
+                               uint64_t* __restrict__ keys) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    const uint32_t ij = tiles[t];
+    const uint32_t I = ij >> 16, J = ij & 0xFFFFu;
+    keys[t] = ((uint64_t)((I / S) * (uint32_t)NSB + J / S) << 32) | (uint64_t)ij;
+}
+
+__global__ void k_sp_tile_codes(const uint64_t* __restrict__ keys, int64_t nt, uint32_t* __restrict__ tiles) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nt) tiles[t] = (uint32_t)(keys[t] & 0xFFFFFFFFull);
 }
 
 // Rows of X and labels in the new order: Xp[r] = X[order[r]].
@@ -471,6 +499,18 @@ hipError_t launch_sp_prune(const float* Xp, int64_t N, int64_t m, int NB, const 
 hipError_t sp_select(void* tmp, size_t* bytes, const uint32_t* in, const uint8_t* flags, uint32_t* out,
                      int64_t* nsel, int64_t n, hipStream_t s) {
     return hipcub::DeviceSelect::Flagged(tmp, *bytes, in, flags, out, nsel, (int)n, s);
+}
+
+hipError_t sp_tile_order(void* tmp, size_t* bytes, uint32_t* tiles, int64_t nt, int S, int NB, uint64_t* k0,
+                         uint64_t* k1, hipStream_t s) {
+    if (tmp == nullptr) return hipcub::DeviceRadixSort::SortKeys(tmp, *bytes, k0, k1, (int)nt, 0, 64, s);
+    if (nt <= 0) return hipSuccess;
+    const int NSB = (NB + S - 1) / S;
+    hipLaunchKernelGGL(k_sp_tile_keys, dim3(blocks(nt)), dim3(WG), 0, s, tiles, nt, S, NSB, k0);
+    hipError_t e = hipcub::DeviceRadixSort::SortKeys(tmp, *bytes, k0, k1, (int)nt, 0, 64, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sp_tile_codes, dim3(blocks(nt)), dim3(WG), 0, s, k1, nt, tiles);
+    return hipGetLastError();
 }
 
 hipError_t launch_sp_unpermute(const double* in, const int32_t* order, int64_t N, double* out, hipStream_t s) {

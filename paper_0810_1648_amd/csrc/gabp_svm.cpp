@@ -748,6 +748,21 @@ gabp_status solve_sparse_impl(gabp_svm* h, const float* X, const float* y, int64
     int64_t nts = 0;
     HIPCHK(h, hipMemcpyAsync(&nts, h->sp_nsel.p, 8, hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));
+    // super-blocked tile order: S x S tiles share 2 S row fragments, sized to
+    // stay well inside one XCD's L2
+    if (nts > 0) {
+        const int planes = (gram == GRAM_F32) ? 2 : (gram == GRAM_BF16) ? 1 : (gram == GRAM_BF16X3) ? 2 : 3;
+        const int64_t frag_bytes = (int64_t)TILE * m_pad * 2 * planes;
+        const int S = (int)std::max<int64_t>(4, std::min<int64_t>(16, ((int64_t)1 << 21) / (2 * frag_bytes)));
+        A(h->sp_keys, (size_t)nts * 8); A(h->sp_keys2, (size_t)nts * 8);
+        if (ae != hipSuccess) { h->release_all(); return fail(h, GABP_E_NOMEM, "tile order storage"); }
+        size_t ob = 0;
+        HIPCHK(h, sp_tile_order(nullptr, &ob, h->sp_tsel.as<uint32_t>(), nts, S, NB, h->sp_keys.as<uint64_t>(),
+                                h->sp_keys2.as<uint64_t>(), s));
+        if (h->sp_tmp.ensure(ob) != hipSuccess) { h->release_all(); return fail(h, GABP_E_NOMEM, "sort storage"); }
+        HIPCHK(h, sp_tile_order(h->sp_tmp.p, &ob, h->sp_tsel.as<uint32_t>(), nts, S, NB, h->sp_keys.as<uint64_t>(),
+                                h->sp_keys2.as<uint64_t>(), s));
+    }
     const uint32_t* tsel = h->sp_tsel.as<uint32_t>();
     const float cutf = (float)cut;
     const float c = (float)(-p.gamma * 1.4426950408889634);
