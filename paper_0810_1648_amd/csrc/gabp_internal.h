@@ -226,11 +226,18 @@ hipError_t launch_sweep_grouped_f64(int ksrc, int gram, int levels, int ser, con
 // count: kept pairs of tiles[0], tiles[stride], ... (ntiles launched);
 // fill: every listed tile's kept pairs appended at *cursor (slots >= cap
 // counted, not written).
-hipError_t launch_sp_count(const Features& F, const uint32_t* tiles, int64_t ntiles, int64_t stride, int64_t N,
-                           float cut, int32_t* counts, hipStream_t s);
-hipError_t launch_sp_fill(const Features& F, const uint32_t* tiles, int64_t ntiles, int64_t N, float cut,
-                          float neg_gamma_log2e, float lam2, int64_t cap, unsigned long long* cursor, uint64_t* keys,
-                          float* kv, hipStream_t s);
+// FA, FB: the augmented A and B rows (launch_sp_augment), whose Gram is
+// -d^2 / 2.
+hipError_t launch_sp_count(const Features& FA, const Features& FB, const uint32_t* tiles, int64_t ntiles,
+                           int64_t stride, int64_t N, float cut, int32_t* counts, hipStream_t s);
+hipError_t launch_sp_fill(const Features& FA, const Features& FB, const uint32_t* tiles, int64_t ntiles, int64_t N,
+                          float cut, float neg_gamma_log2e, float lam2, int64_t cap, unsigned long long* cursor,
+                          uint64_t* keys, float* kv, hipStream_t s);
+// Columns m, m + 1 (< m_pad) of the staged rows: A planes (n_i, 1), B planes
+// the first m columns of A and (-1/2, -n_i/2); NPAD rows.
+hipError_t launch_sp_augment(int64_t NPAD, int64_t m, int m_pad, int kind, const float* nrm, float* f32a,
+                             uint16_t* hia, uint16_t* loa, uint16_t* lo2a, float* f32b, uint16_t* hib,
+                             uint16_t* lob, uint16_t* lo2b, hipStream_t s);
 hipError_t sp_scan(void* tmp, size_t* bytes, const int32_t* in, int64_t* out, int64_t n, hipStream_t s);
 // The tile list in super-blocked order (S x S tiles per super-block, NB
 // blocks per side), through the key buffers k0, k1 (nt entries each).

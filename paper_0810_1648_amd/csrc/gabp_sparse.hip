@@ -34,133 +34,152 @@ __device__ inline int64_t xcd_contiguous(int64_t b, int64_t n) {
     return x * base + (x < rem ? x : rem) + q;
 }
 
-// Thresholded distances of one tile on MFMA.  Wave w computes the 32-row
-// bands w and w + 4 together (their A fragments in registers, each B
-// fragment loaded once for both) and walks the eight 32-column blocks.  For
-// every block, `visit(k0, k1, i0r, jcol, d2a, d2b)` receives the ballots of
-// kept pairs of both bands per output register (k0[r], k1[r]) and the
-// distances (formed only where the visitor uses them); blocks without any
-// kept pair cost one ballot per register.  The keep test
-// d^2 = n_i + n_j - 2 g <= cut is evaluated as 2 g - n_i >= n_j - cut: one
-// explicit FMA and the compare that forms the ballot, identical in every
-// pass.
+// Thresholded distances of one tile on MFMA.  The rows are augmented
+// (k_sp_augment): A row a_i = (x_i, n_i, 1), B row b_j = (x_j, -1/2, -n_j/2)
+// with n = ||x||^2, so the Gram a_i . b_j is -d_ij^2 / 2 and the keep test
+// d^2 <= cut is a single compare of the MFMA output with -cut / 2.  Wave w
+// computes the 32-row bands w and w + 4 together (their A fragments in
+// registers, each B fragment loaded once for both) and walks the eight
+// 32-column blocks, the next block's B fragment in flight during the
+// current MFMAs.  For every block, `visit(g0, g1, i0r, jcol)` receives the
+// Gram values of both bands, where the pair of register r of a lane is kept
+// iff its value is >= -cut / 2 (its ballot is the block's mask for that
+// register).  Blocks off the diagonal tile and before the last column hold
+// only pairs i < j < N; in the others the pairs outside i < j < N get
+// -inf first, so that the test stays one compare everywhere.
 template <int KIND, int MP, class Visit>
-__device__ inline void sp_tile(const Features& F, const TileCoord& tc, int64_t N, float cut, Visit&& visit) {
+__device__ inline void sp_tile(const Features& FA, const Features& FB, const TileCoord& tc, int64_t N, float cut,
+                               Visit&& visit) {
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6, h = l >> 5, l32 = l & 31;
     const int64_t i0 = (int64_t)tc.I * TILE, j0 = (int64_t)tc.J * TILE;
     const int64_t rowA0 = i0 + w * 32 + l32, rowA1 = i0 + (w + 4) * 32 + l32;
-    float ni0[16], ni1[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        ni0[r] = F.nrm[i0 + w * 32 + 8 * (r >> 2) + 4 * h + (r & 3)];
-        ni1[r] = F.nrm[i0 + (w + 4) * 32 + 8 * (r >> 2) + 4 * h + (r & 3)];
-    }
+    const float hc = -0.5f * cut;
     RowFrag<KIND, MP> fa0, fa1, fb;
-    fa0.load(F, rowA0);
-    fa1.load(F, rowA1);
+    fa0.load(FA, rowA0);
+    fa1.load(FA, rowA1);
     // first column block with a pair i < j for the lower band
     int cb0 = 0;
     while (cb0 < TILE / 32 && j0 + cb0 * 32 + 31 < i0 + w * 32) ++cb0;
-    if constexpr (MP > 0) fb.load(F, j0 + cb0 * 32 + l32);
+    if constexpr (MP > 0) fb.load(FB, j0 + cb0 * 32 + l32);
 #pragma unroll 1
     for (int cb = cb0; cb < TILE / 32; ++cb) {
         const int64_t j = j0 + cb * 32 + l32;
         f32x16 g0 = {}, g1 = {};
         if constexpr (MP > 0) {
-            // the next block's B fragment is in flight while this one's MFMAs run
             RowFrag<KIND, MP> fn;
-            fn.load(F, j0 + (cb + 1 < TILE / 32 ? cb + 1 : cb) * 32 + l32);
-            frag_mma(fa0, fb, g0, F.m_pad);
-            frag_mma(fa1, fb, g1, F.m_pad);
+            fn.load(FB, j0 + (cb + 1 < TILE / 32 ? cb + 1 : cb) * 32 + l32);
+            frag_mma(fa0, fb, g0, FA.m_pad);
+            frag_mma(fa1, fb, g1, FA.m_pad);
             fb = fn;
         } else {
-            RowFrag<KIND, MP>::gram2(fa0, fa1, F, rowA0, rowA1, F, j, g0, g1);
+            RowFrag<KIND, MP>::gram2(fa0, fa1, FA, rowA0, rowA1, FB, j, g0, g1);
         }
-        const float nj = F.nrm[j], cj = nj - cut;
-        // the index tests matter only on diagonal tiles and in the last column block
-        const bool plain = (tc.I < tc.J) && (j0 + cb * 32 + 31 < N);
-        uint64_t k0[16], k1[16], any = 0;
-        float d0[16], d1[16];
+        if (!((tc.I < tc.J) && (j0 + cb * 32 + 31 < N))) {
+            // register r of lane l holds row 8 (r / 4) + 4 (l / 32) + r % 4 of its band
+            const int64_t dj = j - (i0 + w * 32 + 4 * h);
+            const bool jn = j < N;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int64_t ia = i0 + w * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-            const int64_t ib = ia + 128;
-            d0[r] = fmaxf(fmaf(-2.0f, g0[r], ni0[r] + nj), 0.0f);
-            d1[r] = fmaxf(fmaf(-2.0f, g1[r], ni1[r] + nj), 0.0f);
-            const bool c0 = fmaf(2.0f, g0[r], -ni0[r]) >= cj && (plain || (ia < j && j < N));
-            const bool c1 = fmaf(2.0f, g1[r], -ni1[r]) >= cj && (plain || (ib < j && j < N));
-            k0[r] = __ballot(c0);
-            k1[r] = __ballot(c1);
-            any |= k0[r] | k1[r];
+            for (int r = 0; r < 16; ++r) {
+                const int ro = 8 * (r >> 2) + (r & 3);
+                if (!(jn && dj > ro)) g0[r] = -INFINITY;
+                if (!(jn && dj > ro + 128)) g1[r] = -INFINITY;
+            }
         }
-        if (any == 0) continue;
-        visit(k0, k1, i0 + w * 32, j, d0, d1);
+        visit(g0, g1, i0 + w * 32, j, hc);
     }
 }
 
 // Kept pairs of every stride-th listed tile (stride 1: all of them), one
 // count per launched tile; the host sums a strided sample to size the fill.
 template <int KIND, int MP>
-__global__ __launch_bounds__(WG) void k_sp_count(Features F, const uint32_t* __restrict__ tiles, int64_t stride,
+__global__ __launch_bounds__(WG) void k_sp_count(Features FA, Features FB, const uint32_t* __restrict__ tiles, int64_t stride,
                                                  int64_t N, float cut, int32_t* __restrict__ counts) {
     __shared__ int wsum[4];
     const uint32_t ij = tiles[(int64_t)blockIdx.x * stride];
     const TileCoord tc{(int)(ij >> 16), (int)(ij & 0xFFFFu)};
     int c = 0;   // wave-uniform
-    sp_tile<KIND, MP>(F, tc, N, cut, [&](const uint64_t* k0, const uint64_t* k1, int64_t, int64_t, const float*,
-                                         const float*) {
+    sp_tile<KIND, MP>(FA, FB, tc, N, cut, [&](const f32x16& g0, const f32x16& g1, int64_t, int64_t, float hc) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) c += __popcll(k0[r]) + __popcll(k1[r]);
+        for (int r = 0; r < 16; ++r) c += __popcll(__ballot(g0[r] >= hc)) + __popcll(__ballot(g1[r] >= hc));
     });
     if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
     __syncthreads();
     if (threadIdx.x == 0) counts[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
-// Kept pairs appended at a global cursor: one atomic per wave and 32-column
-// block with kept pairs reserves the block's slots, and a kept lane takes
-// the block's base plus the kept pairs before it (register by register, then
-// lane order).  The order across blocks, waves and tiles is arbitrary: the
-// (i, j) sort that follows fixes it, and every pair's key and K' value do
-// not depend on it.  Slots at or beyond cap are not written but still
-// counted, so the cursor ends at the exact number of kept pairs and the host
-// repeats the pass with room for all of them.
+// Kept pairs appended at a global cursor.  A wave collects its kept pairs
+// (key and K' value) in an LDS buffer, register by register in lane order;
+// a full buffer is drained to slots reserved by one atomic, and at the end
+// of the tile one atomic reserves the slots of all four waves' remainders.
+// The order across waves and tiles is arbitrary: the (i, j) sort that
+// follows fixes it, and every pair's key and K' value do not depend on it.
+// Slots at or beyond cap are not written but still counted, so the cursor
+// ends at the exact number of kept pairs and the host repeats the pass with
+// room for all of them.
 template <int KIND, int MP>
-__global__ __launch_bounds__(WG) void k_sp_fill(Features F, const uint32_t* __restrict__ tiles, int64_t N,
+__global__ __launch_bounds__(WG) void k_sp_fill(Features FA, Features FB, const uint32_t* __restrict__ tiles, int64_t N,
                                                 float cut, float neg_gamma_log2e, float lam2, int64_t cap,
                                                 unsigned long long* __restrict__ cursor,
                                                 uint64_t* __restrict__ keys, float* __restrict__ kv) {
+    constexpr int BW = 512;   // entries buffered per wave
+    __shared__ uint64_t bkey[4][BW];
+    __shared__ float bval[4][BW];
+    __shared__ unsigned long long wbase[4];
+    __shared__ int wcnt[4];
     const uint32_t ij = tiles[xcd_contiguous(blockIdx.x, gridDim.x)];
     const TileCoord tc{(int)(ij >> 16), (int)(ij & 0xFFFFu)};
-    const int l = threadIdx.x & 63, h = l >> 5;
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6, h = l >> 5;
     const uint64_t below = (1ull << l) - 1ull;
-    sp_tile<KIND, MP>(F, tc, N, cut, [&](const uint64_t* k0, const uint64_t* k1, int64_t ib, int64_t j,
-                                         const float* d0, const float* d1) {
-        unsigned long long tot = 0;   // wave-uniform
-#pragma unroll
-        for (int r = 0; r < 16; ++r) tot += __popcll(k0[r]) + __popcll(k1[r]);
-        unsigned long long first = 0;
-        if (l == 0) first = atomicAdd(cursor, tot);
-        int64_t pos = (int64_t)__shfl(first, 0);
+    int n = 0;   // wave-uniform: entries in the wave's buffer
+    // the wave's n buffered entries to slots base, base + 1, ...
+    auto drain = [&](unsigned long long base) {
+        for (int k = l; k < n; k += 64) {
+            const int64_t slot = (int64_t)base + k;
+            if (slot < cap) {
+                keys[slot] = bkey[w][k];
+                kv[slot] = bval[w][k];
+            }
+        }
+    };
+    sp_tile<KIND, MP>(FA, FB, tc, N, cut, [&](const f32x16& g0, const f32x16& g1, int64_t ib, int64_t j, float hc) {
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const uint64_t mask = half ? k1[r] : k0[r];
+                const float gv = half ? g1[r] : g0[r];
+                const uint64_t mask = __ballot(gv >= hc);
                 if (mask == 0) continue;
-                if ((mask >> l) & 1ull) {
-                    const int64_t slot = pos + __popcll(mask & below);
-                    if (slot < cap) {
-                        const int64_t i = ib + 128 * half + 8 * (r >> 2) + 4 * h + (r & 3);
-                        const float d2 = half ? d1[r] : d0[r];
-                        keys[slot] = ((uint64_t)i << 32) | (uint64_t)j;
-                        kv[slot] = __builtin_amdgcn_exp2f(neg_gamma_log2e * d2) + lam2;
-                    }
+                if (n + 64 > BW) {
+                    wave_lds_sync();
+                    unsigned long long first = 0;
+                    if (l == 0) first = atomicAdd(cursor, (unsigned long long)n);
+                    drain(__shfl(first, 0));
+                    n = 0;
+                    wave_lds_sync();
                 }
-                pos += __popcll(mask);
+                if ((mask >> l) & 1ull) {
+                    const int k = n + __popcll(mask & below);
+                    const int64_t i = ib + 128 * half + 8 * (r >> 2) + 4 * h + (r & 3);
+                    bkey[w][k] = ((uint64_t)i << 32) | (uint64_t)j;
+                    bval[w][k] = __builtin_amdgcn_exp2f(neg_gamma_log2e * fmaxf(-2.0f * gv, 0.0f)) + lam2;
+                }
+                n += __popcll(mask);
             }
         }
     });
+    if (l == 0) wcnt[w] = n;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long c0 = wcnt[0], c1 = wcnt[1], c2 = wcnt[2], c3 = wcnt[3];
+        const unsigned long long tot = c0 + c1 + c2 + c3;
+        const unsigned long long b = tot ? atomicAdd(cursor, tot) : 0ull;
+        wbase[0] = b;
+        wbase[1] = b + c0;
+        wbase[2] = b + c0 + c1;
+        wbase[3] = b + c0 + c1 + c2;
+    }
+    __syncthreads();
+    drain(wbase[w]);
 }
 
 // i, j of every sorted edge; node degrees as i-end and as j-end.
@@ -417,6 +436,53 @@ __global__ void k_sp_prune(const uint32_t* __restrict__ tiles, int64_t nt, int64
     keep[t] = (gap > 0.0 && gap * gap > 1.001 * cut) ? 0 : 1;
 }
 
+// Augmented rows of the build: A row i gets (n_i, 1) in columns m, m + 1,
+// B row i (a copy of A's first m columns) gets (-1/2, -n_i/2), each value
+// split into the Gram kind's planes as the features are (hi, then the BF16
+// remainders), so that sum_k a_ik b_jk = x_i . x_j - n_i/2 - n_j/2 for the
+// products the kind forms.  One thread per row; columns past m + 1 stay 0.
+__device__ inline void split3(float v, uint16_t& h, uint16_t& l, uint16_t& l2) {
+    h = f2bf(v);
+    const float r = v - bf2f(h);
+    l = f2bf(r);
+    l2 = f2bf(r - bf2f(l));
+}
+
+__global__ void k_sp_augment(int64_t NPAD, int64_t m, int m_pad, int kind, const float* __restrict__ nrm,
+                             float* f32a, uint16_t* hia, uint16_t* loa, uint16_t* lo2a, float* f32b,
+                             uint16_t* hib, uint16_t* lob, uint16_t* lo2b) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= NPAD) return;
+    const int64_t o = i * m_pad;
+    const float n = nrm[i], nb = -0.5f * n;
+    if (kind == GRAM_F32) {
+        for (int64_t k = 0; k < m; ++k) f32b[o + k] = f32a[o + k];
+        f32a[o + m] = n;
+        f32a[o + m + 1] = 1.0f;
+        f32b[o + m] = -0.5f;
+        f32b[o + m + 1] = nb;
+        for (int64_t k = m + 2; k < m_pad; ++k) f32b[o + k] = 0.0f;
+        return;
+    }
+    const bool x3 = (kind == GRAM_BF16X3 || kind == GRAM_BF16X6), x6 = (kind == GRAM_BF16X6);
+    for (int64_t k = 0; k < m_pad; ++k) {
+        hib[o + k] = (k < m) ? hia[o + k] : 0;
+        if (x3) lob[o + k] = (k < m) ? loa[o + k] : 0;
+        if (x6) lo2b[o + k] = (k < m) ? lo2a[o + k] : 0;
+    }
+    uint16_t h, l, l2;
+    split3(n, h, l, l2);
+    hia[o + m] = h;
+    hia[o + m + 1] = f2bf(1.0f);
+    hib[o + m] = f2bf(-0.5f);
+    if (x3) { loa[o + m] = l; loa[o + m + 1] = 0; lob[o + m] = 0; }
+    if (x6) { lo2a[o + m] = l2; lo2a[o + m + 1] = 0; lo2b[o + m] = 0; }
+    split3(nb, h, l, l2);
+    hib[o + m + 1] = h;
+    if (x3) lob[o + m + 1] = l;
+    if (x6) lo2b[o + m + 1] = l2;
+}
+
 // out[order[r]] = in[r]: a per-node array back to input order.
 __global__ void k_sp_unpermute(const double* __restrict__ in, const int32_t* __restrict__ order, int64_t N,
                                double* __restrict__ out) {
@@ -425,16 +491,17 @@ __global__ void k_sp_unpermute(const double* __restrict__ in, const int32_t* __r
 }
 
 template <int KIND>
-void sp_build_kind(bool fill, int mp, dim3 g, const Features& F, const uint32_t* tiles, int64_t stride, int64_t N,
+void sp_build_kind(bool fill, int mp, dim3 g, const Features& FA, const Features& FB, const uint32_t* tiles, int64_t stride, int64_t N,
                    float cut, float c, float lam2, int32_t* counts, int64_t cap, unsigned long long* cursor,
                    uint64_t* keys, float* kv, hipStream_t s) {
 #define GABP_SP_LAUNCH(MPV)                                                                                  \
     do {                                                                                                     \
         if (fill)                                                                                            \
-            hipLaunchKernelGGL((k_sp_fill<KIND, MPV>), g, dim3(WG), 0, s, F, tiles, N, cut, c, lam2, cap,     \
+            hipLaunchKernelGGL((k_sp_fill<KIND, MPV>), g, dim3(WG), 0, s, FA, FB, tiles, N, cut, c, lam2, cap, \
                                cursor, keys, kv);                                                            \
         else                                                                                                 \
-            hipLaunchKernelGGL((k_sp_count<KIND, MPV>), g, dim3(WG), 0, s, F, tiles, stride, N, cut, counts); \
+            hipLaunchKernelGGL((k_sp_count<KIND, MPV>), g, dim3(WG), 0, s, FA, FB, tiles, stride, N, cut,     \
+                               counts);                                                                      \
     } while (0)
     // register-held fragments of two bands plus the prefetched B fragment
     // fit up to 64 features; beyond, fragments are reloaded per block
@@ -444,17 +511,19 @@ void sp_build_kind(bool fill, int mp, dim3 g, const Features& F, const uint32_t*
 #undef GABP_SP_LAUNCH
 }
 
-hipError_t sp_build(bool fill, const Features& F, const uint32_t* tiles, int64_t ntiles, int64_t stride, int64_t N,
-                    float cut, float c, float lam2, int32_t* counts, int64_t cap, unsigned long long* cursor,
-                    uint64_t* keys, float* kv, hipStream_t s) {
+hipError_t sp_build(bool fill, const Features& FA, const Features& FB, const uint32_t* tiles, int64_t ntiles,
+                    int64_t stride, int64_t N, float cut, float c, float lam2, int32_t* counts, int64_t cap,
+                    unsigned long long* cursor, uint64_t* keys, float* kv, hipStream_t s) {
     const dim3 g((unsigned)ntiles);
-    switch (F.kind) {
-        case GRAM_F32: sp_build_kind<GRAM_F32>(fill, F.m_pad, g, F, tiles, stride, N, cut, c, lam2, counts, cap, cursor, keys, kv, s); break;
-        case GRAM_BF16: sp_build_kind<GRAM_BF16>(fill, F.m_pad, g, F, tiles, stride, N, cut, c, lam2, counts, cap, cursor, keys, kv, s); break;
-        case GRAM_BF16X3: sp_build_kind<GRAM_BF16X3>(fill, F.m_pad, g, F, tiles, stride, N, cut, c, lam2, counts, cap, cursor, keys, kv, s); break;
-        case GRAM_BF16X6: sp_build_kind<GRAM_BF16X6>(fill, F.m_pad, g, F, tiles, stride, N, cut, c, lam2, counts, cap, cursor, keys, kv, s); break;
+#define GABP_SP_KIND(K) sp_build_kind<K>(fill, FA.m_pad, g, FA, FB, tiles, stride, N, cut, c, lam2, counts, cap, cursor, keys, kv, s)
+    switch (FA.kind) {
+        case GRAM_F32: GABP_SP_KIND(GRAM_F32); break;
+        case GRAM_BF16: GABP_SP_KIND(GRAM_BF16); break;
+        case GRAM_BF16X3: GABP_SP_KIND(GRAM_BF16X3); break;
+        case GRAM_BF16X6: GABP_SP_KIND(GRAM_BF16X6); break;
         default: return hipErrorInvalidValue;
     }
+#undef GABP_SP_KIND
     return hipGetLastError();
 }
 
@@ -462,17 +531,27 @@ inline unsigned blocks(int64_t n) { return (unsigned)((n + WG - 1) / WG); }
 
 }  // namespace
 
-hipError_t launch_sp_count(const Features& F, const uint32_t* tiles, int64_t ntiles, int64_t stride, int64_t N,
-                           float cut, int32_t* counts, hipStream_t s) {
+hipError_t launch_sp_count(const Features& FA, const Features& FB, const uint32_t* tiles, int64_t ntiles,
+                           int64_t stride, int64_t N, float cut, int32_t* counts, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
-    return sp_build(false, F, tiles, ntiles, stride, N, cut, 0.0f, 0.0f, counts, 0, nullptr, nullptr, nullptr, s);
+    return sp_build(false, FA, FB, tiles, ntiles, stride, N, cut, 0.0f, 0.0f, counts, 0, nullptr, nullptr, nullptr,
+                    s);
 }
 
-hipError_t launch_sp_fill(const Features& F, const uint32_t* tiles, int64_t ntiles, int64_t N, float cut,
-                          float neg_gamma_log2e, float lam2, int64_t cap, unsigned long long* cursor, uint64_t* keys,
-                          float* kv, hipStream_t s) {
+hipError_t launch_sp_fill(const Features& FA, const Features& FB, const uint32_t* tiles, int64_t ntiles, int64_t N,
+                          float cut, float neg_gamma_log2e, float lam2, int64_t cap, unsigned long long* cursor,
+                          uint64_t* keys, float* kv, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
-    return sp_build(true, F, tiles, ntiles, 1, N, cut, neg_gamma_log2e, lam2, nullptr, cap, cursor, keys, kv, s);
+    return sp_build(true, FA, FB, tiles, ntiles, 1, N, cut, neg_gamma_log2e, lam2, nullptr, cap, cursor, keys, kv, s);
+}
+
+hipError_t launch_sp_augment(int64_t NPAD, int64_t m, int m_pad, int kind, const float* nrm, float* f32a,
+                             uint16_t* hia, uint16_t* loa, uint16_t* lo2a, float* f32b, uint16_t* hib,
+                             uint16_t* lob, uint16_t* lo2b, hipStream_t s) {
+    if (m + 2 > m_pad) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sp_augment, dim3(blocks(NPAD)), dim3(WG), 0, s, NPAD, m, m_pad, kind, nrm, f32a, hia, loa,
+                       lo2a, f32b, hib, lob, lo2b);
+    return hipGetLastError();
 }
 
 hipError_t launch_sp_order(const float* X, int64_t N, int64_t m, const int32_t* lm, int K, uint64_t* key,

@@ -107,16 +107,16 @@ struct gabp_svm {
     // sparsified kernel: tile counts and offsets, keys, K' per edge, edge
     // ends, degrees and offsets of the i-end and j-end lists, permutation
     DevBuf sp_cnt, sp_toff, sp_keys, sp_keys2, sp_kv, sp_kv2, sp_ei, sp_ej, sp_degi, sp_degj, sp_offi,
-        sp_offj, sp_ids, sp_perm, sp_tmp, sp_order, sp_Xp, sp_cent, sp_rad, sp_keep, sp_tsel, sp_nsel;
+        sp_offj, sp_ids, sp_perm, sp_tmp, sp_order, sp_Xp, sp_cent, sp_rad, sp_keep, sp_tsel, sp_nsel, sp_xb;
     bool sparse = false;
     int64_t n_edges = 0;
 
-    DevBuf* all[61] = {&tiles, &Kp, &Pf, &Pb, &Ef, &Eb, &partP, &partE, &Xin, &yd, &mean,
+    DevBuf* all[62] = {&tiles, &Kp, &Pf, &Pb, &Ef, &Eb, &partP, &partE, &Xin, &yd, &mean,
                        &xs32, &xhi, &xlo, &xlo2, &x64, &nrm, &kdiag, &rowmax, &rsum, &Adiag, &Pt, &S, &alpha_d,
                        &blk1, &blk2, &one, &status_d, &trace_d, &flag, &tmp, &Kin, &q_rows,
                        &q_cols, &q_out, &glist, &sp_cnt, &sp_toff, &sp_keys, &sp_keys2, &sp_kv, &sp_kv2,
                        &sp_ei, &sp_ej, &sp_degi, &sp_degj, &sp_offi, &sp_offj, &sp_ids, &sp_perm, &sp_tmp,
-                       &sp_order, &sp_Xp, &sp_cent, &sp_rad, &sp_keep, &sp_tsel, &sp_nsel, &HI, &HM, nullptr};
+                       &sp_order, &sp_Xp, &sp_cent, &sp_rad, &sp_keep, &sp_tsel, &sp_nsel, &sp_xb, &HI, &HM, nullptr};
     size_t held() const {
         size_t b = 0;
         for (int k = 0; all[k]; ++k) b += all[k]->bytes;
@@ -638,7 +638,8 @@ gabp_status solve_sparse_impl(gabp_svm* h, const float* X, const float* y, int64
     const int NB = (int)((N + TILE - 1) / TILE);
     const int64_t NPAD = (int64_t)NB * TILE;
     const int64_t nt = n_tiles(NB);
-    const int m_pad = (int)((m + 15) / 16 * 16);
+    // two augmented columns carry the norms (the build's Gram is -d^2 / 2)
+    const int m_pad = (int)((m + 2 + 15) / 16 * 16);
     const size_t agg = (prec == PREC_FP32) ? 4 : 8;
     const double lam = (p.lambda_aug < 0.0) ? 1.0 / (double)N : p.lambda_aug;
     const double cut = -std::log(p.sparse_tau) / p.gamma;
@@ -655,6 +656,10 @@ gabp_status solve_sparse_impl(gabp_svm* h, const float* X, const float* y, int64
         if (gram != GRAM_BF16) A(h->xlo, (size_t)NPAD * m_pad * 2);
         if (gram == GRAM_BF16X6) A(h->xlo2, (size_t)NPAD * m_pad * 2);
     }
+    // the B rows of the build: every plane of the kind, one after the other
+    const int planes = (gram == GRAM_F32) ? 2 : (gram == GRAM_BF16) ? 1 : (gram == GRAM_BF16X3) ? 2 : 3;
+    const size_t plane_b = (size_t)NPAD * m_pad * 2;
+    A(h->sp_xb, plane_b * planes);
     A(h->yd, (size_t)N * 4);
     A(h->sp_cnt, (size_t)(nt / 32 + 1) * 4); A(h->sp_toff, (size_t)(nt / 32 + 1) * 8);   // sampled tiles
     A(h->partP, (size_t)NPAD * 8); A(h->partE, (size_t)NPAD * 8);
@@ -732,6 +737,19 @@ gabp_status solve_sparse_impl(gabp_svm* h, const float* X, const float* y, int64
                            h->nrm.as<float>(), s));
     F.f32 = h->xs32.as<float>(); F.hi = h->xhi.as<uint16_t>(); F.lo = h->xlo.as<uint16_t>();
     F.lo2 = h->xlo2.as<uint16_t>(); F.nrm = h->nrm.as<float>();
+    // augmented rows: A = (x, n, 1) in place, B = (x, -1/2, -n/2) in sp_xb
+    Features FB = F;
+    {
+        uint16_t* b16 = h->sp_xb.as<uint16_t>();
+        float* bf = h->sp_xb.as<float>();
+        uint16_t* bhi = b16;
+        uint16_t* blo = (planes >= 2) ? b16 + plane_b / 2 : nullptr;
+        uint16_t* blo2 = (planes >= 3) ? b16 + plane_b : nullptr;
+        HIPCHK(h, launch_sp_augment(NPAD, m, m_pad, gram, h->nrm.as<float>(), h->xs32.as<float>(),
+                                    h->xhi.as<uint16_t>(), h->xlo.as<uint16_t>(), h->xlo2.as<uint16_t>(), bf, bhi,
+                                    blo, blo2, s));
+        FB.f32 = bf; FB.hi = bhi; FB.lo = blo; FB.lo2 = blo2;
+    }
     HIPCHK(h, hipEventRecord(ev[1], s));
 
     // ---- graph: count per tile, offsets, fill, sort by (i, j), transposed order
@@ -751,7 +769,6 @@ gabp_status solve_sparse_impl(gabp_svm* h, const float* X, const float* y, int64
     // super-blocked tile order: S x S tiles share 2 S row fragments, sized to
     // stay well inside one XCD's L2
     if (nts > 0) {
-        const int planes = (gram == GRAM_F32) ? 2 : (gram == GRAM_BF16) ? 1 : (gram == GRAM_BF16X3) ? 2 : 3;
         const int64_t frag_bytes = (int64_t)TILE * m_pad * 2 * planes;
         const int S = (int)std::max<int64_t>(4, std::min<int64_t>(16, ((int64_t)1 << 21) / (2 * frag_bytes)));
         A(h->sp_keys, (size_t)nts * 8); A(h->sp_keys2, (size_t)nts * 8);
@@ -777,7 +794,7 @@ gabp_status solve_sparse_impl(gabp_svm* h, const float* X, const float* y, int64
         int64_t cap = p.sparse_edges_hint;
         if (cap == 0) {
             const int64_t stride = 32, ns = (nts + stride - 1) / stride;
-            HIPCHK(h, launch_sp_count(F, tsel, ns, stride, N, cutf, h->sp_cnt.as<int32_t>(), s));
+            HIPCHK(h, launch_sp_count(F, FB, tsel, ns, stride, N, cutf, h->sp_cnt.as<int32_t>(), s));
             HIPCHK(h, sp_scan(nullptr, &tb, h->sp_cnt.as<int32_t>(), h->sp_toff.as<int64_t>(), ns, s));
             if (h->sp_tmp.ensure(tb) != hipSuccess) { h->release_all(); return fail(h, GABP_E_NOMEM, "scan storage"); }
             HIPCHK(h, sp_scan(h->sp_tmp.p, &tb, h->sp_cnt.as<int32_t>(), h->sp_toff.as<int64_t>(), ns, s));
@@ -798,7 +815,7 @@ gabp_status solve_sparse_impl(gabp_svm* h, const float* X, const float* y, int64
                                                  hipGetErrorString(ae));
             }
             HIPCHK(h, hipMemsetAsync(cursor, 0, 8, s));
-            HIPCHK(h, launch_sp_fill(F, tsel, nts, N, cutf, c, (float)(lam * lam), cap, cursor,
+            HIPCHK(h, launch_sp_fill(F, FB, tsel, nts, N, cutf, c, (float)(lam * lam), cap, cursor,
                                      h->sp_keys.as<uint64_t>(), h->sp_kv.as<float>(), s));
             unsigned long long total = 0;
             HIPCHK(h, hipMemcpyAsync(&total, cursor, 8, hipMemcpyDeviceToHost, s));
