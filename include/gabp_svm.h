@@ -321,7 +321,11 @@ int32_t gabp_abi_version(void);
  * whether it runs alone or in a mix.  Served plans materialise K'; the edge
  * state (stored pair records or stateless) is chosen per request by the same
  * rule as gabp_svm_solve, and requests of the same precision and level count
- * share a launch.
+ * share a launch.  A request with the GROUPED schedule and a stateless plan
+ * advances one group visit per step (its stop rule runs after the visit of
+ * its last group), with the groups and lists of gabp_svm_solve, so its alpha
+ * is bitwise that of the single grouped solve; with stored pair records it
+ * runs the SYNC schedule.
  * ------------------------------------------------------------------------ */
 typedef struct gabp_server gabp_server;
 
@@ -371,8 +375,9 @@ void gabp_server_params_default(gabp_server_params *p);
 gabp_status gabp_server_create(const gabp_server_params *params, gabp_server **out);
 
 /* Queues one solve: X (N x m float32, row-major, host), y (N float32, +-1,
- * host) and the solver parameters (RBF kernel, K' materialised, SYNC
- * schedule).  Inputs are copied before the call returns.  *ticket identifies
+ * host) and the solver parameters (RBF kernel, K' materialised, SYNC or
+ * GROUPED schedule, no box projection).  Inputs are copied before the call
+ * returns.  *ticket identifies
  * the request.  GABP_E_INVALID for bad inputs or parameters, GABP_E_NOMEM if
  * the request can never fit the arena. */
 gabp_status gabp_server_submit(gabp_server *srv, const float *X, const float *y, int64_t N,

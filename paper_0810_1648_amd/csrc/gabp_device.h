@@ -1119,6 +1119,28 @@ __global__ __launch_bounds__(WG) void k_sweep_dir(SweepArgs a, const uint32_t* _
     else sweep_tile_dir<ST, MT, AT, KSRC, GK, D, SER, true>(a, tile, within, t, sm);
 }
 
+// Served grouped visit (stateless): items are (request, list entry) pairs of
+// every request's current group, built by the host per step; the sweep
+// index of a request is its own count of completed sweeps.
+template <class ST, class MT, class AT, int D, int SER>
+__global__ __launch_bounds__(WG) void k_sweep_dir_batched(const ReqDesc* __restrict__ reqs,
+                                                         const uint2* __restrict__ items, int nitems) {
+    using DT = DirTypes<ST, MT, AT, D, SER>;
+    __shared__ DirSmem<typename DT::XT, typename DT::LT, AT, typename DT::RT, DT::NRL, 0> sm;
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const uint2 w = items[it];
+        const ReqDesc& rd = reqs[w.x];
+        const DevStatus* st = rd.sw.st;
+        if (st->done) continue;
+        const uint32_t e = w.y;
+        const int64_t tile = (int64_t)(e & GE_TILE);
+        const bool within = (e & GE_WITHIN) != 0;
+        if (e & GE_BWD) sweep_tile_dir<ST, MT, AT, KSRC_PLANE, GRAM_F32, D, SER, false>(rd.sw, tile, within, st->t, sm);
+        else sweep_tile_dir<ST, MT, AT, KSRC_PLANE, GRAM_F32, D, SER, true>(rd.sw, tile, within, st->t, sm);
+        __syncthreads();
+    }
+}
+
 // Stored records inside a group: both directions from the previous values
 // (Jacobi within the group), over the listed tiles.
 template <class ST, class MT, class AT, int KSRC, int GK>
@@ -1166,18 +1188,29 @@ inline hipError_t with_stateless(int levels, int ser, F&& f) {
 }
 
 template <class ST, class MT, class AT, int D, int SER>
-inline void served_d(const ReqDesc* reqs, const uint2* items, int n, hipStream_t s) {
+inline void served_d(bool grouped, const ReqDesc* reqs, const uint2* items, int n, hipStream_t s) {
     const int g = std::max(1, std::min(n, 2048));
+    if constexpr (D > 0) {
+        if (grouped) {
+            hipLaunchKernelGGL((k_sweep_dir_batched<ST, MT, AT, D, SER>), dim3(g), dim3(WG), 0, s, reqs, items, n);
+            return;
+        }
+    }
     hipLaunchKernelGGL((k_sweep_batched<ST, MT, AT, D, SER>), dim3(g), dim3(WG), 0, s, reqs, items, n);
 }
 
-// levels 0: stored pair records; 1..8 stateless (1..6 with the series).
+// levels 0: stored pair records; 1..8 stateless (1..6 with the series);
+// grouped: one group visit of stateless requests.
 template <class ST, class MT, class AT>
-inline hipError_t served_sweep(int levels, int ser, const ReqDesc* reqs, const uint2* items, int n,
+inline hipError_t served_sweep(int levels, int ser, bool grouped, const ReqDesc* reqs, const uint2* items, int n,
                                hipStream_t s) {
-    if (levels == 0) { served_d<ST, MT, AT, 0, 0>(reqs, items, n, s); return hipGetLastError(); }
+    if (levels == 0) {
+        if (grouped) return hipErrorInvalidValue;
+        served_d<ST, MT, AT, 0, 0>(false, reqs, items, n, s);
+        return hipGetLastError();
+    }
     const hipError_t e = with_stateless(levels, ser, [&](auto L_, auto S_) {
-        served_d<ST, MT, AT, decltype(L_)::value, decltype(S_)::value>(reqs, items, n, s);
+        served_d<ST, MT, AT, decltype(L_)::value, decltype(S_)::value>(grouped, reqs, items, n, s);
     });
     return e != hipSuccess ? e : hipGetLastError();
 }

@@ -35,7 +35,7 @@ struct DevStatus {
     int32_t reason;
     int32_t since_best;  // sweeps since the smallest change so far
     int32_t bad;         // set when a cavity precision <= 0 or a value is not finite
-    int32_t pad;
+    int32_t g;           // served grouped schedule: the group the next step visits
     double delta;        // ||alpha^t - alpha^(t-1)||_inf
     double amax;         // ||alpha^t||_inf
     double best_delta;
@@ -169,20 +169,25 @@ struct ReqDesc {
     double* trace;
     StopRule rule;
     int nblk;
+    int G;               // groups of the grouped schedule (1: synchronous)
 };
 // One served step for the requests of one group (precision, level count:
 // 0 = stored pair records, >= 1 stateless; series reciprocals): batched sweep
 // over the (request, tile) items, batched finalize over the (request, node
 // block) items, batched stop rule for the request slots listed in `slots`,
 // whose statuses are copied to status_out[0..nslots).
-hipError_t launch_served_step(int prec, int levels, int ser, const ReqDesc* reqs, const uint2* tile_items,
-                              int ntile_items, const uint2* node_items, int nnode_items, const int* slots,
-                              int nslots, DevStatus* status_out, hipStream_t s);
-hipError_t launch_served_sweep_f32(int levels, int ser, const ReqDesc* reqs, const uint2* items, int n,
+// grouped (stateless requests with G > 1): tile items are (request, group
+// list entry) pairs of each request's current group, node items its
+// group's node blocks, and the stop rule runs for a request after the visit
+// of its last group (every slot's status is still copied out).
+hipError_t launch_served_step(int prec, int levels, int ser, bool grouped, const ReqDesc* reqs,
+                              const uint2* tile_items, int ntile_items, const uint2* node_items, int nnode_items,
+                              const int* slots, int nslots, DevStatus* status_out, hipStream_t s);
+hipError_t launch_served_sweep_f32(int levels, int ser, bool grouped, const ReqDesc* reqs, const uint2* items, int n,
                                    hipStream_t s);
-hipError_t launch_served_sweep_mixed(int levels, int ser, const ReqDesc* reqs, const uint2* items, int n,
-                                     hipStream_t s);
-hipError_t launch_served_sweep_f64(int levels, int ser, const ReqDesc* reqs, const uint2* items, int n,
+hipError_t launch_served_sweep_mixed(int levels, int ser, bool grouped, const ReqDesc* reqs, const uint2* items,
+                                     int n, hipStream_t s);
+hipError_t launch_served_sweep_f64(int levels, int ser, bool grouped, const ReqDesc* reqs, const uint2* items, int n,
                                    hipStream_t s);
 // depth 0 = stored edge state, 1..8 = stateless with up to `depth` levels.
 // levels: 0 = stored edge state, >= 1 = stateless with that many levels in

@@ -433,7 +433,7 @@ __global__ void k_diag_shift(int64_t N, const double* __restrict__ kdiag,
 
 __global__ void k_reset_status(DevStatus* st) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        st->t = 0; st->done = 0; st->reason = R_NONE; st->since_best = 0; st->bad = 0; st->pad = 0;
+        st->t = 0; st->done = 0; st->reason = R_NONE; st->since_best = 0; st->bad = 0; st->g = 0;
         st->delta = 0.0; st->amax = 0.0; st->best_delta = INFINITY;
     }
 }
@@ -644,6 +644,26 @@ __global__ __launch_bounds__(WG) void k_status_batched(const ReqDesc* __restrict
     if (threadIdx.x == 0) out[k] = *st;
 }
 
+// Grouped served requests: a step visits one group; after the visit of the
+// last group the stop rule runs (one sweep done), and the group index
+// advances for every request still running.
+__global__ __launch_bounds__(WG) void k_status_grouped(const ReqDesc* __restrict__ reqs,
+                                                      const int* __restrict__ slots, int n,
+                                                      DevStatus* __restrict__ out) {
+    const int k = blockIdx.x;
+    if (k >= n) return;
+    const ReqDesc& rd = reqs[slots[k]];
+    DevStatus* st = rd.sw.st;
+    const int done0 = st->done, g0 = st->g;
+    __syncthreads();
+    if (!done0) {
+        if (g0 == rd.G - 1) status_update(rd.nblk, rd.blk_delta, rd.blk_amax, st, rd.trace, rd.rule);
+        if (threadIdx.x == 0) st->g = (g0 + 1) % rd.G;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) out[k] = *st;
+}
+
 // A-priori bound on the contraction of the message recursion.  With
 // c_i = max_j |A_ij| * sum_{j != i} |A_ij|, every cavity precision satisfies
 // Q_ij >= P~_i^(t-1) (messages are non-positive while Q > 0) and, by
@@ -847,14 +867,15 @@ hipError_t launch_sweep_grouped(int prec, int ksrc, int gram, int levels, int se
     }
 }
 
-hipError_t launch_served_step(int prec, int levels, int ser, const ReqDesc* reqs, const uint2* tile_items,
-                              int ntile_items, const uint2* node_items, int nnode_items, const int* slots,
-                              int nslots, DevStatus* status_out, hipStream_t s) {
+hipError_t launch_served_step(int prec, int levels, int ser, bool grouped, const ReqDesc* reqs,
+                              const uint2* tile_items, int ntile_items, const uint2* node_items, int nnode_items,
+                              const int* slots, int nslots, DevStatus* status_out, hipStream_t s) {
+    if (grouped && levels == 0) return hipErrorInvalidValue;
     hipError_t e;
     switch (prec) {
-        case PREC_FP32: e = launch_served_sweep_f32(levels, ser, reqs, tile_items, ntile_items, s); break;
-        case PREC_MIXED: e = launch_served_sweep_mixed(levels, ser, reqs, tile_items, ntile_items, s); break;
-        case PREC_FP64: e = launch_served_sweep_f64(levels, ser, reqs, tile_items, ntile_items, s); break;
+        case PREC_FP32: e = launch_served_sweep_f32(levels, ser, grouped, reqs, tile_items, ntile_items, s); break;
+        case PREC_MIXED: e = launch_served_sweep_mixed(levels, ser, grouped, reqs, tile_items, ntile_items, s); break;
+        case PREC_FP64: e = launch_served_sweep_f64(levels, ser, grouped, reqs, tile_items, ntile_items, s); break;
         default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
@@ -863,7 +884,12 @@ hipError_t launch_served_step(int prec, int levels, int ser, const ReqDesc* reqs
         hipLaunchKernelGGL(k_finalize_batched<float>, dim3(gf), dim3(WG), 0, s, reqs, node_items, nnode_items);
     else
         hipLaunchKernelGGL(k_finalize_batched<double>, dim3(gf), dim3(WG), 0, s, reqs, node_items, nnode_items);
-    hipLaunchKernelGGL(k_status_batched, dim3(std::max(1, nslots)), dim3(WG), 0, s, reqs, slots, nslots, status_out);
+    if (grouped)
+        hipLaunchKernelGGL(k_status_grouped, dim3(std::max(1, nslots)), dim3(WG), 0, s, reqs, slots, nslots,
+                           status_out);
+    else
+        hipLaunchKernelGGL(k_status_batched, dim3(std::max(1, nslots)), dim3(WG), 0, s, reqs, slots, nslots,
+                           status_out);
     return hipGetLastError();
 }
 

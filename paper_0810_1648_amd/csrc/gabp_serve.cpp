@@ -138,6 +138,13 @@ struct Req {
     int levels = 0;      // 0: stored pair records; >= 1: stateless levels
     int ser = 0;         // stateless reciprocals: 0 exact, 1 / 2 series (top-level terms)
     double rho = 0.0;    // contraction bound
+    // grouped schedule (stateless plans): G groups of whole block rows, the
+    // group the next step visits, the list entries of every group (into
+    // gent from goff[g]) and the first node block of every group
+    bool grouped = false;
+    int G = 1, gcur = 0;
+    std::vector<uint32_t> gent;
+    std::vector<int64_t> goff, gb0;
 };
 
 constexpr int kRing = 8;   // aggregate ring slots (stateless form)
@@ -200,6 +207,14 @@ struct gabp_server {
         int* d_slots = nullptr; int* h_slots = nullptr;
         int ntiles = 0, nnodes = 0, nslots = 0;
         std::vector<int> slot_list;
+        // grouped: the items of one step depend on each request's group, so
+        // every step of a poll has its own lists
+        bool grouped = false;
+        struct StepLists {
+            uint2* d_tiles = nullptr; uint2* h_tiles = nullptr; size_t cap_tiles = 0;
+            uint2* d_nodes = nullptr; uint2* h_nodes = nullptr; size_t cap_nodes = 0;
+        };
+        std::vector<StepLists> steps;
     };
     std::map<int, Group> groups;
     // statistics
@@ -294,6 +309,36 @@ hipError_t setup_request(gabp_server* S, Req& r) {
         S->arena.release_all(sz, of);
         for (int b : planes) { r.footprint -= align_up(r.sizes[b]); r.sizes[b] = 0; }
     }
+    // grouped schedule (same groups and lists as a single solve): stateless
+    // plans only; stored pair records run the synchronous schedule
+    r.grouped = stateless && r.p.schedule == GABP_SCHED_GROUPED;
+    r.G = 1;
+    r.gcur = 0;
+    if (r.grouped) {
+        const int NB = r.NB, G = std::min(r.p.sched_groups > 0 ? r.p.sched_groups : 16, NB);
+        auto grp = [&](int I) { return (int)((int64_t)I * G / NB); };
+        std::vector<std::vector<uint32_t>> dl(G);
+        for (int I = 0; I < NB; ++I)
+            for (int J = I; J < NB; ++J) {
+                const uint32_t k = (uint32_t)tile_index(I, J, NB);
+                const int gi = grp(I), gj = grp(J);
+                const uint32_t in = (gi == gj) ? GE_WITHIN : 0u;
+                dl[gj].push_back(k | in);
+                dl[gi].push_back(k | GE_BWD | in);
+            }
+        r.gent.clear();
+        r.goff.assign(G + 1, 0);
+        for (int g = 0; g < G; ++g) {
+            r.goff[g] = (int64_t)r.gent.size();
+            r.gent.insert(r.gent.end(), dl[g].begin(), dl[g].end());
+        }
+        r.goff[G] = (int64_t)r.gent.size();
+        r.gb0.assign(G + 1, NB);
+        int gc = 0;
+        for (int I = 0; I < NB; ++I)
+            while (gc <= G && grp(I) >= gc) r.gb0[gc++] = I;
+        r.G = G;
+    }
     const int R = stateless ? kRing : 1;
     CK(launch_init(r.prec, r.N, r.NPAD, R, (double*)P(B_ADIAG), (float*)P(B_Y), P(B_PT), P(B_S),
                    (double*)P(B_ALPHA), (DevStatus*)P(B_STATUS), s));
@@ -324,12 +369,13 @@ hipError_t setup_request(gabp_server* S, Req& r) {
     d.trace = (double*)P(B_TRACE);
     d.rule = StopRule{r.p.tol_abs, r.p.tol_rel, r.p.stagnation_rel, r.p.max_sweeps, r.p.stagnation_window};
     d.nblk = (int)((r.N + WG - 1) / WG);
+    d.G = r.G;
     CK(hipMemcpyAsync(S->d_reqs + r.slot, S->h_reqs + r.slot, sizeof(ReqDesc), hipMemcpyHostToDevice, s));
 #undef CK
     return hipSuccess;
 }
 
-inline int group_key(const Req& r) { return r.prec * 100 + r.ser * 10 + r.levels; }
+inline int group_key(const Req& r) { return (r.grouped ? 1000 : 0) + r.prec * 100 + r.ser * 10 + r.levels; }
 
 // Rebuilds the per-group work lists from the active slots.
 hipError_t rebuild_lists(gabp_server* S) {
@@ -342,6 +388,7 @@ hipError_t rebuild_lists(gabp_server* S) {
         G.prec = r->prec;
         G.levels = r->levels;
         G.ser = r->ser;
+        G.grouped = r->grouped;
         G.slot_list.push_back((int)k);
     }
     for (auto& kv : S->groups) {
@@ -350,6 +397,16 @@ hipError_t rebuild_lists(gabp_server* S) {
             const size_t A = S->slots.size();
             if ((e = hipMalloc((void**)&G.d_slots, A * sizeof(int))) != hipSuccess) return e;
             if ((e = hipHostMalloc((void**)&G.h_slots, A * sizeof(int), hipHostMallocDefault)) != hipSuccess) return e;
+        }
+        if (G.grouped) {
+            // per-step item lists are built at launch time (build_step)
+            for (size_t q = 0; q < G.slot_list.size(); ++q) G.h_slots[q] = G.slot_list[q];
+            G.nslots = (int)G.slot_list.size();
+            if (G.nslots &&
+                (e = hipMemcpyAsync(G.d_slots, G.h_slots, G.slot_list.size() * sizeof(int), hipMemcpyHostToDevice,
+                                    S->stream)) != hipSuccess)
+                return e;
+            continue;
         }
         size_t nt = 0, nn = 0;
         for (int k : G.slot_list) {
@@ -375,6 +432,39 @@ hipError_t rebuild_lists(gabp_server* S) {
             if ((e = hipMemcpyAsync(G.d_slots, G.h_slots, G.slot_list.size() * sizeof(int), hipMemcpyHostToDevice, S->stream)) != hipSuccess) return e;
         }
     }
+    return hipSuccess;
+}
+
+// Items of one grouped step (buffer k of the poll): every request's list
+// entries and node blocks of its current group, which then advances.
+hipError_t build_step(gabp_server* S, gabp_server::Group& G, int k, int& ntiles, int& nnodes) {
+    hipError_t e;
+    if ((int)G.steps.size() <= k) G.steps.resize(k + 1);
+    auto& L = G.steps[k];
+    size_t nt = 0, nn = 0;
+    for (int q : G.slot_list) {
+        const Req* r = S->slots[q];
+        nt += (size_t)(r->goff[r->gcur + 1] - r->goff[r->gcur]);
+        nn += (size_t)(r->gb0[r->gcur + 1] - r->gb0[r->gcur]);
+    }
+    if ((e = grow(L.d_tiles, L.h_tiles, L.cap_tiles, std::max<size_t>(nt, 1))) != hipSuccess) return e;
+    if ((e = grow(L.d_nodes, L.h_nodes, L.cap_nodes, std::max<size_t>(nn, 1))) != hipSuccess) return e;
+    size_t it = 0, in = 0;
+    for (int q : G.slot_list) {
+        Req* r = S->slots[q];
+        const int g = r->gcur;
+        for (int64_t u = r->goff[g]; u < r->goff[g + 1]; ++u) L.h_tiles[it++] = make_uint2((unsigned)q, r->gent[(size_t)u]);
+        const int64_t nblk = (r->N + WG - 1) / WG;
+        for (int64_t b = r->gb0[g]; b < std::min<int64_t>(r->gb0[g + 1], nblk); ++b)
+            L.h_nodes[in++] = make_uint2((unsigned)q, (unsigned)b);
+        r->gcur = (g + 1) % r->G;
+    }
+    ntiles = (int)it;
+    nnodes = (int)in;
+    if (it && (e = hipMemcpyAsync(L.d_tiles, L.h_tiles, it * sizeof(uint2), hipMemcpyHostToDevice, S->stream)) != hipSuccess)
+        return e;
+    if (in && (e = hipMemcpyAsync(L.d_nodes, L.h_nodes, in * sizeof(uint2), hipMemcpyHostToDevice, S->stream)) != hipSuccess)
+        return e;
     return hipSuccess;
 }
 
@@ -473,9 +563,20 @@ void worker_loop(gabp_server* S) {
             int base = 0;
             for (auto& kv : S->groups) {
                 auto& G = kv.second;
-                if (G.nslots && e == hipSuccess)
-                    e = launch_served_step(G.prec, G.levels, G.ser, S->d_reqs, G.d_tiles, G.ntiles, G.d_nodes,
-                                           G.nnodes, G.d_slots, G.nslots, S->d_stat + base, S->stream);
+                if (G.nslots && e == hipSuccess) {
+                    if (G.grouped) {
+                        int nt = 0, nn = 0;
+                        e = build_step(S, G, k, nt, nn);
+                        if (e == hipSuccess)
+                            e = launch_served_step(G.prec, G.levels, G.ser, true, S->d_reqs, G.steps[k].d_tiles, nt,
+                                                   G.steps[k].d_nodes, nn, G.d_slots, G.nslots, S->d_stat + base,
+                                                   S->stream);
+                    } else {
+                        e = launch_served_step(G.prec, G.levels, G.ser, false, S->d_reqs, G.d_tiles, G.ntiles,
+                                               G.d_nodes, G.nnodes, G.d_slots, G.nslots, S->d_stat + base,
+                                               S->stream);
+                    }
+                }
                 base += G.nslots;
             }
         }
@@ -591,8 +692,7 @@ gabp_status gabp_server_submit(gabp_server* S, const float* X, const float* y, i
     std::string why;
     if (check_params(params, why) != GABP_OK) return GABP_E_INVALID;
     if (params->kernel != GABP_KERNEL_RBF) return GABP_E_INVALID;
-    if (params->kstore == GABP_KSTORE_RECOMPUTE || params->schedule != GABP_SCHED_SYNC ||
-        params->box_mode == GABP_BOX_PROJECT)
+    if (params->kstore == GABP_KSTORE_RECOMPUTE || params->box_mode == GABP_BOX_PROJECT)
         return GABP_E_INVALID;
     if (N > (int64_t)TILE * 65535) return GABP_E_INVALID;
     for (int64_t k = 0; k < N * m; ++k)
@@ -724,6 +824,12 @@ void gabp_server_destroy(gabp_server* S) {
         if (G.h_nodes) (void)hipHostFree(G.h_nodes);
         if (G.d_slots) (void)hipFree(G.d_slots);
         if (G.h_slots) (void)hipHostFree(G.h_slots);
+        for (auto& L : G.steps) {
+            if (L.d_tiles) (void)hipFree(L.d_tiles);
+            if (L.h_tiles) (void)hipHostFree(L.h_tiles);
+            if (L.d_nodes) (void)hipFree(L.d_nodes);
+            if (L.h_nodes) (void)hipHostFree(L.h_nodes);
+        }
     }
     if (S->d_reqs) (void)hipFree(S->d_reqs);
     if (S->h_reqs) (void)hipHostFree(S->h_reqs);

@@ -12,9 +12,9 @@ hipError_t launch_sweep_f32(int ksrc, int gram, int levels, bool first, int ser,
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_served_sweep_f32(int levels, int ser, const ReqDesc* reqs, const uint2* items, int n,
-                                     hipStream_t s) {
-    return served_sweep<float, float, float>(levels, ser, reqs, items, n, s);
+hipError_t launch_served_sweep_f32(int levels, int ser, bool grouped, const ReqDesc* reqs, const uint2* items,
+                                     int n, hipStream_t s) {
+    return served_sweep<float, float, float>(levels, ser, grouped, reqs, items, n, s);
 }
 
 hipError_t launch_sweep_grouped_f32(int ksrc, int gram, int levels, int ser, const SweepArgs& a,

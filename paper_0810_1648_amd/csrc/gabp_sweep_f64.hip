@@ -12,9 +12,9 @@ hipError_t launch_sweep_f64(int ksrc, int gram, int levels, bool first, int ser,
     return hipErrorInvalidValue;   // FP64 K' is always materialised
 }
 
-hipError_t launch_served_sweep_f64(int levels, int ser, const ReqDesc* reqs, const uint2* items, int n,
-                                     hipStream_t s) {
-    return served_sweep<double, double, double>(levels, ser, reqs, items, n, s);
+hipError_t launch_served_sweep_f64(int levels, int ser, bool grouped, const ReqDesc* reqs, const uint2* items,
+                                     int n, hipStream_t s) {
+    return served_sweep<double, double, double>(levels, ser, grouped, reqs, items, n, s);
 }
 
 hipError_t launch_sweep_grouped_f64(int ksrc, int gram, int levels, int ser, const SweepArgs& a,

@@ -17,9 +17,9 @@ hipError_t launch_sweep_mixed(int ksrc, int gram, int levels, bool first, int se
     }
 }
 
-hipError_t launch_served_sweep_mixed(int levels, int ser, const ReqDesc* reqs, const uint2* items, int n,
-                                     hipStream_t s) {
-    return served_sweep<float, double, double>(levels, ser, reqs, items, n, s);
+hipError_t launch_served_sweep_mixed(int levels, int ser, bool grouped, const ReqDesc* reqs, const uint2* items,
+                                     int n, hipStream_t s) {
+    return served_sweep<float, double, double>(levels, ser, grouped, reqs, items, n, s);
 }
 
 hipError_t launch_sweep_grouped_mixed(int ksrc, int gram, int levels, int ser, const SweepArgs& a,
