@@ -122,6 +122,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-load", type=float, default=0.8, help="offered load / measured capacity")
     ap.add_argument("--serve-precision", default="fp32", choices=["fp32", "mixed", "fp64"])
+    ap.add_argument("--serve-schedule", default="grouped", choices=["grouped", "sync"],
+                    help="schedule of the served requests (the other one is measured beside it)")
     ap.add_argument("--calib-copy-gb", type=float, default=0.0,
                     help="also run a plain device copy of this many GB (counter calibration)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "sweep_traffic.json"))
@@ -151,16 +153,18 @@ def solve_steps(torch, gabp, wl, X, y, params, steps, warmup):
     return wall, sweeps, ktime, klaunch, info
 
 
-def serving_bench(gabp, inputs, n_req, load, precision, seq_sample=24):
+def serving_bench(gabp, inputs, n_req, load, precision, schedule="grouped", seq_sample=24):
     """Serving stream: N log-uniform in [1k, 16k], m in {8, 32, 128}, C in
-    {0.1, 1, 10}, two-blob data with per-request seed, gamma = 1/m.  First the
-    closed-loop capacity (all requests queued at once), then an open loop
-    with Poisson arrivals at `load` x capacity for the latency percentiles,
-    then sequential single solves of a sample for comparison."""
+    {0.1, 1, 10}, two-blob data with per-request seed, gamma = 1/m, every
+    request with the given schedule (grouped: stateless plans visit one group
+    per step, stored plans run synchronously).  First the closed-loop
+    capacity (all requests queued at once), then an open loop with Poisson
+    arrivals at `load` x capacity for the latency percentiles, then
+    sequential single solves of a sample for comparison (seq_sample > 0)."""
     import numpy as np
     stream = inputs.serving_stream(n_req, rate_per_s=1.0, seed=3)
     kws = [dict(gamma=r.workload.gamma, C=r.workload.C, precision=precision, tol_rel=r.workload.tol_rel,
-                kstore="materialise", edge_state="auto") for r in stream]
+                kstore="materialise", edge_state="auto", schedule=schedule) for r in stream]
     sp = dict(arena_bytes=int(120e9), max_active=64, steps_per_poll=2)
     # closed loop
     with gabp.GabpServer(**sp) as srv:
@@ -177,7 +181,7 @@ def serving_bench(gabp, inputs, n_req, load, precision, seq_sample=24):
             key = "stored" if i["stateless_levels"] == 0 else f"stateless_{i['stateless_levels']}"
             plan_mix[key] = plan_mix.get(key, 0) + 1
     capacity = n_req / cap_wall
-    print(f"[bench] serving closed loop: {n_req} solves in {cap_wall:.2f} s", file=sys.stderr, flush=True)
+    print(f"[bench] serving ({schedule}) closed loop: {n_req} solves in {cap_wall:.2f} s", file=sys.stderr, flush=True)
     # open loop, Poisson arrivals at load x capacity
     rate = load * capacity
     rng = np.random.default_rng(11)
@@ -194,19 +198,21 @@ def serving_bench(gabp, inputs, n_req, load, precision, seq_sample=24):
             srv.wait(t)
         open_wall = time.perf_counter() - t0
         opened = srv.stats()
-    print(f"[bench] serving open loop at {rate:.1f}/s: {open_wall:.2f} s", file=sys.stderr, flush=True)
+    print(f"[bench] serving ({schedule}) open loop at {rate:.1f}/s: {open_wall:.2f} s", file=sys.stderr, flush=True)
     # sequential single solves (one handle, one request at a time) on a sample
     k = min(seq_sample, n_req)
-    t0 = time.perf_counter()
-    for r, kw in zip(stream[:k], kws[:k]):
-        h = gabp.GabpSVM(**kw)
-        h.solve(r.workload.X, r.workload.y)
-        h.close()
-    seq_wall = time.perf_counter() - t0
-    work_all = sum(r.workload.N ** 2 for r in stream)
-    work_k = sum(r.workload.N ** 2 for r in stream[:k])
-    seq_rate = k / seq_wall * (work_k / k) / (work_all / n_req)
-    return {"requests": n_req, "precision": precision,
+    seq_rate = None
+    if k > 0:
+        t0 = time.perf_counter()
+        for r, kw in zip(stream[:k], kws[:k]):
+            h = gabp.GabpSVM(**kw)
+            h.solve(r.workload.X, r.workload.y)
+            h.close()
+        seq_wall = time.perf_counter() - t0
+        work_all = sum(r.workload.N ** 2 for r in stream)
+        work_k = sum(r.workload.N ** 2 for r in stream[:k])
+        seq_rate = k / seq_wall * (work_k / k) / (work_all / n_req)
+    return {"requests": n_req, "precision": precision, "schedule": schedule,
             "N_range": [int(min(r.workload.N for r in stream)), int(max(r.workload.N for r in stream))],
             "capacity_solves_per_s": capacity, "offered_rate_per_s": rate, "load": load,
             "p50_ms": opened["p50_ms"], "p99_ms": opened["p99_ms"], "mean_ms": opened["mean_ms"],
@@ -217,9 +223,9 @@ def serving_bench(gabp, inputs, n_req, load, precision, seq_sample=24):
             "mean_sweeps": float(np.mean(sweeps)), "plan_mix": plan_mix,
             "failed": opened["failed"] + closed["failed"],
             "sequential_solves_per_s_est": seq_rate,
-            "sequential_sample": f"first {k} requests solved one at a time on one handle, rate scaled by "
-                                 f"the stream's mean N^2 over the sample's",
-            "batching_speedup": capacity / seq_rate if seq_rate > 0 else None}
+            "sequential_sample": (f"first {k} requests solved one at a time on one handle, rate scaled by "
+                                  f"the stream's mean N^2 over the sample's") if k > 0 else None,
+            "batching_speedup": capacity / seq_rate if seq_rate else None}
 
 
 def predict_bench(torch, gabp, inputs, wl, X, y, params, n_test, reps=5):
@@ -326,7 +332,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     if a.serve_only:
-        res = serving_bench(gabp, inputs, a.serve_requests, a.serve_load, a.serve_precision)
+        res = serving_bench(gabp, inputs, a.serve_requests, a.serve_load, a.serve_precision, a.serve_schedule)
         print(json.dumps({"metric": "served GaBP solves: p50/p99 latency", "value": res["throughput_solves_per_s"],
                           "unit": "solves/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
                           "serving": res}), flush=True)
@@ -451,7 +457,12 @@ def main():
 
     serving = None
     if not a.no_serve:
-        serving = serving_bench(gabp, inputs, a.serve_requests, a.serve_load, a.serve_precision)
+        serving = serving_bench(gabp, inputs, a.serve_requests, a.serve_load, a.serve_precision, a.serve_schedule)
+        other = "sync" if a.serve_schedule == "grouped" else "grouped"
+        o = serving_bench(gabp, inputs, a.serve_requests, a.serve_load, a.serve_precision, other, seq_sample=0)
+        serving[f"{other}_schedule"] = {k: o[k] for k in ("capacity_solves_per_s", "offered_rate_per_s", "p50_ms",
+                                                         "p99_ms", "throughput_solves_per_s", "mean_sweeps",
+                                                         "plan_mix")}
 
     cpu = None
     if not a.no_cpu_baseline:
