@@ -130,6 +130,15 @@ __device__ inline double rcp_fast(double x) {
     return __builtin_isinf(x) ? 0.0 : r;    // 1/inf = 0 (Newton would give NaN)
 }
 
+// Workgroups go to the eight XCDs in turn (workgroup b to XCD b mod 8).
+// This index of workgroup b in [0, n) (n = the grid) gives every XCD one
+// contiguous range instead, so that work items sharing data (neighbouring
+// nodes and edges, tiles of one super-block) meet in the same L2.
+__device__ inline int64_t xcd_contiguous(int64_t b, int64_t n) {
+    const int64_t x = b & 7, q = b >> 3, base = n >> 3, rem = n & 7;
+    return x * base + (x < rem ? x : rem) + q;
+}
+
 struct TileCoord { int I, J; };
 __device__ inline TileCoord tile_of(const uint32_t* tiles) {
     const uint32_t ij = tiles[blockIdx.x];

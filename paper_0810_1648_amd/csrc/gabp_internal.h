@@ -115,7 +115,8 @@ hipError_t launch_stage(const float* X, const double* mean, int64_t N, int64_t m
                         int64_t NPAD, int m_pad, int kind, float* f32, uint16_t* hi,
                         uint16_t* lo, uint16_t* lo2, double* f64, float* nrm, hipStream_t s);
 // FP32-stored K' (every Gram kind but FP64) together with the row/column
-// sum and maximum partials of k_rowsum, in one pass.
+// sum and maximum partials of k_rowsum, in one pass.  `tiles` lists the
+// upper tiles in any order (each is written at its tile_index position).
 hipError_t launch_gram_sums(const Features& F, const KernelParams& kp, const uint32_t* tiles, int64_t ntiles,
                             void* Kp, int NB, double* psum, double* pmax, hipStream_t s);
 hipError_t launch_gram(const Features& F, const KernelParams& kp, const uint32_t* tiles,

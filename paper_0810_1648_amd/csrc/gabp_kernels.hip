@@ -158,8 +158,11 @@ template <int KIND, int MP>
 __global__ __launch_bounds__(WG) void k_gram_sums(Features F, KernelParams kp, const uint32_t* __restrict__ tiles,
                                                  float* __restrict__ Kp, int NB, double* __restrict__ psum,
                                                  double* __restrict__ pmax) {
-    const TileCoord tc = tile_of(tiles);
-    const size_t tbase = (size_t)blockIdx.x * TT;
+    // tiles in list order (any order of the upper tiles, read XCD-contiguously);
+    // each is written at its own position of the plane
+    const uint32_t ij = tiles[xcd_contiguous(blockIdx.x, gridDim.x)];
+    const TileCoord tc{(int)(ij >> 16), (int)(ij & 0xFFFFu)};
+    const size_t tbase = (size_t)tile_index(tc.I, tc.J, NB) * TT;
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, h = l >> 5, l32 = l & 31;
     __shared__ double csum[4][TILE];
     __shared__ float cmax[4][TILE];

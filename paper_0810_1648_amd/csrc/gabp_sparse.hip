@@ -25,14 +25,6 @@ namespace gabp {
 
 namespace {
 
-// Workgroups go to the eight XCDs in turn (workgroup b to XCD b mod 8).
-// This index of workgroup b in [0, n) (n = the grid) gives every XCD one
-// contiguous range instead, so that work items sharing data (neighbouring
-// nodes and edges, tiles of one super-block) meet in the same L2.
-__device__ inline int64_t xcd_contiguous(int64_t b, int64_t n) {
-    const int64_t x = b & 7, q = b >> 3, base = n >> 3, rem = n & 7;
-    return x * base + (x < rem ? x : rem) + q;
-}
 
 // Thresholded distances of one tile on MFMA.  The rows are augmented
 // (k_sp_augment): A row a_i = (x_i, n_i, 1), B row b_j = (x_j, -1/2, -n_j/2)

@@ -357,9 +357,26 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     // FP32-stored K' is built together with the row-sum partials (fused_sums)
     const bool fused_sums = rbf && kmat && gram != GRAM_F64;
     if (rbf) {
-        if (fused_sums)
-            HIPCHK(h, launch_gram_sums(F, kp, h->tiles.as<uint32_t>(), nt, h->Kp.p, NB, h->partP.as<double>(),
+        if (fused_sums) {
+            // build order: super-blocks of S x S tiles (their 2 S row fragments
+            // stay in one XCD's L2); the sweep keeps the row-major list
+            const uint32_t* order = h->tiles.as<uint32_t>();
+            const int planes = (gram == GRAM_F32) ? 2 : (gram == GRAM_BF16) ? 1 : (gram == GRAM_BF16X3) ? 2 : 3;
+            const int64_t frag_bytes = (int64_t)TILE * m_pad * 2 * planes;
+            const int S = (int)std::max<int64_t>(4, std::min<int64_t>(16, ((int64_t)1 << 21) / (2 * frag_bytes)));
+            size_t ob = 0;
+            if (h->sp_tsel.ensure((size_t)nt * 4) == hipSuccess && h->sp_keys.ensure((size_t)nt * 8) == hipSuccess &&
+                h->sp_keys2.ensure((size_t)nt * 8) == hipSuccess &&
+                sp_tile_order(nullptr, &ob, nullptr, nt, S, NB, nullptr, nullptr, s) == hipSuccess &&
+                h->sp_tmp.ensure(ob) == hipSuccess) {
+                HIPCHK(h, hipMemcpyAsync(h->sp_tsel.p, h->tiles.p, (size_t)nt * 4, hipMemcpyDeviceToDevice, s));
+                HIPCHK(h, sp_tile_order(h->sp_tmp.p, &ob, h->sp_tsel.as<uint32_t>(), nt, S, NB,
+                                        h->sp_keys.as<uint64_t>(), h->sp_keys2.as<uint64_t>(), s));
+                order = h->sp_tsel.as<uint32_t>();
+            }
+            HIPCHK(h, launch_gram_sums(F, kp, order, nt, h->Kp.p, NB, h->partP.as<double>(),
                                        h->partE.as<double>(), s));
+        }
         else if (kmat)
             HIPCHK(h, launch_gram(F, kp, h->tiles.as<uint32_t>(), nt, h->Kp.p, s));
         HIPCHK(h, launch_fill_value(h->kdiag.as<double>(), N, 1.0 + lam * lam, s));
