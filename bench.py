@@ -122,6 +122,7 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-load", type=float, default=0.8, help="offered load / measured capacity")
     ap.add_argument("--serve-precision", default="fp32", choices=["fp32", "mixed", "fp64"])
+    ap.add_argument("--serve-steps-per-poll", type=int, default=2, help="server steps between status reads")
     ap.add_argument("--serve-schedule", default="grouped", choices=["grouped", "sync"],
                     help="schedule of the served requests (the other one is measured beside it)")
     ap.add_argument("--calib-copy-gb", type=float, default=0.0,
@@ -153,7 +154,7 @@ def solve_steps(torch, gabp, wl, X, y, params, steps, warmup):
     return wall, sweeps, ktime, klaunch, info
 
 
-def serving_bench(gabp, inputs, n_req, load, precision, schedule="grouped", seq_sample=24):
+def serving_bench(gabp, inputs, n_req, load, precision, schedule="grouped", seq_sample=24, steps_per_poll=2):
     """Serving stream: N log-uniform in [1k, 16k], m in {8, 32, 128}, C in
     {0.1, 1, 10}, two-blob data with per-request seed, gamma = 1/m, every
     request with the given schedule (grouped: stateless plans visit one group
@@ -165,7 +166,7 @@ def serving_bench(gabp, inputs, n_req, load, precision, schedule="grouped", seq_
     stream = inputs.serving_stream(n_req, rate_per_s=1.0, seed=3)
     kws = [dict(gamma=r.workload.gamma, C=r.workload.C, precision=precision, tol_rel=r.workload.tol_rel,
                 kstore="materialise", edge_state="auto", schedule=schedule) for r in stream]
-    sp = dict(arena_bytes=int(120e9), max_active=64, steps_per_poll=2)
+    sp = dict(arena_bytes=int(120e9), max_active=64, steps_per_poll=steps_per_poll)
     # closed loop
     with gabp.GabpServer(**sp) as srv:
         t0 = time.perf_counter()
@@ -332,7 +333,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     if a.serve_only:
-        res = serving_bench(gabp, inputs, a.serve_requests, a.serve_load, a.serve_precision, a.serve_schedule)
+        res = serving_bench(gabp, inputs, a.serve_requests, a.serve_load, a.serve_precision, a.serve_schedule,
+                            steps_per_poll=a.serve_steps_per_poll)
         print(json.dumps({"metric": "served GaBP solves: p50/p99 latency", "value": res["throughput_solves_per_s"],
                           "unit": "solves/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
                           "serving": res}), flush=True)
@@ -457,9 +459,11 @@ def main():
 
     serving = None
     if not a.no_serve:
-        serving = serving_bench(gabp, inputs, a.serve_requests, a.serve_load, a.serve_precision, a.serve_schedule)
+        serving = serving_bench(gabp, inputs, a.serve_requests, a.serve_load, a.serve_precision, a.serve_schedule,
+                                steps_per_poll=a.serve_steps_per_poll)
         other = "sync" if a.serve_schedule == "grouped" else "grouped"
-        o = serving_bench(gabp, inputs, a.serve_requests, a.serve_load, a.serve_precision, other, seq_sample=0)
+        o = serving_bench(gabp, inputs, a.serve_requests, a.serve_load, a.serve_precision, other, seq_sample=0,
+                          steps_per_poll=a.serve_steps_per_poll)
         serving[f"{other}_schedule"] = {k: o[k] for k in ("capacity_solves_per_s", "offered_rate_per_s", "p50_ms",
                                                          "p99_ms", "throughput_solves_per_s", "mean_sweeps",
                                                          "plan_mix")}

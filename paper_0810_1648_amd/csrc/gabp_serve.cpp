@@ -7,7 +7,10 @@
 //      runs their setup kernels (staging, K' tiles, diagonal, sweep 0);
 //   2. launches `steps_per_poll` batched steps over all active requests
 //      (persistent sweep over the union of their tiles, batched finalize,
-//      batched stop rule), one launch group per precision;
+//      batched stop rule), one launch group per precision, level count and
+//      reciprocal form; requests on the grouped schedule have launch groups
+//      of their own, whose step is one group visit of every request (item
+//      lists built per step from each request's current group);
 //   3. reads back the packed statuses, downloads alpha of finished requests
 //      and returns their arena blocks.
 // Device memory comes from one arena allocated at creation, so no hipMalloc
