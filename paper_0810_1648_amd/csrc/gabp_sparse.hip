@@ -4,9 +4,11 @@
 // them and no message on the others.  GaBP itself is unchanged (Algorithm 2
 // with N(i) the kept neighbours); the pair records live in edge order.
 //
-// Build (every pair is examined once, on MFMA, as for the dense K'):
-//   k_sp_count  kept pairs i < j of a strided sample of the tiles: an
-//               estimate that sizes the fill's output;
+// Build (every pair of the unpruned tiles is examined on MFMA, over rows
+// augmented so that the Gram is -d^2 / 2):
+//   k_sp_augment the A and B rows of the build;
+//   k_sp_count  kept pairs i < j of every 32nd tile: an estimate that sizes
+//               the fill's output;
 //   k_sp_fill   per tile: 64-bit keys (i << 32 | j) and K' appended at a
 //               global cursor (arbitrary order); a second pass runs only if
 //               the estimate fell short;
@@ -14,9 +16,9 @@
 //   with the node as i-end are contiguous; a second sort by (j, i) gives
 //   the permutation listing each node's edges as j-end.
 // Sweep (Algorithm 2, synchronous, information form): one thread per edge
-// updates both directions from the previous records and aggregates; one
-// thread per node adds its incoming messages in a fixed order (its i-end
-// edges, then its j-end edges), so every result is reproducible.
+// updates both directions from the previous records and aggregates;
+// sixteen lanes per node add its incoming messages in a fixed order (its
+// i-end edges, then its j-end edges), so every result is reproducible.
 #include "gabp_device.h"
 
 #include <hipcub/hipcub.hpp>
@@ -24,7 +26,6 @@
 namespace gabp {
 
 namespace {
-
 
 // Thresholded distances of one tile on MFMA.  The rows are augmented
 // (k_sp_augment): A row a_i = (x_i, n_i, 1), B row b_j = (x_j, -1/2, -n_j/2)
