@@ -39,16 +39,20 @@ RECOMPUTE_SLOTS_PER_PAIR = 9
 PREDICT_SLOTS_PER_PAIR = 10
 
 
+# The sources of the kernels whose counter traffic is stored (the dense
+# sweeps, the grouped visit and the K' build, MIXED path).
+TRAFFIC_SOURCES = ("gabp_device.h", "gabp_internal.h", "gabp_kernels.hip", "gabp_sweep_mixed.hip")
+
+
 def device_source_hash():
-    """SHA-256 over the device sources (every .hip file and gabp_device.h, in
-    name order) of the HIP library."""
+    """SHA-256 over the sources of the kernels whose traffic is stored (in
+    name order)."""
     import hashlib
     d = os.path.join(ROOT, "paper_0810_1648_amd", "csrc")
     h = hashlib.sha256()
-    for fn in sorted(os.listdir(d)):
-        if fn.endswith(".hip") or fn == "gabp_device.h":
-            h.update(fn.encode())
-            h.update(open(os.path.join(d, fn), "rb").read())
+    for fn in sorted(TRAFFIC_SOURCES):
+        h.update(fn.encode())
+        h.update(open(os.path.join(d, fn), "rb").read())
     return h.hexdigest()
 
 
