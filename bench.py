@@ -127,6 +127,8 @@ def parse():
     ap.add_argument("--serve-load", type=float, default=0.8, help="offered load / measured capacity")
     ap.add_argument("--serve-precision", default="fp32", choices=["fp32", "mixed", "fp64"])
     ap.add_argument("--serve-steps-per-poll", type=int, default=2, help="server steps between status reads")
+    ap.add_argument("--serve-groups", type=int, default=4,
+                    help="groups of a served grouped request (0 = 16); a step visits one group of every request")
     ap.add_argument("--serve-schedule", default="grouped", choices=["grouped", "sync"],
                     help="schedule of the served requests (the other one is measured beside it)")
     ap.add_argument("--calib-copy-gb", type=float, default=0.0,
@@ -158,7 +160,8 @@ def solve_steps(torch, gabp, wl, X, y, params, steps, warmup):
     return wall, sweeps, ktime, klaunch, info
 
 
-def serving_bench(gabp, inputs, n_req, load, precision, schedule="grouped", seq_sample=24, steps_per_poll=2):
+def serving_bench(gabp, inputs, n_req, load, precision, schedule="grouped", seq_sample=24, steps_per_poll=2,
+                  groups=0):
     """Serving stream: N log-uniform in [1k, 16k], m in {8, 32, 128}, C in
     {0.1, 1, 10}, two-blob data with per-request seed, gamma = 1/m, every
     request with the given schedule (grouped: stateless plans visit one group
@@ -169,7 +172,7 @@ def serving_bench(gabp, inputs, n_req, load, precision, schedule="grouped", seq_
     import numpy as np
     stream = inputs.serving_stream(n_req, rate_per_s=1.0, seed=3)
     kws = [dict(gamma=r.workload.gamma, C=r.workload.C, precision=precision, tol_rel=r.workload.tol_rel,
-                kstore="materialise", edge_state="auto", schedule=schedule) for r in stream]
+                kstore="materialise", edge_state="auto", schedule=schedule, sched_groups=groups) for r in stream]
     sp = dict(arena_bytes=int(120e9), max_active=64, steps_per_poll=steps_per_poll)
     # closed loop
     with gabp.GabpServer(**sp) as srv:
@@ -217,7 +220,7 @@ def serving_bench(gabp, inputs, n_req, load, precision, schedule="grouped", seq_
         work_all = sum(r.workload.N ** 2 for r in stream)
         work_k = sum(r.workload.N ** 2 for r in stream[:k])
         seq_rate = k / seq_wall * (work_k / k) / (work_all / n_req)
-    return {"requests": n_req, "precision": precision, "schedule": schedule,
+    return {"requests": n_req, "precision": precision, "schedule": schedule, "sched_groups": groups,
             "N_range": [int(min(r.workload.N for r in stream)), int(max(r.workload.N for r in stream))],
             "capacity_solves_per_s": capacity, "offered_rate_per_s": rate, "load": load,
             "p50_ms": opened["p50_ms"], "p99_ms": opened["p99_ms"], "mean_ms": opened["mean_ms"],
@@ -338,7 +341,7 @@ def main():
     dev = torch.device("cuda:0")
     if a.serve_only:
         res = serving_bench(gabp, inputs, a.serve_requests, a.serve_load, a.serve_precision, a.serve_schedule,
-                            steps_per_poll=a.serve_steps_per_poll)
+                            steps_per_poll=a.serve_steps_per_poll, groups=a.serve_groups)
         print(json.dumps({"metric": "served GaBP solves: p50/p99 latency", "value": res["throughput_solves_per_s"],
                           "unit": "solves/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
                           "serving": res}), flush=True)
@@ -464,10 +467,10 @@ def main():
     serving = None
     if not a.no_serve:
         serving = serving_bench(gabp, inputs, a.serve_requests, a.serve_load, a.serve_precision, a.serve_schedule,
-                                steps_per_poll=a.serve_steps_per_poll)
+                                steps_per_poll=a.serve_steps_per_poll, groups=a.serve_groups)
         other = "sync" if a.serve_schedule == "grouped" else "grouped"
         o = serving_bench(gabp, inputs, a.serve_requests, a.serve_load, a.serve_precision, other, seq_sample=0,
-                          steps_per_poll=a.serve_steps_per_poll)
+                          steps_per_poll=a.serve_steps_per_poll, groups=a.serve_groups)
         serving[f"{other}_schedule"] = {k: o[k] for k in ("capacity_solves_per_s", "offered_rate_per_s", "p50_ms",
                                                          "p99_ms", "throughput_solves_per_s", "mean_sweeps",
                                                          "plan_mix")}
