@@ -177,13 +177,18 @@ struct ReqDesc {
 // over the (request, tile) items, batched finalize over the (request, node
 // block) items, batched stop rule for the request slots listed in `slots`,
 // whose statuses are copied to status_out[0..nslots).
-// grouped (stateless requests with G > 1): tile items are (request, group
-// list entry) pairs of each request's current group, node items its
-// group's node blocks, and the stop rule runs for a request after the visit
-// of its last group (every slot's status is still copied out).
-hipError_t launch_served_step(int prec, int levels, int ser, bool grouped, const ReqDesc* reqs,
-                              const uint2* tile_items, int ntile_items, const uint2* node_items, int nnode_items,
-                              const int* slots, int nslots, DevStatus* status_out, hipStream_t s);
+// A served step, launched in this order on one stream: the batched sweep of
+// every launch group (items (request, tile); grouped: (request, list entry)
+// of each request's current group), the batched finalize of the (request,
+// node block) items of each aggregate type (grouped: the current group's
+// blocks), and the stop rule of every active request (grouped: after the
+// visit of its last group; G = 1 is the synchronous schedule), whose
+// statuses are copied to status_out[0..nslots).
+hipError_t launch_served_sweep(int prec, int levels, int ser, bool grouped, const ReqDesc* reqs, const uint2* items,
+                               int n, hipStream_t s);
+hipError_t launch_served_finalize(bool agg_f32, const ReqDesc* reqs, const uint2* items, int n, hipStream_t s);
+hipError_t launch_served_status(const ReqDesc* reqs, const int* slots, int nslots, DevStatus* status_out,
+                                hipStream_t s);
 hipError_t launch_served_sweep_f32(int levels, int ser, bool grouped, const ReqDesc* reqs, const uint2* items, int n,
                                    hipStream_t s);
 hipError_t launch_served_sweep_mixed(int levels, int ser, bool grouped, const ReqDesc* reqs, const uint2* items,

@@ -635,20 +635,9 @@ __global__ __launch_bounds__(WG) void k_status(int nblk, const double* __restric
 
 // Served form: one workgroup per active request; also copies the request's
 // status into a packed array the host reads back in one transfer.
-__global__ __launch_bounds__(WG) void k_status_batched(const ReqDesc* __restrict__ reqs,
-                                                      const int* __restrict__ slots, int n,
-                                                      DevStatus* __restrict__ out) {
-    const int k = blockIdx.x;
-    if (k >= n) return;
-    const ReqDesc& rd = reqs[slots[k]];
-    DevStatus* st = rd.sw.st;
-    if (!st->done) status_update(rd.nblk, rd.blk_delta, rd.blk_amax, st, rd.trace, rd.rule);
-    __syncthreads();
-    if (threadIdx.x == 0) out[k] = *st;
-}
-
-// Grouped served requests: a step visits one group; after the visit of the
-// last group the stop rule runs (one sweep done), and the group index
+// Stop rule of served requests: a step visits one group of a grouped
+// request (G groups; G = 1 for the synchronous schedule); after the visit of
+// the last group the stop rule runs (one sweep done), and the group index
 // advances for every request still running.
 __global__ __launch_bounds__(WG) void k_status_grouped(const ReqDesc* __restrict__ reqs,
                                                       const int* __restrict__ slots, int n,
@@ -870,29 +859,29 @@ hipError_t launch_sweep_grouped(int prec, int ksrc, int gram, int levels, int se
     }
 }
 
-hipError_t launch_served_step(int prec, int levels, int ser, bool grouped, const ReqDesc* reqs,
-                              const uint2* tile_items, int ntile_items, const uint2* node_items, int nnode_items,
-                              const int* slots, int nslots, DevStatus* status_out, hipStream_t s) {
+hipError_t launch_served_sweep(int prec, int levels, int ser, bool grouped, const ReqDesc* reqs, const uint2* items,
+                               int n, hipStream_t s) {
     if (grouped && levels == 0) return hipErrorInvalidValue;
-    hipError_t e;
     switch (prec) {
-        case PREC_FP32: e = launch_served_sweep_f32(levels, ser, grouped, reqs, tile_items, ntile_items, s); break;
-        case PREC_MIXED: e = launch_served_sweep_mixed(levels, ser, grouped, reqs, tile_items, ntile_items, s); break;
-        case PREC_FP64: e = launch_served_sweep_f64(levels, ser, grouped, reqs, tile_items, ntile_items, s); break;
+        case PREC_FP32: return launch_served_sweep_f32(levels, ser, grouped, reqs, items, n, s);
+        case PREC_MIXED: return launch_served_sweep_mixed(levels, ser, grouped, reqs, items, n, s);
+        case PREC_FP64: return launch_served_sweep_f64(levels, ser, grouped, reqs, items, n, s);
         default: return hipErrorInvalidValue;
     }
-    if (e != hipSuccess) return e;
-    const int gf = std::max(1, std::min(nnode_items, 2048));
-    if (prec == PREC_FP32)
-        hipLaunchKernelGGL(k_finalize_batched<float>, dim3(gf), dim3(WG), 0, s, reqs, node_items, nnode_items);
+}
+
+hipError_t launch_served_finalize(bool agg_f32, const ReqDesc* reqs, const uint2* items, int n, hipStream_t s) {
+    const int gf = std::max(1, std::min(n, 2048));
+    if (agg_f32)
+        hipLaunchKernelGGL(k_finalize_batched<float>, dim3(gf), dim3(WG), 0, s, reqs, items, n);
     else
-        hipLaunchKernelGGL(k_finalize_batched<double>, dim3(gf), dim3(WG), 0, s, reqs, node_items, nnode_items);
-    if (grouped)
-        hipLaunchKernelGGL(k_status_grouped, dim3(std::max(1, nslots)), dim3(WG), 0, s, reqs, slots, nslots,
-                           status_out);
-    else
-        hipLaunchKernelGGL(k_status_batched, dim3(std::max(1, nslots)), dim3(WG), 0, s, reqs, slots, nslots,
-                           status_out);
+        hipLaunchKernelGGL(k_finalize_batched<double>, dim3(gf), dim3(WG), 0, s, reqs, items, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_served_status(const ReqDesc* reqs, const int* slots, int nslots, DevStatus* status_out,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(k_status_grouped, dim3(std::max(1, nslots)), dim3(WG), 0, s, reqs, slots, nslots, status_out);
     return hipGetLastError();
 }
 

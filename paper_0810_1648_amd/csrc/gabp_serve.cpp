@@ -201,25 +201,25 @@ struct gabp_server {
     ReqDesc* h_reqs = nullptr;
     DevStatus* d_stat = nullptr;
     DevStatus* h_stat = nullptr;
-    // launch groups: requests sharing precision, level count and series flag
+    // launch groups: requests sharing schedule, precision, level count and
+    // reciprocal form; a synchronous group's (request, tile) items are fixed
+    // while its membership is
     struct Group {
         int prec = 0, levels = 0;
         int ser = 0;
-        uint2* d_tiles = nullptr; uint2* h_tiles = nullptr; size_t cap_tiles = 0;
-        uint2* d_nodes = nullptr; uint2* h_nodes = nullptr; size_t cap_nodes = 0;
-        int* d_slots = nullptr; int* h_slots = nullptr;
-        int ntiles = 0, nnodes = 0, nslots = 0;
-        std::vector<int> slot_list;
-        // grouped: the items of one step depend on each request's group, so
-        // every step of a poll has its own lists
         bool grouped = false;
-        struct StepLists {
-            uint2* d_tiles = nullptr; uint2* h_tiles = nullptr; size_t cap_tiles = 0;
-            uint2* d_nodes = nullptr; uint2* h_nodes = nullptr; size_t cap_nodes = 0;
-        };
-        std::vector<StepLists> steps;
+        uint2* d_tiles = nullptr; uint2* h_tiles = nullptr; size_t cap_tiles = 0;
+        int ntiles = 0, nslots = 0;
+        std::vector<int> slot_list;
     };
     std::map<int, Group> groups;
+    // every active slot, launch group by launch group (the order of d_stat)
+    int* d_slots = nullptr; int* h_slots = nullptr;
+    int nactive = 0;
+    // per step of a poll: one upload of the grouped requests' (request,
+    // entry) items and of every request's (request, node block) items
+    struct StepLists { uint2* d = nullptr; uint2* h = nullptr; size_t cap = 0; };
+    std::vector<StepLists> step_lists;
     // statistics
     std::vector<double> lat_ms, queue_ms;
     int64_t submitted = 0, completed = 0, failed = 0, steps = 0, active_sum = 0, max_active_seen = 0;
@@ -380,7 +380,8 @@ hipError_t setup_request(gabp_server* S, Req& r) {
 
 inline int group_key(const Req& r) { return (r.grouped ? 1000 : 0) + r.prec * 100 + r.ser * 10 + r.levels; }
 
-// Rebuilds the per-group work lists from the active slots.
+// Rebuilds the launch groups, their fixed tile lists and the slot order
+// from the active slots.
 hipError_t rebuild_lists(gabp_server* S) {
     hipError_t e;
     for (auto& kv : S->groups) kv.second.slot_list.clear();
@@ -394,79 +395,101 @@ hipError_t rebuild_lists(gabp_server* S) {
         G.grouped = r->grouped;
         G.slot_list.push_back((int)k);
     }
+    if (!S->d_slots) {
+        const size_t A = S->slots.size();
+        if ((e = hipMalloc((void**)&S->d_slots, A * sizeof(int))) != hipSuccess) return e;
+        if ((e = hipHostMalloc((void**)&S->h_slots, A * sizeof(int), hipHostMallocDefault)) != hipSuccess) return e;
+    }
+    int na = 0;
     for (auto& kv : S->groups) {
         auto& G = kv.second;
-        if (!G.d_slots) {
-            const size_t A = S->slots.size();
-            if ((e = hipMalloc((void**)&G.d_slots, A * sizeof(int))) != hipSuccess) return e;
-            if ((e = hipHostMalloc((void**)&G.h_slots, A * sizeof(int), hipHostMallocDefault)) != hipSuccess) return e;
-        }
-        if (G.grouped) {
-            // per-step item lists are built at launch time (build_step)
-            for (size_t q = 0; q < G.slot_list.size(); ++q) G.h_slots[q] = G.slot_list[q];
-            G.nslots = (int)G.slot_list.size();
-            if (G.nslots &&
-                (e = hipMemcpyAsync(G.d_slots, G.h_slots, G.slot_list.size() * sizeof(int), hipMemcpyHostToDevice,
-                                    S->stream)) != hipSuccess)
-                return e;
-            continue;
-        }
-        size_t nt = 0, nn = 0;
-        for (int k : G.slot_list) {
-            nt += (size_t)S->slots[k]->nt;
-            nn += (size_t)((S->slots[k]->N + WG - 1) / WG);
-        }
+        G.nslots = (int)G.slot_list.size();
+        for (int k : G.slot_list) S->h_slots[na++] = k;
+        G.ntiles = 0;
+        if (G.grouped) continue;   // per-step items (build_step)
+        size_t nt = 0;
+        for (int k : G.slot_list) nt += (size_t)S->slots[k]->nt;
         if ((e = grow(G.d_tiles, G.h_tiles, G.cap_tiles, std::max<size_t>(nt, 1))) != hipSuccess) return e;
-        if ((e = grow(G.d_nodes, G.h_nodes, G.cap_nodes, std::max<size_t>(nn, 1))) != hipSuccess) return e;
-        size_t it = 0, in = 0;
+        size_t it = 0;
         for (int k : G.slot_list) {
             Req* r = S->slots[k];
             for (int64_t t = 0; t < r->nt; ++t) G.h_tiles[it++] = make_uint2((unsigned)k, (unsigned)t);
-            const int64_t nb = (r->N + WG - 1) / WG;
-            for (int64_t b = 0; b < nb; ++b) G.h_nodes[in++] = make_uint2((unsigned)k, (unsigned)b);
         }
-        for (size_t q = 0; q < G.slot_list.size(); ++q) G.h_slots[q] = G.slot_list[q];
         G.ntiles = (int)it;
-        G.nnodes = (int)in;
-        G.nslots = (int)G.slot_list.size();
-        if (it) {
-            if ((e = hipMemcpyAsync(G.d_tiles, G.h_tiles, it * sizeof(uint2), hipMemcpyHostToDevice, S->stream)) != hipSuccess) return e;
-            if ((e = hipMemcpyAsync(G.d_nodes, G.h_nodes, in * sizeof(uint2), hipMemcpyHostToDevice, S->stream)) != hipSuccess) return e;
-            if ((e = hipMemcpyAsync(G.d_slots, G.h_slots, G.slot_list.size() * sizeof(int), hipMemcpyHostToDevice, S->stream)) != hipSuccess) return e;
-        }
+        if (it && (e = hipMemcpyAsync(G.d_tiles, G.h_tiles, it * sizeof(uint2), hipMemcpyHostToDevice, S->stream)) != hipSuccess)
+            return e;
     }
+    S->nactive = na;
+    if (na && (e = hipMemcpyAsync(S->d_slots, S->h_slots, (size_t)na * sizeof(int), hipMemcpyHostToDevice, S->stream)) != hipSuccess)
+        return e;
     return hipSuccess;
 }
 
-// Items of one grouped step (buffer k of the poll): every request's list
-// entries and node blocks of its current group, which then advances.
-hipError_t build_step(gabp_server* S, gabp_server::Group& G, int k, int& ntiles, int& nnodes) {
+// Items of step k of the poll, uploaded at once: the (request, entry) items
+// of every grouped launch group's requests' current groups, then the
+// (request, node block) items of every active request (its current group's
+// blocks on the grouped schedule, all of them otherwise), FP32 aggregates
+// first.  The grouped requests' groups then advance.
+struct StepPlan {
+    std::vector<std::pair<int64_t, int>> dir;   // per launch group (map order): offset, count
+    int64_t off_f32 = 0, off_f64 = 0;
+    int n_f32 = 0, n_f64 = 0;
+};
+
+hipError_t build_step(gabp_server* S, int k, StepPlan& P) {
     hipError_t e;
-    if ((int)G.steps.size() <= k) G.steps.resize(k + 1);
-    auto& L = G.steps[k];
-    size_t nt = 0, nn = 0;
-    for (int q : G.slot_list) {
-        const Req* r = S->slots[q];
-        nt += (size_t)(r->goff[r->gcur + 1] - r->goff[r->gcur]);
-        nn += (size_t)(r->gb0[r->gcur + 1] - r->gb0[r->gcur]);
-    }
-    if ((e = grow(L.d_tiles, L.h_tiles, L.cap_tiles, std::max<size_t>(nt, 1))) != hipSuccess) return e;
-    if ((e = grow(L.d_nodes, L.h_nodes, L.cap_nodes, std::max<size_t>(nn, 1))) != hipSuccess) return e;
-    size_t it = 0, in = 0;
-    for (int q : G.slot_list) {
-        Req* r = S->slots[q];
-        const int g = r->gcur;
-        for (int64_t u = r->goff[g]; u < r->goff[g + 1]; ++u) L.h_tiles[it++] = make_uint2((unsigned)q, r->gent[(size_t)u]);
+    if ((int)S->step_lists.size() <= k) S->step_lists.resize(k + 1);
+    auto& L = S->step_lists[k];
+    auto node_range = [](const Req* r, int64_t& b0, int64_t& b1) {
         const int64_t nblk = (r->N + WG - 1) / WG;
-        for (int64_t b = r->gb0[g]; b < std::min<int64_t>(r->gb0[g + 1], nblk); ++b)
-            L.h_nodes[in++] = make_uint2((unsigned)q, (unsigned)b);
-        r->gcur = (g + 1) % r->G;
+        if (r->grouped) { b0 = r->gb0[r->gcur]; b1 = std::min<int64_t>(r->gb0[r->gcur + 1], nblk); }
+        else { b0 = 0; b1 = nblk; }
+    };
+    size_t n = 0;
+    for (auto& kv : S->groups)
+        if (kv.second.grouped)
+            for (int q : kv.second.slot_list) {
+                const Req* r = S->slots[q];
+                n += (size_t)(r->goff[r->gcur + 1] - r->goff[r->gcur]);
+            }
+    for (int q = 0; q < S->nactive; ++q) {
+        int64_t b0, b1;
+        node_range(S->slots[S->h_slots[q]], b0, b1);
+        n += (size_t)std::max<int64_t>(b1 - b0, 0);
     }
-    ntiles = (int)it;
-    nnodes = (int)in;
-    if (it && (e = hipMemcpyAsync(L.d_tiles, L.h_tiles, it * sizeof(uint2), hipMemcpyHostToDevice, S->stream)) != hipSuccess)
-        return e;
-    if (in && (e = hipMemcpyAsync(L.d_nodes, L.h_nodes, in * sizeof(uint2), hipMemcpyHostToDevice, S->stream)) != hipSuccess)
+    if ((e = grow(L.d, L.h, L.cap, std::max<size_t>(n, 1))) != hipSuccess) return e;
+    size_t it = 0;
+    P.dir.clear();
+    for (auto& kv : S->groups) {
+        const size_t start = it;
+        if (kv.second.grouped)
+            for (int q : kv.second.slot_list) {
+                const Req* r = S->slots[q];
+                for (int64_t u = r->goff[r->gcur]; u < r->goff[r->gcur + 1]; ++u)
+                    L.h[it++] = make_uint2((unsigned)q, r->gent[(size_t)u]);
+            }
+        P.dir.emplace_back((int64_t)start, (int)(it - start));
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+        const size_t start = it;
+        for (int q = 0; q < S->nactive; ++q) {
+            const int slot = S->h_slots[q];
+            const Req* r = S->slots[slot];
+            if ((r->prec == PREC_FP32) != (pass == 0)) continue;
+            int64_t b0, b1;
+            node_range(r, b0, b1);
+            for (int64_t b = b0; b < b1; ++b) L.h[it++] = make_uint2((unsigned)slot, (unsigned)b);
+        }
+        if (pass == 0) { P.off_f32 = (int64_t)start; P.n_f32 = (int)(it - start); }
+        else { P.off_f64 = (int64_t)start; P.n_f64 = (int)(it - start); }
+    }
+    for (auto& kv : S->groups)
+        if (kv.second.grouped)
+            for (int q : kv.second.slot_list) {
+                Req* r = S->slots[q];
+                r->gcur = (r->gcur + 1) % r->G;
+            }
+    if (it && (e = hipMemcpyAsync(L.d, L.h, it * sizeof(uint2), hipMemcpyHostToDevice, S->stream)) != hipSuccess)
         return e;
     return hipSuccess;
 }
@@ -558,30 +581,31 @@ void worker_loop(gabp_server* S) {
             }
             lists_dirty = false;
         }
-        int nactive = 0;
-        for (auto& kv : S->groups) nactive += kv.second.nslots;
+        const int nactive = S->nactive;
         if (nactive == 0) continue;
         hipError_t e = hipSuccess;
+        // a step: the sweep (or group visit) of every launch group, then the
+        // finalize of every request's node blocks, then every stop rule
+        StepPlan plan;
         for (int k = 0; k < S->p.steps_per_poll && e == hipSuccess; ++k) {
-            int base = 0;
+            e = build_step(S, k, plan);
+            const uint2* items = S->step_lists.empty() ? nullptr : S->step_lists[k].d;
+            size_t gi = 0;
             for (auto& kv : S->groups) {
                 auto& G = kv.second;
-                if (G.nslots && e == hipSuccess) {
-                    if (G.grouped) {
-                        int nt = 0, nn = 0;
-                        e = build_step(S, G, k, nt, nn);
-                        if (e == hipSuccess)
-                            e = launch_served_step(G.prec, G.levels, G.ser, true, S->d_reqs, G.steps[k].d_tiles, nt,
-                                                   G.steps[k].d_nodes, nn, G.d_slots, G.nslots, S->d_stat + base,
-                                                   S->stream);
-                    } else {
-                        e = launch_served_step(G.prec, G.levels, G.ser, false, S->d_reqs, G.d_tiles, G.ntiles,
-                                               G.d_nodes, G.nnodes, G.d_slots, G.nslots, S->d_stat + base,
-                                               S->stream);
-                    }
-                }
-                base += G.nslots;
+                const auto dir = plan.dir[gi++];
+                if (!G.nslots || e != hipSuccess) continue;
+                if (G.grouped)
+                    e = launch_served_sweep(G.prec, G.levels, G.ser, true, S->d_reqs, items + dir.first, dir.second,
+                                            S->stream);
+                else
+                    e = launch_served_sweep(G.prec, G.levels, G.ser, false, S->d_reqs, G.d_tiles, G.ntiles, S->stream);
             }
+            if (e == hipSuccess && plan.n_f32)
+                e = launch_served_finalize(true, S->d_reqs, items + plan.off_f32, plan.n_f32, S->stream);
+            if (e == hipSuccess && plan.n_f64)
+                e = launch_served_finalize(false, S->d_reqs, items + plan.off_f64, plan.n_f64, S->stream);
+            if (e == hipSuccess) e = launch_served_status(S->d_reqs, S->d_slots, nactive, S->d_stat, S->stream);
         }
         if (e == hipSuccess)
             e = hipMemcpyAsync(S->h_stat, S->d_stat, (size_t)nactive * sizeof(DevStatus), hipMemcpyDeviceToHost,
@@ -823,17 +847,13 @@ void gabp_server_destroy(gabp_server* S) {
         auto& G = kv.second;
         if (G.d_tiles) (void)hipFree(G.d_tiles);
         if (G.h_tiles) (void)hipHostFree(G.h_tiles);
-        if (G.d_nodes) (void)hipFree(G.d_nodes);
-        if (G.h_nodes) (void)hipHostFree(G.h_nodes);
-        if (G.d_slots) (void)hipFree(G.d_slots);
-        if (G.h_slots) (void)hipHostFree(G.h_slots);
-        for (auto& L : G.steps) {
-            if (L.d_tiles) (void)hipFree(L.d_tiles);
-            if (L.h_tiles) (void)hipHostFree(L.h_tiles);
-            if (L.d_nodes) (void)hipFree(L.d_nodes);
-            if (L.h_nodes) (void)hipHostFree(L.h_nodes);
-        }
     }
+    for (auto& L : S->step_lists) {
+        if (L.d) (void)hipFree(L.d);
+        if (L.h) (void)hipHostFree(L.h);
+    }
+    if (S->d_slots) (void)hipFree(S->d_slots);
+    if (S->h_slots) (void)hipHostFree(S->h_slots);
     if (S->d_reqs) (void)hipFree(S->d_reqs);
     if (S->h_reqs) (void)hipHostFree(S->h_reqs);
     if (S->d_stat) (void)hipFree(S->d_stat);
