@@ -321,11 +321,10 @@ int32_t gabp_abi_version(void);
  * whether it runs alone or in a mix.  Served plans materialise K'; the edge
  * state (stored pair records or stateless) is chosen per request by the same
  * rule as gabp_svm_solve, and requests of the same precision and level count
- * share a launch.  A request with the GROUPED schedule and a stateless plan
- * advances one group visit per step (its stop rule runs after the visit of
- * its last group), with the groups and lists of gabp_svm_solve, so its alpha
- * is bitwise that of the single grouped solve; with stored pair records it
- * runs the SYNC schedule.
+ * share a launch.  A request with the GROUPED schedule advances one group
+ * visit per step (its stop rule runs after the visit of its last group),
+ * with the groups and lists of gabp_svm_solve, so its alpha is bitwise that
+ * of the single grouped solve.
  * ------------------------------------------------------------------------ */
 typedef struct gabp_server gabp_server;
 

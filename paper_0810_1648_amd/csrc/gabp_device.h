@@ -1128,9 +1128,9 @@ __global__ __launch_bounds__(WG) void k_sweep_dir(SweepArgs a, const uint32_t* _
     else sweep_tile_dir<ST, MT, AT, KSRC, GK, D, SER, true>(a, tile, within, t, sm);
 }
 
-// Served grouped visit (stateless): items are (request, list entry) pairs of
-// every request's current group, built by the host per step; the sweep
-// index of a request is its own count of completed sweeps.
+// Served grouped visit: items are (request, list entry) pairs of every
+// request's current group, built by the host per step; the sweep index of a
+// request is its own count of completed sweeps.
 template <class ST, class MT, class AT, int D, int SER>
 __global__ __launch_bounds__(WG) void k_sweep_dir_batched(const ReqDesc* __restrict__ reqs,
                                                          const uint2* __restrict__ items, int nitems) {
@@ -1199,23 +1199,20 @@ inline hipError_t with_stateless(int levels, int ser, F&& f) {
 template <class ST, class MT, class AT, int D, int SER>
 inline void served_d(bool grouped, const ReqDesc* reqs, const uint2* items, int n, hipStream_t s) {
     const int g = std::max(1, std::min(n, 2048));
-    if constexpr (D > 0) {
-        if (grouped) {
-            hipLaunchKernelGGL((k_sweep_dir_batched<ST, MT, AT, D, SER>), dim3(g), dim3(WG), 0, s, reqs, items, n);
-            return;
-        }
-    }
-    hipLaunchKernelGGL((k_sweep_batched<ST, MT, AT, D, SER>), dim3(g), dim3(WG), 0, s, reqs, items, n);
+    if (grouped)
+        hipLaunchKernelGGL((k_sweep_dir_batched<ST, MT, AT, D, SER>), dim3(g), dim3(WG), 0, s, reqs, items, n);
+    else
+        hipLaunchKernelGGL((k_sweep_batched<ST, MT, AT, D, SER>), dim3(g), dim3(WG), 0, s, reqs, items, n);
 }
 
 // levels 0: stored pair records; 1..8 stateless (1..6 with the series);
-// grouped: one group visit of stateless requests.
+// grouped: the single-direction entries of one group visit (items
+// (request, entry)); otherwise whole tiles (items (request, tile)).
 template <class ST, class MT, class AT>
 inline hipError_t served_sweep(int levels, int ser, bool grouped, const ReqDesc* reqs, const uint2* items, int n,
                                hipStream_t s) {
     if (levels == 0) {
-        if (grouped) return hipErrorInvalidValue;
-        served_d<ST, MT, AT, 0, 0>(false, reqs, items, n, s);
+        served_d<ST, MT, AT, 0, 0>(grouped, reqs, items, n, s);
         return hipGetLastError();
     }
     const hipError_t e = with_stateless(levels, ser, [&](auto L_, auto S_) {

@@ -861,7 +861,6 @@ hipError_t launch_sweep_grouped(int prec, int ksrc, int gram, int levels, int se
 
 hipError_t launch_served_sweep(int prec, int levels, int ser, bool grouped, const ReqDesc* reqs, const uint2* items,
                                int n, hipStream_t s) {
-    if (grouped && levels == 0) return hipErrorInvalidValue;
     switch (prec) {
         case PREC_FP32: return launch_served_sweep_f32(levels, ser, grouped, reqs, items, n, s);
         case PREC_MIXED: return launch_served_sweep_mixed(levels, ser, grouped, reqs, items, n, s);

@@ -141,13 +141,14 @@ struct Req {
     int levels = 0;      // 0: stored pair records; >= 1: stateless levels
     int ser = 0;         // stateless reciprocals: 0 exact, 1 / 2 series (top-level terms)
     double rho = 0.0;    // contraction bound
-    // grouped schedule (stateless plans): G groups of whole block rows, the
-    // group the next step visits, the list entries of every group (into
-    // gent from goff[g]) and the first node block of every group
+    // grouped schedule: G groups of whole block rows, the group the next step
+    // visits, the single-direction list entries of every group (into gent
+    // from goff[g]), with stored pair records the tiles inside every group
+    // (into gwin from gwoff[g]), and the first node block of every group
     bool grouped = false;
     int G = 1, gcur = 0;
-    std::vector<uint32_t> gent;
-    std::vector<int64_t> goff, gb0;
+    std::vector<uint32_t> gent, gwin;
+    std::vector<int64_t> goff, gwoff, gb0;
 };
 
 constexpr int kRing = 8;   // aggregate ring slots (stateless form)
@@ -313,29 +314,41 @@ hipError_t setup_request(gabp_server* S, Req& r) {
         for (int b : planes) { r.footprint -= align_up(r.sizes[b]); r.sizes[b] = 0; }
     }
     // grouped schedule (same groups and lists as a single solve): stateless
-    // plans only; stored pair records run the synchronous schedule
-    r.grouped = stateless && r.p.schedule == GABP_SCHED_GROUPED;
+    // plans visit every message into the group; stored pair records visit
+    // the tiles crossing the group boundary in one direction and the tiles
+    // inside the group in both
+    r.grouped = r.p.schedule == GABP_SCHED_GROUPED;
     r.G = 1;
     r.gcur = 0;
     if (r.grouped) {
         const int NB = r.NB, G = std::min(r.p.sched_groups > 0 ? r.p.sched_groups : 16, NB);
         auto grp = [&](int I) { return (int)((int64_t)I * G / NB); };
-        std::vector<std::vector<uint32_t>> dl(G);
+        std::vector<std::vector<uint32_t>> dl(G), wl(G);
         for (int I = 0; I < NB; ++I)
             for (int J = I; J < NB; ++J) {
                 const uint32_t k = (uint32_t)tile_index(I, J, NB);
                 const int gi = grp(I), gj = grp(J);
-                const uint32_t in = (gi == gj) ? GE_WITHIN : 0u;
-                dl[gj].push_back(k | in);
-                dl[gi].push_back(k | GE_BWD | in);
+                if (!stateless) {
+                    if (gi == gj) wl[gi].push_back(k);
+                    else { dl[gj].push_back(k); dl[gi].push_back(k | GE_BWD); }
+                } else {
+                    const uint32_t in = (gi == gj) ? GE_WITHIN : 0u;
+                    dl[gj].push_back(k | in);
+                    dl[gi].push_back(k | GE_BWD | in);
+                }
             }
         r.gent.clear();
+        r.gwin.clear();
         r.goff.assign(G + 1, 0);
+        r.gwoff.assign(G + 1, 0);
         for (int g = 0; g < G; ++g) {
             r.goff[g] = (int64_t)r.gent.size();
             r.gent.insert(r.gent.end(), dl[g].begin(), dl[g].end());
+            r.gwoff[g] = (int64_t)r.gwin.size();
+            r.gwin.insert(r.gwin.end(), wl[g].begin(), wl[g].end());
         }
         r.goff[G] = (int64_t)r.gent.size();
+        r.gwoff[G] = (int64_t)r.gwin.size();
         r.gb0.assign(G + 1, NB);
         int gc = 0;
         for (int I = 0; I < NB; ++I)
@@ -432,6 +445,7 @@ hipError_t rebuild_lists(gabp_server* S) {
 // first.  The grouped requests' groups then advance.
 struct StepPlan {
     std::vector<std::pair<int64_t, int>> dir;   // per launch group (map order): offset, count
+    std::vector<std::pair<int64_t, int>> win;   // stored records: the (request, tile) items inside the groups
     int64_t off_f32 = 0, off_f64 = 0;
     int n_f32 = 0, n_f64 = 0;
 };
@@ -451,6 +465,7 @@ hipError_t build_step(gabp_server* S, int k, StepPlan& P) {
             for (int q : kv.second.slot_list) {
                 const Req* r = S->slots[q];
                 n += (size_t)(r->goff[r->gcur + 1] - r->goff[r->gcur]);
+                n += (size_t)(r->gwoff[r->gcur + 1] - r->gwoff[r->gcur]);
             }
     for (int q = 0; q < S->nactive; ++q) {
         int64_t b0, b1;
@@ -460,8 +475,9 @@ hipError_t build_step(gabp_server* S, int k, StepPlan& P) {
     if ((e = grow(L.d, L.h, L.cap, std::max<size_t>(n, 1))) != hipSuccess) return e;
     size_t it = 0;
     P.dir.clear();
+    P.win.clear();
     for (auto& kv : S->groups) {
-        const size_t start = it;
+        size_t start = it;
         if (kv.second.grouped)
             for (int q : kv.second.slot_list) {
                 const Req* r = S->slots[q];
@@ -469,6 +485,14 @@ hipError_t build_step(gabp_server* S, int k, StepPlan& P) {
                     L.h[it++] = make_uint2((unsigned)q, r->gent[(size_t)u]);
             }
         P.dir.emplace_back((int64_t)start, (int)(it - start));
+        start = it;
+        if (kv.second.grouped)
+            for (int q : kv.second.slot_list) {
+                const Req* r = S->slots[q];
+                for (int64_t u = r->gwoff[r->gcur]; u < r->gwoff[r->gcur + 1]; ++u)
+                    L.h[it++] = make_uint2((unsigned)q, r->gwin[(size_t)u]);
+            }
+        P.win.emplace_back((int64_t)start, (int)(it - start));
     }
     for (int pass = 0; pass < 2; ++pass) {
         const size_t start = it;
@@ -593,12 +617,18 @@ void worker_loop(gabp_server* S) {
             size_t gi = 0;
             for (auto& kv : S->groups) {
                 auto& G = kv.second;
-                const auto dir = plan.dir[gi++];
+                const auto dir = plan.dir[gi], win = plan.win[gi];
+                ++gi;
                 if (!G.nslots || e != hipSuccess) continue;
-                if (G.grouped)
-                    e = launch_served_sweep(G.prec, G.levels, G.ser, true, S->d_reqs, items + dir.first, dir.second,
-                                            S->stream);
-                else
+                if (G.grouped) {
+                    // stored records: the tiles inside the group (both directions), then the crossing ones
+                    if (win.second)
+                        e = launch_served_sweep(G.prec, G.levels, G.ser, false, S->d_reqs, items + win.first, win.second,
+                                                S->stream);
+                    if (e == hipSuccess)
+                        e = launch_served_sweep(G.prec, G.levels, G.ser, true, S->d_reqs, items + dir.first,
+                                                dir.second, S->stream);
+                } else
                     e = launch_served_sweep(G.prec, G.levels, G.ser, false, S->d_reqs, G.d_tiles, G.ntiles, S->stream);
             }
             if (e == hipSuccess && plan.n_f32)

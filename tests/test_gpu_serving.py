@@ -140,16 +140,15 @@ def test_served_stateless_plans_equal_single(torch):
 
 
 def test_served_grouped_schedule_equals_single(torch):
-    # GROUPED requests with a stateless plan advance one group visit per
-    # step and must match the single grouped solve bitwise (alone and next
-    # to synchronous requests); with stored pair records they run the
-    # synchronous schedule and match the single synchronous solve
+    # GROUPED requests advance one group visit per step and must match the
+    # single grouped solve bitwise, with stateless plans and with stored pair
+    # records, alone and next to synchronous requests
     reqs = []
     for r in range(8):
         n = [200, 900, 2100, 4700][r % 4]             # 1 to 19 blocks
         X, y = inputs.blobs(n, 16, 7300 + r)
-        gamma = [2e-3, 1.0 / 16][r % 2]
-        prec = ["fp32", "mixed", "fp64"][r % 3]
+        gamma = [2e-3, 1.0 / 16, 0.5][r % 3]          # 0.5: stored pair records
+        prec = ["fp32", "mixed", "fp64"][(r // 3) % 3]
         kw = dict(gamma=gamma, C=1.0, precision=prec, tol_rel=1e-7, kstore="materialise",
                   schedule="grouped", sched_groups=[0, 3][r % 2])
         reqs.append((X, y, kw))
@@ -161,14 +160,11 @@ def test_served_grouped_schedule_equals_single(torch):
         s = gabp.GabpSVM(**kw)
         st = s.solve(X, y)
         d = s.plan()["stateless_depth"]
-        if kw["schedule"] == "grouped" and d == 0:   # stored records: served runs SYNC
-            s.close()
-            s = gabp.GabpSVM(**dict(kw, schedule="sync"))
-            st = s.solve(X, y)
         single.append((st, s.alpha(), s.sweeps(), d))
         s.close()
     print("single-solve levels", [d for *_, d in single], "sweeps", [sw for _, _, sw, _ in single])
-    assert sum(1 for (X, y, kw), (_, _, _, d) in zip(reqs, single) if kw["schedule"] == "grouped" and d > 0) >= 4
+    grouped_levels = [d for (X, y, kw), (_, _, _, d) in zip(reqs, single) if kw["schedule"] == "grouped"]
+    assert sum(d > 0 for d in grouped_levels) >= 3 and sum(d == 0 for d in grouped_levels) >= 1
     with gabp.GabpServer(arena_bytes=int(2e9), max_active=1) as srv:
         t = srv.submit(reqs[2][0], reqs[2][1], **reqs[2][2])
         assert srv.wait(t, 120.0)
