@@ -113,3 +113,25 @@ def test_sparse_invalid_parameters(torch):
     with pytest.raises(gabp.GabpError) as e:
         s.predict(X[:4])
     assert e.value.status == gabp.E_STATE
+
+
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+def test_sparse_box_projected_sweeps_match_oracle(torch, prec):
+    """Box projection on the sparsified system: the projected sweeps (belief
+    means clipped to [0, C] every sweep) against the oracle's projected
+    sweeps on the same sparse system, sweep by sweep, with C at the 80%
+    quantile of the unconstrained solution so that the upper bound binds."""
+    X, y, gamma, tau = _case(n=700, seed=76, degree=40)
+    A0, b0 = R.sparse_svm_system(X, y, gamma, 1.0, 1.0 / len(y), tau)
+    C = float(np.quantile(R.cholesky_solve(A0, b0), 0.8))
+    A, b = R.sparse_svm_system(X, y, gamma, C, 1.0 / len(y), tau)   # C also enters the diagonal
+    ref = R.gabp_solve_box(A, b, C, max_sweeps=8, tol_rel=0.0, keep_trajectory=True)
+    for t in (1, 3, 8):
+        s, st = _solve(X, y, gamma, tau, precision=prec, C=C, box_mode="project", max_sweeps=t, tol_abs=0.0,
+                       tol_rel=0.0, stagnation_window=0)
+        assert s.sweeps() == t
+        err = _rel(s.alpha(), ref.trajectory[t])
+        assert err <= TOL, (prec, t, err)
+        a = s.alpha()
+        assert a.min() >= 0.0 and a.max() <= C
+    assert np.sum(ref.trajectory[8] >= C * (1 - 1e-12)) > 0
