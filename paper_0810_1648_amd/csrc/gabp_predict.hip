@@ -137,10 +137,10 @@ __global__ __launch_bounds__(WG) void k_predict_mfma(Features Ft, Features Fq, c
 // 16 bytes lane `lane` feeds the MFMA at k-step `step`), together with the
 // block's norms and weights.  The next block's chunks are loaded into
 // registers while the current block is multiplied, then stored into the
-// other buffer (one barrier per block).  A workgroup covers at most eight
+// other buffer (one barrier per block).  A workgroup covers at most 32
 // training blocks (the chunk): each lane sums its training points' terms in
-// FP32 (at most eight per query), then the 32 training lanes are added in
-// FP64.
+// FP32 (at most 32 per query, an error below 32 ulp of the sum of their
+// magnitudes), then the 32 training lanes are added in FP64.
 template <int KIND, int MP>
 __global__ __launch_bounds__(WG) void k_predict_lds(Features Ft, Features Fq, const double* __restrict__ w,
                                                     int64_t nblk32, int bpc, float neg_gamma_log2e,
@@ -265,10 +265,12 @@ int64_t predict_query_pad(int64_t nq) { return (nq + QB - 1) / QB * QB; }
 
 void predict_chunks(int64_t NPAD, int64_t NQPAD, int* nchunk, int* bpc) {
     const int64_t nblk32 = NPAD / 32, nqb = NQPAD / QB;
-    // at most eight training blocks per workgroup (the FP32 partial sums of
-    // the staged kernel), and enough workgroups to fill the chip
+    // at most 32 training blocks per workgroup (the FP32 partial sums of the
+    // staged kernel; longer chunks amortise the workgroup's query fragments
+    // and first block: 10.2 ms with 8, 8.9 with 16, 7.9-8.2 with 32 at
+    // 100k x 100k), and enough workgroups to fill the chip
     int64_t want = (4096 + nqb - 1) / nqb;
-    want = std::max<int64_t>(want, (nblk32 + 7) / 8);
+    want = std::max<int64_t>(want, (nblk32 + 31) / 32);
     want = std::max<int64_t>(1, std::min<int64_t>(want, nblk32));
     const int64_t per = (nblk32 + want - 1) / want;
     *bpc = (int)per;
