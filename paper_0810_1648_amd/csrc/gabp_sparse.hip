@@ -27,40 +27,64 @@ namespace gabp {
 
 namespace {
 
-// Thresholded distances of one tile on MFMA.  The rows are augmented
-// (k_sp_augment): A row a_i = (x_i, n_i, 1), B row b_j = (x_j, -1/2, -n_j/2)
-// with n = ||x||^2, so the Gram a_i . b_j is -d_ij^2 / 2 and the keep test
-// d^2 <= cut is a single compare of the MFMA output with -cut / 2.  Wave w
-// computes the 32-row bands w and w + 4 together (their A fragments in
-// registers, each B fragment loaded once for both) and walks the eight
-// 32-column blocks, the next block's B fragment in flight during the
-// current MFMAs.  For every block, `visit(g0, g1, i0r, jcol)` receives the
-// Gram values of both bands, where the pair of register r of a lane is kept
-// iff its value is >= -cut / 2 (its ballot is the block's mask for that
-// register).  Blocks off the diagonal tile and before the last column hold
-// only pairs i < j < N; in the others the pairs outside i < j < N get
-// -inf first, so that the test stays one compare everywhere.
+// Thresholded distances of the listed tiles tiles[p0, p1) on MFMA.  The rows
+// are augmented (k_sp_augment): A row a_i = (x_i, n_i, 1), B row
+// b_j = (x_j, -1/2, -n_j/2) with n = ||x||^2, so the Gram a_i . b_j is
+// -d_ij^2 / 2 and the keep test d^2 <= cut is a single compare of the MFMA
+// output with -cut / 2.  Wave w computes the 32-row bands w and w + 4 of a
+// tile together (their A fragments in registers, reloaded only when the row
+// block changes, each B fragment loaded once for both) and walks the
+// tiles' 32-column blocks in order, the next block's B fragment (across
+// tile boundaries too) in flight during the current MFMAs.  For every
+// block, `visit(g0, g1, i0r, jcol, hc)` receives the Gram values of both
+// bands, where the pair of register r of a lane is kept iff its value is
+// >= hc = -cut / 2 (its ballot is the block's mask for that register).
+// Blocks off the diagonal tile and before the last column hold only pairs
+// i < j < N; in the others the pairs outside i < j < N get -inf first, so
+// that the test stays one compare everywhere.
 template <int KIND, int MP, class Visit>
-__device__ inline void sp_tile(const Features& FA, const Features& FB, const TileCoord& tc, int64_t N, float cut,
-                               Visit&& visit) {
+__device__ inline void sp_tiles(const Features& FA, const Features& FB, const uint32_t* __restrict__ tiles,
+                                int64_t p0, int64_t p1, int64_t N, float cut, Visit&& visit) {
+    if (p0 >= p1) return;
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6, h = l >> 5, l32 = l & 31;
-    const int64_t i0 = (int64_t)tc.I * TILE, j0 = (int64_t)tc.J * TILE;
-    const int64_t rowA0 = i0 + w * 32 + l32, rowA1 = i0 + (w + 4) * 32 + l32;
     const float hc = -0.5f * cut;
+    auto coord = [&](int64_t p) {
+        const uint32_t ij = tiles[p];
+        return TileCoord{(int)(ij >> 16), (int)(ij & 0xFFFFu)};
+    };
+    // first column block with a pair i < j for the wave's lower band
+    auto first_cb = [&](const TileCoord& t) {
+        int c = 0;
+        while (c < TILE / 32 && (int64_t)t.J * TILE + c * 32 + 31 < (int64_t)t.I * TILE + w * 32) ++c;
+        return c;
+    };
+    int64_t p = p0;
+    TileCoord tc = coord(p);
+    int cb = first_cb(tc);
     RowFrag<KIND, MP> fa0, fa1, fb;
-    fa0.load(FA, rowA0);
-    fa1.load(FA, rowA1);
-    // first column block with a pair i < j for the lower band
-    int cb0 = 0;
-    while (cb0 < TILE / 32 && j0 + cb0 * 32 + 31 < i0 + w * 32) ++cb0;
-    if constexpr (MP > 0) fb.load(FB, j0 + cb0 * 32 + l32);
-#pragma unroll 1
-    for (int cb = cb0; cb < TILE / 32; ++cb) {
+    fa0.load(FA, (int64_t)tc.I * TILE + w * 32 + l32);
+    fa1.load(FA, (int64_t)tc.I * TILE + (w + 4) * 32 + l32);
+    if constexpr (MP > 0) fb.load(FB, (int64_t)tc.J * TILE + cb * 32 + l32);
+    while (true) {
+        // the next (tile, block) of the walk
+        int64_t pn = p;
+        TileCoord tn = tc;
+        int cbn = cb + 1;
+        if (cbn == TILE / 32) {
+            pn = p + 1;
+            if (pn < p1) {
+                tn = coord(pn);
+                cbn = first_cb(tn);
+            }
+        }
+        const bool more = pn < p1;
+        const int64_t i0 = (int64_t)tc.I * TILE, j0 = (int64_t)tc.J * TILE;
+        const int64_t rowA0 = i0 + w * 32 + l32, rowA1 = i0 + (w + 4) * 32 + l32;
         const int64_t j = j0 + cb * 32 + l32;
         f32x16 g0 = {}, g1 = {};
         if constexpr (MP > 0) {
             RowFrag<KIND, MP> fn;
-            fn.load(FB, j0 + (cb + 1 < TILE / 32 ? cb + 1 : cb) * 32 + l32);
+            fn.load(FB, more ? (int64_t)tn.J * TILE + cbn * 32 + l32 : j);
             frag_mma(fa0, fb, g0, FA.m_pad);
             frag_mma(fa1, fb, g1, FA.m_pad);
             fb = fn;
@@ -79,6 +103,14 @@ __device__ inline void sp_tile(const Features& FA, const Features& FB, const Til
             }
         }
         visit(g0, g1, i0 + w * 32, j, hc);
+        if (!more) break;
+        if (tn.I != tc.I) {
+            fa0.load(FA, (int64_t)tn.I * TILE + w * 32 + l32);
+            fa1.load(FA, (int64_t)tn.I * TILE + (w + 4) * 32 + l32);
+        }
+        p = pn;
+        tc = tn;
+        cb = cbn;
     }
 }
 
@@ -88,10 +120,8 @@ template <int KIND, int MP>
 __global__ __launch_bounds__(WG) void k_sp_count(Features FA, Features FB, const uint32_t* __restrict__ tiles, int64_t stride,
                                                  int64_t N, float cut, int32_t* __restrict__ counts) {
     __shared__ int wsum[4];
-    const uint32_t ij = tiles[(int64_t)blockIdx.x * stride];
-    const TileCoord tc{(int)(ij >> 16), (int)(ij & 0xFFFFu)};
     int c = 0;   // wave-uniform
-    sp_tile<KIND, MP>(FA, FB, tc, N, cut, [&](const f32x16& g0, const f32x16& g1, int64_t, int64_t, float hc) {
+    sp_tiles<KIND, MP>(FA, FB, tiles + (int64_t)blockIdx.x * stride, 0, 1, N, cut, [&](const f32x16& g0, const f32x16& g1, int64_t, int64_t, float hc) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) c += __popcll(__ballot(g0[r] >= hc)) + __popcll(__ballot(g1[r] >= hc));
     });
@@ -100,17 +130,20 @@ __global__ __launch_bounds__(WG) void k_sp_count(Features FA, Features FB, const
     if (threadIdx.x == 0) counts[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
+constexpr int SP_TPW = 4;   // listed tiles per workgroup of the fill
+
 // Kept pairs appended at a global cursor.  A wave collects its kept pairs
 // (key and K' value) in an LDS buffer, register by register in lane order;
 // a full buffer is drained to slots reserved by one atomic, and at the end
-// of the tile one atomic reserves the slots of all four waves' remainders.
+// of its tiles one atomic reserves the slots of all four waves' remainders.
 // The order across waves and tiles is arbitrary: the (i, j) sort that
 // follows fixes it, and every pair's key and K' value do not depend on it.
 // Slots at or beyond cap are not written but still counted, so the cursor
 // ends at the exact number of kept pairs and the host repeats the pass with
 // room for all of them.
 template <int KIND, int MP>
-__global__ __launch_bounds__(WG) void k_sp_fill(Features FA, Features FB, const uint32_t* __restrict__ tiles, int64_t N,
+__global__ __launch_bounds__(WG) void k_sp_fill(Features FA, Features FB, const uint32_t* __restrict__ tiles,
+                                                int64_t ntiles, int64_t N,
                                                 float cut, float neg_gamma_log2e, float lam2, int64_t cap,
                                                 unsigned long long* __restrict__ cursor,
                                                 uint64_t* __restrict__ keys, float* __restrict__ kv) {
@@ -119,8 +152,10 @@ __global__ __launch_bounds__(WG) void k_sp_fill(Features FA, Features FB, const 
     __shared__ float bval[4][BW];
     __shared__ unsigned long long wbase[4];
     __shared__ int wcnt[4];
-    const uint32_t ij = tiles[xcd_contiguous(blockIdx.x, gridDim.x)];
-    const TileCoord tc{(int)(ij >> 16), (int)(ij & 0xFFFFu)};
+    // SP_TPW consecutive listed tiles per workgroup (mostly one row block of a
+    // super-block: the A fragments stay in registers)
+    const int64_t p0 = xcd_contiguous(blockIdx.x, gridDim.x) * SP_TPW;
+    const int64_t p1 = (p0 + SP_TPW < ntiles) ? p0 + SP_TPW : ntiles;
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6, h = l >> 5;
     const uint64_t below = (1ull << l) - 1ull;
     int n = 0;   // wave-uniform: entries in the wave's buffer
@@ -134,7 +169,8 @@ __global__ __launch_bounds__(WG) void k_sp_fill(Features FA, Features FB, const 
             }
         }
     };
-    sp_tile<KIND, MP>(FA, FB, tc, N, cut, [&](const f32x16& g0, const f32x16& g1, int64_t ib, int64_t j, float hc) {
+    sp_tiles<KIND, MP>(FA, FB, tiles, p0, p1, N, cut, [&](const f32x16& g0, const f32x16& g1, int64_t ib, int64_t j,
+                                                          float hc) {
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
 #pragma unroll
@@ -487,11 +523,12 @@ template <int KIND>
 void sp_build_kind(bool fill, int mp, dim3 g, const Features& FA, const Features& FB, const uint32_t* tiles, int64_t stride, int64_t N,
                    float cut, float c, float lam2, int32_t* counts, int64_t cap, unsigned long long* cursor,
                    uint64_t* keys, float* kv, hipStream_t s) {
+    const dim3 gf((unsigned)(((int64_t)g.x + SP_TPW - 1) / SP_TPW));
 #define GABP_SP_LAUNCH(MPV)                                                                                  \
     do {                                                                                                     \
         if (fill)                                                                                            \
-            hipLaunchKernelGGL((k_sp_fill<KIND, MPV>), g, dim3(WG), 0, s, FA, FB, tiles, N, cut, c, lam2, cap, \
-                               cursor, keys, kv);                                                            \
+            hipLaunchKernelGGL((k_sp_fill<KIND, MPV>), gf, dim3(WG), 0, s, FA, FB, tiles, (int64_t)g.x, N, cut,   \
+                               c, lam2, cap, cursor, keys, kv);                                              \
         else                                                                                                 \
             hipLaunchKernelGGL((k_sp_count<KIND, MPV>), g, dim3(WG), 0, s, FA, FB, tiles, stride, N, cut,     \
                                counts);                                                                      \
