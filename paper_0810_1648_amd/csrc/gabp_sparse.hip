@@ -130,7 +130,7 @@ __global__ __launch_bounds__(WG) void k_sp_count(Features FA, Features FB, const
     if (threadIdx.x == 0) counts[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
-constexpr int SP_TPW = 4;   // listed tiles per workgroup of the fill
+constexpr int SP_TPW = 16;   // listed tiles per workgroup of the fill
 
 // Kept pairs appended at a global cursor.  A wave collects its kept pairs
 // (key and K' value) in an LDS buffer, register by register in lane order;
