@@ -23,8 +23,16 @@
  * are Neumaier-compensated sums in index order: results do not depend on
  * the number of threads.
  *
+ * Large systems (the 100k and 300k point workloads) never form A: the
+ * matrix-free product A v recomputes every kernel row from the features
+ * (feeding the conjugate-gradient reference solution alpha* = A^-1 1 and the
+ * residual certificate), and the stateless sweep rebuilds each message from
+ * the aggregate history by unrolling the message recursion, one target row
+ * at a time.
+ *
  * Pinned by tests/test_oracle_pins.py (closed forms for N = 1, 2, the
- * first sweep, tree exactness, LAPACK Cholesky, divergence).
+ * first sweep, tree exactness, LAPACK Cholesky, divergence, the dense
+ * product A v, the stored-state sweep for the stateless form).
  */
 #include <math.h>
 #include <stdint.h>
@@ -291,3 +299,225 @@ int oracle_time_sweeps(const float *X, const float *y, int64_t N, int64_t m,
     free(A); free(b); free(alpha); free(pt);
     return st;
 }
+
+/* ------------------------------------------------------------------------
+ * Matrix-free forms for large N
+ * ------------------------------------------------------------------------ */
+
+/* Features transposed to XT[k*N + j], so that one kernel row is built with
+ * the point index innermost.  The distance of each pair is still summed over
+ * k = 0..m-1 in order, as in oracle_kernel_row, so the entries are the same
+ * bit for bit. */
+static float *transpose_features(const float *X, int64_t N, int64_t m)
+{
+    float *XT = malloc((size_t)N * (size_t)m * sizeof(float));
+    if (!XT) return NULL;
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < N; ++j)
+        for (int64_t k = 0; k < m; ++k) XT[(size_t)k * N + j] = X[(size_t)j * m + k];
+    return XT;
+}
+
+/* Row i of A = weighted(Y K' Y) from the features, into row[0..N): the
+ * off-diagonal entries y_i y_j K'_ij and, at j = i, the weighted diagonal
+ * A_ii of the rule (which needs r_i = sum_{j != i} |A_ij|, formed here by a
+ * compensated sum in index order).  Not defined for the uniform rule. */
+static double svm_row(const float *XT, const float *X, const float *y, int64_t N,
+                      int64_t m, double gamma, double C, double lam,
+                      int diag_mode, double delta, int64_t i, double *row)
+{
+    const float *xi = X + (size_t)i * m;
+    for (int64_t j = 0; j < N; ++j) row[j] = 0.0;
+    for (int64_t k = 0; k < m; ++k) {
+        const double xk = (double)xi[k];
+        const float *col = XT + (size_t)k * N;
+        for (int64_t j = 0; j < N; ++j) {
+            double d = xk - (double)col[j];
+            row[j] += d * d;
+        }
+    }
+    for (int64_t j = 0; j < N; ++j)
+        row[j] = (exp(-gamma * row[j]) + lam * lam) * ((double)y[i] * (double)y[j]);
+    nsum_t r = {0.0, 0.0};
+    for (int64_t j = 0; j < N; ++j)
+        if (j != i) nsum_add(&r, fabs(row[j]));
+    const double aii = diag_rule(diag_mode, row[i], nsum_get(&r), C, delta);
+    row[i] = aii;
+    return aii;
+}
+
+/* out = A v without forming A (each row rebuilt from the features and
+ * summed with compensation in index order); adiag (optional) receives the
+ * weighted diagonal.  O(N^2 m) work, O(N) memory per thread. */
+int oracle_svm_matvec(const float *X, const float *y, int64_t N, int64_t m,
+                      double gamma, double C, double lam, int diag_mode,
+                      double delta, const double *v, double *out,
+                      double *adiag)
+{
+    if (N < 1 || m < 1 || diag_mode == OR_DIAG_DOMINANT_UNIFORM) return OR_INVALID;
+    float *XT = transpose_features(X, N, m);
+    if (!XT) return OR_NOMEM;
+    int err = 0;
+#pragma omp parallel reduction(| : err)
+    {
+        double *row = malloc((size_t)N * sizeof(double));
+        if (!row) err = 1;
+        else {
+#pragma omp for schedule(dynamic, 16)
+            for (int64_t i = 0; i < N; ++i) {
+                const double aii = svm_row(XT, X, y, N, m, gamma, C, lam, diag_mode,
+                                           delta, i, row);
+                nsum_t acc = {0.0, 0.0};
+                for (int64_t j = 0; j < N; ++j) nsum_add(&acc, row[j] * v[j]);
+                out[i] = nsum_get(&acc);
+                if (adiag) adiag[i] = aii;
+            }
+            free(row);
+        }
+    }
+    free(XT);
+    return err ? OR_NOMEM : OR_CONVERGED;
+}
+
+/* Aggregates of target node j after sweep t of the stateless form, from the
+ * aggregate history hP[s], hS[s] (sweeps s = 0 .. t-1, every node) and row j
+ * of A (arow[i] = A_ij).  The message i -> j of sweep t depends on stored
+ * state only through the reverse message j -> i of sweep t-1, which depends
+ * on i -> j of sweep t-2, and so on: the chain is unrolled from sweep
+ * lo = max(1, t - depth + 1), whose reverse message is taken as zero (exact
+ * while t <= depth, since the messages of sweep 0 are zero).  Level s is the
+ * message of sweep s, sent by i when t - s is even and by j otherwise:
+ * P = -a^2 / (P~_src^(s-1) - P_rev), E = -a (S_src^(s-1) - E_rev) / (same).
+ * Returns nonzero if some cavity precision is <= 0 or not finite. */
+static int stateless_target(const double *arow, int64_t N, int64_t j, double ajj,
+                            double bj, const double *const *hP,
+                            const double *const *hS, int t, int depth,
+                            double *Pt_out, double *S_out)
+{
+    int lo = t - depth + 1;
+    if (lo < 1) lo = 1;
+    int bad = 0;
+    nsum_t sp = {0.0, 0.0}, se = {0.0, 0.0};
+    nsum_add(&sp, ajj);
+    nsum_add(&se, bj);
+    for (int64_t i = 0; i < N; ++i) {
+        if (i == j) continue;
+        const double a = arow[i];
+        double P = 0.0, E = 0.0;
+        for (int s = lo; s <= t; ++s) {
+            const int64_t src = ((t - s) % 2 == 0) ? i : j;
+            const double q = hP[s - 1][src] - P;
+            if (!(q > 0.0) || !isfinite(q)) bad = 1;
+            const double Pn = -a * a / q;
+            const double En = -a * (hS[s - 1][src] - E) / q;
+            P = Pn;
+            E = En;
+        }
+        nsum_add(&sp, P);
+        nsum_add(&se, E);
+    }
+    *Pt_out = nsum_get(&sp);
+    *S_out = nsum_get(&se);
+    return bad;
+}
+
+/* Synchronous GaBP with stateless messages on an explicit matrix A (N*N,
+ * row-major, symmetric): `sweeps` sweeps at unroll depth `depth`.  alpha_traj
+ * receives alpha^1 .. alpha^sweeps (sweeps*N), ptilde the last P~.  For
+ * t <= depth the trajectory equals the stored-state sweep (oracle_matrix_solve)
+ * bit for bit.  Returns OR_CONVERGED (all sweeps done), OR_DIVERGED or
+ * OR_NOMEM. */
+int oracle_stateless_matrix(const double *A, const double *b, int64_t N, int depth,
+                            int sweeps, double *alpha_traj, double *ptilde)
+{
+    if (N < 1 || depth < 1 || sweeps < 1) return OR_INVALID;
+    double *hist = malloc((size_t)2 * (size_t)(sweeps + 1) * (size_t)N * sizeof(double));
+    const double **hP = malloc((size_t)(sweeps + 1) * sizeof(double *));
+    const double **hS = malloc((size_t)(sweeps + 1) * sizeof(double *));
+    if (!hist || !hP || !hS) { free(hist); free(hP); free(hS); return OR_NOMEM; }
+    for (int s = 0; s <= sweeps; ++s) {
+        hP[s] = hist + (size_t)(2 * s) * N;
+        hS[s] = hist + (size_t)(2 * s + 1) * N;
+    }
+    for (int64_t i = 0; i < N; ++i) {
+        ((double *)hP[0])[i] = A[(size_t)i * N + i];
+        ((double *)hS[0])[i] = b[i];
+    }
+    int status = OR_CONVERGED;
+    for (int t = 1; t <= sweeps && status == OR_CONVERGED; ++t) {
+        double *nP = (double *)hP[t], *nS = (double *)hS[t];
+        int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+        for (int64_t j = 0; j < N; ++j) {
+            bad |= stateless_target(A + (size_t)j * N, N, j, A[(size_t)j * N + j], b[j],
+                                    hP, hS, t, depth, &nP[j], &nS[j]);
+            if (!(nP[j] > 0.0) || !isfinite(nP[j]) || !isfinite(nS[j])) bad = 1;
+        }
+        for (int64_t j = 0; j < N; ++j) alpha_traj[(size_t)(t - 1) * N + j] = nS[j] / nP[j];
+        if (bad) status = OR_DIVERGED;
+        if (ptilde) for (int64_t j = 0; j < N; ++j) ptilde[j] = nP[j];
+    }
+    free(hist); free(hP); free(hS);
+    return status;
+}
+
+/* One stateless sweep t (unroll depth `depth`) of the SVM system for the
+ * listed target rows only, every row of A rebuilt from the features: the
+ * per-node work of a sweep at the full N.  hist_P / hist_S hold the
+ * aggregates of sweeps 0 .. t-1 for every node ([t][N]); adiag is the
+ * weighted diagonal (the sweep-0 precisions).  outP / outS receive P~^t and
+ * S^t of the listed rows; *secs the wall time of the row loop (the features
+ * are transposed before it).  Returns OR_DIVERGED if a cavity precision is
+ * <= 0, else OR_CONVERGED. */
+int oracle_stateless_rows(const float *X, const float *y, int64_t N, int64_t m,
+                          double gamma, double lam, const double *adiag,
+                          const double *hist_P, const double *hist_S, int t,
+                          int depth, const int64_t *rows, int64_t nrows,
+                          double *outP, double *outS, double *secs)
+{
+    if (N < 1 || m < 1 || t < 1 || depth < 1) return OR_INVALID;
+    float *XT = transpose_features(X, N, m);
+    const double **hP = malloc((size_t)t * sizeof(double *));
+    const double **hS = malloc((size_t)t * sizeof(double *));
+    if (!XT || !hP || !hS) { free(XT); free(hP); free(hS); return OR_NOMEM; }
+    for (int s = 0; s < t; ++s) {
+        hP[s] = hist_P + (size_t)s * N;
+        hS[s] = hist_S + (size_t)s * N;
+    }
+    int bad = 0, err = 0;
+    const double t0 = omp_get_wtime();
+#pragma omp parallel reduction(| : bad, err)
+    {
+        double *row = malloc((size_t)N * sizeof(double));
+        if (!row) err = 1;
+        else {
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t r = 0; r < nrows; ++r) {
+                const int64_t j = rows[r];
+                const float *xj = X + (size_t)j * m;
+                for (int64_t i = 0; i < N; ++i) row[i] = 0.0;
+                for (int64_t k = 0; k < m; ++k) {
+                    const double xk = (double)xj[k];
+                    const float *col = XT + (size_t)k * N;
+                    for (int64_t i = 0; i < N; ++i) {
+                        double d = xk - (double)col[i];
+                        row[i] += d * d;
+                    }
+                }
+                for (int64_t i = 0; i < N; ++i)
+                    row[i] = (exp(-gamma * row[i]) + lam * lam) * ((double)y[j] * (double)y[i]);
+                bad |= stateless_target(row, N, j, adiag[j], 1.0, hP, hS, t, depth,
+                                        &outP[r], &outS[r]);
+            }
+            free(row);
+        }
+    }
+    if (secs) *secs = omp_get_wtime() - t0;
+    free(XT); free(hP); free(hS);
+    if (err) return OR_NOMEM;
+    return bad ? OR_DIVERGED : OR_CONVERGED;
+}
+
+/* Sets the OpenMP thread count of later calls (timing at 1 thread and at all
+ * threads). */
+void oracle_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }

@@ -574,6 +574,37 @@ def cg_solve(matvec, b, tol: float = 1e-13, max_iter: int = 10000):
     return x
 
 
+def pcg_solve(matvec, b, diag, tol: float = 1e-13, max_iter: int = 1000, log=None):
+    """Conjugate gradients with the Jacobi preconditioner (textbook PCG) for
+    an SPD operator given as a function; `diag` is the operator's diagonal.
+    Stops when the recursive residual satisfies ||r||_2 <= tol ||b||_2.
+    Returns (x, iterations)."""
+    b = np.asarray(b, dtype=np.float64)
+    dinv = 1.0 / np.asarray(diag, dtype=np.float64)
+    x = np.zeros_like(b)
+    r = b.copy()
+    z = dinv * r
+    p = z.copy()
+    rz = r @ z
+    bn = np.sqrt(b @ b)
+    it = 0
+    for it in range(1, max_iter + 1):
+        q = matvec(p)
+        a = rz / (p @ q)
+        x += a * p
+        r -= a * q
+        rn = np.sqrt(r @ r)
+        if log is not None:
+            log(it, rn / bn)
+        if rn <= tol * bn:
+            break
+        z = dinv * r
+        rz_new = r @ z
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return x, it
+
+
 def varah_bound(A, alpha, b):
     """||alpha - A^-1 b||_inf <= ||b - A alpha||_inf / min_i (|A_ii| - r_i)
     for a strictly diagonally dominant A (Varah's bound)."""

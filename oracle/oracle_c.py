@@ -1,7 +1,8 @@
 """ctypes access to the compiled FP64 C oracle (test infrastructure only).
 
-The shared object is built from gabp_oracle.c with plain gcc -O2 -fopenmp
-(no fast-math), by the repository's build step.
+The shared object is built from gabp_oracle.c with gcc -O3 -mavx2 -fopenmp
+and no fast-math or contraction (-ffp-contract=off keeps every product and
+sum a separately rounded IEEE operation), by the repository's build step.
 """
 from __future__ import annotations
 
@@ -17,13 +18,13 @@ SRC_PATH = os.path.join(_HERE, "gabp_oracle.c")
 
 DIAG = {"none": 0, "softmargin": 1, "dominant_row": 2, "dominant_uniform": 3}
 STATUS = {0: "converged", 3: "not_converged", 4: "diverged", 2: "nomem", 1: "invalid"}
+CFLAGS = ["-O3", "-mavx2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c11"]
 
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (no GPU code involved)."""
     if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-                               "-o", LIB_PATH, SRC_PATH, "-lm"])
+        subprocess.check_call(["gcc", *CFLAGS, "-o", LIB_PATH, SRC_PATH, "-lm"])
     return LIB_PATH
 
 
@@ -54,6 +55,13 @@ def lib():
         L.oracle_kernel_row.argtypes = [f32p, ct.c_int64, ct.c_int64, ct.c_double, ct.c_double,
                                         ct.c_int64, f64p]
         L.oracle_max_threads.restype = ct.c_int
+        L.oracle_svm_matvec.argtypes = [f32p, f32p, ct.c_int64, ct.c_int64, ct.c_double, ct.c_double,
+                                        ct.c_double, ct.c_int, ct.c_double, f64p, f64p, ct.c_void_p]
+        L.oracle_stateless_matrix.argtypes = [f64p, f64p, ct.c_int64, ct.c_int, ct.c_int, f64p, f64p]
+        L.oracle_stateless_rows.argtypes = [f32p, f32p, ct.c_int64, ct.c_int64, ct.c_double, ct.c_double,
+                                            f64p, f64p, f64p, ct.c_int, ct.c_int, i64p, ct.c_int64,
+                                            f64p, f64p, ct.POINTER(ct.c_double)]
+        L.oracle_set_threads.argtypes = [ct.c_int]
         _lib = L
     return _lib
 
@@ -123,3 +131,52 @@ def time_sweeps(X, y, gamma, C, lam, nsweeps, diag="dominant_row", delta=0.1):
 
 def max_threads() -> int:
     return int(lib().oracle_max_threads())
+
+
+def svm_matvec(X, y, gamma, C, lam, v, diag="dominant_row", delta=0.1, want_diag=False):
+    """A v for the SVM system without forming A (rows rebuilt from the
+    features); with want_diag, also the weighted diagonal A_ii."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    n, m = X.shape
+    out = np.zeros(n)
+    ad = np.zeros(n) if want_diag else None
+    st = lib().oracle_svm_matvec(X, y, n, m, gamma, C, lam, DIAG[diag], delta, v, out,
+                                 ad.ctypes.data if want_diag else None)
+    if st != 0:
+        raise RuntimeError(f"oracle_svm_matvec failed: {STATUS.get(st, st)}")
+    return (out, ad) if want_diag else out
+
+
+def stateless_matrix(A, b, depth, sweeps):
+    """Stateless-form trajectory alpha^1 .. alpha^sweeps on an explicit A."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    n = len(b)
+    traj = np.zeros((sweeps, n))
+    pt = np.zeros(n)
+    st = lib().oracle_stateless_matrix(A, b, n, depth, sweeps, traj, pt)
+    return dict(trajectory=traj, ptilde=pt, status=STATUS[st])
+
+
+def stateless_rows(X, y, gamma, lam, adiag, hist_P, hist_S, t, depth, rows):
+    """Aggregates (P~^t, S^t) of the listed rows after stateless sweep t of
+    the SVM system; hist_P / hist_S are (t, N) aggregate histories."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    n, m = X.shape
+    hist_P = np.ascontiguousarray(hist_P, dtype=np.float64)
+    hist_S = np.ascontiguousarray(hist_S, dtype=np.float64)
+    assert hist_P.shape == (t, n) and hist_S.shape == (t, n)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    outP = np.zeros(len(rows))
+    outS = np.zeros(len(rows))
+    secs = ct.c_double(0.0)
+    st = lib().oracle_stateless_rows(X, y, n, m, gamma, lam, np.ascontiguousarray(adiag, dtype=np.float64),
+                                     hist_P, hist_S, t, depth, rows, len(rows), outP, outS, ct.byref(secs))
+    return dict(P=outP, S=outS, seconds=secs.value, status=STATUS[st])
+
+
+def set_threads(n: int) -> None:
+    lib().oracle_set_threads(int(n))

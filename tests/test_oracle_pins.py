@@ -138,14 +138,20 @@ def test_two_nodes_exact_after_one_sweep(oracle_c):
 
 
 def test_first_sweep_closed_form():
+    """first_sweep (aggregates after one sweep from zero messages) against
+    the hand-worked chain: P~^1 = (15/4, 7/2, 15/4), S^1 = alpha^1 P~^1 =
+    (3/4, 1/2, 3/4); then the sweep itself agrees with it on a dense system."""
+    A, b, rows = _load_chain3()
+    pt, sv = R.first_sweep(A, b)
+    np.testing.assert_array_equal(pt, [15 / 4, 7 / 2, 15 / 4])
+    np.testing.assert_array_equal(sv, [3 / 4, 1 / 2, 3 / 4])
+    np.testing.assert_allclose(sv / pt, rows[1][0], rtol=1e-15)
     A = inputs.random_spd_dominant(12, seed=3)
     b = np.cos(np.arange(12.0))
+    pt, sv = R.first_sweep(A, b)
     r = R.gabp_solve(A, b, max_sweeps=1, tol_rel=0.0)
-    n = len(b)
-    pt = np.array([A[j, j] - sum(A[i, j] ** 2 / A[i, i] for i in range(n) if i != j) for j in range(n)])
-    s = np.array([b[j] - sum(A[i, j] * b[i] / A[i, i] for i in range(n) if i != j) for j in range(n)])
     np.testing.assert_allclose(r.ptilde, pt, rtol=1e-14)
-    np.testing.assert_allclose(r.alpha, s / pt, rtol=1e-14)
+    np.testing.assert_allclose(r.alpha, sv / pt, rtol=1e-14)
 
 
 @pytest.mark.parametrize("n", [5, 9, 17])
@@ -190,6 +196,23 @@ def test_letter_shape_fixed_point_cg_and_cholesky(oracle_c):
     c = oracle_c.svm_solve(wl.X, wl.y, wl.gamma, wl.C, wl.lam, tol_rel=1e-13)
     assert c["status"] == "converged"
     assert _rel(c["alpha"], exact) < 1e-10
+
+
+def test_varah_bound_closed_forms():
+    """Hand-worked values of varah_bound: (i) A = [[4, 1], [1, 3]], b = 1,
+    alpha = 0: residual 1, smallest dominance gap min(4 - 1, 3 - 1) = 2, so
+    the bound is 1/2 (the true error is ||A^-1 1||_inf = 3/11); (ii) a
+    uniform diagonal d I, where the bound is an equality: |b_i - d a_i| / d =
+    |a_i - b_i / d|; (iii) no strict dominance: no bound (+inf)."""
+    A = np.array([[4.0, 1.0], [1.0, 3.0]])
+    assert R.varah_bound(A, np.zeros(2), np.ones(2)) == 0.5
+    assert np.max(np.abs(np.linalg.solve(A, np.ones(2)))) == pytest.approx(3 / 11, rel=1e-15)
+    d = 2.5
+    a = np.array([0.1, -0.3, 0.7])
+    b = np.array([1.0, 2.0, -1.0])
+    err = np.max(np.abs(a - b / d))
+    assert R.varah_bound(d * np.eye(3), a, b) == pytest.approx(err, rel=1e-15)
+    assert R.varah_bound(np.array([[1.0, 1.0], [1.0, 3.0]]), np.zeros(2), np.ones(2)) == np.inf
 
 
 def test_varah_bound_holds_along_trajectory():
@@ -276,12 +299,20 @@ def test_decision_function_identity_on_training_points():
 # ------------------------------------------------------------ divergence --
 
 def test_equicorrelated_divergence_and_dominant_convergence(oracle_c):
+    """diag 2, off-diagonal 0.5, N = 10 is SPD (lambda_min = 1.5) but has no
+    real message fixed point: by symmetry P = -1/4 / (2 + 8 P) has a negative
+    discriminant.  Sweep 1 gives P = -1/8, P~ = 2 - 9/8 = 7/8; sweep 2 gives
+    P = -1/4 / (7/8 + 1/8) = -1/4 and P~ = 2 - 9/4 = -1/4 <= 0: both oracles
+    report divergence at sweep 2."""
     A = inputs.equicorrelated(10, diag=2.0, off=0.5)
     assert np.min(np.linalg.eigvalsh(A)) == pytest.approx(1.5)
+    r1 = R.gabp_solve(A, np.ones(10), max_sweeps=1, tol_rel=0.0)
+    np.testing.assert_allclose(r1.ptilde, 7 / 8, rtol=1e-15)
     r = R.gabp_solve(A, np.ones(10), max_sweeps=200)
-    assert r.status in (R.DIVERGED, R.NOT_CONVERGED)
+    assert r.status == R.DIVERGED and r.sweeps == 2
+    np.testing.assert_allclose(r.ptilde, -1 / 4, rtol=1e-14)
     c = oracle_c.matrix_solve(A, np.ones(10), max_sweeps=200)
-    assert c["status"] in ("diverged", "not_converged")
+    assert c["status"] == "diverged" and c["sweeps"] == 2
     A5 = inputs.equicorrelated(10, diag=5.0, off=0.5)
     exact = np.linalg.solve(A5, np.ones(10))
     r5 = R.gabp_solve(A5, np.ones(10), tol_rel=1e-15, max_sweeps=500)
@@ -556,3 +587,81 @@ def test_projected_gauss_seidel_pins():
     assert np.max(np.abs(g[fr])) <= 1e-10 and np.all(g[lo] <= 1e-10) and np.all(g[hi] >= -1e-10)
     r = R.gabp_solve_box(A, np.ones(300), 0.01, max_sweeps=2000, tol_rel=1e-14)
     assert r.status == R.CONVERGED and np.max(np.abs(r.alpha - h)) <= 1e-12
+
+
+# ------------------------------------------------ matrix-free and stateless C forms --
+
+def test_c_matvec_is_the_dense_product(oracle_c):
+    """The matrix-free product (rows rebuilt from the features) equals A v
+    with A built densely by the NumPy oracle, and its diagonal is A's."""
+    for name, n in (("letter", 700), ("covertype", 900), ("tiny", 333)):
+        wl = inputs.make_workload(name, n=n)
+        A, b = R.svm_system(wl.X, wl.y, wl.gamma, wl.C, wl.lam, delta=wl.delta)
+        v = np.random.default_rng(n).standard_normal(n)
+        out, ad = oracle_c.svm_matvec(wl.X, wl.y, wl.gamma, wl.C, wl.lam, v, delta=wl.delta, want_diag=True)
+        ref = A @ v
+        assert np.max(np.abs(out - ref)) <= 1e-13 * np.max(np.abs(A) @ np.abs(v))
+        np.testing.assert_allclose(ad, np.diag(A), rtol=1e-14)
+
+
+@pytest.mark.parametrize("name,n", [("letter", 1500), ("covertype", 2000), ("tiny", 500)])
+def test_pcg_reference_is_cholesky(oracle_c, name, n):
+    """The reference solution of the large workloads (Jacobi-preconditioned
+    CG on the matrix-free product) against LAPACK Cholesky."""
+    wl = inputs.make_workload(name, n=n)
+    A, b = R.svm_system(wl.X, wl.y, wl.gamma, wl.C, wl.lam, delta=wl.delta)
+    exact = R.cholesky_solve(A, b)
+    mv = lambda v: oracle_c.svm_matvec(wl.X, wl.y, wl.gamma, wl.C, wl.lam, v, delta=wl.delta)  # noqa: E731
+    x, it = R.pcg_solve(mv, b, np.diag(A), tol=1e-13)
+    assert it < 60
+    assert _rel(x, exact) <= 1e-12
+    # the same on the dense matrix, and plain CG agrees
+    x2, _ = R.pcg_solve(lambda v: A @ v, b, np.diag(A), tol=1e-13)
+    assert _rel(x2, exact) <= 1e-12
+    assert _rel(R.cg_solve(lambda v: A @ v, b, tol=1e-14), exact) <= 1e-11
+
+
+def test_pcg_closed_form_two_by_two():
+    """CG solves an n x n SPD system in at most n steps: A = [[4, 1], [1, 3]],
+    b = 1 gives (2/11, 3/11) after two iterations."""
+    A = np.array([[4.0, 1.0], [1.0, 3.0]])
+    x, it = R.pcg_solve(lambda v: A @ v, np.ones(2), np.diag(A), tol=1e-15)
+    assert it <= 2
+    np.testing.assert_allclose(x, [2 / 11, 3 / 11], rtol=1e-15)
+
+
+@pytest.mark.parametrize("depth", [1, 3, 5])
+def test_c_stateless_equals_stored_while_within_depth(oracle_c, depth):
+    """The C oracle's stateless form reproduces its stored-message sweep bit
+    for bit while t <= depth (the chain reaches the zero messages of sweep
+    0), and the NumPy oracle's stateless form after that."""
+    wl = inputs.make_workload("tiny", n=260, seed=7)
+    A, b = R.svm_system(wl.X, wl.y, wl.gamma, wl.C, wl.lam)
+    T = depth + 4
+    c = oracle_c.stateless_matrix(A, b, depth, T)
+    assert c["status"] == "converged"
+    py = R.gabp_solve_stateless(A, b, depth, T)
+    for t in range(1, T + 1):
+        if t <= depth:
+            stored = oracle_c.matrix_solve(A, b, max_sweeps=t, tol_rel=0.0)["alpha"]
+            assert np.array_equal(c["trajectory"][t - 1], stored), t
+        assert _rel(c["trajectory"][t - 1], py[t - 1]) <= 1e-13
+
+
+def test_c_stateless_rows_are_the_sweep_of_the_features(oracle_c):
+    """One stateless sweep for listed rows, each row of A rebuilt from the
+    features, equals the explicit-matrix form: sweep 1 against the first-
+    sweep closed form, sweep 2 (history P~^0, P~^1) against the trajectory."""
+    wl = inputs.make_workload("covertype", n=600, seed=11)
+    A, b = R.svm_system(wl.X, wl.y, wl.gamma, wl.C, wl.lam)
+    ad = np.diag(A).copy()
+    pt1, s1 = R.first_sweep(A, b)
+    rows = np.array([0, 7, 255, 256, 599])
+    r1 = oracle_c.stateless_rows(wl.X, wl.y, wl.gamma, wl.lam, ad, ad[None, :], b[None, :], 1, 3, rows)
+    assert r1["status"] == "converged"
+    np.testing.assert_allclose(r1["P"], pt1[rows], rtol=1e-13)
+    np.testing.assert_allclose(r1["S"], s1[rows], rtol=1e-12)
+    r2 = oracle_c.stateless_rows(wl.X, wl.y, wl.gamma, wl.lam, ad, np.stack([ad, pt1]), np.stack([b, s1]),
+                                 2, 3, rows)
+    ref = oracle_c.stateless_matrix(A, b, 3, 2)["trajectory"][1]
+    np.testing.assert_allclose(r2["S"] / r2["P"], ref[rows], rtol=1e-12)
