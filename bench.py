@@ -7,10 +7,14 @@ points, m = 54 features (43 uniform + 11 one-hot), RBF gamma = 0.5, C = 1,
 labels from a random RBF teacher with 5% flips, inputs resident in device
 memory before the timed region.  The headline `value` is GaBP sweeps per
 second over the whole timed job (all sweeps of all steps / wall time); the
-same line carries solves/s, the plain-FP32 comparison, the roofline of the
-sweep kernel and the timed CPU oracle.
+same line carries solves/s, the error of every form against the oracle's
+FP64 alpha* (tests/golden/alpha_ref/), the device's residual certificate,
+the plain-FP32, stored-record, grouped, 20k-point (plain FP32) and
+300k-point (K' recomputed) forms, the served stream in FP32 and in the mixed
+pattern, the roofline of the sweep kernel and the timed CPU oracle.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py --ingest-counters FETCH_DIR WRITE_DIR   (writes profiles/sweep_traffic.json)
 """
 from __future__ import annotations
 
@@ -56,21 +60,6 @@ def device_source_hash():
     return h.hexdigest()
 
 
-def counter_traffic(path, key):
-    """HBM bytes per launch from the calibrated FETCH_SIZE + WRITE_SIZE counter
-    runs recorded in profiles/, in GB; None when absent or when the kernel
-    source has changed since the counters were taken."""
-    import hashlib
-    try:
-        tj = json.load(open(path))
-        if device_source_hash() != tj["kernel_source_sha256"]:
-            return None
-        e = tj["entries"].get(key)
-        return None if e is None else e["traffic_bytes"] / 1e9
-    except Exception:
-        return None
-
-
 def stateless_slots_per_pair(levels, series, precision="mixed"):
     """Algorithmic VALU issue slots per pair of one stateless sweep with
     `levels` unrolled levels (both directions of the pair), counting a
@@ -98,6 +87,45 @@ def stateless_slots_per_pair(levels, series, precision="mixed"):
     r_top = 4 if precision == "fp32" else 8
     r_low = 8 if precision == "fp64" else 4
     return cvt + 1 + 2 * (levels - 1) * (1 + r_low + 4) + 2 * (1 + r_top + 3)
+
+
+GOLDEN = os.path.join(ROOT, "tests", "golden", "alpha_ref")
+
+
+def alpha_ref(key, X, y):
+    """The oracle's FP64 alpha* for a workload (written by
+    tests/golden/make_alpha_ref.py), or None when absent or computed from
+    other arrays."""
+    import hashlib
+
+    import numpy as np
+    try:
+        meta = json.load(open(os.path.join(GOLDEN, f"{key}.json")))
+        h = hashlib.sha256()
+        h.update(np.ascontiguousarray(X, dtype=np.float32).tobytes())
+        h.update(np.ascontiguousarray(y, dtype=np.float32).tobytes())
+        if h.hexdigest() != meta["data_sha256"]:
+            return None
+        return np.load(os.path.join(GOLDEN, f"{key}.npz"))
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def rel_err(a, ref):
+    import numpy as np
+    if ref is None:
+        return None
+    return float(np.max(np.abs(np.asarray(a) - ref)) / np.max(np.abs(ref)))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def parse():
@@ -134,10 +162,18 @@ def parse():
     ap.add_argument("--calib-copy-gb", type=float, default=0.0,
                     help="also run a plain device copy of this many GB (counter calibration)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "sweep_traffic.json"))
+    ap.add_argument("--side-steps", type=int, default=2,
+                    help="timed solves of the comparison legs (stored records, 20k and 300k workloads)")
+    ap.add_argument("--no-letter", action="store_true", help="skip the 20k-point plain FP32 leg")
+    ap.add_argument("--no-large", action="store_true", help="skip the 300k-point recompute leg")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target seconds of each CPU-oracle sample")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
+                    help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this benchmark into the "
+                         "traffic JSON and exit")
     return ap.parse_args()
 
 
-def solve_steps(torch, gabp, wl, X, y, params, steps, warmup):
+def solve_steps(torch, gabp, wl, X, y, params, steps, warmup, certificate=False):
     s = gabp.GabpSVM(**params)
     for _ in range(warmup):
         s.solve(X, y)
@@ -156,6 +192,11 @@ def solve_steps(torch, gabp, wl, X, y, params, steps, warmup):
     wall = time.perf_counter() - t0
     info = dict(status=int(st), reason=s.reason(), sweeps_per_solve=s.sweeps(), plan=s.plan(),
                 timings=s.timings(), alpha=s.alpha())
+    if certificate:
+        # outside the timed region: one pass over K' for ||1 - A alpha||_inf
+        c = s.residual_bound()
+        c["bound_rel"] = c["bound"] / float(abs(info["alpha"]).max())
+        info["certificate"] = c
     s.close()
     return wall, sweeps, ktime, klaunch, info
 
@@ -182,7 +223,14 @@ def serving_bench(gabp, inputs, n_req, load, precision, schedule="grouped", seq_
             srv.wait(t)
         cap_wall = time.perf_counter() - t0
         closed = srv.stats()
-        infos = [srv.result(t)[1] for t in tickets]
+        results = [srv.result(t) for t in tickets]
+        infos = [r[1] for r in results]
+    # error against the oracle's alpha* for the requests that have one
+    errs = {}
+    for r, (a, _) in zip(stream, results):
+        ref = alpha_ref(f"serve_req{r.rid}", r.workload.X, r.workload.y)
+        if ref is not None:
+            errs[r.rid] = rel_err(a, ref["alpha"])
         sweeps = [i["sweeps"] for i in infos]
         plan_mix = {}
         for i in infos:
@@ -230,6 +278,10 @@ def serving_bench(gabp, inputs, n_req, load, precision, schedule="grouped", seq_
             "closed_loop_p50_ms": closed["p50_ms"], "closed_loop_p99_ms": closed["p99_ms"],
             "mean_sweeps": float(np.mean(sweeps)), "plan_mix": plan_mix,
             "failed": opened["failed"] + closed["failed"],
+            "err_vs_oracle": {"requests": sorted(errs), "max_rel": max(errs.values()) if errs else None,
+                              "per_request": [errs[k] for k in sorted(errs)],
+                              "note": "||alpha - alpha*||_inf / ||alpha*||_inf of the served results (closed "
+                                      "loop) against the oracle's FP64 alpha* of the same requests"},
             "sequential_solves_per_s_est": seq_rate,
             "sequential_sample": (f"first {k} requests solved one at a time on one handle, rate scaled by "
                                   f"the stream's mean N^2 over the sample's") if k > 0 else None,
@@ -309,25 +361,142 @@ def sparse_bench(torch, gabp, inputs, n, tau, steps=2, warmup=1):
                          "alg_bytes_per_launch": plan["alg_bytes_per_sweep"]}}
 
 
-def cpu_baseline(wl, n_full, sample_n):
-    """Times the FP64 oracle's synchronous sweep on the first sample_n points
-    of the same workload and scales its pair rate to N = n_full."""
+def cpu_baseline(wl, adiag, depth, seconds):
+    """The FP64 C oracle's stateless sweep (unroll depth `depth`, every kernel
+    row rebuilt from the features) on the real N-point system, timed on a
+    bounded sample of target rows: each sampled row forms its new aggregates
+    from all N - 1 incoming messages, which is a sweep's per-node work at the
+    full N, so rows/s / N is the oracle's sweep rate.  The aggregate history
+    is the sweep-0 aggregates at every level (a sweep past the first `depth`
+    sweeps unrolls every level; the work per pair does not depend on the
+    values).  Timed at all host threads and at one."""
+    import numpy as np
+
     from oracle import oracle_c
     oracle_c.build()
-    Xs, ys = wl.X[:sample_n], wl.y[:sample_n]
-    nsw = 6
-    r = oracle_c.time_sweeps(Xs, ys, wl.gamma, wl.C, 1.0 / n_full, nsw)
-    pairs = sample_n * (sample_n - 1) / 2.0 * nsw
-    rate = pairs / r["seconds"]
-    return {"value": rate / (n_full * (n_full - 1) / 2.0), "unit": "sweeps/s", "cores": r["threads"],
-            "kind": "oracle",
-            "sample": f"{nsw} FP64 sweeps of the C oracle on the first {sample_n} points of the same "
-                      f"workload ({r['seconds']:.1f} s); pair rate {rate:.3e}/s scaled to "
-                      f"N={n_full} ({n_full * (n_full - 1) // 2} pairs per sweep)"}
+    N = wl.N
+    T = depth + 1
+    hP = np.tile(np.asarray(adiag, dtype=np.float64), (T, 1))
+    hS = np.ones((T, N))
+    nthr = oracle_c.max_threads()
+    rng = np.random.default_rng(0)
+    out = {}
+    for threads in (nthr, 1):
+        oracle_c.set_threads(threads)
+        probe = np.sort(rng.choice(N, size=max(2 * threads, 8), replace=False))
+        r = oracle_c.stateless_rows(wl.X, wl.y, wl.gamma, wl.lam, adiag, hP, hS, T, depth, probe)
+        per_row = r["seconds"] / len(probe)
+        n = int(min(N, max(len(probe), seconds / max(per_row, 1e-9))))
+        rows = np.sort(rng.choice(N, size=n, replace=False))
+        r = oracle_c.stateless_rows(wl.X, wl.y, wl.gamma, wl.lam, adiag, hP, hS, T, depth, rows)
+        out[threads] = {"sweeps_per_s": n / r["seconds"] / N, "rows": n, "seconds": r["seconds"],
+                        "pairs_per_s": n * (N - 1) / r["seconds"]}
+        print(f"[bench] cpu oracle, {threads} threads: {n} rows in {r['seconds']:.2f} s", file=sys.stderr, flush=True)
+    oracle_c.set_threads(nthr)
+    return {"value": out[nthr]["sweeps_per_s"], "unit": "sweeps/s", "cores": nthr, "kind": "oracle",
+            "value_1_thread": out[1]["sweeps_per_s"], "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "sample": (f"FP64 stateless sweep of the C oracle (depth {depth}, K' rebuilt from the features) on the "
+                       f"full N={N} system: {out[nthr]['rows']} target rows with all {nthr} threads in "
+                       f"{out[nthr]['seconds']:.1f} s, {out[1]['rows']} rows with 1 thread in "
+                       f"{out[1]['seconds']:.1f} s, each row over all {N - 1} sources; sweeps/s = rows/s / N"),
+            "threads": {str(k): v for k, v in out.items()}}
+
+
+def cpu_full_solve(wl):
+    """The C oracle's full FP64 solve (stored messages, Algorithm 2) of a
+    small workload at all threads and at one: solves/s and sweeps/s."""
+    from oracle import oracle_c
+    nthr = oracle_c.max_threads()
+    out = {}
+    for threads in (nthr, 1):
+        oracle_c.set_threads(threads)
+        r = oracle_c.svm_solve(wl.X, wl.y, wl.gamma, wl.C, wl.lam, delta=wl.delta, tol_abs=wl.tol_abs,
+                               tol_rel=wl.tol_rel)
+        t = r["build_s"] + r["sweep_s"]
+        out[str(threads)] = {"solves_per_s": 1.0 / t, "sweeps_per_s": r["sweeps"] / r["sweep_s"],
+                             "sweeps": r["sweeps"], "status": r["status"]}
+    oracle_c.set_threads(nthr)
+    return out
+
+
+def hbm_roof(plan, avg_ms, klaunch, kernel, traffic):
+    achieved = plan["alg_bytes_per_sweep"] / (avg_ms * 1e-3) / 1e9 if klaunch else None
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+            "traffic_unit": "GB/launch", "kernel": kernel, "avg_launch_ms": avg_ms, "launches": klaunch,
+            "alg_bytes_per_pair": plan["alg_bytes_per_pair"], "alg_bytes_per_launch": plan["alg_bytes_per_sweep"]}
+
+
+def ingest_counters(fetch_dir, write_dir, calib_bytes, out_path):
+    """Per-kernel HBM bytes per working launch from two rocprofv3 --pmc runs
+    of this benchmark (FETCH_SIZE, then WRITE_SIZE; CSV output), each scaled
+    by what the counter reads for the benchmark's calibration copy of
+    `calib_bytes` bytes.  Launches that return at once after the stop rule
+    (under 5% of the kernel's largest count) are left out."""
+    import csv
+    import glob
+
+    def load(d, counter):
+        rows = {}
+        for fn in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(fn)):
+                if r.get("Counter_Name") != counter:
+                    continue
+                rows.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return rows
+
+    fetch, write = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    copy = [k for k in fetch if "copyBuffer" in k]
+    if not copy:
+        raise SystemExit("no calibration copy in the counter runs (run the benchmark with --calib-copy-gb)")
+    cf = max(fetch[copy[0]])
+    cw = max(write[copy[0]])
+    ff, wf = calib_bytes / (cf * 1024.0), calib_bytes / (cw * 1024.0)
+    entries = {}
+    for k in fetch:
+        if k not in write or "copyBuffer" in k:
+            continue
+        fv = [v for v in fetch[k] if v >= 0.05 * max(fetch[k])]
+        wv = [v for v in write[k] if v >= 0.05 * max(write[k])] or write[k]
+        fk, wk = sum(fv) / len(fv), sum(wv) / len(wv)
+        entries[k] = {"fetch_kib": fk, "write_kib": wk, "fetch_bytes": fk * 1024 * ff, "write_bytes": wk * 1024 * wf,
+                      "traffic_bytes": fk * 1024 * ff + wk * 1024 * wf, "launches": [len(fv), len(wv)]}
+    out = {"kernel_source_sha256": device_source_hash(),
+           "calibration": {"copy_bytes": calib_bytes, "fetch_factor": ff, "write_factor": wf,
+                           "copy_fetch_kib": cf, "copy_write_kib": cw,
+                           "note": "torch device copy (__amd_rocclr_copyBuffer); factor = known bytes / "
+                                   "(counter KiB * 1024)"},
+           "entries": entries}
+    json.dump(out, open(out_path, "w"), indent=1, sort_keys=True)
+    print(f"wrote {out_path}: {len(entries)} kernels, fetch factor {ff:.4f}, write factor {wf:.4f}")
+
+
+def counter_traffic_kernel(path, name_prefix):
+    """Traffic (GB per working launch) of the kernel whose name starts with
+    name_prefix, if the stored counters match the current sources."""
+    try:
+        tj = json.load(open(path))
+        if device_source_hash() != tj["kernel_source_sha256"]:
+            return None
+        for k, e in tj["entries"].items():
+            if k.startswith(name_prefix):
+                return e["traffic_bytes"] / 1e9
+    except Exception:
+        return None
+    return None
+
+
+# kernel names of the measured sweeps (template arguments: storage, message,
+# aggregate type, K' source, Gram kind, levels, first sweep, series terms)
+SWEEP_KERNEL = {("mixed", "stateless"): "gabp::k_sweep<float, double, double, 0, 0, 3, false, 1>",
+                ("mixed", "stored"): "gabp::k_sweep<float, double, double, 0, 0, 0, false, 0>"}
 
 
 def main():
     a = parse()
+    if a.ingest_counters:
+        ingest_counters(a.ingest_counters[0], a.ingest_counters[1], a.calib_copy_gb * 1e9 or 4e9, a.traffic_json)
+        return
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (the solver has no multi-GPU path); got --gpus {a.gpus}",
               file=sys.stderr)
@@ -350,26 +519,30 @@ def main():
     N, m = wl.N, wl.m
     X = torch.from_numpy(wl.X).to(dev)
     y = torch.from_numpy(wl.y).to(dev)
+    ref = alpha_ref(wl.name, wl.X, wl.y) if a.n is None else None
+    aref = ref["alpha"] if ref is not None else None
     torch.cuda.synchronize()
     print(f"[bench] workload {wl.name} N={N} m={m} precision={a.precision} gram={a.gram}", file=sys.stderr, flush=True)
 
     base = dict(gamma=wl.gamma, C=wl.C, lambda_aug=wl.lam, diag_delta=wl.delta, tol_abs=wl.tol_abs,
                 tol_rel=wl.tol_rel, kstore=a.kstore, edge_state=a.edge, time_sweeps=1)
     params = dict(base, precision=a.precision, gram=a.gram)
-    wall, sweeps, ktime, klaunch, info = solve_steps(torch, gabp, wl, X, y, params, a.steps, a.warmup)
+    wall, sweeps, ktime, klaunch, info = solve_steps(torch, gabp, wl, X, y, params, a.steps, a.warmup,
+                                                     certificate=True)
     print(f"[bench] main: {sweeps} sweeps in {wall:.3f} s, reason {info['reason']}, plan {info['plan']}",
           file=sys.stderr, flush=True)
+    side = max(1, min(a.side_steps, a.steps))
 
     plain = None
     if not a.no_plain and a.precision != "fp32":
         pw, ps, pk, pl, pinfo = solve_steps(torch, gabp, wl, X, y, dict(base, precision="fp32"),
                                             a.steps, a.warmup)
-        diff = float(np.max(np.abs(pinfo["alpha"] - info["alpha"])) / np.max(np.abs(info["alpha"])))
         plain = {"sweeps_per_s": ps / pw, "solves_per_s": a.steps / pw, "sweeps_per_solve": pinfo["sweeps_per_solve"],
                  "reason": pinfo["reason"], "sweep_kernel_ms_avg": pk / max(pl, 1),
                  "edge_state": {1: "stored", 2: "stateless"}.get(pinfo["plan"]["edge_state"]),
                  "stateless_depth": pinfo["plan"]["stateless_depth"],
-                 "rel_diff_alpha_vs_main": diff}
+                 "err_vs_oracle": rel_err(pinfo["alpha"], aref),
+                 "rel_diff_alpha_vs_main": rel_err(pinfo["alpha"], info["alpha"])}
         print(f"[bench] plain fp32: {ps} sweeps in {pw:.3f} s", file=sys.stderr, flush=True)
 
     if a.calib_copy_gb > 0:
@@ -385,58 +558,41 @@ def main():
     avg_ms = ktime / max(klaunch, 1)
     pairs = N * (N - 1) / 2.0
     stateless = plan["edge_state"] == gabp.EDGE["stateless"]
-    traffic = counter_traffic(a.traffic_json, f"{wl.name}:{N}:{a.precision}:{plan['kstore']}:{plan['edge_state']}")
     recompute = plan["kstore"] == gabp.KSTORE["recompute"]
+    edge_name = "stateless" if stateless else "stored"
+    traffic = counter_traffic_kernel(a.traffic_json, SWEEP_KERNEL.get((a.precision, edge_name), "-"))
+    if not recompute:
+        # the sweep streams the K' plane (and, with stored records, the four
+        # pair-record planes): HBM-bound on its algorithmic bytes
+        roof = hbm_roof(plan, avg_ms, klaunch, f"k_sweep ({edge_name}, K' materialised)", traffic)
+    else:
+        roof = {"bound": "alu", "kernel": "k_sweep_rc (stateless, K' recomputed)", "traffic": None}
     if stateless:
         slots = stateless_slots_per_pair(plan["stateless_depth"], int(plan["series_reciprocal"]), a.precision)
         if recompute:
             slots += RECOMPUTE_SLOTS_PER_PAIR
-        achieved = slots * pairs / (avg_ms * 1e-3) / 1e9 if klaunch else None
-        roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_GSLOT, "unit": "Gslot/s",
-                "frac": (achieved / VALU_PEAK_GSLOT) if achieved else None, "traffic": traffic,
-                "traffic_unit": "GB/launch",
-                "kernel": "k_sweep (stateless)", "avg_launch_ms": avg_ms, "launches": klaunch,
-                "alg_slots_per_pair": slots, "stateless_depth": plan["stateless_depth"],
-                "series_reciprocal": int(plan["series_reciprocal"]),
-                "stateless_rho": plan["stateless_rho"],
-                "hbm_alg_bytes_per_launch": plan["alg_bytes_per_sweep"],
-                "hbm_frac": plan["alg_bytes_per_sweep"] / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if klaunch else None}
-        if recompute and klaunch:
-            # the Gram of every pair on MFMA, as issued (padded features, split products)
-            gname = {1: "bf16", 2: "bf16x3", 3: "bf16x6"}.get(plan["gram"], "f32")
-            products = {"bf16": 1, "bf16x3": 3, "bf16x6": 6, "f32": 1}[gname]
-            m_pad = (m + 15) // 16 * 16
-            mf = 2.0 * m_pad * products * pairs / (avg_ms * 1e-3) / 1e12
-            roof.update({"kstore": "recompute", "recompute_slots_per_pair": RECOMPUTE_SLOTS_PER_PAIR,
-                         "mfma_gram": gname, "mfma_issued_tflops": mf,
-                         "mfma_frac": mf / MFMA_PEAK_TFLOPS["f32" if gname == "f32" else "bf16"]})
-    else:
-        achieved = plan["alg_bytes_per_sweep"] / (avg_ms * 1e-3) / 1e9 if klaunch else None
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
-                "traffic_unit": "GB/launch",
-                "kernel": "k_sweep (stored)", "avg_launch_ms": avg_ms, "launches": klaunch,
-                "alg_bytes_per_launch": plan["alg_bytes_per_sweep"],
-                "alg_bytes_per_pair": plan["alg_bytes_per_pair"]}
+        valu = slots * pairs / (avg_ms * 1e-3) / 1e9 if klaunch else None
+        roof.update({"valu_slots_per_pair": slots, "valu_gslot_per_s": valu, "valu_peak_gslot_per_s": VALU_PEAK_GSLOT,
+                     "valu_frac": (valu / VALU_PEAK_GSLOT) if valu else None,
+                     "stateless_depth": plan["stateless_depth"], "series_reciprocal": int(plan["series_reciprocal"]),
+                     "stateless_rho": plan["stateless_rho"]})
+        if recompute:
+            roof.update({"achieved": valu, "peak": VALU_PEAK_GSLOT, "unit": "Gslot/s",
+                         "frac": (valu / VALU_PEAK_GSLOT) if valu else None,
+                         "avg_launch_ms": avg_ms, "launches": klaunch})
 
     stored_cmp = None
     if stateless and not a.no_stored:
         sw_, ss_, sk_, sl_, sinfo = solve_steps(torch, gabp, wl, X, y, dict(params, edge_state="stored"),
-                                                 a.steps, a.warmup)
+                                                 side, min(a.warmup, 1))
         sp = sinfo["plan"]
-        s_ms = sk_ / max(sl_, 1)
-        s_ach = sp["alg_bytes_per_sweep"] / (s_ms * 1e-3) / 1e9
-        stored_cmp = {"sweeps_per_s": ss_ / sw_, "solves_per_s": a.steps / sw_,
+        stored_cmp = {"sweeps_per_s": ss_ / sw_, "solves_per_s": side / sw_, "steps": side,
                       "sweeps_per_solve": sinfo["sweeps_per_solve"], "reason": sinfo["reason"],
-                      "rel_diff_alpha_vs_main": float(np.max(np.abs(sinfo["alpha"] - info["alpha"])) /
-                                                      np.max(np.abs(info["alpha"]))),
-                      "roofline": {"bound": "hbm", "achieved": s_ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                   "frac": s_ach / HBM_PEAK_GBS, "kernel": "k_sweep (stored)",
-                                   "traffic": counter_traffic(a.traffic_json, f"{wl.name}:{N}:{a.precision}:{sp['kstore']}:{sp['edge_state']}"),
-                                   "traffic_unit": "GB/launch",
-                                   "avg_launch_ms": s_ms, "launches": sl_,
-                                   "alg_bytes_per_launch": sp["alg_bytes_per_sweep"],
-                                   "alg_bytes_per_pair": sp["alg_bytes_per_pair"]}}
+                      "err_vs_oracle": rel_err(sinfo["alpha"], aref),
+                      "rel_diff_alpha_vs_main": rel_err(sinfo["alpha"], info["alpha"]),
+                      "roofline": hbm_roof(sp, sk_ / max(sl_, 1), sl_, "k_sweep (stored, K' materialised)",
+                                           counter_traffic_kernel(a.traffic_json,
+                                                                  SWEEP_KERNEL.get((a.precision, "stored"), "-")))}
         print(f"[bench] stored state: {ss_} sweeps in {sw_:.3f} s", file=sys.stderr, flush=True)
 
     grouped = None
@@ -450,15 +606,67 @@ def main():
                    "sweep_ms_avg": gk / max(gl, 1),
                    "edge_state": {1: "stored", 2: "stateless"}.get(gp["edge_state"]),
                    "stateless_depth": gp["stateless_depth"],
-                   "rel_diff_alpha_vs_main": float(np.max(np.abs(ginfo["alpha"] - info["alpha"])) /
-                                                   np.max(np.abs(info["alpha"]))),
+                   "err_vs_oracle": rel_err(ginfo["alpha"], aref),
+                   "rel_diff_alpha_vs_main": rel_err(ginfo["alpha"], info["alpha"]),
                    "solve_speedup_vs_sync": (a.steps / gw) / (a.steps / wall)}
         print(f"[bench] grouped schedule: {gsw} sweeps in {gw:.3f} s ({gp['sched_groups']} groups)",
               file=sys.stderr, flush=True)
+    del X, y
+
+    letter = None
+    if not a.no_letter and a.workload != "letter":
+        wl1 = inputs.make_workload("letter")
+        X1, y1 = torch.from_numpy(wl1.X).to(dev), torch.from_numpy(wl1.y).to(dev)
+        r1 = alpha_ref("letter", wl1.X, wl1.y)
+        p1 = dict(gamma=wl1.gamma, C=wl1.C, lambda_aug=wl1.lam, diag_delta=wl1.delta, tol_rel=wl1.tol_rel,
+                  precision="fp32", kstore="materialise", time_sweeps=1)
+        lw, ls, lk, ll, linfo = solve_steps(torch, gabp, wl1, X1, y1, p1, max(side, 3), 1, certificate=True)
+        lp = linfo["plan"]
+        ledge = "stateless" if lp["edge_state"] == gabp.EDGE["stateless"] else "stored"
+        letter = {"workload": f"letter-like N={wl1.N} m={wl1.m} RBF gamma={wl1.gamma:g} C={wl1.C:g}, plain FP32, "
+                              f"K' materialised", "sweeps_per_s": ls / lw, "solves_per_s": max(side, 3) / lw,
+                  "sweeps_per_solve": linfo["sweeps_per_solve"], "reason": linfo["reason"], "edge_state": ledge,
+                  "stateless_depth": lp["stateless_depth"], "err_vs_oracle": rel_err(linfo["alpha"], r1["alpha"] if r1 is not None else None),
+                  "certificate": linfo["certificate"],
+                  "roofline": hbm_roof(lp, lk / max(ll, 1), ll, f"k_sweep ({ledge}, K' materialised, FP32)", None)}
+        print(f"[bench] letter: {ls} sweeps in {lw:.3f} s", file=sys.stderr, flush=True)
+        del X1, y1
+
+    large = None
+    if not a.no_large and a.workload != "large":
+        wl4 = inputs.make_workload("large")
+        X4, y4 = torch.from_numpy(wl4.X).to(dev), torch.from_numpy(wl4.y).to(dev)
+        r4 = alpha_ref("large", wl4.X, wl4.y)
+        p4 = dict(gamma=wl4.gamma, C=wl4.C, lambda_aug=wl4.lam, diag_delta=wl4.delta, tol_rel=wl4.tol_rel,
+                  precision="mixed", kstore="recompute", edge_state="stateless", time_sweeps=1)
+        gw4, gs4, gk4, gl4, ginfo4 = solve_steps(torch, gabp, wl4, X4, y4, p4, side, 1, certificate=True)
+        g4 = ginfo4["plan"]
+        pairs4 = wl4.N * (wl4.N - 1) / 2.0
+        ms4 = gk4 / max(gl4, 1)
+        slots4 = stateless_slots_per_pair(g4["stateless_depth"], int(g4["series_reciprocal"]), "mixed") + \
+            RECOMPUTE_SLOTS_PER_PAIR
+        v4 = slots4 * pairs4 / (ms4 * 1e-3) / 1e9 if gl4 else None
+        mp4 = (wl4.m + 15) // 16 * 16
+        mf4 = 2.0 * mp4 * 6 * pairs4 / (ms4 * 1e-3) / 1e12 if gl4 else None
+        large = {"workload": f"large-like N={wl4.N} m={wl4.m} RBF gamma={wl4.gamma:g} C={wl4.C:g}, MIXED, K' "
+                             f"recomputed per tile, stateless", "sweeps_per_s": gs4 / gw4, "solves_per_s": side / gw4,
+                 "sweeps_per_solve": ginfo4["sweeps_per_solve"], "reason": ginfo4["reason"],
+                 "stateless_depth": g4["stateless_depth"], "device_bytes": g4["device_bytes"],
+                 "err_vs_oracle": rel_err(ginfo4["alpha"], r4["alpha"] if r4 is not None else None),
+                 "certificate": ginfo4["certificate"],
+                 "roofline": {"bound": "alu", "kernel": "k_sweep_rc (stateless, K' recomputed)", "achieved": v4,
+                              "peak": VALU_PEAK_GSLOT, "unit": "Gslot/s", "frac": v4 / VALU_PEAK_GSLOT if v4 else None,
+                              "valu_slots_per_pair": slots4, "avg_launch_ms": ms4, "launches": gl4,
+                              "mfma_issued_tflops": mf4, "mfma_frac": mf4 / MFMA_PEAK_TFLOPS["bf16"] if mf4 else None,
+                              "traffic": None}}
+        print(f"[bench] large: {gs4} sweeps in {gw4:.3f} s", file=sys.stderr, flush=True)
+        del X4, y4
 
     predict = None
     if not a.no_predict:
-        predict = predict_bench(torch, gabp, inputs, wl, X, y, params, a.predict_n)
+        Xp, yp = torch.from_numpy(wl.X).to(dev), torch.from_numpy(wl.y).to(dev)
+        predict = predict_bench(torch, gabp, inputs, wl, Xp, yp, params, a.predict_n)
+        del Xp, yp
 
     sparse = None
     if not a.no_sparse:
@@ -473,13 +681,28 @@ def main():
                           steps_per_poll=a.serve_steps_per_poll, groups=a.serve_groups)
         serving[f"{other}_schedule"] = {k: o[k] for k in ("capacity_solves_per_s", "offered_rate_per_s", "p50_ms",
                                                          "p99_ms", "throughput_solves_per_s", "mean_sweeps",
-                                                         "plan_mix")}
+                                                         "plan_mix", "err_vs_oracle")}
+        mixed_prec = "mixed" if a.serve_precision != "mixed" else "fp32"
+        o2 = serving_bench(gabp, inputs, a.serve_requests, a.serve_load, mixed_prec, a.serve_schedule, seq_sample=0,
+                           steps_per_poll=a.serve_steps_per_poll, groups=a.serve_groups)
+        serving[f"{mixed_prec}_precision"] = {k: o2[k] for k in ("capacity_solves_per_s", "offered_rate_per_s",
+                                                                "p50_ms", "p99_ms", "throughput_solves_per_s",
+                                                                "mean_sweeps", "plan_mix", "err_vs_oracle")}
 
     cpu = None
     if not a.no_cpu_baseline:
-        sn = a.cpu_sample_n or min(N, 20000)
-        cpu = cpu_baseline(wl, N, sn)
+        adiag = ref["adiag"] if (ref is not None and "adiag" in ref.files) else None
+        if adiag is None:
+            from oracle import oracle_c
+            oracle_c.build()
+            _, adiag = oracle_c.svm_matvec(wl.X, wl.y, wl.gamma, wl.C, wl.lam, np.zeros(N), delta=wl.delta,
+                                           want_diag=True)
+        cpu = cpu_baseline(wl, adiag, max(1, plan["stateless_depth"]), a.cpu_seconds)
+        cpu["full_solve_tiny"] = cpu_full_solve(inputs.make_workload("tiny"))
 
+    dtype = {"mixed": "bf16x6-gram/f32-msg/f64-agg", "fp32": "f32", "fp64": "f64"}[a.precision]
+    if a.precision == "mixed" and a.gram != "auto":
+        dtype = f"{a.gram}-gram/f32-msg/f64-agg"
     line = {
         "metric": "GaBP sweeps/s + solves/s at N=100k RBF vs plain FP32; p50/p99 solve latency",
         "value": sweeps / wall,
@@ -491,22 +714,28 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"mixed": "bf16-gram/f32-store/f64-math", "fp32": "f32", "fp64": "f64"}[a.precision],
+        "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": f"{wl.name}-like N={N} m={m} RBF gamma={wl.gamma:g} C={wl.C:g} "
                                f"delta={wl.delta:g} tol_rel={wl.tol_rel:g}",
                    "N": N, "m": m, "precision": a.precision, "gram": a.gram if a.precision == "mixed" else None,
                    "kstore": {1: "materialise", 2: "recompute"}.get(plan["kstore"], plan["kstore"]),
-                   "edge_state": {1: "stored", 2: "stateless"}.get(plan["edge_state"], plan["edge_state"]),
+                   "edge_state": edge_name,
                    "stateless_depth": plan["stateless_depth"] if stateless else None, "tile": plan["tile"]},
         "solves_per_s": a.steps / wall,
         "sweeps_per_solve": info["sweeps_per_solve"],
         "stop_reason": info["reason"],
+        "err_vs_oracle": rel_err(info["alpha"], aref),
+        "err_note": "||alpha - alpha*||_inf / ||alpha*||_inf against the oracle's FP64 alpha* (conjugate gradients "
+                    "on the matrix-free FP64 product, Varah-certified to 1e-10)",
+        "certificate": info["certificate"],
         "phase_ms": {k: info["timings"][k] for k in ("stage_ms", "kbuild_ms", "diag_ms", "sweep_loop_ms", "d2h_ms")},
         "plain_fp32": plain,
         "stored_state": stored_cmp,
-        "serving": serving,
         "grouped_schedule": grouped,
+        "letter_fp32": letter,
+        "large_recompute": large,
+        "serving": serving,
         "sparse": sparse,
         "predict": predict,
         "roofline": roof,

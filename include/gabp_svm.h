@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define GABP_ABI_VERSION 6
+#define GABP_ABI_VERSION 7
 
 /* Opaque solver handle; owns every device buffer it allocates. */
 typedef struct gabp_svm gabp_svm;
@@ -163,7 +163,18 @@ typedef struct gabp_svm_params {
     int32_t kstore;            /* gabp_kstore */
     int32_t edge_state;        /* gabp_edge */
     int32_t gram;              /* gabp_gram (MIXED only) */
-    int32_t stateless_depth;   /* STATELESS unroll depth 1..8; 0 = from the bound */
+    int32_t stateless_depth;   /* STATELESS unroll depth 1..8; 0 = from the
+                                  contraction bound rho.  AUTO takes the
+                                  stateless form only at a depth <= 8 whose
+                                  truncation (about (1.25 rho)^depth) stays
+                                  below the message precision, and returns
+                                  GABP_E_NOMEM when neither that nor the
+                                  stored records fit.  STATELESS with depth 0
+                                  takes min(that depth, 8) and returns
+                                  GABP_E_INVALID without a bound
+                                  (1.25 rho >= 1).  A depth below the bound's
+                                  runs the truncated recursion and is flagged
+                                  (gabp_plan.stateless_bounded = 0) */
     int32_t device;            /* HIP device ordinal */
     uint64_t hbm_budget_bytes; /* 0 = 90% of the device's free memory */
     int32_t time_sweeps;       /* 1: bracket every sweep kernel with HIP
@@ -218,6 +229,12 @@ typedef struct gabp_plan {
                                   level (one term at the lower levels) */
     int32_t sched_groups;      /* groups of the GROUPED schedule; 0 = SYNC */
     int64_t n_edges;           /* RBF_SPARSE: kept pairs (graph edges); else 0 */
+    int32_t stateless_bounded; /* 1: stored records, or a stateless depth at
+                                  least the one the contraction bound asks
+                                  for (the truncation stays below the message
+                                  precision); 0: an explicit stateless_depth
+                                  below it (a truncated recursion) */
+    int32_t reserved;
 } gabp_plan;
 
 /* Query selectors for gabp_svm_query: dst type and size in brackets. */
@@ -236,8 +253,21 @@ enum {
     GABP_Q_TRACE = 11,     /* [double sweeps] change per sweep, t = 1..sweeps */
     GABP_Q_PLAN = 12,      /* [gabp_plan] */
     GABP_Q_REASON = 13,    /* [int32_t] gabp_reason */
-    GABP_Q_EDGES = 14      /* [int64_t 2 x n_edges] RBF_SPARSE: kept pairs
+    GABP_Q_EDGES = 14,     /* [int64_t 2 x n_edges] RBF_SPARSE: kept pairs
                               (i, j), i < j, in lexicographic order */
+    GABP_Q_RESIDUAL_BOUND = 15 /* [double 3] a-posteriori certificate of a
+                              dense solve (subsection "GaBP Algorithm
+                              Convergence": the weighted diagonal makes A
+                              strictly diagonally dominant):
+                              [0] ||1 - A alpha||_inf over all N rows,
+                              [1] min_i (A_ii - sum_{j != i} |A_ij|),
+                              [2] Varah's bound [0] / [1] on
+                              ||alpha - A^-1 1||_inf (+inf unless [1] > 0),
+                              with A the device's own system (its K') and
+                              alpha before output clipping.  Formed by one
+                              pass over K' on the first query after a solve
+                              (default stream); GABP_E_STATE for sparsified
+                              solves */
 };
 
 /* Fills *p with the defaults: RBF, gamma 1, C 1, lambda 1/N, DOMINANT_ROW

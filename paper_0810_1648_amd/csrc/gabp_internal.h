@@ -292,6 +292,15 @@ hipError_t launch_status(int nblk, const double* blk_delta, const double* blk_am
 // bound), one[1] = rho (+inf when no bound exists).
 hipError_t launch_rho_bound(int64_t N, const double* Adiag, const double* rowmax, const double* rsum,
                             double* blk, double* one, hipStream_t s);
+// Residual certificate of a finished dense solve: out[0] = ||1 - A alpha||_inf,
+// out[1] = min_i (A_ii - sum_{j != i} |A_ij|), out[2] = out[0] / out[1]
+// (Varah's bound on ||alpha - A^-1 1||_inf; +inf unless out[1] > 0).  K'
+// from the plane or recomputed; w (NPAD), part (partial-sum layout), blk1,
+// blk2 (grid1(N)) are work buffers.
+hipError_t launch_residual(const void* Kp, int prec, int ksrc, const Features& F, const KernelParams& kp,
+                           const uint32_t* tiles, int64_t ntiles, int NB, int64_t N, int64_t NPAD,
+                           const double* alpha, const float* y, const double* Adiag, const double* rsum,
+                           double* w, double* part, double* blk1, double* blk2, double* out, hipStream_t s);
 hipError_t launch_kernel_entries(const void* Kp, int prec, int NB, const int64_t* rows,
                                  const int64_t* cols, int64_t n, double* out, hipStream_t s);
 // Decision function (gabp_predict.hip).  Queries are padded to

@@ -383,6 +383,115 @@ __global__ __launch_bounds__(WG) void k_rowsum(const ST* __restrict__ Kp, Featur
     }
 }
 
+// Residual certificate of a finished solve: partial products
+// sum_{j != i} K'_ij w_j (w_j = y_j alpha_j) per tile slot, in FP64, in the
+// layout and lane order of k_rowsum (row part: slot J of block I; column
+// part: slot I of block J, or slot NB for a diagonal tile).
+template <class ST, int KSRC, int GK>
+__global__ __launch_bounds__(WG) void k_apply(const ST* __restrict__ Kp, Features F, KernelParams kp,
+                                             const uint32_t* __restrict__ tiles, int NB,
+                                             const double* __restrict__ w, double* __restrict__ part) {
+    const TileCoord tc = tile_of(tiles);
+    const size_t tbase = (size_t)blockIdx.x * TT;
+    const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63, g = l >> 4, q = l & 15;
+    const int col0 = wv * 64 + q * 4;
+    __shared__ double rows[4][TILE];
+    __shared__ float kband[KSRC == KSRC_RECOMPUTE ? 4 : 1][KSRC == KSRC_RECOMPUTE ? 32 * 64 : 1];
+    const double* wI = w + (size_t)tc.I * TILE;
+    const double* wJ = w + (size_t)tc.J * TILE;
+    double wc[4], cs[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) wc[c] = wJ[col0 + c];
+    for (int b = 0; b < TILE / 32; ++b) {
+        if constexpr (KSRC == KSRC_RECOMPUTE) {
+            gram_band<GK>(F, kp, tc.I, tc.J, 32 * b, 64 * wv, kband[wv]);
+            wave_lds_sync();
+        }
+        for (int s2 = 0; s2 < 8; ++s2) {
+            const int r = 32 * b + 4 * s2 + g;
+            V4<ST> k;
+            if constexpr (KSRC == KSRC_RECOMPUTE) {
+                const float4 kk = *reinterpret_cast<const float4*>(&kband[wv][(4 * s2 + g) * 64 + 4 * q]);
+                k = V4<ST>{{(ST)kk.x, (ST)kk.y, (ST)kk.z, (ST)kk.w}};
+            } else {
+                k = ld4(Kp + tbase + (size_t)r * TILE + col0);
+            }
+            const double wr = wI[r];
+            double rs = 0.0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double a = (double)k.v[c];
+                rs = fma(a, wc[c], rs);
+                cs[c] = fma(a, wr, cs[c]);
+            }
+            rs = sum16(rs);
+            if (q == 0) rows[wv][r] = rs;
+        }
+        if constexpr (KSRC == KSRC_RECOMPUTE) wave_lds_sync();
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) cs[c] = sum_groups(cs[c]);
+    __syncthreads();
+    part[((size_t)tc.I * (NB + 1) + tc.J) * TILE + tid] = (rows[0][tid] + rows[1][tid]) + (rows[2][tid] + rows[3][tid]);
+    if (g == 0) {
+        const int slot = (tc.I < tc.J) ? tc.I : NB;
+        const size_t cb = ((size_t)tc.J * (NB + 1) + slot) * TILE + col0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) part[cb + c] = cs[c];
+    }
+}
+
+// w_i = y_i alpha_i on [0, N), zero on the padded rows.
+__global__ void k_weights(int64_t N, int64_t NPAD, const double* __restrict__ alpha,
+                          const float* __restrict__ y, double* __restrict__ w) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < NPAD) w[i] = (i < N) ? (double)y[i] * alpha[i] : 0.0;
+}
+
+// Per node: (A alpha)_i = A_ii alpha_i + y_i sum_{j != i} K'_ij w_j from the
+// slot partials in slot order; per block: max_i |1 - (A alpha)_i| (+inf for a
+// non-finite value) and min_i (A_ii - r_i).
+__global__ __launch_bounds__(WG) void k_residual_blocks(int64_t N, int NB, const double* __restrict__ part,
+                                                        const double* __restrict__ Adiag,
+                                                        const double* __restrict__ rsum,
+                                                        const double* __restrict__ alpha,
+                                                        const float* __restrict__ y, double* __restrict__ bres,
+                                                        double* __restrict__ bgap) {
+    __shared__ double sh4[4];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double res = 0.0, ngap = -INFINITY;
+    if (i < N) {
+        const int64_t B = i / TILE, t = i % TILE;
+        double acc = 0.0;
+        for (int sl = 0; sl <= NB; ++sl) acc += part[((size_t)B * (NB + 1) + sl) * TILE + t];
+        const double r = 1.0 - (Adiag[i] * alpha[i] + (double)y[i] * acc);
+        res = isfinite(r) ? fabs(r) : INFINITY;
+        ngap = -(Adiag[i] - rsum[i]);
+    }
+    res = block_max(res, sh4);
+    __syncthreads();
+    ngap = block_max(ngap, sh4);
+    if (threadIdx.x == 0) { bres[blockIdx.x] = res; bgap[blockIdx.x] = ngap; }
+}
+
+// out[0] = ||1 - A alpha||_inf, out[1] = min_i (A_ii - r_i), out[2] = Varah's
+// bound out[0] / out[1] on ||alpha - A^-1 1||_inf (+inf unless out[1] > 0).
+__global__ __launch_bounds__(WG) void k_residual_final(int nb, const double* __restrict__ bres,
+                                                       const double* __restrict__ bgap, double* __restrict__ out) {
+    __shared__ double sh4[4];
+    double r = 0.0, ng = -INFINITY;
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) { r = fmax(r, bres[k]); ng = fmax(ng, bgap[k]); }
+    r = block_max(r, sh4);
+    __syncthreads();
+    ng = block_max(ng, sh4);
+    if (threadIdx.x == 0) {
+        const double gap = -ng;
+        out[0] = r;
+        out[1] = gap;
+        out[2] = (gap > 0.0) ? r / gap : INFINITY;
+    }
+}
+
 // Weighted diagonal (subsection "GaBP Algorithm Convergence") and the row
 // maxima of |K'|.  For the uniform rule this kernel leaves the per-block max
 // of A_ii - K'_ii for k_diag_shift.
@@ -807,6 +916,32 @@ hipError_t launch_rowsum(const void* Kp, int prec, int ksrc, const Features& F, 
             default: return hipErrorInvalidValue;
         }
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(const void* Kp, int prec, int ksrc, const Features& F, const KernelParams& kp,
+                           const uint32_t* tiles, int64_t ntiles, int NB, int64_t N, int64_t NPAD,
+                           const double* alpha, const float* y, const double* Adiag, const double* rsum,
+                           double* w, double* part, double* blk1, double* blk2, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_weights, dim3(grid1(NPAD)), dim3(WG), 0, s, N, NPAD, alpha, y, w);
+    const dim3 g((unsigned)ntiles), b(WG);
+    if (ksrc == KSRC_PLANE) {
+        if (prec == PREC_FP64)
+            hipLaunchKernelGGL((k_apply<double, KSRC_PLANE, GRAM_F64>), g, b, 0, s, (const double*)Kp, F, kp, tiles, NB, w, part);
+        else
+            hipLaunchKernelGGL((k_apply<float, KSRC_PLANE, GRAM_F32>), g, b, 0, s, (const float*)Kp, F, kp, tiles, NB, w, part);
+    } else {
+        switch (F.kind) {
+            case GRAM_F32: hipLaunchKernelGGL((k_apply<float, KSRC_RECOMPUTE, GRAM_F32>), g, b, 0, s, nullptr, F, kp, tiles, NB, w, part); break;
+            case GRAM_BF16: hipLaunchKernelGGL((k_apply<float, KSRC_RECOMPUTE, GRAM_BF16>), g, b, 0, s, nullptr, F, kp, tiles, NB, w, part); break;
+            case GRAM_BF16X3: hipLaunchKernelGGL((k_apply<float, KSRC_RECOMPUTE, GRAM_BF16X3>), g, b, 0, s, nullptr, F, kp, tiles, NB, w, part); break;
+            case GRAM_BF16X6: hipLaunchKernelGGL((k_apply<float, KSRC_RECOMPUTE, GRAM_BF16X6>), g, b, 0, s, nullptr, F, kp, tiles, NB, w, part); break;
+            default: return hipErrorInvalidValue;
+        }
+    }
+    const unsigned nb = grid1(N);
+    hipLaunchKernelGGL(k_residual_blocks, dim3(nb), dim3(WG), 0, s, N, NB, part, Adiag, rsum, alpha, y, blk1, blk2);
+    hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(WG), 0, s, (int)nb, blk1, blk2, out);
     return hipGetLastError();
 }
 

@@ -138,6 +138,7 @@ struct Req {
     size_t footprint = 0;
     int slot = -1;
     int bypassed = 0;
+    int32_t refused = 0; // set up but refused (gabp_status): no plan without a bound
     int levels = 0;      // 0: stored pair records; >= 1: stateless levels
     int ser = 0;         // stateless reciprocals: 0 exact, 1 / 2 series (top-level terms)
     double rho = 0.0;    // contraction bound
@@ -303,6 +304,12 @@ hipError_t setup_request(gabp_server* S, Req& r) {
     bool stateless = false;
     if (r.p.edge_state == GABP_EDGE_STATELESS) stateless = true;
     else if (r.p.edge_state == GABP_EDGE_AUTO) stateless = dneed <= 8;
+    if (stateless && r.p.stateless_depth == 0 && !(rr < 1.0)) {
+        // as in a single solve: an explicit stateless plan with an automatic
+        // depth needs a contraction bound, else the request is refused
+        r.refused = GABP_E_INVALID;
+        return hipSuccess;
+    }
     r.levels = stateless ? (r.p.stateless_depth > 0 ? r.p.stateless_depth : std::min(dneed, 8)) : 0;
     r.ser = stateless ? stateless_series_form(r.prec, r.levels, rr) : 0;
     if (stateless) {
@@ -592,6 +599,14 @@ void worker_loop(gabp_server* S) {
                 fail_all_active(S);
                 S->cv_done.notify_all();
                 return;
+            }
+            if (r->refused) {
+                std::lock_guard<std::mutex> lk(S->mu);
+                S->arena.release_all(r->sizes, r->offs);
+                S->slots[r->slot] = nullptr;
+                finish(S, *r, r->refused, R_NONE, 0);
+                S->cv_done.notify_all();
+                continue;
             }
             lists_dirty = true;
         }

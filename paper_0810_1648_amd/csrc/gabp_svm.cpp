@@ -110,6 +110,10 @@ struct gabp_svm {
         sp_offj, sp_ids, sp_perm, sp_tmp, sp_order, sp_Xp, sp_cent, sp_rad, sp_keep, sp_tsel, sp_nsel, sp_xb;
     bool sparse = false;
     int64_t n_edges = 0;
+    // residual certificate of the last solve (GABP_Q_RESIDUAL_BOUND), formed
+    // on the first query
+    bool resid_valid = false;
+    double resid[3] = {0.0, 0.0, 0.0};
 
     DevBuf* all[62] = {&tiles, &Kp, &Pf, &Pb, &Ef, &Eb, &partP, &partE, &Xin, &yd, &mean,
                        &xs32, &xhi, &xlo, &xlo2, &x64, &nrm, &kdiag, &rowmax, &rsum, &Adiag, &Pt, &S, &alpha_d,
@@ -168,6 +172,7 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     const double t_start = now_ms();
     const gabp_svm_params& p = h->p;
     h->have_result = false;
+    h->resid_valid = false;
     h->err.clear();
     if (!y || N < 1 || (X && m < 1) || (!X && !K)) return fail(h, GABP_E_INVALID, "need N >= 1, m >= 1 and non-NULL inputs");
     if (mem != GABP_MEM_HOST && mem != GABP_MEM_DEVICE) return fail(h, GABP_E_INVALID, "unknown mem kind");
@@ -416,6 +421,24 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     bool cur_stored = stored;
     int depth = 0;
     if (probe) cur_stored = dneed > 8;
+    // AUTO takes the stateless form only with a depth (<= 8) whose truncation
+    // the contraction bound keeps below the message precision; an explicit
+    // STATELESS plan with an automatic depth takes at most 8 levels and needs
+    // a bound (1.25 rho < 1) to have any; an explicit depth is taken as given.
+    // The plan flags every depth below the bound's (stateless_bounded = 0).
+    if (!cur_stored && p.stateless_depth == 0 &&
+        (p.edge_state == GABP_EDGE_AUTO ? dneed > 8 : !(rr < 1.0))) {
+        char msg[320];
+        if (p.edge_state == GABP_EDGE_AUTO)
+            snprintf(msg, sizeof msg, "stored pair records do not fit the budget (%.3f GB) and the stateless form "
+                     "has no truncation bound within 8 levels for this system (contraction bound rho = %.4g)",
+                     budget / 1e9, rho);
+        else
+            snprintf(msg, sizeof msg, "the stateless form has no truncation bound for this system (contraction "
+                     "bound rho = %.4g); set stateless_depth to accept an unbounded truncation", rho);
+        h->release_all();
+        return fail(h, p.edge_state == GABP_EDGE_AUTO ? GABP_E_NOMEM : GABP_E_INVALID, msg);
+    }
     if (!cur_stored) depth = (p.stateless_depth > 0) ? p.stateless_depth : std::min(dneed, 8);
     const int ser = cur_stored ? 0 : stateless_series_form(prec, depth, rr);
     if (probe && cur_stored) {
@@ -614,6 +637,7 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
                  : (gram == GRAM_BF16 ? GABP_GRAM_BF16 : GABP_GRAM_AUTO);
     h->plan.tile = TILE;
     h->plan.stateless_depth = depth;
+    h->plan.stateless_bounded = stored ? 1 : (depth >= dneed ? 1 : 0);
     h->plan.stateless_rho = rho;
     h->plan.series_reciprocal = ser;
     h->plan.sched_groups = grouped ? G : 0;
@@ -632,12 +656,46 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     return (gabp_status)h->status;
 }
 
+// Residual certificate of the last dense solve (subsection "GaBP Algorithm
+// Convergence": under diagonal dominance, Varah's bound turns the residual
+// into an error bound): ||1 - A alpha||_inf over all N rows, one pass over K'
+// (the plane, or K' recomputed per band as in the sweep) with FP64 sums in a
+// fixed order, min_i (A_ii - r_i) and their quotient.  alpha is the solver's
+// own (before any output clipping).  The handle's work buffers of the solve
+// (partial sums, block maxima) are reused.
+gabp_status residual_certificate(gabp_svm* h) {
+    if (h->sparse) return fail(h, GABP_E_STATE, "the residual certificate is defined for dense solves");
+    HIPCHK(h, hipSetDevice(h->p.device));
+    const bool kmat = h->plan.kstore == GABP_KSTORE_MATERIALISE;
+    Features F{};
+    F.f32 = h->xs32.as<float>(); F.hi = h->xhi.as<uint16_t>(); F.lo = h->xlo.as<uint16_t>();
+    F.lo2 = h->xlo2.as<uint16_t>(); F.f64 = h->x64.as<double>(); F.nrm = h->nrm.as<float>();
+    F.m_pad = h->m_pad; F.kind = h->gram;
+    KernelParams kp{};
+    kp.N = h->N;
+    kp.NB = h->NB;
+    kp.gamma = h->p.gamma;
+    kp.neg_gamma_log2e = (float)(-h->p.gamma * 1.4426950408889634);
+    kp.lam2 = h->rbf ? h->lam * h->lam : 0.0;
+    hipStream_t s = nullptr;
+    HIPCHK(h, launch_residual(h->Kp.p, h->prec, kmat ? KSRC_PLANE : KSRC_RECOMPUTE, F, kp, h->tiles.as<uint32_t>(),
+                              h->ntiles, h->NB, h->N, h->NPAD, h->alpha_d.as<double>(), h->yd.as<float>(),
+                              h->Adiag.as<double>(), h->rsum.as<double>(), h->tmp.as<double>(),
+                              h->partP.as<double>(), h->blk1.as<double>(), h->blk2.as<double>(),
+                              h->one.as<double>(), s));
+    HIPCHK(h, hipMemcpyAsync(h->resid, h->one.p, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    h->resid_valid = true;
+    return GABP_OK;
+}
+
 // Sparsified RBF kernel: graph build on the device, then synchronous GaBP on
 // the kept pairs with stored records per edge (see gabp_sparse.hip).
 gabp_status solve_sparse_impl(gabp_svm* h, const float* X, const float* y, int64_t N, int64_t m, int32_t mem,
                               hipStream_t s) {
     const double t_start = now_ms();
     h->have_result = false;
+    h->resid_valid = false;
     h->status = GABP_E_STATE;
     const gabp_svm_params& p = h->p;
     if (N < 1 || m < 1 || !y) return fail(h, GABP_E_INVALID, "N >= 1, m >= 1 and y are required");
@@ -1140,6 +1198,15 @@ gabp_status gabp_svm_query(const gabp_svm* h, int32_t what, void* dst, size_t by
         case GABP_Q_TRACE: return put(h->trace.data(), h->trace.size() * 8);
         case GABP_Q_PLAN: return put(&h->plan, sizeof h->plan);
         case GABP_Q_REASON: return put(&h->reason, sizeof h->reason);
+        case GABP_Q_RESIDUAL_BOUND: {
+            if (bytes < 3 * sizeof(double)) return GABP_E_BUFSIZE;
+            gabp_svm* hm = const_cast<gabp_svm*>(h);
+            if (!hm->resid_valid) {
+                const gabp_status rs = residual_certificate(hm);
+                if (rs != GABP_OK) return rs;
+            }
+            return put(hm->resid, 3 * sizeof(double));
+        }
         case GABP_Q_EDGES: {
             if (!h->sparse) return GABP_E_STATE;
             const size_t E = (size_t)h->n_edges;

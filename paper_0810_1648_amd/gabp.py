@@ -30,7 +30,7 @@ SCHED = {"sync": 0, "grouped": 1}
 MEM_HOST, MEM_DEVICE = 0, 1
 REASON = {0: "none", 1: "converged", 2: "max_sweeps", 3: "diverged", 4: "stagnated"}
 Q_N, Q_ALPHA, Q_PTILDE, Q_ADIAG, Q_BIAS, Q_SV_MASK, Q_SV_COUNT, Q_SWEEPS, Q_DELTA, Q_STATUS, \
-    Q_TIMINGS, Q_TRACE, Q_PLAN, Q_REASON, Q_EDGES = range(15)
+    Q_TIMINGS, Q_TRACE, Q_PLAN, Q_REASON, Q_EDGES, Q_RESIDUAL_BOUND = range(16)
 
 
 class Params(ct.Structure):
@@ -64,7 +64,7 @@ class Plan(ct.Structure):
                 ("n_blocks", ct.c_int64), ("n_tiles", ct.c_int64), ("device_bytes", ct.c_uint64),
                 ("alg_bytes_per_sweep", ct.c_uint64), ("alg_bytes_per_pair", ct.c_double),
                 ("stateless_rho", ct.c_double), ("series_reciprocal", ct.c_int32), ("sched_groups", ct.c_int32),
-                ("n_edges", ct.c_int64)]
+                ("n_edges", ct.c_int64), ("stateless_bounded", ct.c_int32), ("reserved", ct.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -77,7 +77,7 @@ class GabpError(RuntimeError):
 
 
 _lib = None
-ABI_VERSION = 6     # GABP_ABI_VERSION the structures above describe
+ABI_VERSION = 7     # GABP_ABI_VERSION the structures above describe
 
 
 def lib():
@@ -288,6 +288,13 @@ class GabpSVM:
         """Kept pairs (i, j), i < j, of a sparsified solve (int64, E x 2)."""
         E = int(self.plan()["n_edges"])
         return self._q(Q_EDGES, np.zeros((E, 2), np.int64))
+
+    def residual_bound(self):
+        """GABP_Q_RESIDUAL_BOUND: ||1 - A alpha||_inf over all rows, the
+        dominance gap min_i (A_ii - r_i) and Varah's bound on
+        ||alpha - A^-1 1||_inf (one device pass over K')."""
+        v = self._q(Q_RESIDUAL_BOUND, np.zeros(3))
+        return {"residual_inf": float(v[0]), "gap": float(v[1]), "bound": float(v[2])}
 
     def kernel_entries(self, rows, cols):
         r = np.ascontiguousarray(rows, dtype=np.int64)

@@ -1,15 +1,25 @@
-"""Parity at the full workload sizes, in the plan the benchmark times.
+"""Parity at the full workload sizes, in the plans the benchmark times.
 
-The oracle cannot solve these systems whole, so it computes sampled
-outputs one row at a time from the features (O(N m) per row):
-* the weighted diagonal A_ii of sampled rows, compared element-wise;
-* sampled K' entries (materialised plans), compared element-wise;
-* residual rows r_i = 1 - (A alpha)_i of sampled rows: if
-  ||alpha - alpha*||_inf <= 1e-5 ||alpha*||_inf then
-  |r_i| <= sum_j |A_ij| 1e-5 ||alpha*||_inf <= 2 A_ii 1e-5 ||alpha||_inf
-  under the dominant-row rule (sum_{j != i} |A_ij| <= A_ii / 1.1), which is
-  the property checked.
+alpha is compared element by element with the FP64 reference solution
+alpha* = A^-1 1 of the oracle (tests/golden/alpha_ref/, written by
+tests/golden/make_alpha_ref.py from the oracle alone: conjugate gradients on
+the oracle's matrix-free FP64 product, certified by its residual and Varah's
+bound, and for the 20,000-point workload cross-checked against the oracle's
+own GaBP solve and LAPACK Cholesky):
+    ||alpha - alpha*||_inf <= 1e-5 ||alpha*||_inf.
+The stored arrays carry the SHA-256 of the generated X and y, so a changed
+generator cannot pass against a stale reference.
+
+Sampled outputs the oracle computes one row at a time from the features
+(O(N m) per row) are compared too: the weighted diagonal A_ii and K' entries
+(materialised plans).  The device's residual certificate (one pass over K':
+||1 - A alpha||_inf over every row and Varah's bound) is reported and must
+certify the device's own system to 1e-5.
 """
+import hashlib
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -18,6 +28,41 @@ from paper_0810_1648_amd import gabp, inputs
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "alpha_ref")
+
+
+def alpha_ref(wl, key=None):
+    """The oracle's alpha* for workload wl, after checking that it was
+    computed from these very arrays."""
+    key = key or wl.name
+    meta = json.load(open(os.path.join(GOLDEN, f"{key}.json")))
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(wl.X, dtype=np.float32).tobytes())
+    h.update(np.ascontiguousarray(wl.y, dtype=np.float32).tobytes())
+    assert h.hexdigest() == meta["data_sha256"], f"{key}: generated data differ from the reference's"
+    assert meta["varah_bound_rel"] < 1e-10
+    return np.load(os.path.join(GOLDEN, f"{key}.npz"))["alpha"]
+
+
+def _check_alpha(s, wl, tol=TOL, label=""):
+    ref = alpha_ref(wl)
+    a = s.alpha()
+    err = float(np.max(np.abs(a - ref)) / np.max(np.abs(ref)))
+    print(f"{wl.name}{label}: plan {s.plan()} sweeps {s.sweeps()} reason {s.reason()} "
+          f"||alpha - alpha*||_inf / ||alpha*||_inf = {err:.3e}", flush=True)
+    assert err <= tol
+    return err
+
+
+def _check_certificate(s, wl, tol=TOL):
+    """Device residual certificate: Varah's bound on the distance from the
+    device system's exact solution, relative to ||alpha||_inf."""
+    c = s.residual_bound()
+    rel = c["bound"] / float(np.max(np.abs(s.alpha())))
+    print(f"{wl.name}: residual ||1 - A alpha||_inf = {c['residual_inf']:.3e}, gap {c['gap']:.4g}, "
+          f"Varah bound {c['bound']:.3e} ({rel:.3e} of ||alpha||_inf)", flush=True)
+    assert c["gap"] > 0 and np.isfinite(c["bound"]) and rel <= tol
+    return c
 
 
 @pytest.fixture(scope="module")
@@ -54,11 +99,15 @@ def _check_rows(s, wl, oracle_c, nrows=48, seed=0):
     return rows
 
 
-def test_letter_full_fp32(torch, oracle_c):
+@pytest.mark.parametrize("edge", ["auto", "stored"])
+def test_letter_full_fp32(torch, oracle_c, edge):
     wl = inputs.make_workload("letter")
-    s, st = _solve(torch, wl, precision="fp32")
+    s, st = _solve(torch, wl, precision="fp32", edge_state=edge)
     assert st == gabp.OK
+    _check_alpha(s, wl, label=f" fp32/{edge}")
     _check_rows(s, wl, oracle_c)
+    if edge == "auto":
+        _check_certificate(s, wl)
     if s.plan()["kstore"] == gabp.KSTORE["materialise"]:
         rng = np.random.default_rng(1)
         i = rng.integers(0, wl.N, 64)
@@ -67,22 +116,29 @@ def test_letter_full_fp32(torch, oracle_c):
         np.testing.assert_allclose(s.kernel_entries(i, j), ref, rtol=2e-6)
 
 
-@pytest.mark.parametrize("edge", ["auto", "stored"])
-def test_covertype_full_mixed(torch, oracle_c, edge):
+@pytest.mark.parametrize("prec,edge", [("mixed", "auto"), ("mixed", "stored"), ("fp32", "auto")])
+def test_covertype_full(torch, oracle_c, prec, edge):
+    """The benchmark's headline plan (MIXED, AUTO: stateless three levels,
+    one-term series, FP32 messages, BF16x6 Gram), the stored-record plan and
+    plain FP32, each against alpha* element-wise."""
     wl = inputs.make_workload("covertype")
-    s, st = _solve(torch, wl, edge_state=edge)
+    s, st = _solve(torch, wl, precision=prec, edge_state=edge)
     assert st == gabp.OK
+    _check_alpha(s, wl, label=f" {prec}/{edge}")
     _check_rows(s, wl, oracle_c)
     if edge == "auto":
+        _check_certificate(s, wl)
+    if (prec, edge) == ("mixed", "auto"):
         _check_predict(s, wl)
 
 
 def test_covertype_full_grouped_schedule(torch, oracle_c):
     """The grouped (block Gauss-Seidel) schedule at the full size, in the plan
-    the benchmark times: same residual-row bound as the synchronous solve."""
+    the benchmark times: the same fixed point, alpha* element-wise."""
     wl = inputs.make_workload("covertype")
     s, st = _solve(torch, wl, schedule="grouped")
     assert st == gabp.OK and s.plan()["sched_groups"] >= 2
+    _check_alpha(s, wl, label=" grouped")
     _check_rows(s, wl, oracle_c, seed=3)
 
 
@@ -110,7 +166,9 @@ def test_large_full_stateless_recompute(torch, oracle_c):
     p = s.plan()
     assert p["kstore"] == gabp.KSTORE["recompute"] and p["edge_state"] == gabp.EDGE["stateless"]
     assert st == gabp.OK
+    _check_alpha(s, wl, label=" recompute/stateless")
     _check_rows(s, wl, oracle_c, nrows=32)
+    _check_certificate(s, wl)
 
 
 def test_large_sparse_full(torch):

@@ -6,6 +6,10 @@ request runs alone or in a mix of uneven sizes and precisions; the
 tolerance stated for serving (1e-5 relative to the FP64 oracle) then
 follows from the single-solve parity tests.
 """
+import json
+import os
+import time
+
 import numpy as np
 import pytest
 
@@ -179,3 +183,84 @@ def test_served_grouped_schedule_equals_single(torch):
             st, ref, sw, d = single[k]
             assert info["status"] == st and info["sweeps"] == sw, (k, info, st, sw)
             assert np.array_equal(a, ref), k
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "alpha_ref")
+
+
+@pytest.mark.parametrize("precision", ["fp32", "mixed"])
+def test_served_stream_matches_alpha_ref(torch, precision):
+    """The first requests of the benchmark's serving stream (seed 3), served
+    together, against the oracle's alpha* of each (conjugate gradients on the
+    FP64 matrix-free product; tests/golden/alpha_ref/serve_req*.npz), element
+    by element: ||alpha - alpha*||_inf <= 1e-5 ||alpha*||_inf, in FP32 and in
+    the mixed precision pattern."""
+    import hashlib
+    stream = inputs.serving_stream(512, rate_per_s=1.0, seed=3)
+    reqs = []
+    for rid in range(8):
+        meta = json.load(open(os.path.join(GOLDEN, f"serve_req{rid}.json")))
+        wl = stream[rid].workload
+        h = hashlib.sha256()
+        h.update(wl.X.tobytes())
+        h.update(wl.y.tobytes())
+        assert meta["request"] == rid and h.hexdigest() == meta["data_sha256"]
+        reqs.append((wl, np.load(os.path.join(GOLDEN, f"serve_req{rid}.npz"))["alpha"]))
+    print(f"[case] served stream requests 0-7 ({precision}), N {[w.N for w, _ in reqs]}", flush=True)
+    with gabp.GabpServer(arena_bytes=int(40e9), max_active=8) as srv:
+        tickets = [srv.submit(wl.X, wl.y, gamma=wl.gamma, C=wl.C, precision=precision, tol_rel=wl.tol_rel,
+                              kstore="materialise", schedule="grouped", sched_groups=4) for wl, _ in reqs]
+        for t in tickets:
+            assert srv.wait(t, 300.0)
+        errs = []
+        for (wl, ref), t in zip(reqs, tickets):
+            a, info = srv.result(t)
+            assert info["status"] == gabp.OK
+            errs.append(float(np.max(np.abs(a - ref)) / np.max(np.abs(ref))))
+    print(f"served {precision}: rel err vs alpha* per request {['%.1e' % e for e in errs]}")
+    assert max(errs) <= 1e-5
+
+
+def _footprint(X, y, kw):
+    with gabp.GabpServer(arena_bytes=int(20e9), max_active=1) as srv:
+        t = srv.submit(X, y, **kw)
+        assert srv.wait(t, 120.0)
+        return srv.result(t)[1]["device_bytes"]
+
+
+def test_admission_fifo_with_bounded_bypass(torch):
+    """Admission is FIFO with a bounded bypass: while a large request at the
+    head of the queue does not fit, smaller requests behind it that fit are
+    admitted, but at most max_bypass of them; later ones wait until the head
+    has been admitted, and requests of equal size keep their submission
+    order."""
+    kwb = dict(gamma=1.0 / 16, C=1.0, precision="fp64", tol_rel=1e-12, edge_state="stored", kstore="materialise")
+    kws = dict(gamma=1.0 / 16, C=1.0, precision="fp32", tol_rel=1e-7, edge_state="stored", kstore="materialise")
+    big = [inputs.blobs(12000, 16, 8100 + k) for k in range(2)]
+    small = [inputs.blobs(700, 16, 8200 + k) for k in range(5)]
+    fb, fs = _footprint(*big[0], kwb), _footprint(*small[0], kws)
+    print(f"[case] bypass: big footprint {fb / 1e9:.3f} GB, small {fs / 1e6:.1f} MB", flush=True)
+    arena = int(fb + 3.5 * fs)          # one big request and three small ones at a time
+    with gabp.GabpServer(arena_bytes=arena, max_active=16, max_bypass=2, steps_per_poll=1) as srv:
+        sub = {}
+        tickets = []
+        for name, (X, y), kw in [("B0", big[0], kwb), ("B1", big[1], kwb)] + \
+                [(f"s{k}", small[k], kws) for k in range(5)]:
+            sub[name] = time.monotonic()
+            tickets.append((name, srv.submit(X, y, **kw)))
+        for _, t in tickets:
+            assert srv.wait(t, 300.0)
+        admit = {}
+        for name, t in tickets:
+            _, info = srv.result(t)
+            assert info["status"] == gabp.OK, (name, info)
+            admit[name] = sub[name] + info["queue_ms"] / 1e3
+    order = sorted(admit, key=admit.get)
+    print("admission order", order, {k: round((v - admit['B0']) * 1e3, 2) for k, v in admit.items()})
+    eps = 2e-3                            # host clock reads around the submit calls
+    # the head B1 waits for B0; two small requests pass it, the third does not
+    assert admit["s0"] < admit["B1"] and admit["s1"] < admit["B1"]
+    for k in (2, 3, 4):
+        assert admit[f"s{k}"] >= admit["B1"] - eps, k
+    for k in range(4):
+        assert admit[f"s{k}"] <= admit[f"s{k + 1}"] + eps, k
