@@ -322,6 +322,25 @@ gabp_status gabp_svm_kernel_entries(const gabp_svm *h, const int64_t *rows,
 gabp_status gabp_svm_predict(gabp_svm *h, const float *Xq, int64_t nq,
                              double *f_out, int32_t mem, void *stream);
 
+/* The decision function of gabp_svm_predict, allocating nothing: for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Xq (nq x m float32,
+ * row-major) and f_out (nq float64) are DEVICE pointers; the call only
+ * enqueues work on `stream` (NULL = default stream) and returns, so f_out is
+ * ready once that stream's work completes.  Weights, partial sums and staged
+ * queries live in one scratch array of GABP_PREDICT_SCRATCH_BYTES per device,
+ * held until the process ends and shared by every call on that device: calls
+ * that overlap on one device (other streams, other threads or handles) race
+ * on it and must be serialised by the caller.  Every scratch byte a call
+ * reads is written earlier in the same call.  GABP_E_NOMEM (with the bytes
+ * needed in gabp_svm_last_error) when one call's working set exceeds the
+ * array -- about 3 * 128 * m_pad bytes per 128 queries plus 8 bytes per
+ * training point and per (query, training chunk) partial sum;
+ * GABP_E_STATE without a finished dense RBF solve. */
+#define GABP_PREDICT_SCRATCH_BYTES (64u << 20)
+gabp_status gabp_svm_predict_noalloc(gabp_svm *h, const float *Xq, int64_t nq,
+                                     double *f_out, void *stream);
+
 /* Frees the handle and everything it holds.  NULL is ignored. */
 void gabp_svm_destroy(gabp_svm *h);
 

@@ -308,6 +308,11 @@ hipError_t launch_kernel_entries(const void* Kp, int prec, int NB, const int64_t
 // nchunk chunks of bpc 32-row blocks (predict_chunks) and writes
 // part[nchunk][NQPAD]; the direct FP64 form writes part[nq].
 int64_t predict_query_pad(int64_t nq);
+// Bytes of the per-device scratch array of the allocation-free decision
+// function (gabp_svm_predict_noalloc), and its device address on the current
+// device (looked up once per device, then cached).
+constexpr size_t PREDICT_SCRATCH_BYTES = size_t(64) << 20;
+hipError_t predict_scratch(void** ptr);
 void predict_chunks(int64_t NPAD, int64_t NQPAD, int* nchunk, int* bpc);
 hipError_t launch_predict_weights(const double* alpha, const float* y, int64_t N, int64_t NPAD, bool box,
                                   double C, double* w, double* blk, double* wsum, hipStream_t s);

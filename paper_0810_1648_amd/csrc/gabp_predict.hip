@@ -13,7 +13,36 @@
 // timing.
 #include "gabp_device.h"
 
+#include <mutex>
+
+// Working memory of the allocation-free decision function: weights, partial
+// sums and staged queries of one call.  Each device holds its own copy for
+// the life of the process; host code reaches it only through the address
+// that predict_scratch() looks up (the array's name is not a device address
+// in host code).
+static __device__ __align__(256) unsigned char scratch[gabp::PREDICT_SCRATCH_BYTES];
+
 namespace gabp {
+
+hipError_t predict_scratch(void** ptr) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
 
 namespace {
 

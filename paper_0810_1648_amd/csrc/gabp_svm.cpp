@@ -1135,6 +1135,15 @@ gabp_status gabp_svm_create(const gabp_svm_params* params, gabp_svm** out) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, params->device) != hipSuccess) return GABP_E_DEVICE;
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return GABP_E_DEVICE;
+    // set-up of the allocation-free decision function: the scratch array's
+    // address on this device, looked up once per device with it current
+    {
+        int prev = 0;
+        if (hipGetDevice(&prev) != hipSuccess) { (void)hipGetLastError(); return GABP_E_DEVICE; }
+        void* sp = nullptr;
+        const bool ok = hipSetDevice(params->device) == hipSuccess && predict_scratch(&sp) == hipSuccess;
+        if (hipSetDevice(prev) != hipSuccess || !ok) { (void)hipGetLastError(); return GABP_E_DEVICE; }
+    }
     gabp_svm* h = new (std::nothrow) gabp_svm();
     if (!h) return GABP_E_NOMEM;
     h->p = *params;
@@ -1352,6 +1361,73 @@ gabp_status gabp_svm_predict(gabp_svm* h, const float* Xq, int64_t nq, double* f
             HIPCHK(h, hipEventElapsedTime(&ms, pev.ev[2 * b], pev.ev[2 * b + 1]));
             h->tm.predict_kernel_ms += ms;
         }
+    return GABP_OK;
+}
+
+static_assert(GABP_PREDICT_SCRATCH_BYTES == PREDICT_SCRATCH_BYTES, "scratch size of the header and the library");
+
+gabp_status gabp_svm_predict_noalloc(gabp_svm* h, const float* Xq, int64_t nq, double* f_out, void* stream) {
+    if (!h || !Xq || !f_out || nq < 0) return GABP_E_INVALID;
+    if (!h->have_result || !h->rbf || h->sparse) return fail(h, GABP_E_STATE, "predict needs a finished dense RBF solve");
+    if (nq == 0) return GABP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(h, hipSetDevice(h->p.device));
+    void* base = nullptr;
+    HIPCHK(h, predict_scratch(&base));
+    const int64_t m = h->m, N = h->N, NPAD = h->NPAD;
+    const bool f64 = h->prec == PREC_FP64;
+    const int gram = h->gram, mp = h->m_pad;
+    const int64_t qpad = predict_query_pad(nq);
+    int nc = 1, bp = 1;
+    if (!f64) predict_chunks(NPAD, qpad, &nc, &bp);
+    // layout of one call in the scratch array, 256-byte aligned segments
+    // (every byte read is written earlier in the same call on `stream`, so
+    // nothing needs clearing between calls)
+    size_t off = 0;
+    auto seg = [&](size_t bytes) { const size_t o = off; off += (bytes + 255) / 256 * 256; return o; };
+    const size_t fe = (size_t)qpad * mp;
+    const size_t o_w = seg((size_t)NPAD * 8), o_blk = seg((size_t)(NPAD / WG + 1) * 8), o_ws = seg(64);
+    const size_t o_part = seg(f64 ? (size_t)nq * 8 : (size_t)nc * qpad * 8);
+    size_t o_nrm = 0, o_f32 = 0, o_hi = 0, o_lo = 0, o_lo2 = 0;
+    if (!f64) {
+        o_nrm = seg((size_t)qpad * 4);
+        if (gram == GRAM_F32) o_f32 = seg(fe * 4);
+        else o_hi = seg(fe * 2);
+        if (gram == GRAM_BF16X3 || gram == GRAM_BF16X6) o_lo = seg(fe * 2);
+        if (gram == GRAM_BF16X6) o_lo2 = seg(fe * 2);
+    }
+    if (off > PREDICT_SCRATCH_BYTES) {
+        char msg[200];
+        snprintf(msg, sizeof msg, "%lld queries need %.1f MiB of scratch; the allocation-free predict holds %.0f MiB",
+                 (long long)nq, off / 1048576.0, PREDICT_SCRATCH_BYTES / 1048576.0);
+        return fail(h, GABP_E_NOMEM, msg);
+    }
+    char* b = static_cast<char*>(base);
+    double* w = reinterpret_cast<double*>(b + o_w);
+    double* blk = reinterpret_cast<double*>(b + o_blk);
+    double* wsum = reinterpret_cast<double*>(b + o_ws);
+    double* part = reinterpret_cast<double*>(b + o_part);
+    HIPCHK(h, launch_predict_weights(h->alpha_d.as<double>(), h->yd.as<float>(), N, NPAD,
+                                     h->p.box_mode == GABP_BOX_CLIP_OUTPUT, h->p.C, w, blk, wsum, s));
+    const double lam2 = h->lam * h->lam;
+    if (f64) {
+        HIPCHK(h, launch_predict_direct(h->Xin.as<float>(), w, N, m, Xq, nq, h->p.gamma, part, s));
+        HIPCHK(h, launch_predict_reduce(part, 1, nq, nq, wsum, lam2, f_out, s));
+        return GABP_OK;
+    }
+    Features Ft{}, Fq{};
+    Ft.f32 = h->xs32.as<float>(); Ft.hi = h->xhi.as<uint16_t>(); Ft.lo = h->xlo.as<uint16_t>();
+    Ft.lo2 = h->xlo2.as<uint16_t>(); Ft.nrm = h->nrm.as<float>(); Ft.m_pad = mp; Ft.kind = gram;
+    float* qnrm = reinterpret_cast<float*>(b + o_nrm);
+    float* qf32 = gram == GRAM_F32 ? reinterpret_cast<float*>(b + o_f32) : nullptr;
+    uint16_t* qhi = gram != GRAM_F32 ? reinterpret_cast<uint16_t*>(b + o_hi) : nullptr;
+    uint16_t* qlo = o_lo ? reinterpret_cast<uint16_t*>(b + o_lo) : nullptr;
+    uint16_t* qlo2 = o_lo2 ? reinterpret_cast<uint16_t*>(b + o_lo2) : nullptr;
+    Fq.f32 = qf32; Fq.hi = qhi; Fq.lo = qlo; Fq.lo2 = qlo2; Fq.nrm = qnrm; Fq.m_pad = mp; Fq.kind = gram;
+    const float c = (float)(-h->p.gamma * 1.4426950408889634);
+    HIPCHK(h, launch_stage(Xq, h->mean.as<double>(), nq, m, qpad, mp, gram, qf32, qhi, qlo, qlo2, nullptr, qnrm, s));
+    HIPCHK(h, launch_predict_mfma(Ft, Fq, w, NPAD, qpad, c, nc, bp, part, s));
+    HIPCHK(h, launch_predict_reduce(part, nc, qpad, nq, wsum, lam2, f_out, s));
     return GABP_OK;
 }
 

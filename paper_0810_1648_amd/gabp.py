@@ -102,6 +102,8 @@ def lib():
         L.gabp_svm_kernel_entries.restype = i32
         L.gabp_svm_predict.argtypes = [vp, vp, i64, vp, i32, vp]
         L.gabp_svm_predict.restype = i32
+        L.gabp_svm_predict_noalloc.argtypes = [vp, vp, i64, vp, vp]
+        L.gabp_svm_predict_noalloc.restype = i32
         L.gabp_svm_destroy.argtypes = [vp]
         L.gabp_svm_destroy.restype = None
         L.gabp_status_string.argtypes = [i32]
@@ -323,6 +325,20 @@ class GabpSVM:
             raise self._err(st, "gabp_svm_predict")
         return f
 
+    def predict_noalloc(self, Xq, f_out, stream=None):
+        """gabp_svm_predict_noalloc: Xq (nq x m float32) and f_out (nq
+        float64) are device tensors; the call only enqueues work on the
+        stream (the tensors' current stream by default)."""
+        nq = int(Xq.shape[0])
+        px, mx, kx = _ptr(Xq, np.float32)
+        pf, mf, kf = _ptr(f_out, np.float64)
+        if mx != MEM_DEVICE or mf != MEM_DEVICE or int(f_out.shape[0]) != nq:
+            raise TypeError("predict_noalloc takes device tensors Xq (nq x m) and f_out (nq)")
+        st = lib().gabp_svm_predict_noalloc(self._h, px, nq, pf, _stream_of(Xq, stream))
+        del kx, kf
+        if st != OK:
+            raise self._err(st, "gabp_svm_predict_noalloc")
+        return f_out
 
 # ------------------------------------------------------------------ serving --
 
