@@ -22,6 +22,9 @@ SOURCES = ["gabp_sweep_mixed.hip", "gabp_sweep_f32.hip", "gabp_sweep_f64.hip", "
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include")]
+# per-file additions: the decision function's MFMA accumulators in ordinary
+# VGPRs (its exp2 reads them directly instead of copying each out of an AGPR)
+FILE_FLAGS = {"gabp_predict.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _run(cmd, verbose):
@@ -42,7 +45,7 @@ def build(verbose: bool = False, jobs: int = 6) -> str:
     procs = []
     for src in SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, *FLAGS, *FILE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
             cmd.insert(1, "-xhip")
         objs.append(obj)

@@ -117,6 +117,15 @@ __device__ inline uint16_t f2bf(float f) {  // round to nearest even
     return (uint16_t)(u >> 16);
 }
 __device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+// v = h + l + l2 in BF16 (each the rounding of the remainder left by the
+// terms before it): h alone carries about 2^-9 of v, h + l about 2^-18,
+// h + l + l2 about 2^-27.
+__device__ inline void split3(float v, uint16_t& h, uint16_t& l, uint16_t& l2) {
+    h = f2bf(v);
+    const float r = v - bf2f(h);
+    l = f2bf(r);
+    l2 = f2bf(r - bf2f(l));
+}
 
 // Reciprocals: v_rcp_f32 (1 ulp) for FP32; for FP64, v_rcp_f64 refined by
 // two Newton steps (the cavity precisions are far from the denormal range).

@@ -321,6 +321,16 @@ hipError_t launch_predict_direct(const float* Xtr, const double* w, int64_t N, i
 hipError_t launch_predict_mfma(const Features& Ft, const Features& Fq, const double* w, int64_t NPAD,
                                int64_t NQPAD, float neg_gamma_log2e, int nchunk, int bpc, double* part,
                                hipStream_t s);
+// Augmented form (BF16 split kinds, m + 2 <= mp, mp = 32 or 64): rows staged
+// by launch_stage_aug (side 0 queries (x, n, 1); side 1 training rows
+// c (x, -1/2, -n/2), c = 2 gamma log2(e); `out` holds np planes of NPAD x mp
+// BF16); queries padded to predict_query_pad_aug, part[nchunk][NQPAD].
+int64_t predict_query_pad_aug(int64_t nq);
+void predict_chunks_aug(int64_t NPAD, int64_t NQPAD, int* nchunk, int* bpc);
+hipError_t launch_stage_aug(const float* X, const double* mean, int64_t n, int64_t m, int64_t NPAD, int mp, int kind,
+                            int side, float c, uint16_t* out, hipStream_t s);
+hipError_t launch_predict_aug(int kind, int mp, const uint16_t* Bt, int64_t NPAD, const uint16_t* Aq, int64_t NQPAD,
+                              const double* w, int nchunk, int bpc, double* part, hipStream_t s);
 hipError_t launch_predict_reduce(const double* part, int nchunk, int64_t stride, int64_t nq, const double* wsum,
                                  double lam2, double* f, hipStream_t s);
 hipError_t launch_convert_agg(int prec, const void* src, double* dst, int64_t n, hipStream_t s);

@@ -47,6 +47,8 @@ hipError_t predict_scratch(void** ptr) {
 namespace {
 
 constexpr int QB = 128;   // queries per workgroup: four waves of 32
+constexpr int AUG_FR = 2;                // augmented form: 32-query A fragments per wave
+constexpr int QBA = 4 * 32 * AUG_FR;      // augmented form: queries per workgroup
 
 // w_i = alpha_i y_i (alpha clipped to [0, C] with the box option), zero on
 // padded rows; per-block sums of w in a fixed tree order.
@@ -253,6 +255,196 @@ __global__ __launch_bounds__(WG) void k_predict_lds(Features Ft, Features Fq, co
     }
 }
 
+// ---- augmented rows: the MFMA emits the scaled exponent itself ----------
+//
+// Rows are extended by two columns so that the Gram of a query row a and a
+// training row b is the exponent of the kernel in base 2:
+//   a = (x_q, n_q, 1),   b = c (x_t, -1/2, -n_t/2),   c = 2 gamma log2(e),
+//   a . b = c (x_q . x_t - n_q/2 - n_t/2) = -gamma log2(e) ||x_q - x_t||^2,
+// so K(x_t, x_q) = exp2(min(a . b, 0)) (the clamp keeps rounding from
+// pushing K above 1).  Features are centred with the training column means
+// (distances unchanged), and each entry is split into one, two or three
+// BF16 terms (the Gram kind's planes); n is the squared norm of the split
+// representation.  Columns past m + 1 and rows past n are zero.
+__global__ void k_stage_aug(const float* __restrict__ X, const double* __restrict__ mean, int64_t n, int64_t m,
+                            int64_t NPAD, int mp, int np, int side, float c, uint16_t* __restrict__ out,
+                            int64_t plane) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= NPAD) return;
+    uint16_t* o0 = out + i * mp;
+    uint16_t* o1 = o0 + plane;
+    uint16_t* o2 = o1 + plane;
+    auto put = [&](int k, float v) {
+        uint16_t h, l, l2;
+        split3(v, h, l, l2);
+        o0[k] = h;
+        if (np >= 2) o1[k] = l;
+        if (np >= 3) o2[k] = l2;
+    };
+    float nrm = 0.0f;
+    for (int k = 0; k < mp; ++k) {
+        const bool in = (i < n) && (k < m);
+        const float xc = in ? (float)((double)X[i * m + k] - mean[k]) : 0.0f;
+        if (k < m) {
+            uint16_t h, l, l2;
+            split3(xc, h, l, l2);
+            const float v = bf2f(h) + (np >= 2 ? bf2f(l) : 0.0f) + (np >= 3 ? bf2f(l2) : 0.0f);
+            nrm = fmaf(v, v, nrm);
+        }
+        if (k < m || k >= m + 2) put(k, side == 0 ? xc : c * xc);
+    }
+    if (i >= n) nrm = 0.0f;
+    const bool live = i < n;
+    if (side == 0) {
+        put((int)m, nrm);
+        put((int)m + 1, live ? 1.0f : 0.0f);
+    } else {
+        put((int)m, live ? -0.5f * c : 0.0f);
+        put((int)m + 1, -0.5f * c * nrm);
+    }
+}
+
+// Workgroup (x, y): queries [256 x, 256 x + 256), training blocks of 32 rows
+// [bpc y, bpc (y + 1)), with augmented rows (above).  Wave v owns queries
+// 256 x + 64 v .. + 63 as two 32-row A fragments held in registers, so each
+// B fragment read from LDS feeds two MFMA chains.  A block's B fragments
+// (all split planes) are staged in LDS in fragment order: chunk
+// (plane, step, lane) holds the 16 bytes lane `lane` feeds the MFMA at
+// k-step `step` (training row lane % 32, columns 16 step + 8 (lane / 32)),
+// and thread t loads chunks t, t + 256, ... so the LDS stores are
+// contiguous; the next block's chunks are loaded into registers while the
+// current block is multiplied, then stored into the other LDS buffer (one
+// barrier per block).  MFMA output
+// register r of lane l is query row 8 (r / 4) + 4 (l / 32) + r % 4 of its
+// fragment and training row l % 32; each lane sums its training points'
+// terms in FP32 (at most 32 per query and chunk), then the 32 training lanes
+// are added in FP64 in a fixed order.  K = exp2 of the MFMA output, clamped
+// to [0, 1] by the instruction's clamp modifier.
+template <int KIND, int MP, int FR>
+__global__ __launch_bounds__(WG) void k_predict_aug(const uint16_t* __restrict__ Bt, int64_t bplane,
+                                                    const uint16_t* __restrict__ Aq, int64_t aplane,
+                                                    const double* __restrict__ w, int64_t nblk32, int bpc,
+                                                    int64_t NQPAD, double* __restrict__ part) {
+    constexpr int NP = (KIND == GRAM_BF16X6) ? 3 : (KIND == GRAM_BF16X3) ? 2 : 1;
+    constexpr int NS = MP / 16;
+    constexpr int CH = NP * NS * 64;
+    constexpr int PR = (CH + WG - 1) / WG;
+    constexpr int QW = 32 * FR;                 // queries per wave
+    __shared__ bf16x8 sb[2][CH];
+    __shared__ float swj[2][32];
+    const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63, h = l >> 5, l32 = l & 31;
+    const int64_t q0 = (int64_t)blockIdx.x * (4 * QW) + wv * QW;
+    bf16x8 a[FR][NP][NS];
+#pragma unroll
+    for (int f = 0; f < FR; ++f)
+#pragma unroll
+        for (int pl = 0; pl < NP; ++pl)
+#pragma unroll
+            for (int st = 0; st < NS; ++st)
+                a[f][pl][st] = *reinterpret_cast<const bf16x8*>(Aq + pl * aplane + (q0 + 32 * f + l32) * MP +
+                                                                16 * st + 8 * h);
+    // this thread's staging chunks: source offsets within a block
+    int64_t so[PR];
+#pragma unroll
+    for (int i = 0; i < PR; ++i) {
+        const int c = tid + WG * i, pl = c / (NS * 64), st = (c / 64) % NS, ll = c % 64;
+        so[i] = pl * bplane + (ll & 31) * MP + 16 * st + 8 * (ll >> 5);
+    }
+    float accf[FR][16];
+#pragma unroll
+    for (int f = 0; f < FR; ++f)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) accf[f][r] = 0.0f;
+    const int64_t b0 = (int64_t)blockIdx.y * bpc;
+    const int64_t b1 = (b0 + bpc < nblk32) ? b0 + bpc : nblk32;
+    const int nb = (int)(b1 > b0 ? b1 - b0 : 0);
+
+    auto load = [&](int k, bf16x8 (&pre)[PR], float& pw) {
+        const int64_t off = (b0 + k) * 32 * MP;
+#pragma unroll
+        for (int i = 0; i < PR; ++i)
+            if (tid + WG * i < CH) pre[i] = *reinterpret_cast<const bf16x8*>(Bt + so[i] + off);
+        if (tid < 32) pw = (float)w[(b0 + k) * 32 + tid];
+    };
+    auto store = [&](int k, const bf16x8 (&pre)[PR], float pw) {
+#pragma unroll
+        for (int i = 0; i < PR; ++i)
+            if (tid + WG * i < CH) sb[k & 1][tid + WG * i] = pre[i];
+        if (tid < 32) swj[k & 1][tid] = pw;
+    };
+    // MFMAs of block k (LDS buffer k & 1) into g, the fragments' chains
+    // interleaved (each B fragment read once for all of them)
+    auto mma = [&](int k, f32x16 (&g)[FR]) {
+#pragma unroll
+        for (int f = 0; f < FR; ++f) g[f] = f32x16{};
+        const bf16x8* sbc = sb[k & 1];
+#pragma unroll
+        for (int st = 0; st < NS; ++st) {
+            const bf16x8 bh = sbc[st * 64 + l];
+            if constexpr (NP >= 2) {
+                const bf16x8 bl = sbc[(NS + st) * 64 + l];
+                if constexpr (NP >= 3) {
+                    const bf16x8 bl2 = sbc[(2 * NS + st) * 64 + l];
+#pragma unroll
+                    for (int f = 0; f < FR; ++f)
+                        g[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[f][0][st], bl2, g[f], 0, 0, 0);
+#pragma unroll
+                    for (int f = 0; f < FR; ++f)
+                        g[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[f][2][st], bh, g[f], 0, 0, 0);
+#pragma unroll
+                    for (int f = 0; f < FR; ++f)
+                        g[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[f][1][st], bl, g[f], 0, 0, 0);
+                }
+#pragma unroll
+                for (int f = 0; f < FR; ++f)
+                    g[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[f][0][st], bl, g[f], 0, 0, 0);
+#pragma unroll
+                for (int f = 0; f < FR; ++f)
+                    g[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[f][1][st], bh, g[f], 0, 0, 0);
+            }
+#pragma unroll
+            for (int f = 0; f < FR; ++f)
+                g[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[f][0][st], bh, g[f], 0, 0, 0);
+        }
+    };
+    // exp2 and weighted sums of block k from its Gram g
+    auto terms = [&](int k, const f32x16 (&g)[FR]) {
+        const float wj = swj[k & 1][l32];
+#pragma unroll
+        for (int f = 0; f < FR; ++f)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                accf[f][r] = fmaf(__builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(g[f][r]), 0.0f, 1.0f), wj,
+                                  accf[f][r]);
+    };
+    // one block per step: block k + 1 into registers, the MFMAs of block k
+    // and its terms, block k + 1 into the other LDS buffer, one barrier
+    if (nb > 0) {
+        bf16x8 pre[PR];
+        float pw = 0.0f;
+        load(0, pre, pw);
+        store(0, pre, pw);
+        __syncthreads();
+        for (int k = 0; k < nb; ++k) {
+            const bool more = k + 1 < nb;
+            if (more) load(k + 1, pre, pw);
+            f32x16 g[FR];
+            mma(k, g);
+            terms(k, g);
+            if (more) store(k + 1, pre, pw);
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < FR; ++f)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            double v = sum16((double)accf[f][r]);
+            v = v + __shfl_xor(v, 16);
+            if (l32 == 0) part[(int64_t)blockIdx.y * NQPAD + q0 + 32 * f + 8 * (r >> 2) + 4 * h + (r & 3)] = v;
+        }
+}
+
 // f_q = sum over chunks (in order) of part[c][q] + lambda^2 sum_i w_i.
 __global__ void k_predict_reduce(const double* __restrict__ part, int nchunk, int64_t stride, int64_t nq,
                                  const double* __restrict__ wsum, double lam2, double* __restrict__ f) {
@@ -334,6 +526,57 @@ hipError_t launch_predict_mfma(const Features& Ft, const Features& Fq, const dou
         case GRAM_BF16X6: predict_kind<GRAM_BF16X6>(Ft.m_pad, grid, Ft, Fq, w, nblk32, bpc, neg_gamma_log2e, NQPAD, part, s); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+int64_t predict_query_pad_aug(int64_t nq) { return (nq + QBA - 1) / QBA * QBA; }
+
+void predict_chunks_aug(int64_t NPAD, int64_t NQPAD, int* nchunk, int* bpc) {
+    const int64_t nblk32 = NPAD / 32, nqb = NQPAD / QBA;
+    // at most 32 training blocks per workgroup (FP32 partial sums), and at
+    // least 4096 workgroups when the training set allows
+    int64_t want = (4096 + nqb - 1) / nqb;
+    want = std::max<int64_t>(want, (nblk32 + 31) / 32);
+    want = std::max<int64_t>(1, std::min<int64_t>(want, nblk32));
+    const int64_t per = (nblk32 + want - 1) / want;
+    *bpc = (int)per;
+    *nchunk = (int)((nblk32 + per - 1) / per);
+}
+
+hipError_t launch_stage_aug(const float* X, const double* mean, int64_t n, int64_t m, int64_t NPAD, int mp, int kind,
+                            int side, float c, uint16_t* out, hipStream_t s) {
+    const int np = (kind == GRAM_BF16X6) ? 3 : (kind == GRAM_BF16X3) ? 2 : 1;
+    if (m + 2 > mp || (mp != 32 && mp != 64) || (kind != GRAM_BF16 && kind != GRAM_BF16X3 && kind != GRAM_BF16X6))
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_stage_aug, dim3(blocks_of(NPAD)), dim3(WG), 0, s, X, mean, n, m, NPAD, mp, np, side, c, out,
+                       NPAD * mp);
+    return hipGetLastError();
+}
+
+hipError_t launch_predict_aug(int kind, int mp, const uint16_t* Bt, int64_t NPAD, const uint16_t* Aq, int64_t NQPAD,
+                              const double* w, int nchunk, int bpc, double* part, hipStream_t s) {
+    if (NQPAD % QBA != 0 || NPAD % 32 != 0) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(NQPAD / QBA), (unsigned)nchunk);
+    const int64_t nblk32 = NPAD / 32, bp = NPAD * mp, ap = NQPAD * mp;
+#define GABP_AUG(K, M) hipLaunchKernelGGL((k_predict_aug<K, M, AUG_FR>), grid, dim3(WG), 0, s, Bt, bp, Aq, ap, w, nblk32, bpc, NQPAD, part)
+    if (mp == 32) {
+        switch (kind) {
+            case GRAM_BF16: GABP_AUG(GRAM_BF16, 32); break;
+            case GRAM_BF16X3: GABP_AUG(GRAM_BF16X3, 32); break;
+            case GRAM_BF16X6: GABP_AUG(GRAM_BF16X6, 32); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else if (mp == 64) {
+        switch (kind) {
+            case GRAM_BF16: GABP_AUG(GRAM_BF16, 64); break;
+            case GRAM_BF16X3: GABP_AUG(GRAM_BF16X3, 64); break;
+            case GRAM_BF16X6: GABP_AUG(GRAM_BF16X6, 64); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        return hipErrorInvalidValue;
+    }
+#undef GABP_AUG
     return hipGetLastError();
 }
 

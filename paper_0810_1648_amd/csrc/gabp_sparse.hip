@@ -470,13 +470,6 @@ __global__ void k_sp_prune(const uint32_t* __restrict__ tiles, int64_t nt, int64
 // split into the Gram kind's planes as the features are (hi, then the BF16
 // remainders), so that sum_k a_ik b_jk = x_i . x_j - n_i/2 - n_j/2 for the
 // products the kind forms.  One thread per row; columns past m + 1 stay 0.
-__device__ inline void split3(float v, uint16_t& h, uint16_t& l, uint16_t& l2) {
-    h = f2bf(v);
-    const float r = v - bf2f(h);
-    l = f2bf(r);
-    l2 = f2bf(r - bf2f(l));
-}
-
 __global__ void k_sp_augment(int64_t NPAD, int64_t m, int m_pad, int kind, const float* __restrict__ nrm,
                              float* f32a, uint16_t* hia, uint16_t* loa, uint16_t* lo2a, float* f32b,
                              uint16_t* hib, uint16_t* lob, uint16_t* lo2b) {

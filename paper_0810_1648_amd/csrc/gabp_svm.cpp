@@ -103,7 +103,10 @@ struct gabp_svm {
     // device memory owned by the handle
     DevBuf tiles, Kp, Pf, Pb, Ef, Eb, partP, partE, Xin, yd, mean, xs32, xhi, xlo, xlo2, x64, nrm, kdiag, rowmax, rsum,
         Adiag, Pt, S, alpha_d, blk1, blk2, one, status_d, trace_d, flag, tmp, Kin, q_rows, q_cols,
-        q_out, glist, HI, HM;
+        q_out, glist, HI, HM,
+        xaug,                    // training rows of the augmented decision function
+        parena;                  // working memory of gabp_svm_predict (reused)
+    int aug_kind = -1, aug_mp = 0;
     // sparsified kernel: tile counts and offsets, keys, K' per edge, edge
     // ends, degrees and offsets of the i-end and j-end lists, permutation
     DevBuf sp_cnt, sp_toff, sp_keys, sp_keys2, sp_kv, sp_kv2, sp_ei, sp_ej, sp_degi, sp_degj, sp_offi,
@@ -115,12 +118,12 @@ struct gabp_svm {
     bool resid_valid = false;
     double resid[3] = {0.0, 0.0, 0.0};
 
-    DevBuf* all[62] = {&tiles, &Kp, &Pf, &Pb, &Ef, &Eb, &partP, &partE, &Xin, &yd, &mean,
+    DevBuf* all[64] = {&tiles, &Kp, &Pf, &Pb, &Ef, &Eb, &partP, &partE, &Xin, &yd, &mean,
                        &xs32, &xhi, &xlo, &xlo2, &x64, &nrm, &kdiag, &rowmax, &rsum, &Adiag, &Pt, &S, &alpha_d,
                        &blk1, &blk2, &one, &status_d, &trace_d, &flag, &tmp, &Kin, &q_rows,
                        &q_cols, &q_out, &glist, &sp_cnt, &sp_toff, &sp_keys, &sp_keys2, &sp_kv, &sp_kv2,
                        &sp_ei, &sp_ej, &sp_degi, &sp_degj, &sp_offi, &sp_offj, &sp_ids, &sp_perm, &sp_tmp,
-                       &sp_order, &sp_Xp, &sp_cent, &sp_rad, &sp_keep, &sp_tsel, &sp_nsel, &sp_xb, &HI, &HM, nullptr};
+                       &sp_order, &sp_Xp, &sp_cent, &sp_rad, &sp_keep, &sp_tsel, &sp_nsel, &sp_xb, &HI, &HM, &xaug, &parena, nullptr};
     size_t held() const {
         size_t b = 0;
         for (int k = 0; all[k]; ++k) b += all[k]->bytes;
@@ -217,6 +220,7 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
             default: feat = (size_t)NPAD * m_pad * 8; break;
         }
         feat += (size_t)N * m * 4 + (size_t)NPAD * 4 + (size_t)m * 8;
+        if (gram != GRAM_F64 && m + 2 <= 64) feat += (size_t)NPAD * 64 * 6;   // augmented rows (predict)
     } else if (mem == GABP_MEM_HOST) {
         feat = (size_t)N * N * 8;
     }
@@ -354,6 +358,25 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
         F.lo2 = h->xlo2.as<uint16_t>();
         F.f64 = h->x64.as<double>();
         F.nrm = h->nrm.as<float>();
+        // augmented training rows of the decision function: the solve's BF16
+        // split kind (three-term split for FP32 handles), up to 62 features
+        h->aug_kind = -1;
+        h->aug_mp = 0;
+        if (gram != GRAM_F64 && m + 2 <= 64) {
+            const int ak = (gram == GRAM_F32) ? GRAM_BF16X6 : gram;
+            const int amp = (m + 2 <= 32) ? 32 : 64;
+            const int anp = (ak == GRAM_BF16X6) ? 3 : (ak == GRAM_BF16X3) ? 2 : 1;
+            if (h->xaug.ensure((size_t)NPAD * amp * 2 * anp) == hipSuccess) {
+                HIPCHK(h, launch_stage_aug(Xd, h->mean.as<double>(), N, m, NPAD, amp, ak, 1,
+                                           (float)(2.0 * p.gamma * 1.4426950408889634), h->xaug.as<uint16_t>(), s));
+                h->aug_kind = ak;
+                h->aug_mp = amp;
+            } else {
+                (void)hipGetLastError();
+            }
+        } else {
+            h->xaug.release();
+        }
     }
     HIPCHK(h, hipEventRecord(ev[1], s));
 
@@ -1262,6 +1285,117 @@ gabp_status gabp_svm_kernel_entries(const gabp_svm* hc, const int64_t* rows, con
     return GABP_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Working memory of one decision-function call for `nb` queries, as
+// 256-byte aligned segments of one arena: the weights w_i = alpha_i y_i and
+// their block sums first (the same offsets for every batch size), then the
+// per-chunk partial sums and the staged queries of the form the handle
+// uses (FP64 direct differences; augmented BF16 rows; FP32 or BF16 rows
+// with norms).
+struct PredictPlan {
+    int form = 0;                 // 0 direct FP64, 1 augmented rows, 2 rows + norms
+    int kind = 0, mp = 0, np = 0, nc = 1, bp = 1;
+    int64_t qpad = 0;
+    size_t o_w = 0, o_blk = 0, o_ws = 0, o_part = 0, o_nrm = 0, o_q0 = 0, o_q1 = 0, o_q2 = 0, bytes = 0;
+};
+
+PredictPlan predict_plan(const gabp_svm* h, int64_t nb) {
+    PredictPlan P;
+    size_t off = 0;
+    auto seg = [&](size_t b) { const size_t o = off; off += (b + 255) / 256 * 256; return o; };
+    const int64_t NPAD = h->NPAD;
+    P.o_w = seg((size_t)NPAD * 8);
+    P.o_blk = seg((size_t)(NPAD / WG + 1) * 8);
+    P.o_ws = seg(64);
+    if (h->prec == PREC_FP64) {
+        P.form = 0;
+        P.qpad = nb;
+        P.o_part = seg((size_t)nb * 8);
+    } else if (h->aug_kind >= 0) {
+        P.form = 1;
+        P.kind = h->aug_kind;
+        P.mp = h->aug_mp;
+        P.np = (P.kind == GRAM_BF16X6) ? 3 : (P.kind == GRAM_BF16X3) ? 2 : 1;
+        P.qpad = predict_query_pad_aug(nb);
+        predict_chunks_aug(NPAD, P.qpad, &P.nc, &P.bp);
+        P.o_part = seg((size_t)P.nc * P.qpad * 8);
+        P.o_q0 = seg((size_t)P.qpad * P.mp * 2 * P.np);
+    } else {
+        P.form = 2;
+        P.kind = h->gram;
+        P.mp = h->m_pad;
+        P.qpad = predict_query_pad(nb);
+        predict_chunks(NPAD, P.qpad, &P.nc, &P.bp);
+        P.o_part = seg((size_t)P.nc * P.qpad * 8);
+        P.o_nrm = seg((size_t)P.qpad * 4);
+        const size_t fe = (size_t)P.qpad * P.mp;
+        if (P.kind == GRAM_F32) P.o_q0 = seg(fe * 4);
+        else P.o_q0 = seg(fe * 2);
+        if (P.kind == GRAM_BF16X3 || P.kind == GRAM_BF16X6) P.o_q1 = seg(fe * 2);
+        if (P.kind == GRAM_BF16X6) P.o_q2 = seg(fe * 2);
+    }
+    P.bytes = off;
+    return P;
+}
+
+gabp_status predict_weights(gabp_svm* h, char* base, const PredictPlan& P, hipStream_t s) {
+    HIPCHK(h, launch_predict_weights(h->alpha_d.as<double>(), h->yd.as<float>(), h->N, h->NPAD,
+                                     h->p.box_mode == GABP_BOX_CLIP_OUTPUT, h->p.C,
+                                     reinterpret_cast<double*>(base + P.o_w), reinterpret_cast<double*>(base + P.o_blk),
+                                     reinterpret_cast<double*>(base + P.o_ws), s));
+    return GABP_OK;
+}
+
+// One batch of nb device-resident queries into fd (device); e0 / e1 (if
+// set) bracket the decision kernel.
+gabp_status predict_batch(gabp_svm* h, const PredictPlan& P, char* base, const float* xqd, int64_t nb, double* fd,
+                          hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    const double* w = reinterpret_cast<const double*>(base + P.o_w);
+    const double* wsum = reinterpret_cast<const double*>(base + P.o_ws);
+    double* part = reinterpret_cast<double*>(base + P.o_part);
+    const double lam2 = h->lam * h->lam;
+    if (P.form == 0) {
+        if (e0) HIPCHK(h, hipEventRecord(e0, s));
+        HIPCHK(h, launch_predict_direct(h->Xin.as<float>(), w, h->N, h->m, xqd, nb, h->p.gamma, part, s));
+        if (e1) HIPCHK(h, hipEventRecord(e1, s));
+        HIPCHK(h, launch_predict_reduce(part, 1, nb, nb, wsum, lam2, fd, s));
+        return GABP_OK;
+    }
+    if (P.form == 1) {
+        uint16_t* q = reinterpret_cast<uint16_t*>(base + P.o_q0);
+        HIPCHK(h, launch_stage_aug(xqd, h->mean.as<double>(), nb, h->m, P.qpad, P.mp, P.kind, 0, 0.0f, q, s));
+        if (e0) HIPCHK(h, hipEventRecord(e0, s));   // after the query staging
+        HIPCHK(h, launch_predict_aug(P.kind, P.mp, h->xaug.as<uint16_t>(), h->NPAD, q, P.qpad, w, P.nc, P.bp, part, s));
+        if (e1) HIPCHK(h, hipEventRecord(e1, s));
+        HIPCHK(h, launch_predict_reduce(part, P.nc, P.qpad, nb, wsum, lam2, fd, s));
+        return GABP_OK;
+    }
+    Features Ft{}, Fq{};
+    Ft.f32 = h->xs32.as<float>(); Ft.hi = h->xhi.as<uint16_t>(); Ft.lo = h->xlo.as<uint16_t>();
+    Ft.lo2 = h->xlo2.as<uint16_t>(); Ft.nrm = h->nrm.as<float>(); Ft.m_pad = P.mp; Ft.kind = P.kind;
+    float* qnrm = reinterpret_cast<float*>(base + P.o_nrm);
+    float* qf32 = P.kind == GRAM_F32 ? reinterpret_cast<float*>(base + P.o_q0) : nullptr;
+    uint16_t* qhi = P.kind != GRAM_F32 ? reinterpret_cast<uint16_t*>(base + P.o_q0) : nullptr;
+    uint16_t* qlo = P.o_q1 ? reinterpret_cast<uint16_t*>(base + P.o_q1) : nullptr;
+    uint16_t* qlo2 = P.o_q2 ? reinterpret_cast<uint16_t*>(base + P.o_q2) : nullptr;
+    Fq.f32 = qf32; Fq.hi = qhi; Fq.lo = qlo; Fq.lo2 = qlo2; Fq.nrm = qnrm; Fq.m_pad = P.mp; Fq.kind = P.kind;
+    const float c = (float)(-h->p.gamma * 1.4426950408889634);
+    HIPCHK(h, launch_stage(xqd, h->mean.as<double>(), nb, h->m, P.qpad, P.mp, P.kind, qf32, qhi, qlo, qlo2, nullptr,
+                           qnrm, s));
+    if (e0) HIPCHK(h, hipEventRecord(e0, s));
+    HIPCHK(h, launch_predict_mfma(Ft, Fq, w, h->NPAD, P.qpad, c, P.nc, P.bp, part, s));
+    if (e1) HIPCHK(h, hipEventRecord(e1, s));
+    HIPCHK(h, launch_predict_reduce(part, P.nc, P.qpad, nb, wsum, lam2, fd, s));
+    return GABP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 gabp_status gabp_svm_predict(gabp_svm* h, const float* Xq, int64_t nq, double* f_out, int32_t mem,
                              void* stream) {
     if (!h || !Xq || !f_out || nq < 0) return GABP_E_INVALID;
@@ -1270,58 +1404,28 @@ gabp_status gabp_svm_predict(gabp_svm* h, const float* Xq, int64_t nq, double* f
     if (nq == 0) return GABP_OK;
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(h, hipSetDevice(h->p.device));
-    const int64_t m = h->m, N = h->N, NPAD = h->NPAD;
+    const int64_t m = h->m;
     if (mem == GABP_MEM_HOST) {
         for (int64_t k = 0; k < nq * m; ++k)
             if (!std::isfinite(Xq[k])) return fail(h, GABP_E_INVALID, "Xq has a non-finite entry");
     }
-    // queries are processed in batches of at most QMAX rows
+    // queries are processed in batches of at most QMAX rows; the arena holds
+    // the largest batch's plan (the weights sit at the same offsets in all)
     const int64_t QMAX = int64_t(1) << 18;
     const int64_t qb = std::min(nq, QMAX);
-    const int64_t QPAD = predict_query_pad(qb);
-    const bool f64 = h->prec == PREC_FP64;
-    const int gram = h->gram, mp = h->m_pad;
-    // partial-sum rows: the largest over the full batches and the last one
-    size_t part_elems = (size_t)qb;
-    if (!f64) {
-        int nc = 1, bp = 1;
-        predict_chunks(NPAD, QPAD, &nc, &bp);
-        part_elems = (size_t)nc * QPAD;
-        const int64_t last = nq % QMAX;
-        if (last) {
-            const int64_t lpad = predict_query_pad(last);
-            predict_chunks(NPAD, lpad, &nc, &bp);
-            part_elems = std::max(part_elems, (size_t)nc * lpad);
-        }
-    }
-    const size_t fe = (size_t)QPAD * mp;
-    DevBuf xq, fo, w, blk, wsum, part, qf32, qhi, qlo, qlo2, qnrm;
-    bool ok = w.ensure((size_t)NPAD * 8) == hipSuccess && blk.ensure((size_t)(NPAD / WG + 1) * 8) == hipSuccess &&
-              wsum.ensure(64) == hipSuccess &&
-              part.ensure(part_elems * 8) == hipSuccess;
+    size_t need = predict_plan(h, qb).bytes;
+    if (nq % QMAX && nq > QMAX) need = std::max(need, predict_plan(h, nq % QMAX).bytes);
+    DevBuf xq, fo;
+    bool ok = h->parena.ensure(need) == hipSuccess;
     if (ok && mem == GABP_MEM_HOST) ok = xq.ensure((size_t)qb * m * 4) == hipSuccess && fo.ensure((size_t)qb * 8) == hipSuccess;
-    if (ok && !f64) {
-        ok = qnrm.ensure((size_t)QPAD * 4) == hipSuccess;
-        if (ok && gram == GRAM_F32) ok = qf32.ensure(fe * 4) == hipSuccess;
-        if (ok && gram != GRAM_F32) ok = qhi.ensure(fe * 2) == hipSuccess;
-        if (ok && (gram == GRAM_BF16X3 || gram == GRAM_BF16X6)) ok = qlo.ensure(fe * 2) == hipSuccess;
-        if (ok && gram == GRAM_BF16X6) ok = qlo2.ensure(fe * 2) == hipSuccess;
-    }
     if (!ok) return fail(h, GABP_E_NOMEM, "device allocation for predict failed");
-    Features Ft{}, Fq{};
-    Ft.f32 = h->xs32.as<float>(); Ft.hi = h->xhi.as<uint16_t>(); Ft.lo = h->xlo.as<uint16_t>();
-    Ft.lo2 = h->xlo2.as<uint16_t>(); Ft.nrm = h->nrm.as<float>(); Ft.m_pad = mp; Ft.kind = gram;
-    Fq.f32 = qf32.as<float>(); Fq.hi = qhi.as<uint16_t>(); Fq.lo = qlo.as<uint16_t>();
-    Fq.lo2 = qlo2.as<uint16_t>(); Fq.nrm = qnrm.as<float>(); Fq.m_pad = mp; Fq.kind = gram;
-    const double lam2 = h->lam * h->lam;
-    const float c = (float)(-h->p.gamma * 1.4426950408889634);
+    char* base = static_cast<char*>(h->parena.p);
     const bool timed = h->p.time_sweeps != 0;
     const int64_t nbatch = (nq + QMAX - 1) / QMAX;
     EventPool pev;
     if (timed) HIPCHK(h, pev.make((size_t)(2 * nbatch)));
-    HIPCHK(h, launch_predict_weights(h->alpha_d.as<double>(), h->yd.as<float>(), N, NPAD,
-                                     h->p.box_mode == GABP_BOX_CLIP_OUTPUT, h->p.C, w.as<double>(),
-                                     blk.as<double>(), wsum.as<double>(), s));
+    const PredictPlan P0 = predict_plan(h, qb);
+    if (predict_weights(h, base, P0, s) != GABP_OK) return GABP_E_DEVICE;
     for (int64_t q0 = 0; q0 < nq; q0 += QMAX) {
         const int64_t nb = std::min(QMAX, nq - q0);
         const float* xqd = Xq + q0 * m;
@@ -1331,24 +1435,9 @@ gabp_status gabp_svm_predict(gabp_svm* h, const float* Xq, int64_t nq, double* f
         }
         double* fd = (mem == GABP_MEM_HOST) ? fo.as<double>() : f_out + q0;
         const int64_t bi = q0 / QMAX;
-        if (f64) {
-            if (timed) HIPCHK(h, hipEventRecord(pev.ev[2 * bi], s));
-            HIPCHK(h, launch_predict_direct(h->Xin.as<float>(), w.as<double>(), N, m, xqd, nb, h->p.gamma,
-                                            part.as<double>(), s));
-            if (timed) HIPCHK(h, hipEventRecord(pev.ev[2 * bi + 1], s));
-            HIPCHK(h, launch_predict_reduce(part.as<double>(), 1, nb, nb, wsum.as<double>(), lam2, fd, s));
-        } else {
-            const int64_t qpad = predict_query_pad(nb);
-            int nc = 1, bp = 1;
-            predict_chunks(NPAD, qpad, &nc, &bp);
-            HIPCHK(h, launch_stage(xqd, h->mean.as<double>(), nb, m, qpad, mp, gram, qf32.as<float>(),
-                                   qhi.as<uint16_t>(), qlo.as<uint16_t>(), qlo2.as<uint16_t>(), nullptr,
-                                   qnrm.as<float>(), s));
-            if (timed) HIPCHK(h, hipEventRecord(pev.ev[2 * bi], s));   // after the query staging
-            HIPCHK(h, launch_predict_mfma(Ft, Fq, w.as<double>(), NPAD, qpad, c, nc, bp, part.as<double>(), s));
-            if (timed) HIPCHK(h, hipEventRecord(pev.ev[2 * bi + 1], s));
-            HIPCHK(h, launch_predict_reduce(part.as<double>(), nc, qpad, nb, wsum.as<double>(), lam2, fd, s));
-        }
+        const gabp_status st = predict_batch(h, predict_plan(h, nb), base, xqd, nb, fd, s,
+                                             timed ? pev.ev[2 * bi] : nullptr, timed ? pev.ev[2 * bi + 1] : nullptr);
+        if (st != GABP_OK) return st;
         if (mem == GABP_MEM_HOST)
             HIPCHK(h, hipMemcpyAsync(f_out + q0, fo.p, (size_t)nb * 8, hipMemcpyDeviceToHost, s));
     }
@@ -1374,61 +1463,19 @@ gabp_status gabp_svm_predict_noalloc(gabp_svm* h, const float* Xq, int64_t nq, d
     HIPCHK(h, hipSetDevice(h->p.device));
     void* base = nullptr;
     HIPCHK(h, predict_scratch(&base));
-    const int64_t m = h->m, N = h->N, NPAD = h->NPAD;
-    const bool f64 = h->prec == PREC_FP64;
-    const int gram = h->gram, mp = h->m_pad;
-    const int64_t qpad = predict_query_pad(nq);
-    int nc = 1, bp = 1;
-    if (!f64) predict_chunks(NPAD, qpad, &nc, &bp);
-    // layout of one call in the scratch array, 256-byte aligned segments
-    // (every byte read is written earlier in the same call on `stream`, so
-    // nothing needs clearing between calls)
-    size_t off = 0;
-    auto seg = [&](size_t bytes) { const size_t o = off; off += (bytes + 255) / 256 * 256; return o; };
-    const size_t fe = (size_t)qpad * mp;
-    const size_t o_w = seg((size_t)NPAD * 8), o_blk = seg((size_t)(NPAD / WG + 1) * 8), o_ws = seg(64);
-    const size_t o_part = seg(f64 ? (size_t)nq * 8 : (size_t)nc * qpad * 8);
-    size_t o_nrm = 0, o_f32 = 0, o_hi = 0, o_lo = 0, o_lo2 = 0;
-    if (!f64) {
-        o_nrm = seg((size_t)qpad * 4);
-        if (gram == GRAM_F32) o_f32 = seg(fe * 4);
-        else o_hi = seg(fe * 2);
-        if (gram == GRAM_BF16X3 || gram == GRAM_BF16X6) o_lo = seg(fe * 2);
-        if (gram == GRAM_BF16X6) o_lo2 = seg(fe * 2);
-    }
-    if (off > PREDICT_SCRATCH_BYTES) {
+    // the whole call in one batch in the scratch array (every byte read is
+    // written earlier in the same call on `stream`: nothing to clear)
+    const PredictPlan P = predict_plan(h, nq);
+    if (P.bytes > PREDICT_SCRATCH_BYTES) {
         char msg[200];
         snprintf(msg, sizeof msg, "%lld queries need %.1f MiB of scratch; the allocation-free predict holds %.0f MiB",
-                 (long long)nq, off / 1048576.0, PREDICT_SCRATCH_BYTES / 1048576.0);
+                 (long long)nq, P.bytes / 1048576.0, PREDICT_SCRATCH_BYTES / 1048576.0);
         return fail(h, GABP_E_NOMEM, msg);
     }
     char* b = static_cast<char*>(base);
-    double* w = reinterpret_cast<double*>(b + o_w);
-    double* blk = reinterpret_cast<double*>(b + o_blk);
-    double* wsum = reinterpret_cast<double*>(b + o_ws);
-    double* part = reinterpret_cast<double*>(b + o_part);
-    HIPCHK(h, launch_predict_weights(h->alpha_d.as<double>(), h->yd.as<float>(), N, NPAD,
-                                     h->p.box_mode == GABP_BOX_CLIP_OUTPUT, h->p.C, w, blk, wsum, s));
-    const double lam2 = h->lam * h->lam;
-    if (f64) {
-        HIPCHK(h, launch_predict_direct(h->Xin.as<float>(), w, N, m, Xq, nq, h->p.gamma, part, s));
-        HIPCHK(h, launch_predict_reduce(part, 1, nq, nq, wsum, lam2, f_out, s));
-        return GABP_OK;
-    }
-    Features Ft{}, Fq{};
-    Ft.f32 = h->xs32.as<float>(); Ft.hi = h->xhi.as<uint16_t>(); Ft.lo = h->xlo.as<uint16_t>();
-    Ft.lo2 = h->xlo2.as<uint16_t>(); Ft.nrm = h->nrm.as<float>(); Ft.m_pad = mp; Ft.kind = gram;
-    float* qnrm = reinterpret_cast<float*>(b + o_nrm);
-    float* qf32 = gram == GRAM_F32 ? reinterpret_cast<float*>(b + o_f32) : nullptr;
-    uint16_t* qhi = gram != GRAM_F32 ? reinterpret_cast<uint16_t*>(b + o_hi) : nullptr;
-    uint16_t* qlo = o_lo ? reinterpret_cast<uint16_t*>(b + o_lo) : nullptr;
-    uint16_t* qlo2 = o_lo2 ? reinterpret_cast<uint16_t*>(b + o_lo2) : nullptr;
-    Fq.f32 = qf32; Fq.hi = qhi; Fq.lo = qlo; Fq.lo2 = qlo2; Fq.nrm = qnrm; Fq.m_pad = mp; Fq.kind = gram;
-    const float c = (float)(-h->p.gamma * 1.4426950408889634);
-    HIPCHK(h, launch_stage(Xq, h->mean.as<double>(), nq, m, qpad, mp, gram, qf32, qhi, qlo, qlo2, nullptr, qnrm, s));
-    HIPCHK(h, launch_predict_mfma(Ft, Fq, w, NPAD, qpad, c, nc, bp, part, s));
-    HIPCHK(h, launch_predict_reduce(part, nc, qpad, nq, wsum, lam2, f_out, s));
-    return GABP_OK;
+    const gabp_status st = predict_weights(h, b, P, s);
+    if (st != GABP_OK) return st;
+    return predict_batch(h, P, b, Xq, nq, f_out, s, nullptr, nullptr);
 }
 
 void gabp_svm_destroy(gabp_svm* h) {
