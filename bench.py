@@ -437,6 +437,11 @@ def hbm_roof(plan, avg_ms, klaunch, kernel, traffic):
             "alg_bytes_per_pair": plan["alg_bytes_per_pair"], "alg_bytes_per_launch": plan["alg_bytes_per_sweep"]}
 
 
+def kernel_base_name(name):
+    """A profiler's kernel name without the return type it may print first."""
+    return name[5:] if name.startswith("void ") else name
+
+
 def ingest_counters(fetch_dir, write_dir, calib_bytes, out_path):
     """Per-kernel HBM bytes per working launch from two rocprofv3 --pmc runs
     of this benchmark (FETCH_SIZE, then WRITE_SIZE; CSV output), each scaled
@@ -464,7 +469,8 @@ def ingest_counters(fetch_dir, write_dir, calib_bytes, out_path):
     ff, wf = calib_bytes / (cf * 1024.0), calib_bytes / (cw * 1024.0)
     entries = {}
     for k in fetch:
-        if k not in write or "copyBuffer" in k:
+        # this library's kernels only (library sorts and torch fills aside)
+        if k not in write or not kernel_base_name(k).startswith("gabp::"):
             continue
         fv = [v for v in fetch[k] if v >= 0.05 * max(fetch[k])]
         wv = [v for v in write[k] if v >= 0.05 * max(write[k])] or write[k]
@@ -489,7 +495,7 @@ def counter_traffic_kernel(path, name_prefix):
         if device_source_hash() != tj["kernel_source_sha256"]:
             return None
         for k, e in tj["entries"].items():
-            if k.startswith(name_prefix):
+            if kernel_base_name(k).startswith(name_prefix):
                 return e["traffic_bytes"] / 1e9
     except Exception:
         return None

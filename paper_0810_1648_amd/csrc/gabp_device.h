@@ -5,6 +5,8 @@
 
 #include "gabp_internal.h"
 
+#include <hip/hip_ext.h>
+
 #include <math.h>
 
 #include <algorithm>
@@ -1230,33 +1232,45 @@ inline hipError_t served_sweep(int levels, int ser, bool grouped, const ReqDesc*
     return e != hipSuccess ? e : hipGetLastError();
 }
 
+// Launches `kern` on `s`. With an event pair the events take the dispatch's
+// own begin and end timestamps (no marker packets around the kernel, so the
+// span is the kernel's duration alone); without, a plain launch.
+template <class K, class... Args>
+inline void launch_ev(K kern, dim3 g, dim3 b, hipStream_t s, hipEvent_t e0, hipEvent_t e1, Args... args) {
+    if (e0)
+        hipExtLaunchKernelGGL(kern, g, b, 0, s, e0, e1, 0, args...);
+    else
+        hipLaunchKernelGGL(kern, g, b, 0, s, args...);
+}
+
 // ---- sweep dispatch: precision x K' source x Gram kind x depth x first x series
 template <class ST, class MT, class AT, int KSRC, int GK, int D, int SER>
-inline void sweep_d(bool first, const SweepArgs& a, hipStream_t s) {
+inline void sweep_d(bool first, const SweepArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const dim3 g((unsigned)a.ntiles), blk(WG);
     if constexpr (D == 0) {
         if (first) {
-            hipLaunchKernelGGL((k_sweep<ST, MT, AT, KSRC, GK, D, true, 0>), g, blk, 0, s, a);
+            launch_ev(k_sweep<ST, MT, AT, KSRC, GK, D, true, 0>, g, blk, s, e0, e1, a);
             return;
         }
     }
     if constexpr (KSRC == KSRC_RECOMPUTE && D >= 1)
-        hipLaunchKernelGGL((k_sweep_rc<ST, MT, AT, GK, D, SER>), g, blk, 0, s, a);
+        launch_ev(k_sweep_rc<ST, MT, AT, GK, D, SER>, g, blk, s, e0, e1, a);
     else
-        hipLaunchKernelGGL((k_sweep<ST, MT, AT, KSRC, GK, D, false, SER>), g, blk, 0, s, a);
+        launch_ev(k_sweep<ST, MT, AT, KSRC, GK, D, false, SER>, g, blk, s, e0, e1, a);
 }
 
 // `levels` = 0: stored edge state; >= 1: stateless with exactly that many
 // levels; `ser`: 0 exact reciprocals, 1 / 2 series with a one- / two-term
-// top level.
+// top level. e0 / e1 (optional): timestamps of the launch.
 template <class ST, class MT, class AT, int KSRC, int GK>
-inline hipError_t sweep_depth(int levels, bool first, int ser, const SweepArgs& a, hipStream_t s) {
+inline hipError_t sweep_depth(int levels, bool first, int ser, const SweepArgs& a, hipStream_t s, hipEvent_t e0,
+                              hipEvent_t e1) {
     if (levels == 0) {
-        sweep_d<ST, MT, AT, KSRC, GK, 0, 0>(first, a, s);
+        sweep_d<ST, MT, AT, KSRC, GK, 0, 0>(first, a, s, e0, e1);
         return hipGetLastError();
     }
     const hipError_t e = with_stateless(levels, ser, [&](auto L_, auto S_) {
-        sweep_d<ST, MT, AT, KSRC, GK, decltype(L_)::value, decltype(S_)::value>(first, a, s);
+        sweep_d<ST, MT, AT, KSRC, GK, decltype(L_)::value, decltype(S_)::value>(first, a, s, e0, e1);
     });
     return e != hipSuccess ? e : hipGetLastError();
 }

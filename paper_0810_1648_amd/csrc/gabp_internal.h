@@ -197,15 +197,16 @@ hipError_t launch_served_sweep_f64(int levels, int ser, bool grouped, const ReqD
                                    hipStream_t s);
 // depth 0 = stored edge state, 1..8 = stateless with up to `depth` levels.
 // levels: 0 = stored edge state, >= 1 = stateless with that many levels in
-// this launch; ser: stateless reciprocals by the series around 1/P~.
+// this launch; ser: stateless reciprocals by the series around 1/P~;
+// e0 / e1 (optional): events that take the kernel's begin / end timestamps.
 hipError_t launch_sweep(int prec, int ksrc, int gram, int levels, bool first, int ser, const SweepArgs& a,
-                        hipStream_t s);
+                        hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_sweep_f32(int ksrc, int gram, int levels, bool first, int ser, const SweepArgs& a,
-                            hipStream_t s);
+                            hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 hipError_t launch_sweep_mixed(int ksrc, int gram, int levels, bool first, int ser, const SweepArgs& a,
-                              hipStream_t s);
+                              hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 hipError_t launch_sweep_f64(int ksrc, int gram, int levels, bool first, int ser, const SweepArgs& a,
-                            hipStream_t s);
+                            hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 // Inv / Mean (optional, with Pt / S): the new 1/P~ and S/P~ of the series
 // sweeps, formed once per node here instead of in every tile.
 hipError_t launch_finalize(int prec, int64_t N, int NB, const void* partP, const void* partE,
@@ -329,8 +330,10 @@ int64_t predict_query_pad_aug(int64_t nq);
 void predict_chunks_aug(int64_t NPAD, int64_t NQPAD, int* nchunk, int* bpc);
 hipError_t launch_stage_aug(const float* X, const double* mean, int64_t n, int64_t m, int64_t NPAD, int mp, int kind,
                             int side, float c, uint16_t* out, hipStream_t s);
+// e0 / e1 (optional): events that take the kernel's begin / end timestamps.
 hipError_t launch_predict_aug(int kind, int mp, const uint16_t* Bt, int64_t NPAD, const uint16_t* Aq, int64_t NQPAD,
-                              const double* w, int nchunk, int bpc, double* part, hipStream_t s);
+                              const double* w, int nchunk, int bpc, double* part, hipStream_t s,
+                              hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_predict_reduce(const double* part, int nchunk, int64_t stride, int64_t nq, const double* wsum,
                                  double lam2, double* f, hipStream_t s);
 hipError_t launch_convert_agg(int prec, const void* src, double* dst, int64_t n, hipStream_t s);

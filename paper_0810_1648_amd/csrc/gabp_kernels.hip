@@ -972,12 +972,12 @@ hipError_t launch_init(int prec, int64_t N, int64_t NPAD, int R, const double* A
 
 // Per-precision sweep dispatch lives in gabp_sweep_{f32,mixed,f64}.hip.
 hipError_t launch_sweep(int prec, int ksrc, int gram, int levels, bool first, int ser, const SweepArgs& a,
-                        hipStream_t s) {
+                        hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     if (levels == 0) ser = 0;
     switch (prec) {
-        case PREC_FP32: return launch_sweep_f32(ksrc, gram, levels, first, ser, a, s);
-        case PREC_MIXED: return launch_sweep_mixed(ksrc, gram, levels, first, ser, a, s);
-        case PREC_FP64: return launch_sweep_f64(ksrc, gram, levels, first, ser, a, s);
+        case PREC_FP32: return launch_sweep_f32(ksrc, gram, levels, first, ser, a, s, e0, e1);
+        case PREC_MIXED: return launch_sweep_mixed(ksrc, gram, levels, first, ser, a, s, e0, e1);
+        case PREC_FP64: return launch_sweep_f64(ksrc, gram, levels, first, ser, a, s, e0, e1);
         default: return hipErrorInvalidValue;
     }
 }

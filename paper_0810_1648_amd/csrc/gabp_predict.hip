@@ -554,11 +554,12 @@ hipError_t launch_stage_aug(const float* X, const double* mean, int64_t n, int64
 }
 
 hipError_t launch_predict_aug(int kind, int mp, const uint16_t* Bt, int64_t NPAD, const uint16_t* Aq, int64_t NQPAD,
-                              const double* w, int nchunk, int bpc, double* part, hipStream_t s) {
+                              const double* w, int nchunk, int bpc, double* part, hipStream_t s, hipEvent_t e0,
+                              hipEvent_t e1) {
     if (NQPAD % QBA != 0 || NPAD % 32 != 0) return hipErrorInvalidValue;
     const dim3 grid((unsigned)(NQPAD / QBA), (unsigned)nchunk);
     const int64_t nblk32 = NPAD / 32, bp = NPAD * mp, ap = NQPAD * mp;
-#define GABP_AUG(K, M) hipLaunchKernelGGL((k_predict_aug<K, M, AUG_FR>), grid, dim3(WG), 0, s, Bt, bp, Aq, ap, w, nblk32, bpc, NQPAD, part)
+#define GABP_AUG(K, M) launch_ev(k_predict_aug<K, M, AUG_FR>, grid, dim3(WG), s, e0, e1, Bt, bp, Aq, ap, w, nblk32, bpc, NQPAD, part)
     if (mp == 32) {
         switch (kind) {
             case GRAM_BF16: GABP_AUG(GRAM_BF16, 32); break;

@@ -572,16 +572,17 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
         char* wS = static_cast<char*>(h->S.p) + (size_t)((t + 1) % Rr) * NPAD * agg_bytes;
         char* wI = hinv ? static_cast<char*>(hinv) + (size_t)((t + 1) % Rr) * NPAD * agg_bytes : nullptr;
         char* wM = hmean ? static_cast<char*>(hmean) + (size_t)((t + 1) % Rr) * NPAD * agg_bytes : nullptr;
-        if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot], s));
         if (!grouped) {
-            HIPCHK(h, launch_sweep(prec, ksrc, gram, sa.levels, t == 0, ser, sa, s));
-            if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot + 1], s));
+            // the events take the sweep dispatch's own timestamps
+            HIPCHK(h, launch_sweep(prec, ksrc, gram, sa.levels, t == 0, ser, sa, s,
+                                   p.time_sweeps ? sev[2 * slot] : nullptr, p.time_sweeps ? sev[2 * slot + 1] : nullptr));
             HIPCHK(h, launch_finalize(prec, N, NB, h->partP.p, h->partE.p, h->Adiag.as<double>(),
                                       h->yd.as<float>(), wP, wS, h->alpha_d.as<double>(),
                                       h->blk1.as<double>(), h->blk2.as<double>(), st, s, boxC, wI, wM));
         } else {
             // one visit per group: its messages, then its aggregates (the
             // timed span covers the visits and their group finalizes)
+            if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot], s));
             const uint32_t* gl = h->glist.as<uint32_t>();
             for (int g = 0; g < G; ++g) {
                 HIPCHK(h, launch_sweep_grouped(prec, ksrc, gram, sa.levels, ser, sa, gl + g_within_off[g],
@@ -1367,9 +1368,9 @@ gabp_status predict_batch(gabp_svm* h, const PredictPlan& P, char* base, const f
     if (P.form == 1) {
         uint16_t* q = reinterpret_cast<uint16_t*>(base + P.o_q0);
         HIPCHK(h, launch_stage_aug(xqd, h->mean.as<double>(), nb, h->m, P.qpad, P.mp, P.kind, 0, 0.0f, q, s));
-        if (e0) HIPCHK(h, hipEventRecord(e0, s));   // after the query staging
-        HIPCHK(h, launch_predict_aug(P.kind, P.mp, h->xaug.as<uint16_t>(), h->NPAD, q, P.qpad, w, P.nc, P.bp, part, s));
-        if (e1) HIPCHK(h, hipEventRecord(e1, s));
+        // the events take the kernel dispatch's own timestamps
+        HIPCHK(h, launch_predict_aug(P.kind, P.mp, h->xaug.as<uint16_t>(), h->NPAD, q, P.qpad, w, P.nc, P.bp, part, s,
+                                     e0, e1));
         HIPCHK(h, launch_predict_reduce(part, P.nc, P.qpad, nb, wsum, lam2, fd, s));
         return GABP_OK;
     }

@@ -6,9 +6,9 @@
 namespace gabp {
 
 hipError_t launch_sweep_f32(int ksrc, int gram, int levels, bool first, int ser, const SweepArgs& a,
-                              hipStream_t s) {
-    if (ksrc == KSRC_PLANE) return sweep_depth<float, float, float, KSRC_PLANE, GRAM_F32>(levels, first, ser, a, s);
-    if (gram == GRAM_F32) return sweep_depth<float, float, float, KSRC_RECOMPUTE, GRAM_F32>(levels, first, ser, a, s);
+                              hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (ksrc == KSRC_PLANE) return sweep_depth<float, float, float, KSRC_PLANE, GRAM_F32>(levels, first, ser, a, s, e0, e1);
+    if (gram == GRAM_F32) return sweep_depth<float, float, float, KSRC_RECOMPUTE, GRAM_F32>(levels, first, ser, a, s, e0, e1);
     return hipErrorInvalidValue;
 }
 

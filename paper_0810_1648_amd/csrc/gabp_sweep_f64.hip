@@ -6,8 +6,8 @@
 namespace gabp {
 
 hipError_t launch_sweep_f64(int ksrc, int gram, int levels, bool first, int ser, const SweepArgs& a,
-                              hipStream_t s) {
-    if (ksrc == KSRC_PLANE) return sweep_depth<double, double, double, KSRC_PLANE, GRAM_F64>(levels, first, ser, a, s);
+                              hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (ksrc == KSRC_PLANE) return sweep_depth<double, double, double, KSRC_PLANE, GRAM_F64>(levels, first, ser, a, s, e0, e1);
     (void)gram;
     return hipErrorInvalidValue;   // FP64 K' is always materialised
 }

@@ -7,12 +7,12 @@
 namespace gabp {
 
 hipError_t launch_sweep_mixed(int ksrc, int gram, int levels, bool first, int ser, const SweepArgs& a,
-                              hipStream_t s) {
-    if (ksrc == KSRC_PLANE) return sweep_depth<float, double, double, KSRC_PLANE, GRAM_F32>(levels, first, ser, a, s);
+                              hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (ksrc == KSRC_PLANE) return sweep_depth<float, double, double, KSRC_PLANE, GRAM_F32>(levels, first, ser, a, s, e0, e1);
     switch (gram) {
-        case GRAM_BF16: return sweep_depth<float, double, double, KSRC_RECOMPUTE, GRAM_BF16>(levels, first, ser, a, s);
-        case GRAM_BF16X3: return sweep_depth<float, double, double, KSRC_RECOMPUTE, GRAM_BF16X3>(levels, first, ser, a, s);
-        case GRAM_BF16X6: return sweep_depth<float, double, double, KSRC_RECOMPUTE, GRAM_BF16X6>(levels, first, ser, a, s);
+        case GRAM_BF16: return sweep_depth<float, double, double, KSRC_RECOMPUTE, GRAM_BF16>(levels, first, ser, a, s, e0, e1);
+        case GRAM_BF16X3: return sweep_depth<float, double, double, KSRC_RECOMPUTE, GRAM_BF16X3>(levels, first, ser, a, s, e0, e1);
+        case GRAM_BF16X6: return sweep_depth<float, double, double, KSRC_RECOMPUTE, GRAM_BF16X6>(levels, first, ser, a, s, e0, e1);
         default: return hipErrorInvalidValue;
     }
 }
