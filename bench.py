@@ -65,24 +65,29 @@ def stateless_slots_per_pair(levels, series, precision="mixed"):
     `levels` unrolled levels (both directions of the pair), counting a
     multiply-add as one slot (contracted, as the compiler emits it) and a
     transcendental as four.
-    Series reciprocals (`series` = number of terms at the top level; MIXED
-    computes these messages in FP32 from FP32 K', so no conversion): a^2
-    (1); the lower levels carry G = P / (-a^2) and F = E / a: the deepest
-    level is G = 1/P~, F = -S/P~ of its source (free), each middle level
-    forms, per direction, a^2 u^2 (1), G = u - a^2 u^2 G_rev (1),
-    a F_rev - S (1) and F (1): 8; the top level forms, per direction,
-    e = -a^2 G_rev u (2), the series (1 or 2), the accumulation of P (1,
-    fused), a G (1), a F_rev - S (1) and the accumulation of E (1, fused):
-    14 or 16.  With one level the top level runs from zero reverse
-    messages: 7.
+    Series reciprocals (`series`: 1 / 2 terms at the top level, 3 = one term
+    at the top and none at the lower levels; MIXED computes these messages
+    in FP32 from FP32 K', so no conversion): a^2 (1); the lower levels carry
+    G = P / (-a^2) and F = E / a: the deepest level is G = 1/P~, F = -S/P~ of
+    its source (free), each middle level forms, per direction, a^2 u^2 (1)
+    and G = u - a^2 u^2 G_rev (1) (not with series 3, where G = u),
+    a F_rev - S (1) and F (1): 8 (4); the top level forms, per direction,
+    the reciprocal u - a^2 u^2 G_rev (2: a^2 u^2, then one multiply-add;
+    two terms: e = -a^2 G_rev u (2) and the series (2)), the accumulation
+    of P (1, fused), a G (1), a F_rev - S (1) and the accumulation of E (1,
+    fused): 12 (16 with two terms).  With one level the top level runs from
+    zero reverse messages: 7.
     Exact reciprocals: per direction and level the cavity precision (1), the
     reciprocal (FP32: 4; FP64: 4 + two Newton steps of 2 FMAs = 8) and the
     messages (4; 3 at the top, where the accumulations fuse); MIXED adds the
     conversion of K' to FP64 (1)."""
+    series = int(series)
     if series:
         if levels <= 1:
             return 7
-        return 1 + 8 * (levels - 2) + 2 * (6 + int(series))
+        middle = 4 if series == 3 else 8
+        top = 16 if series == 2 else 12
+        return 1 + middle * (levels - 2) + top
     cvt = 1 if precision == "mixed" else 0
     r_top = 4 if precision == "fp32" else 8
     r_low = 8 if precision == "fp64" else 4

@@ -226,7 +226,10 @@ typedef struct gabp_plan {
     int32_t series_reciprocal; /* stateless reciprocals of the cavity
                                   precisions: 0 exact; 1 / 2 by the series
                                   around 1/P~ with a one- / two-term top
-                                  level (one term at the lower levels) */
+                                  level (one term at the lower levels);
+                                  3 one-term top level, 1/P~ alone at the
+                                  lower levels (depth >= 3, rho^3 below
+                                  the message precision) */
     int32_t sched_groups;      /* groups of the GROUPED schedule; 0 = SYNC */
     int64_t n_edges;           /* RBF_SPARSE: kept pairs (graph edges); else 0 */
     int32_t stateless_bounded; /* 1: stored records, or a stateless depth at

@@ -62,6 +62,34 @@ __device__ inline void st4nt(double* p, const V4<double>& v) {
     __builtin_nontemporal_store(b, reinterpret_cast<f64x2v*>(p + 2));
 }
 
+// K' row steps in flight per lane in the stateless sweep over an FP32 K'
+// plane: each wave streams its row steps into an LDS ring by direct
+// global-to-LDS loads, so the bytes in flight do not occupy registers.
+#ifndef GABP_KRING
+#define GABP_KRING 4
+#endif
+constexpr int KRING = GABP_KRING;
+
+// LDS byte offset of a shared-memory pointer (wave-uniform here).
+__device__ inline uint32_t lds_offset(const void* p) {
+    return (uint32_t)reinterpret_cast<uintptr_t>((const __attribute__((address_space(3))) void*)p);
+}
+
+// One direct global-to-LDS load of 16 bytes per lane: lane l's bytes at
+// base + voff land at LDS offset lds + 16 l, with the non-temporal hint.  The
+// compiler's wait counting does not see this load: callers wait for it with
+// wait_vm before reading the LDS it writes, and issue it only after their
+// last read of that LDS has completed.
+__device__ inline void dma16(const float* base, uint32_t voff, uint32_t lds) {
+    lds = __builtin_amdgcn_readfirstlane(lds);
+    asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, %1 nt"
+                 :: "v"(voff), "s"(base), "s"(lds) : "memory", "m0");
+}
+// Waits until at most N vector-memory operations of this wave are in flight.
+template <int N> __device__ inline void wait_vm() {
+    asm volatile("s_waitcnt vmcnt(%0)" :: "n"(N) : "memory");
+}
+
 // Address of a lane's element from a wave-uniform base (scalar registers)
 // and a 32-bit lane offset: loads and stores then take the scalar-base form
 // and the per-step address arithmetic stays off the vector ALU.
@@ -503,13 +531,15 @@ struct MsgT {
 // reciprocals of the cavity precisions Q = P~ (1 - e), e = P_reverse / P~,
 // are formed from the per-node u = 1/P~ by the series
 // 1/Q = (1 + e + e^2 + ...) u, one term at the lower levels and SER terms at
-// the top.  |e| <= rho^2 holds for every message by the a-priori contraction
-// bound (no run-time check is needed); the host picks the series only when
-// the neglected terms are below the arithmetic's precision.  The lower
-// levels carry G = P / (-a^2) and F = E / a, which the one-term series turns
-// into G_ij = u_i - a^2 u_i^2 G_ji and F_ij = G_ij (a F_ji - S_i): the
-// deepest level (reverse messages zero) is G = u, F = -S/P~ of its source
-// and costs nothing, a middle level costs four operations per direction.
+// the top (SER = 3: one term at the top, none at the lower levels).
+// |e| <= rho^2 holds for every message by the a-priori contraction bound (no
+// run-time check is needed); the host picks the series only when the
+// neglected terms are below the arithmetic's precision.  The lower levels
+// carry G = P / (-a^2) and F = E / a, which the one-term series turns into
+// G_ij = u_i - a^2 u_i^2 G_ji and F_ij = G_ij (a F_ji - S_i): the deepest
+// level (reverse messages zero) is G = u, F = -S/P~ of its source and costs
+// nothing, a middle level costs four operations per direction (two with
+// G = u).
 template <class ST, class MT, class AT, int KSRC, int GK, int D, bool FIRST, int SER>
 __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top) {
     DevStatus* st = a.st;
@@ -521,6 +551,7 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
     constexpr bool XF = MsgT<ST, MT, AT, SER>::F32;
     using LT = typename std::conditional<(SER && D <= 3) || std::is_same<ST, double>::value, XT, float>::type;
     constexpr bool STORED = (D == 0);
+    constexpr bool LEAN = (SER == 3);         // lower levels: G = u (no series term)
     constexpr int DL = (D > 1) ? D - 1 : 1;   // lower levels held per node
     constexpr int NL = STORED ? 1 : DL;
     constexpr int NT = STORED ? 1 : TILE;
@@ -528,7 +559,7 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
     // the deepest level D - 1; exact reciprocals: S at every lower level
     constexpr int NSL = SER ? ((D > 2) ? D - 2 : 1) : NL;
     constexpr int NTS = (SER && D <= 2) ? 1 : NT;
-    constexpr int NTQ = (SER && D > 2) ? NT : 1;
+    constexpr int NTQ = (SER && SER != 3 && D > 2) ? NT : 1;
     constexpr int NTD = (SER && D >= 2) ? NT : 1;
     const uint32_t ij = a.tiles[tile];
     const TileCoord tc{(int)(ij >> 16), (int)(ij & 0xFFFFu)};
@@ -543,13 +574,41 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
     // (the same IEEE quotients as here)
     const AT* HI = static_cast<const AT*>(a.HI);
     const AT* HM = static_cast<const AT*>(a.HM);
-    auto inv_at = [&](int64_t o) -> AT { return HI ? HI[o] : (AT)1 / HP[o]; };
-    auto mean_at = [&](int64_t o) -> AT { return HM ? HM[o] : HS[o] / HP[o]; };
+    // branch-free around the loads (the ring pointers are uniform), so that
+    // the node loads of the tile's prologue issue back to back
+    const AT* HIs = HI ? HI : HP;
+    const AT* HMs = HM ? HM : HS;
+    auto inv_at = [&](int64_t o) -> AT {
+        const AT v = HIs[o];
+        return HI ? v : (AT)1 / v;
+    };
+    auto mean_at = [&](int64_t o) -> AT {
+        const AT v = HMs[o], p = HP[o];
+        return HM ? v : v / p;
+    };
     const ST* Kp = static_cast<const ST*>(a.Kp);
     ST* Pf = static_cast<ST*>(a.Pf);
     ST* Pb = static_cast<ST*>(a.Pb);
     ST* Ef = static_cast<ST*>(a.Ef);
     ST* Eb = static_cast<ST*>(a.Eb);
+    // the lane's offset inside a row group of a tile
+    const uint32_t lo = (uint32_t)(g * TILE + col0);
+
+    // stateless over an FP32 K' plane: row steps stream through a per-wave
+    // LDS ring KR steps ahead (K' is the only stream; one register prefetch
+    // per lane does not cover the HBM latency), the first KR issued before
+    // the node data is loaded; other forms prefetch one row step ahead in
+    // registers
+    constexpr bool RING = (KSRC == KSRC_PLANE) && !STORED && std::is_same<ST, float>::value;
+    constexpr int KR = RING ? KRING : 1;
+    constexpr int SU = (RING && 8 % KR == 0) ? KR : 1;   // row steps unrolled (static ring slots)
+    __shared__ __attribute__((aligned(16))) float kring[KR][4][RING ? 256 : 4];
+    if constexpr (RING) {
+#pragma unroll
+        for (int u = 0; u < KR; ++u)
+            dma16(reinterpret_cast<const float*>(Kp) + tbase + (size_t)u * 4 * TILE, lo * 4u,
+                  lds_offset(&kring[u][w][0]));
+    }
 
     // row-node data: top level (P~ or, with SER, 1/P~) and lower levels
     __shared__ XT sPt[TILE], sS[TILE];
@@ -569,13 +628,19 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
         sPt[tid] = SER ? (XT)inv_at(o) : (XT)HP[o];
         sS[tid] = (XT)HS[o];
     }
-    XT ptj[4], sj[4];
+    // one-term series: the top level forms 1/Q = u - a^2 u^2 G_rev from u and
+    // u^2 (two operations per direction instead of three)
+    constexpr bool SQ1 = (SER == 1 || SER == 3);
+    __shared__ XT sPq[SQ1 ? TILE : 1];
+    XT ptj[4], sj[4], pqj[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         const int64_t o = top + (int64_t)tc.J * TILE + col0 + c;
         ptj[c] = SER ? (XT)inv_at(o) : (XT)HP[o];
         sj[c] = (XT)HS[o];
+        pqj[c] = ptj[c] * ptj[c];
     }
+    if constexpr (SQ1) sPq[tid] = sPt[tid] * sPt[tid];
     // lower levels per node: P~ (exact) or u = 1/P~ (series) at every level;
     // exact: S at every level; series: S and u^2 at the middle levels, S/P~
     // at the deepest
@@ -592,7 +657,7 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
                     if (k == D - 1) {
                         sSIL[tid] = (LT)mean_at(o);
                     } else {
-                        sUQL[k - 1][tid] = (LT)(u * u);
+                        if constexpr (!LEAN) sUQL[k - 1][tid] = (LT)(u * u);
                         sSL[k - 1][tid] = (LT)HS[o];
                     }
                 } else {
@@ -608,7 +673,7 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
                         if (k == D - 1) {
                             sijL[c] = (LT)mean_at(o);
                         } else {
-                            cuqL[k - 1][c] = (LT)(u * u);
+                            if constexpr (!LEAN) cuqL[k - 1][c] = (LT)(u * u);
                             sjL[k - 1][c] = (LT)HS[o];
                         }
                     } else {
@@ -624,12 +689,10 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
     bool bad = false;
     __syncthreads();
 
-    // row offset (wave-uniform: tile base plus 4 TILE per row step) and the
-    // lane's offset inside a row group
+    // row offset (wave-uniform: tile base plus 4 TILE per row step)
     size_t off = tbase;
-    const uint32_t lo = (uint32_t)(g * TILE + col0);
     V4<ST> k{}, pf{}, pb{}, ef{}, eb{};
-    if constexpr (KSRC == KSRC_PLANE) k = ld4nt(lane_ptr(Kp + off, lo));
+    if constexpr (!RING && KSRC == KSRC_PLANE) k = ld4nt(lane_ptr(Kp + off, lo));
     if constexpr (STORED && !FIRST) {
         pf = ld4nt(lane_ptr(Pf + off, lo)); pb = ld4nt(lane_ptr(Pb + off, lo));
         ef = ld4nt(lane_ptr(Ef + off, lo)); eb = ld4nt(lane_ptr(Eb + off, lo));
@@ -640,7 +703,7 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
             gram_band<GK>(a.F, a.kp, tc.I, tc.J, 32 * b, 64 * w, kband[w]);
             wave_lds_sync();
         }
-#pragma unroll 1
+#pragma unroll SU
         for (int s2 = 0; s2 < 8; ++s2) {
             const int r = 32 * b + 4 * s2 + g;
             // prefetch the lane's next row (the last row re-reads itself: the
@@ -648,7 +711,18 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
             const bool more = (b * 8 + s2 + 1) < TILE / 4;
             const size_t off2 = more ? off + 4 * TILE : off;
             V4<ST> k2, pf2, pb2, ef2, eb2;
-            if constexpr (KSRC == KSRC_PLANE) k2 = ld4nt(lane_ptr(Kp + off2, lo));
+            const int u = b * 8 + s2;                 // row step
+            if constexpr (RING) {
+                // this step's slot has landed once at most KR - 1 loads are
+                // in flight (every later step issued one), or all of them near
+                // the tile's end
+                if (u + KR <= TILE / 4) wait_vm<KR - 1>();
+                else wait_vm<0>();
+                const float4 kk = *reinterpret_cast<const float4*>(&kring[u % KR][w][4 * l]);
+                k = V4<ST>{{(ST)kk.x, (ST)kk.y, (ST)kk.z, (ST)kk.w}};
+            } else if constexpr (KSRC == KSRC_PLANE) {
+                k2 = ld4nt(lane_ptr(Kp + off2, lo));
+            }
             if constexpr (STORED && !FIRST) {
                 pf2 = ld4nt(lane_ptr(Pf + off2, lo)); pb2 = ld4nt(lane_ptr(Pb + off2, lo));
                 ef2 = ld4nt(lane_ptr(Ef + off2, lo)); eb2 = ld4nt(lane_ptr(Eb + off2, lo));
@@ -658,6 +732,7 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
                 k = V4<ST>{{(ST)kk.x, (ST)kk.y, (ST)kk.z, (ST)kk.w}};
             }
             const XT pti = sPt[r], si = sS[r];
+            const XT pqi = SQ1 ? sPq[r] : (XT)0;
             AT rp = 0, re = 0;
             XT rpm = 0, rem = 0;                         // XF: FP32 row sums (4 columns, then 64 per wave)
             V4<ST> npf, npb, nef, neb;
@@ -682,8 +757,14 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
                             ff = -sSIL[r];
                             fb = -sijL[c];
                         } else if (kk < kd) {
-                            const LT ngf = fma(-a2l * sUQL[kk - 1][r], gb, sPtL[kk - 1][r]);
-                            const LT ngb = fma(-a2l * cuqL[kk - 1][c], gf, ptjL[kk - 1][c]);
+                            LT ngf, ngb;
+                            if constexpr (LEAN) {
+                                ngf = sPtL[kk - 1][r];
+                                ngb = ptjL[kk - 1][c];
+                            } else {
+                                ngf = fma(-a2l * sUQL[kk - 1][r], gb, sPtL[kk - 1][r]);
+                                ngb = fma(-a2l * cuqL[kk - 1][c], gf, ptjL[kk - 1][c]);
+                            }
                             const LT nff = ngf * fma(al, fb, -sSL[kk - 1][r]);
                             const LT nfb = ngb * fma(al, ff, -sjL[kk - 1][c]);
                             gf = ngf; gb = ngb; ff = nff; fb = nfb;
@@ -711,14 +792,14 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
                 if constexpr (SER) {
                     // opf, opb, oef, oeb hold G_ij, G_ji, F_ij, F_ji here
                     const XT a2 = av * av;
-                    const XT e_f = -(a2 * opb) * pti, e_b = -(a2 * opf) * ptj[c];   // P_ji / P~_i, P_ij / P~_j
                     XT gt_f, gt_b;                                                  // (1 + e + ...) / P~
-                    if constexpr (SER >= 2) {
+                    if constexpr (SER == 2) {
+                        const XT e_f = -(a2 * opb) * pti, e_b = -(a2 * opf) * ptj[c];   // P_ji / P~_i, P_ij / P~_j
                         gt_f = fma(pti, fma(e_f, e_f, e_f), pti);
                         gt_b = fma(ptj[c], fma(e_b, e_b, e_b), ptj[c]);
                     } else {
-                        gt_f = fma(pti, e_f, pti);
-                        gt_b = fma(ptj[c], e_b, ptj[c]);
+                        gt_f = fma(-(a2 * pqi), opb, pti);                          // u (1 + e), e = -a^2 u G_rev
+                        gt_b = fma(-(a2 * pqj[c]), opf, ptj[c]);
                     }
                     pij_m = -a2 * gt_f;
                     pji_m = -a2 * gt_b;
@@ -777,7 +858,14 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
                     wave_lds_sync();
                 }
             }
-            if constexpr (KSRC == KSRC_PLANE) k = k2;
+            if constexpr (RING) {
+                // the slot's next row step (k was read from it and used above)
+                if (u + KR < TILE / 4)
+                    dma16(reinterpret_cast<const float*>(Kp) + tbase + (size_t)(u + KR) * 4 * TILE, lo * 4u,
+                          lds_offset(&kring[u % KR][w][0]));
+            } else if constexpr (KSRC == KSRC_PLANE) {
+                k = k2;
+            }
             if constexpr (STORED && !FIRST) { pf = pf2; pb = pb2; ef = ef2; eb = eb2; }
             off = off2;
         }
@@ -1021,8 +1109,13 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
                                 lp = pv;
                                 le = -siv;
                             } else {
-                                const LT uq = row_side ? sm.lowUQ[mr][r] : clUQ[mc][c];
-                                const LT ng = fma(-a2l * uq, lp, pv);
+                                LT ng;
+                                if constexpr (SER == 3) {       // G = u (no series term)
+                                    ng = pv;
+                                } else {
+                                    const LT uq = row_side ? sm.lowUQ[mr][r] : clUQ[mc][c];
+                                    ng = fma(-a2l * uq, lp, pv);
+                                }
                                 const LT nf = ng * fma(al, le, -sv);
                                 lp = ng; le = nf;
                             }
@@ -1046,7 +1139,7 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
                     const XT a2 = av * av;
                     const XT e = -(a2 * opr) * pt;
                     XT gt;
-                    if constexpr (SER >= 2) gt = fma(pt, fma(e, e, e), pt);
+                    if constexpr (SER == 2) gt = fma(pt, fma(e, e, e), pt);
                     else gt = fma(pt, e, pt);
                     pm = -a2 * gt;
                     em = (av * gt) * fma(av, oer, -sv);
@@ -1202,6 +1295,7 @@ inline hipError_t with_stateless(int levels, int ser, F&& f) {
         GABP_SL(0, 1) GABP_SL(0, 2) GABP_SL(0, 3) GABP_SL(0, 4) GABP_SL(0, 5) GABP_SL(0, 6) GABP_SL(0, 7) GABP_SL(0, 8)
         GABP_SL(1, 1) GABP_SL(1, 2) GABP_SL(1, 3) GABP_SL(1, 4) GABP_SL(1, 5) GABP_SL(1, 6)
         GABP_SL(2, 1) GABP_SL(2, 2) GABP_SL(2, 3) GABP_SL(2, 4) GABP_SL(2, 5) GABP_SL(2, 6)
+        GABP_SL(3, 3) GABP_SL(3, 4) GABP_SL(3, 5) GABP_SL(3, 6)
         default: return hipErrorInvalidValue;
     }
 #undef GABP_SL

@@ -85,15 +85,19 @@ inline int stateless_levels_needed(int prec, double rr) {
     return std::max(1, (int)std::ceil(std::log(eps) / std::log(rr)));
 }
 // Reciprocal form of a stateless plan: 0 exact reciprocals; 1 / 2 series
-// around 1/P~ with a one- / two-term top level.  |e| <= rr^2, so the
+// around 1/P~ with a one- / two-term top level; 3 a one-term top level over
+// lower levels that take G = 1/P~ (no series term).  |e| <= rr^2, so the
 // one-term lower levels err by rr^4, entering the top level scaled by rr,
-// and the top level errs by rr^4 (one term) or rr^6 (two terms); each must
-// stay below the precision of its arithmetic (FP32 messages: FP32 and
+// and the top level errs by rr^4 (one term) or rr^6 (two terms).  Form 3
+// drops the lower levels' e: G errs by rr^2, which reaches the top level's
+// precision term scaled by rr^2 (rr^4) and its mean term through F scaled by
+// rr (rr^3); it needs a middle level (levels >= 3).  Each error must stay
+// below the precision of the message arithmetic (FP32 messages: FP32 and
 // MIXED; FP64 messages: FP64).
 inline int stateless_series_form(int prec, int levels, double rr) {
     const double eps = (prec == PREC_FP64) ? std::ldexp(1.0, -52) : std::ldexp(1.0, -24);
     if (levels < 1 || levels > 6 || !(rr < 0.25) || std::pow(rr, 5) > eps) return 0;
-    if (std::pow(rr, 4) <= eps) return 1;
+    if (std::pow(rr, 4) <= eps) return (levels >= 3 && std::pow(rr, 3) <= eps) ? 3 : 1;
     if (std::pow(rr, 6) <= eps) return 2;
     return 0;
 }

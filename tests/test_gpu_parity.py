@@ -318,9 +318,12 @@ def test_plan_follows_memory_budget(torch):
 
 # (N, gamma, precision, series form): wide RBFs give row sums ~ N and a
 # contraction rho ~ 1/N; FP32 messages (FP32, MIXED) take the one-term top
-# level while rho^4 is below 2^-24 and the two-term one up to rho^6, FP64
-# needs rho^5 below 2^-52 for any series
-SERIES_CASES = [(1500, 2e-3, "fp32", 1), (1500, 2e-3, "mixed", 1), (600, 0.05, "fp32", 2),
+# level while rho^4 is below 2^-24 (form 1), with 1/P~ alone at the lower
+# levels when rho^3 is too and a middle level exists (form 3), and the
+# two-term one up to rho^6 (form 2); FP64 needs rho^5 below 2^-52 for any
+# series (rr = 1.25 rho throughout)
+SERIES_CASES = [(1500, 2e-3, "fp32", 3), (1500, 2e-3, "mixed", 3), (1500, 5e-3, "mixed", 3),
+                (1500, 2e-2, "fp32", 1), (1500, 2e-2, "mixed", 1), (600, 0.05, "fp32", 2),
                 (600, 0.05, "mixed", 2), (2000, 2e-3, "fp64", 2)]
 
 
