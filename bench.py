@@ -509,8 +509,16 @@ def counter_traffic_kernel(path, name_prefix):
 
 # kernel names of the measured sweeps (template arguments: storage, message,
 # aggregate type, K' source, Gram kind, levels, first sweep, series terms)
-SWEEP_KERNEL = {("mixed", "stateless"): "gabp::k_sweep<float, double, double, 0, 0, 3, false, 1>",
-                ("mixed", "stored"): "gabp::k_sweep<float, double, double, 0, 0, 0, false, 0>"}
+TYPES = {"mixed": "float, double, double", "fp32": "float, float, float", "fp64": "double, double, double"}
+
+
+def sweep_kernel_name(precision, plan):
+    """rocprofv3's name of the synchronous sweep kernel a plan launches over
+    the materialised K' (template arguments as above)."""
+    if plan["edge_state"] == 1:   # stored pair records (sweeps after the first)
+        return f"gabp::k_sweep<{TYPES[precision]}, 0, 0, 0, false, 0>"
+    return (f"gabp::k_sweep<{TYPES[precision]}, 0, 0, {plan['stateless_depth']}, false, "
+            f"{int(plan['series_reciprocal'])}>")
 
 
 def main():
@@ -581,7 +589,7 @@ def main():
     stateless = plan["edge_state"] == gabp.EDGE["stateless"]
     recompute = plan["kstore"] == gabp.KSTORE["recompute"]
     edge_name = "stateless" if stateless else "stored"
-    traffic = counter_traffic_kernel(a.traffic_json, SWEEP_KERNEL.get((a.precision, edge_name), "-"))
+    traffic = counter_traffic_kernel(a.traffic_json, sweep_kernel_name(a.precision, plan))
     if not recompute:
         # the sweep streams the K' plane (and, with stored records, the four
         # pair-record planes): HBM-bound on its algorithmic bytes
@@ -612,8 +620,7 @@ def main():
                       "err_vs_oracle": rel_err(sinfo["alpha"], aref),
                       "rel_diff_alpha_vs_main": rel_err(sinfo["alpha"], info["alpha"]),
                       "roofline": hbm_roof(sp, sk_ / max(sl_, 1), sl_, "k_sweep (stored, K' materialised)",
-                                           counter_traffic_kernel(a.traffic_json,
-                                                                  SWEEP_KERNEL.get((a.precision, "stored"), "-")))}
+                                           counter_traffic_kernel(a.traffic_json, sweep_kernel_name(a.precision, sp)))}
         print(f"[bench] stored state: {ss_} sweeps in {sw_:.3f} s", file=sys.stderr, flush=True)
 
     grouped = None
