@@ -503,6 +503,15 @@ __device__ inline void wave_lds_sync() {
 
 // ------------------------------------------------------------------ sweep --
 
+// Stores one partial sum of a tile: in FP32 when the plan keeps its partials
+// in FP32 (the FP32-message form, whose tile sums are FP32 sums rounded once
+// more here), else in the aggregate type.
+template <class AT>
+__device__ inline void put_part(void* base, size_t o, AT v, bool p32) {
+    if (p32) static_cast<float*>(base)[o] = (float)v;
+    else static_cast<AT*>(base)[o] = v;
+}
+
 // Type of the message arithmetic.  The MIXED path (FP32 storage, FP64
 // aggregates) with series reciprocals computes its messages in FP32: the
 // cavity denominator P~ - P_reverse is never formed (the series factor
@@ -878,16 +887,15 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
 #pragma unroll
     for (int c = 0; c < 4; ++c) { cP[c] = sum_groups(cP[c]); cE[c] = sum_groups(cE[c]); }
     __syncthreads();
-    AT* partP = static_cast<AT*>(a.partP);
-    AT* partE = static_cast<AT*>(a.partE);
+    const bool p32 = a.part32 != 0;
     const size_t rowslot = ((size_t)tc.I * (NB + 1) + tc.J) * TILE + tid;
-    partP[rowslot] = ((AT)rP[0][tid] + (AT)rP[1][tid]) + ((AT)rP[2][tid] + (AT)rP[3][tid]);
-    partE[rowslot] = ((AT)rE[0][tid] + (AT)rE[1][tid]) + ((AT)rE[2][tid] + (AT)rE[3][tid]);
+    put_part(a.partP, rowslot, ((AT)rP[0][tid] + (AT)rP[1][tid]) + ((AT)rP[2][tid] + (AT)rP[3][tid]), p32);
+    put_part(a.partE, rowslot, ((AT)rE[0][tid] + (AT)rE[1][tid]) + ((AT)rE[2][tid] + (AT)rE[3][tid]), p32);
     if (g == 0) {
         const int slot = (tc.I < tc.J) ? tc.I : NB;
         const size_t cb = ((size_t)tc.J * (NB + 1) + slot) * TILE + col0;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) { partP[cb + c] = cP[c]; partE[cb + c] = cE[c]; }
+        for (int c = 0; c < 4; ++c) { put_part(a.partP, cb + c, cP[c], p32); put_part(a.partE, cb + c, cE[c], p32); }
     }
     if (__any(bad) && l == 0) st->bad = 1;
 }
@@ -1195,8 +1203,7 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
         }
         if constexpr (KSRC == KSRC_RECOMPUTE) wave_lds_sync();
     }
-    AT* partP = static_cast<AT*>(a.partP);
-    AT* partE = static_cast<AT*>(a.partE);
+    const bool p32 = a.part32 != 0;
     if constexpr (FWD) {
         if constexpr (XF) {
 #pragma unroll
@@ -1208,13 +1215,13 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
             const int slot = (tc.I < tc.J) ? tc.I : NB;
             const size_t cb = ((size_t)tc.J * (NB + 1) + slot) * TILE + col0;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) { partP[cb + c] = cP[c]; partE[cb + c] = cE[c]; }
+            for (int c = 0; c < 4; ++c) { put_part(a.partP, cb + c, cP[c], p32); put_part(a.partE, cb + c, cE[c], p32); }
         }
     } else {
         __syncthreads();
         const size_t rowslot = ((size_t)tc.I * (NB + 1) + tc.J) * TILE + tid;
-        partP[rowslot] = ((AT)sm.rP[0][tid] + (AT)sm.rP[1][tid]) + ((AT)sm.rP[2][tid] + (AT)sm.rP[3][tid]);
-        partE[rowslot] = ((AT)sm.rE[0][tid] + (AT)sm.rE[1][tid]) + ((AT)sm.rE[2][tid] + (AT)sm.rE[3][tid]);
+        put_part(a.partP, rowslot, ((AT)sm.rP[0][tid] + (AT)sm.rP[1][tid]) + ((AT)sm.rP[2][tid] + (AT)sm.rP[3][tid]), p32);
+        put_part(a.partE, rowslot, ((AT)sm.rE[0][tid] + (AT)sm.rE[1][tid]) + ((AT)sm.rE[2][tid] + (AT)sm.rE[3][tid]), p32);
     }
     if (__any(bad) && l == 0) st->bad = 1;
 }

@@ -154,7 +154,8 @@ struct SweepArgs {
     const void *HI, *HM;          // series: rings of 1/P~ and S/P~ (null: formed in the tile)
     int64_t NPAD;
     int R, slot_top, levels;      // ring depth, top slot, stateless levels in use
-    void *partP, *partE;          // [NB][NB+1][TILE] partial sums
+    int part32;                   // 1: partial sums stored in FP32 (FP32-message plans)
+    void *partP, *partE;          // [NB][NB+1][TILE] partial sums (aggregate type, or FP32)
     DevStatus* st;
     Features F;                   // KSRC_RECOMPUTE
     KernelParams kp;
@@ -212,12 +213,13 @@ hipError_t launch_sweep_mixed(int ksrc, int gram, int levels, bool first, int se
 hipError_t launch_sweep_f64(int ksrc, int gram, int levels, bool first, int ser, const SweepArgs& a,
                             hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 // Inv / Mean (optional, with Pt / S): the new 1/P~ and S/P~ of the series
-// sweeps, formed once per node here instead of in every tile.
+// sweeps, formed once per node here instead of in every tile.  part32: the
+// partial sums are FP32 (SweepArgs::part32).
 hipError_t launch_finalize(int prec, int64_t N, int NB, const void* partP, const void* partE,
                            const double* Adiag, const float* y, void* Pt, void* S,
                            double* alpha, double* blk_delta, double* blk_amax,
                            DevStatus* st, hipStream_t s, double boxC = 0.0, void* Inv = nullptr,
-                           void* Mean = nullptr);
+                           void* Mean = nullptr, int part32 = 0);
 // Inv / Mean of every ring slot from Pt / S (R slots of NPAD entries).
 hipError_t launch_ring_recip(int prec, int64_t NPAD, int R, const void* Pt, const void* S, void* Inv, void* Mean,
                              hipStream_t s);
@@ -290,7 +292,8 @@ hipError_t launch_sp_sweep(int prec, int64_t E, int64_t N, const int32_t* ei, co
 hipError_t launch_finalize_range(int prec, int64_t b0, int64_t nb, int64_t N, int NB, const void* partP,
                                  const void* partE, const double* Adiag, const float* y, void* Pt, void* S,
                                  double* alpha, double* blk_delta, double* blk_amax, DevStatus* st,
-                                 hipStream_t s, double boxC = 0.0, void* Inv = nullptr, void* Mean = nullptr);
+                                 hipStream_t s, double boxC = 0.0, void* Inv = nullptr, void* Mean = nullptr,
+                                 int part32 = 0);
 hipError_t launch_status(int nblk, const double* blk_delta, const double* blk_amax,
                          DevStatus* st, double* trace, StopRule rule, hipStream_t s);
 // A-priori contraction bound: one[0] = -m* (minus the aggregate lower

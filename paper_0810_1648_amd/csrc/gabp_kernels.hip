@@ -592,9 +592,9 @@ __global__ void k_init(int64_t N, int64_t NPAD, int R, const double* __restrict_
 // slot `wslot`, the new alpha and the per-block change / magnitude maxima.
 // boxC > 0: the belief mean is clipped to [0, boxC] (alpha space) and S is
 // replaced by P~ times the clipped mean.
-template <class AT>
-__device__ inline void finalize_block(int64_t blk, int64_t N, int NB, const AT* __restrict__ partP,
-                                      const AT* __restrict__ partE,
+template <class AT, class PT>
+__device__ inline void finalize_block(int64_t blk, int64_t N, int NB, const PT* __restrict__ partP,
+                                      const PT* __restrict__ partE,
                                       const double* __restrict__ Adiag,
                                       const float* __restrict__ y, AT* __restrict__ Pt,
                                       AT* __restrict__ S, double* __restrict__ alpha,
@@ -614,7 +614,7 @@ __device__ inline void finalize_block(int64_t blk, int64_t N, int NB, const AT* 
         for (int s = s0; s < s1; ++s) {
             const size_t o = ((size_t)blk * S1 + s) * TILE + l;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) { ap[k] += partP[o + 64 * k]; ae[k] += partE[o + 64 * k]; }
+            for (int k = 0; k < 4; ++k) { ap[k] += (AT)partP[o + 64 * k]; ae[k] += (AT)partE[o + 64 * k]; }
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) { shp[w][l + 64 * k] = ap[k]; she[w][l + 64 * k] = ae[k]; }
@@ -646,9 +646,9 @@ __device__ inline void finalize_block(int64_t blk, int64_t N, int NB, const AT* 
     if (threadIdx.x == 0) { blk_delta[blk] = d; blk_amax[blk] = am; }
 }
 
-template <class AT>
-__global__ __launch_bounds__(WG) void k_finalize(int64_t N, int NB, const AT* __restrict__ partP,
-                                                const AT* __restrict__ partE,
+template <class AT, class PT>
+__global__ __launch_bounds__(WG) void k_finalize(int64_t N, int NB, const PT* __restrict__ partP,
+                                                const PT* __restrict__ partE,
                                                 const double* __restrict__ Adiag,
                                                 const float* __restrict__ y, AT* __restrict__ Pt,
                                                 AT* __restrict__ S, double* __restrict__ alpha,
@@ -656,8 +656,8 @@ __global__ __launch_bounds__(WG) void k_finalize(int64_t N, int NB, const AT* __
                                                 double* __restrict__ blk_amax, DevStatus* st, double boxC,
                                                 AT* __restrict__ Inv, AT* __restrict__ Mean) {
     if (st->done) return;
-    finalize_block<AT>(blockIdx.x, N, NB, partP, partE, Adiag, y, Pt, S, alpha, blk_delta, blk_amax, st, boxC,
-                       Inv, Mean);
+    finalize_block<AT, PT>(blockIdx.x, N, NB, partP, partE, Adiag, y, Pt, S, alpha, blk_delta, blk_amax, st, boxC,
+                           Inv, Mean);
 }
 
 // 1/P~ and S/P~ of every ring slot (series sweeps): P~ = +inf, S = 0 give 0
@@ -672,9 +672,9 @@ __global__ void k_ring_recip(int64_t n, const AT* __restrict__ Pt, const AT* __r
 }
 
 // Grouped schedule: the node blocks [b0, b0 + gridDim.x) of one group.
-template <class AT>
-__global__ __launch_bounds__(WG) void k_finalize_range(int64_t b0, int64_t N, int NB, const AT* __restrict__ partP,
-                                                      const AT* __restrict__ partE,
+template <class AT, class PT>
+__global__ __launch_bounds__(WG) void k_finalize_range(int64_t b0, int64_t N, int NB, const PT* __restrict__ partP,
+                                                      const PT* __restrict__ partE,
                                                       const double* __restrict__ Adiag,
                                                       const float* __restrict__ y, AT* __restrict__ Pt,
                                                       AT* __restrict__ S, double* __restrict__ alpha,
@@ -682,8 +682,8 @@ __global__ __launch_bounds__(WG) void k_finalize_range(int64_t b0, int64_t N, in
                                                       double* __restrict__ blk_amax, DevStatus* st, double boxC,
                                                       AT* __restrict__ Inv, AT* __restrict__ Mean) {
     if (st->done) return;
-    finalize_block<AT>(b0 + blockIdx.x, N, NB, partP, partE, Adiag, y, Pt, S, alpha, blk_delta, blk_amax, st,
-                       boxC, Inv, Mean);
+    finalize_block<AT, PT>(b0 + blockIdx.x, N, NB, partP, partE, Adiag, y, Pt, S, alpha, blk_delta, blk_amax, st,
+                           boxC, Inv, Mean);
 }
 
 // Served form: items are (request, block of 256 nodes).
@@ -695,11 +695,16 @@ __global__ __launch_bounds__(WG) void k_finalize_batched(const ReqDesc* __restri
         const ReqDesc& rd = reqs[w.x];
         if (rd.sw.st->done) continue;
         const int64_t wslot = (int64_t)((rd.sw.st->t + 1) % rd.sw.R) * rd.sw.NPAD;
-        finalize_block<AT>((int64_t)w.y, rd.N, rd.sw.NB, static_cast<const AT*>(rd.sw.partP),
-                           static_cast<const AT*>(rd.sw.partE), rd.Adiag, rd.y,
-                           static_cast<AT*>(const_cast<void*>(rd.sw.HP)) + wslot,
-                           static_cast<AT*>(const_cast<void*>(rd.sw.HS)) + wslot, rd.alpha, rd.blk_delta,
-                           rd.blk_amax, rd.sw.st, 0.0, nullptr, nullptr);
+        AT* const Pt = static_cast<AT*>(const_cast<void*>(rd.sw.HP)) + wslot;
+        AT* const S = static_cast<AT*>(const_cast<void*>(rd.sw.HS)) + wslot;
+        if (rd.sw.part32)
+            finalize_block<AT, float>((int64_t)w.y, rd.N, rd.sw.NB, static_cast<const float*>(rd.sw.partP),
+                                      static_cast<const float*>(rd.sw.partE), rd.Adiag, rd.y, Pt, S, rd.alpha,
+                                      rd.blk_delta, rd.blk_amax, rd.sw.st, 0.0, nullptr, nullptr);
+        else
+            finalize_block<AT, AT>((int64_t)w.y, rd.N, rd.sw.NB, static_cast<const AT*>(rd.sw.partP),
+                                   static_cast<const AT*>(rd.sw.partE), rd.Adiag, rd.y, Pt, S, rd.alpha,
+                                   rd.blk_delta, rd.blk_amax, rd.sw.st, 0.0, nullptr, nullptr);
         __syncthreads();
     }
 }
@@ -1022,15 +1027,19 @@ hipError_t launch_served_status(const ReqDesc* reqs, const int* slots, int nslot
 hipError_t launch_finalize(int prec, int64_t N, int NB, const void* partP, const void* partE,
                            const double* Adiag, const float* y, void* Pt, void* S, double* alpha,
                            double* blk_delta, double* blk_amax, DevStatus* st, hipStream_t s, double boxC,
-                           void* Inv, void* Mean) {
+                           void* Inv, void* Mean, int part32) {
     if ((Inv == nullptr) != (Mean == nullptr)) return hipErrorInvalidValue;
     const dim3 g(grid1(N)), b(WG);
     if (prec == PREC_FP32)
-        hipLaunchKernelGGL(k_finalize<float>, g, b, 0, s, N, NB, (const float*)partP,
+        hipLaunchKernelGGL((k_finalize<float, float>), g, b, 0, s, N, NB, (const float*)partP,
                            (const float*)partE, Adiag, y, (float*)Pt, (float*)S, alpha, blk_delta,
                            blk_amax, st, boxC, (float*)Inv, (float*)Mean);
+    else if (part32)
+        hipLaunchKernelGGL((k_finalize<double, float>), g, b, 0, s, N, NB, (const float*)partP,
+                           (const float*)partE, Adiag, y, (double*)Pt, (double*)S, alpha,
+                           blk_delta, blk_amax, st, boxC, (double*)Inv, (double*)Mean);
     else
-        hipLaunchKernelGGL(k_finalize<double>, g, b, 0, s, N, NB, (const double*)partP,
+        hipLaunchKernelGGL((k_finalize<double, double>), g, b, 0, s, N, NB, (const double*)partP,
                            (const double*)partE, Adiag, y, (double*)Pt, (double*)S, alpha,
                            blk_delta, blk_amax, st, boxC, (double*)Inv, (double*)Mean);
     return hipGetLastError();
@@ -1051,16 +1060,20 @@ hipError_t launch_ring_recip(int prec, int64_t NPAD, int R, const void* Pt, cons
 hipError_t launch_finalize_range(int prec, int64_t b0, int64_t nb, int64_t N, int NB, const void* partP,
                                  const void* partE, const double* Adiag, const float* y, void* Pt, void* S,
                                  double* alpha, double* blk_delta, double* blk_amax, DevStatus* st,
-                                 hipStream_t s, double boxC, void* Inv, void* Mean) {
+                                 hipStream_t s, double boxC, void* Inv, void* Mean, int part32) {
     if (nb <= 0) return hipSuccess;
     if ((Inv == nullptr) != (Mean == nullptr)) return hipErrorInvalidValue;
     const dim3 g((unsigned)nb), b(WG);
     if (prec == PREC_FP32)
-        hipLaunchKernelGGL(k_finalize_range<float>, g, b, 0, s, b0, N, NB, (const float*)partP,
+        hipLaunchKernelGGL((k_finalize_range<float, float>), g, b, 0, s, b0, N, NB, (const float*)partP,
                            (const float*)partE, Adiag, y, (float*)Pt, (float*)S, alpha, blk_delta, blk_amax, st,
                            boxC, (float*)Inv, (float*)Mean);
+    else if (part32)
+        hipLaunchKernelGGL((k_finalize_range<double, float>), g, b, 0, s, b0, N, NB, (const float*)partP,
+                           (const float*)partE, Adiag, y, (double*)Pt, (double*)S, alpha, blk_delta, blk_amax,
+                           st, boxC, (double*)Inv, (double*)Mean);
     else
-        hipLaunchKernelGGL(k_finalize_range<double>, g, b, 0, s, b0, N, NB, (const double*)partP,
+        hipLaunchKernelGGL((k_finalize_range<double, double>), g, b, 0, s, b0, N, NB, (const double*)partP,
                            (const double*)partE, Adiag, y, (double*)Pt, (double*)S, alpha, blk_delta, blk_amax,
                            st, boxC, (double*)Inv, (double*)Mean);
     return hipGetLastError();

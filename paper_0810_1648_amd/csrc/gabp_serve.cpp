@@ -379,6 +379,7 @@ hipError_t setup_request(gabp_server* S, Req& r) {
     d.sw.R = R;
     d.sw.slot_top = 0;
     d.sw.levels = r.levels;
+    d.sw.part32 = (r.prec == PREC_MIXED && stateless && r.ser > 0) ? 1 : 0;   // as in a single solve
     d.sw.partP = P(B_PARTP); d.sw.partE = P(B_PARTE);
     d.sw.st = (DevStatus*)P(B_STATUS);
     d.sw.F = F;

@@ -499,6 +499,9 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     sa.HI = hinv; sa.HM = hmean;
     sa.NPAD = NPAD;
     sa.R = Rr;
+    // the FP32-message form (MIXED, series reciprocals) sums each tile's
+    // messages in FP32; its partial sums are kept in FP32 (half the traffic)
+    sa.part32 = (prec == PREC_MIXED && !cur_stored && ser > 0) ? 1 : 0;
     sa.partP = h->partP.p; sa.partE = h->partE.p;
     sa.st = st;
     sa.F = F;
@@ -578,7 +581,8 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
                                    p.time_sweeps ? sev[2 * slot] : nullptr, p.time_sweeps ? sev[2 * slot + 1] : nullptr));
             HIPCHK(h, launch_finalize(prec, N, NB, h->partP.p, h->partE.p, h->Adiag.as<double>(),
                                       h->yd.as<float>(), wP, wS, h->alpha_d.as<double>(),
-                                      h->blk1.as<double>(), h->blk2.as<double>(), st, s, boxC, wI, wM));
+                                      h->blk1.as<double>(), h->blk2.as<double>(), st, s, boxC, wI, wM,
+                                      sa.part32));
         } else {
             // one visit per group: its messages, then its aggregates (the
             // timed span covers the visits and their group finalizes)
@@ -592,7 +596,7 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
                 HIPCHK(h, launch_finalize_range(prec, b0, b1 - b0, N, NB, h->partP.p, h->partE.p,
                                                 h->Adiag.as<double>(), h->yd.as<float>(), wP, wS,
                                                 h->alpha_d.as<double>(), h->blk1.as<double>(),
-                                                h->blk2.as<double>(), st, s, boxC, wI, wM));
+                                                h->blk2.as<double>(), st, s, boxC, wI, wM, sa.part32));
             }
             if (p.time_sweeps) HIPCHK(h, hipEventRecord(sev[2 * slot + 1], s));
         }
