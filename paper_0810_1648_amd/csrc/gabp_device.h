@@ -661,12 +661,15 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
                 const int64_t base = (int64_t)((slot_top - k + a.R) % a.R) * a.NPAD;
                 const int64_t o = base + (int64_t)tc.I * TILE + tid;
                 if constexpr (SER) {
-                    const AT u = inv_at(o);
-                    sPtL[k - 1][tid] = (LT)u;
+                    // form 3: the deepest level's G (= u) is never read
+                    if (!(LEAN && k == D - 1)) sPtL[k - 1][tid] = (LT)inv_at(o);
                     if (k == D - 1) {
                         sSIL[tid] = (LT)mean_at(o);
                     } else {
-                        if constexpr (!LEAN) sUQL[k - 1][tid] = (LT)(u * u);
+                        if constexpr (!LEAN) {
+                            const AT u = inv_at(o);
+                            sUQL[k - 1][tid] = (LT)(u * u);
+                        }
                         sSL[k - 1][tid] = (LT)HS[o];
                     }
                 } else {
@@ -678,7 +681,7 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
                     const int64_t o = base + (int64_t)tc.J * TILE + col0 + c;
                     if constexpr (SER) {
                         const AT u = inv_at(o);
-                        ptjL[k - 1][c] = (LT)u;
+                        if (!(LEAN && k == D - 1)) ptjL[k - 1][c] = (LT)u;
                         if (k == D - 1) {
                             sijL[c] = (LT)mean_at(o);
                         } else {
@@ -761,8 +764,10 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
 #pragma unroll
                     for (int kk = D - 1; kk >= 1; --kk) {
                         if (kk == kd) {               // deepest level: reverse messages zero
-                            gf = sPtL[kk - 1][r];
-                            gb = ptjL[kk - 1][c];
+                            if constexpr (!LEAN) {    // (form 3 never reads this level's G)
+                                gf = sPtL[kk - 1][r];
+                                gb = ptjL[kk - 1][c];
+                            }
                             ff = -sSIL[r];
                             fb = -sijL[c];
                         } else if (kk < kd) {
