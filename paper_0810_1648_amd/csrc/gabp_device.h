@@ -81,7 +81,14 @@ __device__ inline uint32_t lds_offset(const void* p) {
 // wait_vm before reading the LDS it writes, and issue it only after their
 // last read of that LDS has completed.
 __device__ inline void dma16(const float* base, uint32_t voff, uint32_t lds) {
+    // the base and the LDS offset are wave-uniform: scalar operands
     lds = __builtin_amdgcn_readfirstlane(lds);
+    // (the builtin returns a signed int: each half goes through uint32_t so
+    // that the low half is zero-extended, never sign-extended)
+    const uint64_t b = reinterpret_cast<uint64_t>(base);
+    const uint32_t bh = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+    const uint32_t bl = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+    base = reinterpret_cast<const float*>(((uint64_t)bh << 32) | (uint64_t)bl);
     asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, %1 nt"
                  :: "v"(voff), "s"(base), "s"(lds) : "memory", "m0");
 }
@@ -954,8 +961,11 @@ __device__ inline int level_visit_offset(bool fwd, bool within, int k) {
 
 // LDS of one single-direction visit, declared by the kernel so that both
 // directions share it.
-template <class MT, class LT, class AT, class RT, int NRL, int RECOMP>
+template <class MT, class LT, class AT, class RT, int NRL, int RECOMP, int KRN = 0>
 struct DirSmem {
+    static constexpr int RING_STEPS = KRN;
+    // K' ring (stateless visits over an FP32 plane): KRN row steps per wave
+    __attribute__((aligned(16))) float kring[KRN > 0 ? KRN : 1][4][KRN > 0 ? 256 : 4];
     MT topP[TILE], topS[TILE];            // row source at level 0 (FWD)
     LT lowP[NRL][TILE], lowS[NRL][TILE];  // row source at lower levels
     LT lowSI[NRL][TILE];                  // series: S / P~
@@ -1001,6 +1011,21 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
     const AT* HI = static_cast<const AT*>(a.HI);
     const AT* HM = static_cast<const AT*>(a.HM);
     const ST* Kp = static_cast<const ST*>(a.Kp);
+    const uint32_t lo = (uint32_t)(g * TILE + col0);      // lane offset inside a row group
+    // stateless visits over an FP32 K' plane (single solves): row steps
+    // stream through the per-wave LDS ring as in the synchronous sweep, the
+    // first KR issued first.  The served form keeps the one-step register
+    // prefetch: its many small launches run more workgroups per CU without
+    // the ring's LDS.
+    constexpr bool RING = (SM::RING_STEPS > 0) && (KSRC == KSRC_PLANE) && !STORED && std::is_same<ST, float>::value;
+    constexpr int KR = RING ? SM::RING_STEPS : 1;
+    constexpr int SU = (RING && 8 % KR == 0) ? KR : 1;   // row steps unrolled (static ring slots)
+    if constexpr (RING) {
+#pragma unroll
+        for (int u = 0; u < KR; ++u)
+            dma16(reinterpret_cast<const float*>(Kp) + tbase + (size_t)u * 4 * TILE, lo * 4u,
+                  lds_offset(&sm.kring[u][w][0]));
+    }
     auto slot_of = [&](int k) -> int64_t {
         if constexpr (STORED) return 0;
         const int v = t + level_version_offset(FWD, within, k);
@@ -1073,9 +1098,8 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
     ST* Ewr = static_cast<ST*>(FWD ? a.Ef : a.Eb);
 
     size_t off = tbase;                                   // wave-uniform row offset
-    const uint32_t lo = (uint32_t)(g * TILE + col0);      // lane offset inside a row group
     V4<ST> k4{}, pr{}, er{};
-    if constexpr (KSRC == KSRC_PLANE) k4 = ld4nt(lane_ptr(Kp + off, lo));
+    if constexpr (KSRC == KSRC_PLANE && !RING) k4 = ld4nt(lane_ptr(Kp + off, lo));
     if constexpr (STORED) { pr = ld4nt(lane_ptr(Prd + off, lo)); er = ld4nt(lane_ptr(Erd + off, lo)); }
 
     for (int b = 0; b < TILE / 32; ++b) {
@@ -1083,13 +1107,21 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
             gram_band<GK>(a.F, a.kp, tc.I, tc.J, 32 * b, 64 * w, sm.kband[w]);
             wave_lds_sync();
         }
-#pragma unroll 1
+#pragma unroll SU
         for (int s2 = 0; s2 < 8; ++s2) {
             const int r = 32 * b + 4 * s2 + g;
             const bool more = (b * 8 + s2 + 1) < TILE / 4;
             const size_t off2 = more ? off + 4 * TILE : off;
             V4<ST> k2, pr2, er2;
-            if constexpr (KSRC == KSRC_PLANE) k2 = ld4nt(lane_ptr(Kp + off2, lo));
+            const int u = b * 8 + s2;                 // row step
+            if constexpr (RING) {
+                if (u + KR <= TILE / 4) wait_vm<KR - 1>();
+                else wait_vm<0>();
+                const float4 kk = *reinterpret_cast<const float4*>(&sm.kring[u % KR][w][4 * l]);
+                k4 = V4<ST>{{(ST)kk.x, (ST)kk.y, (ST)kk.z, (ST)kk.w}};
+            } else if constexpr (KSRC == KSRC_PLANE) {
+                k2 = ld4nt(lane_ptr(Kp + off2, lo));
+            }
             if constexpr (STORED) { pr2 = ld4nt(lane_ptr(Prd + off2, lo)); er2 = ld4nt(lane_ptr(Erd + off2, lo)); }
             if constexpr (KSRC == KSRC_RECOMPUTE) {
                 const float4 kk = *reinterpret_cast<const float4*>(&sm.kband[w][(4 * s2 + g) * 64 + 4 * q]);
@@ -1202,7 +1234,14 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
                     wave_lds_sync();
                 }
             }
-            if constexpr (KSRC == KSRC_PLANE) k4 = k2;
+            if constexpr (RING) {
+                // the slot's next row step (k4 was read from it and used above)
+                if (u + KR < TILE / 4)
+                    dma16(reinterpret_cast<const float*>(Kp) + tbase + (size_t)(u + KR) * 4 * TILE, lo * 4u,
+                          lds_offset(&sm.kring[u % KR][w][0]));
+            } else if constexpr (KSRC == KSRC_PLANE) {
+                k4 = k2;
+            }
             if constexpr (STORED) { pr = pr2; er = er2; }
             off = off2;
         }
@@ -1235,7 +1274,8 @@ __device__ inline void sweep_tile_dir(const SweepArgs& a, int64_t tile, bool wit
 template <class ST, class MT, class AT, int KSRC, int GK, int D, int SER>
 __global__ __launch_bounds__(WG) void k_sweep_dir(SweepArgs a, const uint32_t* __restrict__ list, int t) {
     using DT = DirTypes<ST, MT, AT, D, SER>;
-    __shared__ DirSmem<typename DT::XT, typename DT::LT, AT, typename DT::RT, DT::NRL, KSRC == KSRC_RECOMPUTE> sm;
+    __shared__ DirSmem<typename DT::XT, typename DT::LT, AT, typename DT::RT, DT::NRL, KSRC == KSRC_RECOMPUTE,
+                       (KSRC == KSRC_PLANE && D >= 1 && std::is_same<ST, float>::value) ? KRING : 0> sm;
     if (a.st->done) return;
     const uint32_t e = list[blockIdx.x];
     const int64_t tile = (int64_t)(e & GE_TILE);
