@@ -510,6 +510,15 @@ __device__ inline void wave_lds_sync() {
 
 // ------------------------------------------------------------------ sweep --
 
+// Sums of one tile's messages: the row sums of node `threadIdx.x` of the row
+// block, and the column sums of the lane's four columns (every row group of
+// a wave holds the same values).
+template <class AT>
+struct TileSums {
+    AT rp, re;
+    AT cp[4], ce[4];
+};
+
 // Stores one partial sum of a tile: in FP32 when the plan keeps its partials
 // in FP32 (the FP32-message form, whose tile sums are FP32 sums rounded once
 // more here), else in the aggregate type.
@@ -557,7 +566,7 @@ struct MsgT {
 // nothing, a middle level costs four operations per direction (two with
 // G = u).
 template <class ST, class MT, class AT, int KSRC, int GK, int D, bool FIRST, int SER>
-__device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top) {
+__device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top, TileSums<AT>* out = nullptr) {
     DevStatus* st = a.st;
     // lower levels: FP32 storage precision; with the series and up to three
     // levels they run in the top level's type (FP64 FMA issues at the FP32
@@ -899,23 +908,108 @@ __device__ inline void sweep_tile(const SweepArgs& a, int64_t tile, int slot_top
 #pragma unroll
     for (int c = 0; c < 4; ++c) { cP[c] = sum_groups(cP[c]); cE[c] = sum_groups(cE[c]); }
     __syncthreads();
+    if (__any(bad) && l == 0) st->bad = 1;
+    const AT rowP = ((AT)rP[0][tid] + (AT)rP[1][tid]) + ((AT)rP[2][tid] + (AT)rP[3][tid]);
+    const AT rowE = ((AT)rE[0][tid] + (AT)rE[1][tid]) + ((AT)rE[2][tid] + (AT)rE[3][tid]);
+    if (out) {
+        out->rp = rowP; out->re = rowE;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) { out->cp[c] = cP[c]; out->ce[c] = cE[c]; }
+        return;
+    }
     const bool p32 = a.part32 != 0;
     const size_t rowslot = ((size_t)tc.I * (NB + 1) + tc.J) * TILE + tid;
-    put_part(a.partP, rowslot, ((AT)rP[0][tid] + (AT)rP[1][tid]) + ((AT)rP[2][tid] + (AT)rP[3][tid]), p32);
-    put_part(a.partE, rowslot, ((AT)rE[0][tid] + (AT)rE[1][tid]) + ((AT)rE[2][tid] + (AT)rE[3][tid]), p32);
+    put_part(a.partP, rowslot, rowP, p32);
+    put_part(a.partE, rowslot, rowE, p32);
     if (g == 0) {
         const int slot = (tc.I < tc.J) ? tc.I : NB;
         const size_t cb = ((size_t)tc.J * (NB + 1) + slot) * TILE + col0;
 #pragma unroll
         for (int c = 0; c < 4; ++c) { put_part(a.partP, cb + c, cP[c], p32); put_part(a.partE, cb + c, cE[c], p32); }
     }
-    if (__any(bad) && l == 0) st->bad = 1;
 }
 
 template <class ST, class MT, class AT, int KSRC, int GK, int D, bool FIRST, int SER>
 __global__ __launch_bounds__(WG) void k_sweep(SweepArgs a) {
     if (a.st->done) return;
     sweep_tile<ST, MT, AT, KSRC, GK, D, FIRST, SER>(a, blockIdx.x, a.slot_top);
+}
+
+// The sweeps chunk_plan selects (a.chunk = 2, single solves and served
+// alike) run over 2 x 2 chunks of tiles; every other sweep takes one tile per
+// workgroup.
+template <class ST, class MT, class AT, int KSRC, int D, int SER>
+constexpr bool chunk_sweep_ok() {
+    return KSRC == KSRC_PLANE && std::is_same<ST, float>::value &&
+           chunk_plan(std::is_same<AT, float>::value || MsgT<ST, MT, AT, SER>::F32, D, SER);
+}
+
+// Synchronous sweep over chunks of C x C tiles (a.chunks: Ic << 16 | Jc,
+// Ic <= Jc; the diagonal chunk holds its tiles with I <= J).  One workgroup
+// per chunk adds each row's sums over the chunk's columns and each column's
+// over its rows before storing them: a chunk stores one partial vector per
+// row block and per column block, where single tiles store two per tile
+// (C = 2 halves the partial-sum bytes, which reach HBM in small write bursts
+// between the K' stream's reads).  The slots of block K (Kc = K / C, NBc =
+// ceil(NB / C)) are those of the single-tile scheme with chunks in place of
+// blocks: s < Kc the column sums of chunk (s, Kc), s = Kc the row sums of the
+// diagonal chunk, Kc < s < NBc the row sums of chunk (Kc, s), s = NBc the
+// column sums of the diagonal chunk.  Sums over a chunk are kept in CT: FP32
+// where the partials are stored in FP32.
+template <class ST, class MT, class AT, int GK, int D, int SER, int C>
+__device__ inline void sweep_chunk(const SweepArgs& a, int Ic, int Jc, int slot_top) {
+    using CT = typename std::conditional<MsgT<ST, MT, AT, SER>::F32, float, AT>::type;
+    const int NB = a.NB, NBc = (NB + C - 1) / C;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, q = l & 15;
+    const int col0 = w * 64 + q * 4;
+    const bool p32 = a.part32 != 0;
+    // row sums per row block of the chunk, in LDS (each thread its own row);
+    // the column sums stay in registers
+    __shared__ CT rs[C][2][TILE];
+#pragma unroll
+    for (int ii = 0; ii < C; ++ii) { rs[ii][0][tid] = 0; rs[ii][1][tid] = 0; }
+    bool first = true;
+    // one copy of the tile code (loops not unrolled)
+#pragma unroll 1
+    for (int jj = 0; jj < C; ++jj) {
+        const int J = Jc * C + jj;
+        if (J >= NB) break;
+        CT csP[4] = {0, 0, 0, 0}, csE[4] = {0, 0, 0, 0};
+#pragma unroll 1
+        for (int ii = 0; ii < C; ++ii) {
+            const int I = Ic * C + ii;
+            if (I > J) break;          // (I >= NB implies I > J)
+            if (!first) __syncthreads();
+            first = false;
+            TileSums<AT> o;
+            sweep_tile<ST, MT, AT, KSRC_PLANE, GK, D, false, SER>(a, tile_index(I, J, NB), slot_top, &o);
+            rs[ii][0][tid] += (CT)o.rp;
+            rs[ii][1][tid] += (CT)o.re;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) { csP[c] += (CT)o.cp[c]; csE[c] += (CT)o.ce[c]; }
+        }
+        if (g == 0) {
+            const int slot = (Ic < Jc) ? Ic : NBc;
+            const size_t cb = ((size_t)J * (NBc + 1) + slot) * TILE + col0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) { put_part(a.partP, cb + c, (AT)csP[c], p32); put_part(a.partE, cb + c, (AT)csE[c], p32); }
+        }
+    }
+#pragma unroll
+    for (int ii = 0; ii < C; ++ii) {
+        const int I = Ic * C + ii;
+        if (I >= NB) break;
+        const size_t o = ((size_t)I * (NBc + 1) + Jc) * TILE + tid;
+        put_part(a.partP, o, (AT)rs[ii][0][tid], p32);
+        put_part(a.partE, o, (AT)rs[ii][1][tid], p32);
+    }
+}
+
+template <class ST, class MT, class AT, int GK, int D, int SER, int C>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_sweep_chunk(SweepArgs a) {
+    if (a.st->done) return;
+    const uint32_t cc = a.chunks[blockIdx.x];
+    sweep_chunk<ST, MT, AT, GK, D, SER, C>(a, (int)(cc >> 16), (int)(cc & 0xFFFFu), a.slot_top);
 }
 
 // Stateless sweep with K' recomputed per band: the Gram fragments, the
@@ -1334,6 +1428,22 @@ __global__ __launch_bounds__(WG) void k_sweep_batched(const ReqDesc* __restrict_
     }
 }
 
+// The plans whose single solve runs over 2 x 2 chunks of tiles take the same
+// chunks here (items (request, Ic << 16 | Jc)), so that both sum in the same
+// order.
+template <class ST, class MT, class AT, int D, int SER>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_sweep_batched_chunk(
+    const ReqDesc* __restrict__ reqs, const uint2* __restrict__ items, int nitems) {
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const uint2 w = items[it];
+        const ReqDesc& rd = reqs[w.x];
+        const DevStatus* st = rd.sw.st;
+        if (st->done) continue;
+        sweep_chunk<ST, MT, AT, GRAM_F32, D, SER, 2>(rd.sw, (int)(w.y >> 16), (int)(w.y & 0xFFFFu), st->t % rd.sw.R);
+        __syncthreads();
+    }
+}
+
 // Run-time (levels, reciprocal form) of a stateless launch to the
 // compile-time pair (D, SER): exact reciprocals up to 8 levels, the series
 // (one- or two-term top level) up to 6.  Every pair is its own
@@ -1358,6 +1468,8 @@ inline void served_d(bool grouped, const ReqDesc* reqs, const uint2* items, int 
     const int g = std::max(1, std::min(n, 2048));
     if (grouped)
         hipLaunchKernelGGL((k_sweep_dir_batched<ST, MT, AT, D, SER>), dim3(g), dim3(WG), 0, s, reqs, items, n);
+    else if constexpr (chunk_sweep_ok<ST, MT, AT, KSRC_PLANE, D, SER>())
+        hipLaunchKernelGGL((k_sweep_batched_chunk<ST, MT, AT, D, SER>), dim3(g), dim3(WG), 0, s, reqs, items, n);
     else
         hipLaunchKernelGGL((k_sweep_batched<ST, MT, AT, D, SER>), dim3(g), dim3(WG), 0, s, reqs, items, n);
 }
@@ -1390,19 +1502,30 @@ inline void launch_ev(K kern, dim3 g, dim3 b, hipStream_t s, hipEvent_t e0, hipE
 }
 
 // ---- sweep dispatch: precision x K' source x Gram kind x depth x first x series
+
 template <class ST, class MT, class AT, int KSRC, int GK, int D, int SER>
-inline void sweep_d(bool first, const SweepArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+inline hipError_t sweep_d(bool first, const SweepArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const dim3 g((unsigned)a.ntiles), blk(WG);
+    if (a.chunk > 1) {
+        if constexpr (chunk_sweep_ok<ST, MT, AT, KSRC, D, SER>()) {
+            if (a.chunk != 2 || a.chunks == nullptr || a.nchunks <= 0) return hipErrorInvalidValue;
+            launch_ev(k_sweep_chunk<ST, MT, AT, GK, D, SER, 2>, dim3((unsigned)a.nchunks), blk, s, e0, e1, a);
+            return hipSuccess;
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     if constexpr (D == 0) {
         if (first) {
             launch_ev(k_sweep<ST, MT, AT, KSRC, GK, D, true, 0>, g, blk, s, e0, e1, a);
-            return;
+            return hipSuccess;
         }
     }
     if constexpr (KSRC == KSRC_RECOMPUTE && D >= 1)
         launch_ev(k_sweep_rc<ST, MT, AT, GK, D, SER>, g, blk, s, e0, e1, a);
     else
         launch_ev(k_sweep<ST, MT, AT, KSRC, GK, D, false, SER>, g, blk, s, e0, e1, a);
+    return hipSuccess;
 }
 
 // `levels` = 0: stored edge state; >= 1: stateless with exactly that many
@@ -1412,13 +1535,15 @@ template <class ST, class MT, class AT, int KSRC, int GK>
 inline hipError_t sweep_depth(int levels, bool first, int ser, const SweepArgs& a, hipStream_t s, hipEvent_t e0,
                               hipEvent_t e1) {
     if (levels == 0) {
-        sweep_d<ST, MT, AT, KSRC, GK, 0, 0>(first, a, s, e0, e1);
-        return hipGetLastError();
+        const hipError_t e = sweep_d<ST, MT, AT, KSRC, GK, 0, 0>(first, a, s, e0, e1);
+        return e != hipSuccess ? e : hipGetLastError();
     }
+    hipError_t ed = hipSuccess;
     const hipError_t e = with_stateless(levels, ser, [&](auto L_, auto S_) {
-        sweep_d<ST, MT, AT, KSRC, GK, decltype(L_)::value, decltype(S_)::value>(first, a, s, e0, e1);
+        ed = sweep_d<ST, MT, AT, KSRC, GK, decltype(L_)::value, decltype(S_)::value>(first, a, s, e0, e1);
     });
-    return e != hipSuccess ? e : hipGetLastError();
+    if (e != hipSuccess) return e;
+    return ed != hipSuccess ? ed : hipGetLastError();
 }
 
 // ---- grouped schedule dispatch: one group visit

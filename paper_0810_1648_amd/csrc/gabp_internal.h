@@ -105,6 +105,14 @@ inline int stateless_series_form(int prec, int levels, double rr) {
 // row block (BWD; clear: into the column block), bit 30 = both blocks lie in
 // the visited group, low 30 bits = tile index.
 constexpr uint32_t GE_BWD = 0x80000000u, GE_WITHIN = 0x40000000u, GE_TILE = 0x3FFFFFFFu;
+// Synchronous stateless sweeps over an FP32 K' plane with FP32 partial sums
+// (FP32 plan, or FP32 messages) run over 2 x 2 chunks of tiles where the
+// chunk's sums fit beside the message recursion in the registers of four
+// waves per SIMD: one level, two with series reciprocals, three with series
+// form 3.
+__host__ __device__ constexpr bool chunk_plan(bool fp32_partials, int levels, int ser) {
+    return fp32_partials && (levels == 1 || (levels == 2 && ser > 0) || (levels == 3 && ser == 3));
+}
 // Storage index of tile (I, J), I <= J: row-major over the upper triangle.
 __host__ __device__ inline int64_t tile_index(int I, int J, int NB) {
     return (int64_t)I * NB - (int64_t)I * (I - 1) / 2 + (J - I);
@@ -155,7 +163,11 @@ struct SweepArgs {
     int64_t NPAD;
     int R, slot_top, levels;      // ring depth, top slot, stateless levels in use
     int part32;                   // 1: partial sums stored in FP32 (FP32-message plans)
-    void *partP, *partE;          // [NB][NB+1][TILE] partial sums (aggregate type, or FP32)
+    void *partP, *partE;          // [NB][NB+1][TILE] partial sums (aggregate type, or FP32); chunked
+                                  // sweeps: [NB][NBc+1][TILE], NBc = ceil(NB / chunk)
+    const uint32_t* chunks;       // chunked synchronous sweep: Ic << 16 | Jc, Ic <= Jc < NBc (row-major)
+    int64_t nchunks;
+    int chunk;                    // tiles per chunk side (0 or 1: one tile per workgroup)
     DevStatus* st;
     Features F;                   // KSRC_RECOMPUTE
     KernelParams kp;

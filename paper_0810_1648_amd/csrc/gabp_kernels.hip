@@ -697,12 +697,14 @@ __global__ __launch_bounds__(WG) void k_finalize_batched(const ReqDesc* __restri
         const int64_t wslot = (int64_t)((rd.sw.st->t + 1) % rd.sw.R) * rd.sw.NPAD;
         AT* const Pt = static_cast<AT*>(const_cast<void*>(rd.sw.HP)) + wslot;
         AT* const S = static_cast<AT*>(const_cast<void*>(rd.sw.HS)) + wslot;
+        // slots per block: NB + 1, or NBc + 1 after a sweep over chunks
+        const int ns = (rd.sw.chunk > 1) ? (rd.sw.NB + rd.sw.chunk - 1) / rd.sw.chunk : rd.sw.NB;
         if (rd.sw.part32)
-            finalize_block<AT, float>((int64_t)w.y, rd.N, rd.sw.NB, static_cast<const float*>(rd.sw.partP),
+            finalize_block<AT, float>((int64_t)w.y, rd.N, ns, static_cast<const float*>(rd.sw.partP),
                                       static_cast<const float*>(rd.sw.partE), rd.Adiag, rd.y, Pt, S, rd.alpha,
                                       rd.blk_delta, rd.blk_amax, rd.sw.st, 0.0, nullptr, nullptr);
         else
-            finalize_block<AT, AT>((int64_t)w.y, rd.N, rd.sw.NB, static_cast<const AT*>(rd.sw.partP),
+            finalize_block<AT, AT>((int64_t)w.y, rd.N, ns, static_cast<const AT*>(rd.sw.partP),
                                    static_cast<const AT*>(rd.sw.partE), rd.Adiag, rd.y, Pt, S, rd.alpha,
                                    rd.blk_delta, rd.blk_amax, rd.sw.st, 0.0, nullptr, nullptr);
         __syncthreads();

@@ -141,6 +141,7 @@ struct Req {
     int32_t refused = 0; // set up but refused (gabp_status): no plan without a bound
     int levels = 0;      // 0: stored pair records; >= 1: stateless levels
     int ser = 0;         // stateless reciprocals: 0 exact, 1 / 2 series (top-level terms)
+    bool chunked = false;  // synchronous sweeps over 2 x 2 chunks of tiles
     double rho = 0.0;    // contraction bound
     // grouped schedule: G groups of whole block rows, the group the next step
     // visits, the single-direction list entries of every group (into gent
@@ -380,6 +381,10 @@ hipError_t setup_request(gabp_server* S, Req& r) {
     d.sw.slot_top = 0;
     d.sw.levels = r.levels;
     d.sw.part32 = (r.prec == PREC_MIXED && stateless && r.ser > 0) ? 1 : 0;   // as in a single solve
+    // synchronous stateless sweeps with FP32 partial sums run over 2 x 2
+    // chunks of tiles, as in a single solve (items (request, Ic << 16 | Jc))
+    d.sw.chunk = (!r.grouped && stateless && chunk_plan(r.prec == PREC_FP32 || d.sw.part32, r.levels, r.ser)) ? 2 : 1;
+    r.chunked = d.sw.chunk > 1;
     d.sw.partP = P(B_PARTP); d.sw.partE = P(B_PARTE);
     d.sw.st = (DevStatus*)P(B_STATUS);
     d.sw.F = F;
@@ -428,13 +433,26 @@ hipError_t rebuild_lists(gabp_server* S) {
         for (int k : G.slot_list) S->h_slots[na++] = k;
         G.ntiles = 0;
         if (G.grouped) continue;   // per-step items (build_step)
+        // items: (request, tile), or (request, Ic << 16 | Jc) for a request
+        // whose sweeps run over 2 x 2 chunks of tiles
+        auto nitems = [](const Req* r) {
+            const int64_t nbc = (r->NB + 1) / 2;
+            return r->chunked ? nbc * (nbc + 1) / 2 : r->nt;
+        };
         size_t nt = 0;
-        for (int k : G.slot_list) nt += (size_t)S->slots[k]->nt;
+        for (int k : G.slot_list) nt += (size_t)nitems(S->slots[k]);
         if ((e = grow(G.d_tiles, G.h_tiles, G.cap_tiles, std::max<size_t>(nt, 1))) != hipSuccess) return e;
         size_t it = 0;
         for (int k : G.slot_list) {
             Req* r = S->slots[k];
-            for (int64_t t = 0; t < r->nt; ++t) G.h_tiles[it++] = make_uint2((unsigned)k, (unsigned)t);
+            if (r->chunked) {
+                const int nbc = (r->NB + 1) / 2;
+                for (int ic = 0; ic < nbc; ++ic)
+                    for (int jc = ic; jc < nbc; ++jc)
+                        G.h_tiles[it++] = make_uint2((unsigned)k, ((unsigned)ic << 16) | (unsigned)jc);
+            } else {
+                for (int64_t t = 0; t < r->nt; ++t) G.h_tiles[it++] = make_uint2((unsigned)k, (unsigned)t);
+            }
         }
         G.ntiles = (int)it;
         if (it && (e = hipMemcpyAsync(G.d_tiles, G.h_tiles, it * sizeof(uint2), hipMemcpyHostToDevice, S->stream)) != hipSuccess)

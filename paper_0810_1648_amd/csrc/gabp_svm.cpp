@@ -104,6 +104,7 @@ struct gabp_svm {
     DevBuf tiles, Kp, Pf, Pb, Ef, Eb, partP, partE, Xin, yd, mean, xs32, xhi, xlo, xlo2, x64, nrm, kdiag, rowmax, rsum,
         Adiag, Pt, S, alpha_d, blk1, blk2, one, status_d, trace_d, flag, tmp, Kin, q_rows, q_cols,
         q_out, glist, HI, HM,
+        chunks,                  // 2 x 2 tile chunks of the synchronous FP32-partial sweep
         xaug,                    // training rows of the augmented decision function
         parena;                  // working memory of gabp_svm_predict (reused)
     int aug_kind = -1, aug_mp = 0;
@@ -118,12 +119,12 @@ struct gabp_svm {
     bool resid_valid = false;
     double resid[3] = {0.0, 0.0, 0.0};
 
-    DevBuf* all[64] = {&tiles, &Kp, &Pf, &Pb, &Ef, &Eb, &partP, &partE, &Xin, &yd, &mean,
+    DevBuf* all[72] = {&tiles, &Kp, &Pf, &Pb, &Ef, &Eb, &partP, &partE, &Xin, &yd, &mean,
                        &xs32, &xhi, &xlo, &xlo2, &x64, &nrm, &kdiag, &rowmax, &rsum, &Adiag, &Pt, &S, &alpha_d,
                        &blk1, &blk2, &one, &status_d, &trace_d, &flag, &tmp, &Kin, &q_rows,
                        &q_cols, &q_out, &glist, &sp_cnt, &sp_toff, &sp_keys, &sp_keys2, &sp_kv, &sp_kv2,
                        &sp_ei, &sp_ej, &sp_degi, &sp_degj, &sp_offi, &sp_offj, &sp_ids, &sp_perm, &sp_tmp,
-                       &sp_order, &sp_Xp, &sp_cent, &sp_rad, &sp_keep, &sp_tsel, &sp_nsel, &sp_xb, &HI, &HM, &xaug, &parena, nullptr};
+                       &sp_order, &sp_Xp, &sp_cent, &sp_rad, &sp_keep, &sp_tsel, &sp_nsel, &sp_xb, &HI, &HM, &chunks, &xaug, &parena, nullptr};
     size_t held() const {
         size_t b = 0;
         for (int k = 0; all[k]; ++k) b += all[k]->bytes;
@@ -279,6 +280,9 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     hipError_t ae = hipSuccess;
     auto A = [&](DevBuf& b, size_t n) { if (ae == hipSuccess) ae = b.ensure(n); };
     A(h->tiles, (size_t)nt * 4);
+    const int NBc = (NB + 1) / 2;
+    const int64_t nchunks = (int64_t)NBc * (NBc + 1) / 2;
+    A(h->chunks, (size_t)nchunks * 4);
     if (kmat) A(h->Kp, plane); else h->Kp.release();
     // pair-record planes: allocated now for a stored plan, on demand after the probe
     if (stored && !probe) { A(h->Pf, plane); A(h->Pb, plane); A(h->Ef, plane); A(h->Eb, plane); }
@@ -382,6 +386,7 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
 
     // ---- K' tiles (materialised plan)
     HIPCHK(h, launch_fill_tiles(h->tiles.as<uint32_t>(), NB, s));
+    HIPCHK(h, launch_fill_tiles(h->chunks.as<uint32_t>(), NBc, s));
     // FP32-stored K' is built together with the row-sum partials (fused_sums)
     const bool fused_sums = rbf && kmat && gram != GRAM_F64;
     if (rbf) {
@@ -503,6 +508,15 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     // messages in FP32; its partial sums are kept in FP32 (half the traffic)
     sa.part32 = (prec == PREC_MIXED && !cur_stored && ser > 0) ? 1 : 0;
     sa.partP = h->partP.p; sa.partE = h->partE.p;
+    // synchronous stateless sweeps over an FP32 K' plane with FP32 partial
+    // sums run over 2 x 2 chunks of tiles (half the partial-sum stores); the
+    // finalize then reads NBc + 1 slots per block
+    const bool chunked = p.schedule != GABP_SCHED_GROUPED && kmat && !cur_stored &&
+                         chunk_plan(prec == PREC_FP32 || sa.part32, depth, ser);
+    sa.chunks = h->chunks.as<uint32_t>();
+    sa.nchunks = nchunks;
+    sa.chunk = chunked ? 2 : 1;
+    const int nslot = chunked ? NBc : NB;
     sa.st = st;
     sa.F = F;
     sa.kp = kp;
@@ -579,7 +593,7 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
             // the events take the sweep dispatch's own timestamps
             HIPCHK(h, launch_sweep(prec, ksrc, gram, sa.levels, t == 0, ser, sa, s,
                                    p.time_sweeps ? sev[2 * slot] : nullptr, p.time_sweeps ? sev[2 * slot + 1] : nullptr));
-            HIPCHK(h, launch_finalize(prec, N, NB, h->partP.p, h->partE.p, h->Adiag.as<double>(),
+            HIPCHK(h, launch_finalize(prec, N, nslot, h->partP.p, h->partE.p, h->Adiag.as<double>(),
                                       h->yd.as<float>(), wP, wS, h->alpha_d.as<double>(),
                                       h->blk1.as<double>(), h->blk2.as<double>(), st, s, boxC, wI, wM,
                                       sa.part32));
