@@ -508,8 +508,17 @@ def counter_traffic_kernel(path, name_prefix):
 
 
 # kernel names of the measured sweeps (template arguments: storage, message,
-# aggregate type, K' source, Gram kind, levels, first sweep, series terms)
+# aggregate type, K' source, Gram kind, levels, first sweep, series terms;
+# the chunked sweep: storage, message, aggregate type, Gram kind, levels,
+# series terms, tiles per chunk side)
 TYPES = {"mixed": "float, double, double", "fp32": "float, float, float", "fp64": "double, double, double"}
+
+
+def sweep_label(plan, edge_name, extra=""):
+    """Short description of the sweep kernel a plan runs over the K' plane."""
+    if plan.get("tile_chunk", 1) > 1:
+        return f"k_sweep_chunk ({edge_name}, 2 x 2 tile chunks, K' materialised{extra})"
+    return f"k_sweep ({edge_name}, K' materialised{extra})"
 
 
 def sweep_kernel_name(precision, plan):
@@ -517,6 +526,9 @@ def sweep_kernel_name(precision, plan):
     the materialised K' (template arguments as above)."""
     if plan["edge_state"] == 1:   # stored pair records (sweeps after the first)
         return f"gabp::k_sweep<{TYPES[precision]}, 0, 0, 0, false, 0>"
+    if plan.get("tile_chunk", 1) > 1:
+        return (f"gabp::k_sweep_chunk<{TYPES[precision]}, 0, {plan['stateless_depth']}, "
+                f"{int(plan['series_reciprocal'])}, {plan['tile_chunk']}>")
     return (f"gabp::k_sweep<{TYPES[precision]}, 0, 0, {plan['stateless_depth']}, false, "
             f"{int(plan['series_reciprocal'])}>")
 
@@ -593,7 +605,7 @@ def main():
     if not recompute:
         # the sweep streams the K' plane (and, with stored records, the four
         # pair-record planes): HBM-bound on its algorithmic bytes
-        roof = hbm_roof(plan, avg_ms, klaunch, f"k_sweep ({edge_name}, K' materialised)", traffic)
+        roof = hbm_roof(plan, avg_ms, klaunch, sweep_label(plan, edge_name), traffic)
     else:
         roof = {"bound": "alu", "kernel": "k_sweep_rc (stateless, K' recomputed)", "traffic": None}
     if stateless:
@@ -656,7 +668,7 @@ def main():
                   "sweeps_per_solve": linfo["sweeps_per_solve"], "reason": linfo["reason"], "edge_state": ledge,
                   "stateless_depth": lp["stateless_depth"], "err_vs_oracle": rel_err(linfo["alpha"], r1["alpha"] if r1 is not None else None),
                   "certificate": linfo["certificate"],
-                  "roofline": hbm_roof(lp, lk / max(ll, 1), ll, f"k_sweep ({ledge}, K' materialised, FP32)", None)}
+                  "roofline": hbm_roof(lp, lk / max(ll, 1), ll, sweep_label(lp, ledge, ", FP32"), None)}
         print(f"[bench] letter: {ls} sweeps in {lw:.3f} s", file=sys.stderr, flush=True)
         del X1, y1
 

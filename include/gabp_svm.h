@@ -237,7 +237,13 @@ typedef struct gabp_plan {
                                   for (the truncation stays below the message
                                   precision); 0: an explicit stateless_depth
                                   below it (a truncated recursion) */
-    int32_t reserved;
+    int32_t tile_chunk;        /* synchronous sweep: 2 = one workgroup per
+                                  2 x 2 chunk of tiles, whose row and column
+                                  sums are added over the chunk before they
+                                  are stored (FP32 partial sums; one level,
+                                  two with series reciprocals, three with
+                                  series form 3); 1 = one tile per workgroup;
+                                  0 = the sparsified kernel (no tiles) */
 } gabp_plan;
 
 /* Query selectors for gabp_svm_query: dst type and size in brackets. */

@@ -682,6 +682,7 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     h->plan.stateless_bounded = stored ? 1 : (depth >= dneed ? 1 : 0);
     h->plan.stateless_rho = rho;
     h->plan.series_reciprocal = ser;
+    h->plan.tile_chunk = chunked ? 2 : 1;
     h->plan.sched_groups = grouped ? G : 0;
     h->plan.n_blocks = NB;
     h->plan.n_tiles = nt;

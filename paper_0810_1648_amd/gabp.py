@@ -64,7 +64,7 @@ class Plan(ct.Structure):
                 ("n_blocks", ct.c_int64), ("n_tiles", ct.c_int64), ("device_bytes", ct.c_uint64),
                 ("alg_bytes_per_sweep", ct.c_uint64), ("alg_bytes_per_pair", ct.c_double),
                 ("stateless_rho", ct.c_double), ("series_reciprocal", ct.c_int32), ("sched_groups", ct.c_int32),
-                ("n_edges", ct.c_int64), ("stateless_bounded", ct.c_int32), ("reserved", ct.c_int32)]
+                ("n_edges", ct.c_int64), ("stateless_bounded", ct.c_int32), ("tile_chunk", ct.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
