@@ -77,7 +77,7 @@ class GabpError(RuntimeError):
 
 
 _lib = None
-ABI_VERSION = 7     # GABP_ABI_VERSION the structures above describe
+ABI_VERSION = 8     # GABP_ABI_VERSION the structures above describe
 
 
 def lib():

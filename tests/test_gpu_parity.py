@@ -271,6 +271,46 @@ def test_recompute_matches_materialised(torch):
         assert err <= 1e-6
 
 
+def _chunk_rule(prec, levels, ser):
+    # the synchronous stateless sweeps that run over 2 x 2 chunks of tiles:
+    # FP32 partial sums (FP32, or MIXED with series reciprocals) and a
+    # recursion small enough for the chunk's sums
+    fp32_partials = prec == "fp32" or (prec == "mixed" and ser > 0)
+    return fp32_partials and (levels == 1 or (levels == 2 and ser > 0) or (levels == 3 and ser == 3))
+
+
+@pytest.mark.parametrize("prec,n,depth", [("mixed", 200, 3), ("mixed", 700, 3), ("fp32", 1100, 2),
+                                          ("mixed", 1500, 1), ("fp32", 2900, 3)])
+def test_chunked_sweep_matches_oracle_trajectory(torch, prec, n, depth):
+    # one to twelve blocks (odd and even counts, a ragged last block): the
+    # sweep over 2 x 2 chunks of tiles follows the oracle's stateless
+    # recursion sweep by sweep
+    wl = inputs.make_workload("covertype", n=n, seed=31)
+    A, b = R.svm_system(wl.X, wl.y, wl.gamma, wl.C, wl.lam, delta=wl.delta)
+    ref = R.gabp_solve_stateless(A, b, depth=depth, sweeps=12)
+    for t in (1, depth, depth + 1, 12):
+        s, st = run(torch, wl, precision=prec, edge_state="stateless", kstore="materialise", stateless_depth=depth,
+                    max_sweeps=t, tol_abs=0.0, tol_rel=0.0, stagnation_window=0)
+        p = s.plan()
+        assert p["tile_chunk"] == (2 if _chunk_rule(prec, depth, p["series_reciprocal"]) else 1), p
+        assert s.sweeps() == t
+        err = _rel(s.alpha(), ref[t - 1])
+        assert err <= TOL, (prec, n, depth, t, p["tile_chunk"], err)
+    print(f"{prec} n={n} depth={depth}: series form {p['series_reciprocal']}, tile chunk {p['tile_chunk']}")
+
+
+def test_chunking_only_where_the_rule_allows(torch):
+    # FP64 plans, stored pair records and the grouped schedule keep one tile
+    # per workgroup
+    wl = inputs.make_workload("covertype", n=900, seed=32)
+    for kw in (dict(precision="fp64", edge_state="stateless", stateless_depth=2),
+               dict(precision="mixed", edge_state="stored"),
+               dict(precision="mixed", edge_state="stateless", stateless_depth=2, schedule="grouped"),
+               dict(precision="mixed", edge_state="stateless", stateless_depth=4)):
+        s, st = run(torch, wl, kstore="materialise", **kw)
+        assert s.plan()["tile_chunk"] == 1, (kw, s.plan())
+
+
 @pytest.mark.parametrize("depth", [1, 3, 6])
 def test_stateless_matches_oracle_truncated_recursion(torch, depth):
     wl = inputs.make_workload("tiny", n=600, seed=13)
