@@ -190,6 +190,16 @@ typedef struct gabp_svm_params {
                                   hint below the true number costs a second
                                   pass; the graph is the same either way */
     double sparse_tau;         /* RBF_SPARSE: kernel threshold in (0, 1] */
+    int32_t tile_chunk;        /* synchronous stateless sweeps over the K'
+                                  plane with FP32 partial sums (FP32, or MIXED
+                                  with series reciprocals; one level, two with
+                                  series reciprocals, three with series form
+                                  3): 0 = 2 x 2 chunks of tiles per workgroup
+                                  when there are at least 4,096 chunks, else
+                                  one tile; 1 = one tile per workgroup; 2 =
+                                  2 x 2 chunks at any size.  Other plans take
+                                  one tile per workgroup (gabp_plan.tile_chunk
+                                  reports the choice) */
 } gabp_svm_params;
 
 /* Per-phase device times of the last solve, in milliseconds (HIP events on

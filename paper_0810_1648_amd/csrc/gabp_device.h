@@ -552,7 +552,9 @@ struct MsgT {
 //      slot from before sweep 0 holds P~ = inf, S = 0 and yields exactly zero
 //      messages), lower levels in LT (see below);
 //   FIRST: the stored planes are all zero (sweep 1) and are not read.
-// Work of one tile.  SER (stateless only; 0 = exact reciprocals): the
+// Work of one tile: its row and column sums go to the tile's partial slots,
+// or, with `out`, to the caller (a chunk adds them up first).  SER (stateless
+// only; 0 = exact reciprocals): the
 // reciprocals of the cavity precisions Q = P~ (1 - e), e = P_reverse / P~,
 // are formed from the per-node u = 1/P~ by the series
 // 1/Q = (1 + e + e^2 + ...) u, one term at the lower levels and SER terms at
@@ -1428,9 +1430,10 @@ __global__ __launch_bounds__(WG) void k_sweep_batched(const ReqDesc* __restrict_
     }
 }
 
-// The plans whose single solve runs over 2 x 2 chunks of tiles take the same
-// chunks here (items (request, Ic << 16 | Jc)), so that both sum in the same
-// order.
+// Launch groups whose plan may run over 2 x 2 chunks of tiles: a request
+// whose single solve takes chunks (sw.chunk = 2) takes the same chunks here
+// (items (request, Ic << 16 | Jc)), so that both sum in the same order; the
+// others take whole tiles (items (request, tile)).
 template <class ST, class MT, class AT, int D, int SER>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_sweep_batched_chunk(
     const ReqDesc* __restrict__ reqs, const uint2* __restrict__ items, int nitems) {
@@ -1439,7 +1442,10 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 8))) void
         const ReqDesc& rd = reqs[w.x];
         const DevStatus* st = rd.sw.st;
         if (st->done) continue;
-        sweep_chunk<ST, MT, AT, GRAM_F32, D, SER, 2>(rd.sw, (int)(w.y >> 16), (int)(w.y & 0xFFFFu), st->t % rd.sw.R);
+        if (rd.sw.chunk > 1)
+            sweep_chunk<ST, MT, AT, GRAM_F32, D, SER, 2>(rd.sw, (int)(w.y >> 16), (int)(w.y & 0xFFFFu), st->t % rd.sw.R);
+        else
+            sweep_tile<ST, MT, AT, KSRC_PLANE, GRAM_F32, D, false, SER>(rd.sw, (int64_t)w.y, st->t % rd.sw.R);
         __syncthreads();
     }
 }

@@ -113,6 +113,16 @@ constexpr uint32_t GE_BWD = 0x80000000u, GE_WITHIN = 0x40000000u, GE_TILE = 0x3F
 __host__ __device__ constexpr bool chunk_plan(bool fp32_partials, int levels, int ser) {
     return fp32_partials && (levels == 1 || (levels == 2 && ser > 0) || (levels == 3 && ser == 3));
 }
+// The choice for one solve (`mode`: the tile_chunk parameter): automatic
+// (0) takes chunks only with at least four per workgroup slot of the GPU (256
+// CUs x 4 workgroups), since fewer balance worse than single tiles; 1 never,
+// 2 wherever the plan allows.
+constexpr int64_t kChunkMin = 4096;
+inline bool chunk_sweep(bool fp32_partials, int levels, int ser, int NB, int mode) {
+    const int64_t nbc = (NB + 1) / 2;
+    if (mode == 1 || !chunk_plan(fp32_partials, levels, ser)) return false;
+    return mode == 2 || nbc * (nbc + 1) / 2 >= kChunkMin;
+}
 // Storage index of tile (I, J), I <= J: row-major over the upper triangle.
 __host__ __device__ inline int64_t tile_index(int I, int J, int NB) {
     return (int64_t)I * NB - (int64_t)I * (I - 1) / 2 + (J - I);

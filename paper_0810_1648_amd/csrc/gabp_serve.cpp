@@ -383,7 +383,8 @@ hipError_t setup_request(gabp_server* S, Req& r) {
     d.sw.part32 = (r.prec == PREC_MIXED && stateless && r.ser > 0) ? 1 : 0;   // as in a single solve
     // synchronous stateless sweeps with FP32 partial sums run over 2 x 2
     // chunks of tiles, as in a single solve (items (request, Ic << 16 | Jc))
-    d.sw.chunk = (!r.grouped && stateless && chunk_plan(r.prec == PREC_FP32 || d.sw.part32, r.levels, r.ser)) ? 2 : 1;
+    d.sw.chunk = (!r.grouped && stateless && chunk_sweep(r.prec == PREC_FP32 || d.sw.part32, r.levels, r.ser, r.NB,
+                                                               r.p.tile_chunk)) ? 2 : 1;
     r.chunked = d.sw.chunk > 1;
     d.sw.partP = P(B_PARTP); d.sw.partE = P(B_PARTE);
     d.sw.st = (DevStatus*)P(B_STATUS);

@@ -81,6 +81,7 @@ gabp_status check_params(const gabp_svm_params* p, std::string& why) {
     if (p->stateless_depth < 0 || p->stateless_depth > 8) { why = "stateless_depth must be in [0, 8]"; return GABP_E_INVALID; }
     if (p->schedule < 0 || p->schedule > 1) { why = "unknown schedule"; return GABP_E_INVALID; }
     if (p->sched_groups < 0 || p->sched_groups > 4096) { why = "sched_groups must be in [0, 4096]"; return GABP_E_INVALID; }
+    if (p->tile_chunk < 0 || p->tile_chunk > 2) { why = "tile_chunk must be 0, 1 or 2"; return GABP_E_INVALID; }
     return GABP_OK;
 }
 }  // namespace gabp
@@ -512,7 +513,7 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     // sums run over 2 x 2 chunks of tiles (half the partial-sum stores); the
     // finalize then reads NBc + 1 slots per block
     const bool chunked = p.schedule != GABP_SCHED_GROUPED && kmat && !cur_stored &&
-                         chunk_plan(prec == PREC_FP32 || sa.part32, depth, ser);
+                         chunk_sweep(prec == PREC_FP32 || sa.part32, depth, ser, NB, p.tile_chunk);
     sa.chunks = h->chunks.as<uint32_t>();
     sa.nchunks = nchunks;
     sa.chunk = chunked ? 2 : 1;
@@ -1164,6 +1165,7 @@ void gabp_svm_params_default(gabp_svm_params* p) {
     p->sched_groups = 0;
     p->sparse_edges_hint = 0;
     p->sparse_tau = 1e-3;
+    p->tile_chunk = 0;
 }
 
 gabp_status gabp_svm_create(const gabp_svm_params* params, gabp_svm** out) {

@@ -44,7 +44,7 @@ class Params(ct.Structure):
         ("edge_state", ct.c_int32), ("gram", ct.c_int32), ("stateless_depth", ct.c_int32),
         ("device", ct.c_int32), ("hbm_budget_bytes", ct.c_uint64), ("time_sweeps", ct.c_int32),
         ("schedule", ct.c_int32), ("sched_groups", ct.c_int32), ("sparse_edges_hint", ct.c_int32),
-        ("sparse_tau", ct.c_double),
+        ("sparse_tau", ct.c_double), ("tile_chunk", ct.c_int32),
     ]
 
 

@@ -283,14 +283,15 @@ def _chunk_rule(prec, levels, ser):
                                           ("mixed", 1500, 1), ("fp32", 2900, 3)])
 def test_chunked_sweep_matches_oracle_trajectory(torch, prec, n, depth):
     # one to twelve blocks (odd and even counts, a ragged last block): the
-    # sweep over 2 x 2 chunks of tiles follows the oracle's stateless
-    # recursion sweep by sweep
+    # sweep over 2 x 2 chunks of tiles (asked for at these sizes, which take
+    # single tiles by default) follows the oracle's stateless recursion sweep
+    # by sweep
     wl = inputs.make_workload("covertype", n=n, seed=31)
     A, b = R.svm_system(wl.X, wl.y, wl.gamma, wl.C, wl.lam, delta=wl.delta)
     ref = R.gabp_solve_stateless(A, b, depth=depth, sweeps=12)
     for t in (1, depth, depth + 1, 12):
         s, st = run(torch, wl, precision=prec, edge_state="stateless", kstore="materialise", stateless_depth=depth,
-                    max_sweeps=t, tol_abs=0.0, tol_rel=0.0, stagnation_window=0)
+                    max_sweeps=t, tol_abs=0.0, tol_rel=0.0, stagnation_window=0, tile_chunk=2)
         p = s.plan()
         assert p["tile_chunk"] == (2 if _chunk_rule(prec, depth, p["series_reciprocal"]) else 1), p
         assert s.sweeps() == t
@@ -300,15 +301,22 @@ def test_chunked_sweep_matches_oracle_trajectory(torch, prec, n, depth):
 
 
 def test_chunking_only_where_the_rule_allows(torch):
-    # FP64 plans, stored pair records and the grouped schedule keep one tile
-    # per workgroup
+    # FP64 plans, stored pair records, the grouped schedule and deeper
+    # recursions keep one tile per workgroup even when chunks are asked for;
+    # a plan that allows chunks takes them by default only from 4,096 chunks
+    # on (not at 900 points), and never with tile_chunk = 1
     wl = inputs.make_workload("covertype", n=900, seed=32)
-    for kw in (dict(precision="fp64", edge_state="stateless", stateless_depth=2),
-               dict(precision="mixed", edge_state="stored"),
-               dict(precision="mixed", edge_state="stateless", stateless_depth=2, schedule="grouped"),
-               dict(precision="mixed", edge_state="stateless", stateless_depth=4)):
+    for kw in (dict(precision="fp64", edge_state="stateless", stateless_depth=2, tile_chunk=2),
+               dict(precision="mixed", edge_state="stored", tile_chunk=2),
+               dict(precision="mixed", edge_state="stateless", stateless_depth=2, schedule="grouped", tile_chunk=2),
+               dict(precision="mixed", edge_state="stateless", stateless_depth=4, tile_chunk=2),
+               dict(precision="fp32", edge_state="stateless", stateless_depth=1),
+               dict(precision="fp32", edge_state="stateless", stateless_depth=1, tile_chunk=1)):
         s, st = run(torch, wl, kstore="materialise", **kw)
         assert s.plan()["tile_chunk"] == 1, (kw, s.plan())
+    s, st = run(torch, wl, kstore="materialise", precision="fp32", edge_state="stateless", stateless_depth=1,
+                tile_chunk=2)
+    assert s.plan()["tile_chunk"] == 2, s.plan()
 
 
 @pytest.mark.parametrize("depth", [1, 3, 6])

@@ -120,16 +120,27 @@ def test_served_stateless_plans_equal_single(torch):
         X, y = inputs.blobs(n, 16, 7100 + r)
         gamma = [2e-3, 1.0 / 16, 0.5][r % 3]        # from strongly to weakly contracting
         prec = ["fp32", "mixed", "fp64"][(r // 3) % 3]
-        reqs.append((X, y, dict(gamma=gamma, C=1.0, precision=prec, tol_rel=1e-7, kstore="materialise")))
+        # every other request asks for 2 x 2 tile chunks (taken where its plan
+        # allows them), next to requests on single tiles in the same launches
+        reqs.append((X, y, dict(gamma=gamma, C=1.0, precision=prec, tol_rel=1e-7, kstore="materialise",
+                                tile_chunk=2 * (r % 2))))
+    # shallow explicit recursions whose plans allow chunks: one level (FP32),
+    # two levels with series reciprocals (MIXED)
+    for r, (prec, depth) in enumerate((("fp32", 1), ("mixed", 2))):
+        X, y = inputs.blobs([700, 1300][r], 16, 7150 + r)
+        reqs.append((X, y, dict(gamma=2e-3, C=1.0, precision=prec, tol_rel=1e-7, kstore="materialise",
+                                edge_state="stateless", stateless_depth=depth, tile_chunk=2)))
     print(f"[case] stateless serving mix of {len(reqs)} requests", flush=True)
-    single = []
+    single, chunks = [], []
     for X, y, kw in reqs:
         s = gabp.GabpSVM(**kw)
         st = s.solve(X, y)
         single.append((st, s.alpha(), s.sweeps(), s.plan()["stateless_depth"]))
+        chunks.append(s.plan()["tile_chunk"])
         s.close()
     levels = [d for _, _, _, d in single]
-    print("single-solve levels", levels)
+    print("single-solve levels", levels, "tile chunks", chunks)
+    assert 2 in chunks and 1 in chunks
     assert any(d > 0 for d in levels) and len(set(levels)) >= 2
     with gabp.GabpServer(arena_bytes=int(2e9), max_active=6, steps_per_poll=2) as srv:
         tickets = [srv.submit(X, y, **kw) for X, y, kw in reqs]
