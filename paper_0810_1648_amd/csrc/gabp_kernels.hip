@@ -154,6 +154,11 @@ __global__ __launch_bounds__(WG) void k_gram_mfma(Features F, KernelParams kp,
 // 32 x 32 block goes through LDS once: column sums come from the MFMA layout
 // (a lane holds 16 rows of one column), row sums and the 16-byte row stores
 // from the transposed read (eight lanes per row).  All sums in a fixed order.
+// BF16 Gram kinds: the four waves walk the same column blocks, so each
+// block's B fragments are staged once in LDS in fragment order (BStage), the
+// next block's chunks loaded into registers while the current one is
+// multiplied (one barrier per block; the products in the same order as from
+// registers, so K' is the same to the bit).
 template <int KIND, int MP>
 __global__ __launch_bounds__(WG) void k_gram_sums(Features F, KernelParams kp, const uint32_t* __restrict__ tiles,
                                                  float* __restrict__ Kp, int NB, double* __restrict__ psum,
@@ -169,6 +174,21 @@ __global__ __launch_bounds__(WG) void k_gram_sums(Features F, KernelParams kp, c
     __shared__ float blk[4][32][33];
     const int64_t i0 = (int64_t)tc.I * TILE, j0 = (int64_t)tc.J * TILE;
     const int rr = l >> 3, cq = 4 * (l & 7);       // transposed read: row rr + 8 k, columns cq .. cq + 3
+    constexpr bool STG = (KIND != GRAM_F32) && (MP > 0);
+    using BS = BStage<KIND>;
+    constexpr int CH = STG ? BS::NP * (MP / 16) * 64 : 1;                  // 16-byte chunks per block
+    constexpr int PR = (CH + WG - 1) / WG;                                 // per thread
+    __shared__ bf16x8 sb[2][CH];
+    const int ns = F.m_pad / 16, ch = BS::NP * ns * 64;
+    int cur = 0;
+    if constexpr (STG) {
+#pragma unroll
+        for (int i = 0; i < PR; ++i) {
+            const int k = tid + WG * i;
+            if (k < ch) sb[0][BS::dst(ns, k)] = *BS::src(F, j0, ns, k);
+        }
+        __syncthreads();
+    }
 #pragma unroll 1
     for (int pass = 0; pass < 2; ++pass) {
         const int band = w + 4 * pass;
@@ -183,7 +203,22 @@ __global__ __launch_bounds__(WG) void k_gram_sums(Features F, KernelParams kp, c
 #pragma unroll 1
         for (int cb = 0; cb < TILE / 32; ++cb) {
             const int64_t colB = j0 + cb * 32 + l32;
-            const f32x16 acc = fa.gram(F, rowA, F, colB);
+            // the next block (the first again after the last of pass 0)
+            const bool more = STG && !(pass == 1 && cb == TILE / 32 - 1);
+            const int64_t nb0 = j0 + ((cb + 1) % (TILE / 32)) * 32;
+            bf16x8 pre[PR];
+            if constexpr (STG) {
+                if (more) {
+#pragma unroll
+                    for (int i = 0; i < PR; ++i) {
+                        const int k = tid + WG * i;
+                        if (k < ch) pre[i] = *BS::src(F, nb0, ns, k);
+                    }
+                }
+            }
+            f32x16 acc = {};
+            if constexpr (STG) BS::template mma<MP>(fa, sb[cur], ns, l, acc);
+            else acc = fa.gram(F, rowA, F, colB);
             const float nj = F.nrm[colB];
             double cs = 0.0;
             float cm = 0.0f;
@@ -214,6 +249,17 @@ __global__ __launch_bounds__(WG) void k_gram_sums(Features F, KernelParams kp, c
                 rm[k] = fmaxf(rm[k], fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3])));
             }
             wave_lds_sync();
+            if constexpr (STG) {
+                if (more) {
+#pragma unroll
+                    for (int i = 0; i < PR; ++i) {
+                        const int k = tid + WG * i;
+                        if (k < ch) sb[cur ^ 1][BS::dst(ns, k)] = pre[i];
+                    }
+                }
+                __syncthreads();
+                cur ^= 1;
+            }
         }
         // rows rr + 8 k: the eight lanes of each row add their column quads
 #pragma unroll
