@@ -487,15 +487,17 @@ __device__ inline void gram_band(const Features& F, const KernelParams& kp, int 
         const int64_t colB = (int64_t)J * TILE + col0 + 32 * cb + l32;
         const f32x16 acc = mfma_gram_32x32<KIND>(F, rowA, colB);
         const float nj = F.nrm[colB];
+        // the lane's column of its row half: the 16 rows sit at constant offsets
+        float* kl = kb + 4 * h * 64 + 32 * cb + l32;
         if (plain) {
 #pragma unroll
             for (int r = 0; r < 16; ++r)
-                kb[(8 * (r >> 2) + 4 * h + (r & 3)) * 64 + 32 * cb + l32] = kernel_value(ni[r], nj, acc[r], kp);
+                kl[(8 * (r >> 2) + (r & 3)) * 64] = kernel_value(ni[r], nj, acc[r], kp);
         } else {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int row = 8 * (r >> 2) + 4 * h + (r & 3);
-                kb[row * 64 + 32 * cb + l32] =
+                kl[(8 * (r >> 2) + (r & 3)) * 64] =
                     kernel_entry(ni[r], nj, acc[r], (int64_t)I * TILE + row0 + row, colB, kp);
             }
         }
