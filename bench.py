@@ -35,8 +35,15 @@ VALU_PEAK_GSLOT = 256 * 64 * 2.4
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}
 # K' of one pair recomputed inside the sweep, beyond the MFMA Gram: the
 # distance (norm sum, -2 g, clamp: 3), the scale (1), exp2 (a transcendental:
-# 4) and + lambda^2 (1)
+# 4) and + lambda^2 (1); from augmented rows, whose Gram is the exponent, the
+# clamp (1), exp2 (4) and + lambda^2 (1)
 RECOMPUTE_SLOTS_PER_PAIR = 9
+RECOMPUTE_AUG_SLOTS_PER_PAIR = 6
+
+
+def recompute_slots(plan):
+    """VALU slots per pair of K' recomputed in the sweep (the plan's form)."""
+    return RECOMPUTE_AUG_SLOTS_PER_PAIR if plan.get("recompute_aug", 0) else RECOMPUTE_SLOTS_PER_PAIR
 # decision function on augmented rows (the MFMA emits the scaled exponent),
 # VALU slots per (query, training point) pair: exp2 with its clamp modifier
 # (a transcendental: 4 slots) and the FP32 multiply-add of the weighted sum
@@ -611,7 +618,7 @@ def main():
     if stateless:
         slots = stateless_slots_per_pair(plan["stateless_depth"], int(plan["series_reciprocal"]), a.precision)
         if recompute:
-            slots += RECOMPUTE_SLOTS_PER_PAIR
+            slots += recompute_slots(plan)
         valu = slots * pairs / (avg_ms * 1e-3) / 1e9 if klaunch else None
         roof.update({"valu_slots_per_pair": slots, "valu_gslot_per_s": valu, "valu_peak_gslot_per_s": VALU_PEAK_GSLOT,
                      "valu_frac": (valu / VALU_PEAK_GSLOT) if valu else None,
@@ -684,7 +691,7 @@ def main():
         pairs4 = wl4.N * (wl4.N - 1) / 2.0
         ms4 = gk4 / max(gl4, 1)
         slots4 = stateless_slots_per_pair(g4["stateless_depth"], int(g4["series_reciprocal"]), "mixed") + \
-            RECOMPUTE_SLOTS_PER_PAIR
+            recompute_slots(g4)
         v4 = slots4 * pairs4 / (ms4 * 1e-3) / 1e9 if gl4 else None
         mp4 = (wl4.m + 15) // 16 * 16
         mf4 = 2.0 * mp4 * 6 * pairs4 / (ms4 * 1e-3) / 1e12 if gl4 else None

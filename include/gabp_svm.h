@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define GABP_ABI_VERSION 8
+#define GABP_ABI_VERSION 9
 
 /* Opaque solver handle; owns every device buffer it allocates. */
 typedef struct gabp_svm gabp_svm;
@@ -254,6 +254,13 @@ typedef struct gabp_plan {
                                   two with series reciprocals, three with
                                   series form 3); 1 = one tile per workgroup;
                                   0 = the sparsified kernel (no tiles) */
+    int32_t recompute_aug;     /* K' recomputed per band: 1 = each entry from
+                                  the Gram of augmented rows (x, |x|^2, 1) and
+                                  (c x, -c/2, -c/2 |x|^2), which is the
+                                  exponent itself (BF16 splits with m + 2 <=
+                                  m_pad); 0 = from the plain Gram and the norms,
+                                  or K' materialised */
+    int32_t reserved;
 } gabp_plan;
 
 /* Query selectors for gabp_svm_query: dst type and size in brackets. */

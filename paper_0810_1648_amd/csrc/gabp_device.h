@@ -477,11 +477,40 @@ __device__ inline void gram_band(const Features& F, const KernelParams& kp, int 
                                  int col0, float* kb) {
     const int l = threadIdx.x & 63, h = l >> 5, l32 = l & 31;
     const int64_t rowA = (int64_t)I * TILE + row0 + l32;
+    // the index test matters only on diagonal tiles and in the last column block
+    const bool plain = (I < J) && ((int64_t)J * TILE + col0 + 64 <= kp.N);
+    if constexpr (KIND != GRAM_F32) {
+        if (F.aug0) {
+            // augmented rows: the MFMA output is the exponent (clamped at 0,
+            // the largest value of -gamma log2(e) d^2), K' = exp2 + lambda^2
+            Features FA = F, FB = F;
+            FA.hi = F.aug0; FA.lo = F.aug0 + F.aug_plane; FA.lo2 = F.aug0 + 2 * F.aug_plane;
+            FB.hi = F.aug1; FB.lo = F.aug1 + F.aug_plane; FB.lo2 = F.aug1 + 2 * F.aug_plane;
+            const float lam2 = (float)kp.lam2;
+#pragma unroll 1
+            for (int cb = 0; cb < 2; ++cb) {
+                const int64_t colB = (int64_t)J * TILE + col0 + 32 * cb + l32;
+                const f32x16 acc = mfma_gram_32x32<KIND>(FA, rowA, FB, colB);
+                float* kl = kb + 4 * h * 64 + 32 * cb + l32;
+                if (plain) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        kl[(8 * (r >> 2) + (r & 3)) * 64] = __builtin_amdgcn_exp2f(fminf(acc[r], 0.0f)) + lam2;
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int64_t i = (int64_t)I * TILE + row0 + 8 * (r >> 2) + 4 * h + (r & 3);
+                        const float kv = __builtin_amdgcn_exp2f(fminf(acc[r], 0.0f)) + lam2;
+                        kl[(8 * (r >> 2) + (r & 3)) * 64] = (i < colB && colB < kp.N) ? kv : 0.0f;
+                    }
+                }
+            }
+            return;
+        }
+    }
     float ni[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) ni[r] = F.nrm[(int64_t)I * TILE + row0 + 8 * (r >> 2) + 4 * h + (r & 3)];
-    // the index test matters only on diagonal tiles and in the last column block
-    const bool plain = (I < J) && ((int64_t)J * TILE + col0 + 64 <= kp.N);
 #pragma unroll 1
     for (int cb = 0; cb < 2; ++cb) {
         const int64_t colB = (int64_t)J * TILE + col0 + 32 * cb + l32;

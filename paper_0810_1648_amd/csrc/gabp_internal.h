@@ -56,6 +56,14 @@ struct Features {
     const float* nrm;        // squared norms of the staged rows (FP32)
     int32_t m_pad;
     int32_t kind;            // GramKind
+    // BF16 kinds with m + 2 <= m_pad, K' recomputed: the training rows
+    // augmented as (x, |x|^2, 1) (aug0) and (c x, -c/2, -c/2 |x|^2) (aug1,
+    // c = 2 gamma log2(e)), in the kind's split planes `aug_plane` apart, so
+    // that their Gram is the exponent -gamma log2(e) |x_i - x_j|^2 itself
+    // (null: K' from the plain Gram and the norms)
+    const uint16_t* aug0;
+    const uint16_t* aug1;
+    int64_t aug_plane;
 };
 
 struct KernelParams {

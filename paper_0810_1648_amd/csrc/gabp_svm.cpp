@@ -107,6 +107,7 @@ struct gabp_svm {
         q_out, glist, HI, HM,
         chunks,                  // 2 x 2 tile chunks of the synchronous FP32-partial sweep
         xaug,                    // training rows of the augmented decision function
+        xaug0,                   // the other augmentation, for K' recomputed per band
         parena;                  // working memory of gabp_svm_predict (reused)
     int aug_kind = -1, aug_mp = 0;
     // sparsified kernel: tile counts and offsets, keys, K' per edge, edge
@@ -125,7 +126,7 @@ struct gabp_svm {
                        &blk1, &blk2, &one, &status_d, &trace_d, &flag, &tmp, &Kin, &q_rows,
                        &q_cols, &q_out, &glist, &sp_cnt, &sp_toff, &sp_keys, &sp_keys2, &sp_kv, &sp_kv2,
                        &sp_ei, &sp_ej, &sp_degi, &sp_degj, &sp_offi, &sp_offj, &sp_ids, &sp_perm, &sp_tmp,
-                       &sp_order, &sp_Xp, &sp_cent, &sp_rad, &sp_keep, &sp_tsel, &sp_nsel, &sp_xb, &HI, &HM, &chunks, &xaug, &parena, nullptr};
+                       &sp_order, &sp_Xp, &sp_cent, &sp_rad, &sp_keep, &sp_tsel, &sp_nsel, &sp_xb, &HI, &HM, &chunks, &xaug, &xaug0, &parena, nullptr};
     size_t held() const {
         size_t b = 0;
         for (int k = 0; all[k]; ++k) b += all[k]->bytes;
@@ -381,6 +382,22 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
             }
         } else {
             h->xaug.release();
+        }
+        // K' recomputed per band from augmented rows (the solve's own split
+        // kind and width): the Gram of (x, |x|^2, 1) and (c x, -c/2, -c/2 |x|^2)
+        // is the exponent, so a K' entry costs a clamped exp2 and an add
+        h->xaug0.release();
+        if (!kmat && h->aug_kind == gram && h->aug_mp == m_pad) {
+            const int anp = (gram == GRAM_BF16X6) ? 3 : (gram == GRAM_BF16X3) ? 2 : 1;
+            if (h->xaug0.ensure((size_t)NPAD * m_pad * 2 * anp) == hipSuccess) {
+                HIPCHK(h, launch_stage_aug(Xd, h->mean.as<double>(), N, m, NPAD, m_pad, gram, 0, 0.0f,
+                                           h->xaug0.as<uint16_t>(), s));
+                F.aug0 = h->xaug0.as<uint16_t>();
+                F.aug1 = h->xaug.as<uint16_t>();
+                F.aug_plane = NPAD * m_pad;
+            } else {
+                (void)hipGetLastError();
+            }
         }
     }
     HIPCHK(h, hipEventRecord(ev[1], s));
@@ -684,6 +701,7 @@ gabp_status solve_impl(gabp_svm* h, const float* X, const double* K, const float
     h->plan.stateless_rho = rho;
     h->plan.series_reciprocal = ser;
     h->plan.tile_chunk = chunked ? 2 : 1;
+    h->plan.recompute_aug = (!kmat && h->xaug0.p) ? 1 : 0;
     h->plan.sched_groups = grouped ? G : 0;
     h->plan.n_blocks = NB;
     h->plan.n_tiles = nt;
@@ -715,6 +733,11 @@ gabp_status residual_certificate(gabp_svm* h) {
     F.f32 = h->xs32.as<float>(); F.hi = h->xhi.as<uint16_t>(); F.lo = h->xlo.as<uint16_t>();
     F.lo2 = h->xlo2.as<uint16_t>(); F.f64 = h->x64.as<double>(); F.nrm = h->nrm.as<float>();
     F.m_pad = h->m_pad; F.kind = h->gram;
+    if (h->xaug0.p) {   // the solve's K' came from the augmented rows
+        F.aug0 = h->xaug0.as<uint16_t>();
+        F.aug1 = h->xaug.as<uint16_t>();
+        F.aug_plane = h->NPAD * h->m_pad;
+    }
     KernelParams kp{};
     kp.N = h->N;
     kp.NB = h->NB;

@@ -64,7 +64,8 @@ class Plan(ct.Structure):
                 ("n_blocks", ct.c_int64), ("n_tiles", ct.c_int64), ("device_bytes", ct.c_uint64),
                 ("alg_bytes_per_sweep", ct.c_uint64), ("alg_bytes_per_pair", ct.c_double),
                 ("stateless_rho", ct.c_double), ("series_reciprocal", ct.c_int32), ("sched_groups", ct.c_int32),
-                ("n_edges", ct.c_int64), ("stateless_bounded", ct.c_int32), ("tile_chunk", ct.c_int32)]
+                ("n_edges", ct.c_int64), ("stateless_bounded", ct.c_int32), ("tile_chunk", ct.c_int32),
+                ("recompute_aug", ct.c_int32), ("reserved", ct.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -77,7 +78,7 @@ class GabpError(RuntimeError):
 
 
 _lib = None
-ABI_VERSION = 8     # GABP_ABI_VERSION the structures above describe
+ABI_VERSION = 9     # GABP_ABI_VERSION the structures above describe
 
 
 def lib():

@@ -49,7 +49,7 @@ def test_params_default_and_layout(lib):
     assert p.struct_size == ct.sizeof(gabp.Params)
     assert p.precision == gabp.PREC["mixed"] and p.diag_mode == gabp.DIAG["dominant_row"]
     assert p.diag_delta == 0.1 and p.lambda_aug < 0 and p.tol_rel == 1e-7
-    assert gabp.lib().gabp_abi_version() == gabp.ABI_VERSION == 8
+    assert gabp.lib().gabp_abi_version() == gabp.ABI_VERSION == 9
     assert gabp.lib().gabp_status_string(4) == b"diverged"
 
 

@@ -260,12 +260,16 @@ def test_box_clip_and_sv_mask(torch):
 # ------------------------------------------- K' recomputed / stateless edges --
 
 def test_recompute_matches_materialised(torch):
-    for prec, n in (("fp32", 900), ("mixed", 700)):
+    # FP32 Gram: both forms compute K' by the same formula (row sums equal to
+    # rounding order); BF16 splits: the recomputed bands take the exponent
+    # straight from the Gram of augmented rows, the plane forms the distance
+    # on the VALU, each within FP32 rounding of the kernel value
+    for prec, n, rtol in (("fp32", 900, 1e-12), ("mixed", 700, 1e-6)):
         wl = inputs.make_workload("covertype", n=n, seed=21)
         a, _ = run(torch, wl, precision=prec, kstore="materialise", edge_state="stored")
         b, _ = run(torch, wl, precision=prec, kstore="recompute", edge_state="stored")
         assert b.plan()["kstore"] == gabp.KSTORE["recompute"]
-        np.testing.assert_allclose(b.adiag(), a.adiag(), rtol=1e-12)
+        np.testing.assert_allclose(b.adiag(), a.adiag(), rtol=rtol)
         err = _rel(b.alpha(), a.alpha())
         print(f"recompute vs materialise {prec}: rel diff {err:.2e}, sweeps {b.sweeps()} vs {a.sweeps()}")
         assert err <= 1e-6
